@@ -1,0 +1,200 @@
+"""CPU oracle for the phased SSSP path -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this package. The GPU product path never links or calls it, and the
+oracle imports nothing from the product package: the two share only the
+seeded input generators in ``graphgen``.
+
+The arithmetic lives in ``oracle.c`` (plain C, compiled on first use with
+gcc); this module only marshals numpy arrays. Criterion bit values follow
+the disjunction convention of Section 3 (a set of bits = their OR).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+INF = np.uint64(0xFFFFFFFFFFFFFFFF)
+INF_INT = 0xFFFFFFFFFFFFFFFF
+
+DIJK, IN_STATIC, OUT_STATIC, IN_SIMPLE, OUT_SIMPLE, IN_FULL, OUT_WEAK, OUT_FULL = (1 << i for i in range(8))
+BIT_NAMES = ["DIJK", "IN_STATIC", "OUT_STATIC", "IN_SIMPLE", "OUT_SIMPLE", "IN_FULL", "OUT_WEAK", "OUT_FULL"]
+CRIT = {name: 1 << i for i, name in enumerate(BIT_NAMES)}
+STATIC_OR = IN_STATIC | OUT_STATIC
+SIMPLE_OR = IN_SIMPLE | OUT_SIMPLE
+FULL_OR = IN_FULL | OUT_FULL
+
+
+def build(force: bool = False) -> str:
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC", _SRC, "-o", tmp])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("phases", ctypes.c_uint32), ("pad", ctypes.c_uint32), ("sum_f", ctypes.c_uint64),
+                ("n_reach", ctypes.c_uint64), ("m_reach", ctypes.c_uint64),
+                ("relax_edges", ctypes.c_uint64), ("improving", ctypes.c_uint64)]
+
+
+class _DStats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_uint32), ("buckets", ctypes.c_uint32),
+                ("light_relax", ctypes.c_uint64), ("heavy_relax", ctypes.c_uint64),
+                ("sum_frontier", ctypes.c_uint64)]
+
+
+def _L():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            lib = ctypes.CDLL(_LIB_PATH)
+            P, u32, u64, i = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+            lib.orc_validate.argtypes = [u32, P, P]
+            lib.orc_dijkstra.argtypes = [u32, P, P, P, u32, P, P]
+            lib.orc_dijkstra.restype = ctypes.c_int64
+            lib.orc_bellman_ford.argtypes = [u32, P, P, P, u32, P]
+            lib.orc_static_minima.argtypes = [u32, P, P, P, P, P]
+            lib.orc_phased.argtypes = [u32, P, P, P, u32, u32, P, u32, i, P, P,
+                                       ctypes.POINTER(_Stats), u32, P, P, P, P, P]
+            lib.orc_delta_step.argtypes = [u32, P, P, P, u32, P, u32, P, ctypes.POINTER(_DStats), u32, P]
+            _lib = lib
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _csr(g):
+    return (int(g.n), np.ascontiguousarray(g.row_ptr, np.uint64), np.ascontiguousarray(g.col, np.uint32),
+            np.ascontiguousarray(g.w, np.uint32))
+
+
+def validate(g) -> bool:
+    n, rp, col, _ = _csr(g)
+    return _L().orc_validate(n, _p(rp), _p(col) if col.size else None) == 0
+
+
+def dijkstra(g, src: int):
+    """(dist u64[n] with INF for unreachable, hops u32[n]) -- Section 2."""
+    n, rp, col, w = _csr(g)
+    dist = np.empty(n, np.uint64)
+    hops = np.empty(n, np.uint32)
+    rc = _L().orc_dijkstra(n, _p(rp), _p(col), _p(w), src, _p(dist), _p(hops))
+    if rc < 0:
+        raise RuntimeError("orc_dijkstra failed: %d" % rc)
+    return dist, hops
+
+
+def bellman_ford(g, src: int) -> np.ndarray:
+    n, rp, col, w = _csr(g)
+    dist = np.empty(n, np.uint64)
+    rc = _L().orc_bellman_ford(n, _p(rp), _p(col), _p(w), src, _p(dist))
+    if rc != 0:
+        raise RuntimeError("orc_bellman_ford failed: %d" % rc)
+    return dist
+
+
+def static_minima(g):
+    """(minIn u32[n], minOut u32[n]); 0xFFFFFFFF where a vertex has no such edge."""
+    n, rp, col, w = _csr(g)
+    mi = np.empty(n, np.uint32)
+    mo = np.empty(n, np.uint32)
+    if _L().orc_static_minima(n, _p(rp), _p(col), _p(w), _p(mi), _p(mo)) != 0:
+        raise RuntimeError("orc_static_minima failed")
+    return mi, mo
+
+
+@dataclass
+class PhasedResult:
+    dist: np.ndarray
+    phases: int
+    sum_f: int
+    n_reach: int
+    m_reach: int
+    relax_edges: int
+    improving: int
+    trace_f: np.ndarray
+    trace_s: np.ndarray
+    trace_mind: np.ndarray
+    trace_counts: np.ndarray | None
+    phase_of: np.ndarray
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+_ERRS = {-1: "invalid argument", -2: "out of memory", -10: "unsound: certified vertex not correct",
+         -11: "incomplete: a minimum-distance vertex was not certified", -12: "strength chain violated",
+         -13: "final distances differ from the reference"}
+
+
+def phased(g, src: int, crit: int, crit_seq=None, check: bool = False, dist_ref=None,
+           trace_cap: int | None = None) -> PhasedResult:
+    """Generic phased algorithm of Section 3 with the given criterion bits."""
+    n, rp, col, w = _csr(g)
+    cap = n if trace_cap is None else trace_cap
+    dist = np.empty(n, np.uint64)
+    tf = np.zeros(cap, np.uint32)
+    ts = np.zeros(cap, np.uint32)
+    tm = np.zeros(cap, np.uint64)
+    tc = np.zeros(8 * cap, np.uint32) if check else None
+    seq = None if crit_seq is None else np.ascontiguousarray(crit_seq, np.uint32)
+    po = np.zeros(n, np.uint32)
+    st = _Stats()
+    rc = _L().orc_phased(n, _p(rp), _p(col), _p(w), src, crit, _p(seq), 0 if seq is None else len(seq),
+                         int(check), _p(None if dist_ref is None else np.ascontiguousarray(dist_ref, np.uint64)),
+                         _p(dist), ctypes.byref(st), cap, _p(tf), _p(ts), _p(tm), _p(tc), _p(po))
+    if rc != 0:
+        raise OracleError("orc_phased: %s (%d)" % (_ERRS.get(rc, "?"), rc))
+    k = min(st.phases, cap)
+    return PhasedResult(dist, int(st.phases), int(st.sum_f), int(st.n_reach), int(st.m_reach),
+                        int(st.relax_edges), int(st.improving), tf[:k], ts[:k], tm[:k],
+                        None if tc is None else tc[:8 * k].reshape(k, 8), po)
+
+
+@dataclass
+class DeltaResult:
+    dist: np.ndarray
+    rounds: int
+    buckets: int
+    light_relax: int
+    heavy_relax: int
+    sum_frontier: int
+    trace_delta: np.ndarray
+
+
+def delta_step(g, src: int, deltas, trace_cap: int = 0) -> DeltaResult:
+    """Delta-stepping; bucket b uses deltas[min(b, len-1)]."""
+    n, rp, col, w = _csr(g)
+    ds = np.ascontiguousarray(np.atleast_1d(deltas), np.uint64)
+    dist = np.empty(n, np.uint64)
+    td = np.zeros(max(trace_cap, 1), np.uint64)
+    st = _DStats()
+    rc = _L().orc_delta_step(n, _p(rp), _p(col), _p(w), src, _p(ds), len(ds), _p(dist), ctypes.byref(st),
+                             trace_cap, _p(td))
+    if rc != 0:
+        raise OracleError("orc_delta_step: %s (%d)" % (_ERRS.get(rc, "?"), rc))
+    return DeltaResult(dist, int(st.rounds), int(st.buckets), int(st.light_relax), int(st.heavy_relax),
+                       int(st.sum_frontier), td[:min(trace_cap, st.buckets)])
+
+
+def reach_stats(g, dist):
+    """(n_reach, m_reach): reachable vertices and the out-edges they own."""
+    reach = dist != INF
+    return int(reach.sum()), int(np.diff(g.row_ptr)[reach].sum())
