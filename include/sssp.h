@@ -1,0 +1,179 @@
+/*
+ * sssp.h -- C ABI of the MI355X (gfx950) phased single-source shortest path library.
+ *
+ * Method: M. Kainer, J. L. Traff, "More Parallelism in Dijkstra's Single-Source
+ * Shortest Path Algorithm", arXiv 1903.12085.
+ *
+ * Problem (Section 2): a directed graph G = (V, E), non-negative edge costs
+ * c(u, v), a source s; compute dist(s, v) for every v, infinity if v is not
+ * reachable. Costs are uint32 (non-negative by type); distances are uint64,
+ * with UINT64_MAX standing for infinity.
+ *
+ * Method (Section 3): the generic phased algorithm. Vertices are settled (S),
+ * queued (F) or unexplored (U). Each phase evaluates a correctness criterion
+ * on every queued vertex against the phase-start state, settles every vertex
+ * it certifies and relaxes all their out-edges in parallel, until F is empty.
+ * A criterion is a bit set; several bits mean their disjunction, which is
+ * sound because each disjunct is (Section 3).
+ *
+ * Conventions for every entry point:
+ *   - Graph data is given in CSR form (row_ptr[n+1], col[m], weight[m]) with
+ *     row_ptr[0] = 0, row_ptr non-decreasing, row_ptr[n] = m, col[e] < n.
+ *     Self-loops and parallel edges are allowed and enter every minimum.
+ *   - Output distance arrays are DEVICE pointers with room for n uint64 and
+ *     are owned by the caller; the library never frees caller memory.
+ *   - Every call is synchronous: when it returns, outputs are complete.
+ *     Work runs on the graph's HIP stream (sssp_set_stream).
+ *   - Return value: SSSP_OK (0) or a negative sssp_status. On error, output
+ *     buffers hold unspecified data; sssp_last_error() describes the failure
+ *     (thread-local string, valid until the next call on that thread).
+ *   - A graph handle may be used by one host thread at a time.
+ *   - Limits: 1 <= n < 2^26, m < 2^32; otherwise SSSP_ERR_UNSUPPORTED.
+ */
+#ifndef SSSP_H
+#define SSSP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sssp_graph sssp_graph;
+
+typedef enum {
+    SSSP_OK = 0,
+    SSSP_ERR_INVALID = -1,     /* bad argument or malformed CSR */
+    SSSP_ERR_OOM = -2,         /* device or host allocation failed */
+    SSSP_ERR_DEVICE = -3,      /* a HIP runtime call failed */
+    SSSP_ERR_UNSUPPORTED = -4, /* size beyond the documented limits */
+    SSSP_ERR_INTERNAL = -5     /* invariant violated (e.g. phase count above n) */
+} sssp_status;
+
+/* Criterion bits (Section 3). The phase settles v in F when any set bit holds:
+ *   SSSP_DIJK        d[v] = min_{u in F} d[u]
+ *   SSSP_IN_STATIC   d[v] - min over all in-edges (w,v) of c(w,v) <= minD      (eq. crit:instatic)
+ *   SSSP_OUT_STATIC  d[v] <= min_{u in F} d[u] + min over all out-edges of u   (eq. crit:outstatic)
+ *   SSSP_IN_SIMPLE   as IN_STATIC, in-edges from non-settled w only            (eq. crit:insimple)
+ *   SSSP_OUT_SIMPLE  as OUT_STATIC, out-edges (u,w) to non-settled w only      (eq. crit:outsimple,
+ *                    read with u in F and w in F u U)
+ *   SSSP_IN_FULL     IN: in-edges from F, or two-edge paths through U          (eq. crit:in)
+ *   SSSP_OUT_WEAK    OUT with the second edge minimised over all of V          (eq. crit:outweak)
+ *   SSSP_OUT_FULL    OUT: edges into F, or two-edge paths into U then F u U    (eq. crit:out)
+ * minD = min_{u in F} d[u]; all terms use the phase-start snapshot. */
+enum {
+    SSSP_DIJK = 1u << 0,
+    SSSP_IN_STATIC = 1u << 1,
+    SSSP_OUT_STATIC = 1u << 2,
+    SSSP_IN_SIMPLE = 1u << 3,
+    SSSP_OUT_SIMPLE = 1u << 4,
+    SSSP_IN_FULL = 1u << 5,
+    SSSP_OUT_WEAK = 1u << 6,
+    SSSP_OUT_FULL = 1u << 7,
+    SSSP_CRIT_ALL = 0xFFu
+};
+
+/* Per-solve statistics (Section 4 measures phases and the summed fringe sizes). */
+typedef struct {
+    uint32_t phases;       /* phases (phased solver) or rounds (Delta-stepping) */
+    uint32_t buckets;      /* Delta-stepping buckets processed; 0 for the phased solver */
+    uint64_t sum_f;        /* sum over phases of |F| at phase start */
+    uint64_t n_reach;      /* vertices settled = vertices reachable from the source */
+    uint64_t m_reach;      /* out-edges of reachable vertices (the GTEPS numerator) */
+    uint64_t relax_edges;  /* edge relaxations attempted towards non-settled targets */
+    uint64_t improving;    /* relaxations that lowered a tentative distance */
+    uint64_t precompute_ns;/* one-time per-graph preprocessing time, nanoseconds */
+} sssp_stats;
+
+/* One record per phase (Section 4 plots vertices settled per phase). */
+typedef struct {
+    uint64_t min_d;        /* minD at phase start (or the bucket floor for Delta-stepping) */
+    uint32_t fringe;       /* |F| at phase start */
+    uint32_t settled;      /* |S'| settled in this phase (frontier size for a light round) */
+    uint32_t criterion;    /* criterion bits evaluated in this phase (learned solves vary it) */
+    uint32_t edges;        /* out-edges expanded in this phase */
+} sssp_phase_rec;
+
+/*
+ * Create a device graph from CSR arrays (Section 5 uses an adjacency array of
+ * out-edges). device_ptrs = 0: row_ptr/col/weight are host pointers;
+ * device_ptrs = 1: they are device pointers. The library copies the data into
+ * buffers it owns, so the caller may free its arrays after the call. It
+ * precomputes the static minima minIn/minOut (equations crit:instatic and
+ * crit:outstatic, computed once in O(m), Section 3) and sorts every row by
+ * weight. hip_stream: a hipStream_t or NULL for the null stream.
+ * Errors: SSSP_ERR_INVALID for n = 0, a malformed CSR (checked on the device
+ * when device_ptrs = 1) or out == NULL; SSSP_ERR_OOM; SSSP_ERR_UNSUPPORTED.
+ */
+int sssp_graph_create(uint32_t n, uint64_t m, const uint64_t *row_ptr, const uint32_t *col,
+                      const uint32_t *weight, int device_ptrs, void *hip_stream, sssp_graph **out);
+
+/* Release every device buffer the graph owns. NULL is accepted. */
+int sssp_graph_destroy(sssp_graph *g);
+
+/* Change the HIP stream used by later calls on g. */
+int sssp_set_stream(sssp_graph *g, void *hip_stream);
+
+/* Copy the static minima to caller DEVICE buffers of n uint32 each
+ * (UINT32_MAX where a vertex has no in- / out-edge). Either may be NULL. */
+int sssp_graph_minima(sssp_graph *g, uint32_t *min_in, uint32_t *min_out);
+
+/*
+ * Phased SSSP (Section 3) with the given criterion bits.
+ *   dist_out   DEVICE, n uint64: dist(s, v), UINT64_MAX if unreachable.
+ *   phases_out HOST, may be NULL: number of phases (phase 1 settles s).
+ * Errors: SSSP_ERR_INVALID for source >= n, criterion 0 or unknown bits,
+ * dist_out NULL.
+ */
+int sssp_solve(sssp_graph *g, uint32_t source, uint32_t criterion, uint64_t *dist_out,
+               uint32_t *phases_out);
+
+/*
+ * sssp_solve with observability.
+ *   stats      HOST, may be NULL.
+ *   phase_of   DEVICE, n uint32, may be NULL: the 1-based phase in which each
+ *              vertex was settled, 0 if never.
+ *   trace      HOST, trace_cap records, may be NULL: one record per phase for
+ *              the first trace_cap phases.
+ */
+int sssp_solve_ex(sssp_graph *g, uint32_t source, uint32_t criterion, uint64_t *dist_out,
+                  sssp_stats *stats, uint32_t *phase_of, sssp_phase_rec *trace, uint32_t trace_cap);
+
+/*
+ * Delta-stepping (Section 5, the comparison algorithm), run on the same
+ * kernels. Bucket b is the window [b*delta, (b+1)*delta) holding the smallest
+ * queued distance; light edges (c < delta) are relaxed in synchronous rounds
+ * until no vertex inside the window improves, then one round relaxes the
+ * heavy edges (c >= delta) of everything the bucket removed.
+ *   phases_out HOST, may be NULL: light rounds + heavy rounds.
+ * Errors: SSSP_ERR_INVALID for delta = 0, source >= n, dist_out NULL.
+ */
+int sssp_delta_step(sssp_graph *g, uint32_t source, uint64_t delta, uint64_t *dist_out,
+                    uint32_t *phases_out);
+
+/* Delta-stepping with a per-bucket width: bucket b uses deltas[min(b, n_deltas-1)]
+ * (HOST array, every entry >= 1). stats/trace as for sssp_solve_ex. */
+int sssp_delta_step_ex(sssp_graph *g, uint32_t source, const uint64_t *deltas, uint32_t n_deltas,
+                       uint64_t *dist_out, sssp_stats *stats, sssp_phase_rec *trace,
+                       uint32_t trace_cap);
+
+/*
+ * Batched phased SSSP: nq independent queries (graphs[i], sources[i]) in one
+ * persistent launch. Graph handles may repeat. Every query uses `criterion`.
+ *   dist_outs  HOST array of nq DEVICE pointers, each with room for
+ *              graphs[i]->n uint64.
+ *   phases_out HOST, nq entries, may be NULL.
+ * Errors: SSSP_ERR_INVALID for nq = 0, a NULL pointer, a bad source or
+ * criterion.
+ */
+int sssp_solve_batch(sssp_graph *const *graphs, const uint32_t *sources, uint32_t nq,
+                     uint32_t criterion, uint64_t *const *dist_outs, uint32_t *phases_out);
+
+/* Human-readable description of the last error on the calling thread. */
+const char *sssp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSSP_H */

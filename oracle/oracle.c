@@ -328,14 +328,17 @@ static void out_thresholds(uint32_t want, const uint32_t *Flist, uint64_t nF, co
                            const uint32_t *min_out, uint64_t *inner_ns, uint32_t *memo_stamp,
                            uint32_t stamp, thresholds_t *T) {
     T->t_out_static = T->t_out_simple = T->t_out_weak = T->t_out_full = INF;
+    const uint32_t dyn = want & (C_OUT_SIMPLE | C_OUT_WEAK | C_OUT_FULL);
     for (uint64_t i = 0; i < nF; ++i) {
         uint32_t u = Flist[i];
         uint64_t du = d[u];
+        /* crit:outstatic: min over u in F and all out-edges (u, w) of d[u] + c(u, w)
+         * = d[u] + minOut[u], the precomputed static minimum (Section 3) */
+        if (want & C_OUT_STATIC) T->t_out_static = min64(T->t_out_static, sadd(du, w64(min_out[u])));
+        if (!dyn) continue;
         for (uint64_t e = rp[u]; e < rp[u + 1]; ++e) {
             uint32_t x = col[e];
             uint64_t c = w[e];
-            /* crit:outstatic: u in F, w in V */
-            if (want & C_OUT_STATIC) T->t_out_static = min64(T->t_out_static, sadd(du, c));
             if (st[x] == ST_S) continue;
             /* crit:outsimple (sets read as u in F, w in F u U) */
             if (want & C_OUT_SIMPLE) T->t_out_simple = min64(T->t_out_simple, sadd(du, c));

@@ -1,0 +1,227 @@
+"""ctypes binding of libsssp.so (the C ABI declared in include/sssp.h).
+
+Argument marshalling only: every step of every solve runs in the library's
+HIP kernels. PyTorch provides device memory and the stream. If the library is
+missing this module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsssp.so")
+
+# Criterion bits (include/sssp.h)
+DIJK, IN_STATIC, OUT_STATIC, IN_SIMPLE, OUT_SIMPLE, IN_FULL, OUT_WEAK, OUT_FULL = (1 << i for i in range(8))
+CRIT_NAMES = ["DIJK", "IN_STATIC", "OUT_STATIC", "IN_SIMPLE", "OUT_SIMPLE", "IN_FULL", "OUT_WEAK", "OUT_FULL"]
+CRIT = {name: 1 << i for i, name in enumerate(CRIT_NAMES)}
+STATIC_OR = IN_STATIC | OUT_STATIC
+SIMPLE_OR = IN_SIMPLE | OUT_SIMPLE
+FULL_OR = IN_FULL | OUT_FULL
+
+SYMBOLS = ["sssp_graph_create", "sssp_graph_destroy", "sssp_set_stream", "sssp_graph_minima", "sssp_solve",
+           "sssp_solve_ex", "sssp_delta_step", "sssp_delta_step_ex", "sssp_solve_batch", "sssp_last_error"]
+
+ERRORS = {-1: "SSSP_ERR_INVALID", -2: "SSSP_ERR_OOM", -3: "SSSP_ERR_DEVICE", -4: "SSSP_ERR_UNSUPPORTED",
+          -5: "SSSP_ERR_INTERNAL"}
+
+
+class SsspError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (ERRORS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("phases", ctypes.c_uint32), ("buckets", ctypes.c_uint32), ("sum_f", ctypes.c_uint64),
+                ("n_reach", ctypes.c_uint64), ("m_reach", ctypes.c_uint64), ("relax_edges", ctypes.c_uint64),
+                ("improving", ctypes.c_uint64), ("precompute_ns", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+PHASE_REC = np.dtype([("min_d", np.uint64), ("fringe", np.uint32), ("settled", np.uint32),
+                      ("criterion", np.uint32), ("edges", np.uint32)])
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libsssp.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libsssp.so not built (%s); run paper_1903_12085_amd.build.build()" % path)
+    lib = ctypes.CDLL(path)
+    P, u32, u64, i = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    lib.sssp_graph_create.argtypes = [u32, u64, P, P, P, i, P, ctypes.POINTER(P)]
+    lib.sssp_graph_destroy.argtypes = [P]
+    lib.sssp_set_stream.argtypes = [P, P]
+    lib.sssp_graph_minima.argtypes = [P, P, P]
+    lib.sssp_solve.argtypes = [P, u32, u32, P, P]
+    lib.sssp_solve_ex.argtypes = [P, u32, u32, P, ctypes.POINTER(Stats), P, P, u32]
+    lib.sssp_delta_step.argtypes = [P, u32, u64, P, P]
+    lib.sssp_delta_step_ex.argtypes = [P, u32, P, u32, P, ctypes.POINTER(Stats), P, u32]
+    lib.sssp_solve_batch.argtypes = [P, P, u32, u32, P, P]
+    lib.sssp_last_error.restype = ctypes.c_char_p
+    lib.sssp_last_error.argtypes = []
+    for name in SYMBOLS:
+        getattr(lib, name)
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise SsspError(rc, load().sssp_last_error().decode(errors="replace"))
+
+
+def _stream_ptr():
+    """torch's current HIP stream (NULL stream when torch sees no GPU: argument checks only)."""
+    import torch
+    if not torch.cuda.is_available():
+        return None
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+class DeviceGraph:
+    """A graph resident on the GPU (library-owned buffers)."""
+
+    def __init__(self, n, row_ptr, col, w, device_ptrs: bool = False):
+        lib = load()
+        self.n = int(n)
+        self._h = ctypes.c_void_p()
+        if device_ptrs:
+            m = int(col.numel())
+            ptrs = [ctypes.c_void_p(t.data_ptr()) for t in (row_ptr, col, w)]
+        else:
+            row_ptr = np.ascontiguousarray(row_ptr, np.uint64)
+            col = np.ascontiguousarray(col, np.uint32)
+            w = np.ascontiguousarray(w, np.uint32)
+            m = int(col.size)
+            ptrs = [_np_ptr(row_ptr), _np_ptr(col) if m else None, _np_ptr(w) if m else None]
+        self.m = m
+        _check(lib.sssp_graph_create(self.n, m, ptrs[0], ptrs[1], ptrs[2], int(device_ptrs), _stream_ptr(),
+                                     ctypes.byref(self._h)))
+
+    @classmethod
+    def from_graph(cls, g):
+        return cls(g.n, g.row_ptr, g.col, g.w)
+
+    def close(self):
+        if self._h:
+            load().sssp_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def _bind_stream(self):
+        load().sssp_set_stream(self._h, _stream_ptr())
+
+    def minima(self):
+        import torch
+        mi = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        mo = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        self._bind_stream()
+        _check(load().sssp_graph_minima(self._h, ctypes.c_void_p(mi.data_ptr()), ctypes.c_void_p(mo.data_ptr())))
+        return mi, mo
+
+
+def new_dist(n):
+    """Device buffer for n uint64 distances (int64 storage, reinterpret on the host)."""
+    import torch
+    return torch.empty(n, dtype=torch.int64, device="cuda")
+
+
+def to_u64(t) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint64)
+
+
+@dataclass
+class SolveResult:
+    dist: object            # torch int64 device tensor holding uint64 bits
+    phases: int
+    stats: dict | None = None
+    phase_of: object = None
+    trace: np.ndarray | None = None
+
+    def dist_u64(self) -> np.ndarray:
+        return to_u64(self.dist)
+
+
+def solve(g: DeviceGraph, source: int, criterion: int, dist=None) -> SolveResult:
+    dist = new_dist(g.n) if dist is None else dist
+    ph = ctypes.c_uint32(0)
+    g._bind_stream()
+    _check(load().sssp_solve(g.handle, source, criterion, ctypes.c_void_p(dist.data_ptr()), ctypes.byref(ph)))
+    return SolveResult(dist, int(ph.value))
+
+
+def solve_ex(g: DeviceGraph, source: int, criterion: int, dist=None, phase_of: bool = False,
+             trace_cap: int = 0) -> SolveResult:
+    import torch
+    dist = new_dist(g.n) if dist is None else dist
+    po = torch.empty(g.n, dtype=torch.int32, device="cuda") if phase_of else None
+    tr = np.zeros(trace_cap, PHASE_REC) if trace_cap else None
+    st = Stats()
+    g._bind_stream()
+    _check(load().sssp_solve_ex(g.handle, source, criterion, ctypes.c_void_p(dist.data_ptr()), ctypes.byref(st),
+                                ctypes.c_void_p(po.data_ptr()) if po is not None else None,
+                                _np_ptr(tr), trace_cap))
+    if tr is not None:
+        tr = tr[:min(st.phases, trace_cap)]
+    return SolveResult(dist, int(st.phases), st.as_dict(), po, tr)
+
+
+def delta_step(g: DeviceGraph, source: int, delta: int, dist=None) -> SolveResult:
+    dist = new_dist(g.n) if dist is None else dist
+    ph = ctypes.c_uint32(0)
+    g._bind_stream()
+    _check(load().sssp_delta_step(g.handle, source, int(delta), ctypes.c_void_p(dist.data_ptr()), ctypes.byref(ph)))
+    return SolveResult(dist, int(ph.value))
+
+
+def delta_step_ex(g: DeviceGraph, source: int, deltas, dist=None, trace_cap: int = 0) -> SolveResult:
+    dist = new_dist(g.n) if dist is None else dist
+    ds = np.ascontiguousarray(np.atleast_1d(deltas), np.uint64)
+    tr = np.zeros(trace_cap, PHASE_REC) if trace_cap else None
+    st = Stats()
+    g._bind_stream()
+    _check(load().sssp_delta_step_ex(g.handle, source, _np_ptr(ds), len(ds), ctypes.c_void_p(dist.data_ptr()),
+                                     ctypes.byref(st), _np_ptr(tr), trace_cap))
+    if tr is not None:
+        tr = tr[:min(st.phases, trace_cap)]
+    return SolveResult(dist, int(st.phases), st.as_dict(), None, tr)
+
+
+def solve_batch(graphs, sources, criterion: int, dists=None):
+    """graphs: list of DeviceGraph (may repeat), sources: list of ints."""
+    nq = len(sources)
+    if dists is None:
+        dists = [new_dist(g.n) for g in graphs]
+    handles = (ctypes.c_void_p * nq)(*[g.handle.value for g in graphs])
+    srcs = np.ascontiguousarray(sources, np.uint32)
+    outs = (ctypes.c_void_p * nq)(*[d.data_ptr() for d in dists])
+    phases = np.zeros(nq, np.uint32)
+    for g in set(graphs):
+        g._bind_stream()
+    _check(load().sssp_solve_batch(handles, _np_ptr(srcs), nq, criterion, outs, _np_ptr(phases)))
+    return dists, phases

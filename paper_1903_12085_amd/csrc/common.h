@@ -1,0 +1,189 @@
+// Internal declarations shared by the HIP translation units of libsssp.
+// Target: gfx950 (CDNA4), 64-wide wavefronts.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sssp.h"
+
+#define INF64 0xFFFFFFFFFFFFFFFFull
+#define INF32 0xFFFFFFFFu
+
+// Vertex state byte: low two bits = set membership, bit 2 = "IN test passed"
+// flag written by the dynamic-term pass for the current phase.
+enum : uint8_t { ST_U = 0, ST_F = 1, ST_S = 2, ST_R = 3, ST_SET = 3, ST_INOK = 4 };
+
+// Which IN-family / OUT-family member a phase evaluates. Inside each family
+// the members are ordered by strength (X-STATIC => X-SIMPLE => (OUTWEAK =>) X,
+// Section 3), so a disjunction of members equals its strongest member, and
+// DIJK implies every other criterion.
+enum InMode : int { IN_NONE = 0, IN_DIJK = 1, IN_STATIC_M = 2, IN_SIMPLE_M = 3, IN_FULL_M = 4 };
+enum OutMode : int { OUT_NONE = 0, OUT_STATIC_M = 1, OUT_SIMPLE_M = 2, OUT_WEAK_M = 3, OUT_FULL_M = 4 };
+
+static inline void crit_modes(uint32_t c, int *in, int *out) {
+    *in = (c & SSSP_IN_FULL) ? IN_FULL_M : (c & SSSP_IN_SIMPLE) ? IN_SIMPLE_M
+        : (c & SSSP_IN_STATIC) ? IN_STATIC_M : IN_NONE;
+    *out = (c & SSSP_OUT_FULL) ? OUT_FULL_M : (c & SSSP_OUT_WEAK) ? OUT_WEAK_M
+         : (c & SSSP_OUT_SIMPLE) ? OUT_SIMPLE_M : (c & SSSP_OUT_STATIC) ? OUT_STATIC_M : OUT_NONE;
+    if (*in == IN_NONE && *out == OUT_NONE && (c & SSSP_DIJK)) *in = IN_DIJK;
+}
+
+// Device control block of one solve. Slots indexed by phase parity (mod 2 or
+// mod 3) let phase k fold values for phase k+1 while k's are still read,
+// with no host round trip between phases.
+struct Ctl {
+    unsigned long long reached;     // vertices ever queued (source included)
+    unsigned long long settled;     // vertices settled
+    unsigned long long sum_f;       // sum of |F| at phase start
+    unsigned long long relax_edges; // relaxations towards non-settled targets
+    unsigned long long improving;   // relaxations that lowered d
+    unsigned long long spack[2];    // S' with out-edges: (count << 32) | edge total
+    unsigned long long szero[2];    // S' without out-edges: count
+    unsigned long long minD[3];     // min_{v in F} d[v] for the phase
+    unsigned long long tst[3];      // OUT-STATIC threshold min_{u in F} d[u] + minOut[u]
+    unsigned long long tdyn[3];     // dynamic OUT threshold from the term pass
+    unsigned int pnum[2];           // 0-based index of the phase running with this parity
+    unsigned int phases;            // phases executed so far
+    unsigned int done;              // set once F is empty
+    // Delta-stepping
+    unsigned long long nextmin[2];  // min d over F for the next bucket (by bucket parity)
+    unsigned long long win_lo, win_hi, win_delta;
+    unsigned long long win_improved[2]; // vertices improved inside the window, by round parity
+    unsigned int rmode[2];          // round kind by parity: 0 bucket start, 1 light, 2 heavy
+    unsigned int buckets;           // buckets finished (written by the heavy round's identify)
+    unsigned int win_bucket;        // index of the bucket in progress
+    unsigned int n_deltas;
+    // learned selector
+    unsigned int choice[2];         // per-phase choice index by parity
+    unsigned long long m_reach;     // out-edges of settled vertices
+};
+
+// Per-phase device trace record (mirrors sssp_phase_rec).
+struct PhaseRec {
+    unsigned long long min_d;
+    unsigned int fringe, settled, criterion, edges;
+};
+
+// Device-resident graph plus the per-solve scratch kept between solves.
+struct sssp_graph_impl;
+
+struct DevGraph {
+    uint32_t n;
+    uint64_t m;
+    const uint32_t *rp;     // row_ptr (u32, n+1)
+    const uint2 *edges;     // (target, weight), each row sorted by weight
+    const uint2 *vmin;      // (minIn, minOut) per vertex
+    const uint32_t *ip;     // CSC in_ptr (n+1) or null
+    const uint2 *in_edges;  // CSC (source, weight), rows sorted by weight, or null
+};
+
+// Scratch used by a solve.
+struct SolveBufs {
+    Ctl *ctl;
+    uint8_t *st;
+    uint32_t *sid;          // S' vertex ids (vertices with out-edges)
+    uint32_t *soff;         // S' exclusive edge offsets
+    unsigned long long *sdu;// S' snapshot distances
+    uint32_t *zid;          // S' vertices without out-edges
+    uint32_t *chunk_start;  // first S' entry of each edge chunk
+    uint32_t *in_cur;       // IN-SIMPLE cursors (absolute CSC index)
+    uint32_t *out_cur;      // OUT-SIMPLE cursors (absolute CSR index)
+    uint32_t *stamp;        // Delta-stepping improvement stamps
+    unsigned long long *deltas; // Delta-stepping widths per bucket
+    PhaseRec *trace;
+    uint32_t trace_cap;
+    uint32_t *phase_of;
+    unsigned long long *dist;
+};
+
+int sssp_set_error(int code, const char *fmt, ...);
+
+// Release helpers for clean-up paths, where a failure has nothing left to undo.
+static inline void sssp_free(void *p) {
+    if (p) (void)hipFree(p);
+}
+static inline void sssp_host_free(void *p) {
+    if (p) (void)hipHostFree(p);
+}
+
+#define HIP_OK(call)                                                                      \
+    do {                                                                                  \
+        hipError_t _e = (call);                                                           \
+        if (_e != hipSuccess)                                                             \
+            return sssp_set_error(_e == hipErrorOutOfMemory ? SSSP_ERR_OOM : SSSP_ERR_DEVICE, \
+                                  "%s failed: %s (%s:%d)", #call, hipGetErrorString(_e),  \
+                                  __FILE__, __LINE__);                                    \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Device helpers
+
+__device__ __forceinline__ unsigned long long sadd64(unsigned long long a, unsigned long long b) {
+    unsigned long long s = a + b;
+    return s < a ? INF64 : s;
+}
+__device__ __forceinline__ unsigned long long w64(uint32_t x) {
+    return x == INF32 ? INF64 : (unsigned long long)x;
+}
+__device__ __forceinline__ unsigned long long umin64(unsigned long long a, unsigned long long b) {
+    return a < b ? a : b;
+}
+
+__device__ __forceinline__ unsigned long long wave_min64(unsigned long long x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = umin64(x, __shfl_xor(x, o, 64));
+    return x;
+}
+__device__ __forceinline__ unsigned long long wave_sum64(unsigned long long x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+// Inclusive prefix sum over the 64 lanes of a wavefront.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+// Block-wide min of up to 16 wavefronts, result valid in thread 0.
+template <int NWAVES>
+__device__ __forceinline__ unsigned long long block_min64(unsigned long long x, unsigned long long *sh) {
+    x = wave_min64(x);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[w] = x;
+    __syncthreads();
+    unsigned long long r = INF64;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < NWAVES; ++i) r = umin64(r, sh[i]);
+    __syncthreads();
+    return r;
+}
+template <int NWAVES>
+__device__ __forceinline__ unsigned long long block_sum64(unsigned long long x, unsigned long long *sh) {
+    x = wave_sum64(x);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[w] = x;
+    __syncthreads();
+    unsigned long long r = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < NWAVES; ++i) r += sh[i];
+    __syncthreads();
+    return r;
+}
+
+constexpr int kBlock = 256;          // threads per block for the phase kernels
+constexpr int kWaves = kBlock / 64;
+
+// Launch shape chosen per graph (autotuned; see tune.cpp).
+struct LaunchCfg {
+    int scan_blocks;    // blocks of the dense vertex-scan kernels
+    int relax_blocks;   // blocks of the relax kernel
+    int chunk;          // edges per relax chunk (multiple of kBlock, <= kMaxChunk)
+};
+constexpr int kMaxChunk = 2048;

@@ -1,0 +1,31 @@
+// The opaque sssp_graph handle and the helpers shared between translation units.
+#pragma once
+
+#include "common.h"
+
+struct sssp_graph {
+    uint32_t n = 0;
+    uint64_t m = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    uint32_t *rp = nullptr;        // row_ptr as u32 (n+1)
+    uint2 *edges = nullptr;        // (target, weight), rows sorted by weight
+    uint2 *vmin = nullptr;         // (minIn, minOut)
+    uint32_t *ip = nullptr;        // CSC in_ptr (lazy)
+    uint2 *in_edges = nullptr;     // CSC (source, weight), rows sorted by weight (lazy)
+    uint64_t precompute_ns = 0;
+    LaunchCfg cfg{};
+    // per-solve scratch, allocated on first use and kept
+    SolveBufs b{};
+    bool bufs_ready = false;
+    uint64_t chunk_cap = 0;        // entries of b.chunk_start
+    uint32_t delta_cap = 0;        // entries of b.deltas
+    Ctl *h_ctl = nullptr;          // pinned host mirror of the control block
+    hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
+DevGraph dev_view(const sssp_graph *g);
+int graph_ensure_csc(sssp_graph *g);
+void graph_default_cfg(sssp_graph *g);
+int solve_bufs_ensure(sssp_graph *g, bool cursors, bool stamps);
+void solve_bufs_free(sssp_graph *g);

@@ -1,0 +1,763 @@
+// Phased SSSP (Section 3) and Delta-stepping (Section 5) on one set of kernels.
+//
+// One phase = [term pass] -> identify -> relax, all launched back to back on
+// the graph's stream with no host round trip:
+//   term pass  (dynamic criteria only) per queued vertex v: the IN-family
+//              minimum over in-edges of its equation, and the OUT-family
+//              minimum over out-edges; the IN test result is stored as a flag
+//              bit, the OUT right-hand side min_{u in F} d[u] + term(u) is
+//              reduced to one threshold.
+//   identify   dense, coalesced scan of the 1-byte vertex state array; every
+//              queued vertex is tested against the phase-start thresholds.
+//              Certified vertices are settled and compacted into S' with a
+//              wavefront ballot + prefix sum and one packed (count, edges)
+//              atomic per wavefront, which also assigns each its exclusive
+//              offset in the phase's edge space. Vertices that stay queued
+//              contribute to next phase's minD and OUT-STATIC threshold.
+//   relax      the edge space of S' is cut into equal chunks; a block stages
+//              the chunk's S' entries (start edge, snapshot distance) in LDS
+//              and each lane finds its edge's owner by binary search (merge
+//              path), so rows of any degree split evenly. Each edge does a
+//              plain-load filter and a 64-bit atomicMin; the atomic that
+//              replaces infinity discovers the target (U -> F). Improving
+//              candidates fold into next phase's minD / OUT-STATIC threshold
+//              (d only decreases, so the minimum over final values equals the
+//              minimum over kept values and improving candidates).
+// Control state lives in device memory slots indexed by phase parity, so
+// phases can be queued many at a time and empty phases exit at once.
+#include <string.h>
+
+#include "common.h"
+#include "graph.h"
+
+static_assert(sizeof(PhaseRec) == sizeof(sssp_phase_rec), "trace record layout");
+
+struct KArgs {
+    DevGraph g;
+    SolveBufs b;
+    uint32_t crit;
+};
+
+// ---------------------------------------------------------------------------
+// initialisation
+
+__global__ void k_init_state(uint32_t n, uint32_t src, unsigned long long *__restrict__ d,
+                             uint8_t *__restrict__ st, uint32_t *__restrict__ phase_of,
+                             uint32_t *__restrict__ out_cur, const uint32_t *__restrict__ rp,
+                             uint32_t *__restrict__ in_cur, const uint32_t *__restrict__ ip,
+                             uint32_t *__restrict__ stamp) {
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        d[v] = v == src ? 0ull : INF64;
+        st[v] = v == src ? ST_F : ST_U;
+        if (phase_of) phase_of[v] = 0;
+        if (out_cur) out_cur[v] = rp[v];
+        if (in_cur) in_cur[v] = ip[v];
+        if (stamp) stamp[v] = 0;
+    }
+}
+
+__global__ void k_init_ctl(Ctl *ctl, const uint2 *__restrict__ vmin, uint32_t src, uint32_t n_deltas) {
+    Ctl c;
+    memset(&c, 0, sizeof c);
+    c.reached = 1;
+    c.minD[0] = 0;
+    c.minD[1] = c.minD[2] = INF64;
+    c.tst[0] = w64(vmin[src].y);  // 0 + minOut[s]
+    c.tst[1] = c.tst[2] = INF64;
+    c.tdyn[0] = c.tdyn[1] = c.tdyn[2] = INF64;
+    c.nextmin[0] = 0;
+    c.nextmin[1] = INF64;
+    c.n_deltas = n_deltas;
+    *ctl = c;
+}
+
+// ---------------------------------------------------------------------------
+// S' append: one packed atomic per wavefront gives consecutive S' slots and
+// consecutive edge offsets; chunk_start[c] records the entry owning edge c*CH.
+
+template <int CH>
+__device__ __forceinline__ void append_settled(const KArgs &a, unsigned long long *spack,
+                                               unsigned long long *szero, bool set, uint32_t v,
+                                               uint32_t deg, unsigned long long dv) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    const bool app = set && deg > 0;
+    const unsigned long long mask = __ballot(app);
+    if (mask) {
+        const uint32_t x = app ? deg : 0u;
+        const uint32_t incl = wave_incl_scan(x);
+        const uint32_t tot = __shfl(incl, 63, 64);
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(spack, ((unsigned long long)__popcll(mask) << 32) | tot);
+        base = __shfl(base, 0, 64);
+        if (app) {
+            const uint32_t j = (uint32_t)(base >> 32) + (uint32_t)__popcll(mask & lt);
+            const uint64_t off = (uint32_t)base + incl - x;
+            a.b.sid[j] = v;
+            a.b.soff[j] = (uint32_t)off;
+            a.b.sdu[j] = dv;
+            for (uint64_t c = (off + CH - 1) / CH; c * CH < off + deg; ++c) a.b.chunk_start[c] = j;
+        }
+    }
+    const bool z = set && deg == 0;
+    const unsigned long long zm = __ballot(z);
+    if (zm) {
+        unsigned long long zb = 0;
+        if (lane == 0) zb = atomicAdd(szero, (unsigned long long)__popcll(zm));
+        zb = __shfl(zb, 0, 64);
+        if (z) a.b.zid[zb + __popcll(zm & lt)] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// term pass (dynamic criteria)
+
+// Minimum weight of an out-edge of x towards a non-settled vertex, read-only
+// walk of x's weight-sorted row (x is unexplored, so no cursor owner exists).
+__device__ __forceinline__ unsigned long long walk_nonsettled(const KArgs &a, uint32_t x) {
+    const uint32_t end = a.g.rp[x + 1];
+    for (uint32_t c = a.g.rp[x]; c < end; ++c) {
+        const uint2 ed = a.g.edges[c];
+        if ((a.b.st[ed.x] & ST_SET) != ST_S) return ed.y;
+    }
+    return INF64;
+}
+
+template <int IN, int OUT>
+__global__ __launch_bounds__(kBlock) void k_terms(KArgs a, int par) {
+    Ctl *ctl = a.b.ctl;
+    const int p3 = par % 3;
+    __shared__ unsigned long long sh[kWaves];
+    if (ctl->reached == ctl->settled) return;
+    const unsigned long long minD = ctl->minD[p3];
+    unsigned long long tmin = INF64;
+    const uint32_t n = a.g.n;
+    for (uint32_t v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) {
+        const uint8_t s = a.b.st[v];
+        if ((s & ST_SET) != ST_F) continue;
+        const unsigned long long dv = a.b.dist[v];
+        if (IN != IN_NONE) {
+            unsigned long long term = INF64;
+            if (IN == IN_SIMPLE_M) {
+                // eq. crit:insimple: lightest in-edge from a non-settled vertex; sorted row + cursor
+                uint32_t cur = a.b.in_cur[v];
+                const uint32_t end = a.g.ip[v + 1];
+                while (cur < end && (a.b.st[a.g.in_edges[cur].x] & ST_SET) == ST_S) ++cur;
+                a.b.in_cur[v] = cur;
+                if (cur < end) term = a.g.in_edges[cur].y;
+            } else {
+                // eq. crit:in: in-edges from F, or from w in U plus w's own lightest in-edge
+                // (every in-neighbour of an unexplored w is queued or unexplored)
+                const uint32_t end = a.g.ip[v + 1];
+                for (uint32_t e = a.g.ip[v]; e < end; ++e) {
+                    const uint2 ie = a.g.in_edges[e];
+                    const uint8_t sw = a.b.st[ie.x] & ST_SET;
+                    if (sw == ST_F) term = umin64(term, ie.y);
+                    else if (sw == ST_U) term = umin64(term, sadd64(ie.y, w64(a.g.vmin[ie.x].x)));
+                }
+            }
+            const bool ok = dv <= sadd64(minD, term);
+            a.b.st[v] = ok ? (uint8_t)(ST_F | ST_INOK) : (uint8_t)ST_F;
+        }
+        if (OUT != OUT_NONE) {
+            unsigned long long term = INF64;
+            const uint32_t end = a.g.rp[v + 1];
+            if (OUT == OUT_SIMPLE_M) {
+                // eq. crit:outsimple (u in F, w in F u U): lightest out-edge to a non-settled vertex
+                uint32_t cur = a.b.out_cur[v];
+                while (cur < end && (a.b.st[a.g.edges[cur].x] & ST_SET) == ST_S) ++cur;
+                a.b.out_cur[v] = cur;
+                if (cur < end) term = a.g.edges[cur].y;
+            } else {
+                for (uint32_t e = a.g.rp[v]; e < end; ++e) {
+                    const uint2 ed = a.g.edges[e];
+                    const uint8_t sx = a.b.st[ed.x] & ST_SET;
+                    if (sx == ST_F) {
+                        term = umin64(term, ed.y);
+                    } else if (sx == ST_U) {
+                        // eq. crit:outweak: second edge over all of V; eq. crit:out: into F u U
+                        const unsigned long long second =
+                            OUT == OUT_WEAK_M ? w64(a.g.vmin[ed.x].y) : walk_nonsettled(a, ed.x);
+                        term = umin64(term, sadd64(ed.y, second));
+                    }
+                }
+            }
+            tmin = umin64(tmin, sadd64(dv, term));
+        }
+    }
+    if (OUT != OUT_NONE) {
+        tmin = block_min64<kWaves>(tmin, sh);
+        if (threadIdx.x == 0 && tmin != INF64) atomicMin(&ctl->tdyn[p3], tmin);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// identify (phased)
+
+// IN: IN_NONE, IN_DIJK, IN_STATIC_M, or 3 = "flag from the term pass".
+// OUT: 0 none, 1 static threshold, 2 threshold from the term pass.
+template <int IN, int OUT, int CH>
+__global__ __launch_bounds__(kBlock) void k_identify(KArgs a, int par) {
+    Ctl *ctl = a.b.ctl;
+    const int p2 = par & 1, p3 = par % 3;
+    __shared__ unsigned long long sh[kWaves];
+    const unsigned long long reached = ctl->reached, settled = ctl->settled;
+    const unsigned int P = ctl->pnum[p2];
+    if (reached == settled) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            ctl->done = 1;
+            ctl->pnum[p2 ^ 1] = P;
+            ctl->spack[p2 ^ 1] = 0;
+            ctl->szero[p2 ^ 1] = 0;
+        }
+        return;
+    }
+    const unsigned long long minD = ctl->minD[p3];
+    const unsigned long long T = OUT == 1 ? ctl->tst[p3] : OUT == 2 ? ctl->tdyn[p3] : 0ull;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->pnum[p2 ^ 1] = P + 1;
+        ctl->phases = P + 1;
+        ctl->sum_f += reached - settled;
+        ctl->spack[p2 ^ 1] = 0;
+        ctl->szero[p2 ^ 1] = 0;
+        ctl->minD[(p3 + 2) % 3] = INF64;
+        ctl->tst[(p3 + 2) % 3] = INF64;
+        ctl->tdyn[(p3 + 1) % 3] = INF64;
+        if (P < a.b.trace_cap) {
+            PhaseRec r;
+            r.min_d = minD;
+            r.fringe = (unsigned int)(reached - settled);
+            r.settled = 0;
+            r.criterion = a.crit;
+            r.edges = 0;
+            a.b.trace[P] = r;
+        }
+    }
+    unsigned long long fmin = INF64, ftst = INF64;
+    const uint32_t n = a.g.n;
+    for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
+        const uint32_t v = base + threadIdx.x;
+        bool set = false;
+        uint32_t deg = 0;
+        unsigned long long dv = INF64;
+        if (v < n) {
+            const uint8_t s = a.b.st[v];
+            if ((s & ST_SET) == ST_F) {
+                dv = a.b.dist[v];
+                bool ok = false;
+                if (IN == IN_DIJK) ok = dv == minD;
+                else if (IN == IN_STATIC_M) ok = dv <= sadd64(minD, w64(a.g.vmin[v].x));
+                else if (IN == 3) ok = (s & ST_INOK) != 0;
+                if (OUT != 0) ok = ok || dv <= T;
+                set = ok;
+                if (set) {
+                    deg = a.g.rp[v + 1] - a.g.rp[v];
+                    a.b.st[v] = ST_S;
+                    if (a.b.phase_of) a.b.phase_of[v] = P + 1;
+                } else {
+                    fmin = umin64(fmin, dv);
+                    ftst = umin64(ftst, sadd64(dv, w64(a.g.vmin[v].y)));
+                }
+            }
+        }
+        append_settled<CH>(a, &ctl->spack[p2], &ctl->szero[p2], set, v, deg, dv);
+    }
+    fmin = block_min64<kWaves>(fmin, sh);
+    ftst = block_min64<kWaves>(ftst, sh);
+    if (threadIdx.x == 0) {
+        if (fmin != INF64) atomicMin(&ctl->minD[(p3 + 1) % 3], fmin);
+        if (ftst != INF64) atomicMin(&ctl->tst[(p3 + 1) % 3], ftst);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// identify (Delta-stepping round)
+
+// Round kinds: 0 = first light round of a bucket (every queued vertex inside
+// the window), 1 = later light round (vertices improved inside the window in
+// the previous round), 2 = heavy round (everything the bucket removed).
+template <int CH>
+__global__ __launch_bounds__(kBlock) void k_identify_delta(KArgs a, int par) {
+    Ctl *ctl = a.b.ctl;
+    const int p2 = par & 1;
+    __shared__ unsigned long long sh[kWaves];
+    const unsigned long long reached = ctl->reached, settled = ctl->settled;
+    const unsigned int P = ctl->pnum[p2];
+    int kind = 0;
+    if (P > 0) {
+        const unsigned int prev = ctl->rmode[p2 ^ 1];
+        kind = prev == 2 ? 0 : (ctl->win_improved[p2 ^ 1] > 0 ? 1 : 2);
+    }
+    if (kind == 0 && reached == settled) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            ctl->done = 1;
+            ctl->pnum[p2 ^ 1] = P;
+            ctl->rmode[p2] = 2;  // later empty rounds stay "after heavy"
+            ctl->spack[p2 ^ 1] = 0;
+            ctl->szero[p2 ^ 1] = 0;
+        }
+        return;
+    }
+    const unsigned int b = kind == 0 ? ctl->buckets : ctl->win_bucket;
+    unsigned long long lo, hi, delta;
+    if (kind == 0) {
+        delta = a.b.deltas[b < ctl->n_deltas ? b : ctl->n_deltas - 1];
+        const unsigned long long mn = ctl->nextmin[b & 1];
+        lo = (mn / delta) * delta;
+        hi = sadd64(lo, delta);
+    } else {
+        lo = ctl->win_lo;
+        hi = ctl->win_hi;
+        delta = ctl->win_delta;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->pnum[p2 ^ 1] = P + 1;
+        ctl->phases = P + 1;
+        ctl->rmode[p2] = kind;
+        ctl->win_improved[p2] = 0;
+        ctl->spack[p2 ^ 1] = 0;
+        ctl->szero[p2 ^ 1] = 0;
+        if (kind == 2) ctl->buckets = b + 1;
+        if (kind == 0) {
+            ctl->win_bucket = b;
+            ctl->win_lo = lo;
+            ctl->win_hi = hi;
+            ctl->win_delta = delta;
+            ctl->nextmin[(b + 1) & 1] = INF64;
+            ctl->sum_f += reached - settled;
+        }
+        if (P < a.b.trace_cap) {
+            PhaseRec r;
+            r.min_d = lo;
+            r.fringe = (unsigned int)(reached - settled);
+            r.settled = 0;
+            r.criterion = kind;
+            r.edges = 0;
+            a.b.trace[P] = r;
+        }
+    }
+    unsigned long long fmin = INF64;
+    const uint32_t n = a.g.n;
+    for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
+        const uint32_t v = base + threadIdx.x;
+        bool set = false;
+        uint32_t deg = 0;
+        unsigned long long dv = INF64;
+        if (v < n) {
+            const uint8_t s = a.b.st[v] & ST_SET;
+            if (kind == 0) {
+                if (s == ST_F) {
+                    dv = a.b.dist[v];
+                    set = dv < hi;
+                }
+            } else if (kind == 1) {
+                if ((s == ST_F || s == ST_R) && a.b.stamp[v] == P) {
+                    dv = a.b.dist[v];
+                    set = true;
+                }
+            } else {
+                if (s == ST_R) {
+                    dv = a.b.dist[v];
+                    set = true;
+                } else if (s == ST_F) {
+                    fmin = umin64(fmin, a.b.dist[v]);  // exact: nothing leaves F until the next bucket
+                }
+            }
+            if (set) {
+                deg = a.g.rp[v + 1] - a.g.rp[v];
+                a.b.st[v] = kind == 2 ? ST_S : ST_R;
+                if (kind == 2 && a.b.phase_of) a.b.phase_of[v] = P + 1;
+            }
+        }
+        append_settled<CH>(a, &ctl->spack[p2], &ctl->szero[p2], set, v, deg, dv);
+    }
+    if (kind == 2) {
+        fmin = block_min64<kWaves>(fmin, sh);
+        if (threadIdx.x == 0 && fmin != INF64) atomicMin(&ctl->nextmin[(b + 1) & 1], fmin);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// relax
+
+template <int CH, bool DELTA>
+__global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
+    Ctl *ctl = a.b.ctl;
+    const int p2 = par & 1, p3 = par % 3;
+    __shared__ uint32_t s_pos[CH + 1];
+    __shared__ uint32_t s_start[CH + 1];
+    __shared__ unsigned long long s_du[CH + 1];
+    __shared__ unsigned long long sh[kWaves];
+    const unsigned long long pk = ctl->spack[p2];
+    const uint32_t ns = (uint32_t)(pk >> 32), E = (uint32_t)pk;
+    const uint32_t nz = (uint32_t)ctl->szero[p2];
+    if ((ns == 0 && nz == 0) || ctl->done) return;
+    const unsigned int P = ctl->pnum[p2];
+    int kind = 0;
+    unsigned long long hi = INF64, delta = 0;
+    if (DELTA) {
+        kind = ctl->rmode[p2] == 2 ? 2 : 1;
+        hi = ctl->win_hi;
+        delta = ctl->win_delta;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (!DELTA || kind == 2) {
+            ctl->settled += ns + nz;
+            ctl->m_reach += E;
+        }
+        if (P < a.b.trace_cap) {
+            a.b.trace[P].settled = ns + nz;
+            a.b.trace[P].edges = E;
+        }
+    }
+    unsigned long long cmin = INF64, ctst = INF64, tried = 0, improv = 0, disc = 0, winimp = 0;
+    const uint32_t nch = (E + CH - 1) / CH;
+    for (uint32_t c = blockIdx.x; c < nch; c += gridDim.x) {
+        const uint32_t e0 = c * CH;
+        const uint32_t len = min(E - e0, (uint32_t)CH);
+        const uint32_t j0 = a.b.chunk_start[c];
+        const uint32_t jend = (c + 1 < nch) ? a.b.chunk_start[c + 1] : ns - 1;
+        const uint32_t cnt = jend - j0 + 1;
+        __syncthreads();
+        for (uint32_t t = threadIdx.x; t < cnt; t += kBlock) {
+            const uint32_t j = j0 + t;
+            const uint32_t off = a.b.soff[j];
+            const uint32_t u = a.b.sid[j];
+            s_pos[t] = off > e0 ? off - e0 : 0u;
+            s_start[t] = a.g.rp[u] + (off > e0 ? 0u : e0 - off);
+            s_du[t] = a.b.sdu[j];
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < len; i += kBlock) {
+            uint32_t lo = 0, hi2 = cnt - 1;  // last entry whose first chunk position is <= i
+            while (lo < hi2) {
+                const uint32_t mid = (lo + hi2 + 1) >> 1;
+                if (s_pos[mid] <= i) lo = mid; else hi2 = mid - 1;
+            }
+            const uint2 ed = a.g.edges[s_start[lo] + (i - s_pos[lo])];
+            const uint32_t v = ed.x;
+            if (DELTA) {
+                if (kind == 1 && ed.y >= delta) continue;  // light: c < delta
+                if (kind == 2 && ed.y < delta) continue;   // heavy: c >= delta
+            }
+            if ((a.b.st[v] & ST_SET) == ST_S) continue;
+            ++tried;
+            const unsigned long long cand = s_du[lo] + ed.y;
+            if (cand < a.b.dist[v]) {
+                const unsigned long long old = atomicMin(&a.b.dist[v], cand);
+                if (cand < old) {
+                    ++improv;
+                    if (!DELTA) {
+                        cmin = umin64(cmin, cand);
+                        ctst = umin64(ctst, sadd64(cand, w64(a.g.vmin[v].y)));
+                    } else if (kind == 2) {
+                        cmin = umin64(cmin, cand);
+                    } else if (cand < hi) {
+                        const unsigned int prev = atomicExch(&a.b.stamp[v], P + 1);
+                        if (prev != P + 1) ++winimp;
+                    }
+                    if (old == INF64) {
+                        a.b.st[v] = ST_F;
+                        ++disc;
+                    }
+                }
+            }
+        }
+    }
+    cmin = block_min64<kWaves>(cmin, sh);
+    tried = block_sum64<kWaves>(tried, sh);
+    improv = block_sum64<kWaves>(improv, sh);
+    disc = block_sum64<kWaves>(disc, sh);
+    if (!DELTA) ctst = block_min64<kWaves>(ctst, sh);
+    if (DELTA) winimp = block_sum64<kWaves>(winimp, sh);
+    if (threadIdx.x == 0) {
+        if (cmin != INF64) {
+            if (!DELTA) atomicMin(&ctl->minD[(p3 + 1) % 3], cmin);
+            else atomicMin(&ctl->nextmin[(ctl->win_bucket + 1) & 1], cmin);
+        }
+        if (!DELTA && ctst != INF64) atomicMin(&ctl->tst[(p3 + 1) % 3], ctst);
+        if (tried) atomicAdd(&ctl->relax_edges, tried);
+        if (improv) atomicAdd(&ctl->improving, improv);
+        if (disc) atomicAdd(&ctl->reached, disc);
+        if (winimp) atomicAdd(&ctl->win_improved[p2], winimp);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+
+DevGraph dev_view(const sssp_graph *g) {
+    DevGraph d;
+    d.n = g->n;
+    d.m = g->m;
+    d.rp = g->rp;
+    d.edges = g->edges;
+    d.vmin = g->vmin;
+    d.ip = g->ip;
+    d.in_edges = g->in_edges;
+    return d;
+}
+
+static int num_cus() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        hipDeviceProp_t p;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess)
+            cus = p.multiProcessorCount;
+        if (cus <= 0) cus = 256;
+    }
+    return cus;
+}
+
+void graph_default_cfg(sssp_graph *g) {
+    const int cus = num_cus();
+    uint64_t sb = ((uint64_t)g->n + kBlock * 4 - 1) / (kBlock * 4);
+    if (sb < 1) sb = 1;
+    if (sb > (uint64_t)cus * 8) sb = (uint64_t)cus * 8;
+    g->cfg.scan_blocks = (int)sb;
+    g->cfg.chunk = 512;
+    uint64_t rb = (g->m + g->cfg.chunk - 1) / g->cfg.chunk;
+    if (rb < 1) rb = 1;
+    if (rb > (uint64_t)cus * 8) rb = (uint64_t)cus * 8;
+    g->cfg.relax_blocks = (int)rb;
+}
+
+void solve_bufs_free(sssp_graph *g) {
+    SolveBufs &b = g->b;
+    sssp_free(b.ctl); sssp_free(b.st); sssp_free(b.sid); sssp_free(b.soff); sssp_free(b.sdu); sssp_free(b.zid);
+    sssp_free(b.chunk_start); sssp_free(b.in_cur); sssp_free(b.out_cur); sssp_free(b.stamp); sssp_free(b.deltas);
+    if (g->h_ctl) sssp_host_free(g->h_ctl);
+    for (int i = 0; i < 2; ++i) if (g->ev[i]) (void)hipEventDestroy(g->ev[i]);
+    memset(&b, 0, sizeof b);
+    g->h_ctl = nullptr;
+    g->ev[0] = g->ev[1] = nullptr;
+    g->bufs_ready = false;
+}
+
+int solve_bufs_ensure(sssp_graph *g, bool cursors, bool stamps) {
+    SolveBufs &b = g->b;
+    const uint64_t n = g->n;
+    if (!g->bufs_ready) {
+        g->chunk_cap = g->m / 256 + 2;
+        HIP_OK(hipMalloc(&b.ctl, sizeof(Ctl)));
+        HIP_OK(hipMalloc(&b.st, n));
+        HIP_OK(hipMalloc(&b.sid, n * 4));
+        HIP_OK(hipMalloc(&b.soff, n * 4));
+        HIP_OK(hipMalloc(&b.sdu, n * 8));
+        HIP_OK(hipMalloc(&b.zid, n * 4));
+        HIP_OK(hipMalloc(&b.chunk_start, g->chunk_cap * 4));
+        HIP_OK(hipHostMalloc((void **)&g->h_ctl, 2 * sizeof(Ctl), hipHostMallocDefault));
+        HIP_OK(hipEventCreateWithFlags(&g->ev[0], hipEventDisableTiming));
+        HIP_OK(hipEventCreateWithFlags(&g->ev[1], hipEventDisableTiming));
+        g->bufs_ready = true;
+    }
+    if (cursors && !b.out_cur) {
+        HIP_OK(hipMalloc(&b.in_cur, n * 4));
+        HIP_OK(hipMalloc(&b.out_cur, n * 4));
+    }
+    if (stamps && !b.stamp) HIP_OK(hipMalloc(&b.stamp, n * 4));
+    return SSSP_OK;
+}
+
+typedef void (*kfn)(KArgs, int);
+
+template <int CH>
+static kfn pick_identify(int in, int out) {
+    // in: IN_NONE, IN_DIJK, IN_STATIC_M, >= IN_SIMPLE_M -> flag (3)
+    // out: OUT_NONE, OUT_STATIC_M, dynamic -> 2
+    const int i = in >= IN_SIMPLE_M ? 3 : in;
+    const int o = out >= OUT_SIMPLE_M ? 2 : out;
+    static const kfn tab[4][3] = {
+        {k_identify<0, 0, CH>, k_identify<0, 1, CH>, k_identify<0, 2, CH>},
+        {k_identify<1, 0, CH>, k_identify<1, 1, CH>, k_identify<1, 2, CH>},
+        {k_identify<2, 0, CH>, k_identify<2, 1, CH>, k_identify<2, 2, CH>},
+        {k_identify<3, 0, CH>, k_identify<3, 1, CH>, k_identify<3, 2, CH>}};
+    return tab[i][o];
+}
+
+static kfn pick_terms(int in, int out) {
+    const int i = in == IN_SIMPLE_M ? 1 : in == IN_FULL_M ? 2 : 0;
+    const int o = out == OUT_SIMPLE_M ? 1 : out == OUT_WEAK_M ? 2 : out == OUT_FULL_M ? 3 : 0;
+    static const kfn tab[3][4] = {
+        {nullptr, k_terms<0, OUT_SIMPLE_M>, k_terms<0, OUT_WEAK_M>, k_terms<0, OUT_FULL_M>},
+        {k_terms<IN_SIMPLE_M, 0>, k_terms<IN_SIMPLE_M, OUT_SIMPLE_M>, k_terms<IN_SIMPLE_M, OUT_WEAK_M>,
+         k_terms<IN_SIMPLE_M, OUT_FULL_M>},
+        {k_terms<IN_FULL_M, 0>, k_terms<IN_FULL_M, OUT_SIMPLE_M>, k_terms<IN_FULL_M, OUT_WEAK_M>,
+         k_terms<IN_FULL_M, OUT_FULL_M>}};
+    return tab[i][o];
+}
+
+struct PhaseKernels {
+    kfn terms = nullptr, identify = nullptr, relax = nullptr;
+};
+
+static PhaseKernels pick_phase(int chunk, int in, int out, bool delta) {
+    PhaseKernels k;
+    if (delta) {
+        switch (chunk) {
+        case 256: k.identify = k_identify_delta<256>; k.relax = k_relax<256, true>; break;
+        case 1024: k.identify = k_identify_delta<1024>; k.relax = k_relax<1024, true>; break;
+        default: k.identify = k_identify_delta<512>; k.relax = k_relax<512, true>; break;
+        }
+        return k;
+    }
+    k.terms = pick_terms(in, out);
+    switch (chunk) {
+    case 256: k.identify = pick_identify<256>(in, out); k.relax = k_relax<256, false>; break;
+    case 1024: k.identify = pick_identify<1024>(in, out); k.relax = k_relax<1024, false>; break;
+    default: k.identify = pick_identify<512>(in, out); k.relax = k_relax<512, false>; break;
+    }
+    return k;
+}
+
+static int valid_chunk(int c) { return c == 256 || c == 512 || c == 1024; }
+
+// Runs the phase loop: queues phases in growing batches, keeps one batch in
+// flight while the host inspects the previous batch's copy of the control
+// block, and stops once a batch ends with F empty.
+static int run_loop(sssp_graph *g, const KArgs &a, const PhaseKernels &K, uint64_t max_phases) {
+    hipStream_t s = g->stream;
+    const dim3 blk(kBlock);
+    const dim3 gs(g->cfg.scan_blocks), gr(g->cfg.relax_blocks);
+    uint64_t k = 0;
+    uint32_t batch = 4;
+    int slot = 0;
+    bool have_prev = false;
+    for (;;) {
+        for (uint32_t i = 0; i < batch; ++i, ++k) {
+            const int par = (int)(k % 6);
+            if (K.terms) hipLaunchKernelGGL(K.terms, gs, blk, 0, s, a, par);
+            hipLaunchKernelGGL(K.identify, gs, blk, 0, s, a, par);
+            hipLaunchKernelGGL(K.relax, gr, blk, 0, s, a, par);
+        }
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipMemcpyAsync(&g->h_ctl[slot], a.b.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipEventRecord(g->ev[slot], s));
+        if (have_prev) {
+            HIP_OK(hipEventSynchronize(g->ev[slot ^ 1]));
+            if (g->h_ctl[slot ^ 1].done) break;
+        }
+        have_prev = true;
+        slot ^= 1;
+        if (batch < 64) batch *= 2;
+        if (k > max_phases + 2 * 64 + 8)
+            return sssp_set_error(SSSP_ERR_INTERNAL, "phase loop did not terminate after %llu phases",
+                                  (unsigned long long)k);
+    }
+    HIP_OK(hipStreamSynchronize(s));
+    HIP_OK(hipMemcpy(&g->h_ctl[0], a.b.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    if (!g->h_ctl[0].done) return sssp_set_error(SSSP_ERR_INTERNAL, "solve ended without an empty fringe");
+    return SSSP_OK;
+}
+
+static void fill_stats(const sssp_graph *g, const Ctl &c, sssp_stats *st) {
+    if (!st) return;
+    st->phases = c.phases;
+    st->buckets = c.buckets;
+    st->sum_f = c.sum_f;
+    st->n_reach = c.settled;
+    st->m_reach = c.m_reach;
+    st->relax_edges = c.relax_edges;
+    st->improving = c.improving;
+    st->precompute_ns = g->precompute_ns;
+}
+
+static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_t crit,
+                        const uint64_t *deltas, uint32_t n_deltas, uint64_t *dist_out,
+                        sssp_stats *stats, uint32_t *phase_of, sssp_phase_rec *trace,
+                        uint32_t trace_cap) {
+    if (!g) return sssp_set_error(SSSP_ERR_INVALID, "graph is NULL");
+    if (!dist_out) return sssp_set_error(SSSP_ERR_INVALID, "dist_out is NULL");
+    if (source >= g->n) return sssp_set_error(SSSP_ERR_INVALID, "source %u >= n = %u", source, g->n);
+    if (trace_cap && !trace) return sssp_set_error(SSSP_ERR_INVALID, "trace is NULL but trace_cap > 0");
+    int in = IN_NONE, out = OUT_NONE;
+    if (!delta_mode) {
+        if (crit == 0 || (crit & ~SSSP_CRIT_ALL))
+            return sssp_set_error(SSSP_ERR_INVALID, "criterion 0x%x is empty or has unknown bits", crit);
+        crit_modes(crit, &in, &out);
+    } else {
+        if (!deltas || n_deltas == 0) return sssp_set_error(SSSP_ERR_INVALID, "no bucket width given");
+        for (uint32_t i = 0; i < n_deltas; ++i)
+            if (deltas[i] == 0) return sssp_set_error(SSSP_ERR_INVALID, "bucket width must be >= 1");
+    }
+    if (!valid_chunk(g->cfg.chunk)) return sssp_set_error(SSSP_ERR_INTERNAL, "bad chunk size");
+    HIP_OK(hipSetDevice(g->device));
+    const bool dyn = in >= IN_SIMPLE_M || out >= OUT_SIMPLE_M;
+    if (in >= IN_SIMPLE_M) {
+        int rc = graph_ensure_csc(g);
+        if (rc) return rc;
+    }
+    int rc = solve_bufs_ensure(g, dyn, delta_mode);
+    if (rc) return rc;
+    if (delta_mode && g->delta_cap < n_deltas) {
+        sssp_free(g->b.deltas);
+        g->b.deltas = nullptr;
+        HIP_OK(hipMalloc(&g->b.deltas, n_deltas * sizeof(unsigned long long)));
+        g->delta_cap = n_deltas;
+    }
+    hipStream_t s = g->stream;
+    if (delta_mode)
+        HIP_OK(hipMemcpyAsync(g->b.deltas, deltas, n_deltas * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    KArgs a;
+    a.g = dev_view(g);
+    a.b = g->b;
+    a.b.dist = (unsigned long long *)dist_out;
+    a.b.phase_of = phase_of;
+    a.b.trace = nullptr;
+    a.b.trace_cap = 0;
+    a.crit = crit;
+    if (trace_cap) {
+        HIP_OK(hipMalloc(&a.b.trace, (uint64_t)trace_cap * sizeof(PhaseRec)));
+        a.b.trace_cap = trace_cap;
+    }
+    const int ib = (int)(((uint64_t)g->n + 255) / 256 > 8192 ? 8192 : ((uint64_t)g->n + 255) / 256);
+    hipLaunchKernelGGL(k_init_state, dim3(ib), dim3(256), 0, s, g->n, source, a.b.dist, a.b.st, phase_of,
+                       dyn ? a.b.out_cur : nullptr, g->rp, (in >= IN_SIMPLE_M) ? a.b.in_cur : nullptr,
+                       g->ip, delta_mode ? a.b.stamp : nullptr);
+    hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(1), 0, s, a.b.ctl, g->vmin, source, n_deltas);
+    const PhaseKernels K = pick_phase(g->cfg.chunk, in, out, delta_mode);
+    // phases <= reachable vertices; Delta rounds <= 2 * n + light rounds bounded by n per bucket
+    // Delta: light rounds per bucket <= window vertices + 1, one heavy round per bucket
+    const uint64_t max_phases = delta_mode ? 4ull * g->n + 64 : (uint64_t)g->n + 2;
+    rc = run_loop(g, a, K, max_phases);
+    if (rc == SSSP_OK) {
+        fill_stats(g, g->h_ctl[0], stats);
+        if (trace_cap) {
+            uint32_t cnt = g->h_ctl[0].phases < trace_cap ? g->h_ctl[0].phases : trace_cap;
+            if (cnt && hipMemcpy(trace, a.b.trace, cnt * sizeof(PhaseRec), hipMemcpyDeviceToHost) != hipSuccess)
+                rc = sssp_set_error(SSSP_ERR_DEVICE, "trace copy failed");
+        }
+    }
+    if (a.b.trace) sssp_free(a.b.trace);
+    return rc;
+}
+
+extern "C" int sssp_solve(sssp_graph *g, uint32_t source, uint32_t criterion, uint64_t *dist_out,
+                          uint32_t *phases_out) {
+    sssp_stats st;
+    int rc = solve_common(g, source, false, criterion, nullptr, 0, dist_out, &st, nullptr, nullptr, 0);
+    if (rc == SSSP_OK && phases_out) *phases_out = st.phases;
+    return rc;
+}
+
+extern "C" int sssp_solve_ex(sssp_graph *g, uint32_t source, uint32_t criterion, uint64_t *dist_out,
+                             sssp_stats *stats, uint32_t *phase_of, sssp_phase_rec *trace,
+                             uint32_t trace_cap) {
+    return solve_common(g, source, false, criterion, nullptr, 0, dist_out, stats, phase_of, trace, trace_cap);
+}
+
+extern "C" int sssp_delta_step(sssp_graph *g, uint32_t source, uint64_t delta, uint64_t *dist_out,
+                               uint32_t *phases_out) {
+    if (delta == 0) return sssp_set_error(SSSP_ERR_INVALID, "delta must be >= 1");
+    sssp_stats st;
+    int rc = solve_common(g, source, true, 0, &delta, 1, dist_out, &st, nullptr, nullptr, 0);
+    if (rc == SSSP_OK && phases_out) *phases_out = st.phases;
+    return rc;
+}
+
+extern "C" int sssp_delta_step_ex(sssp_graph *g, uint32_t source, const uint64_t *deltas, uint32_t n_deltas,
+                                  uint64_t *dist_out, sssp_stats *stats, sssp_phase_rec *trace,
+                                  uint32_t trace_cap) {
+    return solve_common(g, source, true, 0, deltas, n_deltas, dist_out, stats, nullptr, trace, trace_cap);
+}

@@ -1,0 +1,167 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, element by element.
+
+Distances must be bit-exact (all arithmetic is integer). Phase counts, the phase in which each
+vertex settles, the summed fringe sizes and the number of relaxations towards non-settled targets
+are unique under the phase-start snapshot semantics (Section 3) and must match exactly.
+Delta-stepping: distances exact, rounds and buckets exact under the round rules stated in the oracle.
+"""
+import numpy as np
+import pytest
+
+import graphgen as G
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+CRITS = [("DIJK", O.DIJK), ("IN_STATIC", O.IN_STATIC), ("OUT_STATIC", O.OUT_STATIC),
+         ("IN_SIMPLE", O.IN_SIMPLE), ("OUT_SIMPLE", O.OUT_SIMPLE), ("IN_FULL", O.IN_FULL),
+         ("OUT_WEAK", O.OUT_WEAK), ("OUT_FULL", O.OUT_FULL), ("STATIC_OR", O.STATIC_OR),
+         ("SIMPLE_OR", O.SIMPLE_OR), ("FULL_OR", O.FULL_OR), ("IN_FULL|OUT_WEAK", O.IN_FULL | O.OUT_WEAK),
+         ("DIJK|OUT_STATIC", O.DIJK | O.OUT_STATIC), ("IN_STATIC|OUT_FULL", O.IN_STATIC | O.OUT_FULL)]
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    from paper_1903_12085_amd import binding
+    binding.load()
+    return binding
+
+
+def check_phased(B, g, src, crit, label=""):
+    dg = B.DeviceGraph.from_graph(g)
+    ref = O.phased(g, src, crit)
+    r = B.solve_ex(dg, src, crit, phase_of=True, trace_cap=ref.phases + 4)
+    got = r.dist_u64()
+    assert np.array_equal(got, ref.dist), "%s: distances differ at %d vertices" % (label, int((got != ref.dist).sum()))
+    assert r.phases == ref.phases, "%s: phases %d != oracle %d" % (label, r.phases, ref.phases)
+    po = r.phase_of.cpu().numpy().view(np.uint32)
+    assert np.array_equal(po, ref.phase_of), "%s: settle phases differ" % label
+    st = r.stats
+    assert st["sum_f"] == ref.sum_f, label
+    assert st["n_reach"] == ref.n_reach and st["m_reach"] == ref.m_reach, label
+    assert st["relax_edges"] == ref.relax_edges, label
+    assert np.array_equal(r.trace["fringe"], ref.trace_f), label
+    assert np.array_equal(r.trace["settled"], ref.trace_s), label
+    assert np.array_equal(r.trace["min_d"], ref.trace_mind), label
+    dg.close()
+    return r
+
+
+def small_cases():
+    out = []
+    for s in range(60):
+        x = G.u64_stream(s, 21, 3)
+        n = 1 + int(x[0] % np.uint64(40))
+        m = int(x[1] % np.uint64(5 * n + 1))
+        wmax = [1, 4, 100, 0xFFFFFFFF][int(x[2] % np.uint64(4))]
+        out.append(G.random_small(n, m, wmax, 100 + s))
+    return out
+
+
+def test_hand_traces_all_criteria(B):
+    import json, os
+    fix = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "hand_traces.json")))
+    for key, ent in fix["graphs"].items():
+        g = G.from_edges(ent["n"], ent["edges"])
+        for name, c in CRITS:
+            check_phased(B, g, 0, c, "%s/%s" % (key, name))
+
+
+def test_random_multigraphs_all_criteria(B):
+    # zero weights, self-loops, parallel edges, unreachable parts, weights up to 2^32-1
+    for g in small_cases():
+        src = int(G.u64_stream(7, 3, 1)[0] % np.uint64(g.n))
+        for name, c in CRITS:
+            check_phased(B, g, src, c, "%s/%s" % (g.name, name))
+
+
+@pytest.mark.parametrize("name,c", CRITS)
+def test_config_small_er16k(B, name, c):
+    check_phased(B, G.config_small(), 0, c, "er16k/" + name)
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: G.er(1 << 15, 16, 1, (1 << 20) - 1, 5),
+    lambda: G.rmat(14, 16, 1, (1 << 20) - 1, 6),
+    lambda: G.grid(96, 80, 1, 1 << 16, 7),
+    lambda: G.er(5000, 3, 1, 7, 8),          # many ties, sparse: unreachable vertices
+])
+def test_medium_graphs_key_criteria(B, maker):
+    g = maker()
+    src = int(G.sources(g, 1, 3)[0])
+    for name, c in [("STATIC_OR", O.STATIC_OR), ("SIMPLE_OR", O.SIMPLE_OR), ("FULL_OR", O.FULL_OR),
+                    ("IN_STATIC", O.IN_STATIC), ("OUT_WEAK", O.OUT_WEAK), ("DIJK", O.DIJK)]:
+        check_phased(B, g, src, c, "%s/%s" % (g.name, name))
+
+
+def test_edge_cases(B):
+    one = G.from_edges(1, [])
+    r = B.solve(B.DeviceGraph.from_graph(one), 0, O.STATIC_OR)
+    assert r.phases == 1 and list(r.dist_u64()) == [0]
+    loop = G.from_edges(2, [(0, 0, 5), (1, 0, 3)])  # self-loop on the source, vertex 1 unreachable
+    check_phased(B, loop, 0, O.FULL_OR, "selfloop")
+    sink = G.from_edges(4, [(1, 2, 1), (2, 3, 1)])  # source without out-edges
+    check_phased(B, sink, 0, O.STATIC_OR, "sink-source")
+    heavy = G.from_edges(3, [(0, 1, 0xFFFFFFFF), (1, 2, 0xFFFFFFFF), (0, 2, 0xFFFFFFFF)])
+    r = check_phased(B, heavy, 0, O.SIMPLE_OR, "max-weights")
+    assert int(r.dist_u64()[2]) == 0xFFFFFFFF
+
+
+def test_repeat_runs_are_identical(B):
+    g = G.rmat(13, 16, 1, 1000, 9)
+    dg = B.DeviceGraph.from_graph(g)
+    a = B.solve_ex(dg, 0, O.STATIC_OR, phase_of=True, trace_cap=4096)
+    b = B.solve_ex(dg, 0, O.STATIC_OR, phase_of=True, trace_cap=4096)
+    assert np.array_equal(a.dist_u64(), b.dist_u64())
+    assert np.array_equal(a.trace, b.trace)
+    assert np.array_equal(a.phase_of.cpu().numpy(), b.phase_of.cpu().numpy())
+
+
+def test_static_minima_on_device(B):
+    g = G.random_small(300, 1500, 1000, 4)
+    mi, mo = B.DeviceGraph.from_graph(g).minima()
+    rmi, rmo = O.static_minima(g)
+    assert np.array_equal(mi.cpu().numpy().view(np.uint32), rmi)
+    assert np.array_equal(mo.cpu().numpy().view(np.uint32), rmo)
+
+
+def check_delta(B, g, src, deltas):
+    dg = B.DeviceGraph.from_graph(g)
+    ref = O.delta_step(g, src, deltas, trace_cap=0)
+    r = B.delta_step_ex(dg, src, deltas)
+    got = r.dist_u64()
+    assert np.array_equal(got, ref.dist), "delta %s: distances differ" % (deltas,)
+    assert r.phases == ref.rounds, "delta %s: rounds %d != %d" % (deltas, r.phases, ref.rounds)
+    assert r.stats["buckets"] == ref.buckets
+    dg.close()
+
+
+def test_delta_stepping_small(B):
+    for g in small_cases()[:30]:
+        for deltas in ([1], [3], [1000], [1 << 40], [2, 50, 7]):
+            check_delta(B, g, 0, deltas)
+
+
+@pytest.mark.parametrize("delta", [1 << 12, 1 << 14, 1 << 16])
+def test_delta_stepping_medium(B, delta):
+    for g in (G.er(1 << 14, 16, 1, (1 << 20) - 1, 3), G.rmat(13, 16, 1, (1 << 20) - 1, 4),
+              G.grid(64, 64, 1, 1 << 16, 5)):
+        check_delta(B, g, int(G.sources(g, 1, 1)[0]), [delta])
+
+
+def test_invalid_arguments_rejected(B):
+    g = G.config_small()
+    dg = B.DeviceGraph.from_graph(g)
+    with pytest.raises(B.SsspError):
+        B.solve(dg, g.n, O.STATIC_OR)        # source out of range
+    with pytest.raises(B.SsspError):
+        B.solve(dg, 0, 0)                    # empty criterion
+    with pytest.raises(B.SsspError):
+        B.solve(dg, 0, 1 << 9)               # unknown bit
+    with pytest.raises(B.SsspError):
+        B.delta_step(dg, 0, 0)               # zero bucket width
+    r = B.solve(dg, 0, O.STATIC_OR)          # the handle still works afterwards
+    assert r.phases > 1
