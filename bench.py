@@ -1,0 +1,167 @@
+#!/usr/bin/env python3
+"""Benchmark: GTEPS and phases per SSSP solve on one MI355X.
+
+Workload (the headline configuration): directed random graph, n = 2^22 vertices, each with 16
+distinct uniform random out-neighbours, uint32 weights uniform in [1, 2^20), source 0, seed 1;
+plain phased solver with the combined IN-STATIC | OUT-STATIC criterion, uint64 distances.
+A step = one whole solve (every phase: identify, compaction, relaxation) with the graph already
+resident in HBM. GTEPS = out-edges of reachable vertices / solve time.
+
+Also reported (outside the timed region): the other criteria and Delta-stepping on the same
+graph, the dominant kernel's roofline fraction (algorithmic bytes / HIP-event kernel time vs the
+8 TB/s HBM peak), and the CPU oracle (binary-heap Dijkstra, one core) timed on the host.
+
+usage: python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu] [--no-extra]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "GTEPS + phases per SSSP; plain vs batched/learned on 1 GPU, distances exact"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def alg_bytes(kernel, st, phases):
+    """Algorithmic bytes per launch of a phase kernel (per-unit figures from the design notes)."""
+    if kernel == "identify":
+        return 24.0 * st["sum_f"] / phases  # id 4 + d 8 + minIn 4 + minOut 4 + compacted write 4 per queued vertex
+    # relax: per S' vertex 16 B (row range 8, id + snapshot distance 8); per edge 16 B (target+weight 8,
+    # target distance 8); per improving relaxation 8 B (the atomic write)
+    return (16.0 * st["n_reach"] + 16.0 * st["relax_edges"] + 8.0 * st["improving"]) / phases
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--log2n", type=int, default=22)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the solver runs on a single device "
+              "(multi-GPU sharding is a design note, not built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import graphgen as G
+    from paper_1903_12085_amd import binding as B
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    B.load()
+    seed, src = 1, 0
+    t = time.time()
+    g = G.config_er_large(seed=seed, log2n=args.log2n)
+    log("graph n=%d m=%d generated in %.1fs" % (g.n, g.m, time.time() - t))
+    t = time.time()
+    dg = B.DeviceGraph.from_graph(g)
+    torch.cuda.synchronize()
+    log("device graph ready in %.1fs" % (time.time() - t))
+    crit = B.STATIC_OR
+    dist = B.new_dist(g.n)
+
+    for _ in range(args.warmup):
+        B.solve(dg, src, crit, dist)
+    torch.cuda.synchronize()
+    log("warmup done")
+    phases = None
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        phases = B.solve(dg, src, crit, dist).phases
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    log("timed %d steps: %.3f ms/step, %d phases" % (args.steps, ms, phases))
+
+    r = B.solve_ex(dg, src, crit, dist)
+    st = r.stats
+    gteps = st["m_reach"] / (ms * 1e-3) / 1e9
+
+    # per-kernel HIP-event timing on the solve stream (same workload, separate pass)
+    dg.profile(True)
+    prof_ms = []
+    for _ in range(max(1, min(args.steps, 3))):
+        tp = time.perf_counter()
+        B.solve(dg, src, crit, dist)
+        torch.cuda.synchronize()
+        prof_ms.append((time.perf_counter() - tp) * 1e3)
+    prof = dg.last_profile()
+    dg.profile(False)
+    kern = "identify" if prof["identify_ms"] >= prof["relax_ms"] else "relax"
+    kms = prof[kern + "_ms"]
+    per_launch = alg_bytes(kern, st, prof["phases"])
+    avg_us = kms * 1e3 / prof["phases"]
+    achieved = per_launch / (avg_us * 1e-6) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_" + kern,
+                "alg_bytes_per_launch": round(per_launch), "avg_launch_us": round(avg_us, 2),
+                "launches": prof["phases"], "identify_ms": round(prof["identify_ms"], 3),
+                "relax_ms": round(prof["relax_ms"], 3)}
+    log("profile", prof)
+
+    out = {
+        "metric": METRIC, "value": round(gteps, 4), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "er_n%d_outdeg16_w1-2^20_src0" % g.n, "n": g.n, "m": g.m, "seed": seed,
+                   "source": src, "criterion": "IN_STATIC|OUT_STATIC", "form": "plain"},
+        "phases": phases, "sum_f": st["sum_f"], "m_reach": st["m_reach"], "n_reach": st["n_reach"],
+        "us_per_phase": round(ms * 1e3 / phases, 2), "precompute_ms": round(st["precompute_ns"] / 1e6, 3),
+        "gteps_incl_precompute": round(st["m_reach"] / ((ms + st["precompute_ns"] / 1e6) * 1e-3) / 1e9, 4),
+        "roofline": roofline,
+    }
+
+    if not args.no_extra:
+        forms = {}
+        for name, c in [("IN_STATIC", B.IN_STATIC), ("OUT_STATIC", B.OUT_STATIC), ("SIMPLE_OR", B.SIMPLE_OR),
+                        ("IN_FULL|OUT_WEAK", B.IN_FULL | B.OUT_WEAK), ("FULL_OR", B.FULL_OR)]:
+            B.solve(dg, src, c, dist)
+            torch.cuda.synchronize()
+            tt = time.perf_counter()
+            ph = B.solve(dg, src, c, dist).phases
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - tt
+            forms[name] = {"phases": ph, "ms": round(dt * 1e3, 3), "gteps": round(st["m_reach"] / dt / 1e9, 4)}
+            log("criterion", name, forms[name])
+        for k in (12, 14, 16):
+            B.delta_step(dg, src, 1 << k, dist)
+            torch.cuda.synchronize()
+            tt = time.perf_counter()
+            ph = B.delta_step(dg, src, 1 << k, dist).phases
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - tt
+            forms["delta_2^%d" % k] = {"rounds": ph, "ms": round(dt * 1e3, 3),
+                                       "gteps": round(st["m_reach"] / dt / 1e9, 4)}
+            log("delta", k, forms["delta_2^%d" % k])
+        out["forms"] = forms
+
+    if not args.no_cpu:
+        import oracle as O
+        tc = time.perf_counter()
+        ref, _ = O.dijkstra(g, src)
+        tcpu = time.perf_counter() - tc
+        got = B.to_u64(dist) if args.no_extra else B.to_u64(B.solve(dg, src, crit, dist).dist)
+        out["distances_exact"] = bool(np.array_equal(got, ref))
+        out["cpu_baseline"] = {"value": round(st["m_reach"] / tcpu / 1e9, 5), "unit": "GTEPS", "cores": 1,
+                               "kind": "oracle", "seconds": round(tcpu, 2),
+                               "sample": "one full solve of the same graph and source with the oracle's "
+                                         "binary-heap Dijkstra (single thread)"}
+        log("cpu oracle %.1fs, exact=%s" % (tcpu, out["distances_exact"]))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -169,6 +169,22 @@ int sssp_delta_step_ex(sssp_graph *g, uint32_t source, const uint64_t *deltas, u
 int sssp_solve_batch(sssp_graph *const *graphs, const uint32_t *sources, uint32_t nq,
                      uint32_t criterion, uint64_t *const *dist_outs, uint32_t *phases_out);
 
+/* Per-kernel device time of the last solve on g, measured with HIP events on
+ * the graph's stream around every kernel launch (observability; enabling it
+ * adds one host synchronisation per batch of queued phases). */
+typedef struct {
+    uint32_t phases;       /* non-empty phases (or rounds) that were timed */
+    float term_ms;         /* total time of the dynamic-term pass kernels */
+    float identify_ms;     /* total time of the identify kernels */
+    float relax_ms;        /* total time of the relax kernels */
+} sssp_kernel_profile;
+
+/* Turn per-kernel event timing on (enable != 0) or off for later solves on g. */
+int sssp_profile_enable(sssp_graph *g, int enable);
+
+/* Read the per-kernel times of the last solve run with timing on. */
+int sssp_profile_get(const sssp_graph *g, sssp_kernel_profile *out);
+
 /* Human-readable description of the last error on the calling thread. */
 const char *sssp_last_error(void);
 

@@ -24,7 +24,8 @@ SIMPLE_OR = IN_SIMPLE | OUT_SIMPLE
 FULL_OR = IN_FULL | OUT_FULL
 
 SYMBOLS = ["sssp_graph_create", "sssp_graph_destroy", "sssp_set_stream", "sssp_graph_minima", "sssp_solve",
-           "sssp_solve_ex", "sssp_delta_step", "sssp_delta_step_ex", "sssp_solve_batch", "sssp_last_error"]
+           "sssp_solve_ex", "sssp_delta_step", "sssp_delta_step_ex", "sssp_solve_batch", "sssp_last_error",
+           "sssp_profile_enable", "sssp_profile_get"]
 
 ERRORS = {-1: "SSSP_ERR_INVALID", -2: "SSSP_ERR_OOM", -3: "SSSP_ERR_DEVICE", -4: "SSSP_ERR_UNSUPPORTED",
           -5: "SSSP_ERR_INTERNAL"}
@@ -43,6 +44,14 @@ class Stats(ctypes.Structure):
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class KernelProfile(ctypes.Structure):
+    _fields_ = [("phases", ctypes.c_uint32), ("term_ms", ctypes.c_float), ("identify_ms", ctypes.c_float),
+                ("relax_ms", ctypes.c_float)]
+
+    def as_dict(self):
+        return {k: (int(getattr(self, k)) if k == "phases" else float(getattr(self, k))) for k, _ in self._fields_}
 
 
 PHASE_REC = np.dtype([("min_d", np.uint64), ("fringe", np.uint32), ("settled", np.uint32),
@@ -69,6 +78,8 @@ def load(path: str = LIB_PATH):
     lib.sssp_delta_step.argtypes = [P, u32, u64, P, P]
     lib.sssp_delta_step_ex.argtypes = [P, u32, P, u32, P, ctypes.POINTER(Stats), P, u32]
     lib.sssp_solve_batch.argtypes = [P, P, u32, u32, P, P]
+    lib.sssp_profile_enable.argtypes = [P, i]
+    lib.sssp_profile_get.argtypes = [P, ctypes.POINTER(KernelProfile)]
     lib.sssp_last_error.restype = ctypes.c_char_p
     lib.sssp_last_error.argtypes = []
     for name in SYMBOLS:
@@ -135,6 +146,14 @@ class DeviceGraph:
 
     def _bind_stream(self):
         load().sssp_set_stream(self._h, _stream_ptr())
+
+    def profile(self, enable: bool):
+        _check(load().sssp_profile_enable(self._h, int(enable)))
+
+    def last_profile(self) -> dict:
+        p = KernelProfile()
+        _check(load().sssp_profile_get(self._h, ctypes.byref(p)))
+        return p.as_dict()
 
     def minima(self):
         import torch

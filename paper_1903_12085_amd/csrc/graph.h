@@ -22,6 +22,11 @@ struct sssp_graph {
     uint32_t delta_cap = 0;        // entries of b.deltas
     Ctl *h_ctl = nullptr;          // pinned host mirror of the control block
     hipEvent_t ev[2] = {nullptr, nullptr};
+    // per-kernel event timing
+    bool prof = false;
+    hipEvent_t *pev = nullptr;     // 4 events per phase of one batch
+    uint32_t pev_cap = 0;
+    sssp_kernel_profile last_prof{};
 };
 
 DevGraph dev_view(const sssp_graph *g);

@@ -528,6 +528,10 @@ void solve_bufs_free(sssp_graph *g) {
     sssp_free(b.ctl); sssp_free(b.st); sssp_free(b.sid); sssp_free(b.soff); sssp_free(b.sdu); sssp_free(b.zid);
     sssp_free(b.chunk_start); sssp_free(b.in_cur); sssp_free(b.out_cur); sssp_free(b.stamp); sssp_free(b.deltas);
     if (g->h_ctl) sssp_host_free(g->h_ctl);
+    for (uint32_t i = 0; i < g->pev_cap; ++i) (void)hipEventDestroy(g->pev[i]);
+    delete[] g->pev;
+    g->pev = nullptr;
+    g->pev_cap = 0;
     for (int i = 0; i < 2; ++i) if (g->ev[i]) (void)hipEventDestroy(g->ev[i]);
     memset(&b, 0, sizeof b);
     g->h_ctl = nullptr;
@@ -613,10 +617,62 @@ static PhaseKernels pick_phase(int chunk, int in, int out, bool delta) {
 
 static int valid_chunk(int c) { return c == 256 || c == 512 || c == 1024; }
 
+// Phase loop with an event before and after every kernel (profiling): one
+// batch at a time, durations summed over the non-empty phases.
+static int run_loop_profiled(sssp_graph *g, const KArgs &a, const PhaseKernels &K, uint64_t max_phases) {
+    constexpr uint32_t kBatch = 64;
+    hipStream_t s = g->stream;
+    if (g->pev_cap < 4 * kBatch) {
+        g->pev = new (std::nothrow) hipEvent_t[4 * kBatch];
+        if (!g->pev) return sssp_set_error(SSSP_ERR_OOM, "event pool");
+        for (uint32_t i = 0; i < 4 * kBatch; ++i) HIP_OK(hipEventCreate(&g->pev[i]));
+        g->pev_cap = 4 * kBatch;
+    }
+    sssp_kernel_profile pr{};
+    const dim3 blk(kBlock), gs(g->cfg.scan_blocks), gr(g->cfg.relax_blocks);
+    uint64_t k = 0;
+    for (;;) {
+        const uint64_t k0 = k;
+        for (uint32_t i = 0; i < kBatch; ++i, ++k) {
+            const int par = (int)(k % 6);
+            hipEvent_t *e = &g->pev[4 * i];
+            HIP_OK(hipEventRecord(e[0], s));
+            if (K.terms) hipLaunchKernelGGL(K.terms, gs, blk, 0, s, a, par);
+            HIP_OK(hipEventRecord(e[1], s));
+            hipLaunchKernelGGL(K.identify, gs, blk, 0, s, a, par);
+            HIP_OK(hipEventRecord(e[2], s));
+            hipLaunchKernelGGL(K.relax, gr, blk, 0, s, a, par);
+            HIP_OK(hipEventRecord(e[3], s));
+        }
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipMemcpyAsync(&g->h_ctl[0], a.b.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        const uint64_t real = g->h_ctl[0].phases;
+        for (uint32_t i = 0; i < kBatch && k0 + i < real; ++i) {
+            float t0 = 0, t1 = 0, t2 = 0;
+            hipEvent_t *e = &g->pev[4 * i];
+            HIP_OK(hipEventElapsedTime(&t0, e[0], e[1]));
+            HIP_OK(hipEventElapsedTime(&t1, e[1], e[2]));
+            HIP_OK(hipEventElapsedTime(&t2, e[2], e[3]));
+            pr.term_ms += K.terms ? t0 : 0.f;
+            pr.identify_ms += t1;
+            pr.relax_ms += t2;
+            pr.phases++;
+        }
+        if (g->h_ctl[0].done) break;
+        if (k > max_phases + 2 * kBatch)
+            return sssp_set_error(SSSP_ERR_INTERNAL, "phase loop did not terminate after %llu phases",
+                                  (unsigned long long)k);
+    }
+    g->last_prof = pr;
+    return SSSP_OK;
+}
+
 // Runs the phase loop: queues phases in growing batches, keeps one batch in
 // flight while the host inspects the previous batch's copy of the control
 // block, and stops once a batch ends with F empty.
 static int run_loop(sssp_graph *g, const KArgs &a, const PhaseKernels &K, uint64_t max_phases) {
+    if (g->prof) return run_loop_profiled(g, a, K, max_phases);
     hipStream_t s = g->stream;
     const dim3 blk(kBlock);
     const dim3 gs(g->cfg.scan_blocks), gr(g->cfg.relax_blocks);
@@ -760,4 +816,16 @@ extern "C" int sssp_delta_step_ex(sssp_graph *g, uint32_t source, const uint64_t
                                   uint64_t *dist_out, sssp_stats *stats, sssp_phase_rec *trace,
                                   uint32_t trace_cap) {
     return solve_common(g, source, true, 0, deltas, n_deltas, dist_out, stats, nullptr, trace, trace_cap);
+}
+
+extern "C" int sssp_profile_enable(sssp_graph *g, int enable) {
+    if (!g) return sssp_set_error(SSSP_ERR_INVALID, "graph is NULL");
+    g->prof = enable != 0;
+    return SSSP_OK;
+}
+
+extern "C" int sssp_profile_get(const sssp_graph *g, sssp_kernel_profile *out) {
+    if (!g || !out) return sssp_set_error(SSSP_ERR_INVALID, "NULL argument");
+    *out = g->last_prof;
+    return SSSP_OK;
 }
