@@ -185,6 +185,22 @@ int sssp_profile_enable(sssp_graph *g, int enable);
 /* Read the per-kernel times of the last solve run with timing on. */
 int sssp_profile_get(const sssp_graph *g, sssp_kernel_profile *out);
 
+/* Launch shape of the phase kernels of a graph (tuning; results never depend
+ * on it). Defaults are chosen from n, m and the device's compute-unit count. */
+typedef struct {
+    uint32_t scan_blocks;   /* blocks of the per-vertex scan kernels (identify, term pass) */
+    uint32_t relax_blocks;  /* blocks of the relax kernel */
+    uint32_t chunk;         /* edges per relax chunk: 256, 512 or 1024 */
+    uint32_t use_graph;     /* 1: replay phases from a captured HIP graph; 0: plain launches */
+} sssp_launch_cfg;
+
+/* Read the launch shape used by later solves on g. */
+int sssp_get_launch(const sssp_graph *g, sssp_launch_cfg *out);
+
+/* Set the launch shape for later solves on g. Errors: SSSP_ERR_INVALID for a
+ * zero block count or an unsupported chunk size. */
+int sssp_set_launch(sssp_graph *g, const sssp_launch_cfg *cfg);
+
 /* Human-readable description of the last error on the calling thread. */
 const char *sssp_last_error(void);
 

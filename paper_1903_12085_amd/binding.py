@@ -25,7 +25,7 @@ FULL_OR = IN_FULL | OUT_FULL
 
 SYMBOLS = ["sssp_graph_create", "sssp_graph_destroy", "sssp_set_stream", "sssp_graph_minima", "sssp_solve",
            "sssp_solve_ex", "sssp_delta_step", "sssp_delta_step_ex", "sssp_solve_batch", "sssp_last_error",
-           "sssp_profile_enable", "sssp_profile_get"]
+           "sssp_profile_enable", "sssp_profile_get", "sssp_get_launch", "sssp_set_launch"]
 
 ERRORS = {-1: "SSSP_ERR_INVALID", -2: "SSSP_ERR_OOM", -3: "SSSP_ERR_DEVICE", -4: "SSSP_ERR_UNSUPPORTED",
           -5: "SSSP_ERR_INTERNAL"}
@@ -54,6 +54,14 @@ class KernelProfile(ctypes.Structure):
         return {k: (int(getattr(self, k)) if k == "phases" else float(getattr(self, k))) for k, _ in self._fields_}
 
 
+class LaunchCfg(ctypes.Structure):
+    _fields_ = [("scan_blocks", ctypes.c_uint32), ("relax_blocks", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
+                ("use_graph", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 PHASE_REC = np.dtype([("min_d", np.uint64), ("fringe", np.uint32), ("settled", np.uint32),
                       ("criterion", np.uint32), ("edges", np.uint32)])
 
@@ -80,6 +88,8 @@ def load(path: str = LIB_PATH):
     lib.sssp_solve_batch.argtypes = [P, P, u32, u32, P, P]
     lib.sssp_profile_enable.argtypes = [P, i]
     lib.sssp_profile_get.argtypes = [P, ctypes.POINTER(KernelProfile)]
+    lib.sssp_get_launch.argtypes = [P, ctypes.POINTER(LaunchCfg)]
+    lib.sssp_set_launch.argtypes = [P, ctypes.POINTER(LaunchCfg)]
     lib.sssp_last_error.restype = ctypes.c_char_p
     lib.sssp_last_error.argtypes = []
     for name in SYMBOLS:
@@ -154,6 +164,18 @@ class DeviceGraph:
         p = KernelProfile()
         _check(load().sssp_profile_get(self._h, ctypes.byref(p)))
         return p.as_dict()
+
+    def launch(self) -> dict:
+        c = LaunchCfg()
+        _check(load().sssp_get_launch(self._h, ctypes.byref(c)))
+        return c.as_dict()
+
+    def set_launch(self, **kw):
+        c = LaunchCfg()
+        _check(load().sssp_get_launch(self._h, ctypes.byref(c)))
+        for k, v in kw.items():
+            setattr(c, k, int(v))
+        _check(load().sssp_set_launch(self._h, ctypes.byref(c)))
 
     def minima(self):
         import torch

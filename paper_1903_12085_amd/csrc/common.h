@@ -29,34 +29,49 @@ static inline void crit_modes(uint32_t c, int *in, int *out) {
     if (*in == IN_NONE && *out == OUT_NONE && (c & SSSP_DIJK)) *in = IN_DIJK;
 }
 
-// Device control block of one solve. Slots indexed by phase parity (mod 2 or
-// mod 3) let phase k fold values for phase k+1 while k's are still read,
-// with no host round trip between phases.
-struct Ctl {
-    unsigned long long reached;     // vertices ever queued (source included)
+// Same-address device-scope atomics serialise (about 12 ns each on MI355X),
+// so every value that many blocks combine is spread over kShards slots, each
+// on its own 128-byte line; block b uses slot b % kShards and readers combine
+// the kShards slots with one wavefront.
+constexpr int kShards = 32;
+constexpr int kPad = 16;  // 16 x 8 B = 128 B between slots
+struct alignas(128) Sharded {
+    unsigned long long v[kShards * kPad];
+};
+
+// Scalar part of the control block: single writers only (block 0 of a
+// kernel); the host copies just this header between batches of phases.
+struct alignas(128) CtlHead {
     unsigned long long settled;     // vertices settled
     unsigned long long sum_f;       // sum of |F| at phase start
-    unsigned long long relax_edges; // relaxations towards non-settled targets
-    unsigned long long improving;   // relaxations that lowered d
-    unsigned long long spack[2];    // S' with out-edges: (count << 32) | edge total
-    unsigned long long szero[2];    // S' without out-edges: count
-    unsigned long long minD[3];     // min_{v in F} d[v] for the phase
-    unsigned long long tst[3];      // OUT-STATIC threshold min_{u in F} d[u] + minOut[u]
-    unsigned long long tdyn[3];     // dynamic OUT threshold from the term pass
+    unsigned long long m_reach;     // out-edges of settled vertices
     unsigned int pnum[2];           // 0-based index of the phase running with this parity
     unsigned int phases;            // phases executed so far
     unsigned int done;              // set once F is empty
     // Delta-stepping
-    unsigned long long nextmin[2];  // min d over F for the next bucket (by bucket parity)
-    unsigned long long win_lo, win_hi, win_delta;
-    unsigned long long win_improved[2]; // vertices improved inside the window, by round parity
     unsigned int rmode[2];          // round kind by parity: 0 bucket start, 1 light, 2 heavy
     unsigned int buckets;           // buckets finished (written by the heavy round's identify)
     unsigned int win_bucket;        // index of the bucket in progress
     unsigned int n_deltas;
-    // learned selector
-    unsigned int choice[2];         // per-phase choice index by parity
-    unsigned long long m_reach;     // out-edges of settled vertices
+    unsigned int pad;
+    unsigned long long win_lo, win_hi, win_delta;
+};
+
+// Device control block of one solve. Slots indexed by phase parity (mod 2 or
+// mod 3) let phase k fold values for phase k+1 while k's are still read,
+// with no host round trip between phases.
+struct Ctl {
+    CtlHead h;
+    Sharded reached;                // sum: vertices ever queued (source included)
+    Sharded relax_edges;            // sum: relaxations towards non-settled targets
+    Sharded improving;              // sum: relaxations that lowered d
+    Sharded spack[2];               // per shard: S' (count << 32) | edge total
+    Sharded szero[2];               // per shard: S' vertices without out-edges
+    Sharded minD[3];                // min: min_{v in F} d[v] for the phase
+    Sharded tst[3];                 // min: OUT-STATIC threshold min_{u in F} d[u] + minOut[u]
+    Sharded tdyn[3];                // min: dynamic OUT threshold from the term pass
+    Sharded nextmin[2];             // min: Delta-stepping, min d over F for the next bucket
+    Sharded win_improved[2];        // sum: Delta-stepping, vertices improved inside the window
 };
 
 // Per-phase device trace record (mirrors sssp_phase_rec).
@@ -81,12 +96,13 @@ struct DevGraph {
 // Scratch used by a solve.
 struct SolveBufs {
     Ctl *ctl;
+    uint32_t shard_cap;     // S' entries per shard (sid/soff/sdu hold kShards * shard_cap)
+    uint32_t chunk_cap;     // chunk_start entries per shard
     uint8_t *st;
     uint32_t *sid;          // S' vertex ids (vertices with out-edges)
     uint32_t *soff;         // S' exclusive edge offsets
     unsigned long long *sdu;// S' snapshot distances
-    uint32_t *zid;          // S' vertices without out-edges
-    uint32_t *chunk_start;  // first S' entry of each edge chunk
+    uint32_t *chunk_start;  // first S' entry (shard-local) of each shard-local edge chunk
     uint32_t *in_cur;       // IN-SIMPLE cursors (absolute CSC index)
     uint32_t *out_cur;      // OUT-SIMPLE cursors (absolute CSR index)
     uint32_t *stamp;        // Delta-stepping improvement stamps
@@ -184,6 +200,7 @@ constexpr int kWaves = kBlock / 64;
 struct LaunchCfg {
     int scan_blocks;    // blocks of the dense vertex-scan kernels
     int relax_blocks;   // blocks of the relax kernel
-    int chunk;          // edges per relax chunk (multiple of kBlock, <= kMaxChunk)
+    int chunk;          // edges per relax chunk (256, 512 or 1024)
+    int use_graph;      // replay phases from a captured HIP graph
 };
 constexpr int kMaxChunk = 2048;

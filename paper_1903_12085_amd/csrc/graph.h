@@ -18,15 +18,21 @@ struct sssp_graph {
     // per-solve scratch, allocated on first use and kept
     SolveBufs b{};
     bool bufs_ready = false;
-    uint64_t chunk_cap = 0;        // entries of b.chunk_start
+    uint32_t bufs_scan_blocks = 0; // scan grid the S' shard capacity was sized for
     uint32_t delta_cap = 0;        // entries of b.deltas
-    Ctl *h_ctl = nullptr;          // pinned host mirror of the control block
+    CtlHead *h_ctl = nullptr;      // pinned host mirror of the control-block header (2 slots)
     hipEvent_t ev[2] = {nullptr, nullptr};
     // per-kernel event timing
     bool prof = false;
     hipEvent_t *pev = nullptr;     // 4 events per phase of one batch
     uint32_t pev_cap = 0;
     sssp_kernel_profile last_prof{};
+    // captured phase batch (6 phases) for graph replay
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    unsigned char graph_key[512] = {0};
+    uint32_t graph_key_len = 0;
 };
 
 DevGraph dev_view(const sssp_graph *g);

@@ -11,20 +11,22 @@
 //              queued vertex is tested against the phase-start thresholds.
 //              Certified vertices are settled and compacted into S' with a
 //              wavefront ballot + prefix sum and one packed (count, edges)
-//              atomic per wavefront, which also assigns each its exclusive
-//              offset in the phase's edge space. Vertices that stay queued
-//              contribute to next phase's minD and OUT-STATIC threshold.
-//   relax      the edge space of S' is cut into equal chunks; a block stages
-//              the chunk's S' entries (start edge, snapshot distance) in LDS
-//              and each lane finds its edge's owner by binary search (merge
-//              path), so rows of any degree split evenly. Each edge does a
-//              plain-load filter and a 64-bit atomicMin; the atomic that
+//              atomic per wavefront on the block's shard, which also assigns
+//              each entry its shard-local offset in the phase's edge space.
+//              Vertices that stay queued contribute to next phase's minD and
+//              OUT-STATIC threshold.
+//   relax      each shard's edge space is cut into equal chunks; a block
+//              stages a chunk's S' entries (start edge, snapshot distance) in
+//              LDS and each lane finds its edge's owner by binary search
+//              (merge path), so rows of any degree split evenly. Each edge does
+//              a plain-load filter and a 64-bit atomicMin; the atomic that
 //              replaces infinity discovers the target (U -> F). Improving
 //              candidates fold into next phase's minD / OUT-STATIC threshold
 //              (d only decreases, so the minimum over final values equals the
 //              minimum over kept values and improving candidates).
 // Control state lives in device memory slots indexed by phase parity, so
-// phases can be queued many at a time and empty phases exit at once.
+// phases can be queued many at a time and empty phases exit at once; values
+// combined by many blocks are sharded (see Sharded in common.h).
 #include <string.h>
 
 #include "common.h"
@@ -37,6 +39,23 @@ struct KArgs {
     SolveBufs b;
     uint32_t crit;
 };
+
+__device__ __forceinline__ unsigned long long *slot_of(Sharded &s, int i) { return &s.v[i * kPad]; }
+__device__ __forceinline__ int my_shard() { return (int)(blockIdx.x % kShards); }
+
+// Combine a sharded value inside wavefront 0 (lanes >= kShards contribute the neutral value).
+__device__ __forceinline__ unsigned long long shard_sum_w0(Sharded &s) {
+    const int i = threadIdx.x;
+    return wave_sum64(i < kShards ? s.v[i * kPad] : 0ull);
+}
+__device__ __forceinline__ unsigned long long shard_min_w0(Sharded &s) {
+    const int i = threadIdx.x;
+    return wave_min64(i < kShards ? s.v[i * kPad] : INF64);
+}
+// Block 0, threads < kShards: reset every slot.
+__device__ __forceinline__ void shard_fill(Sharded &s, unsigned long long x) {
+    if (threadIdx.x < kShards) s.v[threadIdx.x * kPad] = x;
+}
 
 // ---------------------------------------------------------------------------
 // initialisation
@@ -56,56 +75,140 @@ __global__ void k_init_state(uint32_t n, uint32_t src, unsigned long long *__res
     }
 }
 
+// One block of 64 threads.
 __global__ void k_init_ctl(Ctl *ctl, const uint2 *__restrict__ vmin, uint32_t src, uint32_t n_deltas) {
-    Ctl c;
-    memset(&c, 0, sizeof c);
-    c.reached = 1;
-    c.minD[0] = 0;
-    c.minD[1] = c.minD[2] = INF64;
-    c.tst[0] = w64(vmin[src].y);  // 0 + minOut[s]
-    c.tst[1] = c.tst[2] = INF64;
-    c.tdyn[0] = c.tdyn[1] = c.tdyn[2] = INF64;
-    c.nextmin[0] = 0;
-    c.nextmin[1] = INF64;
-    c.n_deltas = n_deltas;
-    *ctl = c;
+    const int i = threadIdx.x;
+    if (i == 0) {
+        CtlHead h;
+        memset(&h, 0, sizeof h);
+        h.n_deltas = n_deltas;
+        ctl->h = h;
+    }
+    if (i < kShards) {
+        const int o = i * kPad;
+        ctl->reached.v[o] = i == 0 ? 1ull : 0ull;
+        ctl->relax_edges.v[o] = ctl->improving.v[o] = 0;
+        for (int k = 0; k < 2; ++k) {
+            ctl->spack[k].v[o] = ctl->szero[k].v[o] = 0;
+            ctl->win_improved[k].v[o] = 0;
+        }
+        for (int k = 0; k < 3; ++k) ctl->minD[k].v[o] = ctl->tst[k].v[o] = ctl->tdyn[k].v[o] = INF64;
+        ctl->minD[0].v[o] = i == 0 ? 0ull : INF64;
+        ctl->tst[0].v[o] = i == 0 ? w64(vmin[src].y) : INF64;  // 0 + minOut[s]
+        ctl->nextmin[0].v[o] = i == 0 ? 0ull : INF64;
+        ctl->nextmin[1].v[o] = INF64;
+    }
 }
 
 // ---------------------------------------------------------------------------
-// S' append: one packed atomic per wavefront gives consecutive S' slots and
-// consecutive edge offsets; chunk_start[c] records the entry owning edge c*CH.
+// S' append. Settled vertices are first collected per block in LDS (one LDS
+// atomic per wavefront); at the end of the scan the block takes one packed
+// (count, edges) atomic on its shard, which gives consecutive shard slots and
+// consecutive shard-local edge offsets, and writes the entries out.
+// chunk_start records the entry owning edge c*CH of the shard. If the LDS
+// buffer fills, a wavefront appends straight to its shard instead.
+
+constexpr int kAppendBuf = 512;
+
+struct AppendLds {
+    uint32_t v[kAppendBuf];
+    uint32_t deg[kAppendBuf];
+    uint32_t cnt;     // slots reserved (may run past kAppendBuf)
+    uint32_t filled;  // slots written: wavefronts whose reservation fit, which tile [0, filled)
+    uint32_t zero;
+    uint32_t wsum[kWaves];
+    unsigned long long base;
+};
 
 template <int CH>
-__device__ __forceinline__ void append_settled(const KArgs &a, unsigned long long *spack,
-                                               unsigned long long *szero, bool set, uint32_t v,
-                                               uint32_t deg, unsigned long long dv) {
+__device__ __forceinline__ void write_entry(const KArgs &a, int sh, uint32_t j, uint64_t off, uint32_t v,
+                                            uint32_t deg, unsigned long long dv) {
+    const uint64_t g = (uint64_t)sh * a.b.shard_cap + j;
+    a.b.sid[g] = v;
+    a.b.soff[g] = (uint32_t)off;
+    a.b.sdu[g] = dv;
+    uint32_t *cs = a.b.chunk_start + (uint64_t)sh * a.b.chunk_cap;
+    for (uint64_t c = (off + CH - 1) / CH; c * CH < off + deg; ++c) cs[c] = (uint32_t)j;
+}
+
+// Wavefront-uniform call: every lane of the wavefront takes part.
+template <int CH>
+__device__ __forceinline__ void append_settled(const KArgs &a, Ctl *ctl, int p2, AppendLds &L, bool set,
+                                               uint32_t v, uint32_t deg, unsigned long long dv) {
     const int lane = threadIdx.x & 63;
     const unsigned long long lt = (1ull << lane) - 1ull;
     const bool app = set && deg > 0;
     const unsigned long long mask = __ballot(app);
     if (mask) {
-        const uint32_t x = app ? deg : 0u;
-        const uint32_t incl = wave_incl_scan(x);
-        const uint32_t tot = __shfl(incl, 63, 64);
-        unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(spack, ((unsigned long long)__popcll(mask) << 32) | tot);
-        base = __shfl(base, 0, 64);
-        if (app) {
-            const uint32_t j = (uint32_t)(base >> 32) + (uint32_t)__popcll(mask & lt);
-            const uint64_t off = (uint32_t)base + incl - x;
-            a.b.sid[j] = v;
-            a.b.soff[j] = (uint32_t)off;
-            a.b.sdu[j] = dv;
-            for (uint64_t c = (off + CH - 1) / CH; c * CH < off + deg; ++c) a.b.chunk_start[c] = j;
+        const uint32_t cntw = (uint32_t)__popcll(mask);
+        uint32_t pos = 0;
+        if (lane == 0) pos = atomicAdd(&L.cnt, cntw);
+        pos = __shfl(pos, 0, 64);
+        if (pos + cntw <= kAppendBuf) {
+            if (app) {
+                const uint32_t r = pos + (uint32_t)__popcll(mask & lt);
+                L.v[r] = v;
+                L.deg[r] = deg;
+            }
+            if (lane == 0) atomicAdd(&L.filled, cntw);
+        } else {  // buffer full: direct append for this wavefront (its reserved slots stay unused)
+            const uint32_t x = app ? deg : 0u;
+            const uint32_t incl = wave_incl_scan(x);
+            const uint32_t tot = __shfl(incl, 63, 64);
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(slot_of(ctl->spack[p2], my_shard()), ((unsigned long long)cntw << 32) | tot);
+            base = __shfl(base, 0, 64);
+            if (app)
+                write_entry<CH>(a, my_shard(), (uint32_t)(base >> 32) + (uint32_t)__popcll(mask & lt),
+                                (uint32_t)base + incl - x, v, deg, dv);
         }
     }
-    const bool z = set && deg == 0;
-    const unsigned long long zm = __ballot(z);
-    if (zm) {
-        unsigned long long zb = 0;
-        if (lane == 0) zb = atomicAdd(szero, (unsigned long long)__popcll(zm));
-        zb = __shfl(zb, 0, 64);
-        if (z) a.b.zid[zb + __popcll(zm & lt)] = v;
+    const unsigned long long zm = __ballot(set && deg == 0);
+    if (zm && lane == 0) atomicAdd(&L.zero, (uint32_t)__popcll(zm));
+}
+
+// Block-wide flush of the LDS buffer (all threads call it once, after the scan).
+template <int CH>
+__device__ __forceinline__ void append_flush(const KArgs &a, Ctl *ctl, int p2, AppendLds &L) {
+    __syncthreads();
+    // Reservations are handed out in increasing order, so every wavefront that
+    // fit reserved before the first one that did not: the written slots are
+    // exactly [0, filled). Slots reserved by overflowing wavefronts are never read.
+    const uint32_t cnt = L.filled;
+    constexpr int PER = kAppendBuf / kBlock;
+    uint32_t loc[PER];
+    uint32_t tsum = 0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const uint32_t t = threadIdx.x * PER + q;
+        loc[q] = tsum;
+        tsum += t < cnt ? L.deg[t] : 0u;
+    }
+    const uint32_t incl = wave_incl_scan(tsum);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 63) L.wsum[w] = incl;
+    __syncthreads();
+    uint32_t wbase = 0, total = 0;
+    for (int i = 0; i < kWaves; ++i) {
+        wbase += i < w ? L.wsum[i] : 0u;
+        total += L.wsum[i];
+    }
+    const uint32_t excl = wbase + incl - tsum;
+    if (threadIdx.x == 0) {
+        const int sh = my_shard();
+        L.base = cnt ? atomicAdd(slot_of(ctl->spack[p2], sh), ((unsigned long long)cnt << 32) | total) : 0ull;
+        if (L.zero) atomicAdd(slot_of(ctl->szero[p2], sh), (unsigned long long)L.zero);
+    }
+    __syncthreads();
+    const unsigned long long base = L.base;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const uint32_t t = threadIdx.x * PER + q;
+        if (t < cnt) {
+            const uint32_t v = L.v[t];
+            write_entry<CH>(a, my_shard(), (uint32_t)(base >> 32) + t, (uint64_t)(uint32_t)base + excl + loc[q], v,
+                            L.deg[t], a.b.dist[v]);
+        }
     }
 }
 
@@ -128,8 +231,15 @@ __global__ __launch_bounds__(kBlock) void k_terms(KArgs a, int par) {
     Ctl *ctl = a.b.ctl;
     const int p3 = par % 3;
     __shared__ unsigned long long sh[kWaves];
-    if (ctl->reached == ctl->settled) return;
-    const unsigned long long minD = ctl->minD[p3];
+    __shared__ unsigned long long s_reached, s_minD;
+    if (threadIdx.x < 64) {
+        const unsigned long long r = shard_sum_w0(ctl->reached);
+        const unsigned long long md = shard_min_w0(ctl->minD[p3]);
+        if (threadIdx.x == 0) { s_reached = r; s_minD = md; }
+    }
+    __syncthreads();
+    if (s_reached == ctl->h.settled) return;
+    const unsigned long long minD = s_minD;
     unsigned long long tmin = INF64;
     const uint32_t n = a.g.n;
     for (uint32_t v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) {
@@ -187,7 +297,7 @@ __global__ __launch_bounds__(kBlock) void k_terms(KArgs a, int par) {
     }
     if (OUT != OUT_NONE) {
         tmin = block_min64<kWaves>(tmin, sh);
-        if (threadIdx.x == 0 && tmin != INF64) atomicMin(&ctl->tdyn[p3], tmin);
+        if (threadIdx.x == 0 && tmin != INF64) atomicMin(slot_of(ctl->tdyn[p3], my_shard()), tmin);
     }
 }
 
@@ -201,37 +311,51 @@ __global__ __launch_bounds__(kBlock) void k_identify(KArgs a, int par) {
     Ctl *ctl = a.b.ctl;
     const int p2 = par & 1, p3 = par % 3;
     __shared__ unsigned long long sh[kWaves];
-    const unsigned long long reached = ctl->reached, settled = ctl->settled;
-    const unsigned int P = ctl->pnum[p2];
+    __shared__ unsigned long long s_reached, s_minD, s_T;
+    __shared__ AppendLds L;
+    if (threadIdx.x == 0) { L.cnt = 0; L.filled = 0; L.zero = 0; }
+    if (threadIdx.x < 64) {
+        const unsigned long long r = shard_sum_w0(ctl->reached);
+        const unsigned long long md = shard_min_w0(ctl->minD[p3]);
+        const unsigned long long t = OUT == 1 ? shard_min_w0(ctl->tst[p3])
+                                   : OUT == 2 ? shard_min_w0(ctl->tdyn[p3]) : 0ull;
+        if (threadIdx.x == 0) { s_reached = r; s_minD = md; s_T = t; }
+    }
+    __syncthreads();
+    const unsigned long long reached = s_reached, settled = ctl->h.settled;
+    const unsigned int P = ctl->h.pnum[p2];
     if (reached == settled) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            ctl->done = 1;
-            ctl->pnum[p2 ^ 1] = P;
-            ctl->spack[p2 ^ 1] = 0;
-            ctl->szero[p2 ^ 1] = 0;
+        if (blockIdx.x == 0) {
+            if (threadIdx.x == 0) {
+                ctl->h.done = 1;
+                ctl->h.pnum[p2 ^ 1] = P;
+            }
+            shard_fill(ctl->spack[p2 ^ 1], 0);
+            shard_fill(ctl->szero[p2 ^ 1], 0);
         }
         return;
     }
-    const unsigned long long minD = ctl->minD[p3];
-    const unsigned long long T = OUT == 1 ? ctl->tst[p3] : OUT == 2 ? ctl->tdyn[p3] : 0ull;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        ctl->pnum[p2 ^ 1] = P + 1;
-        ctl->phases = P + 1;
-        ctl->sum_f += reached - settled;
-        ctl->spack[p2 ^ 1] = 0;
-        ctl->szero[p2 ^ 1] = 0;
-        ctl->minD[(p3 + 2) % 3] = INF64;
-        ctl->tst[(p3 + 2) % 3] = INF64;
-        ctl->tdyn[(p3 + 1) % 3] = INF64;
-        if (P < a.b.trace_cap) {
-            PhaseRec r;
-            r.min_d = minD;
-            r.fringe = (unsigned int)(reached - settled);
-            r.settled = 0;
-            r.criterion = a.crit;
-            r.edges = 0;
-            a.b.trace[P] = r;
+    const unsigned long long minD = s_minD, T = s_T;
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) {
+            ctl->h.pnum[p2 ^ 1] = P + 1;
+            ctl->h.phases = P + 1;
+            ctl->h.sum_f += reached - settled;
+            if (P < a.b.trace_cap) {
+                PhaseRec r;
+                r.min_d = minD;
+                r.fringe = (unsigned int)(reached - settled);
+                r.settled = 0;
+                r.criterion = a.crit;
+                r.edges = 0;
+                a.b.trace[P] = r;
+            }
         }
+        shard_fill(ctl->spack[p2 ^ 1], 0);
+        shard_fill(ctl->szero[p2 ^ 1], 0);
+        shard_fill(ctl->minD[(p3 + 2) % 3], INF64);
+        shard_fill(ctl->tst[(p3 + 2) % 3], INF64);
+        shard_fill(ctl->tdyn[(p3 + 1) % 3], INF64);
     }
     unsigned long long fmin = INF64, ftst = INF64;
     const uint32_t n = a.g.n;
@@ -260,13 +384,14 @@ __global__ __launch_bounds__(kBlock) void k_identify(KArgs a, int par) {
                 }
             }
         }
-        append_settled<CH>(a, &ctl->spack[p2], &ctl->szero[p2], set, v, deg, dv);
+        append_settled<CH>(a, ctl, p2, L, set, v, deg, dv);
     }
+    append_flush<CH>(a, ctl, p2, L);
     fmin = block_min64<kWaves>(fmin, sh);
     ftst = block_min64<kWaves>(ftst, sh);
     if (threadIdx.x == 0) {
-        if (fmin != INF64) atomicMin(&ctl->minD[(p3 + 1) % 3], fmin);
-        if (ftst != INF64) atomicMin(&ctl->tst[(p3 + 1) % 3], ftst);
+        if (fmin != INF64) atomicMin(slot_of(ctl->minD[(p3 + 1) % 3], my_shard()), fmin);
+        if (ftst != INF64) atomicMin(slot_of(ctl->tst[(p3 + 1) % 3], my_shard()), ftst);
     }
 }
 
@@ -281,60 +406,78 @@ __global__ __launch_bounds__(kBlock) void k_identify_delta(KArgs a, int par) {
     Ctl *ctl = a.b.ctl;
     const int p2 = par & 1;
     __shared__ unsigned long long sh[kWaves];
-    const unsigned long long reached = ctl->reached, settled = ctl->settled;
-    const unsigned int P = ctl->pnum[p2];
+    __shared__ unsigned long long s_reached, s_improved;
+    __shared__ AppendLds L;
+    if (threadIdx.x == 0) { L.cnt = 0; L.filled = 0; L.zero = 0; }
+    const unsigned int P = ctl->h.pnum[p2];
+    const unsigned int b_now = ctl->h.buckets;
+    if (threadIdx.x < 64) {
+        const unsigned long long r = shard_sum_w0(ctl->reached);
+        const unsigned long long im = shard_sum_w0(ctl->win_improved[p2 ^ 1]);
+        if (threadIdx.x == 0) { s_reached = r; s_improved = im; }
+    }
+    __shared__ unsigned long long s_next;
+    if (threadIdx.x < 64) {
+        const unsigned long long nm = shard_min_w0(ctl->nextmin[b_now & 1]);
+        if (threadIdx.x == 0) s_next = nm;
+    }
+    __syncthreads();
+    const unsigned long long reached = s_reached, settled = ctl->h.settled;
     int kind = 0;
     if (P > 0) {
-        const unsigned int prev = ctl->rmode[p2 ^ 1];
-        kind = prev == 2 ? 0 : (ctl->win_improved[p2 ^ 1] > 0 ? 1 : 2);
+        const unsigned int prev = ctl->h.rmode[p2 ^ 1];
+        kind = prev == 2 ? 0 : (s_improved > 0 ? 1 : 2);
     }
     if (kind == 0 && reached == settled) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            ctl->done = 1;
-            ctl->pnum[p2 ^ 1] = P;
-            ctl->rmode[p2] = 2;  // later empty rounds stay "after heavy"
-            ctl->spack[p2 ^ 1] = 0;
-            ctl->szero[p2 ^ 1] = 0;
+        if (blockIdx.x == 0) {
+            if (threadIdx.x == 0) {
+                ctl->h.done = 1;
+                ctl->h.pnum[p2 ^ 1] = P;
+                ctl->h.rmode[p2] = 2;  // later empty rounds stay "after heavy"
+            }
+            shard_fill(ctl->spack[p2 ^ 1], 0);
+            shard_fill(ctl->szero[p2 ^ 1], 0);
         }
         return;
     }
-    const unsigned int b = kind == 0 ? ctl->buckets : ctl->win_bucket;
+    const unsigned int b = kind == 0 ? b_now : ctl->h.win_bucket;
     unsigned long long lo, hi, delta;
     if (kind == 0) {
-        delta = a.b.deltas[b < ctl->n_deltas ? b : ctl->n_deltas - 1];
-        const unsigned long long mn = ctl->nextmin[b & 1];
-        lo = (mn / delta) * delta;
+        delta = a.b.deltas[b < ctl->h.n_deltas ? b : ctl->h.n_deltas - 1];
+        lo = (s_next / delta) * delta;
         hi = sadd64(lo, delta);
     } else {
-        lo = ctl->win_lo;
-        hi = ctl->win_hi;
-        delta = ctl->win_delta;
+        lo = ctl->h.win_lo;
+        hi = ctl->h.win_hi;
+        delta = ctl->h.win_delta;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        ctl->pnum[p2 ^ 1] = P + 1;
-        ctl->phases = P + 1;
-        ctl->rmode[p2] = kind;
-        ctl->win_improved[p2] = 0;
-        ctl->spack[p2 ^ 1] = 0;
-        ctl->szero[p2 ^ 1] = 0;
-        if (kind == 2) ctl->buckets = b + 1;
-        if (kind == 0) {
-            ctl->win_bucket = b;
-            ctl->win_lo = lo;
-            ctl->win_hi = hi;
-            ctl->win_delta = delta;
-            ctl->nextmin[(b + 1) & 1] = INF64;
-            ctl->sum_f += reached - settled;
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) {
+            ctl->h.pnum[p2 ^ 1] = P + 1;
+            ctl->h.phases = P + 1;
+            ctl->h.rmode[p2] = kind;
+            if (kind == 2) ctl->h.buckets = b + 1;
+            if (kind == 0) {
+                ctl->h.win_bucket = b;
+                ctl->h.win_lo = lo;
+                ctl->h.win_hi = hi;
+                ctl->h.win_delta = delta;
+                ctl->h.sum_f += reached - settled;
+            }
+            if (P < a.b.trace_cap) {
+                PhaseRec r;
+                r.min_d = lo;
+                r.fringe = (unsigned int)(reached - settled);
+                r.settled = 0;
+                r.criterion = kind;
+                r.edges = 0;
+                a.b.trace[P] = r;
+            }
         }
-        if (P < a.b.trace_cap) {
-            PhaseRec r;
-            r.min_d = lo;
-            r.fringe = (unsigned int)(reached - settled);
-            r.settled = 0;
-            r.criterion = kind;
-            r.edges = 0;
-            a.b.trace[P] = r;
-        }
+        shard_fill(ctl->win_improved[p2], 0);
+        shard_fill(ctl->spack[p2 ^ 1], 0);
+        shard_fill(ctl->szero[p2 ^ 1], 0);
+        if (kind == 0) shard_fill(ctl->nextmin[(b + 1) & 1], INF64);
     }
     unsigned long long fmin = INF64;
     const uint32_t n = a.g.n;
@@ -369,18 +512,21 @@ __global__ __launch_bounds__(kBlock) void k_identify_delta(KArgs a, int par) {
                 if (kind == 2 && a.b.phase_of) a.b.phase_of[v] = P + 1;
             }
         }
-        append_settled<CH>(a, &ctl->spack[p2], &ctl->szero[p2], set, v, deg, dv);
+        append_settled<CH>(a, ctl, p2, L, set, v, deg, dv);
     }
+    append_flush<CH>(a, ctl, p2, L);
     if (kind == 2) {
         fmin = block_min64<kWaves>(fmin, sh);
-        if (threadIdx.x == 0 && fmin != INF64) atomicMin(&ctl->nextmin[(b + 1) & 1], fmin);
+        if (threadIdx.x == 0 && fmin != INF64) atomicMin(slot_of(ctl->nextmin[(b + 1) & 1], my_shard()), fmin);
     }
 }
 
 // ---------------------------------------------------------------------------
 // relax
 
-template <int CH, bool DELTA>
+// FOLDT: also fold the OUT-STATIC threshold (needed when OUT-STATIC is the
+// OUT member of the phase's criterion).
+template <int CH, bool DELTA, bool FOLDT>
 __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
     Ctl *ctl = a.b.ctl;
     const int p2 = par & 1, p3 = par % 3;
@@ -388,39 +534,63 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
     __shared__ uint32_t s_start[CH + 1];
     __shared__ unsigned long long s_du[CH + 1];
     __shared__ unsigned long long sh[kWaves];
-    const unsigned long long pk = ctl->spack[p2];
-    const uint32_t ns = (uint32_t)(pk >> 32), E = (uint32_t)pk;
-    const uint32_t nz = (uint32_t)ctl->szero[p2];
-    if ((ns == 0 && nz == 0) || ctl->done) return;
-    const unsigned int P = ctl->pnum[p2];
+    __shared__ uint32_t s_ns[kShards], s_E[kShards], s_cb[kShards + 1];
+    __shared__ unsigned long long s_tot_settled, s_tot_edges;
+    if (threadIdx.x < 64) {
+        // per-shard S' sizes, edge totals and an exclusive prefix of their chunk counts
+        const int i = threadIdx.x;
+        const unsigned long long pk = i < kShards ? ctl->spack[p2].v[i * kPad] : 0ull;
+        const unsigned long long nz = i < kShards ? ctl->szero[p2].v[i * kPad] : 0ull;
+        const uint32_t ns = (uint32_t)(pk >> 32), E = (uint32_t)pk;
+        const uint32_t nch = (uint32_t)(((uint64_t)E + CH - 1) / CH);
+        const uint32_t incl = wave_incl_scan(nch);
+        if (i < kShards) {
+            s_ns[i] = ns;
+            s_E[i] = E;
+            s_cb[i] = incl - nch;
+        }
+        if (i == kShards - 1) s_cb[kShards] = incl;
+        const unsigned long long tset = wave_sum64((unsigned long long)ns + nz);
+        const unsigned long long tedge = wave_sum64(E);
+        if (i == 0) { s_tot_settled = tset; s_tot_edges = tedge; }
+    }
+    __syncthreads();
+    if (s_tot_settled == 0 || ctl->h.done) return;
+    const unsigned int P = ctl->h.pnum[p2];
     int kind = 0;
     unsigned long long hi = INF64, delta = 0;
     if (DELTA) {
-        kind = ctl->rmode[p2] == 2 ? 2 : 1;
-        hi = ctl->win_hi;
-        delta = ctl->win_delta;
+        kind = ctl->h.rmode[p2] == 2 ? 2 : 1;
+        hi = ctl->h.win_hi;
+        delta = ctl->h.win_delta;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (!DELTA || kind == 2) {
-            ctl->settled += ns + nz;
-            ctl->m_reach += E;
+            ctl->h.settled += s_tot_settled;
+            ctl->h.m_reach += s_tot_edges;
         }
         if (P < a.b.trace_cap) {
-            a.b.trace[P].settled = ns + nz;
-            a.b.trace[P].edges = E;
+            a.b.trace[P].settled = (unsigned int)s_tot_settled;
+            a.b.trace[P].edges = (unsigned int)s_tot_edges;
         }
     }
     unsigned long long cmin = INF64, ctst = INF64, tried = 0, improv = 0, disc = 0, winimp = 0;
-    const uint32_t nch = (E + CH - 1) / CH;
+    const uint32_t nch = s_cb[kShards];
     for (uint32_t c = blockIdx.x; c < nch; c += gridDim.x) {
-        const uint32_t e0 = c * CH;
-        const uint32_t len = min(E - e0, (uint32_t)CH);
-        const uint32_t j0 = a.b.chunk_start[c];
-        const uint32_t jend = (c + 1 < nch) ? a.b.chunk_start[c + 1] : ns - 1;
+        int sd = 0;  // shard of chunk c: last sd with s_cb[sd] <= c
+        while (sd + 1 < kShards && s_cb[sd + 1] <= c) ++sd;
+        const uint32_t lc = c - s_cb[sd];
+        const uint32_t Es = s_E[sd], ns = s_ns[sd];
+        const uint32_t e0 = lc * CH;
+        const uint32_t len = min(Es - e0, (uint32_t)CH);
+        const uint32_t *cs = a.b.chunk_start + (uint64_t)sd * a.b.chunk_cap;
+        const uint32_t j0 = cs[lc];
+        const uint32_t jend = (e0 + CH < Es) ? cs[lc + 1] : ns - 1;
         const uint32_t cnt = jend - j0 + 1;
+        const uint64_t gbase = (uint64_t)sd * a.b.shard_cap;
         __syncthreads();
         for (uint32_t t = threadIdx.x; t < cnt; t += kBlock) {
-            const uint32_t j = j0 + t;
+            const uint64_t j = gbase + j0 + t;
             const uint32_t off = a.b.soff[j];
             const uint32_t u = a.b.sid[j];
             s_pos[t] = off > e0 ? off - e0 : 0u;
@@ -440,16 +610,18 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
                 if (kind == 1 && ed.y >= delta) continue;  // light: c < delta
                 if (kind == 2 && ed.y < delta) continue;   // heavy: c >= delta
             }
-            if ((a.b.st[v] & ST_SET) == ST_S) continue;
+            const uint8_t sv = a.b.st[v];
+            const unsigned long long cur = a.b.dist[v];  // issued together with the state load
+            if ((sv & ST_SET) == ST_S) continue;
             ++tried;
             const unsigned long long cand = s_du[lo] + ed.y;
-            if (cand < a.b.dist[v]) {
+            if (cand < cur) {
                 const unsigned long long old = atomicMin(&a.b.dist[v], cand);
                 if (cand < old) {
                     ++improv;
                     if (!DELTA) {
                         cmin = umin64(cmin, cand);
-                        ctst = umin64(ctst, sadd64(cand, w64(a.g.vmin[v].y)));
+                        if (FOLDT) ctst = umin64(ctst, sadd64(cand, w64(a.g.vmin[v].y)));
                     } else if (kind == 2) {
                         cmin = umin64(cmin, cand);
                     } else if (cand < hi) {
@@ -468,18 +640,19 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
     tried = block_sum64<kWaves>(tried, sh);
     improv = block_sum64<kWaves>(improv, sh);
     disc = block_sum64<kWaves>(disc, sh);
-    if (!DELTA) ctst = block_min64<kWaves>(ctst, sh);
+    if (FOLDT) ctst = block_min64<kWaves>(ctst, sh);
     if (DELTA) winimp = block_sum64<kWaves>(winimp, sh);
     if (threadIdx.x == 0) {
+        const int s = my_shard();
         if (cmin != INF64) {
-            if (!DELTA) atomicMin(&ctl->minD[(p3 + 1) % 3], cmin);
-            else atomicMin(&ctl->nextmin[(ctl->win_bucket + 1) & 1], cmin);
+            if (!DELTA) atomicMin(slot_of(ctl->minD[(p3 + 1) % 3], s), cmin);
+            else atomicMin(slot_of(ctl->nextmin[(ctl->h.win_bucket + 1) & 1], s), cmin);
         }
-        if (!DELTA && ctst != INF64) atomicMin(&ctl->tst[(p3 + 1) % 3], ctst);
-        if (tried) atomicAdd(&ctl->relax_edges, tried);
-        if (improv) atomicAdd(&ctl->improving, improv);
-        if (disc) atomicAdd(&ctl->reached, disc);
-        if (winimp) atomicAdd(&ctl->win_improved[p2], winimp);
+        if (FOLDT && ctst != INF64) atomicMin(slot_of(ctl->tst[(p3 + 1) % 3], s), ctst);
+        if (tried) atomicAdd(slot_of(ctl->relax_edges, s), tried);
+        if (improv) atomicAdd(slot_of(ctl->improving, s), improv);
+        if (disc) atomicAdd(slot_of(ctl->reached, s), disc);
+        if (winimp) atomicAdd(slot_of(ctl->win_improved[p2], s), winimp);
     }
 }
 
@@ -516,7 +689,7 @@ void graph_default_cfg(sssp_graph *g) {
     if (sb < 1) sb = 1;
     if (sb > (uint64_t)cus * 8) sb = (uint64_t)cus * 8;
     g->cfg.scan_blocks = (int)sb;
-    g->cfg.chunk = 512;
+    g->cfg.chunk = 256;
     uint64_t rb = (g->m + g->cfg.chunk - 1) / g->cfg.chunk;
     if (rb < 1) rb = 1;
     if (rb > (uint64_t)cus * 8) rb = (uint64_t)cus * 8;
@@ -525,7 +698,7 @@ void graph_default_cfg(sssp_graph *g) {
 
 void solve_bufs_free(sssp_graph *g) {
     SolveBufs &b = g->b;
-    sssp_free(b.ctl); sssp_free(b.st); sssp_free(b.sid); sssp_free(b.soff); sssp_free(b.sdu); sssp_free(b.zid);
+    sssp_free(b.ctl); sssp_free(b.st); sssp_free(b.sid); sssp_free(b.soff); sssp_free(b.sdu);
     sssp_free(b.chunk_start); sssp_free(b.in_cur); sssp_free(b.out_cur); sssp_free(b.stamp); sssp_free(b.deltas);
     if (g->h_ctl) sssp_host_free(g->h_ctl);
     for (uint32_t i = 0; i < g->pev_cap; ++i) (void)hipEventDestroy(g->pev[i]);
@@ -533,28 +706,52 @@ void solve_bufs_free(sssp_graph *g) {
     g->pev = nullptr;
     g->pev_cap = 0;
     for (int i = 0; i < 2; ++i) if (g->ev[i]) (void)hipEventDestroy(g->ev[i]);
+    if (g->graph_exec) (void)hipGraphExecDestroy(g->graph_exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
+    g->graph_exec = nullptr;
+    g->graph = nullptr;
+    g->cap_stream = nullptr;
+    g->graph_key_len = 0;
     memset(&b, 0, sizeof b);
     g->h_ctl = nullptr;
     g->ev[0] = g->ev[1] = nullptr;
     g->bufs_ready = false;
+    g->bufs_scan_blocks = 0;
+    g->delta_cap = 0;  // b.deltas was released with the rest
+}
+
+// Vertices a shard can settle in one phase: block b scans vertices
+// b*kBlock + i + k*G*kBlock, shard = b % kShards, so a shard owns at most
+// ceil(G / kShards) blocks of at most kBlock * ceil(n / (G * kBlock)) vertices.
+static uint32_t shard_capacity(uint32_t n, int G) {
+    const uint64_t iters = ((uint64_t)n + (uint64_t)G * kBlock - 1) / ((uint64_t)G * kBlock);
+    const uint64_t blocks = ((uint64_t)G + kShards - 1) / kShards;
+    return (uint32_t)(blocks * kBlock * iters);
 }
 
 int solve_bufs_ensure(sssp_graph *g, bool cursors, bool stamps) {
     SolveBufs &b = g->b;
     const uint64_t n = g->n;
+    if (g->bufs_ready && g->bufs_scan_blocks != (uint32_t)g->cfg.scan_blocks) {
+        // the S' shard layout depends on the scan grid: rebuild the scratch
+        solve_bufs_free(g);
+    }
     if (!g->bufs_ready) {
-        g->chunk_cap = g->m / 256 + 2;
+        b.shard_cap = shard_capacity(g->n, g->cfg.scan_blocks);
+        b.chunk_cap = (uint32_t)(g->m / 256 + 2);  // every chunk size is >= 256 edges
+        const uint64_t sent = (uint64_t)kShards * b.shard_cap;
         HIP_OK(hipMalloc(&b.ctl, sizeof(Ctl)));
         HIP_OK(hipMalloc(&b.st, n));
-        HIP_OK(hipMalloc(&b.sid, n * 4));
-        HIP_OK(hipMalloc(&b.soff, n * 4));
-        HIP_OK(hipMalloc(&b.sdu, n * 8));
-        HIP_OK(hipMalloc(&b.zid, n * 4));
-        HIP_OK(hipMalloc(&b.chunk_start, g->chunk_cap * 4));
-        HIP_OK(hipHostMalloc((void **)&g->h_ctl, 2 * sizeof(Ctl), hipHostMallocDefault));
+        HIP_OK(hipMalloc(&b.sid, sent * 4));
+        HIP_OK(hipMalloc(&b.soff, sent * 4));
+        HIP_OK(hipMalloc(&b.sdu, sent * 8));
+        HIP_OK(hipMalloc(&b.chunk_start, (uint64_t)kShards * b.chunk_cap * 4));
+        HIP_OK(hipHostMalloc((void **)&g->h_ctl, 2 * sizeof(CtlHead), hipHostMallocDefault));
         HIP_OK(hipEventCreateWithFlags(&g->ev[0], hipEventDisableTiming));
         HIP_OK(hipEventCreateWithFlags(&g->ev[1], hipEventDisableTiming));
         g->bufs_ready = true;
+        g->bufs_scan_blocks = (uint32_t)g->cfg.scan_blocks;
     }
     if (cursors && !b.out_cur) {
         HIP_OK(hipMalloc(&b.in_cur, n * 4));
@@ -596,23 +793,26 @@ struct PhaseKernels {
     kfn terms = nullptr, identify = nullptr, relax = nullptr;
 };
 
-static PhaseKernels pick_phase(int chunk, int in, int out, bool delta) {
+template <int CH>
+static PhaseKernels pick_phase_ch(int in, int out, bool delta) {
     PhaseKernels k;
     if (delta) {
-        switch (chunk) {
-        case 256: k.identify = k_identify_delta<256>; k.relax = k_relax<256, true>; break;
-        case 1024: k.identify = k_identify_delta<1024>; k.relax = k_relax<1024, true>; break;
-        default: k.identify = k_identify_delta<512>; k.relax = k_relax<512, true>; break;
-        }
+        k.identify = k_identify_delta<CH>;
+        k.relax = k_relax<CH, true, false>;
         return k;
     }
     k.terms = pick_terms(in, out);
-    switch (chunk) {
-    case 256: k.identify = pick_identify<256>(in, out); k.relax = k_relax<256, false>; break;
-    case 1024: k.identify = pick_identify<1024>(in, out); k.relax = k_relax<1024, false>; break;
-    default: k.identify = pick_identify<512>(in, out); k.relax = k_relax<512, false>; break;
-    }
+    k.identify = pick_identify<CH>(in, out);
+    k.relax = out == OUT_STATIC_M ? k_relax<CH, false, true> : k_relax<CH, false, false>;
     return k;
+}
+
+static PhaseKernels pick_phase(int chunk, int in, int out, bool delta) {
+    switch (chunk) {
+    case 256: return pick_phase_ch<256>(in, out, delta);
+    case 1024: return pick_phase_ch<1024>(in, out, delta);
+    default: return pick_phase_ch<512>(in, out, delta);
+    }
 }
 
 static int valid_chunk(int c) { return c == 256 || c == 512 || c == 1024; }
@@ -645,7 +845,7 @@ static int run_loop_profiled(sssp_graph *g, const KArgs &a, const PhaseKernels &
             HIP_OK(hipEventRecord(e[3], s));
         }
         HIP_OK(hipGetLastError());
-        HIP_OK(hipMemcpyAsync(&g->h_ctl[0], a.b.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipMemcpyAsync(&g->h_ctl[0], a.b.ctl, sizeof(CtlHead), hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
         const uint64_t real = g->h_ctl[0].phases;
         for (uint32_t i = 0; i < kBatch && k0 + i < real; ++i) {
@@ -668,27 +868,77 @@ static int run_loop_profiled(sssp_graph *g, const KArgs &a, const PhaseKernels &
     return SSSP_OK;
 }
 
+// Six consecutive phases (every parity of the control slots) captured once
+// into a HIP graph; re-captured only when the kernel arguments change.
+constexpr int kGraphPhases = 6;
+
+struct GraphKey {
+    KArgs a;
+    PhaseKernels K;
+    LaunchCfg cfg;
+};
+
+static int ensure_phase_graph(sssp_graph *g, const KArgs &a, const PhaseKernels &K) {
+    GraphKey key;
+    memset(&key, 0, sizeof key);
+    key.a = a;
+    key.K = K;
+    key.cfg = g->cfg;
+    static_assert(sizeof(GraphKey) <= sizeof(g->graph_key), "graph key size");
+    if (g->graph_exec && g->graph_key_len == sizeof key && memcmp(g->graph_key, &key, sizeof key) == 0)
+        return SSSP_OK;
+    if (g->graph_exec) (void)hipGraphExecDestroy(g->graph_exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    g->graph_exec = nullptr;
+    g->graph = nullptr;
+    g->graph_key_len = 0;
+    if (!g->cap_stream) HIP_OK(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
+    hipStream_t cs = g->cap_stream;
+    const dim3 blk(kBlock), gs(g->cfg.scan_blocks), gr(g->cfg.relax_blocks);
+    HIP_OK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    for (int par = 0; par < kGraphPhases; ++par) {
+        if (K.terms) hipLaunchKernelGGL(K.terms, gs, blk, 0, cs, a, par);
+        hipLaunchKernelGGL(K.identify, gs, blk, 0, cs, a, par);
+        hipLaunchKernelGGL(K.relax, gr, blk, 0, cs, a, par);
+    }
+    hipError_t e = hipStreamEndCapture(cs, &g->graph);
+    if (e != hipSuccess) return sssp_set_error(SSSP_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    HIP_OK(hipGraphInstantiate(&g->graph_exec, g->graph, nullptr, nullptr, 0));
+    memcpy(g->graph_key, &key, sizeof key);
+    g->graph_key_len = sizeof key;
+    return SSSP_OK;
+}
+
 // Runs the phase loop: queues phases in growing batches, keeps one batch in
 // flight while the host inspects the previous batch's copy of the control
 // block, and stops once a batch ends with F empty.
 static int run_loop(sssp_graph *g, const KArgs &a, const PhaseKernels &K, uint64_t max_phases) {
     if (g->prof) return run_loop_profiled(g, a, K, max_phases);
+    if (g->cfg.use_graph) {
+        int rc = ensure_phase_graph(g, a, K);
+        if (rc) return rc;
+    }
     hipStream_t s = g->stream;
     const dim3 blk(kBlock);
     const dim3 gs(g->cfg.scan_blocks), gr(g->cfg.relax_blocks);
     uint64_t k = 0;
-    uint32_t batch = 4;
+    uint32_t batch = g->cfg.use_graph ? kGraphPhases : 4;
     int slot = 0;
     bool have_prev = false;
     for (;;) {
-        for (uint32_t i = 0; i < batch; ++i, ++k) {
-            const int par = (int)(k % 6);
-            if (K.terms) hipLaunchKernelGGL(K.terms, gs, blk, 0, s, a, par);
-            hipLaunchKernelGGL(K.identify, gs, blk, 0, s, a, par);
-            hipLaunchKernelGGL(K.relax, gr, blk, 0, s, a, par);
+        if (g->cfg.use_graph) {
+            for (uint32_t i = 0; i < batch; i += kGraphPhases, k += kGraphPhases)
+                HIP_OK(hipGraphLaunch(g->graph_exec, s));
+        } else {
+            for (uint32_t i = 0; i < batch; ++i, ++k) {
+                const int par = (int)(k % 6);
+                if (K.terms) hipLaunchKernelGGL(K.terms, gs, blk, 0, s, a, par);
+                hipLaunchKernelGGL(K.identify, gs, blk, 0, s, a, par);
+                hipLaunchKernelGGL(K.relax, gr, blk, 0, s, a, par);
+            }
         }
         HIP_OK(hipGetLastError());
-        HIP_OK(hipMemcpyAsync(&g->h_ctl[slot], a.b.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipMemcpyAsync(&g->h_ctl[slot], a.b.ctl, sizeof(CtlHead), hipMemcpyDeviceToHost, s));
         HIP_OK(hipEventRecord(g->ev[slot], s));
         if (have_prev) {
             HIP_OK(hipEventSynchronize(g->ev[slot ^ 1]));
@@ -696,27 +946,46 @@ static int run_loop(sssp_graph *g, const KArgs &a, const PhaseKernels &K, uint64
         }
         have_prev = true;
         slot ^= 1;
-        if (batch < 64) batch *= 2;
+        if (batch < 48) batch *= 2;
         if (k > max_phases + 2 * 64 + 8)
             return sssp_set_error(SSSP_ERR_INTERNAL, "phase loop did not terminate after %llu phases",
                                   (unsigned long long)k);
     }
     HIP_OK(hipStreamSynchronize(s));
-    HIP_OK(hipMemcpy(&g->h_ctl[0], a.b.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
-    if (!g->h_ctl[0].done) return sssp_set_error(SSSP_ERR_INTERNAL, "solve ended without an empty fringe");
     return SSSP_OK;
 }
 
-static void fill_stats(const sssp_graph *g, const Ctl &c, sssp_stats *st) {
-    if (!st) return;
-    st->phases = c.phases;
-    st->buckets = c.buckets;
-    st->sum_f = c.sum_f;
-    st->n_reach = c.settled;
-    st->m_reach = c.m_reach;
-    st->relax_edges = c.relax_edges;
-    st->improving = c.improving;
-    st->precompute_ns = g->precompute_ns;
+static unsigned long long shard_sum(const Sharded &x) {
+    unsigned long long t = 0;
+    for (int i = 0; i < kShards; ++i) t += x.v[i * kPad];
+    return t;
+}
+
+// Copies the whole control block once at the end of a solve and checks the
+// end state: F empty, and every vertex ever queued settled.
+static int finish_stats(const sssp_graph *g, const Ctl *dctl, sssp_stats *st, uint32_t *phases) {
+    Ctl *c = new (std::nothrow) Ctl;
+    if (!c) return sssp_set_error(SSSP_ERR_OOM, "host control block");
+    hipError_t e = hipMemcpy(c, dctl, sizeof(Ctl), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) { delete c; return sssp_set_error(SSSP_ERR_DEVICE, "control block copy: %s", hipGetErrorString(e)); }
+    const unsigned long long reached = shard_sum(c->reached);
+    int rc = SSSP_OK;
+    if (!c->h.done || reached != c->h.settled)
+        rc = sssp_set_error(SSSP_ERR_INTERNAL, "solve ended in an inconsistent state (done=%u reached=%llu settled=%llu)",
+                            c->h.done, reached, c->h.settled);
+    if (phases) *phases = c->h.phases;
+    if (st) {
+        st->phases = c->h.phases;
+        st->buckets = c->h.buckets;
+        st->sum_f = c->h.sum_f;
+        st->n_reach = c->h.settled;
+        st->m_reach = c->h.m_reach;
+        st->relax_edges = shard_sum(c->relax_edges);
+        st->improving = shard_sum(c->improving);
+        st->precompute_ns = g->precompute_ns;
+    }
+    delete c;
+    return rc;
 }
 
 static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_t crit,
@@ -771,19 +1040,18 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
     hipLaunchKernelGGL(k_init_state, dim3(ib), dim3(256), 0, s, g->n, source, a.b.dist, a.b.st, phase_of,
                        dyn ? a.b.out_cur : nullptr, g->rp, (in >= IN_SIMPLE_M) ? a.b.in_cur : nullptr,
                        g->ip, delta_mode ? a.b.stamp : nullptr);
-    hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(1), 0, s, a.b.ctl, g->vmin, source, n_deltas);
+    hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(64), 0, s, a.b.ctl, g->vmin, source, n_deltas);
     const PhaseKernels K = pick_phase(g->cfg.chunk, in, out, delta_mode);
     // phases <= reachable vertices; Delta rounds <= 2 * n + light rounds bounded by n per bucket
     // Delta: light rounds per bucket <= window vertices + 1, one heavy round per bucket
     const uint64_t max_phases = delta_mode ? 4ull * g->n + 64 : (uint64_t)g->n + 2;
     rc = run_loop(g, a, K, max_phases);
-    if (rc == SSSP_OK) {
-        fill_stats(g, g->h_ctl[0], stats);
-        if (trace_cap) {
-            uint32_t cnt = g->h_ctl[0].phases < trace_cap ? g->h_ctl[0].phases : trace_cap;
-            if (cnt && hipMemcpy(trace, a.b.trace, cnt * sizeof(PhaseRec), hipMemcpyDeviceToHost) != hipSuccess)
-                rc = sssp_set_error(SSSP_ERR_DEVICE, "trace copy failed");
-        }
+    uint32_t phases = 0;
+    if (rc == SSSP_OK) rc = finish_stats(g, a.b.ctl, stats, &phases);
+    if (rc == SSSP_OK && trace_cap) {
+        const uint32_t cnt = phases < trace_cap ? phases : trace_cap;
+        if (cnt && hipMemcpy(trace, a.b.trace, cnt * sizeof(PhaseRec), hipMemcpyDeviceToHost) != hipSuccess)
+            rc = sssp_set_error(SSSP_ERR_DEVICE, "trace copy failed");
     }
     if (a.b.trace) sssp_free(a.b.trace);
     return rc;
@@ -827,5 +1095,27 @@ extern "C" int sssp_profile_enable(sssp_graph *g, int enable) {
 extern "C" int sssp_profile_get(const sssp_graph *g, sssp_kernel_profile *out) {
     if (!g || !out) return sssp_set_error(SSSP_ERR_INVALID, "NULL argument");
     *out = g->last_prof;
+    return SSSP_OK;
+}
+
+extern "C" int sssp_get_launch(const sssp_graph *g, sssp_launch_cfg *out) {
+    if (!g || !out) return sssp_set_error(SSSP_ERR_INVALID, "NULL argument");
+    out->scan_blocks = (uint32_t)g->cfg.scan_blocks;
+    out->relax_blocks = (uint32_t)g->cfg.relax_blocks;
+    out->chunk = (uint32_t)g->cfg.chunk;
+    out->use_graph = (uint32_t)g->cfg.use_graph;
+    return SSSP_OK;
+}
+
+extern "C" int sssp_set_launch(sssp_graph *g, const sssp_launch_cfg *cfg) {
+    if (!g || !cfg) return sssp_set_error(SSSP_ERR_INVALID, "NULL argument");
+    if (cfg->scan_blocks == 0 || cfg->relax_blocks == 0 || cfg->scan_blocks > (1u << 20) ||
+        cfg->relax_blocks > (1u << 20) || !valid_chunk((int)cfg->chunk))
+        return sssp_set_error(SSSP_ERR_INVALID, "bad launch shape (%u, %u, %u)", cfg->scan_blocks,
+                              cfg->relax_blocks, cfg->chunk);
+    g->cfg.scan_blocks = (int)cfg->scan_blocks;
+    g->cfg.relax_blocks = (int)cfg->relax_blocks;
+    g->cfg.chunk = (int)cfg->chunk;
+    g->cfg.use_graph = cfg->use_graph != 0;
     return SSSP_OK;
 }

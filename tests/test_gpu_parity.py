@@ -165,3 +165,64 @@ def test_invalid_arguments_rejected(B):
         B.delta_step(dg, 0, 0)               # zero bucket width
     r = B.solve(dg, 0, O.STATIC_OR)          # the handle still works afterwards
     assert r.phases > 1
+
+
+def test_graph_replay_matches_stream_launches(B):
+    """Phases replayed from a captured HIP graph give the same results as plain launches, on every
+    replay, with eager solves in between."""
+    g = G.rmat(14, 16, 1, 1 << 16, 12)
+    dg = B.DeviceGraph.from_graph(g)
+    ref = O.phased(g, 0, O.STATIC_OR)
+    for use_graph in (0, 1, 1, 0, 1, 1):
+        dg.set_launch(use_graph=use_graph)
+        r = B.solve_ex(dg, 0, O.STATIC_OR, phase_of=True)
+        assert np.array_equal(r.dist_u64(), ref.dist)
+        assert r.phases == ref.phases and r.stats["sum_f"] == ref.sum_f
+        assert np.array_equal(r.phase_of.cpu().numpy().view(np.uint32), ref.phase_of)
+    for use_graph in (1, 0, 1):
+        dg.set_launch(use_graph=use_graph)
+        r = B.delta_step_ex(dg, 0, [1 << 12])
+        rd = O.delta_step(g, 0, [1 << 12])
+        assert np.array_equal(r.dist_u64(), rd.dist) and r.phases == rd.rounds
+
+
+@pytest.mark.parametrize("cfg", [dict(scan_blocks=1, relax_blocks=1, chunk=256),
+                                 dict(scan_blocks=7, relax_blocks=3, chunk=1024),
+                                 dict(scan_blocks=4096, relax_blocks=4096, chunk=512)])
+def test_launch_shapes_do_not_change_results(B, cfg):
+    g = G.er(20000, 12, 1, 5000, 13)
+    dg = B.DeviceGraph.from_graph(g)
+    dg.set_launch(**cfg)
+    for c in (O.STATIC_OR, O.FULL_OR):
+        check_phased(B, g, 0, c, str(cfg))
+
+
+def test_settle_buffer_overflow_path(B):
+    """One phase settles thousands of vertices with out-edges inside a single scan block, more than
+    the per-block LDS collection buffer holds, so part of them take the direct append path."""
+    k = 60000
+    edges = [(0, 1 + i, 1) for i in range(k)] + [(1 + i, 1 + k + i, 1 + (i % 5)) for i in range(k)]
+    g = G.from_edges(1 + 2 * k, edges, "two-level-star")
+    dg = B.DeviceGraph.from_graph(g)
+    dg.set_launch(scan_blocks=8)  # about 15000 vertices per block
+    ref = O.phased(g, 0, O.STATIC_OR)
+    r = B.solve_ex(dg, 0, O.STATIC_OR, phase_of=True)
+    assert np.array_equal(r.dist_u64(), ref.dist) and r.phases == ref.phases
+    assert np.array_equal(r.phase_of.cpu().numpy().view(np.uint32), ref.phase_of)
+    rd = B.delta_step_ex(dg, 0, [1 << 20])
+    od = O.delta_step(g, 0, [1 << 20])
+    assert np.array_equal(rd.dist_u64(), od.dist) and rd.phases == od.rounds
+
+
+def test_scratch_rebuilt_after_launch_change(B):
+    """Changing the scan grid rebuilds the per-solve scratch; every solve kind still works after it."""
+    g = G.er(3000, 6, 1, 300, 14)
+    dg = B.DeviceGraph.from_graph(g)
+    od = O.delta_step(g, 0, [64])
+    op = O.phased(g, 0, O.FULL_OR)
+    for sb in (3, 11, 3):
+        r = B.delta_step_ex(dg, 0, [64])
+        assert np.array_equal(r.dist_u64(), od.dist) and r.phases == od.rounds
+        r = B.solve(dg, 0, O.FULL_OR)
+        assert np.array_equal(r.dist_u64(), op.dist) and r.phases == op.phases
+        dg.set_launch(scan_blocks=sb)
