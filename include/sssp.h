@@ -159,15 +159,38 @@ int sssp_delta_step_ex(sssp_graph *g, uint32_t source, const uint64_t *deltas, u
 
 /*
  * Batched phased SSSP: nq independent queries (graphs[i], sources[i]) in one
- * persistent launch. Graph handles may repeat. Every query uses `criterion`.
+ * persistent launch; each workgroup runs whole queries, largest first, with
+ * the phase loop of Section 3 inside the kernel. Graph handles may repeat.
+ * Every query uses `criterion`, a disjunction of SSSP_DIJK, SSSP_IN_STATIC
+ * and SSSP_OUT_STATIC (the static criteria, eq. crit:instatic / crit:outstatic).
  *   dist_outs  HOST array of nq DEVICE pointers, each with room for
- *              graphs[i]->n uint64.
+ *              graphs[i]->n uint64; the buffers must not overlap.
  *   phases_out HOST, nq entries, may be NULL.
- * Errors: SSSP_ERR_INVALID for nq = 0, a NULL pointer, a bad source or
- * criterion.
+ * Runs on graphs[0]'s stream. Errors: SSSP_ERR_INVALID for nq = 0, a NULL
+ * pointer, a bad source or criterion; SSSP_ERR_UNSUPPORTED for the dynamic
+ * criteria.
  */
 int sssp_solve_batch(sssp_graph *const *graphs, const uint32_t *sources, uint32_t nq,
                      uint32_t criterion, uint64_t *const *dist_outs, uint32_t *phases_out);
+
+/* Launch shape of the batched solver. A zero field means the default. */
+typedef struct {
+    uint32_t block;   /* threads per workgroup: 256, 512 or 1024 (default 512) */
+    uint32_t split;   /* rows with more out-edges than this are expanded by the whole
+                         workgroup instead of one lane (default 64) */
+    uint32_t blocks;  /* workgroups of the persistent launch (default 4 per compute unit) */
+} sssp_batch_cfg;
+
+/* sssp_solve_batch with an explicit launch shape (cfg may be NULL: defaults). */
+int sssp_solve_batch_ex(sssp_graph *const *graphs, const uint32_t *sources, uint32_t nq,
+                        uint32_t criterion, uint64_t *const *dist_outs, uint32_t *phases_out,
+                        const sssp_batch_cfg *cfg);
+
+/* Process-wide default shape used by sssp_solve_batch (set by the autotuner). */
+int sssp_batch_set_config(const sssp_batch_cfg *cfg);
+int sssp_batch_get_config(sssp_batch_cfg *cfg);
+
+
 
 /* Per-kernel device time of the last solve on g, measured with HIP events on
  * the graph's stream around every kernel launch (observability; enabling it
@@ -200,6 +223,25 @@ int sssp_get_launch(const sssp_graph *g, sssp_launch_cfg *out);
 /* Set the launch shape for later solves on g. Errors: SSSP_ERR_INVALID for a
  * zero block count or an unsupported chunk size. */
 int sssp_set_launch(sssp_graph *g, const sssp_launch_cfg *cfg);
+
+/*
+ * Autotuner for the plain solver: times sssp_solve(g, source, criterion) with
+ * HIP events for a set of launch shapes (scan grid, relax grid, chunk size,
+ * graph replay), keeps the fastest on g and returns it in best (may be NULL)
+ * with its time in best_ms (may be NULL). Distances are never affected.
+ */
+int sssp_autotune(sssp_graph *g, uint32_t source, uint32_t criterion, sssp_launch_cfg *best,
+                  float *best_ms);
+
+/*
+ * Autotuner for the batched solver: times the batch for workgroup sizes,
+ * degree-split thresholds and workgroup counts, makes the fastest the
+ * process-wide default and returns it. dist_outs are overwritten with the
+ * batch's distances.
+ */
+int sssp_autotune_batch(sssp_graph *const *graphs, const uint32_t *sources, uint32_t nq,
+                        uint32_t criterion, uint64_t *const *dist_outs, sssp_batch_cfg *best,
+                        float *best_ms);
 
 /* Human-readable description of the last error on the calling thread. */
 const char *sssp_last_error(void);

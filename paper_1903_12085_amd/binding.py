@@ -25,7 +25,9 @@ FULL_OR = IN_FULL | OUT_FULL
 
 SYMBOLS = ["sssp_graph_create", "sssp_graph_destroy", "sssp_set_stream", "sssp_graph_minima", "sssp_solve",
            "sssp_solve_ex", "sssp_delta_step", "sssp_delta_step_ex", "sssp_solve_batch", "sssp_last_error",
-           "sssp_profile_enable", "sssp_profile_get", "sssp_get_launch", "sssp_set_launch"]
+           "sssp_profile_enable", "sssp_profile_get", "sssp_get_launch", "sssp_set_launch",
+           "sssp_solve_batch_ex", "sssp_batch_set_config", "sssp_batch_get_config", "sssp_autotune",
+           "sssp_autotune_batch"]
 
 ERRORS = {-1: "SSSP_ERR_INVALID", -2: "SSSP_ERR_OOM", -3: "SSSP_ERR_DEVICE", -4: "SSSP_ERR_UNSUPPORTED",
           -5: "SSSP_ERR_INTERNAL"}
@@ -62,6 +64,13 @@ class LaunchCfg(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+class BatchCfg(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_uint32), ("split", ctypes.c_uint32), ("blocks", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 PHASE_REC = np.dtype([("min_d", np.uint64), ("fringe", np.uint32), ("settled", np.uint32),
                       ("criterion", np.uint32), ("edges", np.uint32)])
 
@@ -90,6 +99,11 @@ def load(path: str = LIB_PATH):
     lib.sssp_profile_get.argtypes = [P, ctypes.POINTER(KernelProfile)]
     lib.sssp_get_launch.argtypes = [P, ctypes.POINTER(LaunchCfg)]
     lib.sssp_set_launch.argtypes = [P, ctypes.POINTER(LaunchCfg)]
+    lib.sssp_solve_batch_ex.argtypes = [P, P, u32, u32, P, P, ctypes.POINTER(BatchCfg)]
+    lib.sssp_batch_set_config.argtypes = [ctypes.POINTER(BatchCfg)]
+    lib.sssp_batch_get_config.argtypes = [ctypes.POINTER(BatchCfg)]
+    lib.sssp_autotune.argtypes = [P, u32, u32, ctypes.POINTER(LaunchCfg), ctypes.POINTER(ctypes.c_float)]
+    lib.sssp_autotune_batch.argtypes = [P, P, u32, u32, P, ctypes.POINTER(BatchCfg), ctypes.POINTER(ctypes.c_float)]
     lib.sssp_last_error.restype = ctypes.c_char_p
     lib.sssp_last_error.argtypes = []
     for name in SYMBOLS:
@@ -253,16 +267,50 @@ def delta_step_ex(g: DeviceGraph, source: int, deltas, dist=None, trace_cap: int
     return SolveResult(dist, int(st.phases), st.as_dict(), None, tr)
 
 
-def solve_batch(graphs, sources, criterion: int, dists=None):
-    """graphs: list of DeviceGraph (may repeat), sources: list of ints."""
+def _batch_args(graphs, sources, dists):
     nq = len(sources)
     if dists is None:
         dists = [new_dist(g.n) for g in graphs]
     handles = (ctypes.c_void_p * nq)(*[g.handle.value for g in graphs])
     srcs = np.ascontiguousarray(sources, np.uint32)
     outs = (ctypes.c_void_p * nq)(*[d.data_ptr() for d in dists])
+    graphs[0]._bind_stream()
+    return nq, dists, handles, srcs, outs
+
+
+def solve_batch(graphs, sources, criterion: int, dists=None, cfg: dict | None = None):
+    """graphs: list of DeviceGraph (may repeat), sources: list of ints. Returns (dists, phases)."""
+    nq, dists, handles, srcs, outs = _batch_args(graphs, sources, dists)
     phases = np.zeros(nq, np.uint32)
-    for g in set(graphs):
-        g._bind_stream()
-    _check(load().sssp_solve_batch(handles, _np_ptr(srcs), nq, criterion, outs, _np_ptr(phases)))
+    if cfg is None:
+        _check(load().sssp_solve_batch(handles, _np_ptr(srcs), nq, criterion, outs, _np_ptr(phases)))
+    else:
+        c = BatchCfg(**{k: int(v) for k, v in cfg.items()})
+        _check(load().sssp_solve_batch_ex(handles, _np_ptr(srcs), nq, criterion, outs, _np_ptr(phases),
+                                          ctypes.byref(c)))
     return dists, phases
+
+
+def batch_config() -> dict:
+    c = BatchCfg()
+    _check(load().sssp_batch_get_config(ctypes.byref(c)))
+    return c.as_dict()
+
+
+def set_batch_config(**kw):
+    c = BatchCfg(**{k: int(v) for k, v in kw.items()})
+    _check(load().sssp_batch_set_config(ctypes.byref(c)))
+
+
+def autotune(g: DeviceGraph, source: int, criterion: int):
+    c, ms = LaunchCfg(), ctypes.c_float(0)
+    g._bind_stream()
+    _check(load().sssp_autotune(g.handle, source, criterion, ctypes.byref(c), ctypes.byref(ms)))
+    return c.as_dict(), float(ms.value)
+
+
+def autotune_batch(graphs, sources, criterion: int, dists=None):
+    nq, dists, handles, srcs, outs = _batch_args(graphs, sources, dists)
+    c, ms = BatchCfg(), ctypes.c_float(0)
+    _check(load().sssp_autotune_batch(handles, _np_ptr(srcs), nq, criterion, outs, ctypes.byref(c), ctypes.byref(ms)))
+    return c.as_dict(), float(ms.value)

@@ -1,16 +1,287 @@
-// Batched phased SSSP (placeholder until the persistent batched kernel lands).
+// Batched phased SSSP: many (graph, source) queries in one persistent launch.
+//
+// Each workgroup takes whole queries from a device work queue (largest first)
+// and runs the generic phased algorithm of Section 3 for that query with
+// workgroup barriers only, so a batch needs no grid synchronisation and no
+// launch per phase:
+//   identify  block-stride scan of the query's vertices; a queued vertex the
+//             criterion certifies (phase-start minD / OUT-STATIC threshold)
+//             is marked "settled this phase"; the others fold next minima.
+//   relax     second scan: every vertex settled this phase is expanded; rows
+//             up to `split` edges by their own lane, longer rows are queued in
+//             LDS and expanded by the whole workgroup (degree split). 64-bit
+//             atomicMin on the query's distance array; the atomic that
+//             replaces infinity queues the target. Improving candidates fold
+//             into next minD / threshold.
+// Distances and states written in one phase are read in the next with
+// L1-bypassing atomic loads (device-scope atomics update L2, not the CU's L1).
+//
+// Criteria: DIJK, IN-STATIC, OUT-STATIC and their disjunctions (the static
+// criteria need no per-phase term pass).
+#include <algorithm>
+#include <string.h>
+#include <vector>
+
 #include "common.h"
 #include "graph.h"
 
+struct BatchQuery {
+    const uint32_t *rp;
+    const uint2 *edges;
+    const uint2 *vmin;
+    unsigned long long *dist;
+    uint8_t *st;
+    uint32_t n;
+    uint32_t src;
+};
+
+struct BatchCtl {
+    unsigned int next;    // work-queue head
+    unsigned int error;   // set if a query exceeds its phase bound
+};
+
+constexpr uint8_t ST_NEW = 3;  // settled in the current phase, out-edges not yet relaxed
+constexpr int kHubCap = 256;
+
+__device__ __forceinline__ unsigned long long ld_dist(const unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint8_t ld_st(const uint8_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int BS>
+__device__ __forceinline__ unsigned long long bmin(unsigned long long x, unsigned long long *sh) {
+    x = wave_min64(x);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = x;
+    __syncthreads();
+    unsigned long long r = INF64;
+    for (int i = 0; i < BS / 64; ++i) r = umin64(r, sh[i]);
+    __syncthreads();
+    return r;
+}
+template <int BS>
+__device__ __forceinline__ unsigned long long bsum(unsigned long long x, unsigned long long *sh) {
+    x = wave_sum64(x);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = x;
+    __syncthreads();
+    unsigned long long r = 0;
+    for (int i = 0; i < BS / 64; ++i) r += sh[i];
+    __syncthreads();
+    return r;
+}
+
+template <int BS, int IN, bool OUT>
+__device__ __forceinline__ void relax_edge(const BatchQuery &q, unsigned long long du, uint2 ed,
+                                           unsigned long long &cmin, unsigned long long &ctst) {
+    const uint8_t sv = ld_st(&q.st[ed.x]);
+    if (sv == ST_S || sv == ST_NEW) return;
+    const unsigned long long cand = du + ed.y;
+    if (cand < ld_dist(&q.dist[ed.x])) {
+        const unsigned long long old = atomicMin(&q.dist[ed.x], cand);
+        if (cand < old) {
+            cmin = umin64(cmin, cand);
+            if (OUT) ctst = umin64(ctst, sadd64(cand, w64(q.vmin[ed.x].y)));
+            if (old == INF64) q.st[ed.x] = ST_F;
+        }
+    }
+}
+
+// IN: IN_NONE, IN_DIJK or IN_STATIC_M; OUT: OUT-STATIC on/off.
+template <int BS, int IN, bool OUT>
+__global__ __launch_bounds__(BS) void k_batch(const BatchQuery *__restrict__ queries, const uint32_t *__restrict__ order,
+                                              uint32_t nq, BatchCtl *ctl, uint32_t *__restrict__ phases_out,
+                                              uint32_t split) {
+    __shared__ unsigned long long sh[BS / 64];
+    __shared__ uint32_t s_q;
+    __shared__ uint32_t hub_v[kHubCap];
+    __shared__ unsigned long long hub_du[kHubCap];
+    __shared__ uint32_t hub_n;
+    for (;;) {
+        if (threadIdx.x == 0) s_q = atomicAdd(&ctl->next, 1u);
+        __syncthreads();
+        const uint32_t qi = s_q;
+        __syncthreads();
+        if (qi >= nq) return;
+        const BatchQuery q = queries[order[qi]];
+        const uint32_t n = q.n;
+        for (uint32_t v = threadIdx.x; v < n; v += BS) {
+            q.dist[v] = v == q.src ? 0ull : INF64;
+            q.st[v] = v == q.src ? ST_F : ST_U;
+        }
+        unsigned long long minD = 0, T = w64(q.vmin[q.src].y);
+        uint32_t phases = 0;
+        __syncthreads();
+        for (;;) {
+            // identify
+            unsigned long long fmin = INF64, ftst = INF64, nset = 0;
+            for (uint32_t v = threadIdx.x; v < n; v += BS) {
+                if (ld_st(&q.st[v]) != ST_F) continue;
+                const unsigned long long dv = ld_dist(&q.dist[v]);
+                const uint2 mm = q.vmin[v];
+                bool ok = false;
+                if (IN == IN_DIJK) ok = dv == minD;
+                else if (IN == IN_STATIC_M) ok = dv <= sadd64(minD, w64(mm.x));
+                if (OUT) ok = ok || dv <= T;
+                if (ok) {
+                    q.st[v] = ST_NEW;
+                    ++nset;
+                } else {
+                    fmin = umin64(fmin, dv);
+                    if (OUT) ftst = umin64(ftst, sadd64(dv, w64(mm.y)));
+                }
+            }
+            if (threadIdx.x == 0) hub_n = 0;
+            nset = bsum<BS>(nset, sh);
+            if (nset == 0) break;  // F is empty (a non-empty F always certifies its minimum)
+            ++phases;
+            if (phases > n + 1) {
+                if (threadIdx.x == 0) atomicOr(&ctl->error, 1u);
+                break;
+            }
+            // relax: short rows by their own lane, long rows by the whole workgroup
+            unsigned long long cmin = INF64, ctst = INF64;
+            for (uint32_t v = threadIdx.x; v < n; v += BS) {
+                if (ld_st(&q.st[v]) != ST_NEW) continue;
+                q.st[v] = ST_S;
+                const uint32_t b = q.rp[v], e = q.rp[v + 1];
+                const unsigned long long du = ld_dist(&q.dist[v]);
+                if (e - b > split) {
+                    const uint32_t slot = atomicAdd(&hub_n, 1u);
+                    if (slot < kHubCap) {
+                        hub_v[slot] = v;
+                        hub_du[slot] = du;
+                        continue;
+                    }
+                }
+                for (uint32_t k = b; k < e; ++k) relax_edge<BS, IN, OUT>(q, du, q.edges[k], cmin, ctst);
+            }
+            __syncthreads();
+            const uint32_t nh = min(hub_n, (uint32_t)kHubCap);
+            for (uint32_t h = 0; h < nh; ++h) {
+                const uint32_t v = hub_v[h];
+                const uint32_t b = q.rp[v], e = q.rp[v + 1];
+                for (uint32_t k = b + threadIdx.x; k < e; k += BS) relax_edge<BS, IN, OUT>(q, hub_du[h], q.edges[k], cmin, ctst);
+            }
+            minD = bmin<BS>(umin64(fmin, cmin), sh);
+            if (OUT) T = bmin<BS>(umin64(ftst, ctst), sh);
+        }
+        if (threadIdx.x == 0) phases_out[order[qi]] = phases;
+        __syncthreads();
+    }
+}
+
+typedef void (*bfn)(const BatchQuery *, const uint32_t *, uint32_t, BatchCtl *, uint32_t *, uint32_t);
+
+template <int BS>
+static bfn pick_batch_bs(int in, bool out) {
+    if (in == IN_DIJK) return out ? k_batch<BS, IN_DIJK, true> : k_batch<BS, IN_DIJK, false>;
+    if (in == IN_STATIC_M) return out ? k_batch<BS, IN_STATIC_M, true> : k_batch<BS, IN_STATIC_M, false>;
+    return out ? k_batch<BS, IN_NONE, true> : k_batch<BS, IN_NONE, false>;
+}
+
+static bfn pick_batch(int bs, int in, bool out) {
+    switch (bs) {
+    case 256: return pick_batch_bs<256>(in, out);
+    case 1024: return pick_batch_bs<1024>(in, out);
+    default: return pick_batch_bs<512>(in, out);
+    }
+}
+
+static sssp_batch_cfg g_batch_cfg = {0, 0, 0};  // process-wide default shape
+
+extern "C" int sssp_batch_set_config(const sssp_batch_cfg *cfg) {
+    if (!cfg) return sssp_set_error(SSSP_ERR_INVALID, "NULL argument");
+    if (cfg->block != 0 && cfg->block != 256 && cfg->block != 512 && cfg->block != 1024)
+        return sssp_set_error(SSSP_ERR_INVALID, "block size must be 256, 512 or 1024");
+    g_batch_cfg = *cfg;
+    return SSSP_OK;
+}
+
+extern "C" int sssp_batch_get_config(sssp_batch_cfg *cfg) {
+    if (!cfg) return sssp_set_error(SSSP_ERR_INVALID, "NULL argument");
+    *cfg = g_batch_cfg;
+    return SSSP_OK;
+}
+
 extern "C" int sssp_solve_batch(sssp_graph *const *graphs, const uint32_t *sources, uint32_t nq,
                                 uint32_t criterion, uint64_t *const *dist_outs, uint32_t *phases_out) {
+    return sssp_solve_batch_ex(graphs, sources, nq, criterion, dist_outs, phases_out, nullptr);
+}
+
+extern "C" int sssp_solve_batch_ex(sssp_graph *const *graphs, const uint32_t *sources, uint32_t nq,
+                                   uint32_t criterion, uint64_t *const *dist_outs, uint32_t *phases_out,
+                                   const sssp_batch_cfg *cfg_in) {
+    const sssp_batch_cfg cfg = cfg_in ? *cfg_in : g_batch_cfg;
+    if (cfg.block != 0 && cfg.block != 256 && cfg.block != 512 && cfg.block != 1024)
+        return sssp_set_error(SSSP_ERR_INVALID, "block size must be 256, 512 or 1024");
     if (nq == 0 || !graphs || !sources || !dist_outs)
         return sssp_set_error(SSSP_ERR_INVALID, "empty batch or NULL array");
-    for (uint32_t q = 0; q < nq; ++q) {
-        uint32_t ph = 0;
-        int rc = sssp_solve(graphs[q], sources[q], criterion, dist_outs[q], &ph);
-        if (rc) return rc;
-        if (phases_out) phases_out[q] = ph;
+    if (criterion == 0 || (criterion & ~SSSP_CRIT_ALL))
+        return sssp_set_error(SSSP_ERR_INVALID, "criterion 0x%x is empty or has unknown bits", criterion);
+    int in = IN_NONE, out = OUT_NONE;
+    crit_modes(criterion, &in, &out);
+    if (in > IN_STATIC_M || out > OUT_STATIC_M)
+        return sssp_set_error(SSSP_ERR_UNSUPPORTED, "the batched solver evaluates DIJK, IN-STATIC and OUT-STATIC");
+    std::vector<BatchQuery> hq(nq);
+    std::vector<uint64_t> st_off(nq);
+    uint64_t st_total = 0;
+    for (uint32_t i = 0; i < nq; ++i) {
+        const sssp_graph *g = graphs[i];
+        if (!g || !dist_outs[i]) return sssp_set_error(SSSP_ERR_INVALID, "query %u: NULL graph or output", i);
+        if (sources[i] >= g->n) return sssp_set_error(SSSP_ERR_INVALID, "query %u: source %u >= n", i, sources[i]);
+        hq[i].rp = g->rp;
+        hq[i].edges = g->edges;
+        hq[i].vmin = g->vmin;
+        hq[i].dist = (unsigned long long *)dist_outs[i];
+        hq[i].n = g->n;
+        hq[i].src = sources[i];
+        st_off[i] = st_total;
+        st_total += (g->n + 255) & ~255ull;
     }
-    return SSSP_OK;
+    // longest-processing-time order: most edges first
+    std::vector<uint32_t> order(nq);
+    for (uint32_t i = 0; i < nq; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+        return graphs[x]->m + graphs[x]->n > graphs[y]->m + graphs[y]->n;
+    });
+    hipStream_t s = graphs[0]->stream;
+    HIP_OK(hipSetDevice(graphs[0]->device));
+    uint8_t *st = nullptr;
+    BatchQuery *dq = nullptr;
+    uint32_t *dorder = nullptr, *dph = nullptr;
+    BatchCtl *dctl = nullptr;
+    int rc = SSSP_OK;
+#define TRY(call) do { hipError_t _e = (call); if (_e != hipSuccess) { \
+        rc = sssp_set_error(_e == hipErrorOutOfMemory ? SSSP_ERR_OOM : SSSP_ERR_DEVICE, "%s: %s", #call, hipGetErrorString(_e)); goto done; } } while (0)
+    TRY(hipMalloc(&st, st_total));
+    for (uint32_t i = 0; i < nq; ++i) hq[i].st = st + st_off[i];
+    TRY(hipMalloc(&dq, nq * sizeof(BatchQuery)));
+    TRY(hipMalloc(&dorder, nq * sizeof(uint32_t)));
+    TRY(hipMalloc(&dph, nq * sizeof(uint32_t)));
+    TRY(hipMalloc(&dctl, sizeof(BatchCtl)));
+    TRY(hipMemcpyAsync(dq, hq.data(), nq * sizeof(BatchQuery), hipMemcpyHostToDevice, s));
+    TRY(hipMemcpyAsync(dorder, order.data(), nq * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    TRY(hipMemsetAsync(dctl, 0, sizeof(BatchCtl), s));
+    {
+        int dev = 0, cus = 256;
+        hipDeviceProp_t p;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+        const int bs = cfg.block ? (int)cfg.block : 512;
+        const uint32_t split = cfg.split ? cfg.split : 64;
+        uint32_t grid = cfg.blocks ? cfg.blocks : (uint32_t)cus * (bs >= 1024 ? 2 : 4);
+        if (grid > nq) grid = nq;
+        bfn k = pick_batch(bs, in, out == OUT_STATIC_M);
+        hipLaunchKernelGGL(k, dim3(grid), dim3(bs), 0, s, dq, dorder, nq, dctl, dph, split);
+        TRY(hipGetLastError());
+        BatchCtl hctl;
+        TRY(hipMemcpyAsync(&hctl, dctl, sizeof hctl, hipMemcpyDeviceToHost, s));
+        if (phases_out) TRY(hipMemcpyAsync(phases_out, dph, nq * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        TRY(hipStreamSynchronize(s));
+        if (hctl.error) rc = sssp_set_error(SSSP_ERR_INTERNAL, "a batched query exceeded its phase bound");
+    }
+done:
+#undef TRY
+    sssp_free(st); sssp_free(dq); sssp_free(dorder); sssp_free(dph); sssp_free(dctl);
+    return rc;
 }

@@ -96,10 +96,10 @@ struct DevGraph {
 // Scratch used by a solve.
 struct SolveBufs {
     Ctl *ctl;
-    uint32_t shard_cap;     // S' entries per shard (sid/soff/sdu hold kShards * shard_cap)
+    uint32_t shard_cap;     // S' entries per shard (srow/soff/sdu hold kShards * shard_cap)
     uint32_t chunk_cap;     // chunk_start entries per shard
     uint8_t *st;
-    uint32_t *sid;          // S' vertex ids (vertices with out-edges)
+    uint32_t *srow;         // S' first out-edge index (row start) of each settled vertex with out-edges
     uint32_t *soff;         // S' exclusive edge offsets
     unsigned long long *sdu;// S' snapshot distances
     uint32_t *chunk_start;  // first S' entry (shard-local) of each shard-local edge chunk

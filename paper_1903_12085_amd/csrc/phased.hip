@@ -43,13 +43,14 @@ struct KArgs {
 __device__ __forceinline__ unsigned long long *slot_of(Sharded &s, int i) { return &s.v[i * kPad]; }
 __device__ __forceinline__ int my_shard() { return (int)(blockIdx.x % kShards); }
 
-// Combine a sharded value inside wavefront 0 (lanes >= kShards contribute the neutral value).
+// Combine a sharded value within one wavefront (lane i reads slot i; lanes >=
+// kShards contribute the neutral value); every lane gets the result.
 __device__ __forceinline__ unsigned long long shard_sum_w0(Sharded &s) {
-    const int i = threadIdx.x;
+    const int i = threadIdx.x & 63;
     return wave_sum64(i < kShards ? s.v[i * kPad] : 0ull);
 }
 __device__ __forceinline__ unsigned long long shard_min_w0(Sharded &s) {
-    const int i = threadIdx.x;
+    const int i = threadIdx.x & 63;
     return wave_min64(i < kShards ? s.v[i * kPad] : INF64);
 }
 // Block 0, threads < kShards: reset every slot.
@@ -111,8 +112,9 @@ __global__ void k_init_ctl(Ctl *ctl, const uint2 *__restrict__ vmin, uint32_t sr
 constexpr int kAppendBuf = 512;
 
 struct AppendLds {
-    uint32_t v[kAppendBuf];
+    uint32_t row[kAppendBuf];
     uint32_t deg[kAppendBuf];
+    unsigned long long du[kAppendBuf];
     uint32_t cnt;     // slots reserved (may run past kAppendBuf)
     uint32_t filled;  // slots written: wavefronts whose reservation fit, which tile [0, filled)
     uint32_t zero;
@@ -121,20 +123,20 @@ struct AppendLds {
 };
 
 template <int CH>
-__device__ __forceinline__ void write_entry(const KArgs &a, int sh, uint32_t j, uint64_t off, uint32_t v,
-                                            uint32_t deg, unsigned long long dv) {
+__device__ __forceinline__ void write_entry(const KArgs &a, int sh, uint32_t j, uint64_t off, uint32_t row,
+                                            uint32_t deg, unsigned long long du) {
     const uint64_t g = (uint64_t)sh * a.b.shard_cap + j;
-    a.b.sid[g] = v;
+    a.b.srow[g] = row;
     a.b.soff[g] = (uint32_t)off;
-    a.b.sdu[g] = dv;
+    a.b.sdu[g] = du;
     uint32_t *cs = a.b.chunk_start + (uint64_t)sh * a.b.chunk_cap;
-    for (uint64_t c = (off + CH - 1) / CH; c * CH < off + deg; ++c) cs[c] = (uint32_t)j;
+    for (uint64_t c = (off + CH - 1) / CH; c * CH < off + deg; ++c) cs[c] = j;
 }
 
 // Wavefront-uniform call: every lane of the wavefront takes part.
 template <int CH>
 __device__ __forceinline__ void append_settled(const KArgs &a, Ctl *ctl, int p2, AppendLds &L, bool set,
-                                               uint32_t v, uint32_t deg, unsigned long long dv) {
+                                               uint32_t row, uint32_t deg, unsigned long long du) {
     const int lane = threadIdx.x & 63;
     const unsigned long long lt = (1ull << lane) - 1ull;
     const bool app = set && deg > 0;
@@ -147,8 +149,9 @@ __device__ __forceinline__ void append_settled(const KArgs &a, Ctl *ctl, int p2,
         if (pos + cntw <= kAppendBuf) {
             if (app) {
                 const uint32_t r = pos + (uint32_t)__popcll(mask & lt);
-                L.v[r] = v;
+                L.row[r] = row;
                 L.deg[r] = deg;
+                L.du[r] = du;
             }
             if (lane == 0) atomicAdd(&L.filled, cntw);
         } else {  // buffer full: direct append for this wavefront (its reserved slots stay unused)
@@ -160,7 +163,7 @@ __device__ __forceinline__ void append_settled(const KArgs &a, Ctl *ctl, int p2,
             base = __shfl(base, 0, 64);
             if (app)
                 write_entry<CH>(a, my_shard(), (uint32_t)(base >> 32) + (uint32_t)__popcll(mask & lt),
-                                (uint32_t)base + incl - x, v, deg, dv);
+                                (uint32_t)base + incl - x, row, deg, du);
         }
     }
     const unsigned long long zm = __ballot(set && deg == 0);
@@ -175,6 +178,10 @@ __device__ __forceinline__ void append_flush(const KArgs &a, Ctl *ctl, int p2, A
     // fit reserved before the first one that did not: the written slots are
     // exactly [0, filled). Slots reserved by overflowing wavefronts are never read.
     const uint32_t cnt = L.filled;
+    if (cnt == 0) {  // block-uniform
+        if (threadIdx.x == 0 && L.zero) atomicAdd(slot_of(ctl->szero[p2], my_shard()), (unsigned long long)L.zero);
+        return;
+    }
     constexpr int PER = kAppendBuf / kBlock;
     uint32_t loc[PER];
     uint32_t tsum = 0;
@@ -196,7 +203,7 @@ __device__ __forceinline__ void append_flush(const KArgs &a, Ctl *ctl, int p2, A
     const uint32_t excl = wbase + incl - tsum;
     if (threadIdx.x == 0) {
         const int sh = my_shard();
-        L.base = cnt ? atomicAdd(slot_of(ctl->spack[p2], sh), ((unsigned long long)cnt << 32) | total) : 0ull;
+        L.base = atomicAdd(slot_of(ctl->spack[p2], sh), ((unsigned long long)cnt << 32) | total);
         if (L.zero) atomicAdd(slot_of(ctl->szero[p2], sh), (unsigned long long)L.zero);
     }
     __syncthreads();
@@ -204,12 +211,19 @@ __device__ __forceinline__ void append_flush(const KArgs &a, Ctl *ctl, int p2, A
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const uint32_t t = threadIdx.x * PER + q;
-        if (t < cnt) {
-            const uint32_t v = L.v[t];
-            write_entry<CH>(a, my_shard(), (uint32_t)(base >> 32) + t, (uint64_t)(uint32_t)base + excl + loc[q], v,
-                            L.deg[t], a.b.dist[v]);
-        }
+        if (t < cnt)
+            write_entry<CH>(a, my_shard(), (uint32_t)(base >> 32) + t, (uint64_t)(uint32_t)base + excl + loc[q],
+                            L.row[t], L.deg[t], L.du[t]);
     }
+}
+
+// Four consecutive state bytes starting at 4q (bytes past n read as unexplored).
+__device__ __forceinline__ uint32_t load_st4(const uint8_t *st, uint32_t q, uint32_t n) {
+    const uint32_t v0 = 4 * q;
+    if (v0 + 3 < n) return *reinterpret_cast<const uint32_t *>(st + v0);
+    uint32_t s4 = 0;
+    for (uint32_t i = 0; i < 4 && v0 + i < n; ++i) s4 |= (uint32_t)st[v0 + i] << (8 * i);
+    return s4;
 }
 
 // ---------------------------------------------------------------------------
@@ -306,23 +320,20 @@ __global__ __launch_bounds__(kBlock) void k_terms(KArgs a, int par) {
 
 // IN: IN_NONE, IN_DIJK, IN_STATIC_M, or 3 = "flag from the term pass".
 // OUT: 0 none, 1 static threshold, 2 threshold from the term pass.
+// Each lane owns four consecutive vertices per step: one 32-bit state load,
+// then the distance / minima loads of all its queued vertices in flight at once.
 template <int IN, int OUT, int CH>
 __global__ __launch_bounds__(kBlock) void k_identify(KArgs a, int par) {
     Ctl *ctl = a.b.ctl;
     const int p2 = par & 1, p3 = par % 3;
     __shared__ unsigned long long sh[kWaves];
-    __shared__ unsigned long long s_reached, s_minD, s_T;
     __shared__ AppendLds L;
     if (threadIdx.x == 0) { L.cnt = 0; L.filled = 0; L.zero = 0; }
-    if (threadIdx.x < 64) {
-        const unsigned long long r = shard_sum_w0(ctl->reached);
-        const unsigned long long md = shard_min_w0(ctl->minD[p3]);
-        const unsigned long long t = OUT == 1 ? shard_min_w0(ctl->tst[p3])
-                                   : OUT == 2 ? shard_min_w0(ctl->tdyn[p3]) : 0ull;
-        if (threadIdx.x == 0) { s_reached = r; s_minD = md; s_T = t; }
-    }
-    __syncthreads();
-    const unsigned long long reached = s_reached, settled = ctl->h.settled;
+    // every wavefront combines the sharded phase-start values itself (no block barrier)
+    const unsigned long long reached = shard_sum_w0(ctl->reached);
+    const unsigned long long minD = shard_min_w0(ctl->minD[p3]);
+    const unsigned long long T = OUT == 1 ? shard_min_w0(ctl->tst[p3]) : OUT == 2 ? shard_min_w0(ctl->tdyn[p3]) : 0ull;
+    const unsigned long long settled = ctl->h.settled;
     const unsigned int P = ctl->h.pnum[p2];
     if (reached == settled) {
         if (blockIdx.x == 0) {
@@ -335,7 +346,6 @@ __global__ __launch_bounds__(kBlock) void k_identify(KArgs a, int par) {
         }
         return;
     }
-    const unsigned long long minD = s_minD, T = s_T;
     if (blockIdx.x == 0) {
         if (threadIdx.x == 0) {
             ctl->h.pnum[p2 ^ 1] = P + 1;
@@ -357,38 +367,53 @@ __global__ __launch_bounds__(kBlock) void k_identify(KArgs a, int par) {
         shard_fill(ctl->tst[(p3 + 2) % 3], INF64);
         shard_fill(ctl->tdyn[(p3 + 1) % 3], INF64);
     }
+    __syncthreads();  // LDS counters initialised
     unsigned long long fmin = INF64, ftst = INF64;
     const uint32_t n = a.g.n;
-    for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
-        const uint32_t v = base + threadIdx.x;
-        bool set = false;
-        uint32_t deg = 0;
-        unsigned long long dv = INF64;
-        if (v < n) {
-            const uint8_t s = a.b.st[v];
+    const uint32_t nq = (n + 3) / 4;
+    for (uint32_t base = blockIdx.x * kBlock; base < nq; base += gridDim.x * kBlock) {
+        const uint32_t q = base + threadIdx.x;
+        const uint32_t s4 = q < nq ? load_st4(a.b.st, q, n) : 0u;
+        unsigned long long dv[4];
+        uint2 mm[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            dv[i] = INF64;
+            mm[i] = make_uint2(INF32, INF32);
+            if (((s4 >> (8 * i)) & ST_SET) == ST_F) {
+                dv[i] = a.b.dist[4 * q + i];
+                if (IN == IN_STATIC_M || OUT == 1) mm[i] = a.g.vmin[4 * q + i];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t v = 4 * q + i;
+            const uint8_t s = (uint8_t)(s4 >> (8 * i));
+            bool set = false;
+            uint32_t row = 0, deg = 0;
             if ((s & ST_SET) == ST_F) {
-                dv = a.b.dist[v];
                 bool ok = false;
-                if (IN == IN_DIJK) ok = dv == minD;
-                else if (IN == IN_STATIC_M) ok = dv <= sadd64(minD, w64(a.g.vmin[v].x));
+                if (IN == IN_DIJK) ok = dv[i] == minD;
+                else if (IN == IN_STATIC_M) ok = dv[i] <= sadd64(minD, w64(mm[i].x));
                 else if (IN == 3) ok = (s & ST_INOK) != 0;
-                if (OUT != 0) ok = ok || dv <= T;
+                if (OUT != 0) ok = ok || dv[i] <= T;
                 set = ok;
                 if (set) {
-                    deg = a.g.rp[v + 1] - a.g.rp[v];
+                    row = a.g.rp[v];
+                    deg = a.g.rp[v + 1] - row;
                     a.b.st[v] = ST_S;
                     if (a.b.phase_of) a.b.phase_of[v] = P + 1;
                 } else {
-                    fmin = umin64(fmin, dv);
-                    ftst = umin64(ftst, sadd64(dv, w64(a.g.vmin[v].y)));
+                    fmin = umin64(fmin, dv[i]);
+                    if (OUT == 1) ftst = umin64(ftst, sadd64(dv[i], w64(mm[i].y)));
                 }
             }
+            append_settled<CH>(a, ctl, p2, L, set, row, deg, dv[i]);
         }
-        append_settled<CH>(a, ctl, p2, L, set, v, deg, dv);
     }
     append_flush<CH>(a, ctl, p2, L);
     fmin = block_min64<kWaves>(fmin, sh);
-    ftst = block_min64<kWaves>(ftst, sh);
+    if (OUT == 1) ftst = block_min64<kWaves>(ftst, sh);
     if (threadIdx.x == 0) {
         if (fmin != INF64) atomicMin(slot_of(ctl->minD[(p3 + 1) % 3], my_shard()), fmin);
         if (ftst != INF64) atomicMin(slot_of(ctl->tst[(p3 + 1) % 3], my_shard()), ftst);
@@ -406,27 +431,18 @@ __global__ __launch_bounds__(kBlock) void k_identify_delta(KArgs a, int par) {
     Ctl *ctl = a.b.ctl;
     const int p2 = par & 1;
     __shared__ unsigned long long sh[kWaves];
-    __shared__ unsigned long long s_reached, s_improved;
     __shared__ AppendLds L;
     if (threadIdx.x == 0) { L.cnt = 0; L.filled = 0; L.zero = 0; }
     const unsigned int P = ctl->h.pnum[p2];
     const unsigned int b_now = ctl->h.buckets;
-    if (threadIdx.x < 64) {
-        const unsigned long long r = shard_sum_w0(ctl->reached);
-        const unsigned long long im = shard_sum_w0(ctl->win_improved[p2 ^ 1]);
-        if (threadIdx.x == 0) { s_reached = r; s_improved = im; }
-    }
-    __shared__ unsigned long long s_next;
-    if (threadIdx.x < 64) {
-        const unsigned long long nm = shard_min_w0(ctl->nextmin[b_now & 1]);
-        if (threadIdx.x == 0) s_next = nm;
-    }
-    __syncthreads();
-    const unsigned long long reached = s_reached, settled = ctl->h.settled;
+    const unsigned long long reached = shard_sum_w0(ctl->reached);
+    const unsigned long long improved = shard_sum_w0(ctl->win_improved[p2 ^ 1]);
+    const unsigned long long next = shard_min_w0(ctl->nextmin[b_now & 1]);
+    const unsigned long long settled = ctl->h.settled;
     int kind = 0;
     if (P > 0) {
         const unsigned int prev = ctl->h.rmode[p2 ^ 1];
-        kind = prev == 2 ? 0 : (s_improved > 0 ? 1 : 2);
+        kind = prev == 2 ? 0 : (improved > 0 ? 1 : 2);
     }
     if (kind == 0 && reached == settled) {
         if (blockIdx.x == 0) {
@@ -444,7 +460,7 @@ __global__ __launch_bounds__(kBlock) void k_identify_delta(KArgs a, int par) {
     unsigned long long lo, hi, delta;
     if (kind == 0) {
         delta = a.b.deltas[b < ctl->h.n_deltas ? b : ctl->h.n_deltas - 1];
-        lo = (s_next / delta) * delta;
+        lo = (next / delta) * delta;
         hi = sadd64(lo, delta);
     } else {
         lo = ctl->h.win_lo;
@@ -479,40 +495,46 @@ __global__ __launch_bounds__(kBlock) void k_identify_delta(KArgs a, int par) {
         shard_fill(ctl->szero[p2 ^ 1], 0);
         if (kind == 0) shard_fill(ctl->nextmin[(b + 1) & 1], INF64);
     }
+    __syncthreads();  // LDS counters initialised
     unsigned long long fmin = INF64;
     const uint32_t n = a.g.n;
-    for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
-        const uint32_t v = base + threadIdx.x;
-        bool set = false;
-        uint32_t deg = 0;
-        unsigned long long dv = INF64;
-        if (v < n) {
-            const uint8_t s = a.b.st[v] & ST_SET;
-            if (kind == 0) {
-                if (s == ST_F) {
-                    dv = a.b.dist[v];
-                    set = dv < hi;
-                }
-            } else if (kind == 1) {
-                if ((s == ST_F || s == ST_R) && a.b.stamp[v] == P) {
-                    dv = a.b.dist[v];
-                    set = true;
-                }
-            } else {
-                if (s == ST_R) {
-                    dv = a.b.dist[v];
-                    set = true;
-                } else if (s == ST_F) {
-                    fmin = umin64(fmin, a.b.dist[v]);  // exact: nothing leaves F until the next bucket
-                }
+    const uint32_t nq = (n + 3) / 4;
+    for (uint32_t base = blockIdx.x * kBlock; base < nq; base += gridDim.x * kBlock) {
+        const uint32_t q = base + threadIdx.x;
+        const uint32_t s4 = q < nq ? load_st4(a.b.st, q, n) : 0u;
+        unsigned long long dv[4];
+        uint32_t stp[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint8_t s = (s4 >> (8 * i)) & ST_SET;
+            dv[i] = INF64;
+            stp[i] = 0;
+            const bool need = kind == 0 ? s == ST_F : kind == 1 ? (s == ST_F || s == ST_R) : (s == ST_F || s == ST_R);
+            if (need) {
+                dv[i] = a.b.dist[4 * q + i];
+                if (kind == 1) stp[i] = a.b.stamp[4 * q + i];
             }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t v = 4 * q + i;
+            const uint8_t s = (s4 >> (8 * i)) & ST_SET;
+            bool set = false;
+            if (kind == 0) set = s == ST_F && dv[i] < hi;
+            else if (kind == 1) set = (s == ST_F || s == ST_R) && stp[i] == P;
+            else {
+                set = s == ST_R;
+                if (s == ST_F) fmin = umin64(fmin, dv[i]);  // exact: nothing leaves F until the next bucket
+            }
+            uint32_t row = 0, deg = 0;
             if (set) {
-                deg = a.g.rp[v + 1] - a.g.rp[v];
+                row = a.g.rp[v];
+                deg = a.g.rp[v + 1] - row;
                 a.b.st[v] = kind == 2 ? ST_S : ST_R;
                 if (kind == 2 && a.b.phase_of) a.b.phase_of[v] = P + 1;
             }
+            append_settled<CH>(a, ctl, p2, L, set, row, deg, dv[i]);
         }
-        append_settled<CH>(a, ctl, p2, L, set, v, deg, dv);
     }
     append_flush<CH>(a, ctl, p2, L);
     if (kind == 2) {
@@ -592,9 +614,8 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
         for (uint32_t t = threadIdx.x; t < cnt; t += kBlock) {
             const uint64_t j = gbase + j0 + t;
             const uint32_t off = a.b.soff[j];
-            const uint32_t u = a.b.sid[j];
             s_pos[t] = off > e0 ? off - e0 : 0u;
-            s_start[t] = a.g.rp[u] + (off > e0 ? 0u : e0 - off);
+            s_start[t] = a.b.srow[j] + (off > e0 ? 0u : e0 - off);
             s_du[t] = a.b.sdu[j];
         }
         __syncthreads();
@@ -698,7 +719,7 @@ void graph_default_cfg(sssp_graph *g) {
 
 void solve_bufs_free(sssp_graph *g) {
     SolveBufs &b = g->b;
-    sssp_free(b.ctl); sssp_free(b.st); sssp_free(b.sid); sssp_free(b.soff); sssp_free(b.sdu);
+    sssp_free(b.ctl); sssp_free(b.st); sssp_free(b.srow); sssp_free(b.soff); sssp_free(b.sdu);
     sssp_free(b.chunk_start); sssp_free(b.in_cur); sssp_free(b.out_cur); sssp_free(b.stamp); sssp_free(b.deltas);
     if (g->h_ctl) sssp_host_free(g->h_ctl);
     for (uint32_t i = 0; i < g->pev_cap; ++i) (void)hipEventDestroy(g->pev[i]);
@@ -721,13 +742,15 @@ void solve_bufs_free(sssp_graph *g) {
     g->delta_cap = 0;  // b.deltas was released with the rest
 }
 
-// Vertices a shard can settle in one phase: block b scans vertices
-// b*kBlock + i + k*G*kBlock, shard = b % kShards, so a shard owns at most
-// ceil(G / kShards) blocks of at most kBlock * ceil(n / (G * kBlock)) vertices.
+// Vertices a shard can settle in one phase: block b scans the vertex quads
+// q = b*kBlock + i + k*G*kBlock (vertices 4q..4q+3), shard = b % kShards, so
+// a shard owns at most ceil(G / kShards) blocks of at most
+// 4 * kBlock * ceil(ceil(n / 4) / (G * kBlock)) vertices each.
 static uint32_t shard_capacity(uint32_t n, int G) {
-    const uint64_t iters = ((uint64_t)n + (uint64_t)G * kBlock - 1) / ((uint64_t)G * kBlock);
+    const uint64_t nq = ((uint64_t)n + 3) / 4;
+    const uint64_t iters = (nq + (uint64_t)G * kBlock - 1) / ((uint64_t)G * kBlock);
     const uint64_t blocks = ((uint64_t)G + kShards - 1) / kShards;
-    return (uint32_t)(blocks * kBlock * iters);
+    return (uint32_t)(blocks * 4 * kBlock * iters);
 }
 
 int solve_bufs_ensure(sssp_graph *g, bool cursors, bool stamps) {
@@ -743,7 +766,7 @@ int solve_bufs_ensure(sssp_graph *g, bool cursors, bool stamps) {
         const uint64_t sent = (uint64_t)kShards * b.shard_cap;
         HIP_OK(hipMalloc(&b.ctl, sizeof(Ctl)));
         HIP_OK(hipMalloc(&b.st, n));
-        HIP_OK(hipMalloc(&b.sid, sent * 4));
+        HIP_OK(hipMalloc(&b.srow, sent * 4));
         HIP_OK(hipMalloc(&b.soff, sent * 4));
         HIP_OK(hipMalloc(&b.sdu, sent * 8));
         HIP_OK(hipMalloc(&b.chunk_start, (uint64_t)kShards * b.chunk_cap * 4));

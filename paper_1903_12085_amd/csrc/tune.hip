@@ -1,0 +1,114 @@
+// Autotuners: time candidate launch shapes with HIP events on the graph's
+// stream and keep the fastest. Results never depend on the shape, only time.
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+#include "graph.h"
+
+static int device_cus() {
+    int dev = 0, cus = 256;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+    return cus > 0 ? cus : 256;
+}
+
+// Median of `reps` timed calls of fn (after one untimed call).
+template <class F>
+static int time_call(hipStream_t s, int reps, F fn, float *ms_out) {
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    int rc = fn();
+    std::vector<float> t;
+    for (int r = 0; rc == SSSP_OK && r < reps; ++r) {
+        float ms = 0;
+        if (hipEventRecord(e0, s) != hipSuccess) { rc = sssp_set_error(SSSP_ERR_DEVICE, "event record"); break; }
+        rc = fn();
+        if (rc) break;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = sssp_set_error(SSSP_ERR_DEVICE, "event timing");
+            break;
+        }
+        t.push_back(ms);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == SSSP_OK) {
+        std::sort(t.begin(), t.end());
+        *ms_out = t[t.size() / 2];
+    }
+    return rc;
+}
+
+extern "C" int sssp_autotune(sssp_graph *g, uint32_t source, uint32_t criterion, sssp_launch_cfg *best,
+                             float *best_ms) {
+    if (!g) return sssp_set_error(SSSP_ERR_INVALID, "graph is NULL");
+    if (source >= g->n) return sssp_set_error(SSSP_ERR_INVALID, "source %u >= n", source);
+    uint64_t *dist = nullptr;
+    HIP_OK(hipMalloc(&dist, (uint64_t)g->n * sizeof(uint64_t)));
+    const int cus = device_cus();
+    const uint64_t quads = ((uint64_t)g->n + 3) / 4;
+    std::vector<sssp_launch_cfg> cands;
+    for (int sb_mul : {1, 2, 4, 8})
+        for (int rb_mul : {2, 4, 8})
+            for (uint32_t ch : {256u, 512u})
+                for (uint32_t ug : {0u, 1u}) {
+                    uint64_t sb = (uint64_t)cus * sb_mul;
+                    const uint64_t need = (quads + kBlock - 1) / kBlock;
+                    if (sb > need) sb = need ? need : 1;
+                    uint64_t rb = (uint64_t)cus * rb_mul;
+                    const uint64_t rneed = (g->m + ch - 1) / ch;
+                    if (rb > rneed) rb = rneed ? rneed : 1;
+                    sssp_launch_cfg c = {(uint32_t)sb, (uint32_t)rb, ch, ug};
+                    bool dup = false;
+                    for (auto &o : cands) dup |= o.scan_blocks == c.scan_blocks && o.relax_blocks == c.relax_blocks &&
+                                                o.chunk == c.chunk && o.use_graph == c.use_graph;
+                    if (!dup) cands.push_back(c);
+                }
+    sssp_launch_cfg keep;
+    sssp_get_launch(g, &keep);
+    sssp_launch_cfg win = keep;
+    float win_ms = 1e30f;
+    int rc = SSSP_OK;
+    for (const auto &c : cands) {
+        rc = sssp_set_launch(g, &c);
+        if (rc) break;
+        float ms = 0;
+        rc = time_call(g->stream, 3, [&] { return sssp_solve(g, source, criterion, dist, nullptr); }, &ms);
+        if (rc) break;
+        if (ms < win_ms) { win_ms = ms; win = c; }
+    }
+    sssp_free(dist);
+    if (rc) { sssp_set_launch(g, &keep); return rc; }
+    sssp_set_launch(g, &win);
+    if (best) *best = win;
+    if (best_ms) *best_ms = win_ms;
+    return SSSP_OK;
+}
+
+extern "C" int sssp_autotune_batch(sssp_graph *const *graphs, const uint32_t *sources, uint32_t nq,
+                                   uint32_t criterion, uint64_t *const *dist_outs, sssp_batch_cfg *best,
+                                   float *best_ms) {
+    if (nq == 0 || !graphs || !graphs[0]) return sssp_set_error(SSSP_ERR_INVALID, "empty batch");
+    const int cus = device_cus();
+    sssp_batch_cfg win = {0, 0, 0};
+    float win_ms = 1e30f;
+    for (uint32_t bs : {256u, 512u, 1024u})
+        for (uint32_t split : {16u, 64u, 256u})
+            for (uint32_t per_cu : {1u, 2u, 4u}) {
+                if (bs == 1024 && per_cu > 2) continue;
+                sssp_batch_cfg c = {bs, split, (uint32_t)cus * per_cu};
+                float ms = 0;
+                int rc = time_call(graphs[0]->stream, 2, [&] {
+                    return sssp_solve_batch_ex(graphs, sources, nq, criterion, dist_outs, nullptr, &c);
+                }, &ms);
+                if (rc) return rc;
+                if (ms < win_ms) { win_ms = ms; win = c; }
+            }
+    sssp_batch_set_config(&win);
+    if (best) *best = win;
+    if (best_ms) *best_ms = win_ms;
+    return SSSP_OK;
+}

@@ -226,3 +226,47 @@ def test_scratch_rebuilt_after_launch_change(B):
         r = B.solve(dg, 0, O.FULL_OR)
         assert np.array_equal(r.dist_u64(), op.dist) and r.phases == op.phases
         dg.set_launch(scan_blocks=sb)
+
+
+def small_batch():
+    graphs = [G.er(1 << 10, 6, 1, 1 << 16, 31), G.grid(40, 30, 1, 1 << 16, 32), G.rmat(10, 16, 1, 1 << 16, 33),
+              G.er(3000, 20, 1, 100, 34), G.random_small(200, 900, 50, 35), G.from_edges(1, [])]
+    queries = []
+    for i, g in enumerate(graphs):
+        for s in range(5 if g.n > 1 else 1):
+            queries.append((i, int(G.u64_stream(i, s, 1)[0] % np.uint64(g.n))))
+    return graphs, queries
+
+
+@pytest.mark.parametrize("crit", [O.STATIC_OR, O.IN_STATIC, O.OUT_STATIC, O.DIJK])
+@pytest.mark.parametrize("cfg", [None, dict(block=256, split=4, blocks=3), dict(block=1024, split=1000, blocks=64)])
+def test_batched_matches_oracle(B, crit, cfg):
+    graphs, queries = small_batch()
+    dgs = [B.DeviceGraph.from_graph(g) for g in graphs]
+    dists, phases = B.solve_batch([dgs[i] for i, _ in queries], [s for _, s in queries], crit, cfg=cfg)
+    for (i, s), d, ph in zip(queries, dists, phases):
+        ref = O.phased(graphs[i], s, crit)
+        assert np.array_equal(B.to_u64(d), ref.dist), (graphs[i].name, s)
+        assert int(ph) == ref.phases, (graphs[i].name, s, int(ph), ref.phases)
+
+
+def test_batched_rejects_dynamic_criteria(B):
+    graphs, queries = small_batch()
+    dg = B.DeviceGraph.from_graph(graphs[0])
+    with pytest.raises(B.SsspError):
+        B.solve_batch([dg], [0], O.FULL_OR)
+
+
+def test_autotuners_keep_results(B):
+    g = G.rmat(12, 16, 1, 1 << 16, 36)
+    dg = B.DeviceGraph.from_graph(g)
+    cfg, ms = B.autotune(dg, 0, O.STATIC_OR)
+    assert ms > 0 and cfg["chunk"] in (256, 512)
+    check_phased(B, g, 0, O.STATIC_OR, "after autotune")
+    graphs, queries = small_batch()
+    dgs = [B.DeviceGraph.from_graph(x) for x in graphs]
+    bcfg, bms = B.autotune_batch([dgs[i] for i, _ in queries], [s for _, s in queries], O.STATIC_OR)
+    assert bms > 0 and bcfg["block"] in (256, 512, 1024)
+    dists, phases = B.solve_batch([dgs[i] for i, _ in queries], [s for _, s in queries], O.STATIC_OR)
+    for (i, s), d in zip(queries, dists):
+        assert np.array_equal(B.to_u64(d), O.dijkstra(graphs[i], s)[0])
