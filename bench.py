@@ -41,6 +41,51 @@ def alg_bytes(kernel, st, phases):
     return (16.0 * st["n_reach"] + 16.0 * st["relax_edges"] + 8.0 * st["improving"]) / phases
 
 
+def bench_batched(B, torch, G):
+    """512 queries over 64 uneven graphs: one persistent batched launch vs the same queries one by one."""
+    t = time.time()
+    graphs, queries = G.batch_workload(seed=7)
+    dgs = [B.DeviceGraph.from_graph(g) for g in graphs]
+    torch.cuda.synchronize()
+    log("batch workload: %d graphs, %d queries, %.1fs" % (len(graphs), len(queries), time.time() - t))
+    qg = [dgs[i] for i, _ in queries]
+    qs = [s for _, s in queries]
+    dists = [B.new_dist(graphs[i].n) for i, _ in queries]
+    tuned, tuned_ms = B.autotune_batch(qg, qs, B.STATIC_OR, dists)
+    log("batch autotune", tuned, "%.2f ms" % tuned_ms)
+    reps = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        tt = time.perf_counter()
+        _, bph = B.solve_batch(qg, qs, B.STATIC_OR, dists)
+        torch.cuda.synchronize()
+        reps.append(time.perf_counter() - tt)
+    tb = sorted(reps)[1]
+    m_reach = 0
+    for (i, _), d in zip(queries, dists):
+        reach = B.to_u64(d) != np.uint64(0xFFFFFFFFFFFFFFFF)
+        m_reach += int(np.diff(graphs[i].row_ptr)[reach].sum())
+    # the same queries through the plain solver, one call each
+    pd = [B.new_dist(graphs[i].n) for i, _ in queries]
+    for dg in dgs:  # warm each graph's scratch once
+        B.solve(dg, 0, B.STATIC_OR)
+    torch.cuda.synchronize()
+    tt = time.perf_counter()
+    pph = [B.solve(dg, s, B.STATIC_OR, d).phases for dg, s, d in zip(qg, qs, pd)]
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - tt
+    same = all(np.array_equal(B.to_u64(a), B.to_u64(b)) for a, b in zip(dists, pd)) and list(bph) == pph
+    res = {"workload": "64 graphs (random 2^12..2^18 deg 4..32, grids 64^2..512^2, R-MAT 12..18 ef 16), "
+                       "8 sources each, weights [1, 2^16], IN_STATIC|OUT_STATIC",
+           "queries": len(queries), "m_reach_total": m_reach, "batched_ms": round(tb * 1e3, 3),
+           "batched_gteps": round(m_reach / tb / 1e9, 4), "plain_ms": round(tp * 1e3, 3),
+           "plain_gteps": round(m_reach / tp / 1e9, 4), "speedup_vs_plain": round(tp / tb, 2),
+           "phases_total": int(sum(pph)), "max_phases": int(max(pph)), "autotuned": tuned,
+           "batched_equals_plain": bool(same)}
+    log("batched", res)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -49,6 +94,7 @@ def main():
     ap.add_argument("--log2n", type=int, default=22)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the solver runs on a single device "
@@ -72,6 +118,8 @@ def main():
     log("device graph ready in %.1fs" % (time.time() - t))
     crit = B.STATIC_OR
     dist = B.new_dist(g.n)
+    tuned, tuned_ms = B.autotune(dg, src, crit)  # one-time launch-shape search (untimed)
+    log("autotuned launch shape", tuned, "%.3f ms" % tuned_ms)
 
     for _ in range(args.warmup):
         B.solve(dg, src, crit, dist)
@@ -117,7 +165,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": "er_n%d_outdeg16_w1-2^20_src0" % g.n, "n": g.n, "m": g.m, "seed": seed,
-                   "source": src, "criterion": "IN_STATIC|OUT_STATIC", "form": "plain"},
+                   "source": src, "criterion": "IN_STATIC|OUT_STATIC", "form": "plain", "launch": tuned},
         "phases": phases, "sum_f": st["sum_f"], "m_reach": st["m_reach"], "n_reach": st["n_reach"],
         "us_per_phase": round(ms * 1e3 / phases, 2), "precompute_ms": round(st["precompute_ns"] / 1e6, 3),
         "gteps_incl_precompute": round(st["m_reach"] / ((ms + st["precompute_ns"] / 1e6) * 1e-3) / 1e9, 4),
@@ -147,6 +195,9 @@ def main():
                                        "gteps": round(st["m_reach"] / dt / 1e9, 4)}
             log("delta", k, forms["delta_2^%d" % k])
         out["forms"] = forms
+
+    if not args.no_batch:
+        out["batched"] = bench_batched(B, torch, G)
 
     if not args.no_cpu:
         import oracle as O

@@ -4,15 +4,16 @@
 // and runs the generic phased algorithm of Section 3 for that query with
 // workgroup barriers only, so a batch needs no grid synchronisation and no
 // launch per phase:
-//   identify  block-stride scan of the query's vertices; a queued vertex the
-//             criterion certifies (phase-start minD / OUT-STATIC threshold)
-//             is marked "settled this phase"; the others fold next minima.
-//   relax     second scan: every vertex settled this phase is expanded; rows
-//             up to `split` edges by their own lane, longer rows are queued in
-//             LDS and expanded by the whole workgroup (degree split). 64-bit
-//             atomicMin on the query's distance array; the atomic that
-//             replaces infinity queues the target. Improving candidates fold
-//             into next minD / threshold.
+//   identify  over the query's fringe list: a vertex the criterion certifies
+//             (phase-start minD / OUT-STATIC threshold) goes to the settled
+//             list, the others to the next fringe list and fold next minima
+//             (wavefront ballot + one LDS atomic per wavefront).
+//   relax     over the settled list: rows up to `split` edges by their own
+//             lane, longer rows are queued in LDS and expanded by the whole
+//             workgroup (degree split). 64-bit atomicMin on the query's
+//             distance array; the atomic that replaces infinity appends the
+//             target to the next fringe. Improving candidates fold into next
+//             minD / threshold.
 // Distances and states written in one phase are read in the next with
 // L1-bypassing atomic loads (device-scope atomics update L2, not the CU's L1).
 //
@@ -31,6 +32,7 @@ struct BatchQuery {
     const uint2 *vmin;
     unsigned long long *dist;
     uint8_t *st;
+    uint32_t *fl;      // 3 * n entries: fringe list A, fringe list B, settled list
     uint32_t n;
     uint32_t src;
 };
@@ -43,10 +45,16 @@ struct BatchCtl {
 constexpr uint8_t ST_NEW = 3;  // settled in the current phase, out-edges not yet relaxed
 constexpr int kHubCap = 256;
 
+// Values written by other wavefronts of the workgroup in an earlier phase are
+// read with L1-bypassing loads (device-scope atomics update L2, not the CU's L1,
+// and list buffers are reused every other phase).
 __device__ __forceinline__ unsigned long long ld_dist(const unsigned long long *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ uint8_t ld_st(const uint8_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_u32(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -60,31 +68,41 @@ __device__ __forceinline__ unsigned long long bmin(unsigned long long x, unsigne
     __syncthreads();
     return r;
 }
-template <int BS>
-__device__ __forceinline__ unsigned long long bsum(unsigned long long x, unsigned long long *sh) {
-    x = wave_sum64(x);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = x;
-    __syncthreads();
-    unsigned long long r = 0;
-    for (int i = 0; i < BS / 64; ++i) r += sh[i];
-    __syncthreads();
-    return r;
+
+// Wavefront-aggregated append of v to a list whose length is the LDS counter
+// *cnt: one LDS atomic by the lowest taking lane, which is always active.
+__device__ __forceinline__ void wave_append(bool take, uint32_t v, uint32_t *list, uint32_t *cnt) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long mask = __ballot(take);
+    if (!mask) return;
+    const int leader = __ffsll((long long)mask) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(cnt, (uint32_t)__popcll(mask));
+    base = __shfl(base, leader, 64);
+    if (take) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = v;
 }
 
-template <int BS, int IN, bool OUT>
-__device__ __forceinline__ void relax_edge(const BatchQuery &q, unsigned long long du, uint2 ed,
+// Returns true when this relaxation discovered ed.x (infinity replaced).
+template <int BS, bool OUT>
+__device__ __forceinline__ bool relax_edge(const BatchQuery &q, unsigned long long du, uint2 ed,
                                            unsigned long long &cmin, unsigned long long &ctst) {
+    bool disc = false;
     const uint8_t sv = ld_st(&q.st[ed.x]);
-    if (sv == ST_S || sv == ST_NEW) return;
-    const unsigned long long cand = du + ed.y;
-    if (cand < ld_dist(&q.dist[ed.x])) {
-        const unsigned long long old = atomicMin(&q.dist[ed.x], cand);
-        if (cand < old) {
-            cmin = umin64(cmin, cand);
-            if (OUT) ctst = umin64(ctst, sadd64(cand, w64(q.vmin[ed.x].y)));
-            if (old == INF64) q.st[ed.x] = ST_F;
+    if (sv != ST_S && sv != ST_NEW) {
+        const unsigned long long cand = du + ed.y;
+        if (cand < ld_dist(&q.dist[ed.x])) {
+            const unsigned long long old = atomicMin(&q.dist[ed.x], cand);
+            if (cand < old) {
+                cmin = umin64(cmin, cand);
+                if (OUT) ctst = umin64(ctst, sadd64(cand, w64(q.vmin[ed.x].y)));
+                if (old == INF64) {
+                    q.st[ed.x] = ST_F;
+                    disc = true;
+                }
+            }
         }
     }
+    return disc;
 }
 
 // IN: IN_NONE, IN_DIJK or IN_STATIC_M; OUT: OUT-STATIC on/off.
@@ -96,7 +114,7 @@ __global__ __launch_bounds__(BS) void k_batch(const BatchQuery *__restrict__ que
     __shared__ uint32_t s_q;
     __shared__ uint32_t hub_v[kHubCap];
     __shared__ unsigned long long hub_du[kHubCap];
-    __shared__ uint32_t hub_n;
+    __shared__ uint32_t hub_n, s_nset, s_nnext;
     for (;;) {
         if (threadIdx.x == 0) s_q = atomicAdd(&ctl->next, 1u);
         __syncthreads();
@@ -109,62 +127,107 @@ __global__ __launch_bounds__(BS) void k_batch(const BatchQuery *__restrict__ que
             q.dist[v] = v == q.src ? 0ull : INF64;
             q.st[v] = v == q.src ? ST_F : ST_U;
         }
+        if (threadIdx.x == 0) q.fl[0] = q.src;
+        uint32_t nF = 1, cur = 0, phases = 0;
         unsigned long long minD = 0, T = w64(q.vmin[q.src].y);
-        uint32_t phases = 0;
         __syncthreads();
-        for (;;) {
-            // identify
-            unsigned long long fmin = INF64, ftst = INF64, nset = 0;
-            for (uint32_t v = threadIdx.x; v < n; v += BS) {
-                if (ld_st(&q.st[v]) != ST_F) continue;
-                const unsigned long long dv = ld_dist(&q.dist[v]);
-                const uint2 mm = q.vmin[v];
-                bool ok = false;
-                if (IN == IN_DIJK) ok = dv == minD;
-                else if (IN == IN_STATIC_M) ok = dv <= sadd64(minD, w64(mm.x));
-                if (OUT) ok = ok || dv <= T;
-                if (ok) {
-                    q.st[v] = ST_NEW;
-                    ++nset;
-                } else {
-                    fmin = umin64(fmin, dv);
-                    if (OUT) ftst = umin64(ftst, sadd64(dv, w64(mm.y)));
+        while (nF > 0) {
+            uint32_t *F = q.fl + (uint64_t)cur * n;
+            uint32_t *Fn = q.fl + (uint64_t)(cur ^ 1) * n;
+            uint32_t *Sp = q.fl + 2ull * n;
+            if (threadIdx.x == 0) { s_nset = 0; s_nnext = 0; hub_n = 0; }
+            __syncthreads();
+            // identify over the fringe list
+            unsigned long long fmin = INF64, ftst = INF64;
+            for (uint32_t base = 0; base < nF; base += BS) {
+                const uint32_t i = base + threadIdx.x;
+                bool set = false, keep = false;
+                uint32_t v = 0;
+                if (i < nF) {
+                    v = ld_u32(&F[i]);
+                    const unsigned long long dv = ld_dist(&q.dist[v]);
+                    const uint2 mm = q.vmin[v];
+                    bool ok = false;
+                    if (IN == IN_DIJK) ok = dv == minD;
+                    else if (IN == IN_STATIC_M) ok = dv <= sadd64(minD, w64(mm.x));
+                    if (OUT) ok = ok || dv <= T;
+                    set = ok;
+                    keep = !ok;
+                    if (keep) {
+                        fmin = umin64(fmin, dv);
+                        if (OUT) ftst = umin64(ftst, sadd64(dv, w64(mm.y)));
+                    } else {
+                        q.st[v] = ST_NEW;
+                    }
                 }
+                wave_append(set, v, Sp, &s_nset);
+                wave_append(keep, v, Fn, &s_nnext);
             }
-            if (threadIdx.x == 0) hub_n = 0;
-            nset = bsum<BS>(nset, sh);
-            if (nset == 0) break;  // F is empty (a non-empty F always certifies its minimum)
+            __syncthreads();
+            const uint32_t nS = s_nset;
             ++phases;
-            if (phases > n + 1) {
+            if (nS == 0 || phases > n + 1) {  // a non-empty fringe always certifies its minimum
                 if (threadIdx.x == 0) atomicOr(&ctl->error, 1u);
                 break;
             }
             // relax: short rows by their own lane, long rows by the whole workgroup
             unsigned long long cmin = INF64, ctst = INF64;
-            for (uint32_t v = threadIdx.x; v < n; v += BS) {
-                if (ld_st(&q.st[v]) != ST_NEW) continue;
-                q.st[v] = ST_S;
-                const uint32_t b = q.rp[v], e = q.rp[v + 1];
-                const unsigned long long du = ld_dist(&q.dist[v]);
-                if (e - b > split) {
-                    const uint32_t slot = atomicAdd(&hub_n, 1u);
-                    if (slot < kHubCap) {
-                        hub_v[slot] = v;
-                        hub_du[slot] = du;
-                        continue;
+            for (uint32_t base = 0; base < nS; base += BS) {
+                const uint32_t i = base + threadIdx.x;
+                uint32_t b = 0, e = 0;
+                unsigned long long du = 0;
+                if (i < nS) {
+                    const uint32_t v = ld_u32(&Sp[i]);
+                    q.st[v] = ST_S;
+                    b = q.rp[v];
+                    e = q.rp[v + 1];
+                    du = ld_dist(&q.dist[v]);
+                    if (e - b > split) {
+                        const uint32_t slot = atomicAdd(&hub_n, 1u);
+                        if (slot < kHubCap) {
+                            hub_v[slot] = v;
+                            hub_du[slot] = du;
+                            e = b;  // expanded below by the whole workgroup
+                        }
                     }
                 }
-                for (uint32_t k = b; k < e; ++k) relax_edge<BS, IN, OUT>(q, du, q.edges[k], cmin, ctst);
+                // lanes walk their rows in lock step so discoveries can be appended per wavefront
+                uint32_t len = e - b;
+                uint32_t mx = len;
+                for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor(mx, o, 64));
+                for (uint32_t k = 0; k < mx; ++k) {
+                    bool disc = false;
+                    uint32_t tgt = 0;
+                    if (k < len) {
+                        const uint2 ed = q.edges[b + k];
+                        tgt = ed.x;
+                        disc = relax_edge<BS, OUT>(q, du, ed, cmin, ctst);
+                    }
+                    wave_append(disc, tgt, Fn, &s_nnext);  // every lane of the wavefront takes part
+                }
             }
             __syncthreads();
             const uint32_t nh = min(hub_n, (uint32_t)kHubCap);
             for (uint32_t h = 0; h < nh; ++h) {
                 const uint32_t v = hub_v[h];
                 const uint32_t b = q.rp[v], e = q.rp[v + 1];
-                for (uint32_t k = b + threadIdx.x; k < e; k += BS) relax_edge<BS, IN, OUT>(q, hub_du[h], q.edges[k], cmin, ctst);
+                for (uint32_t kb = b; kb < e; kb += BS) {
+                    const uint32_t k = kb + threadIdx.x;
+                    bool disc = false;
+                    uint32_t tgt = 0;
+                    if (k < e) {
+                        const uint2 ed = q.edges[k];
+                        tgt = ed.x;
+                        disc = relax_edge<BS, OUT>(q, hub_du[h], ed, cmin, ctst);
+                    }
+                    wave_append(disc, tgt, Fn, &s_nnext);
+                }
             }
             minD = bmin<BS>(umin64(fmin, cmin), sh);
             if (OUT) T = bmin<BS>(umin64(ftst, ctst), sh);
+            nF = s_nnext;  // complete: bmin ends with a barrier
+            cur ^= 1;
+            __syncthreads();  // every wavefront has read s_nnext before thread 0 resets it
         }
         if (threadIdx.x == 0) phases_out[order[qi]] = phases;
         __syncthreads();
@@ -224,8 +287,8 @@ extern "C" int sssp_solve_batch_ex(sssp_graph *const *graphs, const uint32_t *so
     if (in > IN_STATIC_M || out > OUT_STATIC_M)
         return sssp_set_error(SSSP_ERR_UNSUPPORTED, "the batched solver evaluates DIJK, IN-STATIC and OUT-STATIC");
     std::vector<BatchQuery> hq(nq);
-    std::vector<uint64_t> st_off(nq);
-    uint64_t st_total = 0;
+    std::vector<uint64_t> st_off(nq), fl_off(nq);
+    uint64_t st_total = 0, fl_total = 0;
     for (uint32_t i = 0; i < nq; ++i) {
         const sssp_graph *g = graphs[i];
         if (!g || !dist_outs[i]) return sssp_set_error(SSSP_ERR_INVALID, "query %u: NULL graph or output", i);
@@ -238,6 +301,8 @@ extern "C" int sssp_solve_batch_ex(sssp_graph *const *graphs, const uint32_t *so
         hq[i].src = sources[i];
         st_off[i] = st_total;
         st_total += (g->n + 255) & ~255ull;
+        fl_off[i] = fl_total;
+        fl_total += 3ull * g->n;
     }
     // longest-processing-time order: most edges first
     std::vector<uint32_t> order(nq);
@@ -248,6 +313,7 @@ extern "C" int sssp_solve_batch_ex(sssp_graph *const *graphs, const uint32_t *so
     hipStream_t s = graphs[0]->stream;
     HIP_OK(hipSetDevice(graphs[0]->device));
     uint8_t *st = nullptr;
+    uint32_t *fl = nullptr;
     BatchQuery *dq = nullptr;
     uint32_t *dorder = nullptr, *dph = nullptr;
     BatchCtl *dctl = nullptr;
@@ -255,7 +321,11 @@ extern "C" int sssp_solve_batch_ex(sssp_graph *const *graphs, const uint32_t *so
 #define TRY(call) do { hipError_t _e = (call); if (_e != hipSuccess) { \
         rc = sssp_set_error(_e == hipErrorOutOfMemory ? SSSP_ERR_OOM : SSSP_ERR_DEVICE, "%s: %s", #call, hipGetErrorString(_e)); goto done; } } while (0)
     TRY(hipMalloc(&st, st_total));
-    for (uint32_t i = 0; i < nq; ++i) hq[i].st = st + st_off[i];
+    TRY(hipMalloc(&fl, fl_total * sizeof(uint32_t)));
+    for (uint32_t i = 0; i < nq; ++i) {
+        hq[i].st = st + st_off[i];
+        hq[i].fl = fl + fl_off[i];
+    }
     TRY(hipMalloc(&dq, nq * sizeof(BatchQuery)));
     TRY(hipMalloc(&dorder, nq * sizeof(uint32_t)));
     TRY(hipMalloc(&dph, nq * sizeof(uint32_t)));
@@ -282,6 +352,6 @@ extern "C" int sssp_solve_batch_ex(sssp_graph *const *graphs, const uint32_t *so
     }
 done:
 #undef TRY
-    sssp_free(st); sssp_free(dq); sssp_free(dorder); sssp_free(dph); sssp_free(dctl);
+    sssp_free(st); sssp_free(fl); sssp_free(dq); sssp_free(dorder); sssp_free(dph); sssp_free(dctl);
     return rc;
 }

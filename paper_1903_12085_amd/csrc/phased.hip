@@ -706,15 +706,17 @@ static int num_cus() {
 
 void graph_default_cfg(sssp_graph *g) {
     const int cus = num_cus();
-    uint64_t sb = ((uint64_t)g->n + kBlock * 4 - 1) / (kBlock * 4);
+    // scan: 4 vertices per lane, about 4 blocks per compute unit on large graphs
+    uint64_t sb = ((uint64_t)g->n + 4 * kBlock - 1) / (4 * kBlock);
     if (sb < 1) sb = 1;
-    if (sb > (uint64_t)cus * 8) sb = (uint64_t)cus * 8;
+    if (sb > (uint64_t)cus * 4) sb = (uint64_t)cus * 4;
     g->cfg.scan_blocks = (int)sb;
     g->cfg.chunk = 256;
     uint64_t rb = (g->m + g->cfg.chunk - 1) / g->cfg.chunk;
     if (rb < 1) rb = 1;
-    if (rb > (uint64_t)cus * 8) rb = (uint64_t)cus * 8;
+    if (rb > (uint64_t)cus * 4) rb = (uint64_t)cus * 4;
     g->cfg.relax_blocks = (int)rb;
+    g->cfg.use_graph = 0;
 }
 
 void solve_bufs_free(sssp_graph *g) {
