@@ -41,6 +41,20 @@ def alg_bytes(kernel, st, phases):
     return (16.0 * st["n_reach"] + 16.0 * st["relax_edges"] + 8.0 * st["improving"]) / phases
 
 
+def measured_traffic(kern, log2n):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE record, or None when the
+    kernel source changed since the counters were taken (or another kernel/size dominates)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_identify_er22.json")
+    if kern != "identify" or log2n != 22 or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in ("paper_1903_12085_amd/csrc/phased.hip", "paper_1903_12085_amd/csrc/common.h"):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
+
+
 def bench_batched(B, torch, G):
     """512 queries over 64 uneven graphs: one persistent batched launch vs the same queries one by one."""
     t = time.time()
@@ -95,6 +109,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="one solve with the default launch shape, for rocprofv3 (no tuning, no extra passes)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 1 GiB device-to-device copy kernel (known bytes) for counter calibration")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the solver runs on a single device "
@@ -108,6 +126,21 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     B.load()
+    if args.copy_calibration:
+        src_t = torch.empty(1 << 27, dtype=torch.int64, device="cuda").fill_(1)  # 1 GiB
+        dst_t = torch.empty_like(src_t)
+        torch.cuda.synchronize()
+        dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": 1 << 30}))
+        return
+    if args.profile_run:
+        g = G.config_er_large(seed=1, log2n=args.log2n)
+        dg = B.DeviceGraph.from_graph(g)
+        r = B.solve(dg, 0, B.STATIC_OR)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_run": True, "phases": r.phases, "launch": dg.launch()}))
+        return
     seed, src = 1, 0
     t = time.time()
     g = G.config_er_large(seed=seed, log2n=args.log2n)
@@ -154,7 +187,8 @@ def main():
     avg_us = kms * 1e3 / prof["phases"]
     achieved = per_launch / (avg_us * 1e-6) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_" + kern,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kern, args.log2n),
+                "kernel": "k_" + kern,
                 "alg_bytes_per_launch": round(per_launch), "avg_launch_us": round(avg_us, 2),
                 "launches": prof["phases"], "identify_ms": round(prof["identify_ms"], 3),
                 "relax_ms": round(prof["relax_ms"], 3)}
