@@ -39,7 +39,7 @@ FULL_OR = IN_FULL | OUT_FULL
 def build(force: bool = False) -> str:
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC", _SRC, "-o", tmp])
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-ffp-contract=off", "-shared", "-fPIC", _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -69,8 +69,11 @@ def _L():
             lib.orc_bellman_ford.argtypes = [u32, P, P, P, u32, P]
             lib.orc_static_minima.argtypes = [u32, P, P, P, P, P]
             lib.orc_phased.argtypes = [u32, P, P, P, u32, u32, P, u32, i, P, P,
-                                       ctypes.POINTER(_Stats), u32, P, P, P, P, P]
-            lib.orc_delta_step.argtypes = [u32, P, P, P, u32, P, u32, P, ctypes.POINTER(_DStats), u32, P]
+                                       ctypes.POINTER(_Stats), u32, P, P, P, P, P, P, P, P, P]
+            lib.orc_delta_step.argtypes = [u32, P, P, P, u32, P, u32, P, ctypes.POINTER(_DStats), u32, P, P]
+            lib.orc_features.argtypes = [P, ctypes.c_double, i, P]
+            lib.orc_features.restype = None
+            lib.orc_mlp_choice.argtypes = [P, P, i, P]
             _lib = lib
     return _lib
 
@@ -133,6 +136,9 @@ class PhasedResult:
     trace_mind: np.ndarray
     trace_counts: np.ndarray | None
     phase_of: np.ndarray
+    trace_crit: np.ndarray | None = None
+    trace_union: np.ndarray | None = None
+    trace_feat: np.ndarray | None = None
 
 
 class OracleError(RuntimeError):
@@ -145,9 +151,13 @@ _ERRS = {-1: "invalid argument", -2: "out of memory", -10: "unsound: certified v
 
 
 def phased(g, src: int, crit: int, crit_seq=None, check: bool = False, dist_ref=None,
-           trace_cap: int | None = None) -> PhasedResult:
-    """Generic phased algorithm of Section 3 with the given criterion bits."""
+           trace_cap: int | None = None, mlp_w=None) -> PhasedResult:
+    """Generic phased algorithm of Section 3 with the given criterion bits.
+
+    mlp_w: float32[5382] selector weights; the criterion of each phase is then the selector's
+    choice on that phase's features (crit is ignored)."""
     n, rp, col, w = _csr(g)
+    mw = None if mlp_w is None else np.ascontiguousarray(mlp_w, np.float32)
     cap = n if trace_cap is None else trace_cap
     dist = np.empty(n, np.uint64)
     tf = np.zeros(cap, np.uint32)
@@ -156,16 +166,22 @@ def phased(g, src: int, crit: int, crit_seq=None, check: bool = False, dist_ref=
     tc = np.zeros(8 * cap, np.uint32) if check else None
     seq = None if crit_seq is None else np.ascontiguousarray(crit_seq, np.uint32)
     po = np.zeros(n, np.uint32)
+    tcr = np.zeros(cap, np.uint32)
+    tun = np.zeros(3 * cap, np.uint32) if check else None
+    tft = np.zeros(12 * cap, np.float32) if mw is not None else None
     st = _Stats()
     rc = _L().orc_phased(n, _p(rp), _p(col), _p(w), src, crit, _p(seq), 0 if seq is None else len(seq),
                          int(check), _p(None if dist_ref is None else np.ascontiguousarray(dist_ref, np.uint64)),
-                         _p(dist), ctypes.byref(st), cap, _p(tf), _p(ts), _p(tm), _p(tc), _p(po))
+                         _p(dist), ctypes.byref(st), cap, _p(tf), _p(ts), _p(tm), _p(tc), _p(po), _p(mw), _p(tcr),
+                         _p(tun), _p(tft))
     if rc != 0:
         raise OracleError("orc_phased: %s (%d)" % (_ERRS.get(rc, "?"), rc))
     k = min(st.phases, cap)
     return PhasedResult(dist, int(st.phases), int(st.sum_f), int(st.n_reach), int(st.m_reach),
                         int(st.relax_edges), int(st.improving), tf[:k], ts[:k], tm[:k],
-                        None if tc is None else tc[:8 * k].reshape(k, 8), po)
+                        None if tc is None else tc[:8 * k].reshape(k, 8), po, tcr[:k],
+                        None if tun is None else tun[:3 * k].reshape(k, 3),
+                        None if tft is None else tft[:12 * k].reshape(k, 12))
 
 
 @dataclass
@@ -179,15 +195,16 @@ class DeltaResult:
     trace_delta: np.ndarray
 
 
-def delta_step(g, src: int, deltas, trace_cap: int = 0) -> DeltaResult:
-    """Delta-stepping; bucket b uses deltas[min(b, len-1)]."""
+def delta_step(g, src: int, deltas, trace_cap: int = 0, mlp_w=None) -> DeltaResult:
+    """Delta-stepping; bucket b uses deltas[min(b, len-1)], or the selector's choice when mlp_w is given."""
     n, rp, col, w = _csr(g)
-    ds = np.ascontiguousarray(np.atleast_1d(deltas), np.uint64)
+    ds = np.ascontiguousarray(np.atleast_1d(deltas if deltas is not None else [1]), np.uint64)
+    mw = None if mlp_w is None else np.ascontiguousarray(mlp_w, np.float32)
     dist = np.empty(n, np.uint64)
     td = np.zeros(max(trace_cap, 1), np.uint64)
     st = _DStats()
     rc = _L().orc_delta_step(n, _p(rp), _p(col), _p(w), src, _p(ds), len(ds), _p(dist), ctypes.byref(st),
-                             trace_cap, _p(td))
+                             trace_cap, _p(td), _p(mw))
     if rc != 0:
         raise OracleError("orc_delta_step: %s (%d)" % (_ERRS.get(rc, "?"), rc))
     return DeltaResult(dist, int(st.rounds), int(st.buckets), int(st.light_relax), int(st.heavy_relax),
@@ -198,3 +215,24 @@ def reach_stats(g, dist):
     """(n_reach, m_reach): reachable vertices and the out-edges they own."""
     reach = dist != INF
     return int(reach.sum()), int(np.diff(g.row_ptr)[reach].sum())
+
+
+MLP_NPARAM = 64 * 12 + 64 + 64 * 64 + 64 + 6 * 64 + 6
+CHOICE_CRIT = [STATIC_OR, SIMPLE_OR, FULL_OR]
+
+
+def features(ints, Wm: float, delta_mode: bool = False) -> np.ndarray:
+    """The 12 selector features of one state; ints = (n m F S R a t SD DG Fp Sp Ip Op k)."""
+    a = np.ascontiguousarray(ints, np.uint64)
+    x = np.zeros(12, np.float32)
+    _L().orc_features(_p(a), float(Wm), int(delta_mode), _p(x))
+    return x
+
+
+def mlp_choice(wts, x, lo: int = 0):
+    """FP32 forward pass of the selector; (argmax over outputs lo..lo+2, logits)."""
+    wv = np.ascontiguousarray(wts, np.float32)
+    xv = np.ascontiguousarray(x, np.float32)
+    z = np.zeros(6, np.float32)
+    c = _L().orc_mlp_choice(_p(wv), _p(xv), lo, _p(z))
+    return int(c), z

@@ -59,6 +59,7 @@
  * strength chains DIJK => X-STATIC => X-SIMPLE => (OUTWEAK =>) X hold on
  * every snapshot, ORACLE lower bound <= phases <= reachable vertices).
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -364,6 +365,107 @@ static void out_thresholds(uint32_t want, const uint32_t *Flist, uint64_t nF, co
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Learned per-phase selector: features and FP32 forward pass.               */
+/*
+ * Twelve features of the phase-start state, each a ratio of exact integers
+ * evaluated in double precision in the order written, then rounded to float:
+ *   n, m          vertices, edges;  Wm = (sum of weights) / m (1 if m = 0)
+ *   F, S, R       |F|, settled, reached (= F + S)
+ *   a, t          minD and the OUT-STATIC threshold min_{u in F} d[u] (+) minOut[u]
+ *   SD, DG        sum over F of d[u], sum over F of out-degree
+ *   Fp, Sp        |F| at the previous phase start and |S'| of the previous phase
+ *   Ip, Op        previous-phase queued vertices passing IN-STATIC / OUT-STATIC
+ *   k             0-based phase index
+ * x0 = F/n; x1 = S/n; x2 = Fp ? Sp/Fp : 0; x3 = min(k,4096)/4096;
+ * x4 = t = INF ? 1 : min((t-a)/Wm, 64)/64;
+ * x5 = min(max((SD/F - a)/Wm, 0), 256)/256; x6 = min((DG/F)/(m/n), 8)/8;
+ * x7 = Fp ? Ip/Fp : 0; x8 = Fp ? Op/Fp : 0; x9 = Fp ? min(F/Fp, 4)/4 : 0;
+ * x10 = (n-R)/n; x11 = min(a/Wm, 4096)/4096.
+ * For Delta-stepping the state is taken at a bucket start (k = bucket index,
+ * a = minD, Fp / Sp = |F| at the previous bucket start and the vertices that
+ * bucket settled); x4..x9 are 0.
+ * MLP: 12 -> 64 (ReLU) -> 64 (ReLU) -> 6, FP32; each neuron is its bias
+ * followed by fmaf over its inputs in index order. Weights, flat: W1[64][12],
+ * b1[64], W2[64][64], b2[64], W3[6][64], b3[6] (5382 floats). The phased
+ * solver takes the argmax of outputs 0..2 (ties: lowest index) as the phase's
+ * criterion: 0 = IN-STATIC|OUT-STATIC, 1 = IN-SIMPLE|OUT-SIMPLE, 2 =
+ * IN|OUT; Delta-stepping takes the argmax of outputs 3..5 as the bucket width
+ * 2^12, 2^14, 2^16.
+ */
+#define MLP_IN 12
+#define MLP_H 64
+#define MLP_OUT 6
+#define MLP_NPARAM (MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H + MLP_OUT * MLP_H + MLP_OUT)
+
+typedef struct {
+    uint64_t n, m, F, S, R, a, t, SD, DG, Fp, Sp, Ip, Op, k;
+    double Wm;
+    int delta_mode;
+} feat_in;
+
+static double dmin(double x, double y) { return x < y ? x : y; }
+static double dmax(double x, double y) { return x > y ? x : y; }
+
+static void features(const feat_in *q, float *x) {
+    const double n = (double)q->n, m = (double)q->m, F = (double)q->F, Fp = (double)q->Fp;
+    x[0] = (float)(F / n);
+    x[1] = (float)((double)q->S / n);
+    x[2] = (float)(q->Fp ? (double)q->Sp / Fp : 0.0);
+    x[3] = (float)(dmin((double)q->k, 4096.0) / 4096.0);
+    x[10] = (float)((n - (double)q->R) / n);
+    x[11] = (float)(dmin((double)q->a / q->Wm, 4096.0) / 4096.0);
+    if (q->delta_mode) {
+        for (int i = 4; i < 10; ++i) x[i] = 0.0f;
+        return;
+    }
+    x[4] = (float)(q->t == INF ? 1.0 : dmin((double)(q->t - q->a) / q->Wm, 64.0) / 64.0);
+    x[5] = (float)(dmin(dmax(((double)q->SD / F - (double)q->a) / q->Wm, 0.0), 256.0) / 256.0);
+    x[6] = (float)(dmin(((double)q->DG / F) / (m / n), 8.0) / 8.0);
+    x[7] = (float)(q->Fp ? (double)q->Ip / Fp : 0.0);
+    x[8] = (float)(q->Fp ? (double)q->Op / Fp : 0.0);
+    x[9] = (float)(q->Fp ? dmin(F / Fp, 4.0) / 4.0 : 0.0);
+}
+
+/* FP32 forward pass; returns the argmax of outputs [lo, lo+3). */
+static int mlp_choice(const float *w, const float *x, int lo, float *out_logits) {
+    const float *W1 = w, *b1 = W1 + MLP_H * MLP_IN, *W2 = b1 + MLP_H, *b2 = W2 + MLP_H * MLP_H;
+    const float *W3 = b2 + MLP_H, *b3 = W3 + MLP_OUT * MLP_H;
+    float h1[MLP_H], h2[MLP_H], z[MLP_OUT];
+    for (int j = 0; j < MLP_H; ++j) {
+        float acc = b1[j];
+        for (int i = 0; i < MLP_IN; ++i) acc = fmaf(W1[j * MLP_IN + i], x[i], acc);
+        h1[j] = acc > 0.0f ? acc : 0.0f;
+    }
+    for (int j = 0; j < MLP_H; ++j) {
+        float acc = b2[j];
+        for (int i = 0; i < MLP_H; ++i) acc = fmaf(W2[j * MLP_H + i], h1[i], acc);
+        h2[j] = acc > 0.0f ? acc : 0.0f;
+    }
+    for (int j = 0; j < MLP_OUT; ++j) {
+        float acc = b3[j];
+        for (int i = 0; i < MLP_H; ++i) acc = fmaf(W3[j * MLP_H + i], h2[i], acc);
+        z[j] = acc;
+    }
+    if (out_logits) memcpy(out_logits, z, sizeof z);
+    int best = lo;
+    for (int j = lo + 1; j < lo + 3; ++j)
+        if (z[j] > z[best]) best = j;
+    return best;
+}
+
+/* Exported for tests: features of one state and the forward pass. */
+void orc_features(const uint64_t *ints /* n m F S R a t SD DG Fp Sp Ip Op k */, double Wm, int delta_mode,
+                  float *x) {
+    feat_in q = {ints[0], ints[1], ints[2], ints[3], ints[4], ints[5], ints[6], ints[7], ints[8], ints[9],
+                 ints[10], ints[11], ints[12], ints[13], Wm, delta_mode};
+    features(&q, x);
+}
+
+int orc_mlp_choice(const float *w, const float *x, int lo, float *logits) { return mlp_choice(w, x, lo, logits); }
+
+static const uint32_t CHOICE_CRIT[3] = {C_IN_STATIC | C_OUT_STATIC, C_IN_SIMPLE | C_OUT_SIMPLE, C_IN_FULL | C_OUT_FULL};
+
 static const uint32_t ALL_BITS[8] = {C_DIJK, C_IN_STATIC, C_OUT_STATIC, C_IN_SIMPLE,
                                      C_OUT_SIMPLE, C_IN_FULL, C_OUT_WEAK, C_OUT_FULL};
 
@@ -400,8 +502,9 @@ int orc_phased(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32
                uint32_t crit, const uint32_t *crit_seq, uint32_t seq_len, int check,
                const uint64_t *dist_ref, uint64_t *dist_out, orc_stats *stats, uint32_t trace_cap,
                uint32_t *trace_f, uint32_t *trace_s, uint64_t *trace_mind, uint32_t *trace_counts,
-               uint32_t *phase_of) {
-    if (src >= n || (crit == 0 && !crit_seq) || (crit & ~C_ALL)) return ORC_EINVAL;
+               uint32_t *phase_of, const float *mlp_w, uint32_t *trace_crit, uint32_t *trace_union,
+               float *trace_feat) {
+    if (src >= n || (crit == 0 && !crit_seq && !mlp_w) || (crit & ~C_ALL)) return ORC_EINVAL;
     int rc = ORC_OK;
     csc_t c = {0, 0, 0};
     uint32_t *min_in = (uint32_t *)malloc((uint64_t)n * 4), *min_out = (uint32_t *)malloc((uint64_t)n * 4);
@@ -423,21 +526,48 @@ int orc_phased(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32
     uint64_t nF = 1;
     Fl[0] = src;
     uint32_t k = 0;
+    /* learned mode: previous-phase aggregates for the features */
+    uint64_t prevF = 0, prevS = 0, prevI = 0, prevO = 0, settled = 0;
+    double Wm = 1.0;
+    if (mlp_w && rp[n] > 0) {  /* exact integer weight sum, then one division */
+        uint64_t sw = 0;
+        for (uint64_t e = 0; e < rp[n]; ++e) sw += w[e];
+        Wm = (double)sw / (double)rp[n];
+    }
     while (nF > 0) {
         uint32_t ck = crit_seq ? crit_seq[k < seq_len ? k : seq_len - 1] : crit;
-        if (ck == 0 || (ck & ~C_ALL)) { rc = ORC_EINVAL; goto out; }
         uint32_t want = check ? C_ALL : ck;
         thresholds_t T;
         T.minD = INF;
         for (uint64_t i = 0; i < nF; ++i) T.minD = min64(T.minD, d[Fl[i]]);
+        if (mlp_w) {
+            /* the phase's criterion comes from the selector evaluated on this state */
+            thresholds_t Ts;
+            Ts.minD = T.minD;
+            out_thresholds(C_OUT_STATIC, Fl, nF, rp, col, w, d, st, min_out, inner, stamp, k + 1, &Ts);
+            uint64_t SD = 0, DG = 0;
+            for (uint64_t i = 0; i < nF; ++i) { SD += d[Fl[i]]; DG += rp[Fl[i] + 1] - rp[Fl[i]]; }
+            feat_in q = {n, rp[n], nF, settled, nF + settled, T.minD, Ts.t_out_static, SD, DG, prevF, prevS, prevI,
+                         prevO, k, Wm, 0};
+            float x[MLP_IN];
+            features(&q, x);
+            if (k < trace_cap && trace_feat) memcpy(trace_feat + (uint64_t)MLP_IN * k, x, sizeof x);
+            ck = CHOICE_CRIT[mlp_choice(mlp_w, x, 0, NULL)];
+            want = (check ? C_ALL : ck) | C_IN_STATIC | C_OUT_STATIC;
+        }
+        if (ck == 0 || (ck & ~C_ALL)) { rc = ORC_EINVAL; goto out; }
+        if (k < trace_cap && trace_crit) trace_crit[k] = ck;
         out_thresholds(want, Fl, nF, rp, col, w, d, st, min_out, inner, stamp, k + 1, &T);
-        uint32_t cnt[8] = {0};
-        uint64_t nS = 0, nK = 0;
+        uint32_t cnt[8] = {0}, uni[3] = {0, 0, 0};
+        uint64_t nS = 0, nK = 0, nin = 0, nout = 0;
         for (uint64_t i = 0; i < nF; ++i) {
             uint32_t v = Fl[i];
             uint32_t b = eval_bits(v, want, &T, d, st, min_in, &c);
+            nin += (b & C_IN_STATIC) ? 1 : 0;
+            nout += (b & C_OUT_STATIC) ? 1 : 0;
             if (check) {
                 for (int j = 0; j < 8; ++j) cnt[j] += (b & ALL_BITS[j]) ? 1 : 0;
+                for (int j = 0; j < 3; ++j) uni[j] += (b & CHOICE_CRIT[j]) ? 1 : 0;
                 if (!chain_ok(b)) { rc = ORC_ECHAIN; goto out; }
                 if (d[v] == T.minD && !(b & C_DIJK)) { rc = ORC_EINCOMPLETE; goto out; }
             }
@@ -454,7 +584,9 @@ int orc_phased(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32
             if (trace_s) trace_s[k] = (uint32_t)nS;
             if (trace_mind) trace_mind[k] = T.minD;
             if (trace_counts) memcpy(trace_counts + 8ull * k, cnt, sizeof cnt);
+            if (trace_union) memcpy(trace_union + 3ull * k, uni, sizeof uni);
         }
+        prevF = nF; prevS = nS; prevI = nin; prevO = nout; settled += nS;
         S.sum_f += nF;
         /* settle all of S' (moved to S), then relax their out-edges */
         for (uint64_t i = 0; i < nS; ++i) st[Sp[i]] = ST_S;
@@ -503,9 +635,16 @@ typedef struct {
 
 int orc_delta_step(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32_t *w,
                    uint32_t src, const uint64_t *deltas, uint32_t n_deltas, uint64_t *dist_out,
-                   orc_dstats *stats, uint32_t trace_cap, uint64_t *trace_delta) {
-    if (src >= n || n_deltas == 0) return ORC_EINVAL;
+                   orc_dstats *stats, uint32_t trace_cap, uint64_t *trace_delta, const float *mlp_w) {
+    if (src >= n || (n_deltas == 0 && !mlp_w)) return ORC_EINVAL;
     for (uint32_t i = 0; i < n_deltas; ++i) if (deltas[i] == 0) return ORC_EINVAL;
+    double Wm = 1.0;
+    if (mlp_w && rp[n] > 0) {  /* exact integer weight sum, then one division */
+        uint64_t sw = 0;
+        for (uint64_t e = 0; e < rp[n]; ++e) sw += w[e];
+        Wm = (double)sw / (double)rp[n];
+    }
+    uint64_t Fp = 0, Sp = 0, settled = 0;
     int rc = ORC_OK;
     uint64_t *d = dist_out;
     uint8_t *st = (uint8_t *)calloc(n, 1);
@@ -526,10 +665,19 @@ int orc_delta_step(uint32_t n, const uint64_t *rp, const uint32_t *col, const ui
     Fl[0] = src;
     uint32_t rstamp = 0;
     while (nF > 0) {
-        uint64_t delta = deltas[D.buckets < n_deltas ? D.buckets : n_deltas - 1];
-        if (D.buckets < trace_cap && trace_delta) trace_delta[D.buckets] = delta;
         uint64_t minD = INF;
         for (uint64_t i = 0; i < nF; ++i) minD = min64(minD, d[Fl[i]]);
+        uint64_t delta;
+        if (mlp_w) {
+            feat_in q = {n, rp[n], nF, settled, nF + settled, minD, INF, 0, 0, Fp, Sp, 0, 0, D.buckets, Wm, 1};
+            float x[MLP_IN];
+            features(&q, x);
+            delta = 1ull << (12 + 2 * (mlp_choice(mlp_w, x, 3, NULL) - 3));
+        } else {
+            delta = deltas[D.buckets < n_deltas ? D.buckets : n_deltas - 1];
+        }
+        if (D.buckets < trace_cap && trace_delta) trace_delta[D.buckets] = delta;
+        Fp = nF;
         uint64_t lo = (minD / delta) * delta;  /* bucket floor(minD / delta) */
         uint64_t hi = sadd(lo, delta);
         uint64_t nX = 0, nR = 0, nF0 = nF;
@@ -564,6 +712,8 @@ int orc_delta_step(uint32_t n, const uint64_t *rp, const uint32_t *col, const ui
         /* heavy round: everything the bucket removed is settled and relaxes
          * its heavy edges once */
         D.rounds++;
+        Sp = nR;
+        settled += nR;
         for (uint64_t i = 0; i < nR; ++i) { st[R[i]] = ST_S; inR[R[i]] = 0; }
         for (uint64_t i = 0; i < nR; ++i) {
             uint32_t u = R[i];

@@ -1,0 +1,156 @@
+"""Pins for the selector side of the oracle (no GPU).
+
+* The float64 network reference is pinned by central finite differences and by a per-sample loop
+  forward pass written separately.
+* The oracle's FP32 forward pass agrees with the float64 reference wherever the top two logits are
+  clearly apart.
+* Learned-mode replay with a network that always prefers one output equals the fixed criterion
+  (or the fixed bucket width) exactly.
+* The 12 features the oracle computes equal an independent pure-Python re-simulation of the phased
+  algorithm on small graphs.
+"""
+import numpy as np
+import pytest
+
+import graphgen as G
+import oracle as O
+from oracle import mlp_ref as M
+
+
+def test_gradient_matches_finite_differences():
+    rng = np.random.default_rng(0)
+    w = M.init_params(1) + rng.normal(0, 0.05, M.NPARAM)
+    X = rng.uniform(0, 1, (9, 12))
+    y = rng.integers(0, 6, 9)
+    _, g = M.loss_and_grad(w, X, y)
+    idx = rng.choice(M.NPARAM, 120, replace=False)
+    for i in idx:
+        e = np.zeros(M.NPARAM)
+        e[i] = 1e-6
+        fd = (M.loss_and_grad(w + e, X, y)[0] - M.loss_and_grad(w - e, X, y)[0]) / 2e-6
+        assert abs(fd - g[i]) <= 1e-6 + 1e-5 * abs(g[i]), (i, fd, g[i])
+
+
+def test_forward_matches_per_sample_loops():
+    rng = np.random.default_rng(2)
+    w = M.init_params(3)
+    p = M.unpack(w)
+    X = rng.uniform(0, 1, (5, 12))
+    z, _ = M.forward(w, X)
+    for s in range(5):
+        h1 = [max(0.0, p["b1"][j] + sum(p["W1"][j][i] * X[s][i] for i in range(12))) for j in range(64)]
+        h2 = [max(0.0, p["b2"][j] + sum(p["W2"][j][i] * h1[i] for i in range(64))) for j in range(64)]
+        out = [p["b3"][j] + sum(p["W3"][j][i] * h2[i] for i in range(64)) for j in range(6)]
+        assert np.allclose(out, z[s], rtol=1e-12, atol=1e-12)
+
+
+def test_fp32_forward_agrees_with_reference():
+    rng = np.random.default_rng(4)
+    w = M.init_params(5)
+    checked = 0
+    for _ in range(300):
+        x = rng.uniform(0, 1, 12).astype(np.float32)
+        z64, _ = M.forward(w, x[None, :].astype(np.float64))
+        for lo in (0, 3):
+            seg = np.sort(z64[0, lo:lo + 3])
+            if seg[-1] - seg[-2] < 1e-4:
+                continue
+            c, z32 = O.mlp_choice(w.astype(np.float32), x, lo)
+            assert c == lo + int(np.argmax(z64[0, lo:lo + 3]))
+            assert np.allclose(z32, z64[0], rtol=1e-4, atol=1e-4)
+            checked += 1
+    assert checked > 400
+
+
+def constant_net(choice):
+    w = np.zeros(M.NPARAM, np.float32)
+    w[-6 + choice] = 10.0  # b3: this output always wins
+    return w
+
+
+@pytest.mark.parametrize("choice", [0, 1, 2])
+def test_learned_replay_with_constant_choice_equals_fixed_criterion(choice):
+    for g in (G.er(600, 5, 1, 300, 2), G.rmat(9, 8, 1, 1000, 3), G.grid(12, 9, 1, 40, 4)):
+        ref = O.phased(g, 0, O.CHOICE_CRIT[choice])
+        lr = O.phased(g, 0, 0, mlp_w=constant_net(choice), check=True)
+        assert lr.phases == ref.phases and np.array_equal(lr.phase_of, ref.phase_of)
+        assert (lr.trace_crit == O.CHOICE_CRIT[choice]).all()
+
+
+@pytest.mark.parametrize("choice", [3, 4, 5])
+def test_learned_delta_with_constant_choice_equals_fixed_width(choice):
+    g = G.er(2000, 6, 1, 1 << 16, 5)
+    delta = 1 << (12 + 2 * (choice - 3))
+    ref = O.delta_step(g, 0, [delta])
+    lr = O.delta_step(g, 0, None, mlp_w=constant_net(choice), trace_cap=64)
+    assert lr.rounds == ref.rounds and np.array_equal(lr.dist, ref.dist)
+    assert (lr.trace_delta == delta).all()
+
+
+def python_features(g, src):
+    """Independent re-simulation of IN-STATIC|OUT-STATIC with the feature definitions."""
+    n, m = g.n, g.m
+    rp, col, w = [int(x) for x in g.row_ptr], [int(x) for x in g.col], [int(x) for x in g.w]
+    INF = O.INF_INT
+    min_in = [INF] * n
+    min_out = [INF] * n
+    for u in range(n):
+        for e in range(rp[u], rp[u + 1]):
+            min_out[u] = min(min_out[u], w[e])
+            min_in[col[e]] = min(min_in[col[e]], w[e])
+    Wm = (float(sum(w)) / float(m)) if m else 1.0
+    d = [INF] * n
+    st = [0] * n
+    d[src] = 0
+    st[src] = 1
+    settled = 0
+    prev = (0, 0, 0, 0)
+    out = []
+    k = 0
+    while True:
+        Fs = [v for v in range(n) if st[v] == 1]
+        if not Fs:
+            break
+        F = len(Fs)
+        a = min(d[v] for v in Fs)
+        t = min((d[v] + min_out[v]) if min_out[v] != INF else INF for v in Fs)
+        SD = sum(d[v] for v in Fs)
+        DG = sum(rp[v + 1] - rp[v] for v in Fs)
+        Fp, Sp, Ip, Op = prev
+        x = [0.0] * 12
+        x[0] = F / n
+        x[1] = settled / n
+        x[2] = Sp / Fp if Fp else 0.0
+        x[3] = min(float(k), 4096.0) / 4096.0
+        x[4] = 1.0 if t == INF else min((t - a) / Wm, 64.0) / 64.0
+        x[5] = min(max((SD / F - a) / Wm, 0.0), 256.0) / 256.0
+        x[6] = min((DG / F) / (m / n), 8.0) / 8.0
+        x[7] = Ip / Fp if Fp else 0.0
+        x[8] = Op / Fp if Fp else 0.0
+        x[9] = min(F / Fp, 4.0) / 4.0 if Fp else 0.0
+        x[10] = (n - (F + settled)) / n
+        x[11] = min(a / Wm, 4096.0) / 4096.0
+        out.append(np.array(x, np.float64).astype(np.float32))
+        ins = [v for v in Fs if min_in[v] == INF or d[v] <= a + min_in[v]]
+        outs = [v for v in Fs if d[v] <= t]
+        S = sorted(set(ins) | set(outs))
+        for v in S:
+            st[v] = 2
+        for u in S:
+            for e in range(rp[u], rp[u + 1]):
+                x_ = col[e]
+                if st[x_] != 2 and d[u] + w[e] < d[x_]:
+                    d[x_] = d[u] + w[e]
+                    st[x_] = 1
+        prev = (F, len(S), len(ins), len(outs))
+        settled += len(S)
+        k += 1
+    return np.array(out)
+
+
+def test_features_match_independent_simulation():
+    for g in (G.er(300, 4, 1, 500, 7), G.random_small(40, 150, 9, 8), G.grid(7, 6, 1, 30, 9)):
+        ref = python_features(g, 0)
+        lr = O.phased(g, 0, 0, mlp_w=constant_net(0))
+        assert lr.trace_feat.shape == ref.shape
+        assert np.array_equal(lr.trace_feat, ref)
