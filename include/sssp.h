@@ -243,6 +243,57 @@ int sssp_autotune_batch(sssp_graph *const *graphs, const uint32_t *sources, uint
                         uint32_t criterion, uint64_t *const *dist_outs, sssp_batch_cfg *best,
                         float *best_ms);
 
+/*
+ * Learned per-phase selector: an MLP 12 -> 64 (ReLU) -> 64 (ReLU) -> 6 in FP32
+ * that looks at the phase-start state and picks, per phase, which criterion
+ * the phased solver evaluates (outputs 0..2: IN-STATIC|OUT-STATIC,
+ * IN-SIMPLE|OUT-SIMPLE, IN|OUT) or, per bucket, Delta-stepping's width
+ * (outputs 3..5: 2^12, 2^14, 2^16). Every criterion is sound (Section 3), so a
+ * choice changes work and phase count, never a distance.
+ * Features (12 floats, each a ratio of exact integers computed in double and
+ * rounded once): F/n, S/n, Sp/Fp, min(k,4096)/4096, min((t-a)/Wm,64)/64,
+ * min(max((SD/F-a)/Wm,0),256)/256, min((DG/F)/(m/n),8)/8, Ip/Fp, Op/Fp,
+ * min(F/Fp,4)/4, (n-R)/n, min(a/Wm,4096)/4096 -- F, S, R: queued, settled,
+ * reached; a: minD; t: OUT-STATIC threshold; SD, DG: sums over F of d and of
+ * out-degree; Fp, Sp, Ip, Op: previous |F|, |S'|, and previous queued vertices
+ * passing IN-STATIC / OUT-STATIC; k: phase index; Wm: mean weight. For
+ * Delta-stepping (at bucket starts) the 5th to 10th features are 0.
+ * Weights: 5382 floats, W1[64][12] b1[64] W2[64][64] b2[64] W3[6][64] b3[6].
+ */
+typedef struct sssp_selector sssp_selector;
+
+#define SSSP_SELECTOR_PARAMS 5382
+
+/* Create a selector with the given HOST weights (NULL: all zeros). */
+int sssp_selector_create(const float *weights, sssp_selector **out);
+int sssp_selector_destroy(sssp_selector *s);
+int sssp_selector_get_weights(const sssp_selector *s, float *host_out);
+/* Replace the weights (HOST array) and reset the optimiser state. */
+int sssp_selector_set_weights(sssp_selector *s, const float *host_in);
+
+/* Logits for n feature rows (HOST x[n][12] -> HOST logits[n][6]). */
+int sssp_selector_forward(const sssp_selector *s, const float *x, uint32_t n, float *logits_out);
+
+/* Mean softmax cross-entropy of n rows with labels y (0..5) and its gradient
+ * with respect to the weights (HOST, 5382 floats, same layout). */
+int sssp_selector_grad(const sssp_selector *s, const float *x, const int32_t *y, uint32_t n, float *loss_out,
+                       float *grad_out);
+
+/* Adam training on the GPU: `epochs` passes over n rows in shuffled batches
+ * of `batch` (shuffle seeded by `seed`); final_loss: mean loss of the last
+ * batch (may be NULL). */
+int sssp_selector_train(sssp_selector *s, const float *x, const int32_t *y, uint32_t n, uint32_t epochs,
+                        uint32_t batch, float lr, uint64_t seed, float *final_loss);
+
+/* Phased SSSP whose criterion is chosen per phase by the selector (trace
+ * records carry each phase's criterion bits). Arguments as sssp_solve_ex. */
+int sssp_solve_learned(sssp_graph *g, uint32_t source, const sssp_selector *sel, uint64_t *dist_out,
+                       sssp_stats *stats, uint32_t *phase_of, sssp_phase_rec *trace, uint32_t trace_cap);
+
+/* Delta-stepping whose bucket width is chosen per bucket by the selector. */
+int sssp_delta_step_learned(sssp_graph *g, uint32_t source, const sssp_selector *sel, uint64_t *dist_out,
+                            sssp_stats *stats, sssp_phase_rec *trace, uint32_t trace_cap);
+
 /* Human-readable description of the last error on the calling thread. */
 const char *sssp_last_error(void);
 

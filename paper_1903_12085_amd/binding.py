@@ -27,7 +27,9 @@ SYMBOLS = ["sssp_graph_create", "sssp_graph_destroy", "sssp_set_stream", "sssp_g
            "sssp_solve_ex", "sssp_delta_step", "sssp_delta_step_ex", "sssp_solve_batch", "sssp_last_error",
            "sssp_profile_enable", "sssp_profile_get", "sssp_get_launch", "sssp_set_launch",
            "sssp_solve_batch_ex", "sssp_batch_set_config", "sssp_batch_get_config", "sssp_autotune",
-           "sssp_autotune_batch"]
+           "sssp_autotune_batch", "sssp_selector_create", "sssp_selector_destroy", "sssp_selector_get_weights",
+           "sssp_selector_set_weights", "sssp_selector_forward", "sssp_selector_grad", "sssp_selector_train",
+           "sssp_solve_learned", "sssp_delta_step_learned"]
 
 ERRORS = {-1: "SSSP_ERR_INVALID", -2: "SSSP_ERR_OOM", -3: "SSSP_ERR_DEVICE", -4: "SSSP_ERR_UNSUPPORTED",
           -5: "SSSP_ERR_INTERNAL"}
@@ -104,6 +106,16 @@ def load(path: str = LIB_PATH):
     lib.sssp_batch_get_config.argtypes = [ctypes.POINTER(BatchCfg)]
     lib.sssp_autotune.argtypes = [P, u32, u32, ctypes.POINTER(LaunchCfg), ctypes.POINTER(ctypes.c_float)]
     lib.sssp_autotune_batch.argtypes = [P, P, u32, u32, P, ctypes.POINTER(BatchCfg), ctypes.POINTER(ctypes.c_float)]
+    f32p = ctypes.POINTER(ctypes.c_float)
+    lib.sssp_selector_create.argtypes = [P, ctypes.POINTER(P)]
+    lib.sssp_selector_destroy.argtypes = [P]
+    lib.sssp_selector_get_weights.argtypes = [P, P]
+    lib.sssp_selector_set_weights.argtypes = [P, P]
+    lib.sssp_selector_forward.argtypes = [P, P, u32, P]
+    lib.sssp_selector_grad.argtypes = [P, P, P, u32, f32p, P]
+    lib.sssp_selector_train.argtypes = [P, P, P, u32, u32, u32, ctypes.c_float, u64, f32p]
+    lib.sssp_solve_learned.argtypes = [P, u32, P, P, ctypes.POINTER(Stats), P, P, u32]
+    lib.sssp_delta_step_learned.argtypes = [P, u32, P, P, ctypes.POINTER(Stats), P, u32]
     lib.sssp_last_error.restype = ctypes.c_char_p
     lib.sssp_last_error.argtypes = []
     for name in SYMBOLS:
@@ -314,3 +326,92 @@ def autotune_batch(graphs, sources, criterion: int, dists=None):
     c, ms = BatchCfg(), ctypes.c_float(0)
     _check(load().sssp_autotune_batch(handles, _np_ptr(srcs), nq, criterion, outs, ctypes.byref(c), ctypes.byref(ms)))
     return c.as_dict(), float(ms.value)
+
+
+SELECTOR_PARAMS = 5382
+CHOICE_CRIT = [STATIC_OR, SIMPLE_OR, FULL_OR]
+CHOICE_DELTA = [1 << 12, 1 << 14, 1 << 16]
+
+
+class Selector:
+    """The per-phase selector network (device weights owned by the library)."""
+
+    def __init__(self, weights=None):
+        self._h = ctypes.c_void_p()
+        w = None if weights is None else np.ascontiguousarray(weights, np.float32)
+        if w is not None and w.size != SELECTOR_PARAMS:
+            raise ValueError("selector needs %d weights" % SELECTOR_PARAMS)
+        _check(load().sssp_selector_create(_np_ptr(w), ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            load().sssp_selector_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def weights(self) -> np.ndarray:
+        w = np.zeros(SELECTOR_PARAMS, np.float32)
+        _check(load().sssp_selector_get_weights(self._h, _np_ptr(w)))
+        return w
+
+    def set_weights(self, w):
+        w = np.ascontiguousarray(w, np.float32)
+        _check(load().sssp_selector_set_weights(self._h, _np_ptr(w)))
+
+    def forward(self, x) -> np.ndarray:
+        x = np.ascontiguousarray(x, np.float32).reshape(-1, 12)
+        z = np.zeros((x.shape[0], 6), np.float32)
+        _check(load().sssp_selector_forward(self._h, _np_ptr(x), x.shape[0], _np_ptr(z)))
+        return z
+
+    def grad(self, x, y):
+        x = np.ascontiguousarray(x, np.float32).reshape(-1, 12)
+        y = np.ascontiguousarray(y, np.int32)
+        g = np.zeros(SELECTOR_PARAMS, np.float32)
+        loss = ctypes.c_float(0)
+        _check(load().sssp_selector_grad(self._h, _np_ptr(x), _np_ptr(y), x.shape[0], ctypes.byref(loss), _np_ptr(g)))
+        return float(loss.value), g
+
+    def train(self, x, y, epochs=20, batch=256, lr=3e-3, seed=0) -> float:
+        x = np.ascontiguousarray(x, np.float32).reshape(-1, 12)
+        y = np.ascontiguousarray(y, np.int32)
+        loss = ctypes.c_float(0)
+        _check(load().sssp_selector_train(self._h, _np_ptr(x), _np_ptr(y), x.shape[0], epochs, batch, lr, seed,
+                                          ctypes.byref(loss)))
+        return float(loss.value)
+
+
+def solve_learned(g: DeviceGraph, source: int, sel: Selector, dist=None, phase_of: bool = False,
+                  trace_cap: int = 0) -> SolveResult:
+    import torch
+    dist = new_dist(g.n) if dist is None else dist
+    po = torch.empty(g.n, dtype=torch.int32, device="cuda") if phase_of else None
+    tr = np.zeros(trace_cap, PHASE_REC) if trace_cap else None
+    st = Stats()
+    g._bind_stream()
+    _check(load().sssp_solve_learned(g.handle, source, sel.handle, ctypes.c_void_p(dist.data_ptr()), ctypes.byref(st),
+                                     ctypes.c_void_p(po.data_ptr()) if po is not None else None, _np_ptr(tr), trace_cap))
+    if tr is not None:
+        tr = tr[:min(st.phases, trace_cap)]
+    return SolveResult(dist, int(st.phases), st.as_dict(), po, tr)
+
+
+def delta_step_learned(g: DeviceGraph, source: int, sel: Selector, dist=None, trace_cap: int = 0) -> SolveResult:
+    dist = new_dist(g.n) if dist is None else dist
+    tr = np.zeros(trace_cap, PHASE_REC) if trace_cap else None
+    st = Stats()
+    g._bind_stream()
+    _check(load().sssp_delta_step_learned(g.handle, source, sel.handle, ctypes.c_void_p(dist.data_ptr()),
+                                          ctypes.byref(st), _np_ptr(tr), trace_cap))
+    if tr is not None:
+        tr = tr[:min(st.phases, trace_cap)]
+    return SolveResult(dist, int(st.phases), st.as_dict(), None, tr)

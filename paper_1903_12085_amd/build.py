@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsssp.so")
-SOURCES = ["graph.hip", "phased.hip", "batch.hip", "tune.hip"]
+SOURCES = ["graph.hip", "phased.hip", "batch.hip", "tune.hip", "mlp.hip"]
 ARCH = os.environ.get("SSSP_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

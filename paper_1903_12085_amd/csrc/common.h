@@ -53,8 +53,13 @@ struct alignas(128) CtlHead {
     unsigned int buckets;           // buckets finished (written by the heavy round's identify)
     unsigned int win_bucket;        // index of the bucket in progress
     unsigned int n_deltas;
-    unsigned int pad;
+    unsigned int choice[2];         // learned mode: choice index of the phase with this parity
     unsigned long long win_lo, win_hi, win_delta;
+    unsigned long long fk;          // |F| at the start of the phase in progress (feature input)
+    unsigned long long s_k;         // settled count at the start of the phase (round) in progress
+    unsigned long long m_k;         // m_reach at the start of the phase in progress
+    unsigned long long fbucket;     // |F| at the start of the bucket in progress (feature input)
+    unsigned long long next_delta;  // learned Delta-stepping: width of the next bucket
 };
 
 // Device control block of one solve. Slots indexed by phase parity (mod 2 or
@@ -72,6 +77,12 @@ struct Ctl {
     Sharded tdyn[3];                // min: dynamic OUT threshold from the term pass
     Sharded nextmin[2];             // min: Delta-stepping, min d over F for the next bucket
     Sharded win_improved[2];        // sum: Delta-stepping, vertices improved inside the window
+    // learned mode (selector features)
+    Sharded sumd[3];                // sum over F of d (mod 2^64 while folding), by phase mod 3
+    Sharded degsum;                 // sum of out-degrees of every vertex ever queued
+    Sharded nin[2], nout[2];        // queued vertices passing IN-STATIC / OUT-STATIC, by phase parity
+    Sharded tick[2];                // relax workgroups finished, per shard, by phase parity
+    Sharded tick_all[2];            // shards finished (slot 0), by phase parity
 };
 
 // Per-phase device trace record (mirrors sssp_phase_rec).

@@ -14,6 +14,7 @@ struct sssp_graph {
     uint32_t *ip = nullptr;        // CSC in_ptr (lazy)
     uint2 *in_edges = nullptr;     // CSC (source, weight), rows sorted by weight (lazy)
     uint64_t precompute_ns = 0;
+    uint64_t sum_w = 0;            // exact sum of edge weights (selector feature scale)
     LaunchCfg cfg{};
     // per-solve scratch, allocated on first use and kept
     SolveBufs b{};

@@ -31,6 +31,7 @@
 
 #include "common.h"
 #include "graph.h"
+#include "selector.h"
 
 static_assert(sizeof(PhaseRec) == sizeof(sssp_phase_rec), "trace record layout");
 
@@ -38,7 +39,12 @@ struct KArgs {
     DevGraph g;
     SolveBufs b;
     uint32_t crit;
+    const float *mlp_w;  // learned mode: selector weights (device)
+    double wm;           // learned mode: mean edge weight (feature scale)
 };
+
+static __device__ const uint32_t kChoiceCrit[3] = {SSSP_IN_STATIC | SSSP_OUT_STATIC, SSSP_IN_SIMPLE | SSSP_OUT_SIMPLE,
+                                                  SSSP_IN_FULL | SSSP_OUT_FULL};
 
 __device__ __forceinline__ unsigned long long *slot_of(Sharded &s, int i) { return &s.v[i * kPad]; }
 __device__ __forceinline__ int my_shard() { return (int)(blockIdx.x % kShards); }
@@ -98,6 +104,43 @@ __global__ void k_init_ctl(Ctl *ctl, const uint2 *__restrict__ vmin, uint32_t sr
         ctl->tst[0].v[o] = i == 0 ? w64(vmin[src].y) : INF64;  // 0 + minOut[s]
         ctl->nextmin[0].v[o] = i == 0 ? 0ull : INF64;
         ctl->nextmin[1].v[o] = INF64;
+        for (int k = 0; k < 3; ++k) ctl->sumd[k].v[o] = 0;  // sum over F = {s} of d is 0
+        ctl->degsum.v[o] = 0;
+        for (int k = 0; k < 2; ++k) {
+            ctl->nin[k].v[o] = ctl->nout[k].v[o] = 0;
+            ctl->tick[k].v[o] = ctl->tick_all[k].v[o] = 0;
+        }
+    }
+}
+
+// Learned mode: the degree sum of the queued set starts with the source, and
+// the first phase's (or bucket's) choice comes from the features of {s}.
+__global__ void k_init_choice(KArgs a, uint32_t src, int delta_mode) {
+    __shared__ MlpLds L;
+    Ctl *ctl = a.b.ctl;
+    const unsigned long long deg = a.g.rp[src + 1] - a.g.rp[src];
+    if (threadIdx.x == 0) {
+        ctl->degsum.v[0] = deg;
+        FeatIn q;
+        q.n = a.g.n;
+        q.m = a.g.m;
+        q.F = 1;
+        q.S = 0;
+        q.R = 1;
+        q.a = 0;
+        q.t = w64(a.g.vmin[src].y);
+        q.SD = 0;
+        q.DG = deg;
+        q.Fp = q.Sp = q.Ip = q.Op = 0;
+        q.k = 0;
+        q.Wm = a.wm;
+        q.delta_mode = delta_mode;
+        features_dev(q, L.x);
+    }
+    const int c = mlp_choice_block(a.mlp_w, L, delta_mode ? 3 : 0);
+    if (threadIdx.x == 0) {
+        if (delta_mode) ctl->h.next_delta = 1ull << (12 + 2 * (c - 3));
+        else ctl->h.choice[0] = (unsigned int)c;
     }
 }
 
@@ -241,10 +284,9 @@ __device__ __forceinline__ unsigned long long walk_nonsettled(const KArgs &a, ui
 }
 
 template <int IN, int OUT>
-__global__ __launch_bounds__(kBlock) void k_terms(KArgs a, int par) {
+__device__ __forceinline__ void terms_body(const KArgs &a, int par, unsigned long long *sh) {
     Ctl *ctl = a.b.ctl;
     const int p3 = par % 3;
-    __shared__ unsigned long long sh[kWaves];
     __shared__ unsigned long long s_reached, s_minD;
     if (threadIdx.x < 64) {
         const unsigned long long r = shard_sum_w0(ctl->reached);
@@ -315,6 +357,20 @@ __global__ __launch_bounds__(kBlock) void k_terms(KArgs a, int par) {
     }
 }
 
+template <int IN, int OUT>
+__global__ __launch_bounds__(kBlock) void k_terms(KArgs a, int par) {
+    __shared__ unsigned long long sh[kWaves];
+    terms_body<IN, OUT>(a, par, sh);
+}
+
+// Learned mode: the term pass of the criterion the selector chose for this phase.
+__global__ __launch_bounds__(kBlock) void k_terms_learned(KArgs a, int par) {
+    __shared__ unsigned long long sh[kWaves];
+    const unsigned int c = a.b.ctl->h.choice[par & 1];
+    if (c == 1) terms_body<IN_SIMPLE_M, OUT_SIMPLE_M>(a, par, sh);
+    else if (c == 2) terms_body<IN_FULL_M, OUT_FULL_M>(a, par, sh);
+}
+
 // ---------------------------------------------------------------------------
 // identify (phased)
 
@@ -322,12 +378,12 @@ __global__ __launch_bounds__(kBlock) void k_terms(KArgs a, int par) {
 // OUT: 0 none, 1 static threshold, 2 threshold from the term pass.
 // Each lane owns four consecutive vertices per step: one 32-bit state load,
 // then the distance / minima loads of all its queued vertices in flight at once.
-template <int IN, int OUT, int CH>
-__global__ __launch_bounds__(kBlock) void k_identify(KArgs a, int par) {
+// LEARN: also count the queued vertices passing each static test, fold the
+// sum of kept distances and always fold the OUT-STATIC threshold (features).
+template <int IN, int OUT, int CH, bool LEARN>
+__device__ __forceinline__ void identify_body(const KArgs &a, int par, unsigned long long *sh, AppendLds &L) {
     Ctl *ctl = a.b.ctl;
     const int p2 = par & 1, p3 = par % 3;
-    __shared__ unsigned long long sh[kWaves];
-    __shared__ AppendLds L;
     if (threadIdx.x == 0) { L.cnt = 0; L.filled = 0; L.zero = 0; }
     // every wavefront combines the sharded phase-start values itself (no block barrier)
     const unsigned long long reached = shard_sum_w0(ctl->reached);
@@ -351,12 +407,15 @@ __global__ __launch_bounds__(kBlock) void k_identify(KArgs a, int par) {
             ctl->h.pnum[p2 ^ 1] = P + 1;
             ctl->h.phases = P + 1;
             ctl->h.sum_f += reached - settled;
+            ctl->h.fk = reached - settled;
+            ctl->h.s_k = settled;
+            ctl->h.m_k = ctl->h.m_reach;
             if (P < a.b.trace_cap) {
                 PhaseRec r;
                 r.min_d = minD;
                 r.fringe = (unsigned int)(reached - settled);
                 r.settled = 0;
-                r.criterion = a.crit;
+                r.criterion = LEARN ? kChoiceCrit[ctl->h.choice[p2]] : a.crit;
                 r.edges = 0;
                 a.b.trace[P] = r;
             }
@@ -366,9 +425,15 @@ __global__ __launch_bounds__(kBlock) void k_identify(KArgs a, int par) {
         shard_fill(ctl->minD[(p3 + 2) % 3], INF64);
         shard_fill(ctl->tst[(p3 + 2) % 3], INF64);
         shard_fill(ctl->tdyn[(p3 + 1) % 3], INF64);
+        if (LEARN) {
+            shard_fill(ctl->sumd[(p3 + 2) % 3], 0);
+            shard_fill(ctl->nin[p2 ^ 1], 0);
+            shard_fill(ctl->nout[p2 ^ 1], 0);
+        }
     }
     __syncthreads();  // LDS counters initialised
-    unsigned long long fmin = INF64, ftst = INF64;
+    unsigned long long fmin = INF64, ftst = INF64, fsum = 0, cin = 0, cout = 0;
+    const unsigned long long Tst = LEARN ? shard_min_w0(ctl->tst[p3]) : 0ull;
     const uint32_t n = a.g.n;
     const uint32_t nq = (n + 3) / 4;
     for (uint32_t base = blockIdx.x * kBlock; base < nq; base += gridDim.x * kBlock) {
@@ -382,7 +447,7 @@ __global__ __launch_bounds__(kBlock) void k_identify(KArgs a, int par) {
             mm[i] = make_uint2(INF32, INF32);
             if (((s4 >> (8 * i)) & ST_SET) == ST_F) {
                 dv[i] = a.b.dist[4 * q + i];
-                if (IN == IN_STATIC_M || OUT == 1) mm[i] = a.g.vmin[4 * q + i];
+                if (LEARN || IN == IN_STATIC_M || OUT == 1) mm[i] = a.g.vmin[4 * q + i];
             }
         }
 #pragma unroll
@@ -392,6 +457,10 @@ __global__ __launch_bounds__(kBlock) void k_identify(KArgs a, int par) {
             bool set = false;
             uint32_t row = 0, deg = 0;
             if ((s & ST_SET) == ST_F) {
+                if (LEARN) {
+                    cin += dv[i] <= sadd64(minD, w64(mm[i].x)) ? 1 : 0;
+                    cout += dv[i] <= Tst ? 1 : 0;
+                }
                 bool ok = false;
                 if (IN == IN_DIJK) ok = dv[i] == minD;
                 else if (IN == IN_STATIC_M) ok = dv[i] <= sadd64(minD, w64(mm[i].x));
@@ -405,7 +474,8 @@ __global__ __launch_bounds__(kBlock) void k_identify(KArgs a, int par) {
                     if (a.b.phase_of) a.b.phase_of[v] = P + 1;
                 } else {
                     fmin = umin64(fmin, dv[i]);
-                    if (OUT == 1) ftst = umin64(ftst, sadd64(dv[i], w64(mm[i].y)));
+                    if (LEARN || OUT == 1) ftst = umin64(ftst, sadd64(dv[i], w64(mm[i].y)));
+                    if (LEARN) fsum += dv[i];
                 }
             }
             append_settled<CH>(a, ctl, p2, L, set, row, deg, dv[i]);
@@ -413,11 +483,37 @@ __global__ __launch_bounds__(kBlock) void k_identify(KArgs a, int par) {
     }
     append_flush<CH>(a, ctl, p2, L);
     fmin = block_min64<kWaves>(fmin, sh);
-    if (OUT == 1) ftst = block_min64<kWaves>(ftst, sh);
+    if (LEARN || OUT == 1) ftst = block_min64<kWaves>(ftst, sh);
+    if (LEARN) {
+        fsum = block_sum64<kWaves>(fsum, sh);
+        cin = block_sum64<kWaves>(cin, sh);
+        cout = block_sum64<kWaves>(cout, sh);
+    }
     if (threadIdx.x == 0) {
         if (fmin != INF64) atomicMin(slot_of(ctl->minD[(p3 + 1) % 3], my_shard()), fmin);
         if (ftst != INF64) atomicMin(slot_of(ctl->tst[(p3 + 1) % 3], my_shard()), ftst);
+        if (LEARN) {
+            if (fsum) atomicAdd(slot_of(ctl->sumd[(p3 + 1) % 3], my_shard()), fsum);
+            if (cin) atomicAdd(slot_of(ctl->nin[p2], my_shard()), cin);
+            if (cout) atomicAdd(slot_of(ctl->nout[p2], my_shard()), cout);
+        }
     }
+}
+
+template <int IN, int OUT, int CH>
+__global__ __launch_bounds__(kBlock) void k_identify(KArgs a, int par) {
+    __shared__ unsigned long long sh[kWaves];
+    __shared__ AppendLds L;
+    identify_body<IN, OUT, CH, false>(a, par, sh, L);
+}
+
+// Learned mode: identify with the criterion the selector chose for this phase.
+template <int CH>
+__global__ __launch_bounds__(kBlock) void k_identify_learned(KArgs a, int par) {
+    __shared__ unsigned long long sh[kWaves];
+    __shared__ AppendLds L;
+    if (a.b.ctl->h.choice[par & 1] == 0) identify_body<IN_STATIC_M, 1, CH, true>(a, par, sh, L);
+    else identify_body<3, 2, CH, true>(a, par, sh, L);
 }
 
 // ---------------------------------------------------------------------------
@@ -426,7 +522,7 @@ __global__ __launch_bounds__(kBlock) void k_identify(KArgs a, int par) {
 // Round kinds: 0 = first light round of a bucket (every queued vertex inside
 // the window), 1 = later light round (vertices improved inside the window in
 // the previous round), 2 = heavy round (everything the bucket removed).
-template <int CH>
+template <int CH, bool LEARN>
 __global__ __launch_bounds__(kBlock) void k_identify_delta(KArgs a, int par) {
     Ctl *ctl = a.b.ctl;
     const int p2 = par & 1;
@@ -459,7 +555,7 @@ __global__ __launch_bounds__(kBlock) void k_identify_delta(KArgs a, int par) {
     const unsigned int b = kind == 0 ? b_now : ctl->h.win_bucket;
     unsigned long long lo, hi, delta;
     if (kind == 0) {
-        delta = a.b.deltas[b < ctl->h.n_deltas ? b : ctl->h.n_deltas - 1];
+        delta = LEARN ? ctl->h.next_delta : a.b.deltas[b < ctl->h.n_deltas ? b : ctl->h.n_deltas - 1];
         lo = (next / delta) * delta;
         hi = sadd64(lo, delta);
     } else {
@@ -472,8 +568,10 @@ __global__ __launch_bounds__(kBlock) void k_identify_delta(KArgs a, int par) {
             ctl->h.pnum[p2 ^ 1] = P + 1;
             ctl->h.phases = P + 1;
             ctl->h.rmode[p2] = kind;
+            ctl->h.s_k = settled;
             if (kind == 2) ctl->h.buckets = b + 1;
             if (kind == 0) {
+                ctl->h.fbucket = reached - settled;
                 ctl->h.win_bucket = b;
                 ctl->h.win_lo = lo;
                 ctl->h.win_hi = hi;
@@ -548,7 +646,46 @@ __global__ __launch_bounds__(kBlock) void k_identify_delta(KArgs a, int par) {
 
 // FOLDT: also fold the OUT-STATIC threshold (needed when OUT-STATIC is the
 // OUT member of the phase's criterion).
-template <int CH, bool DELTA, bool FOLDT>
+// Two-level completion ticket: the workgroup that finishes its shard last
+// takes a ticket on the shard counter; the one completing all shards is the
+// last workgroup of the kernel, and sees every other workgroup's atomics.
+__device__ __forceinline__ bool last_workgroup(Ctl *ctl, int p2) {
+    __shared__ int s_last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const int sh = my_shard();
+        const unsigned long long in_shard = (gridDim.x - sh + kShards - 1) / kShards;
+        const unsigned long long shards = gridDim.x < (unsigned)kShards ? gridDim.x : kShards;
+        bool last = false;
+        if (atomicAdd(slot_of(ctl->tick[p2], sh), 1ull) + 1 == in_shard)
+            last = atomicAdd(slot_of(ctl->tick_all[p2], 0), 1ull) + 1 == shards;
+        s_last = last;
+        if (last) __threadfence();
+    }
+    __syncthreads();
+    return s_last != 0;
+}
+
+__device__ __forceinline__ unsigned long long aload(const unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long shard_sum_all(const Sharded &s) {
+    unsigned long long t = 0;
+    for (int i = 0; i < kShards; ++i) t += aload(&s.v[i * kPad]);
+    return t;
+}
+__device__ __forceinline__ unsigned long long shard_min_all(const Sharded &s) {
+    unsigned long long t = INF64;
+    for (int i = 0; i < kShards; ++i) t = umin64(t, aload(&s.v[i * kPad]));
+    return t;
+}
+
+// FOLDT: also fold the OUT-STATIC threshold (needed when OUT-STATIC is the
+// OUT member of the phase's criterion).
+// LEARN: fold the selector's feature sums; the last workgroup evaluates the
+// selector for the next phase (or, after a heavy round, the next bucket).
+template <int CH, bool DELTA, bool FOLDT, bool LEARN>
 __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
     Ctl *ctl = a.b.ctl;
     const int p2 = par & 1, p3 = par % 3;
@@ -596,7 +733,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
             a.b.trace[P].edges = (unsigned int)s_tot_edges;
         }
     }
-    unsigned long long cmin = INF64, ctst = INF64, tried = 0, improv = 0, disc = 0, winimp = 0;
+    unsigned long long cmin = INF64, ctst = INF64, tried = 0, improv = 0, disc = 0, winimp = 0, dsum = 0, ddeg = 0;
     const uint32_t nch = s_cb[kShards];
     for (uint32_t c = blockIdx.x; c < nch; c += gridDim.x) {
         int sd = 0;  // shard of chunk c: last sd with s_cb[sd] <= c
@@ -649,9 +786,11 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
                         const unsigned int prev = atomicExch(&a.b.stamp[v], P + 1);
                         if (prev != P + 1) ++winimp;
                     }
+                    if (LEARN && !DELTA) dsum += old == INF64 ? cand : cand - old;  // mod 2^64: sum over F of d
                     if (old == INF64) {
                         a.b.st[v] = ST_F;
                         ++disc;
+                        if (LEARN && !DELTA) ddeg += a.g.rp[v + 1] - a.g.rp[v];
                     }
                 }
             }
@@ -663,8 +802,16 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
     disc = block_sum64<kWaves>(disc, sh);
     if (FOLDT) ctst = block_min64<kWaves>(ctst, sh);
     if (DELTA) winimp = block_sum64<kWaves>(winimp, sh);
+    if (LEARN && !DELTA) {
+        dsum = block_sum64<kWaves>(dsum, sh);
+        ddeg = block_sum64<kWaves>(ddeg, sh);
+    }
     if (threadIdx.x == 0) {
         const int s = my_shard();
+        if (LEARN && !DELTA) {
+            if (dsum) atomicAdd(slot_of(ctl->sumd[(p3 + 1) % 3], s), dsum);
+            if (ddeg) atomicAdd(slot_of(ctl->degsum, s), ddeg);
+        }
         if (cmin != INF64) {
             if (!DELTA) atomicMin(slot_of(ctl->minD[(p3 + 1) % 3], s), cmin);
             else atomicMin(slot_of(ctl->nextmin[(ctl->h.win_bucket + 1) & 1], s), cmin);
@@ -674,6 +821,54 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
         if (improv) atomicAdd(slot_of(ctl->improving, s), improv);
         if (disc) atomicAdd(slot_of(ctl->reached, s), disc);
         if (winimp) atomicAdd(slot_of(ctl->win_improved[p2], s), winimp);
+    }
+    if (LEARN && (!DELTA || kind == 2)) {
+        if (!last_workgroup(ctl, p2)) return;
+        __shared__ MlpLds M;
+        __shared__ int s_go;
+        if (threadIdx.x == 0) {
+            for (int i = 0; i < kShards; ++i) {  // reset the tickets for the phase two ahead
+                ctl->tick[p2].v[i * kPad] = 0;
+                ctl->tick_all[p2].v[i * kPad] = 0;
+            }
+            const unsigned long long R = shard_sum_all(ctl->reached);
+            const unsigned long long S = ctl->h.s_k + s_tot_settled;
+            FeatIn q;
+            q.n = a.g.n;
+            q.m = a.g.m;
+            q.F = R - S;
+            q.S = S;
+            q.R = R;
+            q.Sp = s_tot_settled;
+            q.Wm = a.wm;
+            if (!DELTA) {
+                q.a = shard_min_all(ctl->minD[(p3 + 1) % 3]);
+                q.t = shard_min_all(ctl->tst[(p3 + 1) % 3]);
+                q.SD = shard_sum_all(ctl->sumd[(p3 + 1) % 3]);
+                q.DG = shard_sum_all(ctl->degsum) - (ctl->h.m_k + s_tot_edges);
+                q.Fp = ctl->h.fk;
+                q.Ip = shard_sum_all(ctl->nin[p2]);
+                q.Op = shard_sum_all(ctl->nout[p2]);
+                q.k = P + 1;
+                q.delta_mode = 0;
+            } else {
+                q.a = shard_min_all(ctl->nextmin[(ctl->h.win_bucket + 1) & 1]);
+                q.t = INF64;
+                q.SD = q.DG = q.Ip = q.Op = 0;
+                q.Fp = ctl->h.fbucket;
+                q.k = ctl->h.win_bucket + 1;
+                q.delta_mode = 1;
+            }
+            s_go = q.F > 0;
+            if (q.F > 0) features_dev(q, M.x);
+        }
+        __syncthreads();
+        if (!s_go) return;  // F is empty: no next phase
+        const int c = mlp_choice_block(a.mlp_w, M, DELTA ? 3 : 0);
+        if (threadIdx.x == 0) {
+            if (DELTA) ctl->h.next_delta = 1ull << (12 + 2 * (c - 3));
+            else ctl->h.choice[p2 ^ 1] = (unsigned int)c;
+        }
     }
 }
 
@@ -819,24 +1014,30 @@ struct PhaseKernels {
 };
 
 template <int CH>
-static PhaseKernels pick_phase_ch(int in, int out, bool delta) {
+static PhaseKernels pick_phase_ch(int in, int out, bool delta, bool learn) {
     PhaseKernels k;
     if (delta) {
-        k.identify = k_identify_delta<CH>;
-        k.relax = k_relax<CH, true, false>;
+        k.identify = learn ? k_identify_delta<CH, true> : k_identify_delta<CH, false>;
+        k.relax = learn ? k_relax<CH, true, false, true> : k_relax<CH, true, false, false>;
+        return k;
+    }
+    if (learn) {
+        k.terms = k_terms_learned;
+        k.identify = k_identify_learned<CH>;
+        k.relax = k_relax<CH, false, true, true>;
         return k;
     }
     k.terms = pick_terms(in, out);
     k.identify = pick_identify<CH>(in, out);
-    k.relax = out == OUT_STATIC_M ? k_relax<CH, false, true> : k_relax<CH, false, false>;
+    k.relax = out == OUT_STATIC_M ? k_relax<CH, false, true, false> : k_relax<CH, false, false, false>;
     return k;
 }
 
-static PhaseKernels pick_phase(int chunk, int in, int out, bool delta) {
+static PhaseKernels pick_phase(int chunk, int in, int out, bool delta, bool learn) {
     switch (chunk) {
-    case 256: return pick_phase_ch<256>(in, out, delta);
-    case 1024: return pick_phase_ch<1024>(in, out, delta);
-    default: return pick_phase_ch<512>(in, out, delta);
+    case 256: return pick_phase_ch<256>(in, out, delta, learn);
+    case 1024: return pick_phase_ch<1024>(in, out, delta, learn);
+    default: return pick_phase_ch<512>(in, out, delta, learn);
     }
 }
 
@@ -1016,13 +1217,19 @@ static int finish_stats(const sssp_graph *g, const Ctl *dctl, sssp_stats *st, ui
 static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_t crit,
                         const uint64_t *deltas, uint32_t n_deltas, uint64_t *dist_out,
                         sssp_stats *stats, uint32_t *phase_of, sssp_phase_rec *trace,
-                        uint32_t trace_cap) {
+                        uint32_t trace_cap, const sssp_selector *sel = nullptr) {
+    const bool learn = sel != nullptr;
     if (!g) return sssp_set_error(SSSP_ERR_INVALID, "graph is NULL");
     if (!dist_out) return sssp_set_error(SSSP_ERR_INVALID, "dist_out is NULL");
     if (source >= g->n) return sssp_set_error(SSSP_ERR_INVALID, "source %u >= n = %u", source, g->n);
     if (trace_cap && !trace) return sssp_set_error(SSSP_ERR_INVALID, "trace is NULL but trace_cap > 0");
     int in = IN_NONE, out = OUT_NONE;
-    if (!delta_mode) {
+    if (learn && !delta_mode) {
+        in = IN_FULL_M;  // any of the three criteria may be chosen: CSC and cursors are needed
+        out = OUT_FULL_M;
+    } else if (learn) {
+        // bucket widths come from the selector
+    } else if (!delta_mode) {
         if (crit == 0 || (crit & ~SSSP_CRIT_ALL))
             return sssp_set_error(SSSP_ERR_INVALID, "criterion 0x%x is empty or has unknown bits", crit);
         crit_modes(crit, &in, &out);
@@ -1040,6 +1247,7 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
     }
     int rc = solve_bufs_ensure(g, dyn, delta_mode);
     if (rc) return rc;
+    if (learn) n_deltas = 0;
     if (delta_mode && g->delta_cap < n_deltas) {
         sssp_free(g->b.deltas);
         g->b.deltas = nullptr;
@@ -1047,7 +1255,7 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
         g->delta_cap = n_deltas;
     }
     hipStream_t s = g->stream;
-    if (delta_mode)
+    if (delta_mode && n_deltas)
         HIP_OK(hipMemcpyAsync(g->b.deltas, deltas, n_deltas * sizeof(uint64_t), hipMemcpyHostToDevice, s));
     KArgs a;
     a.g = dev_view(g);
@@ -1057,6 +1265,8 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
     a.b.trace = nullptr;
     a.b.trace_cap = 0;
     a.crit = crit;
+    a.mlp_w = learn ? selector_device_weights(sel) : nullptr;
+    a.wm = g->m ? (double)g->sum_w / (double)g->m : 1.0;
     if (trace_cap) {
         HIP_OK(hipMalloc(&a.b.trace, (uint64_t)trace_cap * sizeof(PhaseRec)));
         a.b.trace_cap = trace_cap;
@@ -1066,7 +1276,8 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
                        dyn ? a.b.out_cur : nullptr, g->rp, (in >= IN_SIMPLE_M) ? a.b.in_cur : nullptr,
                        g->ip, delta_mode ? a.b.stamp : nullptr);
     hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(64), 0, s, a.b.ctl, g->vmin, source, n_deltas);
-    const PhaseKernels K = pick_phase(g->cfg.chunk, in, out, delta_mode);
+    if (learn) hipLaunchKernelGGL(k_init_choice, dim3(1), dim3(64), 0, s, a, source, (int)delta_mode);
+    const PhaseKernels K = pick_phase(g->cfg.chunk, in, out, delta_mode, learn);
     // phases <= reachable vertices; Delta rounds <= 2 * n + light rounds bounded by n per bucket
     // Delta: light rounds per bucket <= window vertices + 1, one heavy round per bucket
     const uint64_t max_phases = delta_mode ? 4ull * g->n + 64 : (uint64_t)g->n + 2;
@@ -1143,4 +1354,16 @@ extern "C" int sssp_set_launch(sssp_graph *g, const sssp_launch_cfg *cfg) {
     g->cfg.chunk = (int)cfg->chunk;
     g->cfg.use_graph = cfg->use_graph != 0;
     return SSSP_OK;
+}
+
+extern "C" int sssp_solve_learned(sssp_graph *g, uint32_t source, const sssp_selector *sel, uint64_t *dist_out,
+                                  sssp_stats *stats, uint32_t *phase_of, sssp_phase_rec *trace, uint32_t trace_cap) {
+    if (!sel) return sssp_set_error(SSSP_ERR_INVALID, "selector is NULL");
+    return solve_common(g, source, false, 0, nullptr, 0, dist_out, stats, phase_of, trace, trace_cap, sel);
+}
+
+extern "C" int sssp_delta_step_learned(sssp_graph *g, uint32_t source, const sssp_selector *sel, uint64_t *dist_out,
+                                       sssp_stats *stats, sssp_phase_rec *trace, uint32_t trace_cap) {
+    if (!sel) return sssp_set_error(SSSP_ERR_INVALID, "selector is NULL");
+    return solve_common(g, source, true, 0, nullptr, 0, dist_out, stats, nullptr, trace, trace_cap, sel);
 }

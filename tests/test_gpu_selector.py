@@ -1,0 +1,114 @@
+"""GPU selector: forward and gradients against the CPU references, learned solves against the
+oracle's replay of the same network (weights from the oracle side), and training.
+
+Weights used for parity come from oracle/mlp_ref.py (seeded initialisation, optionally trained in
+float64 there), never from the HIP path.
+"""
+import numpy as np
+import pytest
+
+import graphgen as G
+import oracle as O
+from oracle import mlp_ref as M
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    from paper_1903_12085_amd import binding
+    binding.load()
+    return binding
+
+
+def seeded_xy(seed, n):
+    x = G.uniform01(seed, 1, n * 12).reshape(n, 12).astype(np.float32)
+    y = (G.u64_stream(seed, 2, n) % np.uint64(6)).astype(np.int32)
+    return x, y
+
+
+def test_forward_bitwise_equals_oracle_fp32(B):
+    w = M.init_params(11).astype(np.float32)
+    x, _ = seeded_xy(3, 200)
+    sel = B.Selector(w)
+    z = sel.forward(x)
+    for i in range(200):
+        _, zo = O.mlp_choice(w, x[i], 0)
+        assert np.array_equal(z[i], zo), i
+
+
+def test_gradients_match_float64_reference(B):
+    rng = np.random.default_rng(5)
+    w = (M.init_params(12) + rng.normal(0, 0.05, M.NPARAM)).astype(np.float32)
+    for n in (1, 7, 64, 300):
+        x, y = seeded_xy(10 + n, n)
+        loss, g = B.Selector(w).grad(x, y)
+        rl, rg = M.loss_and_grad(w.astype(np.float64), x.astype(np.float64), y)
+        assert abs(loss - rl) <= 1e-5 * max(1.0, abs(rl))
+        scale = np.abs(rg).max()
+        assert np.abs(g - rg).max() <= 1e-4 * scale, (n, np.abs(g - rg).max(), scale)
+
+
+def test_training_reduces_loss(B):
+    x, _ = seeded_xy(21, 4096)
+    y = ((x[:, 0] > 0.5).astype(np.int32) + 2 * (x[:, 3] > 0.5).astype(np.int32))  # learnable labels 0..3
+    sel = B.Selector(M.init_params(22).astype(np.float32))
+    l0, _ = sel.grad(x, y)
+    sel.train(x, y, epochs=40, batch=256, lr=3e-3, seed=1)
+    l1, _ = sel.grad(x, y)
+    assert l1 < 0.5 * l0
+    acc = (sel.forward(x).argmax(1) == y).mean()
+    assert acc > 0.9
+
+
+def mixed_weights(seed):
+    """Seeded weights whose phase choices vary along a solve (oracle-side, float32)."""
+    w = M.init_params(seed)
+    p = M.unpack(w)
+    p["W3"] *= 4.0
+    return M.pack(p).astype(np.float32)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4])
+def test_learned_solve_matches_oracle_replay(B, seed):
+    w = mixed_weights(seed)
+    sel = B.Selector(w)
+    seen = set()
+    for g in (G.er(3000, 8, 1, 1000, seed), G.rmat(11, 16, 1, 1 << 16, seed), G.grid(40, 37, 1, 1 << 16, seed),
+              G.random_small(60, 240, 30, seed)):
+        ref = O.phased(g, 0, 0, mlp_w=w)
+        dg = B.DeviceGraph.from_graph(g)
+        r = B.solve_learned(dg, 0, sel, phase_of=True, trace_cap=ref.phases + 4)
+        assert np.array_equal(r.dist_u64(), ref.dist), g.name
+        assert r.phases == ref.phases, (g.name, r.phases, ref.phases)
+        assert np.array_equal(r.trace["criterion"], ref.trace_crit), g.name
+        assert np.array_equal(r.phase_of.cpu().numpy().view(np.uint32), ref.phase_of), g.name
+        seen |= set(int(c) for c in ref.trace_crit)
+    assert len(seen) >= 1
+
+
+def test_learned_solve_uses_several_criteria(B):
+    # over a few seeds the oracle replay must see more than one criterion, and the GPU must agree
+    kinds = set()
+    for seed in range(5, 12):
+        w = mixed_weights(seed)
+        g = G.er(2000, 6, 1, 500, seed)
+        ref = O.phased(g, 0, 0, mlp_w=w)
+        r = B.solve_learned(B.DeviceGraph.from_graph(g), 0, B.Selector(w), trace_cap=ref.phases + 4)
+        assert r.phases == ref.phases and np.array_equal(r.trace["criterion"], ref.trace_crit)
+        kinds |= set(int(c) for c in ref.trace_crit)
+    assert len(kinds) >= 2
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_learned_delta_matches_oracle_replay(B, seed):
+    w = mixed_weights(seed + 40)
+    sel = B.Selector(w)
+    for g in (G.er(4000, 8, 1, 1 << 16, seed), G.grid(30, 30, 1, 1 << 16, seed)):
+        ref = O.delta_step(g, 0, None, mlp_w=w, trace_cap=1 << 16)
+        r = B.delta_step_learned(B.DeviceGraph.from_graph(g), 0, sel)
+        assert np.array_equal(r.dist_u64(), ref.dist)
+        assert r.phases == ref.rounds and r.stats["buckets"] == ref.buckets
