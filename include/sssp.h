@@ -199,7 +199,7 @@ typedef struct {
     uint32_t phases;       /* non-empty phases (or rounds) that were timed */
     float term_ms;         /* total time of the dynamic-term pass kernels */
     float identify_ms;     /* total time of the identify kernels */
-    float relax_ms;        /* total time of the relax kernels */
+    float relax_ms;        /* total time of the relax kernels (learned mode: plus the selector) */
 } sssp_kernel_profile;
 
 /* Turn per-kernel event timing on (enable != 0) or off for later solves on g. */
@@ -251,12 +251,12 @@ int sssp_autotune_batch(sssp_graph *const *graphs, const uint32_t *sources, uint
  * (outputs 3..5: 2^12, 2^14, 2^16). Every criterion is sound (Section 3), so a
  * choice changes work and phase count, never a distance.
  * Features (12 floats, each a ratio of exact integers computed in double and
- * rounded once): F/n, S/n, Sp/Fp, min(k,4096)/4096, min((t-a)/Wm,64)/64,
+ * rounded once): F/n, S/n, Sp/Fp, min(F/2^22,4)/4, min((t-a)/Wm,64)/64,
  * min(max((SD/F-a)/Wm,0),256)/256, min((DG/F)/(m/n),8)/8, Ip/Fp, Op/Fp,
  * min(F/Fp,4)/4, (n-R)/n, min(a/Wm,4096)/4096 -- F, S, R: queued, settled,
  * reached; a: minD; t: OUT-STATIC threshold; SD, DG: sums over F of d and of
  * out-degree; Fp, Sp, Ip, Op: previous |F|, |S'|, and previous queued vertices
- * passing IN-STATIC / OUT-STATIC; k: phase index; Wm: mean weight. For
+ * passing IN-STATIC / OUT-STATIC; Wm: mean weight. For
  * Delta-stepping (at bucket starts) the 5th to 10th features are 0.
  * Weights: 5382 floats, W1[64][12] b1[64] W2[64][64] b2[64] W3[6][64] b3[6].
  */
@@ -293,6 +293,19 @@ int sssp_solve_learned(sssp_graph *g, uint32_t source, const sssp_selector *sel,
 /* Delta-stepping whose bucket width is chosen per bucket by the selector. */
 int sssp_delta_step_learned(sssp_graph *g, uint32_t source, const sssp_selector *sel, uint64_t *dist_out,
                             sssp_stats *stats, sssp_phase_rec *trace, uint32_t trace_cap);
+
+/*
+ * Training traces from the solver itself. delta_mode = 0: a learned phased
+ * solve that, on every phase's snapshot, also evaluates all three criteria
+ * and records how many queued vertices each certifies (counts_out[k][3],
+ * HOST) next to the phase's features (features_out[k][12], HOST); the phase
+ * still settles what the selector's choice certifies. delta_mode = 1: a
+ * learned Delta-stepping solve recording the features of every bucket start
+ * (counts_out unused). trace_cap records at most; trace as for sssp_solve_ex.
+ */
+int sssp_trace_learned(sssp_graph *g, uint32_t source, const sssp_selector *sel, int delta_mode,
+                       uint64_t *dist_out, sssp_stats *stats, uint32_t trace_cap, sssp_phase_rec *trace,
+                       float *features_out, uint32_t *counts_out);
 
 /* Human-readable description of the last error on the calling thread. */
 const char *sssp_last_error(void);

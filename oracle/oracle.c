@@ -376,8 +376,8 @@ static void out_thresholds(uint32_t want, const uint32_t *Flist, uint64_t nF, co
  *   SD, DG        sum over F of d[u], sum over F of out-degree
  *   Fp, Sp        |F| at the previous phase start and |S'| of the previous phase
  *   Ip, Op        previous-phase queued vertices passing IN-STATIC / OUT-STATIC
- *   k             0-based phase index
- * x0 = F/n; x1 = S/n; x2 = Fp ? Sp/Fp : 0; x3 = min(k,4096)/4096;
+ *   k             0-based phase index (bucket index for Delta-stepping)
+ * x0 = F/n; x1 = S/n; x2 = Fp ? Sp/Fp : 0; x3 = min(F/2^22, 4)/4;
  * x4 = t = INF ? 1 : min((t-a)/Wm, 64)/64;
  * x5 = min(max((SD/F - a)/Wm, 0), 256)/256; x6 = min((DG/F)/(m/n), 8)/8;
  * x7 = Fp ? Ip/Fp : 0; x8 = Fp ? Op/Fp : 0; x9 = Fp ? min(F/Fp, 4)/4 : 0;
@@ -412,7 +412,7 @@ static void features(const feat_in *q, float *x) {
     x[0] = (float)(F / n);
     x[1] = (float)((double)q->S / n);
     x[2] = (float)(q->Fp ? (double)q->Sp / Fp : 0.0);
-    x[3] = (float)(dmin((double)q->k, 4096.0) / 4096.0);
+    x[3] = (float)(dmin(F / 4194304.0, 4.0) / 4.0);
     x[10] = (float)((n - (double)q->R) / n);
     x[11] = (float)(dmin((double)q->a / q->Wm, 4096.0) / 4096.0);
     if (q->delta_mode) {

@@ -29,7 +29,7 @@ SYMBOLS = ["sssp_graph_create", "sssp_graph_destroy", "sssp_set_stream", "sssp_g
            "sssp_solve_batch_ex", "sssp_batch_set_config", "sssp_batch_get_config", "sssp_autotune",
            "sssp_autotune_batch", "sssp_selector_create", "sssp_selector_destroy", "sssp_selector_get_weights",
            "sssp_selector_set_weights", "sssp_selector_forward", "sssp_selector_grad", "sssp_selector_train",
-           "sssp_solve_learned", "sssp_delta_step_learned"]
+           "sssp_solve_learned", "sssp_delta_step_learned", "sssp_trace_learned"]
 
 ERRORS = {-1: "SSSP_ERR_INVALID", -2: "SSSP_ERR_OOM", -3: "SSSP_ERR_DEVICE", -4: "SSSP_ERR_UNSUPPORTED",
           -5: "SSSP_ERR_INTERNAL"}
@@ -116,6 +116,7 @@ def load(path: str = LIB_PATH):
     lib.sssp_selector_train.argtypes = [P, P, P, u32, u32, u32, ctypes.c_float, u64, f32p]
     lib.sssp_solve_learned.argtypes = [P, u32, P, P, ctypes.POINTER(Stats), P, P, u32]
     lib.sssp_delta_step_learned.argtypes = [P, u32, P, P, ctypes.POINTER(Stats), P, u32]
+    lib.sssp_trace_learned.argtypes = [P, u32, P, i, P, ctypes.POINTER(Stats), u32, P, P, P]
     lib.sssp_last_error.restype = ctypes.c_char_p
     lib.sssp_last_error.argtypes = []
     for name in SYMBOLS:
@@ -415,3 +416,19 @@ def delta_step_learned(g: DeviceGraph, source: int, sel: Selector, dist=None, tr
     if tr is not None:
         tr = tr[:min(st.phases, trace_cap)]
     return SolveResult(dist, int(st.phases), st.as_dict(), None, tr)
+
+
+def trace_learned(g: DeviceGraph, source: int, sel: Selector, delta_mode: bool = False, cap: int = 1 << 16):
+    """(result, features[k][12], counts[k][3] or None): a learned solve that records training data."""
+    dist = new_dist(g.n)
+    tr = np.zeros(cap, PHASE_REC)
+    feat = np.zeros((cap, 12), np.float32)
+    cnt = None if delta_mode else np.zeros((cap, 3), np.uint32)
+    st = Stats()
+    g._bind_stream()
+    _check(load().sssp_trace_learned(g.handle, source, sel.handle, int(delta_mode), ctypes.c_void_p(dist.data_ptr()),
+                                     ctypes.byref(st), cap, _np_ptr(tr), _np_ptr(feat), _np_ptr(cnt)))
+    k = min(st.phases, cap)
+    kb = min(st.buckets, cap) if delta_mode else k
+    res = SolveResult(dist, int(st.phases), st.as_dict(), None, tr[:k])
+    return res, feat[:kb], (None if cnt is None else cnt[:k])

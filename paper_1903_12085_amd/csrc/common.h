@@ -11,8 +11,9 @@
 #define INF32 0xFFFFFFFFu
 
 // Vertex state byte: low two bits = set membership, bit 2 = "IN test passed"
-// flag written by the dynamic-term pass for the current phase.
-enum : uint8_t { ST_U = 0, ST_F = 1, ST_S = 2, ST_R = 3, ST_SET = 3, ST_INOK = 4 };
+// flag written by the dynamic-term pass for the current phase (bit 3: the IN
+// (full) test, written only by the trace-mode term pass, which evaluates both).
+enum : uint8_t { ST_U = 0, ST_F = 1, ST_S = 2, ST_R = 3, ST_SET = 3, ST_INOK = 4, ST_INOK_FULL = 8 };
 
 // Which IN-family / OUT-family member a phase evaluates. Inside each family
 // the members are ordered by strength (X-STATIC => X-SIMPLE => (OUTWEAK =>) X,
@@ -60,6 +61,7 @@ struct alignas(128) CtlHead {
     unsigned long long m_k;         // m_reach at the start of the phase in progress
     unsigned long long fbucket;     // |F| at the start of the bucket in progress (feature input)
     unsigned long long next_delta;  // learned Delta-stepping: width of the next bucket
+    unsigned long long last_settled;// |S'| of the last phase (selector feature input)
 };
 
 // Device control block of one solve. Slots indexed by phase parity (mod 2 or
@@ -81,8 +83,9 @@ struct Ctl {
     Sharded sumd[3];                // sum over F of d (mod 2^64 while folding), by phase mod 3
     Sharded degsum;                 // sum of out-degrees of every vertex ever queued
     Sharded nin[2], nout[2];        // queued vertices passing IN-STATIC / OUT-STATIC, by phase parity
-    Sharded tick[2];                // relax workgroups finished, per shard, by phase parity
-    Sharded tick_all[2];            // shards finished (slot 0), by phase parity
+    // trace mode (training data): every criterion evaluated on every snapshot
+    Sharded tdyn2[3];               // min: OUT (full) threshold, while tdyn holds OUT-SIMPLE's
+    Sharded cnt_cf[6];              // sum: vertices each of the three criteria certifies, [parity*3 + c]
 };
 
 // Per-phase device trace record (mirrors sssp_phase_rec).
@@ -120,6 +123,8 @@ struct SolveBufs {
     unsigned long long *deltas; // Delta-stepping widths per bucket
     PhaseRec *trace;
     uint32_t trace_cap;
+    float *trace_feat;      // trace mode: selector features of each phase (bucket), [cap][12]
+    uint32_t *trace_cf;     // trace mode: vertices each criterion certifies per phase, [cap][3]
     uint32_t *phase_of;
     unsigned long long *dist;
 };
@@ -176,6 +181,31 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
         if (lane >= o) x += y;
     }
     return x;
+}
+
+// Block-wide sums of three values with one pair of barriers; results valid in thread 0.
+template <int NWAVES>
+__device__ __forceinline__ void block_sum3(unsigned long long &a, unsigned long long &b, unsigned long long &c,
+                                           unsigned long long *sh /* 3 * NWAVES */) {
+    a = wave_sum64(a);
+    b = wave_sum64(b);
+    c = wave_sum64(c);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[w] = a;
+        sh[NWAVES + w] = b;
+        sh[2 * NWAVES + w] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = b = c = 0;
+        for (int i = 0; i < NWAVES; ++i) {
+            a += sh[i];
+            b += sh[NWAVES + i];
+            c += sh[2 * NWAVES + i];
+        }
+    }
+    __syncthreads();
 }
 
 // Block-wide min of up to 16 wavefronts, result valid in thread 0.

@@ -3,7 +3,7 @@
 // Training kernels (deterministic: every sum runs in a fixed order in one
 // thread, no atomics): dense layer forward, softmax cross-entropy, weight and
 // input gradients of a dense layer, Adam. The in-solver forward pass
-// (mlp_choice_block, selector.h) uses the same sequential fmaf order as the
+// (mlp_eval, selector.h) uses the same sequential fmaf order as the
 // batch forward here, so a decision depends only on the weights and the
 // features.
 #include <algorithm>

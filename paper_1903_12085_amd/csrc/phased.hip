@@ -49,15 +49,13 @@ static __device__ const uint32_t kChoiceCrit[3] = {SSSP_IN_STATIC | SSSP_OUT_STA
 __device__ __forceinline__ unsigned long long *slot_of(Sharded &s, int i) { return &s.v[i * kPad]; }
 __device__ __forceinline__ int my_shard() { return (int)(blockIdx.x % kShards); }
 
-// Combine a sharded value within one wavefront (lane i reads slot i; lanes >=
-// kShards contribute the neutral value); every lane gets the result.
-__device__ __forceinline__ unsigned long long shard_sum_w0(Sharded &s) {
+// Slot `lane` of a sharded value (or `idle` for lanes past the last shard);
+// wave_sum64 / wave_min64 of it combines the value in every lane. A kernel
+// loads every slot it needs before the first combine, so that all those loads
+// are in flight together.
+__device__ __forceinline__ unsigned long long lane_slot(const Sharded &s, unsigned long long idle) {
     const int i = threadIdx.x & 63;
-    return wave_sum64(i < kShards ? s.v[i * kPad] : 0ull);
-}
-__device__ __forceinline__ unsigned long long shard_min_w0(Sharded &s) {
-    const int i = threadIdx.x & 63;
-    return wave_min64(i < kShards ? s.v[i * kPad] : INF64);
+    return i < kShards ? s.v[i * kPad] : idle;
 }
 // Block 0, threads < kShards: reset every slot.
 __device__ __forceinline__ void shard_fill(Sharded &s, unsigned long long x) {
@@ -108,39 +106,43 @@ __global__ void k_init_ctl(Ctl *ctl, const uint2 *__restrict__ vmin, uint32_t sr
         ctl->degsum.v[o] = 0;
         for (int k = 0; k < 2; ++k) {
             ctl->nin[k].v[o] = ctl->nout[k].v[o] = 0;
-            ctl->tick[k].v[o] = ctl->tick_all[k].v[o] = 0;
         }
+        for (int k = 0; k < 3; ++k) ctl->tdyn2[k].v[o] = INF64;
+        for (int k = 0; k < 6; ++k) ctl->cnt_cf[k].v[o] = 0;
     }
 }
 
 // Learned mode: the degree sum of the queued set starts with the source, and
 // the first phase's (or bucket's) choice comes from the features of {s}.
-__global__ void k_init_choice(KArgs a, uint32_t src, int delta_mode) {
-    __shared__ MlpLds L;
+// One wavefront.
+__global__ __launch_bounds__(64) void k_init_choice(KArgs a, uint32_t src, int delta_mode) {
     Ctl *ctl = a.b.ctl;
     const unsigned long long deg = a.g.rp[src + 1] - a.g.rp[src];
+    FeatIn q;
+    q.n = a.g.n;
+    q.m = a.g.m;
+    q.F = 1;
+    q.S = 0;
+    q.R = 1;
+    q.a = 0;
+    q.t = w64(a.g.vmin[src].y);
+    q.SD = 0;
+    q.DG = deg;
+    q.Fp = q.Sp = q.Ip = q.Op = 0;
+    q.k = 0;
+    q.Wm = a.wm;
+    q.delta_mode = delta_mode;
+    float x[kMlpIn];
+    features_dev(q, x);
+    MlpRegs W;
+    mlp_load(a.mlp_w, W);
+    const int c = mlp_eval(W, x, delta_mode ? 3 : 0);
     if (threadIdx.x == 0) {
         ctl->degsum.v[0] = deg;
-        FeatIn q;
-        q.n = a.g.n;
-        q.m = a.g.m;
-        q.F = 1;
-        q.S = 0;
-        q.R = 1;
-        q.a = 0;
-        q.t = w64(a.g.vmin[src].y);
-        q.SD = 0;
-        q.DG = deg;
-        q.Fp = q.Sp = q.Ip = q.Op = 0;
-        q.k = 0;
-        q.Wm = a.wm;
-        q.delta_mode = delta_mode;
-        features_dev(q, L.x);
-    }
-    const int c = mlp_choice_block(a.mlp_w, L, delta_mode ? 3 : 0);
-    if (threadIdx.x == 0) {
         if (delta_mode) ctl->h.next_delta = 1ull << (12 + 2 * (c - 3));
         else ctl->h.choice[0] = (unsigned int)c;
+        if (a.b.trace_feat && a.b.trace_cap)
+            for (int i = 0; i < kMlpIn; ++i) a.b.trace_feat[i] = x[i];
     }
 }
 
@@ -289,8 +291,9 @@ __device__ __forceinline__ void terms_body(const KArgs &a, int par, unsigned lon
     const int p3 = par % 3;
     __shared__ unsigned long long s_reached, s_minD;
     if (threadIdx.x < 64) {
-        const unsigned long long r = shard_sum_w0(ctl->reached);
-        const unsigned long long md = shard_min_w0(ctl->minD[p3]);
+        const unsigned long long r0 = lane_slot(ctl->reached, 0ull), m0 = lane_slot(ctl->minD[p3], INF64);
+        const unsigned long long r = wave_sum64(r0);
+        const unsigned long long md = wave_min64(m0);
         if (threadIdx.x == 0) { s_reached = r; s_minD = md; }
     }
     __syncthreads();
@@ -357,6 +360,59 @@ __device__ __forceinline__ void terms_body(const KArgs &a, int par, unsigned lon
     }
 }
 
+// Trace mode: every dynamic term of every criterion on the same snapshot.
+// IN-SIMPLE and IN (full) results go to state bits 2 and 3; OUT-SIMPLE's
+// threshold to tdyn, OUT (full)'s to tdyn2.
+__global__ __launch_bounds__(kBlock) void k_terms_trace(KArgs a, int par) {
+    __shared__ unsigned long long sh[kWaves];
+    Ctl *ctl = a.b.ctl;
+    const int p3 = par % 3;
+    const unsigned long long r0 = lane_slot(ctl->reached, 0ull), m0 = lane_slot(ctl->minD[p3], INF64);
+    const unsigned long long settled = ctl->h.settled;
+    const unsigned long long reached = wave_sum64(r0);
+    if (reached == settled) return;
+    const unsigned long long minD = wave_min64(m0);
+    unsigned long long ts = INF64, tf = INF64;
+    const uint32_t n = a.g.n;
+    for (uint32_t v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) {
+        const uint8_t s = a.b.st[v];
+        if ((s & ST_SET) != ST_F) continue;
+        const unsigned long long dv = a.b.dist[v];
+        unsigned long long ins = INF64, inf = INF64, outs = INF64, outf = INF64;
+        uint32_t cur = a.b.in_cur[v];
+        uint32_t end = a.g.ip[v + 1];
+        while (cur < end && (a.b.st[a.g.in_edges[cur].x] & ST_SET) == ST_S) ++cur;
+        a.b.in_cur[v] = cur;
+        if (cur < end) ins = a.g.in_edges[cur].y;
+        for (uint32_t e = a.g.ip[v]; e < end; ++e) {
+            const uint2 ie = a.g.in_edges[e];
+            const uint8_t sw = a.b.st[ie.x] & ST_SET;
+            if (sw == ST_F) inf = umin64(inf, ie.y);
+            else if (sw == ST_U) inf = umin64(inf, sadd64(ie.y, w64(a.g.vmin[ie.x].x)));
+        }
+        end = a.g.rp[v + 1];
+        cur = a.b.out_cur[v];
+        while (cur < end && (a.b.st[a.g.edges[cur].x] & ST_SET) == ST_S) ++cur;
+        a.b.out_cur[v] = cur;
+        if (cur < end) outs = a.g.edges[cur].y;
+        for (uint32_t e = a.g.rp[v]; e < end; ++e) {
+            const uint2 ed = a.g.edges[e];
+            const uint8_t sx = a.b.st[ed.x] & ST_SET;
+            if (sx == ST_F) outf = umin64(outf, ed.y);
+            else if (sx == ST_U) outf = umin64(outf, sadd64(ed.y, walk_nonsettled(a, ed.x)));
+        }
+        a.b.st[v] = (uint8_t)(ST_F | (dv <= sadd64(minD, ins) ? ST_INOK : 0) | (dv <= sadd64(minD, inf) ? ST_INOK_FULL : 0));
+        ts = umin64(ts, sadd64(dv, outs));
+        tf = umin64(tf, sadd64(dv, outf));
+    }
+    ts = block_min64<kWaves>(ts, sh);
+    tf = block_min64<kWaves>(tf, sh);
+    if (threadIdx.x == 0) {
+        if (ts != INF64) atomicMin(slot_of(ctl->tdyn[p3], my_shard()), ts);
+        if (tf != INF64) atomicMin(slot_of(ctl->tdyn2[p3], my_shard()), tf);
+    }
+}
+
 template <int IN, int OUT>
 __global__ __launch_bounds__(kBlock) void k_terms(KArgs a, int par) {
     __shared__ unsigned long long sh[kWaves];
@@ -380,17 +436,25 @@ __global__ __launch_bounds__(kBlock) void k_terms_learned(KArgs a, int par) {
 // then the distance / minima loads of all its queued vertices in flight at once.
 // LEARN: also count the queued vertices passing each static test, fold the
 // sum of kept distances and always fold the OUT-STATIC threshold (features).
-template <int IN, int OUT, int CH, bool LEARN>
+// TRACE: evaluate all three criteria (flags / thresholds from k_terms_trace),
+// count what each certifies, settle what the phase's chosen one certifies.
+template <int IN, int OUT, int CH, bool LEARN, bool TRACE = false>
 __device__ __forceinline__ void identify_body(const KArgs &a, int par, unsigned long long *sh, AppendLds &L) {
     Ctl *ctl = a.b.ctl;
     const int p2 = par & 1, p3 = par % 3;
     if (threadIdx.x == 0) { L.cnt = 0; L.filled = 0; L.zero = 0; }
     // every wavefront combines the sharded phase-start values itself (no block barrier)
-    const unsigned long long reached = shard_sum_w0(ctl->reached);
-    const unsigned long long minD = shard_min_w0(ctl->minD[p3]);
-    const unsigned long long T = OUT == 1 ? shard_min_w0(ctl->tst[p3]) : OUT == 2 ? shard_min_w0(ctl->tdyn[p3]) : 0ull;
+    const unsigned long long r0 = lane_slot(ctl->reached, 0ull), m0 = lane_slot(ctl->minD[p3], INF64);
+    const unsigned long long t0 = OUT == 1 ? lane_slot(ctl->tst[p3], INF64) : OUT == 2 ? lane_slot(ctl->tdyn[p3], INF64) : 0ull;
+    const unsigned long long st0 = LEARN ? lane_slot(ctl->tst[p3], INF64) : 0ull;
+    const unsigned long long si0 = TRACE ? lane_slot(ctl->tdyn[p3], INF64) : 0ull;
+    const unsigned long long sf0 = TRACE ? lane_slot(ctl->tdyn2[p3], INF64) : 0ull;
     const unsigned long long settled = ctl->h.settled;
     const unsigned int P = ctl->h.pnum[p2];
+    const unsigned int choice = TRACE ? ctl->h.choice[p2] : 0u;
+    const unsigned long long reached = wave_sum64(r0);
+    const unsigned long long minD = wave_min64(m0);
+    const unsigned long long T = OUT ? wave_min64(t0) : 0ull;
     if (reached == settled) {
         if (blockIdx.x == 0) {
             if (threadIdx.x == 0) {
@@ -430,10 +494,16 @@ __device__ __forceinline__ void identify_body(const KArgs &a, int par, unsigned 
             shard_fill(ctl->nin[p2 ^ 1], 0);
             shard_fill(ctl->nout[p2 ^ 1], 0);
         }
+        if (TRACE) {
+            shard_fill(ctl->tdyn2[(p3 + 1) % 3], INF64);
+            for (int c = 0; c < 3; ++c) shard_fill(ctl->cnt_cf[(p2 ^ 1) * 3 + c], 0);
+        }
     }
     __syncthreads();  // LDS counters initialised
-    unsigned long long fmin = INF64, ftst = INF64, fsum = 0, cin = 0, cout = 0;
-    const unsigned long long Tst = LEARN ? shard_min_w0(ctl->tst[p3]) : 0ull;
+    unsigned long long fmin = INF64, ftst = INF64, fsum = 0, cin = 0, cout = 0, cc[3] = {0, 0, 0};
+    const unsigned long long Tst = LEARN ? wave_min64(st0) : 0ull;
+    const unsigned long long Tsi = TRACE ? wave_min64(si0) : 0ull;
+    const unsigned long long Tfu = TRACE ? wave_min64(sf0) : 0ull;
     const uint32_t n = a.g.n;
     const uint32_t nq = (n + 3) / 4;
     for (uint32_t base = blockIdx.x * kBlock; base < nq; base += gridDim.x * kBlock) {
@@ -462,10 +532,20 @@ __device__ __forceinline__ void identify_body(const KArgs &a, int par, unsigned 
                     cout += dv[i] <= Tst ? 1 : 0;
                 }
                 bool ok = false;
-                if (IN == IN_DIJK) ok = dv[i] == minD;
-                else if (IN == IN_STATIC_M) ok = dv[i] <= sadd64(minD, w64(mm[i].x));
-                else if (IN == 3) ok = (s & ST_INOK) != 0;
-                if (OUT != 0) ok = ok || dv[i] <= T;
+                if (TRACE) {
+                    const bool c0 = dv[i] <= sadd64(minD, w64(mm[i].x)) || dv[i] <= Tst;
+                    const bool c1 = (s & ST_INOK) != 0 || dv[i] <= Tsi;
+                    const bool c2 = (s & ST_INOK_FULL) != 0 || dv[i] <= Tfu;
+                    cc[0] += c0;
+                    cc[1] += c1;
+                    cc[2] += c2;
+                    ok = choice == 0 ? c0 : choice == 1 ? c1 : c2;
+                } else {
+                    if (IN == IN_DIJK) ok = dv[i] == minD;
+                    else if (IN == IN_STATIC_M) ok = dv[i] <= sadd64(minD, w64(mm[i].x));
+                    else if (IN == 3) ok = (s & ST_INOK) != 0;
+                    if (OUT != 0) ok = ok || dv[i] <= T;
+                }
                 set = ok;
                 if (set) {
                     row = a.g.rp[v];
@@ -485,10 +565,14 @@ __device__ __forceinline__ void identify_body(const KArgs &a, int par, unsigned 
     fmin = block_min64<kWaves>(fmin, sh);
     if (LEARN || OUT == 1) ftst = block_min64<kWaves>(ftst, sh);
     if (LEARN) {
-        fsum = block_sum64<kWaves>(fsum, sh);
-        cin = block_sum64<kWaves>(cin, sh);
-        cout = block_sum64<kWaves>(cout, sh);
+        __shared__ unsigned long long sh3[3 * kWaves];
+        block_sum3<kWaves>(fsum, cin, cout, sh3);
     }
+    if (TRACE)
+        for (int c = 0; c < 3; ++c) {
+            cc[c] = block_sum64<kWaves>(cc[c], sh);
+            if (threadIdx.x == 0 && cc[c]) atomicAdd(slot_of(ctl->cnt_cf[p2 * 3 + c], my_shard()), cc[c]);
+        }
     if (threadIdx.x == 0) {
         if (fmin != INF64) atomicMin(slot_of(ctl->minD[(p3 + 1) % 3], my_shard()), fmin);
         if (ftst != INF64) atomicMin(slot_of(ctl->tst[(p3 + 1) % 3], my_shard()), ftst);
@@ -505,6 +589,13 @@ __global__ __launch_bounds__(kBlock) void k_identify(KArgs a, int par) {
     __shared__ unsigned long long sh[kWaves];
     __shared__ AppendLds L;
     identify_body<IN, OUT, CH, false>(a, par, sh, L);
+}
+
+template <int CH>
+__global__ __launch_bounds__(kBlock) void k_identify_trace(KArgs a, int par) {
+    __shared__ unsigned long long sh[kWaves];
+    __shared__ AppendLds L;
+    identify_body<IN_STATIC_M, 1, CH, true, true>(a, par, sh, L);
 }
 
 // Learned mode: identify with the criterion the selector chose for this phase.
@@ -531,10 +622,12 @@ __global__ __launch_bounds__(kBlock) void k_identify_delta(KArgs a, int par) {
     if (threadIdx.x == 0) { L.cnt = 0; L.filled = 0; L.zero = 0; }
     const unsigned int P = ctl->h.pnum[p2];
     const unsigned int b_now = ctl->h.buckets;
-    const unsigned long long reached = shard_sum_w0(ctl->reached);
-    const unsigned long long improved = shard_sum_w0(ctl->win_improved[p2 ^ 1]);
-    const unsigned long long next = shard_min_w0(ctl->nextmin[b_now & 1]);
+    const unsigned long long r0 = lane_slot(ctl->reached, 0ull), i0 = lane_slot(ctl->win_improved[p2 ^ 1], 0ull);
+    const unsigned long long n0 = lane_slot(ctl->nextmin[b_now & 1], INF64);
     const unsigned long long settled = ctl->h.settled;
+    const unsigned long long reached = wave_sum64(r0);
+    const unsigned long long improved = wave_sum64(i0);
+    const unsigned long long next = wave_min64(n0);
     int kind = 0;
     if (P > 0) {
         const unsigned int prev = ctl->h.rmode[p2 ^ 1];
@@ -644,29 +737,6 @@ __global__ __launch_bounds__(kBlock) void k_identify_delta(KArgs a, int par) {
 // ---------------------------------------------------------------------------
 // relax
 
-// FOLDT: also fold the OUT-STATIC threshold (needed when OUT-STATIC is the
-// OUT member of the phase's criterion).
-// Two-level completion ticket: the workgroup that finishes its shard last
-// takes a ticket on the shard counter; the one completing all shards is the
-// last workgroup of the kernel, and sees every other workgroup's atomics.
-__device__ __forceinline__ bool last_workgroup(Ctl *ctl, int p2) {
-    __shared__ int s_last;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const int sh = my_shard();
-        const unsigned long long in_shard = (gridDim.x - sh + kShards - 1) / kShards;
-        const unsigned long long shards = gridDim.x < (unsigned)kShards ? gridDim.x : kShards;
-        bool last = false;
-        if (atomicAdd(slot_of(ctl->tick[p2], sh), 1ull) + 1 == in_shard)
-            last = atomicAdd(slot_of(ctl->tick_all[p2], 0), 1ull) + 1 == shards;
-        s_last = last;
-        if (last) __threadfence();
-    }
-    __syncthreads();
-    return s_last != 0;
-}
-
 __device__ __forceinline__ unsigned long long aload(const unsigned long long *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -683,8 +753,8 @@ __device__ __forceinline__ unsigned long long shard_min_all(const Sharded &s) {
 
 // FOLDT: also fold the OUT-STATIC threshold (needed when OUT-STATIC is the
 // OUT member of the phase's criterion).
-// LEARN: fold the selector's feature sums; the last workgroup evaluates the
-// selector for the next phase (or, after a heavy round, the next bucket).
+// LEARN: also fold the selector's feature sums (sum of d and of out-degrees
+// over the queued set) for the next phase.
 template <int CH, bool DELTA, bool FOLDT, bool LEARN>
 __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
     Ctl *ctl = a.b.ctl;
@@ -728,9 +798,12 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
             ctl->h.settled += s_tot_settled;
             ctl->h.m_reach += s_tot_edges;
         }
+        ctl->h.last_settled = s_tot_settled;  // |S'| of this phase (selector feature)
         if (P < a.b.trace_cap) {
             a.b.trace[P].settled = (unsigned int)s_tot_settled;
             a.b.trace[P].edges = (unsigned int)s_tot_edges;
+            if (a.b.trace_cf && !DELTA)
+                for (int c = 0; c < 3; ++c) a.b.trace_cf[3 * P + c] = (uint32_t)shard_sum_all(ctl->cnt_cf[p2 * 3 + c]);
         }
     }
     unsigned long long cmin = INF64, ctst = INF64, tried = 0, improv = 0, disc = 0, winimp = 0, dsum = 0, ddeg = 0;
@@ -803,8 +876,9 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
     if (FOLDT) ctst = block_min64<kWaves>(ctst, sh);
     if (DELTA) winimp = block_sum64<kWaves>(winimp, sh);
     if (LEARN && !DELTA) {
-        dsum = block_sum64<kWaves>(dsum, sh);
-        ddeg = block_sum64<kWaves>(ddeg, sh);
+        __shared__ unsigned long long sh3[3 * kWaves];
+        unsigned long long unused = 0;
+        block_sum3<kWaves>(dsum, ddeg, unused, sh3);
     }
     if (threadIdx.x == 0) {
         const int s = my_shard();
@@ -822,53 +896,68 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
         if (disc) atomicAdd(slot_of(ctl->reached, s), disc);
         if (winimp) atomicAdd(slot_of(ctl->win_improved[p2], s), winimp);
     }
-    if (LEARN && (!DELTA || kind == 2)) {
-        if (!last_workgroup(ctl, p2)) return;
-        __shared__ MlpLds M;
-        __shared__ int s_go;
-        if (threadIdx.x == 0) {
-            for (int i = 0; i < kShards; ++i) {  // reset the tickets for the phase two ahead
-                ctl->tick[p2].v[i * kPad] = 0;
-                ctl->tick_all[p2].v[i * kPad] = 0;
-            }
-            const unsigned long long R = shard_sum_all(ctl->reached);
-            const unsigned long long S = ctl->h.s_k + s_tot_settled;
-            FeatIn q;
-            q.n = a.g.n;
-            q.m = a.g.m;
-            q.F = R - S;
-            q.S = S;
-            q.R = R;
-            q.Sp = s_tot_settled;
-            q.Wm = a.wm;
-            if (!DELTA) {
-                q.a = shard_min_all(ctl->minD[(p3 + 1) % 3]);
-                q.t = shard_min_all(ctl->tst[(p3 + 1) % 3]);
-                q.SD = shard_sum_all(ctl->sumd[(p3 + 1) % 3]);
-                q.DG = shard_sum_all(ctl->degsum) - (ctl->h.m_k + s_tot_edges);
-                q.Fp = ctl->h.fk;
-                q.Ip = shard_sum_all(ctl->nin[p2]);
-                q.Op = shard_sum_all(ctl->nout[p2]);
-                q.k = P + 1;
-                q.delta_mode = 0;
-            } else {
-                q.a = shard_min_all(ctl->nextmin[(ctl->h.win_bucket + 1) & 1]);
-                q.t = INF64;
-                q.SD = q.DG = q.Ip = q.Op = 0;
-                q.Fp = ctl->h.fbucket;
-                q.k = ctl->h.win_bucket + 1;
-                q.delta_mode = 1;
-            }
-            s_go = q.F > 0;
-            if (q.F > 0) features_dev(q, M.x);
-        }
-        __syncthreads();
-        if (!s_go) return;  // F is empty: no next phase
-        const int c = mlp_choice_block(a.mlp_w, M, DELTA ? 3 : 0);
-        if (threadIdx.x == 0) {
-            if (DELTA) ctl->h.next_delta = 1ull << (12 + 2 * (c - 3));
-            else ctl->h.choice[p2 ^ 1] = (unsigned int)c;
-        }
+}
+
+// ---------------------------------------------------------------------------
+// learned mode: the selector between phases
+
+// One wavefront after relax(k): features of phase k+1's start state, network,
+// choice for phase k+1 (or, after a heavy Delta round, the next bucket's width).
+template <bool DELTA>
+__global__ __launch_bounds__(64) void k_select(KArgs a, int par) {
+    Ctl *ctl = a.b.ctl;
+    const int p2 = par & 1, p3 = par % 3;
+    MlpRegs W;
+    mlp_load(a.mlp_w, W);
+    const unsigned int done = ctl->h.done, rmode = ctl->h.rmode[p2], P = ctl->h.pnum[p2];
+    const unsigned int wb = ctl->h.win_bucket;
+    const unsigned long long S = ctl->h.settled, Sp = ctl->h.last_settled, mr = ctl->h.m_reach;
+    const unsigned long long Fp = DELTA ? ctl->h.fbucket : ctl->h.fk;
+    const int q1 = (p3 + 1) % 3;
+    const unsigned long long r0 = lane_slot(ctl->reached, 0ull);
+    const unsigned long long a0 = DELTA ? lane_slot(ctl->nextmin[(wb + 1) & 1], INF64) : lane_slot(ctl->minD[q1], INF64);
+    const unsigned long long t0 = DELTA ? INF64 : lane_slot(ctl->tst[q1], INF64);
+    const unsigned long long sd0 = DELTA ? 0ull : lane_slot(ctl->sumd[q1], 0ull);
+    const unsigned long long dg0 = DELTA ? 0ull : lane_slot(ctl->degsum, 0ull);
+    const unsigned long long in0 = DELTA ? 0ull : lane_slot(ctl->nin[p2], 0ull);
+    const unsigned long long out0 = DELTA ? 0ull : lane_slot(ctl->nout[p2], 0ull);
+    if (done) return;
+    if (DELTA && rmode != 2) return;  // only after a heavy round
+    const unsigned long long R = wave_sum64(r0);
+    FeatIn q;
+    q.n = a.g.n;
+    q.m = a.g.m;
+    q.F = R - S;
+    q.S = S;
+    q.R = R;
+    q.Sp = Sp;
+    q.Wm = a.wm;
+    q.Fp = Fp;
+    q.a = wave_min64(a0);
+    if (!DELTA) {
+        q.t = wave_min64(t0);
+        q.SD = wave_sum64(sd0);
+        q.DG = wave_sum64(dg0) - mr;
+        q.Ip = wave_sum64(in0);
+        q.Op = wave_sum64(out0);
+        q.k = P + 1;
+        q.delta_mode = 0;
+    } else {
+        q.t = INF64;
+        q.SD = q.DG = q.Ip = q.Op = 0;
+        q.k = wb + 1;
+        q.delta_mode = 1;
+    }
+    if (q.F == 0) return;  // F is empty: no next phase
+    float x[kMlpIn];
+    features_dev(q, x);
+    const int c = mlp_eval(W, x, DELTA ? 3 : 0);
+    if (threadIdx.x == 0) {
+        if (DELTA) ctl->h.next_delta = 1ull << (12 + 2 * (c - 3));
+        else ctl->h.choice[p2 ^ 1] = (unsigned int)c;
+        const unsigned long long idx = q.k;
+        if (a.b.trace_feat && idx < a.b.trace_cap)
+            for (int i = 0; i < kMlpIn; ++i) a.b.trace_feat[idx * kMlpIn + i] = x[i];
     }
 }
 
@@ -1010,21 +1099,30 @@ static kfn pick_terms(int in, int out) {
 }
 
 struct PhaseKernels {
-    kfn terms = nullptr, identify = nullptr, relax = nullptr;
+    kfn terms = nullptr, identify = nullptr, relax = nullptr, select = nullptr;
 };
 
 template <int CH>
-static PhaseKernels pick_phase_ch(int in, int out, bool delta, bool learn) {
+static PhaseKernels pick_phase_ch(int in, int out, bool delta, bool learn, bool trace = false) {
     PhaseKernels k;
+    if (trace && !delta) {
+        k.terms = k_terms_trace;
+        k.identify = k_identify_trace<CH>;
+        k.relax = k_relax<CH, false, true, true>;
+        k.select = k_select<false>;
+        return k;
+    }
     if (delta) {
         k.identify = learn ? k_identify_delta<CH, true> : k_identify_delta<CH, false>;
         k.relax = learn ? k_relax<CH, true, false, true> : k_relax<CH, true, false, false>;
+        if (learn) k.select = k_select<true>;
         return k;
     }
     if (learn) {
         k.terms = k_terms_learned;
         k.identify = k_identify_learned<CH>;
         k.relax = k_relax<CH, false, true, true>;
+        k.select = k_select<false>;
         return k;
     }
     k.terms = pick_terms(in, out);
@@ -1033,11 +1131,11 @@ static PhaseKernels pick_phase_ch(int in, int out, bool delta, bool learn) {
     return k;
 }
 
-static PhaseKernels pick_phase(int chunk, int in, int out, bool delta, bool learn) {
+static PhaseKernels pick_phase(int chunk, int in, int out, bool delta, bool learn, bool trace) {
     switch (chunk) {
-    case 256: return pick_phase_ch<256>(in, out, delta, learn);
-    case 1024: return pick_phase_ch<1024>(in, out, delta, learn);
-    default: return pick_phase_ch<512>(in, out, delta, learn);
+    case 256: return pick_phase_ch<256>(in, out, delta, learn, trace);
+    case 1024: return pick_phase_ch<1024>(in, out, delta, learn, trace);
+    default: return pick_phase_ch<512>(in, out, delta, learn, trace);
     }
 }
 
@@ -1068,6 +1166,7 @@ static int run_loop_profiled(sssp_graph *g, const KArgs &a, const PhaseKernels &
             hipLaunchKernelGGL(K.identify, gs, blk, 0, s, a, par);
             HIP_OK(hipEventRecord(e[2], s));
             hipLaunchKernelGGL(K.relax, gr, blk, 0, s, a, par);
+            if (K.select) hipLaunchKernelGGL(K.select, dim3(1), dim3(64), 0, s, a, par);
             HIP_OK(hipEventRecord(e[3], s));
         }
         HIP_OK(hipGetLastError());
@@ -1126,6 +1225,7 @@ static int ensure_phase_graph(sssp_graph *g, const KArgs &a, const PhaseKernels 
         if (K.terms) hipLaunchKernelGGL(K.terms, gs, blk, 0, cs, a, par);
         hipLaunchKernelGGL(K.identify, gs, blk, 0, cs, a, par);
         hipLaunchKernelGGL(K.relax, gr, blk, 0, cs, a, par);
+        if (K.select) hipLaunchKernelGGL(K.select, dim3(1), dim3(64), 0, cs, a, par);
     }
     hipError_t e = hipStreamEndCapture(cs, &g->graph);
     if (e != hipSuccess) return sssp_set_error(SSSP_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
@@ -1161,6 +1261,7 @@ static int run_loop(sssp_graph *g, const KArgs &a, const PhaseKernels &K, uint64
                 if (K.terms) hipLaunchKernelGGL(K.terms, gs, blk, 0, s, a, par);
                 hipLaunchKernelGGL(K.identify, gs, blk, 0, s, a, par);
                 hipLaunchKernelGGL(K.relax, gr, blk, 0, s, a, par);
+                if (K.select) hipLaunchKernelGGL(K.select, dim3(1), dim3(64), 0, s, a, par);
             }
         }
         HIP_OK(hipGetLastError());
@@ -1217,8 +1318,10 @@ static int finish_stats(const sssp_graph *g, const Ctl *dctl, sssp_stats *st, ui
 static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_t crit,
                         const uint64_t *deltas, uint32_t n_deltas, uint64_t *dist_out,
                         sssp_stats *stats, uint32_t *phase_of, sssp_phase_rec *trace,
-                        uint32_t trace_cap, const sssp_selector *sel = nullptr) {
+                        uint32_t trace_cap, const sssp_selector *sel = nullptr, float *feat_host = nullptr,
+                        uint32_t *cf_host = nullptr) {
     const bool learn = sel != nullptr;
+    const bool trace_mode = learn && !delta_mode && cf_host != nullptr;
     if (!g) return sssp_set_error(SSSP_ERR_INVALID, "graph is NULL");
     if (!dist_out) return sssp_set_error(SSSP_ERR_INVALID, "dist_out is NULL");
     if (source >= g->n) return sssp_set_error(SSSP_ERR_INVALID, "source %u >= n = %u", source, g->n);
@@ -1267,9 +1370,13 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
     a.crit = crit;
     a.mlp_w = learn ? selector_device_weights(sel) : nullptr;
     a.wm = g->m ? (double)g->sum_w / (double)g->m : 1.0;
+    a.b.trace_feat = nullptr;
+    a.b.trace_cf = nullptr;
     if (trace_cap) {
         HIP_OK(hipMalloc(&a.b.trace, (uint64_t)trace_cap * sizeof(PhaseRec)));
         a.b.trace_cap = trace_cap;
+        if (feat_host) HIP_OK(hipMalloc(&a.b.trace_feat, (uint64_t)trace_cap * kMlpIn * sizeof(float)));
+        if (cf_host) HIP_OK(hipMalloc(&a.b.trace_cf, (uint64_t)trace_cap * 3 * sizeof(uint32_t)));
     }
     const int ib = (int)(((uint64_t)g->n + 255) / 256 > 8192 ? 8192 : ((uint64_t)g->n + 255) / 256);
     hipLaunchKernelGGL(k_init_state, dim3(ib), dim3(256), 0, s, g->n, source, a.b.dist, a.b.st, phase_of,
@@ -1277,7 +1384,7 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
                        g->ip, delta_mode ? a.b.stamp : nullptr);
     hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(64), 0, s, a.b.ctl, g->vmin, source, n_deltas);
     if (learn) hipLaunchKernelGGL(k_init_choice, dim3(1), dim3(64), 0, s, a, source, (int)delta_mode);
-    const PhaseKernels K = pick_phase(g->cfg.chunk, in, out, delta_mode, learn);
+    const PhaseKernels K = pick_phase(g->cfg.chunk, in, out, delta_mode, learn, trace_mode);
     // phases <= reachable vertices; Delta rounds <= 2 * n + light rounds bounded by n per bucket
     // Delta: light rounds per bucket <= window vertices + 1, one heavy round per bucket
     const uint64_t max_phases = delta_mode ? 4ull * g->n + 64 : (uint64_t)g->n + 2;
@@ -1288,7 +1395,17 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
         const uint32_t cnt = phases < trace_cap ? phases : trace_cap;
         if (cnt && hipMemcpy(trace, a.b.trace, cnt * sizeof(PhaseRec), hipMemcpyDeviceToHost) != hipSuccess)
             rc = sssp_set_error(SSSP_ERR_DEVICE, "trace copy failed");
+        const uint32_t fcnt = delta_mode ? (stats ? stats->buckets : 0) : cnt;
+        const uint32_t fc = fcnt < trace_cap ? fcnt : trace_cap;
+        if (rc == SSSP_OK && feat_host && fc &&
+            hipMemcpy(feat_host, a.b.trace_feat, (uint64_t)fc * kMlpIn * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+            rc = sssp_set_error(SSSP_ERR_DEVICE, "feature trace copy failed");
+        if (rc == SSSP_OK && cf_host && cnt &&
+            hipMemcpy(cf_host, a.b.trace_cf, (uint64_t)cnt * 3 * sizeof(uint32_t), hipMemcpyDeviceToHost) != hipSuccess)
+            rc = sssp_set_error(SSSP_ERR_DEVICE, "count trace copy failed");
     }
+    sssp_free(a.b.trace_feat);
+    sssp_free(a.b.trace_cf);
     if (a.b.trace) sssp_free(a.b.trace);
     return rc;
 }
@@ -1366,4 +1483,17 @@ extern "C" int sssp_delta_step_learned(sssp_graph *g, uint32_t source, const sss
                                        sssp_stats *stats, sssp_phase_rec *trace, uint32_t trace_cap) {
     if (!sel) return sssp_set_error(SSSP_ERR_INVALID, "selector is NULL");
     return solve_common(g, source, true, 0, nullptr, 0, dist_out, stats, nullptr, trace, trace_cap, sel);
+}
+
+extern "C" int sssp_trace_learned(sssp_graph *g, uint32_t source, const sssp_selector *sel, int delta_mode,
+                                  uint64_t *dist_out, sssp_stats *stats, uint32_t trace_cap, sssp_phase_rec *trace,
+                                  float *features_out, uint32_t *counts_out) {
+    if (!sel) return sssp_set_error(SSSP_ERR_INVALID, "selector is NULL");
+    if (!trace_cap || !trace || !features_out || (!delta_mode && !counts_out))
+        return sssp_set_error(SSSP_ERR_INVALID, "trace buffers missing");
+    sssp_stats st;
+    int rc = solve_common(g, source, delta_mode != 0, 0, nullptr, 0, dist_out, &st, nullptr, trace, trace_cap, sel,
+                          features_out, delta_mode ? nullptr : counts_out);
+    if (stats) *stats = st;
+    return rc;
 }

@@ -4,7 +4,7 @@
 // Features: twelve ratios of exact integers, each evaluated in double
 // precision in the order written and rounded to float once:
 //   x0 = F/n              x1 = S/n                 x2 = Fp ? Sp/Fp : 0
-//   x3 = min(k,4096)/4096 x4 = t inf ? 1 : min((t-a)/Wm, 64)/64
+//   x3 = min(F/2^22,4)/4  x4 = t inf ? 1 : min((t-a)/Wm, 64)/64
 //   x5 = min(max((SD/F - a)/Wm, 0), 256)/256       x6 = min((DG/F)/(m/n), 8)/8
 //   x7 = Fp ? Ip/Fp : 0   x8 = Fp ? Op/Fp : 0      x9 = Fp ? min(F/Fp, 4)/4 : 0
 //   x10 = (n-R)/n         x11 = min(a/Wm, 4096)/4096
@@ -34,13 +34,13 @@ struct FeatIn {
 __device__ __forceinline__ double fdmin(double x, double y) { return x < y ? x : y; }
 __device__ __forceinline__ double fdmax(double x, double y) { return x > y ? x : y; }
 
-__device__ __noinline__ void features_dev(const FeatIn &q, float *x) {
+__device__ __forceinline__ void features_dev(const FeatIn &q, float *x) {
 #pragma clang fp contract(off)
     const double n = (double)q.n, m = (double)q.m, F = (double)q.F, Fp = (double)q.Fp;
     x[0] = (float)(F / n);
     x[1] = (float)((double)q.S / n);
     x[2] = (float)(q.Fp ? (double)q.Sp / Fp : 0.0);
-    x[3] = (float)(fdmin((double)q.k, 4096.0) / 4096.0);
+    x[3] = (float)(fdmin(F / 4194304.0, 4.0) / 4.0);
     x[10] = (float)((n - (double)q.R) / n);
     x[11] = (float)(fdmin((double)q.a / q.Wm, 4096.0) / 4096.0);
     if (q.delta_mode) {
@@ -55,47 +55,77 @@ __device__ __noinline__ void features_dev(const FeatIn &q, float *x) {
     x[9] = (float)(q.Fp ? fdmin(F / Fp, 4.0) / 4.0 : 0.0);
 }
 
-struct MlpLds {
-    float x[kMlpIn];
-    float h1[kMlpH];
-    float h2[kMlpH];
-    float z[kMlpOut];
-    int choice;
+// One wavefront evaluates the network. Lane j loads row j of W1 and W2 and
+// row min(j,5) of W3 with 16-byte loads, all issued before any arithmetic,
+// and hidden activations reach every lane through readlane, so there is no
+// LDS traffic and no barrier. x must be the same in every lane. Returns the
+// argmax of outputs [lo, lo+3) in every lane.
+constexpr int kOffB1 = kMlpH * kMlpIn, kOffW2 = kOffB1 + kMlpH, kOffB2 = kOffW2 + kMlpH * kMlpH;
+constexpr int kOffW3 = kOffB2 + kMlpH, kOffB3 = kOffW3 + kMlpOut * kMlpH;
+static_assert(kOffW2 % 4 == 0 && kOffW3 % 4 == 0 && kMlpIn % 4 == 0, "16-byte aligned weight rows");
+
+__device__ __forceinline__ float bcast(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+struct MlpRegs {
+    float4 w1[kMlpIn / 4], w2[kMlpH / 4], w3[kMlpH / 4];
+    float c1, c2, c3;
 };
 
-// Called by every thread of one workgroup (>= 64 threads) after thread 0 has
-// written L.x; returns the argmax of outputs [lo, lo+3) to every thread.
-__device__ __forceinline__ int mlp_choice_block(const float *__restrict__ w, MlpLds &L, int lo) {
-    const float *W1 = w, *b1 = W1 + kMlpH * kMlpIn, *W2 = b1 + kMlpH, *b2 = W2 + kMlpH * kMlpH;
-    const float *W3 = b2 + kMlpH, *b3 = W3 + kMlpOut * kMlpH;
-    const int j = threadIdx.x;
-    __syncthreads();
-    if (j < kMlpH) {
-        float acc = b1[j];
-        for (int i = 0; i < kMlpIn; ++i) acc = fmaf(W1[j * kMlpIn + i], L.x[i], acc);
-        L.h1[j] = acc > 0.0f ? acc : 0.0f;
+// Issues every weight load of this lane (no waits): call it before other
+// loads so that all of them are in flight together.
+__device__ __forceinline__ void mlp_load(const float *__restrict__ w, MlpRegs &R) {
+    const int j = threadIdx.x & 63;
+    const int o = j < kMlpOut ? j : kMlpOut - 1;
+    const float4 *r1 = reinterpret_cast<const float4 *>(w + j * kMlpIn);
+    const float4 *r2 = reinterpret_cast<const float4 *>(w + kOffW2 + j * kMlpH);
+    const float4 *r3 = reinterpret_cast<const float4 *>(w + kOffW3 + o * kMlpH);
+#pragma unroll
+    for (int i = 0; i < kMlpIn / 4; ++i) R.w1[i] = r1[i];
+#pragma unroll
+    for (int i = 0; i < kMlpH / 4; ++i) R.w2[i] = r2[i];
+#pragma unroll
+    for (int i = 0; i < kMlpH / 4; ++i) R.w3[i] = r3[i];
+    R.c1 = w[kOffB1 + j];
+    R.c2 = w[kOffB2 + j];
+    R.c3 = w[kOffB3 + o];
+}
+
+__device__ __forceinline__ int mlp_eval(const MlpRegs &R, const float *x, int lo) {
+    float acc = R.c1;
+#pragma unroll
+    for (int i = 0; i < kMlpIn / 4; ++i) {
+        acc = fmaf(R.w1[i].x, x[4 * i], acc);
+        acc = fmaf(R.w1[i].y, x[4 * i + 1], acc);
+        acc = fmaf(R.w1[i].z, x[4 * i + 2], acc);
+        acc = fmaf(R.w1[i].w, x[4 * i + 3], acc);
     }
-    __syncthreads();
-    if (j < kMlpH) {
-        float acc = b2[j];
-        for (int i = 0; i < kMlpH; ++i) acc = fmaf(W2[j * kMlpH + i], L.h1[i], acc);
-        L.h2[j] = acc > 0.0f ? acc : 0.0f;
+    const float h1 = acc > 0.0f ? acc : 0.0f;
+    acc = R.c2;
+#pragma unroll
+    for (int i = 0; i < kMlpH / 4; ++i) {
+        acc = fmaf(R.w2[i].x, bcast(h1, 4 * i), acc);
+        acc = fmaf(R.w2[i].y, bcast(h1, 4 * i + 1), acc);
+        acc = fmaf(R.w2[i].z, bcast(h1, 4 * i + 2), acc);
+        acc = fmaf(R.w2[i].w, bcast(h1, 4 * i + 3), acc);
     }
-    __syncthreads();
-    if (j < kMlpOut) {
-        float acc = b3[j];
-        for (int i = 0; i < kMlpH; ++i) acc = fmaf(W3[j * kMlpH + i], L.h2[i], acc);
-        L.z[j] = acc;
+    const float h2 = acc > 0.0f ? acc : 0.0f;
+    acc = R.c3;  // lane o < 6: output o
+#pragma unroll
+    for (int i = 0; i < kMlpH / 4; ++i) {
+        acc = fmaf(R.w3[i].x, bcast(h2, 4 * i), acc);
+        acc = fmaf(R.w3[i].y, bcast(h2, 4 * i + 1), acc);
+        acc = fmaf(R.w3[i].z, bcast(h2, 4 * i + 2), acc);
+        acc = fmaf(R.w3[i].w, bcast(h2, 4 * i + 3), acc);
     }
-    __syncthreads();
-    if (j == 0) {
-        int best = lo;
-        for (int c = lo + 1; c < lo + 3; ++c)
-            if (L.z[c] > L.z[best]) best = c;
-        L.choice = best;
-    }
-    __syncthreads();
-    return L.choice;
+    float z[kMlpOut];
+#pragma unroll
+    for (int c = 0; c < kMlpOut; ++c) z[c] = bcast(acc, c);
+    int best = lo;
+    for (int c = lo + 1; c < lo + 3; ++c)
+        if (z[c] > z[best]) best = c;
+    return best;
 }
 
 struct sssp_selector;

@@ -112,3 +112,27 @@ def test_learned_delta_matches_oracle_replay(B, seed):
         r = B.delta_step_learned(B.DeviceGraph.from_graph(g), 0, sel)
         assert np.array_equal(r.dist_u64(), ref.dist)
         assert r.phases == ref.rounds and r.stats["buckets"] == ref.buckets
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_trace_mode_counts_and_features_match_oracle(B, seed):
+    """Training traces: per phase, how many queued vertices each criterion certifies on the same
+    snapshot, and the features, equal the oracle's check-mode evaluation of the same trajectory."""
+    w = mixed_weights(seed + 20)
+    sel = B.Selector(w)
+    for g in (G.er(2500, 8, 1, 1000, seed), G.rmat(11, 16, 1, 1 << 16, seed), G.grid(25, 30, 1, 1 << 16, seed)):
+        ref = O.phased(g, 0, 0, mlp_w=w, check=True)
+        r, feat, cnt = B.trace_learned(B.DeviceGraph.from_graph(g), 0, sel, cap=ref.phases + 4)
+        assert np.array_equal(r.dist_u64(), ref.dist) and r.phases == ref.phases
+        assert np.array_equal(r.trace["criterion"], ref.trace_crit)
+        assert np.array_equal(cnt, ref.trace_union), g.name
+        assert np.array_equal(feat, ref.trace_feat), g.name
+
+
+def test_trace_mode_delta_features_match_oracle(B):
+    w = mixed_weights(31)
+    g = G.er(3000, 8, 1, 1 << 16, 3)
+    ref = O.delta_step(g, 0, None, mlp_w=w, trace_cap=1 << 12)
+    r, feat, _ = B.trace_learned(B.DeviceGraph.from_graph(g), 0, B.Selector(w), delta_mode=True)
+    assert r.phases == ref.rounds and feat.shape[0] == ref.buckets
+    assert np.array_equal(r.dist_u64(), ref.dist)

@@ -121,7 +121,7 @@ def python_features(g, src):
         x[0] = F / n
         x[1] = settled / n
         x[2] = Sp / Fp if Fp else 0.0
-        x[3] = min(float(k), 4096.0) / 4096.0
+        x[3] = min(F / 4194304.0, 4.0) / 4.0
         x[4] = 1.0 if t == INF else min((t - a) / Wm, 64.0) / 64.0
         x[5] = min(max((SD / F - a) / Wm, 0.0), 256.0) / 256.0
         x[6] = min((DG / F) / (m / n), 8.0) / 8.0
