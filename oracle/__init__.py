@@ -222,7 +222,7 @@ CHOICE_CRIT = [STATIC_OR, SIMPLE_OR, FULL_OR]
 
 
 def features(ints, Wm: float, delta_mode: bool = False) -> np.ndarray:
-    """The 12 selector features of one state; ints = (n m F S R a t SD DG Fp Sp Ip Op k)."""
+    """The 12 selector features of one state; ints = (n m F S R a t SD DG Fp D Sp Ip Op k)."""
     a = np.ascontiguousarray(ints, np.uint64)
     x = np.zeros(12, np.float32)
     _L().orc_features(_p(a), float(Wm), int(delta_mode), _p(x))

@@ -368,23 +368,30 @@ static void out_thresholds(uint32_t want, const uint32_t *Flist, uint64_t nF, co
 /* ------------------------------------------------------------------------ */
 /* Learned per-phase selector: features and FP32 forward pass.               */
 /*
- * Twelve features of the phase-start state, each a ratio of exact integers
- * evaluated in double precision in the order written, then rounded to float:
+ * Twelve features of a snapshot of the solver state and of the outcome of the
+ * last criterion evaluation, each a ratio of exact integers evaluated in
+ * double precision in the order written, then rounded to float:
  *   n, m          vertices, edges;  Wm = (sum of weights) / m (1 if m = 0)
- *   F, S, R       |F|, settled, reached (= F + S)
+ *   F, S, R       |F|, settled, reached (= F + S) at the snapshot
  *   a, t          minD and the OUT-STATIC threshold min_{u in F} d[u] (+) minOut[u]
  *   SD, DG        sum over F of d[u], sum over F of out-degree
- *   Fp, Sp        |F| at the previous phase start and |S'| of the previous phase
- *   Ip, Op        previous-phase queued vertices passing IN-STATIC / OUT-STATIC
- *   k             0-based phase index (bucket index for Delta-stepping)
- * x0 = F/n; x1 = S/n; x2 = Fp ? Sp/Fp : 0; x3 = min(F/2^22, 4)/4;
+ *   Fp            |F| at the previous snapshot
+ *   D, Sp, Ip, Op queued vertices the last evaluation ran over, how many it
+ *                 settled, and how many of them pass IN-STATIC / OUT-STATIC
+ *   k             index of the phase (bucket) the choice is for
+ * x0 = F/n; x1 = S/n; x2 = D ? Sp/D : 0; x3 = min(F/2^22, 4)/4;
  * x4 = t = INF ? 1 : min((t-a)/Wm, 64)/64;
  * x5 = min(max((SD/F - a)/Wm, 0), 256)/256; x6 = min((DG/F)/(m/n), 8)/8;
- * x7 = Fp ? Ip/Fp : 0; x8 = Fp ? Op/Fp : 0; x9 = Fp ? min(F/Fp, 4)/4 : 0;
+ * x7 = D ? Ip/D : 0; x8 = D ? Op/D : 0; x9 = Fp ? min(F/Fp, 4)/4 : 0;
  * x10 = (n-R)/n; x11 = min(a/Wm, 4096)/4096.
- * For Delta-stepping the state is taken at a bucket start (k = bucket index,
- * a = minD, Fp / Sp = |F| at the previous bucket start and the vertices that
- * bucket settled); x4..x9 are 0.
+ * Phased solver: the criterion of phase 0 comes from the state {s} with no
+ * evaluation yet (D = Sp = Ip = Op = Fp = 0); the criterion of phase k+1 comes
+ * from phase k's snapshot together with phase k's own outcome (D = |F_k|,
+ * Sp = |S'_k|, Fp = |F_{k-1}|), so it is known as soon as phase k has
+ * identified S'_k and can be evaluated while S'_k relaxes.
+ * Delta-stepping: the state is taken at a bucket start (a = minD, D = |F| at
+ * the previous bucket start, Sp = the vertices that bucket settled, Ip = Op =
+ * 0); x4..x9 are 0.
  * MLP: 12 -> 64 (ReLU) -> 64 (ReLU) -> 6, FP32; each neuron is its bias
  * followed by fmaf over its inputs in index order. Weights, flat: W1[64][12],
  * b1[64], W2[64][64], b2[64], W3[6][64], b3[6] (5382 floats). The phased
@@ -399,7 +406,7 @@ static void out_thresholds(uint32_t want, const uint32_t *Flist, uint64_t nF, co
 #define MLP_NPARAM (MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H + MLP_OUT * MLP_H + MLP_OUT)
 
 typedef struct {
-    uint64_t n, m, F, S, R, a, t, SD, DG, Fp, Sp, Ip, Op, k;
+    uint64_t n, m, F, S, R, a, t, SD, DG, Fp, D, Sp, Ip, Op, k;
     double Wm;
     int delta_mode;
 } feat_in;
@@ -408,10 +415,10 @@ static double dmin(double x, double y) { return x < y ? x : y; }
 static double dmax(double x, double y) { return x > y ? x : y; }
 
 static void features(const feat_in *q, float *x) {
-    const double n = (double)q->n, m = (double)q->m, F = (double)q->F, Fp = (double)q->Fp;
+    const double n = (double)q->n, m = (double)q->m, F = (double)q->F, Fp = (double)q->Fp, D = (double)q->D;
     x[0] = (float)(F / n);
     x[1] = (float)((double)q->S / n);
-    x[2] = (float)(q->Fp ? (double)q->Sp / Fp : 0.0);
+    x[2] = (float)(q->D ? (double)q->Sp / D : 0.0);
     x[3] = (float)(dmin(F / 4194304.0, 4.0) / 4.0);
     x[10] = (float)((n - (double)q->R) / n);
     x[11] = (float)(dmin((double)q->a / q->Wm, 4096.0) / 4096.0);
@@ -422,8 +429,8 @@ static void features(const feat_in *q, float *x) {
     x[4] = (float)(q->t == INF ? 1.0 : dmin((double)(q->t - q->a) / q->Wm, 64.0) / 64.0);
     x[5] = (float)(dmin(dmax(((double)q->SD / F - (double)q->a) / q->Wm, 0.0), 256.0) / 256.0);
     x[6] = (float)(dmin(((double)q->DG / F) / (m / n), 8.0) / 8.0);
-    x[7] = (float)(q->Fp ? (double)q->Ip / Fp : 0.0);
-    x[8] = (float)(q->Fp ? (double)q->Op / Fp : 0.0);
+    x[7] = (float)(q->D ? (double)q->Ip / D : 0.0);
+    x[8] = (float)(q->D ? (double)q->Op / D : 0.0);
     x[9] = (float)(q->Fp ? dmin(F / Fp, 4.0) / 4.0 : 0.0);
 }
 
@@ -455,10 +462,10 @@ static int mlp_choice(const float *w, const float *x, int lo, float *out_logits)
 }
 
 /* Exported for tests: features of one state and the forward pass. */
-void orc_features(const uint64_t *ints /* n m F S R a t SD DG Fp Sp Ip Op k */, double Wm, int delta_mode,
+void orc_features(const uint64_t *ints /* n m F S R a t SD DG Fp D Sp Ip Op k */, double Wm, int delta_mode,
                   float *x) {
     feat_in q = {ints[0], ints[1], ints[2], ints[3], ints[4], ints[5], ints[6], ints[7], ints[8], ints[9],
-                 ints[10], ints[11], ints[12], ints[13], Wm, delta_mode};
+                 ints[10], ints[11], ints[12], ints[13], ints[14], Wm, delta_mode};
     features(&q, x);
 }
 
@@ -526,13 +533,22 @@ int orc_phased(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32
     uint64_t nF = 1;
     Fl[0] = src;
     uint32_t k = 0;
-    /* learned mode: previous-phase aggregates for the features */
-    uint64_t prevF = 0, prevS = 0, prevI = 0, prevO = 0, settled = 0;
+    /* learned mode: |F| of the previous phase and the choice for the next phase */
+    uint64_t prevF = 0, settled = 0;
+    int choice = 0;
     double Wm = 1.0;
     if (mlp_w && rp[n] > 0) {  /* exact integer weight sum, then one division */
         uint64_t sw = 0;
         for (uint64_t e = 0; e < rp[n]; ++e) sw += w[e];
         Wm = (double)sw / (double)rp[n];
+    }
+    if (mlp_w) {  /* phase 0: the state {s}, nothing evaluated yet */
+        feat_in q = {n, rp[n], 1, 0, 1, 0, w64(min_out[src]), 0, rp[src + 1] - rp[src],
+                     0, 0, 0, 0, 0, 0, Wm, 0};
+        float x[MLP_IN];
+        features(&q, x);
+        if (trace_cap && trace_feat) memcpy(trace_feat, x, sizeof x);
+        choice = mlp_choice(mlp_w, x, 0, NULL);
     }
     while (nF > 0) {
         uint32_t ck = crit_seq ? crit_seq[k < seq_len ? k : seq_len - 1] : crit;
@@ -541,18 +557,7 @@ int orc_phased(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32
         T.minD = INF;
         for (uint64_t i = 0; i < nF; ++i) T.minD = min64(T.minD, d[Fl[i]]);
         if (mlp_w) {
-            /* the phase's criterion comes from the selector evaluated on this state */
-            thresholds_t Ts;
-            Ts.minD = T.minD;
-            out_thresholds(C_OUT_STATIC, Fl, nF, rp, col, w, d, st, min_out, inner, stamp, k + 1, &Ts);
-            uint64_t SD = 0, DG = 0;
-            for (uint64_t i = 0; i < nF; ++i) { SD += d[Fl[i]]; DG += rp[Fl[i] + 1] - rp[Fl[i]]; }
-            feat_in q = {n, rp[n], nF, settled, nF + settled, T.minD, Ts.t_out_static, SD, DG, prevF, prevS, prevI,
-                         prevO, k, Wm, 0};
-            float x[MLP_IN];
-            features(&q, x);
-            if (k < trace_cap && trace_feat) memcpy(trace_feat + (uint64_t)MLP_IN * k, x, sizeof x);
-            ck = CHOICE_CRIT[mlp_choice(mlp_w, x, 0, NULL)];
+            ck = CHOICE_CRIT[choice];
             want = (check ? C_ALL : ck) | C_IN_STATIC | C_OUT_STATIC;
         }
         if (ck == 0 || (ck & ~C_ALL)) { rc = ORC_EINVAL; goto out; }
@@ -586,7 +591,18 @@ int orc_phased(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32
             if (trace_counts) memcpy(trace_counts + 8ull * k, cnt, sizeof cnt);
             if (trace_union) memcpy(trace_union + 3ull * k, uni, sizeof uni);
         }
-        prevF = nF; prevS = nS; prevI = nin; prevO = nout; settled += nS;
+        if (mlp_w) {
+            /* the selector for phase k+1, on phase k's snapshot and outcome */
+            uint64_t SD = 0, DG = 0;
+            for (uint64_t i = 0; i < nF; ++i) { SD += d[Fl[i]]; DG += rp[Fl[i] + 1] - rp[Fl[i]]; }
+            feat_in q = {n, rp[n], nF, settled, nF + settled, T.minD, T.t_out_static, SD, DG, prevF, nF, nS, nin,
+                         nout, k + 1, Wm, 0};
+            float x[MLP_IN];
+            features(&q, x);
+            if (k + 1 < trace_cap && trace_feat) memcpy(trace_feat + (uint64_t)MLP_IN * (k + 1), x, sizeof x);
+            choice = mlp_choice(mlp_w, x, 0, NULL);
+        }
+        prevF = nF; settled += nS;
         S.sum_f += nF;
         /* settle all of S' (moved to S), then relax their out-edges */
         for (uint64_t i = 0; i < nS; ++i) st[Sp[i]] = ST_S;
@@ -669,7 +685,7 @@ int orc_delta_step(uint32_t n, const uint64_t *rp, const uint32_t *col, const ui
         for (uint64_t i = 0; i < nF; ++i) minD = min64(minD, d[Fl[i]]);
         uint64_t delta;
         if (mlp_w) {
-            feat_in q = {n, rp[n], nF, settled, nF + settled, minD, INF, 0, 0, Fp, Sp, 0, 0, D.buckets, Wm, 1};
+            feat_in q = {n, rp[n], nF, settled, nF + settled, minD, INF, 0, 0, 0, Fp, Sp, 0, 0, D.buckets, Wm, 1};
             float x[MLP_IN];
             features(&q, x);
             delta = 1ull << (12 + 2 * (mlp_choice(mlp_w, x, 3, NULL) - 3));

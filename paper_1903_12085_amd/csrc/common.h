@@ -57,6 +57,8 @@ struct alignas(128) CtlHead {
     unsigned int choice[2];         // learned mode: choice index of the phase with this parity
     unsigned long long win_lo, win_hi, win_delta;
     unsigned long long fk;          // |F| at the start of the phase in progress (feature input)
+    unsigned long long fprev;       // learned mode: |F| at the start of the previous phase
+    unsigned long long dgk;         // learned mode: sum over F of out-degrees at the phase start
     unsigned long long s_k;         // settled count at the start of the phase (round) in progress
     unsigned long long m_k;         // m_reach at the start of the phase in progress
     unsigned long long fbucket;     // |F| at the start of the bucket in progress (feature input)
@@ -183,55 +185,41 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
     return x;
 }
 
-// Block-wide sums of three values with one pair of barriers; results valid in thread 0.
-template <int NWAVES>
-__device__ __forceinline__ void block_sum3(unsigned long long &a, unsigned long long &b, unsigned long long &c,
-                                           unsigned long long *sh /* 3 * NWAVES */) {
-    a = wave_sum64(a);
-    b = wave_sum64(b);
-    c = wave_sum64(c);
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        sh[w] = a;
-        sh[NWAVES + w] = b;
-        sh[2 * NWAVES + w] = c;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        a = b = c = 0;
-        for (int i = 0; i < NWAVES; ++i) {
-            a += sh[i];
-            b += sh[NWAVES + i];
-            c += sh[2 * NWAVES + i];
-        }
-    }
-    __syncthreads();
+__device__ __forceinline__ uint32_t wave_sum32(uint32_t x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
 }
 
-// Block-wide min of up to 16 wavefronts, result valid in thread 0.
-template <int NWAVES>
-__device__ __forceinline__ unsigned long long block_min64(unsigned long long x, unsigned long long *sh) {
-    x = wave_min64(x);
+// Block-wide combine of the values v[i] whose bit i is set in ACT, all in one
+// LDS round: bit i of MIN set means a minimum, else a sum; bit i of U32 set
+// means the sum over one wavefront fits in 32 bits (cheaper shuffles).
+// Results are valid in thread 0. One barrier and none after it: the caller
+// writes sh (8 * NWAVES entries) no more in this kernel.
+template <int NWAVES, unsigned ACT, unsigned MIN, unsigned U32 = 0u>
+__device__ __forceinline__ void block_reduce(unsigned long long *v, unsigned long long *sh) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        if (!((ACT >> i) & 1u)) continue;
+        if ((MIN >> i) & 1u) v[i] = wave_min64(v[i]);
+        else if ((U32 >> i) & 1u) v[i] = wave_sum32((uint32_t)v[i]);
+        else v[i] = wave_sum64(v[i]);
+    }
     const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) sh[w] = x;
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if ((ACT >> i) & 1u) sh[i * NWAVES + w] = v[i];
     __syncthreads();
-    unsigned long long r = INF64;
     if (threadIdx.x == 0)
-        for (int i = 0; i < NWAVES; ++i) r = umin64(r, sh[i]);
-    __syncthreads();
-    return r;
-}
-template <int NWAVES>
-__device__ __forceinline__ unsigned long long block_sum64(unsigned long long x, unsigned long long *sh) {
-    x = wave_sum64(x);
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) sh[w] = x;
-    __syncthreads();
-    unsigned long long r = 0;
-    if (threadIdx.x == 0)
-        for (int i = 0; i < NWAVES; ++i) r += sh[i];
-    __syncthreads();
-    return r;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            if (!((ACT >> i) & 1u)) continue;
+            for (int k = 1; k < NWAVES; ++k) {
+                const unsigned long long x = sh[i * NWAVES + k];
+                v[i] = ((MIN >> i) & 1u) ? umin64(v[i], x) : v[i] + x;
+            }
+        }
 }
 
 constexpr int kBlock = 256;          // threads per block for the phase kernels

@@ -128,7 +128,7 @@ __global__ __launch_bounds__(64) void k_init_choice(KArgs a, uint32_t src, int d
     q.t = w64(a.g.vmin[src].y);
     q.SD = 0;
     q.DG = deg;
-    q.Fp = q.Sp = q.Ip = q.Op = 0;
+    q.Fp = q.D = q.Sp = q.Ip = q.Op = 0;
     q.k = 0;
     q.Wm = a.wm;
     q.delta_mode = delta_mode;
@@ -355,7 +355,7 @@ __device__ __forceinline__ void terms_body(const KArgs &a, int par, unsigned lon
         }
     }
     if (OUT != OUT_NONE) {
-        tmin = block_min64<kWaves>(tmin, sh);
+        block_reduce<kWaves, 1u, 1u>(&tmin, sh);
         if (threadIdx.x == 0 && tmin != INF64) atomicMin(slot_of(ctl->tdyn[p3], my_shard()), tmin);
     }
 }
@@ -364,7 +364,7 @@ __device__ __forceinline__ void terms_body(const KArgs &a, int par, unsigned lon
 // IN-SIMPLE and IN (full) results go to state bits 2 and 3; OUT-SIMPLE's
 // threshold to tdyn, OUT (full)'s to tdyn2.
 __global__ __launch_bounds__(kBlock) void k_terms_trace(KArgs a, int par) {
-    __shared__ unsigned long long sh[kWaves];
+    __shared__ unsigned long long sh[8 * kWaves];
     Ctl *ctl = a.b.ctl;
     const int p3 = par % 3;
     const unsigned long long r0 = lane_slot(ctl->reached, 0ull), m0 = lane_slot(ctl->minD[p3], INF64);
@@ -405,8 +405,10 @@ __global__ __launch_bounds__(kBlock) void k_terms_trace(KArgs a, int par) {
         ts = umin64(ts, sadd64(dv, outs));
         tf = umin64(tf, sadd64(dv, outf));
     }
-    ts = block_min64<kWaves>(ts, sh);
-    tf = block_min64<kWaves>(tf, sh);
+    unsigned long long v[2] = {ts, tf};
+    block_reduce<kWaves, 3u, 3u>(v, sh);
+    ts = v[0];
+    tf = v[1];
     if (threadIdx.x == 0) {
         if (ts != INF64) atomicMin(slot_of(ctl->tdyn[p3], my_shard()), ts);
         if (tf != INF64) atomicMin(slot_of(ctl->tdyn2[p3], my_shard()), tf);
@@ -415,13 +417,13 @@ __global__ __launch_bounds__(kBlock) void k_terms_trace(KArgs a, int par) {
 
 template <int IN, int OUT>
 __global__ __launch_bounds__(kBlock) void k_terms(KArgs a, int par) {
-    __shared__ unsigned long long sh[kWaves];
+    __shared__ unsigned long long sh[8 * kWaves];
     terms_body<IN, OUT>(a, par, sh);
 }
 
 // Learned mode: the term pass of the criterion the selector chose for this phase.
 __global__ __launch_bounds__(kBlock) void k_terms_learned(KArgs a, int par) {
-    __shared__ unsigned long long sh[kWaves];
+    __shared__ unsigned long long sh[8 * kWaves];
     const unsigned int c = a.b.ctl->h.choice[par & 1];
     if (c == 1) terms_body<IN_SIMPLE_M, OUT_SIMPLE_M>(a, par, sh);
     else if (c == 2) terms_body<IN_FULL_M, OUT_FULL_M>(a, par, sh);
@@ -447,6 +449,7 @@ __device__ __forceinline__ void identify_body(const KArgs &a, int par, unsigned 
     const unsigned long long r0 = lane_slot(ctl->reached, 0ull), m0 = lane_slot(ctl->minD[p3], INF64);
     const unsigned long long t0 = OUT == 1 ? lane_slot(ctl->tst[p3], INF64) : OUT == 2 ? lane_slot(ctl->tdyn[p3], INF64) : 0ull;
     const unsigned long long st0 = LEARN ? lane_slot(ctl->tst[p3], INF64) : 0ull;
+    const unsigned long long dg0 = LEARN && blockIdx.x == 0 ? lane_slot(ctl->degsum, 0ull) : 0ull;
     const unsigned long long si0 = TRACE ? lane_slot(ctl->tdyn[p3], INF64) : 0ull;
     const unsigned long long sf0 = TRACE ? lane_slot(ctl->tdyn2[p3], INF64) : 0ull;
     const unsigned long long settled = ctl->h.settled;
@@ -467,10 +470,16 @@ __device__ __forceinline__ void identify_body(const KArgs &a, int par, unsigned 
         return;
     }
     if (blockIdx.x == 0) {
+        // learned mode: sum over F of out-degrees = degrees of all ever queued minus those settled
+        const unsigned long long dgall = LEARN ? wave_sum64(dg0) : 0ull;
         if (threadIdx.x == 0) {
             ctl->h.pnum[p2 ^ 1] = P + 1;
             ctl->h.phases = P + 1;
             ctl->h.sum_f += reached - settled;
+            if (LEARN) {
+                ctl->h.fprev = ctl->h.fk;
+                ctl->h.dgk = dgall - ctl->h.m_reach;
+            }
             ctl->h.fk = reached - settled;
             ctl->h.s_k = settled;
             ctl->h.m_k = ctl->h.m_reach;
@@ -562,17 +571,18 @@ __device__ __forceinline__ void identify_body(const KArgs &a, int par, unsigned 
         }
     }
     append_flush<CH>(a, ctl, p2, L);
-    fmin = block_min64<kWaves>(fmin, sh);
-    if (LEARN || OUT == 1) ftst = block_min64<kWaves>(ftst, sh);
-    if (LEARN) {
-        __shared__ unsigned long long sh3[3 * kWaves];
-        block_sum3<kWaves>(fsum, cin, cout, sh3);
-    }
-    if (TRACE)
-        for (int c = 0; c < 3; ++c) {
-            cc[c] = block_sum64<kWaves>(cc[c], sh);
-            if (threadIdx.x == 0 && cc[c]) atomicAdd(slot_of(ctl->cnt_cf[p2 * 3 + c], my_shard()), cc[c]);
-        }
+    // [0] fmin, [1] ftst, [2] fsum, [3] cin, [4] cout, [5..7] per-criterion counts
+    unsigned long long v[8] = {fmin, ftst, fsum, cin, cout, cc[0], cc[1], cc[2]};
+    constexpr unsigned kAct = TRACE ? 0xffu : LEARN ? 0x1fu : OUT == 1 ? 0x3u : 0x1u;
+    block_reduce<kWaves, kAct, 0x3u, 0xf8u>(v, sh);
+    fmin = v[0];
+    ftst = v[1];
+    fsum = v[2];
+    cin = v[3];
+    cout = v[4];
+    if (TRACE && threadIdx.x == 0)
+        for (int c = 0; c < 3; ++c)
+            if (v[5 + c]) atomicAdd(slot_of(ctl->cnt_cf[p2 * 3 + c], my_shard()), v[5 + c]);
     if (threadIdx.x == 0) {
         if (fmin != INF64) atomicMin(slot_of(ctl->minD[(p3 + 1) % 3], my_shard()), fmin);
         if (ftst != INF64) atomicMin(slot_of(ctl->tst[(p3 + 1) % 3], my_shard()), ftst);
@@ -586,14 +596,14 @@ __device__ __forceinline__ void identify_body(const KArgs &a, int par, unsigned 
 
 template <int IN, int OUT, int CH>
 __global__ __launch_bounds__(kBlock) void k_identify(KArgs a, int par) {
-    __shared__ unsigned long long sh[kWaves];
+    __shared__ unsigned long long sh[8 * kWaves];
     __shared__ AppendLds L;
     identify_body<IN, OUT, CH, false>(a, par, sh, L);
 }
 
 template <int CH>
 __global__ __launch_bounds__(kBlock) void k_identify_trace(KArgs a, int par) {
-    __shared__ unsigned long long sh[kWaves];
+    __shared__ unsigned long long sh[8 * kWaves];
     __shared__ AppendLds L;
     identify_body<IN_STATIC_M, 1, CH, true, true>(a, par, sh, L);
 }
@@ -601,7 +611,7 @@ __global__ __launch_bounds__(kBlock) void k_identify_trace(KArgs a, int par) {
 // Learned mode: identify with the criterion the selector chose for this phase.
 template <int CH>
 __global__ __launch_bounds__(kBlock) void k_identify_learned(KArgs a, int par) {
-    __shared__ unsigned long long sh[kWaves];
+    __shared__ unsigned long long sh[8 * kWaves];
     __shared__ AppendLds L;
     if (a.b.ctl->h.choice[par & 1] == 0) identify_body<IN_STATIC_M, 1, CH, true>(a, par, sh, L);
     else identify_body<3, 2, CH, true>(a, par, sh, L);
@@ -617,7 +627,7 @@ template <int CH, bool LEARN>
 __global__ __launch_bounds__(kBlock) void k_identify_delta(KArgs a, int par) {
     Ctl *ctl = a.b.ctl;
     const int p2 = par & 1;
-    __shared__ unsigned long long sh[kWaves];
+    __shared__ unsigned long long sh[8 * kWaves];
     __shared__ AppendLds L;
     if (threadIdx.x == 0) { L.cnt = 0; L.filled = 0; L.zero = 0; }
     const unsigned int P = ctl->h.pnum[p2];
@@ -729,7 +739,7 @@ __global__ __launch_bounds__(kBlock) void k_identify_delta(KArgs a, int par) {
     }
     append_flush<CH>(a, ctl, p2, L);
     if (kind == 2) {
-        fmin = block_min64<kWaves>(fmin, sh);
+        block_reduce<kWaves, 1u, 1u>(&fmin, sh);
         if (threadIdx.x == 0 && fmin != INF64) atomicMin(slot_of(ctl->nextmin[(b + 1) & 1], my_shard()), fmin);
     }
 }
@@ -753,8 +763,113 @@ __device__ __forceinline__ unsigned long long shard_min_all(const Sharded &s) {
 
 // FOLDT: also fold the OUT-STATIC threshold (needed when OUT-STATIC is the
 // OUT member of the phase's criterion).
+// Learned mode, block 0 of relax(k): phase k+1's criterion from phase k's
+// snapshot and outcome. Everything read here was final when relax(k) started
+// and no block of relax(k) writes it. To stay within the relax kernel's
+// register budget, lane j of wavefront w holds inputs [16w, 16w+16) of row j
+// of W2 and of row min(j,5) of W3 (loaded once the features are done), and
+// each neuron's fmaf chain passes from wavefront 0 to 3 through LDS, in the
+// same sequential order as the one-wave evaluation.
+__device__ __forceinline__ void select_next_phase(const KArgs &a, int p2, int p3, unsigned int P,
+                                                  unsigned long long nS) {
+    static_assert(kWaves * 16 == kMlpH, "four wavefronts of sixteen inputs");
+    __shared__ float s_h1[kMlpH], s_acc[kMlpH], s_h2[kMlpH], s_z[kMlpOut];
+    Ctl *ctl = a.b.ctl;
+    const float *w = a.mlp_w;
+    const int wv = threadIdx.x >> 6, j = threadIdx.x & 63, o = j < kMlpOut ? j : kMlpOut - 1;
+    float4 w2[4], w3[4];
+    const float4 *r2 = reinterpret_cast<const float4 *>(w + kOffW2 + j * kMlpH + 16 * wv);
+    const float4 *r3 = reinterpret_cast<const float4 *>(w + kOffW3 + o * kMlpH + 16 * wv);
+    if (wv == 0) {
+        const float4 *r1 = reinterpret_cast<const float4 *>(w + j * kMlpIn);
+        float4 w1[kMlpIn / 4];
+#pragma unroll
+        for (int i = 0; i < kMlpIn / 4; ++i) w1[i] = r1[i];
+        const float c1 = w[kOffB1 + j], c2 = w[kOffB2 + j], c3 = w[kOffB3 + o];
+        const unsigned long long F = ctl->h.fk, S = ctl->h.s_k, Fp = ctl->h.fprev, DG = ctl->h.dgk;
+        const unsigned long long a0 = lane_slot(ctl->minD[p3], INF64), t0 = lane_slot(ctl->tst[p3], INF64);
+        const unsigned long long sd0 = lane_slot(ctl->sumd[p3], 0ull);
+        const unsigned long long in0 = lane_slot(ctl->nin[p2], 0ull), out0 = lane_slot(ctl->nout[p2], 0ull);
+        FeatIn q;
+        q.n = a.g.n;
+        q.m = a.g.m;
+        q.F = F;
+        q.S = S;
+        q.R = F + S;
+        q.a = wave_min64(a0);
+        q.t = wave_min64(t0);
+        q.SD = wave_sum64(sd0);
+        q.DG = DG;
+        q.Fp = Fp;
+        q.D = F;
+        q.Sp = nS;
+        q.Ip = wave_sum64(in0);
+        q.Op = wave_sum64(out0);
+        q.k = P + 1ull;
+        q.Wm = a.wm;
+        q.delta_mode = 0;
+        float x[kMlpIn];
+        features_dev(q, x);
+        float acc = c1;
+#pragma unroll
+        for (int i = 0; i < kMlpIn / 4; ++i) {
+            acc = fmaf(w1[i].x, x[4 * i], acc);
+            acc = fmaf(w1[i].y, x[4 * i + 1], acc);
+            acc = fmaf(w1[i].z, x[4 * i + 2], acc);
+            acc = fmaf(w1[i].w, x[4 * i + 3], acc);
+        }
+        s_h1[j] = acc > 0.0f ? acc : 0.0f;
+        s_acc[j] = c2;
+        if (j < kMlpOut) s_z[j] = c3;
+        if (a.b.trace_feat && q.k < a.b.trace_cap && j < kMlpIn) a.b.trace_feat[q.k * kMlpIn + j] = x[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {  // W3 stays in flight during layer 2
+        w2[i] = r2[i];
+        w3[i] = r3[i];
+    }
+    for (int step = 0; step < kWaves; ++step) {  // layer 2, inputs [16 step, 16 step + 16)
+        if (wv == step) {
+            float acc = s_acc[j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                acc = fmaf(w2[i].x, s_h1[16 * step + 4 * i], acc);
+                acc = fmaf(w2[i].y, s_h1[16 * step + 4 * i + 1], acc);
+                acc = fmaf(w2[i].z, s_h1[16 * step + 4 * i + 2], acc);
+                acc = fmaf(w2[i].w, s_h1[16 * step + 4 * i + 3], acc);
+            }
+            if (step == kWaves - 1) s_h2[j] = acc > 0.0f ? acc : 0.0f;
+            else s_acc[j] = acc;
+        }
+        __syncthreads();
+    }
+    for (int step = 0; step < kWaves; ++step) {  // layer 3, lanes 0..5
+        if (wv == step && j < kMlpOut) {
+            float acc = s_z[j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                acc = fmaf(w3[i].x, s_h2[16 * step + 4 * i], acc);
+                acc = fmaf(w3[i].y, s_h2[16 * step + 4 * i + 1], acc);
+                acc = fmaf(w3[i].z, s_h2[16 * step + 4 * i + 2], acc);
+                acc = fmaf(w3[i].w, s_h2[16 * step + 4 * i + 3], acc);
+            }
+            s_z[j] = acc;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        int best = 0;
+        for (int c = 1; c < 3; ++c)
+            if (s_z[c] > s_z[best]) best = c;
+        ctl->h.choice[p2 ^ 1] = (unsigned int)best;
+    }
+}
+
 // LEARN: also fold the selector's feature sums (sum of d and of out-degrees
-// over the queued set) for the next phase.
+// over the queued set) for the next phase; in the phased solver block 0 only
+// evaluates the selector for phase k+1 and the other blocks take its share of
+// the edges.
 template <int CH, bool DELTA, bool FOLDT, bool LEARN>
 __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
     Ctl *ctl = a.b.ctl;
@@ -762,7 +877,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
     __shared__ uint32_t s_pos[CH + 1];
     __shared__ uint32_t s_start[CH + 1];
     __shared__ unsigned long long s_du[CH + 1];
-    __shared__ unsigned long long sh[kWaves];
+    __shared__ unsigned long long sh[8 * kWaves];
     __shared__ uint32_t s_ns[kShards], s_E[kShards], s_cb[kShards + 1];
     __shared__ unsigned long long s_tot_settled, s_tot_edges;
     if (threadIdx.x < 64) {
@@ -806,9 +921,16 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
                 for (int c = 0; c < 3; ++c) a.b.trace_cf[3 * P + c] = (uint32_t)shard_sum_all(ctl->cnt_cf[p2 * 3 + c]);
         }
     }
+    constexpr bool kSel = LEARN && !DELTA;
+    const bool split = kSel && gridDim.x > 1;  // block 0 selects, blocks 1.. relax
+    if (kSel && blockIdx.x == 0) {
+        select_next_phase(a, p2, p3, P, s_tot_settled);
+        if (split) return;
+    }
     unsigned long long cmin = INF64, ctst = INF64, tried = 0, improv = 0, disc = 0, winimp = 0, dsum = 0, ddeg = 0;
     const uint32_t nch = s_cb[kShards];
-    for (uint32_t c = blockIdx.x; c < nch; c += gridDim.x) {
+    const uint32_t cfirst = split ? blockIdx.x - 1 : blockIdx.x, cstep = split ? gridDim.x - 1 : gridDim.x;
+    for (uint32_t c = cfirst; c < nch; c += cstep) {
         int sd = 0;  // shard of chunk c: last sd with s_cb[sd] <= c
         while (sd + 1 < kShards && s_cb[sd + 1] <= c) ++sd;
         const uint32_t lc = c - s_cb[sd];
@@ -869,17 +991,18 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
             }
         }
     }
-    cmin = block_min64<kWaves>(cmin, sh);
-    tried = block_sum64<kWaves>(tried, sh);
-    improv = block_sum64<kWaves>(improv, sh);
-    disc = block_sum64<kWaves>(disc, sh);
-    if (FOLDT) ctst = block_min64<kWaves>(ctst, sh);
-    if (DELTA) winimp = block_sum64<kWaves>(winimp, sh);
-    if (LEARN && !DELTA) {
-        __shared__ unsigned long long sh3[3 * kWaves];
-        unsigned long long unused = 0;
-        block_sum3<kWaves>(dsum, ddeg, unused, sh3);
-    }
+    // [0] cmin, [1] ctst, [2] tried, [3] improv, [4] disc, [5] winimp, [6] dsum, [7] ddeg
+    unsigned long long v[8] = {cmin, ctst, tried, improv, disc, winimp, dsum, ddeg};
+    constexpr unsigned kAct = 0x1du | (FOLDT ? 0x2u : 0u) | (DELTA ? 0x20u : 0u) | (kSel ? 0xc0u : 0u);
+    block_reduce<kWaves, kAct, 0x3u, 0xbcu>(v, sh);
+    cmin = v[0];
+    ctst = v[1];
+    tried = v[2];
+    improv = v[3];
+    disc = v[4];
+    winimp = v[5];
+    dsum = v[6];
+    ddeg = v[7];
     if (threadIdx.x == 0) {
         const int s = my_shard();
         if (LEARN && !DELTA) {
@@ -901,28 +1024,18 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
 // ---------------------------------------------------------------------------
 // learned mode: the selector between phases
 
-// One wavefront after relax(k): features of phase k+1's start state, network,
-// choice for phase k+1 (or, after a heavy Delta round, the next bucket's width).
-template <bool DELTA>
-__global__ __launch_bounds__(64) void k_select(KArgs a, int par) {
+// Learned Delta-stepping, one wavefront after every round: after a heavy
+// round, the next bucket's width from the state at the next bucket start.
+__global__ __launch_bounds__(64) void k_select_delta(KArgs a, int par) {
     Ctl *ctl = a.b.ctl;
-    const int p2 = par & 1, p3 = par % 3;
+    const int p2 = par & 1;
     MlpRegs W;
     mlp_load(a.mlp_w, W);
-    const unsigned int done = ctl->h.done, rmode = ctl->h.rmode[p2], P = ctl->h.pnum[p2];
-    const unsigned int wb = ctl->h.win_bucket;
-    const unsigned long long S = ctl->h.settled, Sp = ctl->h.last_settled, mr = ctl->h.m_reach;
-    const unsigned long long Fp = DELTA ? ctl->h.fbucket : ctl->h.fk;
-    const int q1 = (p3 + 1) % 3;
+    const unsigned int done = ctl->h.done, rmode = ctl->h.rmode[p2], wb = ctl->h.win_bucket;
+    const unsigned long long S = ctl->h.settled, Sp = ctl->h.last_settled, Fb = ctl->h.fbucket;
     const unsigned long long r0 = lane_slot(ctl->reached, 0ull);
-    const unsigned long long a0 = DELTA ? lane_slot(ctl->nextmin[(wb + 1) & 1], INF64) : lane_slot(ctl->minD[q1], INF64);
-    const unsigned long long t0 = DELTA ? INF64 : lane_slot(ctl->tst[q1], INF64);
-    const unsigned long long sd0 = DELTA ? 0ull : lane_slot(ctl->sumd[q1], 0ull);
-    const unsigned long long dg0 = DELTA ? 0ull : lane_slot(ctl->degsum, 0ull);
-    const unsigned long long in0 = DELTA ? 0ull : lane_slot(ctl->nin[p2], 0ull);
-    const unsigned long long out0 = DELTA ? 0ull : lane_slot(ctl->nout[p2], 0ull);
-    if (done) return;
-    if (DELTA && rmode != 2) return;  // only after a heavy round
+    const unsigned long long a0 = lane_slot(ctl->nextmin[(wb + 1) & 1], INF64);
+    if (done || rmode != 2) return;  // only after a heavy round
     const unsigned long long R = wave_sum64(r0);
     FeatIn q;
     q.n = a.g.n;
@@ -930,34 +1043,22 @@ __global__ __launch_bounds__(64) void k_select(KArgs a, int par) {
     q.F = R - S;
     q.S = S;
     q.R = R;
-    q.Sp = Sp;
-    q.Wm = a.wm;
-    q.Fp = Fp;
     q.a = wave_min64(a0);
-    if (!DELTA) {
-        q.t = wave_min64(t0);
-        q.SD = wave_sum64(sd0);
-        q.DG = wave_sum64(dg0) - mr;
-        q.Ip = wave_sum64(in0);
-        q.Op = wave_sum64(out0);
-        q.k = P + 1;
-        q.delta_mode = 0;
-    } else {
-        q.t = INF64;
-        q.SD = q.DG = q.Ip = q.Op = 0;
-        q.k = wb + 1;
-        q.delta_mode = 1;
-    }
-    if (q.F == 0) return;  // F is empty: no next phase
+    q.t = INF64;
+    q.SD = q.DG = q.Ip = q.Op = q.Fp = 0;
+    q.D = Fb;
+    q.Sp = Sp;
+    q.k = wb + 1ull;
+    q.Wm = a.wm;
+    q.delta_mode = 1;
+    if (q.F == 0) return;  // F is empty: no next bucket
     float x[kMlpIn];
     features_dev(q, x);
-    const int c = mlp_eval(W, x, DELTA ? 3 : 0);
+    const int c = mlp_eval(W, x, 3);
     if (threadIdx.x == 0) {
-        if (DELTA) ctl->h.next_delta = 1ull << (12 + 2 * (c - 3));
-        else ctl->h.choice[p2 ^ 1] = (unsigned int)c;
-        const unsigned long long idx = q.k;
-        if (a.b.trace_feat && idx < a.b.trace_cap)
-            for (int i = 0; i < kMlpIn; ++i) a.b.trace_feat[idx * kMlpIn + i] = x[i];
+        ctl->h.next_delta = 1ull << (12 + 2 * (c - 3));
+        if (a.b.trace_feat && q.k < a.b.trace_cap)
+            for (int i = 0; i < kMlpIn; ++i) a.b.trace_feat[q.k * kMlpIn + i] = x[i];
     }
 }
 
@@ -1109,20 +1210,18 @@ static PhaseKernels pick_phase_ch(int in, int out, bool delta, bool learn, bool 
         k.terms = k_terms_trace;
         k.identify = k_identify_trace<CH>;
         k.relax = k_relax<CH, false, true, true>;
-        k.select = k_select<false>;
         return k;
     }
     if (delta) {
         k.identify = learn ? k_identify_delta<CH, true> : k_identify_delta<CH, false>;
         k.relax = learn ? k_relax<CH, true, false, true> : k_relax<CH, true, false, false>;
-        if (learn) k.select = k_select<true>;
+        if (learn) k.select = k_select_delta;
         return k;
     }
     if (learn) {
         k.terms = k_terms_learned;
         k.identify = k_identify_learned<CH>;
         k.relax = k_relax<CH, false, true, true>;
-        k.select = k_select<false>;
         return k;
     }
     k.terms = pick_terms(in, out);

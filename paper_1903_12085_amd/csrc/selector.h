@@ -1,18 +1,23 @@
-// Per-phase selector: features of the phase-start state and the FP32 forward
-// pass evaluated inside the solver (one workgroup). Shared by phased.hip and mlp.hip.
+// Per-phase selector: features of a solver snapshot and the FP32 forward pass
+// evaluated inside the solver by one wavefront. Shared by phased.hip and mlp.hip.
 //
 // Features: twelve ratios of exact integers, each evaluated in double
 // precision in the order written and rounded to float once:
-//   x0 = F/n              x1 = S/n                 x2 = Fp ? Sp/Fp : 0
+//   x0 = F/n              x1 = S/n                 x2 = D ? Sp/D : 0
 //   x3 = min(F/2^22,4)/4  x4 = t inf ? 1 : min((t-a)/Wm, 64)/64
 //   x5 = min(max((SD/F - a)/Wm, 0), 256)/256       x6 = min((DG/F)/(m/n), 8)/8
-//   x7 = Fp ? Ip/Fp : 0   x8 = Fp ? Op/Fp : 0      x9 = Fp ? min(F/Fp, 4)/4 : 0
+//   x7 = D ? Ip/D : 0     x8 = D ? Op/D : 0        x9 = Fp ? min(F/Fp, 4)/4 : 0
 //   x10 = (n-R)/n         x11 = min(a/Wm, 4096)/4096
 // with F = |F|, S = settled, R = reached, a = minD, t = OUT-STATIC threshold,
-// SD / DG = sum over F of d / out-degree, Fp = previous |F|, Sp = previous
-// |S'|, Ip / Op = previous-phase queued vertices passing IN-STATIC /
-// OUT-STATIC, k = phase index, Wm = (sum of weights)/m. For Delta-stepping
-// (bucket starts) x4..x9 are 0.
+// SD / DG = sum over F of d / out-degree (all at the snapshot), Fp = |F| at
+// the previous snapshot, D = queued vertices the last criterion evaluation
+// ran over, Sp / Ip / Op = how many of them it settled / pass IN-STATIC /
+// pass OUT-STATIC, k = index of the phase (bucket) the choice is for,
+// Wm = (sum of weights)/m. Phase 0's choice uses the state {s} with nothing
+// evaluated (D = Sp = Ip = Op = Fp = 0); phase k+1's uses phase k's snapshot
+// and phase k's own outcome (D = |F_k|, Sp = |S'_k|, Fp = |F_{k-1}|), so it
+// is made while S'_k relaxes. For Delta-stepping (bucket starts) D = |F| at
+// the previous bucket start, Sp = what that bucket settled, and x4..x9 are 0.
 // Network: W1[64][12] b1[64] W2[64][64] b2[64] W3[6][64] b3[6]; each neuron is
 // its bias followed by fmaf over its inputs in index order; ReLU on the two
 // hidden layers. Outputs 0..2 choose the phase criterion (IN-STATIC|OUT-STATIC,
@@ -26,7 +31,7 @@ constexpr int kMlpIn = 12, kMlpH = 64, kMlpOut = 6;
 constexpr int kMlpParams = kMlpH * kMlpIn + kMlpH + kMlpH * kMlpH + kMlpH + kMlpOut * kMlpH + kMlpOut;
 
 struct FeatIn {
-    unsigned long long n, m, F, S, R, a, t, SD, DG, Fp, Sp, Ip, Op, k;
+    unsigned long long n, m, F, S, R, a, t, SD, DG, Fp, D, Sp, Ip, Op, k;
     double Wm;
     int delta_mode;
 };
@@ -36,10 +41,10 @@ __device__ __forceinline__ double fdmax(double x, double y) { return x > y ? x :
 
 __device__ __forceinline__ void features_dev(const FeatIn &q, float *x) {
 #pragma clang fp contract(off)
-    const double n = (double)q.n, m = (double)q.m, F = (double)q.F, Fp = (double)q.Fp;
+    const double n = (double)q.n, m = (double)q.m, F = (double)q.F, Fp = (double)q.Fp, D = (double)q.D;
     x[0] = (float)(F / n);
     x[1] = (float)((double)q.S / n);
-    x[2] = (float)(q.Fp ? (double)q.Sp / Fp : 0.0);
+    x[2] = (float)(q.D ? (double)q.Sp / D : 0.0);
     x[3] = (float)(fdmin(F / 4194304.0, 4.0) / 4.0);
     x[10] = (float)((n - (double)q.R) / n);
     x[11] = (float)(fdmin((double)q.a / q.Wm, 4096.0) / 4096.0);
@@ -50,8 +55,8 @@ __device__ __forceinline__ void features_dev(const FeatIn &q, float *x) {
     x[4] = (float)(q.t == INF64 ? 1.0 : fdmin((double)(q.t - q.a) / q.Wm, 64.0) / 64.0);
     x[5] = (float)(fdmin(fdmax(((double)q.SD / F - (double)q.a) / q.Wm, 0.0), 256.0) / 256.0);
     x[6] = (float)(fdmin(((double)q.DG / F) / (m / n), 8.0) / 8.0);
-    x[7] = (float)(q.Fp ? (double)q.Ip / Fp : 0.0);
-    x[8] = (float)(q.Fp ? (double)q.Op / Fp : 0.0);
+    x[7] = (float)(q.D ? (double)q.Ip / D : 0.0);
+    x[8] = (float)(q.D ? (double)q.Op / D : 0.0);
     x[9] = (float)(q.Fp ? fdmin(F / Fp, 4.0) / 4.0 : 0.0);
 }
 

@@ -88,7 +88,8 @@ def test_learned_delta_with_constant_choice_equals_fixed_width(choice):
 
 
 def python_features(g, src):
-    """Independent re-simulation of IN-STATIC|OUT-STATIC with the feature definitions."""
+    """Independent re-simulation of IN-STATIC|OUT-STATIC with the feature definitions: row 0 is the
+    state {s} before any evaluation, row k+1 is phase k's snapshot with phase k's own outcome."""
     n, m = g.n, g.m
     rp, col, w = [int(x) for x in g.row_ptr], [int(x) for x in g.col], [int(x) for x in g.w]
     INF = O.INF_INT
@@ -99,14 +100,30 @@ def python_features(g, src):
             min_out[u] = min(min_out[u], w[e])
             min_in[col[e]] = min(min_in[col[e]], w[e])
     Wm = (float(sum(w)) / float(m)) if m else 1.0
+
+    def feat(F, S, R, a, t, SD, DG, Fp, D, Sp, Ip, Op):
+        x = [0.0] * 12
+        x[0] = F / n
+        x[1] = S / n
+        x[2] = Sp / D if D else 0.0
+        x[3] = min(F / 4194304.0, 4.0) / 4.0
+        x[4] = 1.0 if t == INF else min((t - a) / Wm, 64.0) / 64.0
+        x[5] = min(max((SD / F - a) / Wm, 0.0), 256.0) / 256.0
+        x[6] = min((DG / F) / (m / n), 8.0) / 8.0
+        x[7] = Ip / D if D else 0.0
+        x[8] = Op / D if D else 0.0
+        x[9] = min(F / Fp, 4.0) / 4.0 if Fp else 0.0
+        x[10] = (n - R) / n
+        x[11] = min(a / Wm, 4096.0) / 4096.0
+        return np.array(x, np.float64).astype(np.float32)
+
     d = [INF] * n
     st = [0] * n
     d[src] = 0
     st[src] = 1
     settled = 0
-    prev = (0, 0, 0, 0)
-    out = []
-    k = 0
+    prevF = 0
+    out = [feat(1, 0, 1, 0, min_out[src], 0, rp[src + 1] - rp[src], 0, 0, 0, 0, 0)]
     while True:
         Fs = [v for v in range(n) if st[v] == 1]
         if not Fs:
@@ -116,24 +133,10 @@ def python_features(g, src):
         t = min((d[v] + min_out[v]) if min_out[v] != INF else INF for v in Fs)
         SD = sum(d[v] for v in Fs)
         DG = sum(rp[v + 1] - rp[v] for v in Fs)
-        Fp, Sp, Ip, Op = prev
-        x = [0.0] * 12
-        x[0] = F / n
-        x[1] = settled / n
-        x[2] = Sp / Fp if Fp else 0.0
-        x[3] = min(F / 4194304.0, 4.0) / 4.0
-        x[4] = 1.0 if t == INF else min((t - a) / Wm, 64.0) / 64.0
-        x[5] = min(max((SD / F - a) / Wm, 0.0), 256.0) / 256.0
-        x[6] = min((DG / F) / (m / n), 8.0) / 8.0
-        x[7] = Ip / Fp if Fp else 0.0
-        x[8] = Op / Fp if Fp else 0.0
-        x[9] = min(F / Fp, 4.0) / 4.0 if Fp else 0.0
-        x[10] = (n - (F + settled)) / n
-        x[11] = min(a / Wm, 4096.0) / 4096.0
-        out.append(np.array(x, np.float64).astype(np.float32))
         ins = [v for v in Fs if min_in[v] == INF or d[v] <= a + min_in[v]]
         outs = [v for v in Fs if d[v] <= t]
         S = sorted(set(ins) | set(outs))
+        out.append(feat(F, settled, F + settled, a, t, SD, DG, prevF, F, len(S), len(ins), len(outs)))
         for v in S:
             st[v] = 2
         for u in S:
@@ -142,10 +145,9 @@ def python_features(g, src):
                 if st[x_] != 2 and d[u] + w[e] < d[x_]:
                     d[x_] = d[u] + w[e]
                     st[x_] = 1
-        prev = (F, len(S), len(ins), len(outs))
+        prevF = F
         settled += len(S)
-        k += 1
-    return np.array(out)
+    return np.array(out[:-1])  # the row after the last phase chooses for no phase
 
 
 def test_features_match_independent_simulation():
