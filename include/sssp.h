@@ -208,6 +208,13 @@ int sssp_profile_enable(sssp_graph *g, int enable);
 /* Read the per-kernel times of the last solve run with timing on. */
 int sssp_profile_get(const sssp_graph *g, sssp_kernel_profile *out);
 
+/* Per-phase kernel time (term pass + identify + relax, milliseconds, phase
+ * order) of the last phased solve run with timing on: *count receives the
+ * number of phases, and the first min(*count, cap) times are written to ms
+ * (host memory, caller-owned). Returns SSSP_ERR_INVALID for a NULL g or count,
+ * or a NULL ms with cap > 0. */
+int sssp_profile_phases(const sssp_graph *g, float *ms, uint32_t cap, uint32_t *count);
+
 /* Launch shape of the phase kernels of a graph (tuning; results never depend
  * on it). Defaults are chosen from n, m and the device's compute-unit count. */
 typedef struct {

@@ -25,7 +25,7 @@ FULL_OR = IN_FULL | OUT_FULL
 
 SYMBOLS = ["sssp_graph_create", "sssp_graph_destroy", "sssp_set_stream", "sssp_graph_minima", "sssp_solve",
            "sssp_solve_ex", "sssp_delta_step", "sssp_delta_step_ex", "sssp_solve_batch", "sssp_last_error",
-           "sssp_profile_enable", "sssp_profile_get", "sssp_get_launch", "sssp_set_launch",
+           "sssp_profile_enable", "sssp_profile_get", "sssp_profile_phases", "sssp_get_launch", "sssp_set_launch",
            "sssp_solve_batch_ex", "sssp_batch_set_config", "sssp_batch_get_config", "sssp_autotune",
            "sssp_autotune_batch", "sssp_selector_create", "sssp_selector_destroy", "sssp_selector_get_weights",
            "sssp_selector_set_weights", "sssp_selector_forward", "sssp_selector_grad", "sssp_selector_train",
@@ -99,6 +99,7 @@ def load(path: str = LIB_PATH):
     lib.sssp_solve_batch.argtypes = [P, P, u32, u32, P, P]
     lib.sssp_profile_enable.argtypes = [P, i]
     lib.sssp_profile_get.argtypes = [P, ctypes.POINTER(KernelProfile)]
+    lib.sssp_profile_phases.argtypes = [P, P, u32, ctypes.POINTER(ctypes.c_uint32)]
     lib.sssp_get_launch.argtypes = [P, ctypes.POINTER(LaunchCfg)]
     lib.sssp_set_launch.argtypes = [P, ctypes.POINTER(LaunchCfg)]
     lib.sssp_solve_batch_ex.argtypes = [P, P, u32, u32, P, P, ctypes.POINTER(BatchCfg)]
@@ -191,6 +192,14 @@ class DeviceGraph:
         p = KernelProfile()
         _check(load().sssp_profile_get(self._h, ctypes.byref(p)))
         return p.as_dict()
+
+    def phase_times(self) -> np.ndarray:
+        """Per-phase kernel milliseconds of the last phased solve run with profile(True)."""
+        cnt = ctypes.c_uint32(0)
+        _check(load().sssp_profile_phases(self._h, None, 0, ctypes.byref(cnt)))
+        ms = np.zeros(cnt.value, np.float32)
+        _check(load().sssp_profile_phases(self._h, _np_ptr(ms), cnt.value, ctypes.byref(cnt)))
+        return ms
 
     def launch(self) -> dict:
         c = LaunchCfg()

@@ -164,15 +164,38 @@ __device__ __forceinline__ unsigned long long umin64(unsigned long long a, unsig
     return a < b ? a : b;
 }
 
+// Wavefront reductions with DPP lane moves inside each row of 16 lanes
+// (quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror: after
+// these four steps every lane holds its row's result), then the four row
+// results are read with readlane. Every lane gets the wavefront's result.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp64(unsigned long long v) {
+    return ((unsigned long long)dpp32<CTRL>((uint32_t)(v >> 32)) << 32) | dpp32<CTRL>((uint32_t)v);
+}
+__device__ __forceinline__ unsigned long long readlane64(unsigned long long v, int lane) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return ((unsigned long long)hi << 32) | lo;
+}
+constexpr int kDppQuadSwap1 = 0xB1, kDppQuadSwap2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
 __device__ __forceinline__ unsigned long long wave_min64(unsigned long long x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x = umin64(x, __shfl_xor(x, o, 64));
-    return x;
+    x = umin64(x, dpp64<kDppQuadSwap1>(x));
+    x = umin64(x, dpp64<kDppQuadSwap2>(x));
+    x = umin64(x, dpp64<kDppHalfMirror>(x));
+    x = umin64(x, dpp64<kDppMirror>(x));
+    return umin64(umin64(readlane64(x, 0), readlane64(x, 16)), umin64(readlane64(x, 32), readlane64(x, 48)));
 }
 __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
+    x += dpp64<kDppQuadSwap1>(x);
+    x += dpp64<kDppQuadSwap2>(x);
+    x += dpp64<kDppHalfMirror>(x);
+    x += dpp64<kDppMirror>(x);
+    return (readlane64(x, 0) + readlane64(x, 16)) + (readlane64(x, 32) + readlane64(x, 48));
 }
 // Inclusive prefix sum over the 64 lanes of a wavefront.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
@@ -186,9 +209,12 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
 }
 
 __device__ __forceinline__ uint32_t wave_sum32(uint32_t x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
+    x += dpp32<kDppQuadSwap1>(x);
+    x += dpp32<kDppQuadSwap2>(x);
+    x += dpp32<kDppHalfMirror>(x);
+    x += dpp32<kDppMirror>(x);
+    return ((uint32_t)__builtin_amdgcn_readlane((int)x, 0) + (uint32_t)__builtin_amdgcn_readlane((int)x, 16)) +
+           ((uint32_t)__builtin_amdgcn_readlane((int)x, 32) + (uint32_t)__builtin_amdgcn_readlane((int)x, 48));
 }
 
 // Block-wide combine of the values v[i] whose bit i is set in ACT, all in one

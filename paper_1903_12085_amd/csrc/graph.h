@@ -1,6 +1,8 @@
 // The opaque sssp_graph handle and the helpers shared between translation units.
 #pragma once
 
+#include <vector>
+
 #include "common.h"
 
 struct sssp_graph {
@@ -28,6 +30,7 @@ struct sssp_graph {
     hipEvent_t *pev = nullptr;     // 4 events per phase of one batch
     uint32_t pev_cap = 0;
     sssp_kernel_profile last_prof{};
+    std::vector<float> phase_ms;   // per-phase kernel time of the last timed solve
     // captured phase batch (6 phases) for graph replay
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;

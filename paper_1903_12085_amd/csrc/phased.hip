@@ -595,14 +595,14 @@ __device__ __forceinline__ void identify_body(const KArgs &a, int par, unsigned 
 }
 
 template <int IN, int OUT, int CH>
-__global__ __launch_bounds__(kBlock) void k_identify(KArgs a, int par) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_identify(KArgs a, int par) {
     __shared__ unsigned long long sh[8 * kWaves];
     __shared__ AppendLds L;
     identify_body<IN, OUT, CH, false>(a, par, sh, L);
 }
 
 template <int CH>
-__global__ __launch_bounds__(kBlock) void k_identify_trace(KArgs a, int par) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_identify_trace(KArgs a, int par) {
     __shared__ unsigned long long sh[8 * kWaves];
     __shared__ AppendLds L;
     identify_body<IN_STATIC_M, 1, CH, true, true>(a, par, sh, L);
@@ -610,7 +610,7 @@ __global__ __launch_bounds__(kBlock) void k_identify_trace(KArgs a, int par) {
 
 // Learned mode: identify with the criterion the selector chose for this phase.
 template <int CH>
-__global__ __launch_bounds__(kBlock) void k_identify_learned(KArgs a, int par) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_identify_learned(KArgs a, int par) {
     __shared__ unsigned long long sh[8 * kWaves];
     __shared__ AppendLds L;
     if (a.b.ctl->h.choice[par & 1] == 0) identify_body<IN_STATIC_M, 1, CH, true>(a, par, sh, L);
@@ -1252,6 +1252,7 @@ static int run_loop_profiled(sssp_graph *g, const KArgs &a, const PhaseKernels &
         g->pev_cap = 4 * kBatch;
     }
     sssp_kernel_profile pr{};
+    g->phase_ms.clear();
     const dim3 blk(kBlock), gs(g->cfg.scan_blocks), gr(g->cfg.relax_blocks);
     uint64_t k = 0;
     for (;;) {
@@ -1282,6 +1283,7 @@ static int run_loop_profiled(sssp_graph *g, const KArgs &a, const PhaseKernels &
             pr.identify_ms += t1;
             pr.relax_ms += t2;
             pr.phases++;
+            g->phase_ms.push_back((K.terms ? t0 : 0.f) + t1 + t2);
         }
         if (g->h_ctl[0].done) break;
         if (k > max_phases + 2 * kBatch)
@@ -1547,6 +1549,14 @@ extern "C" int sssp_profile_enable(sssp_graph *g, int enable) {
 extern "C" int sssp_profile_get(const sssp_graph *g, sssp_kernel_profile *out) {
     if (!g || !out) return sssp_set_error(SSSP_ERR_INVALID, "NULL argument");
     *out = g->last_prof;
+    return SSSP_OK;
+}
+
+extern "C" int sssp_profile_phases(const sssp_graph *g, float *ms, uint32_t cap, uint32_t *count) {
+    if (!g || !count || (cap && !ms)) return sssp_set_error(SSSP_ERR_INVALID, "NULL argument");
+    const size_t k = g->phase_ms.size();
+    *count = (uint32_t)k;
+    for (size_t i = 0; i < k && i < cap; ++i) ms[i] = g->phase_ms[i];
     return SSSP_OK;
 }
 

@@ -1,15 +1,13 @@
 """Training pipeline of the per-phase selector (host logic; every solve and every training step
 runs in libsssp's HIP kernels).
 
-Data comes from the solver itself: `trace_learned` runs a phased solve under a fixed policy and, on
-every phase's snapshot, records the 12 features and how many queued vertices each of the three
-criteria (IN-STATIC|OUT-STATIC, IN-SIMPLE|OUT-SIMPLE, IN|OUT) would certify. Labels come from a cost
-model measured on the GPU: for each criterion c, a phase costs alpha_c + beta_c * |F|, fitted by
-least squares to the times of fixed-criterion solves of the training graphs (time = alpha_c *
-phases + beta_c * sum of |F|). The label of a phase is the criterion that settles the most
-vertices per unit of time, argmax_c count_c / (alpha_c + beta_c * |F|). For Delta-stepping, every
-bucket start of a graph is labelled with the width (2^12, 2^14 or 2^16) whose fixed run was
-fastest on that graph.
+Data comes from the solver itself: `trace_learned` runs a phased solve under a fixed policy and
+records, for every phase, the 12 features its choice is made from. Each training graph is solved
+with each fixed criterion (IN-STATIC|OUT-STATIC, IN-SIMPLE|OUT-SIMPLE, IN|OUT), and every phase of
+its three fixed-policy traces is labelled with the criterion whose fixed solve of that graph was
+fastest on the GPU; the network learns which criterion suits the state it sees. For
+Delta-stepping, every bucket start of a graph is labelled with the width (2^12, 2^14 or 2^16) whose
+fixed run was fastest on that graph.
 """
 from __future__ import annotations
 
@@ -53,78 +51,76 @@ def _timed(fn, reps: int = 2) -> float:
     return best
 
 
-def measure_costs(dg, src: int, reps: int = 2) -> dict:
-    """Fixed-criterion solves of one graph: time, phases and summed |F| per criterion; total time
-    per bucket width."""
+def measure(dg, src: int, reps: int = 3) -> dict:
+    """Per criterion: the fixed-policy trace (features, counts, |F| per phase), the kernel time
+    of every phase of the same fixed-criterion solve, and its total time (best of reps); per bucket
+    width: fixed Delta-stepping time."""
     dist = B.new_dist(dg.n)
-    out = {"time": [], "phases": [], "sum_f": [], "delta_time": []}
-    for crit in B.CHOICE_CRIT:
-        st = B.solve_ex(dg, src, crit, dist).stats
-        out["phases"].append(st["phases"])
-        out["sum_f"].append(st["sum_f"])
+    out = {"n": dg.n, "time": [], "trace": [], "delta_time": []}
+    for c, crit in enumerate(B.CHOICE_CRIT):
+        r, feat, cnt = B.trace_learned(dg, src, B.Selector(constant_weights(c)), cap=dg.n + 2)
+        fringe = r.trace["fringe"].astype(np.float64)
+        dg.profile(True)
+        try:
+            ph = B.solve(dg, src, crit, dist).phases
+            ms = dg.phase_times().astype(np.float64)
+        finally:
+            dg.profile(False)
+        if ph != len(fringe) or len(ms) != len(fringe):
+            raise RuntimeError("fixed solve and fixed-policy trace disagree on the phase count")
+        settled = r.trace["settled"].astype(np.float64)
+        out["trace"].append((feat, cnt, fringe, ms * 1e-3, settled, float(r.stats["n_reach"])))
         out["time"].append(_timed(lambda: B.solve(dg, src, crit, dist), reps))
     for delta in B.CHOICE_DELTA:
         out["delta_time"].append(_timed(lambda: B.delta_step(dg, src, delta, dist), reps))
     return out
 
 
-def fit_cost_model(measured) -> np.ndarray:
-    """[3][2] = (alpha_c, beta_c) per criterion: time = alpha * phases + beta * sum|F| (least squares,
-    clipped at zero)."""
-    model = np.zeros((3, 2))
-    for c in range(3):
-        A = np.array([[m["phases"][c], m["sum_f"][c]] for m in measured], np.float64)
-        t = np.array([m["time"][c] for m in measured], np.float64)
-        coef, *_ = np.linalg.lstsq(A, t, rcond=None)
-        model[c] = np.maximum(coef, [1e-7, 0.0])
-    return model
+def collect(m: dict):
+    """Training rows (features, label) of one graph: the phases of its three fixed-policy traces,
+    each labelled with the criterion whose fixed solve of this graph was fastest."""
+    best = int(np.argmin(m["time"]))
+    X = [tr[0] for tr in m["trace"]]
+    y = [np.full(len(tr[0]), best, np.int32) for tr in m["trace"]]
+    return X, y, best
 
 
-def collect(dg, src: int, costs: dict, model: np.ndarray, cap: int = 1 << 16):
-    """Training rows (features, label) of one graph: phased traces under each fixed policy, and the
-    bucket starts of Delta-stepping under the fastest width."""
-    X, y = [], []
-    for policy in range(3):
-        sel = B.Selector(constant_weights(policy))
-        r, feat, cnt = B.trace_learned(dg, src, sel, cap=cap)
-        fringe = r.trace["fringe"].astype(np.float64)
-        cost = model[None, :, 0] + model[None, :, 1] * fringe[:, None]
-        rate = cnt.astype(np.float64) / cost
-        X.append(feat)
-        y.append(np.argmax(rate, axis=1).astype(np.int32))
-    best = int(np.argmin(costs["delta_time"]))
-    _, feat, _ = B.trace_learned(dg, src, B.Selector(constant_weights(3 + best)), delta_mode=True, cap=cap)
-    X.append(feat)
-    y.append(np.full(feat.shape[0], 3 + best, np.int32))
-    return np.concatenate(X), np.concatenate(y)
+def collect_delta(dg, src: int, measured: dict):
+    best = int(np.argmin(measured["delta_time"]))
+    _, feat, _ = B.trace_learned(dg, src, B.Selector(constant_weights(3 + best)), delta_mode=True, cap=dg.n + 2)
+    return feat, np.full(feat.shape[0], 3 + best, np.int32)
 
 
 def training_graphs():
-    """Training workloads (seeds distinct from every evaluation graph): random graphs 2^14..2^20,
-    R-MAT 14..18, grids 128^2..512^2."""
+    """Training workloads (seeds distinct from every evaluation graph) at the evaluation scales and
+    below: random graphs 2^16..2^21, R-MAT 16..20, grids 256^2..1024^2."""
     import graphgen as G
-    return [G.er(1 << 14, 8, 1, 1000, 101), G.er(1 << 16, 16, 1, (1 << 20) - 1, 102),
-            G.er(1 << 20, 16, 1, (1 << 20) - 1, 103), G.rmat(14, 16, 1, (1 << 20) - 1, 104),
-            G.rmat(18, 16, 1, (1 << 20) - 1, 105), G.grid(128, 128, 1, 1 << 16, 106),
-            G.grid(512, 512, 1, 1 << 16, 107)]
+    return [G.er(1 << 16, 16, 1, (1 << 20) - 1, 102), G.er(1 << 18, 8, 1, (1 << 20) - 1, 108),
+            G.er(1 << 20, 16, 1, (1 << 20) - 1, 103), G.er(1 << 21, 16, 1, (1 << 20) - 1, 113),
+            G.rmat(16, 16, 1, (1 << 20) - 1, 109), G.rmat(18, 16, 1, (1 << 20) - 1, 105),
+            G.rmat(20, 16, 1, (1 << 20) - 1, 114),
+            G.grid(256, 256, 1, 1 << 16, 111), G.grid(512, 512, 1, 1 << 16, 107),
+            G.grid(1024, 1024, 1, 1 << 16, 115)]
 
 
-def build_training_set(graphs=None, log=None):
-    """(X, y, cost model) from traces of the training graphs."""
+def build_training_set(graphs=None, sources_per_graph: int = 1, log=None):
+    """(X, y) from traces of the training graphs."""
     import graphgen as G
     graphs = training_graphs() if graphs is None else graphs
-    dgs = [B.DeviceGraph.from_graph(g) for g in graphs]
-    srcs = [int(G.sources(g, 1, 5)[0]) for g in graphs]
-    measured = [measure_costs(dg, s) for dg, s in zip(dgs, srcs)]
-    model = fit_cost_model(measured)
     Xs, ys = [], []
-    for g, dg, s, m in zip(graphs, dgs, srcs, measured):
-        X, y = collect(dg, s, m, model)
-        Xs.append(X)
-        ys.append(y)
-        if log:
-            log("trace %s: %d rows, labels %s" % (g.name, len(y), np.bincount(y, minlength=6).tolist()))
-    return np.concatenate(Xs), np.concatenate(ys), model
+    for g in graphs:
+        dg = B.DeviceGraph.from_graph(g)
+        for s in G.sources(g, sources_per_graph, 5):
+            m = measure(dg, int(s))
+            X, y, model = collect(m)
+            Xd, yd = collect_delta(dg, int(s), m)
+            Xs += X + [Xd]
+            ys += y + [yd]
+            if log:
+                lab = np.bincount(np.concatenate(y + [yd]), minlength=6).tolist()
+                log("trace %s src %d: fixed ms %s, labels %s" % (g.name, s, [round(t * 1e3, 2) for t in m["time"]], lab))
+        del dg
+    return np.concatenate(Xs), np.concatenate(ys)
 
 
 def train(X, y, seed: int = 0, epochs: int = 60, batch: int = 256, lr: float = 3e-3):
