@@ -8,10 +8,12 @@ A step = one whole solve (every phase: identify, compaction, relaxation) with th
 resident in HBM. GTEPS = out-edges of reachable vertices / solve time.
 
 Also reported (outside the timed region): the other criteria and Delta-stepping on the same
-graph, the dominant kernel's roofline fraction (algorithmic bytes / HIP-event kernel time vs the
+graph, the batched form (512 queries over 64 uneven graphs in one launch), the learned per-phase
+selector (headline graph plus held-out R-MAT and grid graphs), the dominant kernel's roofline fraction (algorithmic bytes / HIP-event kernel time vs the
 8 TB/s HBM peak), and the CPU oracle (binary-heap Dijkstra, one core) timed on the host.
 
-usage: python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu] [--no-extra]
+usage: python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu] [--no-extra] [--no-batch]
+                      [--no-learned]
 """
 import argparse
 import json
@@ -100,6 +102,55 @@ def bench_batched(B, torch, G):
     return res
 
 
+def bench_learned(B, torch, G, dg, src, m_reach, plain_ms):
+    """The learned per-phase selector (weights trained on training seeds by the package's training
+    script) on the headline graph and on held-out R-MAT and grid graphs, against every fixed
+    criterion and bucket width; distances are checked against the plain solver's."""
+    from paper_1903_12085_amd import selector as S
+    sel = S.load_trained()
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        ts, r = [], None
+        for _ in range(reps):
+            tt = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - tt)
+        return sorted(ts)[len(ts) // 2], r
+
+    dist = B.new_dist(dg.n)
+    ref = B.to_u64(B.solve(dg, src, B.STATIC_OR, B.new_dist(dg.n)).dist)
+    tl, r = timed(lambda: B.solve_learned(dg, src, sel, dist))
+    exact = bool(np.array_equal(B.to_u64(r.dist), ref))
+    td, rd = timed(lambda: B.delta_step_learned(dg, src, sel, dist))
+    exact = exact and bool(np.array_equal(B.to_u64(rd.dist), ref))
+    res = {"weights": "selector_weights.npy (trained on random 2^16..2^21, R-MAT 16..20, grids 256^2..1024^2; "
+                      "other seeds)",
+           "headline": {"learned_ms": round(tl * 1e3, 3), "learned_phases": r.phases,
+                        "learned_gteps": round(m_reach / tl / 1e9, 4), "plain_ms": round(plain_ms, 3),
+                        "learned_over_plain": round(tl * 1e3 / plain_ms, 3),
+                        "learned_delta_ms": round(td * 1e3, 3), "learned_delta_rounds": rd.phases,
+                        "learned_delta_gteps": round(m_reach / td / 1e9, 4)}}
+    for g in S.evaluation_graphs()[1:]:
+        h = B.DeviceGraph.from_graph(g)
+        s = int(G.sources(g, 1, 5)[0])
+        e = S.evaluate(sel, h, s)
+        ref = B.to_u64(B.solve(h, s, B.STATIC_OR).dist)
+        e["distances_exact"] = bool(np.array_equal(B.to_u64(B.solve_learned(h, s, sel).dist), ref) and
+                                    np.array_equal(B.to_u64(B.delta_step_learned(h, s, sel).dist), ref))
+        exact = exact and e["distances_exact"]
+        fixed = [e["static_or_ms"], e["simple_or_ms"], e["full_or_ms"]]
+        e["learned_over_best_fixed"] = round(e["learned_ms"] / min(fixed), 3)
+        e["learned_over_mean_fixed"] = round(e["learned_ms"] / (sum(fixed) / 3), 3)
+        res[g.name] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in e.items()}
+        del h
+    res["distances_exact"] = exact
+    log("learned", res)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +160,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--profile-run", action="store_true",
                     help="one solve with the default launch shape, for rocprofv3 (no tuning, no extra passes)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -232,6 +284,9 @@ def main():
 
     if not args.no_batch:
         out["batched"] = bench_batched(B, torch, G)
+
+    if not args.no_learned:
+        out["learned"] = bench_learned(B, torch, G, dg, src, st["m_reach"], ms)
 
     if not args.no_cpu:
         import oracle as O

@@ -86,6 +86,9 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError("libsssp.so not built (%s); run paper_1903_12085_amd.build.build()" % path)
+    # torch first: its HIP runtime is then the one libsssp resolves to, so device memory, streams
+    # and the library's kernels all live in one runtime of the process
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     P, u32, u64, i = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
     lib.sssp_graph_create.argtypes = [u32, u64, P, P, P, i, P, ctypes.POINTER(P)]

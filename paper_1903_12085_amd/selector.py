@@ -11,6 +11,7 @@ fixed run was fastest on that graph.
 """
 from __future__ import annotations
 
+import os
 import time
 
 import numpy as np
@@ -147,3 +148,45 @@ def evaluate(sel, dg, src: int, reps: int = 2) -> dict:
     for delta in B.CHOICE_DELTA:
         res["delta_%d_ms" % delta] = 1e3 * _timed(lambda: B.delta_step(dg, src, delta, dist), reps)
     return res
+
+
+WEIGHTS_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_weights.npy")
+
+
+def evaluation_graphs():
+    """Held-out workloads (seeds used by no training graph): random graph 2^22 out-degree 16,
+    R-MAT 20, grid 1024^2."""
+    import graphgen as G
+    return [G.er(1 << 22, 16, 1, (1 << 20) - 1, 2), G.rmat(20, 16, 1, (1 << 20) - 1, 2),
+            G.grid(1024, 1024, 1, 1 << 16, 2)]
+
+
+def load_trained() -> "B.Selector":
+    """The selector trained by `python -m paper_1903_12085_amd.selector` (weights file in the package)."""
+    return B.Selector(np.load(WEIGHTS_FILE))
+
+
+def main(argv=None):
+    import argparse
+    import json
+    import graphgen as G
+    ap = argparse.ArgumentParser(description="train the per-phase selector on the GPU and save its weights")
+    ap.add_argument("--out", default=WEIGHTS_FILE)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--no-eval", action="store_true")
+    args = ap.parse_args(argv)
+    t = time.time()
+    X, y = build_training_set(log=print)
+    sel, loss = train(X, y, seed=args.seed)
+    acc = float((sel.forward(X).argmax(1) == y).mean())
+    print("trained on %d phases in %.1fs: loss %.4f, accuracy %.3f" % (len(y), time.time() - t, loss, acc))
+    np.save(args.out, sel.weights())
+    if not args.no_eval:
+        for g in evaluation_graphs():
+            dg = B.DeviceGraph.from_graph(g)
+            print(g.name, json.dumps({k: (round(v, 3) if isinstance(v, float) else v)
+                                      for k, v in evaluate(sel, dg, int(G.sources(g, 1, 5)[0])).items()}))
+
+
+if __name__ == "__main__":
+    main()
