@@ -215,6 +215,60 @@ __device__ __forceinline__ void append_settled(const KArgs &a, Ctl *ctl, int p2,
     if (zm && lane == 0) atomicAdd(&L.zero, (uint32_t)__popcll(zm));
 }
 
+// Wavefront-uniform call: each lane appends its up to N settled vertices
+// (bit i of sm) that have out-edges, with row start row[i], out-degree deg[i]
+// and snapshot distance dv[i]; one LDS reservation for the whole wavefront.
+template <int CH, int N>
+__device__ __forceinline__ void append_settled_n(const KArgs &a, Ctl *ctl, int p2, AppendLds &L, uint32_t sm,
+                                                 const uint32_t *row, const uint32_t *deg,
+                                                 const unsigned long long *dv) {
+    const int lane = threadIdx.x & 63;
+    uint32_t k = 0, dtot = 0, z = 0;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        if ((sm >> i) & 1u) {
+            if (deg[i]) { ++k; dtot += deg[i]; }
+            else ++z;
+        }
+    if (__ballot(z != 0)) {
+        const uint32_t zw = wave_sum32(z);
+        if (lane == 0) atomicAdd(&L.zero, zw);
+    }
+    if (!__ballot(k != 0)) return;  // wavefront-uniform
+    const uint32_t kin = wave_incl_scan(k);
+    const uint32_t K = (uint32_t)__builtin_amdgcn_readlane((int)kin, 63);
+    uint32_t pos = 0;
+    if (lane == 0) pos = atomicAdd(&L.cnt, K);
+    pos = (uint32_t)__builtin_amdgcn_readlane((int)pos, 0);
+    if (pos + K <= kAppendBuf) {
+        uint32_t r = pos + kin - k;
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            if (((sm >> i) & 1u) && deg[i]) {
+                L.row[r] = row[i];
+                L.deg[r] = deg[i];
+                L.du[r] = dv[i];
+                ++r;
+            }
+        if (lane == 0) atomicAdd(&L.filled, K);
+    } else {  // buffer full: direct append for this wavefront (its reserved slots stay unused)
+        const uint32_t din = wave_incl_scan(dtot);
+        const uint32_t D = (uint32_t)__builtin_amdgcn_readlane((int)din, 63);
+        unsigned long long b = 0;
+        if (lane == 0) b = atomicAdd(slot_of(ctl->spack[p2], my_shard()), ((unsigned long long)K << 32) | D);
+        b = readlane64(b, 0);
+        uint32_t j = (uint32_t)(b >> 32) + kin - k;
+        uint64_t off = (uint64_t)(uint32_t)b + din - dtot;
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            if (((sm >> i) & 1u) && deg[i]) {
+                write_entry<CH>(a, my_shard(), j, off, row[i], deg[i], dv[i]);
+                ++j;
+                off += deg[i];
+            }
+    }
+}
+
 // Block-wide flush of the LDS buffer (all threads call it once, after the scan).
 template <int CH>
 __device__ __forceinline__ void append_flush(const KArgs &a, Ctl *ctl, int p2, AppendLds &L) {
@@ -514,9 +568,10 @@ __device__ __forceinline__ void identify_body(const KArgs &a, int par, unsigned 
     const unsigned long long Tsi = TRACE ? wave_min64(si0) : 0ull;
     const unsigned long long Tfu = TRACE ? wave_min64(sf0) : 0ull;
     const uint32_t n = a.g.n;
-    const uint32_t nq = (n + 3) / 4;
+    const uint32_t nq = (n + 3) / 4;  // lane q takes vertices 4q .. 4q+3
     for (uint32_t base = blockIdx.x * kBlock; base < nq; base += gridDim.x * kBlock) {
         const uint32_t q = base + threadIdx.x;
+        const uint32_t v0 = 4 * q;
         const uint32_t s4 = q < nq ? load_st4(a.b.st, q, n) : 0u;
         unsigned long long dv[4];
         uint2 mm[4];
@@ -525,50 +580,67 @@ __device__ __forceinline__ void identify_body(const KArgs &a, int par, unsigned 
             dv[i] = INF64;
             mm[i] = make_uint2(INF32, INF32);
             if (((s4 >> (8 * i)) & ST_SET) == ST_F) {
-                dv[i] = a.b.dist[4 * q + i];
-                if (LEARN || IN == IN_STATIC_M || OUT == 1) mm[i] = a.g.vmin[4 * q + i];
+                dv[i] = a.b.dist[v0 + i];
+                if (LEARN || IN == IN_STATIC_M || OUT == 1) mm[i] = a.g.vmin[v0 + i];
             }
         }
+        uint32_t sm = 0;  // settled now, bit i = vertex v0 + i
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const uint32_t v = 4 * q + i;
             const uint8_t s = (uint8_t)(s4 >> (8 * i));
-            bool set = false;
-            uint32_t row = 0, deg = 0;
-            if ((s & ST_SET) == ST_F) {
-                if (LEARN) {
-                    cin += dv[i] <= sadd64(minD, w64(mm[i].x)) ? 1 : 0;
-                    cout += dv[i] <= Tst ? 1 : 0;
-                }
-                bool ok = false;
-                if (TRACE) {
-                    const bool c0 = dv[i] <= sadd64(minD, w64(mm[i].x)) || dv[i] <= Tst;
-                    const bool c1 = (s & ST_INOK) != 0 || dv[i] <= Tsi;
-                    const bool c2 = (s & ST_INOK_FULL) != 0 || dv[i] <= Tfu;
-                    cc[0] += c0;
-                    cc[1] += c1;
-                    cc[2] += c2;
-                    ok = choice == 0 ? c0 : choice == 1 ? c1 : c2;
-                } else {
-                    if (IN == IN_DIJK) ok = dv[i] == minD;
-                    else if (IN == IN_STATIC_M) ok = dv[i] <= sadd64(minD, w64(mm[i].x));
-                    else if (IN == 3) ok = (s & ST_INOK) != 0;
-                    if (OUT != 0) ok = ok || dv[i] <= T;
-                }
-                set = ok;
-                if (set) {
-                    row = a.g.rp[v];
-                    deg = a.g.rp[v + 1] - row;
-                    a.b.st[v] = ST_S;
-                    if (a.b.phase_of) a.b.phase_of[v] = P + 1;
-                } else {
-                    fmin = umin64(fmin, dv[i]);
-                    if (LEARN || OUT == 1) ftst = umin64(ftst, sadd64(dv[i], w64(mm[i].y)));
-                    if (LEARN) fsum += dv[i];
-                }
+            if ((s & ST_SET) != ST_F) continue;
+            if (LEARN) {
+                cin += dv[i] <= sadd64(minD, w64(mm[i].x)) ? 1 : 0;
+                cout += dv[i] <= Tst ? 1 : 0;
             }
-            append_settled<CH>(a, ctl, p2, L, set, row, deg, dv[i]);
+            bool ok = false;
+            if (TRACE) {
+                const bool c0 = dv[i] <= sadd64(minD, w64(mm[i].x)) || dv[i] <= Tst;
+                const bool c1 = (s & ST_INOK) != 0 || dv[i] <= Tsi;
+                const bool c2 = (s & ST_INOK_FULL) != 0 || dv[i] <= Tfu;
+                cc[0] += c0;
+                cc[1] += c1;
+                cc[2] += c2;
+                ok = choice == 0 ? c0 : choice == 1 ? c1 : c2;
+            } else {
+                if (IN == IN_DIJK) ok = dv[i] == minD;
+                else if (IN == IN_STATIC_M) ok = dv[i] <= sadd64(minD, w64(mm[i].x));
+                else if (IN == 3) ok = (s & ST_INOK) != 0;
+                if (OUT != 0) ok = ok || dv[i] <= T;
+            }
+            if (ok) {
+                sm |= 1u << i;
+            } else {
+                fmin = umin64(fmin, dv[i]);
+                if (LEARN || OUT == 1) ftst = umin64(ftst, sadd64(dv[i], w64(mm[i].y)));
+                if (LEARN) fsum += dv[i];
+            }
         }
+        uint32_t row[4], deg[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) row[i] = deg[i] = 0;
+        if (sm) {  // row pointers of the four vertices in one batch
+            if (v0 + 4 <= n) {
+                const uint4 r = *reinterpret_cast<const uint4 *>(a.g.rp + v0);
+                const uint32_t r4 = a.g.rp[v0 + 4];
+                row[0] = r.x; row[1] = r.y; row[2] = r.z; row[3] = r.w;
+                deg[0] = r.y - r.x; deg[1] = r.z - r.y; deg[2] = r.w - r.z; deg[3] = r4 - r.w;
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (v0 + i < n) {
+                        row[i] = a.g.rp[v0 + i];
+                        deg[i] = a.g.rp[v0 + i + 1] - row[i];
+                    }
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if ((sm >> i) & 1u) {
+                    a.b.st[v0 + i] = ST_S;
+                    if (a.b.phase_of) a.b.phase_of[v0 + i] = P + 1;
+                }
+        }
+        append_settled_n<CH, 4>(a, ctl, p2, L, sm, row, deg, dv);
     }
     append_flush<CH>(a, ctl, p2, L);
     // [0] fmin, [1] ftst, [2] fsum, [3] cin, [4] cout, [5..7] per-criterion counts
@@ -595,14 +667,14 @@ __device__ __forceinline__ void identify_body(const KArgs &a, int par, unsigned 
 }
 
 template <int IN, int OUT, int CH>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_identify(KArgs a, int par) {
+__global__ __launch_bounds__(kBlock) void k_identify(KArgs a, int par) {
     __shared__ unsigned long long sh[8 * kWaves];
     __shared__ AppendLds L;
     identify_body<IN, OUT, CH, false>(a, par, sh, L);
 }
 
 template <int CH>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_identify_trace(KArgs a, int par) {
+__global__ __launch_bounds__(kBlock) void k_identify_trace(KArgs a, int par) {
     __shared__ unsigned long long sh[8 * kWaves];
     __shared__ AppendLds L;
     identify_body<IN_STATIC_M, 1, CH, true, true>(a, par, sh, L);
@@ -610,7 +682,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
 
 // Learned mode: identify with the criterion the selector chose for this phase.
 template <int CH>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_identify_learned(KArgs a, int par) {
+__global__ __launch_bounds__(kBlock) void k_identify_learned(KArgs a, int par) {
     __shared__ unsigned long long sh[8 * kWaves];
     __shared__ AppendLds L;
     if (a.b.ctl->h.choice[par & 1] == 0) identify_body<IN_STATIC_M, 1, CH, true>(a, par, sh, L);
@@ -1133,11 +1205,16 @@ void solve_bufs_free(sssp_graph *g) {
 // q = b*kBlock + i + k*G*kBlock (vertices 4q..4q+3), shard = b % kShards, so
 // a shard owns at most ceil(G / kShards) blocks of at most
 // 4 * kBlock * ceil(ceil(n / 4) / (G * kBlock)) vertices each.
+// Most S' entries one shard can receive in a phase: the vertices its blocks
+// scan (4 vertices per lane in both identify kernels).
+static uint64_t scan_span(uint32_t n, int G, uint64_t vpl) {
+    const uint64_t nv = ((uint64_t)n + vpl - 1) / vpl;
+    const uint64_t iters = (nv + (uint64_t)G * kBlock - 1) / ((uint64_t)G * kBlock);
+    return vpl * kBlock * iters;
+}
 static uint32_t shard_capacity(uint32_t n, int G) {
-    const uint64_t nq = ((uint64_t)n + 3) / 4;
-    const uint64_t iters = (nq + (uint64_t)G * kBlock - 1) / ((uint64_t)G * kBlock);
     const uint64_t blocks = ((uint64_t)G + kShards - 1) / kShards;
-    return (uint32_t)(blocks * 4 * kBlock * iters);
+    return (uint32_t)(blocks * scan_span(n, G, 4));
 }
 
 int solve_bufs_ensure(sssp_graph *g, bool cursors, bool stamps) {
