@@ -15,6 +15,15 @@
 // (full) test, written only by the trace-mode term pass, which evaluates both).
 enum : uint8_t { ST_U = 0, ST_F = 1, ST_S = 2, ST_R = 3, ST_SET = 3, ST_INOK = 4, ST_INOK_FULL = 8 };
 
+// A settled vertex carries this bit in its distance word while the solve runs
+// (real distances stay below 2^58 and INF is all ones, so a word with the bit
+// set is either INF or settled); relax then learns a target's settled status
+// from the one load it needs anyway. Cleared before the solve returns.
+constexpr unsigned long long kSettledBit = 1ull << 63;
+__host__ __device__ __forceinline__ bool dist_settled(unsigned long long x) {
+    return (x & kSettledBit) != 0 && x != 0xFFFFFFFFFFFFFFFFull;
+}
+
 // Which IN-family / OUT-family member a phase evaluates. Inside each family
 // the members are ordered by strength (X-STATIC => X-SIMPLE => (OUTWEAK =>) X,
 // Section 3), so a disjunction of members equals its strongest member, and

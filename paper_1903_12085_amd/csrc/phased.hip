@@ -65,6 +65,14 @@ __device__ __forceinline__ void shard_fill(Sharded &s, unsigned long long x) {
 // ---------------------------------------------------------------------------
 // initialisation
 
+// End of a solve: drop the settled bit from every distance word.
+__global__ void k_clear_settled(uint32_t n, unsigned long long *__restrict__ d) {
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const unsigned long long x = d[v];
+        if (dist_settled(x)) d[v] = x & ~kSettledBit;
+    }
+}
+
 __global__ void k_init_state(uint32_t n, uint32_t src, unsigned long long *__restrict__ d,
                              uint8_t *__restrict__ st, uint32_t *__restrict__ phase_of,
                              uint32_t *__restrict__ out_cur, const uint32_t *__restrict__ rp,
@@ -637,6 +645,7 @@ __device__ __forceinline__ void identify_body(const KArgs &a, int par, unsigned 
             for (int i = 0; i < 4; ++i)
                 if ((sm >> i) & 1u) {
                     a.b.st[v0 + i] = ST_S;
+                    a.b.dist[v0 + i] = dv[i] | kSettledBit;
                     if (a.b.phase_of) a.b.phase_of[v0 + i] = P + 1;
                 }
         }
@@ -804,7 +813,10 @@ __global__ __launch_bounds__(kBlock) void k_identify_delta(KArgs a, int par) {
                 row = a.g.rp[v];
                 deg = a.g.rp[v + 1] - row;
                 a.b.st[v] = kind == 2 ? ST_S : ST_R;
-                if (kind == 2 && a.b.phase_of) a.b.phase_of[v] = P + 1;
+                if (kind == 2) {
+                    a.b.dist[v] = dv[i] | kSettledBit;
+                    if (a.b.phase_of) a.b.phase_of[v] = P + 1;
+                }
             }
             append_settled<CH>(a, ctl, p2, L, set, row, deg, dv[i]);
         }
@@ -1035,9 +1047,8 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
                 if (kind == 1 && ed.y >= delta) continue;  // light: c < delta
                 if (kind == 2 && ed.y < delta) continue;   // heavy: c >= delta
             }
-            const uint8_t sv = a.b.st[v];
-            const unsigned long long cur = a.b.dist[v];  // issued together with the state load
-            if ((sv & ST_SET) == ST_S) continue;
+            const unsigned long long cur = a.b.dist[v];
+            if (dist_settled(cur)) continue;
             ++tried;
             const unsigned long long cand = s_du[lo] + ed.y;
             if (cand < cur) {
@@ -1567,6 +1578,11 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
     // Delta: light rounds per bucket <= window vertices + 1, one heavy round per bucket
     const uint64_t max_phases = delta_mode ? 4ull * g->n + 64 : (uint64_t)g->n + 2;
     rc = run_loop(g, a, K, max_phases);
+    if (rc == SSSP_OK) {
+        hipLaunchKernelGGL(k_clear_settled, dim3(ib), dim3(256), 0, s, g->n, a.b.dist);
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipStreamSynchronize(s));
+    }
     uint32_t phases = 0;
     if (rc == SSSP_OK) rc = finish_stats(g, a.b.ctl, stats, &phases);
     if (rc == SSSP_OK && trace_cap) {
