@@ -1035,42 +1035,77 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
             s_du[t] = a.b.sdu[j];
         }
         __syncthreads();
-        for (uint32_t i = threadIdx.x; i < len; i += kBlock) {
-            uint32_t lo = 0, hi2 = cnt - 1;  // last entry whose first chunk position is <= i
-            while (lo < hi2) {
-                const uint32_t mid = (lo + hi2 + 1) >> 1;
-                if (s_pos[mid] <= i) lo = mid; else hi2 = mid - 1;
-            }
-            const uint2 ed = a.g.edges[s_start[lo] + (i - s_pos[lo])];
-            const uint32_t v = ed.x;
-            if (DELTA) {
-                if (kind == 1 && ed.y >= delta) continue;  // light: c < delta
-                if (kind == 2 && ed.y < delta) continue;   // heavy: c >= delta
-            }
-            const unsigned long long cur = a.b.dist[v];
-            if (dist_settled(cur)) continue;
-            ++tried;
-            const unsigned long long cand = s_du[lo] + ed.y;
-            if (cand < cur) {
-                const unsigned long long old = atomicMin(&a.b.dist[v], cand);
-                if (cand < old) {
-                    ++improv;
-                    if (!DELTA) {
-                        cmin = umin64(cmin, cand);
-                        if (FOLDT) ctst = umin64(ctst, sadd64(cand, w64(a.g.vmin[v].y)));
-                    } else if (kind == 2) {
-                        cmin = umin64(cmin, cand);
-                    } else if (cand < hi) {
-                        const unsigned int prev = atomicExch(&a.b.stamp[v], P + 1);
-                        if (prev != P + 1) ++winimp;
-                    }
-                    if (LEARN && !DELTA) dsum += old == INF64 ? cand : cand - old;  // mod 2^64: sum over F of d
-                    if (old == INF64) {
-                        a.b.st[v] = ST_F;
-                        ++disc;
-                        if (LEARN && !DELTA) ddeg += a.g.rp[v + 1] - a.g.rp[v];
-                    }
+        // Each thread takes edges threadIdx.x + k * kBlock (k < E) of the chunk, every stage's
+        // loads and atomics for its E edges issued together.
+        constexpr int E = CH / kBlock;
+        constexpr int kSteps = CH >= 1024 ? 11 : CH >= 512 ? 10 : 9;  // > log2(CH + 1)
+        uint32_t lo[E], hi2[E];
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            lo[k] = 0;  // last entry whose first chunk position is <= i
+            hi2[k] = cnt - 1;
+        }
+#pragma unroll
+        for (int it = 0; it < kSteps; ++it)
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                const uint32_t i = threadIdx.x + k * kBlock;
+                if (lo[k] < hi2[k]) {
+                    const uint32_t mid = (lo[k] + hi2[k] + 1) >> 1;
+                    if (s_pos[mid] <= i) lo[k] = mid; else hi2[k] = mid - 1;
                 }
+            }
+        uint2 ed[E];
+        unsigned long long cur[E], cand[E], old[E];
+        uint32_t live = 0, issued = 0;
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            const uint32_t i = threadIdx.x + k * kBlock;
+            ed[k] = make_uint2(0u, 0u);
+            if (i < len) {
+                ed[k] = a.g.edges[s_start[lo[k]] + (i - s_pos[lo[k]])];
+                live |= 1u << k;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            cur[k] = 0;
+            if (DELTA && ((live >> k) & 1u)) {
+                if (kind == 1 && ed[k].y >= delta) live &= ~(1u << k);  // light: c < delta
+                if (kind == 2 && ed[k].y < delta) live &= ~(1u << k);   // heavy: c >= delta
+            }
+            if ((live >> k) & 1u) cur[k] = a.b.dist[ed[k].x];
+        }
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            cand[k] = old[k] = INF64;
+            if (!((live >> k) & 1u) || dist_settled(cur[k])) continue;
+            ++tried;
+            cand[k] = s_du[lo[k]] + ed[k].y;
+            if (cand[k] < cur[k]) {
+                old[k] = atomicMin(&a.b.dist[ed[k].x], cand[k]);
+                issued |= 1u << k;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            if (!((issued >> k) & 1u) || !(cand[k] < old[k])) continue;
+            const uint32_t v = ed[k].x;
+            ++improv;
+            if (!DELTA) {
+                cmin = umin64(cmin, cand[k]);
+                if (FOLDT) ctst = umin64(ctst, sadd64(cand[k], w64(a.g.vmin[v].y)));
+            } else if (kind == 2) {
+                cmin = umin64(cmin, cand[k]);
+            } else if (cand[k] < hi) {
+                const unsigned int prev = atomicExch(&a.b.stamp[v], P + 1);
+                if (prev != P + 1) ++winimp;
+            }
+            if (LEARN && !DELTA) dsum += old[k] == INF64 ? cand[k] : cand[k] - old[k];  // mod 2^64: sum over F of d
+            if (old[k] == INF64) {
+                a.b.st[v] = ST_F;
+                ++disc;
+                if (LEARN && !DELTA) ddeg += a.g.rp[v + 1] - a.g.rp[v];
             }
         }
     }
