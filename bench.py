@@ -38,9 +38,9 @@ def alg_bytes(kernel, st, phases):
     """Algorithmic bytes per launch of a phase kernel (per-unit figures from the design notes)."""
     if kernel == "identify":
         return 24.0 * st["sum_f"] / phases  # id 4 + d 8 + minIn 4 + minOut 4 + compacted write 4 per queued vertex
-    # relax: per S' vertex 16 B (row range 8, id + snapshot distance 8); per edge 16 B (target+weight 8,
-    # target distance 8); per improving relaxation 8 B (the atomic write)
-    return (16.0 * st["n_reach"] + 16.0 * st["relax_edges"] + 8.0 * st["improving"]) / phases
+    # relax: per S' vertex 16 B (row range 8, id + snapshot distance 8); per out-edge of S' 16 B
+    # (target+weight 8, target distance 8); per improving relaxation 8 B (the atomic write)
+    return (16.0 * st["n_reach"] + 16.0 * st["m_reach"] + 8.0 * st["improving"]) / phases
 
 
 def measured_traffic(kern, log2n):
@@ -163,6 +163,9 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--profile-run", action="store_true",
                     help="one solve with the default launch shape, for rocprofv3 (no tuning, no extra passes)")
+    ap.add_argument("--launch", default=None,
+                    help="with --profile-run: scan_blocks,relax_blocks,chunk,use_graph (e.g. the shape the "
+                         "autotuner picks for the timed run)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device-to-device copy kernel (known bytes) for counter calibration")
     args = ap.parse_args()
@@ -189,6 +192,9 @@ def main():
     if args.profile_run:
         g = G.config_er_large(seed=1, log2n=args.log2n)
         dg = B.DeviceGraph.from_graph(g)
+        if args.launch:
+            sb, rb, ch, ug = (int(x) for x in args.launch.split(","))
+            dg.set_launch(scan_blocks=sb, relax_blocks=rb, chunk=ch, use_graph=ug)
         r = B.solve(dg, 0, B.STATIC_OR)
         torch.cuda.synchronize()
         print(json.dumps({"profile_run": True, "phases": r.phases, "launch": dg.launch()}))
@@ -253,6 +259,7 @@ def main():
         "config": {"workload": "er_n%d_outdeg16_w1-2^20_src0" % g.n, "n": g.n, "m": g.m, "seed": seed,
                    "source": src, "criterion": "IN_STATIC|OUT_STATIC", "form": "plain", "launch": tuned},
         "phases": phases, "sum_f": st["sum_f"], "m_reach": st["m_reach"], "n_reach": st["n_reach"],
+        "relax_edges": st["relax_edges"], "improving": st["improving"],
         "us_per_phase": round(ms * 1e3 / phases, 2), "precompute_ms": round(st["precompute_ns"] / 1e6, 3),
         "gteps_incl_precompute": round(st["m_reach"] / ((ms + st["precompute_ns"] / 1e6) * 1e-3) / 1e9, 4),
         "roofline": roofline,
