@@ -577,19 +577,38 @@ __device__ __forceinline__ void identify_body(const KArgs &a, int par, unsigned 
     const unsigned long long Tfu = TRACE ? wave_min64(sf0) : 0ull;
     const uint32_t n = a.g.n;
     const uint32_t nq = (n + 3) / 4;  // lane q takes vertices 4q .. 4q+3
+    constexpr bool kMinima = LEARN || IN == IN_STATIC_M || OUT == 1;
+    // With at least a quarter of the vertices queued nearly every line of d and
+    // (minIn, minOut) holds a queued vertex and is fetched anyway: then a lane
+    // loads its four words of each with 16-byte loads issued together with the
+    // state word, instead of after it.
+    const bool dense = (reached - settled) * 4 >= (unsigned long long)n &&
+                       (reinterpret_cast<uintptr_t>(a.b.dist) & 15) == 0;
     for (uint32_t base = blockIdx.x * kBlock; base < nq; base += gridDim.x * kBlock) {
         const uint32_t q = base + threadIdx.x;
         const uint32_t v0 = 4 * q;
         const uint32_t s4 = q < nq ? load_st4(a.b.st, q, n) : 0u;
         unsigned long long dv[4];
         uint2 mm[4];
+        if (dense && v0 + 4 <= n) {
+            const ulonglong2 *dp = reinterpret_cast<const ulonglong2 *>(a.b.dist + v0);
+            const ulonglong2 d01 = dp[0], d23 = dp[1];
+            dv[0] = d01.x; dv[1] = d01.y; dv[2] = d23.x; dv[3] = d23.y;
+            if (kMinima) {
+                const uint4 *mp = reinterpret_cast<const uint4 *>(a.g.vmin + v0);
+                const uint4 m01 = mp[0], m23 = mp[1];
+                mm[0] = make_uint2(m01.x, m01.y); mm[1] = make_uint2(m01.z, m01.w);
+                mm[2] = make_uint2(m23.x, m23.y); mm[3] = make_uint2(m23.z, m23.w);
+            }
+        } else {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            dv[i] = INF64;
-            mm[i] = make_uint2(INF32, INF32);
-            if (((s4 >> (8 * i)) & ST_SET) == ST_F) {
-                dv[i] = a.b.dist[v0 + i];
-                if (LEARN || IN == IN_STATIC_M || OUT == 1) mm[i] = a.g.vmin[v0 + i];
+            for (int i = 0; i < 4; ++i) {
+                dv[i] = INF64;
+                mm[i] = make_uint2(INF32, INF32);
+                if (((s4 >> (8 * i)) & ST_SET) == ST_F) {
+                    dv[i] = a.b.dist[v0 + i];
+                    if (kMinima) mm[i] = a.g.vmin[v0 + i];
+                }
             }
         }
         uint32_t sm = 0;  // settled now, bit i = vertex v0 + i
