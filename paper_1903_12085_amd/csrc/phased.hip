@@ -983,6 +983,10 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
     __shared__ unsigned long long sh[8 * kWaves];
     __shared__ uint32_t s_ns[kShards], s_E[kShards], s_cb[kShards + 1];
     __shared__ unsigned long long s_tot_settled, s_tot_edges;
+    // header fields, loaded with the shard slots (before the barrier)
+    const unsigned int done = ctl->h.done, P = ctl->h.pnum[p2];
+    const unsigned int rmode = DELTA ? ctl->h.rmode[p2] : 0u;
+    const unsigned long long win_hi = DELTA ? ctl->h.win_hi : INF64, win_delta = DELTA ? ctl->h.win_delta : 0ull;
     if (threadIdx.x < 64) {
         // per-shard S' sizes, edge totals and an exclusive prefix of their chunk counts
         const int i = threadIdx.x;
@@ -1002,14 +1006,13 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
         if (i == 0) { s_tot_settled = tset; s_tot_edges = tedge; }
     }
     __syncthreads();
-    if (s_tot_settled == 0 || ctl->h.done) return;
-    const unsigned int P = ctl->h.pnum[p2];
+    if (s_tot_settled == 0 || done) return;
     int kind = 0;
     unsigned long long hi = INF64, delta = 0;
     if (DELTA) {
-        kind = ctl->h.rmode[p2] == 2 ? 2 : 1;
-        hi = ctl->h.win_hi;
-        delta = ctl->h.win_delta;
+        kind = rmode == 2 ? 2 : 1;
+        hi = win_hi;
+        delta = win_delta;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (!DELTA || kind == 2) {
@@ -1033,16 +1036,34 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
     unsigned long long cmin = INF64, ctst = INF64, tried = 0, improv = 0, disc = 0, winimp = 0, dsum = 0, ddeg = 0;
     const uint32_t nch = s_cb[kShards];
     const uint32_t cfirst = split ? blockIdx.x - 1 : blockIdx.x, cstep = split ? gridDim.x - 1 : gridDim.x;
+    // Chunk c's shard, shard-local index and first / last S' entry; the entry
+    // bounds of the block's next chunk are loaded while this one is processed.
+    struct ChunkRef {
+        int sd;
+        uint32_t lc, j0, jend;
+    };
+    auto chunk_ref = [&](uint32_t c) {
+        ChunkRef r;
+        r.sd = 0;  // last shard with s_cb[sd] <= c
+        while (r.sd + 1 < kShards && s_cb[r.sd + 1] <= c) ++r.sd;
+        r.lc = c - s_cb[r.sd];
+        const uint32_t *cs = a.b.chunk_start + (uint64_t)r.sd * a.b.chunk_cap;
+        r.j0 = cs[r.lc];
+        r.jend = ((uint64_t)r.lc * CH + CH < s_E[r.sd]) ? cs[r.lc + 1] : s_ns[r.sd] - 1;
+        return r;
+    };
+    ChunkRef nxt{};
+    if (cfirst < nch) nxt = chunk_ref(cfirst);
     for (uint32_t c = cfirst; c < nch; c += cstep) {
-        int sd = 0;  // shard of chunk c: last sd with s_cb[sd] <= c
-        while (sd + 1 < kShards && s_cb[sd + 1] <= c) ++sd;
-        const uint32_t lc = c - s_cb[sd];
-        const uint32_t Es = s_E[sd], ns = s_ns[sd];
+        const ChunkRef ck = nxt;
+        if (c + cstep < nch) nxt = chunk_ref(c + cstep);
+        const int sd = ck.sd;
+        const uint32_t lc = ck.lc;
+        const uint32_t Es = s_E[sd];
         const uint32_t e0 = lc * CH;
         const uint32_t len = min(Es - e0, (uint32_t)CH);
-        const uint32_t *cs = a.b.chunk_start + (uint64_t)sd * a.b.chunk_cap;
-        const uint32_t j0 = cs[lc];
-        const uint32_t jend = (e0 + CH < Es) ? cs[lc + 1] : ns - 1;
+        const uint32_t j0 = ck.j0;
+        const uint32_t jend = ck.jend;
         const uint32_t cnt = jend - j0 + 1;
         const uint64_t gbase = (uint64_t)sd * a.b.shard_cap;
         __syncthreads();
