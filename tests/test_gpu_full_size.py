@@ -4,8 +4,8 @@ tests/golden/make_full_size.py, which calls only the oracle and the input genera
 Workloads: random graph n = 2^22 out-degree 16 weights [1, 2^20) (source 0), R-MAT scale 22 edge
 factor 16 weights [1, 2^20) and the 2048 x 2048 grid with weights [1, 2^16] (two seeded sources
 each). Distances: SHA-256 of the whole uint64 array plus 256 sampled vertices; phases, summed
-fringe sizes and relaxation counts exact; Delta-stepping rounds and buckets exact. The solver runs
-in the same launch configuration as bench.py.
+fringe sizes and relaxation counts exact; Delta-stepping rounds and buckets exact. On the random
+graph the solver runs in the launch shape bench.py's autotuner picks and times.
 """
 import glob
 import hashlib
@@ -32,7 +32,10 @@ def device_graph(name):
     if name not in _cache:
         _cache.clear()  # one full-size graph on the device at a time
         g = MAKERS[name]()
-        _cache[name] = (g, B.DeviceGraph.from_graph(g))
+        dg = B.DeviceGraph.from_graph(g)
+        if name == "er22":  # the headline graph: the launch shape bench.py's autotuner picks and times
+            B.autotune(dg, 0, B.STATIC_OR)
+        _cache[name] = (g, dg)
     return _cache[name]
 
 
