@@ -82,28 +82,50 @@ __device__ __forceinline__ void wave_append(bool take, uint32_t v, uint32_t *lis
     if (take) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = v;
 }
 
-// Returns true when this relaxation discovered ed.x (infinity replaced).
-template <int BS, bool OUT>
-__device__ __forceinline__ bool relax_edge(const BatchQuery &q, unsigned long long du, uint2 ed,
-                                           unsigned long long &cmin, unsigned long long &ctst) {
-    bool disc = false;
-    const uint8_t sv = ld_st(&q.st[ed.x]);
-    if (sv != ST_S && sv != ST_NEW) {
-        const unsigned long long cand = du + ed.y;
-        if (cand < ld_dist(&q.dist[ed.x])) {
-            const unsigned long long old = atomicMin(&q.dist[ed.x], cand);
-            if (cand < old) {
-                cmin = umin64(cmin, cand);
-                if (OUT) ctst = umin64(ctst, sadd64(cand, w64(q.vmin[ed.x].y)));
-                if (old == INF64) {
-                    q.st[ed.x] = ST_F;
-                    disc = true;
-                }
-            }
+// Relaxes the edges ed[j] (bit j of have) from a vertex at distance du: the
+// state and distance loads of all of them are issued together, then the
+// atomics. Returns the mask of edges whose atomic replaced infinity (the
+// target was discovered; exactly one atomic can do that).
+template <int U, bool OUT>
+__device__ __forceinline__ uint32_t relax_edges(const BatchQuery &q, unsigned long long du, const uint2 *ed,
+                                                uint32_t have, unsigned long long &cmin, unsigned long long &ctst) {
+    uint8_t sv[U];
+    unsigned long long cur[U], cand[U], old[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+        sv[j] = ST_S;
+        cur[j] = 0;
+        if ((have >> j) & 1u) {
+            sv[j] = ld_st(&q.st[ed[j].x]);
+            cur[j] = ld_dist(&q.dist[ed[j].x]);
+        }
+    }
+    uint32_t issued = 0;
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+        cand[j] = old[j] = INF64;
+        if (sv[j] == ST_S || sv[j] == ST_NEW) continue;
+        cand[j] = du + ed[j].y;
+        if (cand[j] < cur[j]) {
+            old[j] = atomicMin(&q.dist[ed[j].x], cand[j]);
+            issued |= 1u << j;
+        }
+    }
+    uint32_t disc = 0;
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+        if (!((issued >> j) & 1u) || !(cand[j] < old[j])) continue;
+        cmin = umin64(cmin, cand[j]);
+        if (OUT) ctst = umin64(ctst, sadd64(cand[j], w64(q.vmin[ed[j].x].y)));
+        if (old[j] == INF64) {
+            q.st[ed[j].x] = ST_F;
+            disc |= 1u << j;
         }
     }
     return disc;
 }
+
+constexpr int kBatchU = 4;  // fringe entries / edges a lane handles per step
 
 // IN: IN_NONE, IN_DIJK or IN_STATIC_M; OUT: OUT-STATIC on/off.
 template <int BS, int IN, bool OUT>
@@ -139,29 +161,50 @@ __global__ __launch_bounds__(BS) void k_batch(const BatchQuery *__restrict__ que
             __syncthreads();
             // identify over the fringe list
             unsigned long long fmin = INF64, ftst = INF64;
-            for (uint32_t base = 0; base < nF; base += BS) {
-                const uint32_t i = base + threadIdx.x;
-                bool set = false, keep = false;
-                uint32_t v = 0;
-                if (i < nF) {
-                    v = ld_u32(&F[i]);
-                    const unsigned long long dv = ld_dist(&q.dist[v]);
-                    const uint2 mm = q.vmin[v];
-                    bool ok = false;
-                    if (IN == IN_DIJK) ok = dv == minD;
-                    else if (IN == IN_STATIC_M) ok = dv <= sadd64(minD, w64(mm.x));
-                    if (OUT) ok = ok || dv <= T;
-                    set = ok;
-                    keep = !ok;
-                    if (keep) {
-                        fmin = umin64(fmin, dv);
-                        if (OUT) ftst = umin64(ftst, sadd64(dv, w64(mm.y)));
-                    } else {
-                        q.st[v] = ST_NEW;
+            // kBatchU fringe entries per thread and step, their loads issued together
+            for (uint32_t base = 0; base < nF; base += BS * kBatchU) {
+                uint32_t v[kBatchU];
+                unsigned long long dv[kBatchU];
+                uint2 mm[kBatchU];
+                uint32_t have = 0;
+#pragma unroll
+                for (int j = 0; j < kBatchU; ++j) {
+                    const uint32_t i = base + j * BS + threadIdx.x;
+                    v[j] = 0;
+                    if (i < nF) {
+                        v[j] = ld_u32(&F[i]);
+                        have |= 1u << j;
                     }
                 }
-                wave_append(set, v, Sp, &s_nset);
-                wave_append(keep, v, Fn, &s_nnext);
+#pragma unroll
+                for (int j = 0; j < kBatchU; ++j) {
+                    dv[j] = INF64;
+                    mm[j] = make_uint2(INF32, INF32);
+                    if ((have >> j) & 1u) {
+                        dv[j] = ld_dist(&q.dist[v[j]]);
+                        mm[j] = q.vmin[v[j]];
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < kBatchU; ++j) {
+                    bool set = false, keep = false;
+                    if ((have >> j) & 1u) {
+                        bool ok = false;
+                        if (IN == IN_DIJK) ok = dv[j] == minD;
+                        else if (IN == IN_STATIC_M) ok = dv[j] <= sadd64(minD, w64(mm[j].x));
+                        if (OUT) ok = ok || dv[j] <= T;
+                        set = ok;
+                        keep = !ok;
+                        if (keep) {
+                            fmin = umin64(fmin, dv[j]);
+                            if (OUT) ftst = umin64(ftst, sadd64(dv[j], w64(mm[j].y)));
+                        } else {
+                            q.st[v[j]] = ST_NEW;
+                        }
+                    }
+                    wave_append(set, v[j], Sp, &s_nset);
+                    wave_append(keep, v[j], Fn, &s_nnext);
+                }
             }
             __syncthreads();
             const uint32_t nS = s_nset;
@@ -195,15 +238,21 @@ __global__ __launch_bounds__(BS) void k_batch(const BatchQuery *__restrict__ que
                 uint32_t len = e - b;
                 uint32_t mx = len;
                 for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor(mx, o, 64));
-                for (uint32_t k = 0; k < mx; ++k) {
-                    bool disc = false;
-                    uint32_t tgt = 0;
-                    if (k < len) {
-                        const uint2 ed = q.edges[b + k];
-                        tgt = ed.x;
-                        disc = relax_edge<BS, OUT>(q, du, ed, cmin, ctst);
+                for (uint32_t k = 0; k < mx; k += kBatchU) {
+                    uint2 ed[kBatchU];
+                    uint32_t have = 0;
+#pragma unroll
+                    for (int j = 0; j < kBatchU; ++j) {
+                        ed[j] = make_uint2(0u, 0u);
+                        if (k + j < len) {
+                            ed[j] = q.edges[b + k + j];
+                            have |= 1u << j;
+                        }
                     }
-                    wave_append(disc, tgt, Fn, &s_nnext);  // every lane of the wavefront takes part
+                    const uint32_t disc = relax_edges<kBatchU, OUT>(q, du, ed, have, cmin, ctst);
+#pragma unroll
+                    for (int j = 0; j < kBatchU; ++j)  // every lane of the wavefront takes part
+                        wave_append((disc >> j) & 1u, ed[j].x, Fn, &s_nnext);
                 }
             }
             __syncthreads();
@@ -211,16 +260,21 @@ __global__ __launch_bounds__(BS) void k_batch(const BatchQuery *__restrict__ que
             for (uint32_t h = 0; h < nh; ++h) {
                 const uint32_t v = hub_v[h];
                 const uint32_t b = q.rp[v], e = q.rp[v + 1];
-                for (uint32_t kb = b; kb < e; kb += BS) {
-                    const uint32_t k = kb + threadIdx.x;
-                    bool disc = false;
-                    uint32_t tgt = 0;
-                    if (k < e) {
-                        const uint2 ed = q.edges[k];
-                        tgt = ed.x;
-                        disc = relax_edge<BS, OUT>(q, hub_du[h], ed, cmin, ctst);
+                for (uint64_t kb = b; kb < e; kb += BS * kBatchU) {
+                    uint2 ed[kBatchU];
+                    uint32_t have = 0;
+#pragma unroll
+                    for (int j = 0; j < kBatchU; ++j) {
+                        const uint64_t k = kb + (uint64_t)j * BS + threadIdx.x;
+                        ed[j] = make_uint2(0u, 0u);
+                        if (k < e) {
+                            ed[j] = q.edges[k];
+                            have |= 1u << j;
+                        }
                     }
-                    wave_append(disc, tgt, Fn, &s_nnext);
+                    const uint32_t disc = relax_edges<kBatchU, OUT>(q, hub_du[h], ed, have, cmin, ctst);
+#pragma unroll
+                    for (int j = 0; j < kBatchU; ++j) wave_append((disc >> j) & 1u, ed[j].x, Fn, &s_nnext);
                 }
             }
             minD = bmin<BS>(umin64(fmin, cmin), sh);
