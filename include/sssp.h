@@ -202,6 +202,20 @@ typedef struct {
     float relax_ms;        /* total time of the relax kernels (learned mode: plus the selector) */
 } sssp_kernel_profile;
 
+/* Phased solve with the clairvoyant ORACLE criterion of Section 3: a queued
+ * vertex is settled as soon as d[v] = dist(source, v). It needs the answer in
+ * advance, so it measures the fewest phases the generic algorithm can take on
+ * this graph (each v is settled in phase 1 + the fewest edges over its
+ * minimum-cost paths), the bound every sound criterion is compared with.
+ *   dist_ref  device pointer, n words: dist(source, .) of this graph (UINT64_MAX
+ *             for unreachable vertices), e.g. from an earlier sssp_solve; read only.
+ *   dist_out, stats, phase_of  as in sssp_solve_ex (phase_of may be NULL).
+ * Returns SSSP_ERR_INVALID if dist_ref is NULL or turns out not to be
+ * dist(source, .): a phase that certifies nothing while F is not empty stops
+ * the solve. */
+int sssp_solve_oracle(sssp_graph *g, uint32_t source, const uint64_t *dist_ref, uint64_t *dist_out,
+                      sssp_stats *stats, uint32_t *phase_of);
+
 /* Turn per-kernel event timing on (enable != 0) or off for later solves on g. */
 int sssp_profile_enable(sssp_graph *g, int enable);
 

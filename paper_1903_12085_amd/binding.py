@@ -25,7 +25,8 @@ FULL_OR = IN_FULL | OUT_FULL
 
 SYMBOLS = ["sssp_graph_create", "sssp_graph_destroy", "sssp_set_stream", "sssp_graph_minima", "sssp_solve",
            "sssp_solve_ex", "sssp_delta_step", "sssp_delta_step_ex", "sssp_solve_batch", "sssp_last_error",
-           "sssp_profile_enable", "sssp_profile_get", "sssp_profile_phases", "sssp_get_launch", "sssp_set_launch",
+           "sssp_profile_enable", "sssp_profile_get", "sssp_profile_phases", "sssp_solve_oracle",
+           "sssp_get_launch", "sssp_set_launch",
            "sssp_solve_batch_ex", "sssp_batch_set_config", "sssp_batch_get_config", "sssp_autotune",
            "sssp_autotune_batch", "sssp_selector_create", "sssp_selector_destroy", "sssp_selector_get_weights",
            "sssp_selector_set_weights", "sssp_selector_forward", "sssp_selector_grad", "sssp_selector_train",
@@ -98,6 +99,7 @@ def load(path: str = LIB_PATH):
     lib.sssp_solve.argtypes = [P, u32, u32, P, P]
     lib.sssp_solve_ex.argtypes = [P, u32, u32, P, ctypes.POINTER(Stats), P, P, u32]
     lib.sssp_delta_step.argtypes = [P, u32, u64, P, P]
+    lib.sssp_solve_oracle.argtypes = [P, u32, P, P, ctypes.POINTER(Stats), P]
     lib.sssp_delta_step_ex.argtypes = [P, u32, P, u32, P, ctypes.POINTER(Stats), P, u32]
     lib.sssp_solve_batch.argtypes = [P, P, u32, u32, P, P]
     lib.sssp_profile_enable.argtypes = [P, i]
@@ -269,6 +271,23 @@ def solve_ex(g: DeviceGraph, source: int, criterion: int, dist=None, phase_of: b
     if tr is not None:
         tr = tr[:min(st.phases, trace_cap)]
     return SolveResult(dist, int(st.phases), st.as_dict(), po, tr)
+
+
+def solve_oracle(g: DeviceGraph, source: int, dist_ref, dist=None, phase_of: bool = True) -> SolveResult:
+    """Phased solve with the clairvoyant ORACLE criterion; dist_ref = dist(source, .) as a device
+    uint64/int64 tensor (or anything torch.as_tensor accepts, copied to the device)."""
+    import torch
+    ref = torch.as_tensor(np.asarray(dist_ref).view(np.int64) if not torch.is_tensor(dist_ref) else dist_ref)
+    ref = ref.to(device="cuda", dtype=torch.int64).contiguous()
+    if ref.numel() != g.n:
+        raise ValueError("dist_ref needs %d entries" % g.n)
+    dist = new_dist(g.n) if dist is None else dist
+    po = torch.empty(g.n, dtype=torch.int32, device="cuda") if phase_of else None
+    st = Stats()
+    g._bind_stream()
+    _check(load().sssp_solve_oracle(g.handle, source, ctypes.c_void_p(ref.data_ptr()), ctypes.c_void_p(dist.data_ptr()),
+                                    ctypes.byref(st), ctypes.c_void_p(po.data_ptr()) if po is not None else None))
+    return SolveResult(dist, int(st.phases), st.as_dict(), po, None)
 
 
 def delta_step(g: DeviceGraph, source: int, delta: int, dist=None) -> SolveResult:

@@ -73,6 +73,7 @@ struct alignas(128) CtlHead {
     unsigned long long fbucket;     // |F| at the start of the bucket in progress (feature input)
     unsigned long long next_delta;  // learned Delta-stepping: width of the next bucket
     unsigned long long last_settled;// |S'| of the last phase (selector feature input)
+    unsigned int stalled;           // a phase with F non-empty certified nothing (bad ORACLE reference)
 };
 
 // Device control block of one solve. Slots indexed by phase parity (mod 2 or

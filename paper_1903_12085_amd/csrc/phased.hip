@@ -41,6 +41,7 @@ struct KArgs {
     uint32_t crit;
     const float *mlp_w;  // learned mode: selector weights (device)
     double wm;           // learned mode: mean edge weight (feature scale)
+    const unsigned long long *ref;  // ORACLE mode: dist(s, .) of this source (device)
 };
 
 static __device__ const uint32_t kChoiceCrit[3] = {SSSP_IN_STATIC | SSSP_OUT_STATIC, SSSP_IN_SIMPLE | SSSP_OUT_SIMPLE,
@@ -163,6 +164,7 @@ __global__ __launch_bounds__(64) void k_init_choice(KArgs a, uint32_t src, int d
 // buffer fills, a wavefront appends straight to its shard instead.
 
 constexpr int kAppendBuf = 512;
+constexpr int kInOracle = 4;  // identify template value of the ORACLE criterion
 
 struct AppendLds {
     uint32_t row[kAppendBuf];
@@ -494,7 +496,8 @@ __global__ __launch_bounds__(kBlock) void k_terms_learned(KArgs a, int par) {
 // ---------------------------------------------------------------------------
 // identify (phased)
 
-// IN: IN_NONE, IN_DIJK, IN_STATIC_M, or 3 = "flag from the term pass".
+// IN: IN_NONE, IN_DIJK, IN_STATIC_M, 3 = "flag from the term pass", or
+// kInOracle = the clairvoyant criterion d[v] = dist(s, v) against a reference.
 // OUT: 0 none, 1 static threshold, 2 threshold from the term pass.
 // Each lane owns four consecutive vertices per step: one 32-bit state load,
 // then the distance / minima loads of all its queued vertices in flight at once.
@@ -633,6 +636,7 @@ __device__ __forceinline__ void identify_body(const KArgs &a, int par, unsigned 
                 if (IN == IN_DIJK) ok = dv[i] == minD;
                 else if (IN == IN_STATIC_M) ok = dv[i] <= sadd64(minD, w64(mm[i].x));
                 else if (IN == 3) ok = (s & ST_INOK) != 0;
+                else if (IN == kInOracle) ok = dv[i] == a.ref[v0 + i];  // Section 3: ORACLE(v)
                 if (OUT != 0) ok = ok || dv[i] <= T;
             }
             if (ok) {
@@ -1006,6 +1010,12 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
         if (i == 0) { s_tot_settled = tset; s_tot_edges = tedge; }
     }
     __syncthreads();
+    if (!DELTA && s_tot_settled == 0 && !done && blockIdx.x == 0 && threadIdx.x == 0) {
+        // F is non-empty but nothing was certified: only an ORACLE reference that is not
+        // dist(s, .) gets here (every other criterion certifies the queue minimum)
+        ctl->h.stalled = 1;
+        ctl->h.done = 1;
+    }
     if (s_tot_settled == 0 || done) return;
     int kind = 0;
     unsigned long long hi = INF64, delta = 0;
@@ -1401,6 +1411,16 @@ static PhaseKernels pick_phase(int chunk, int in, int out, bool delta, bool lear
     }
 }
 
+static PhaseKernels pick_oracle(int chunk) {
+    PhaseKernels k;
+    switch (chunk) {
+    case 256: k.identify = k_identify<kInOracle, 0, 256>; k.relax = k_relax<256, false, false, false>; break;
+    case 1024: k.identify = k_identify<kInOracle, 0, 1024>; k.relax = k_relax<1024, false, false, false>; break;
+    default: k.identify = k_identify<kInOracle, 0, 512>; k.relax = k_relax<512, false, false, false>; break;
+    }
+    return k;
+}
+
 static int valid_chunk(int c) { return c == 256 || c == 512 || c == 1024; }
 
 // Phase loop with an event before and after every kernel (profiling): one
@@ -1561,7 +1581,10 @@ static int finish_stats(const sssp_graph *g, const Ctl *dctl, sssp_stats *st, ui
     if (e != hipSuccess) { delete c; return sssp_set_error(SSSP_ERR_DEVICE, "control block copy: %s", hipGetErrorString(e)); }
     const unsigned long long reached = shard_sum(c->reached);
     int rc = SSSP_OK;
-    if (!c->h.done || reached != c->h.settled)
+    if (c->h.stalled)
+        rc = sssp_set_error(SSSP_ERR_INVALID, "a phase certified no vertex although F was not empty: the ORACLE "
+                                              "reference is not dist(source, .) of this graph");
+    else if (!c->h.done || reached != c->h.settled)
         rc = sssp_set_error(SSSP_ERR_INTERNAL, "solve ended in an inconsistent state (done=%u reached=%llu settled=%llu)",
                             c->h.done, reached, c->h.settled);
     if (phases) *phases = c->h.phases;
@@ -1583,8 +1606,9 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
                         const uint64_t *deltas, uint32_t n_deltas, uint64_t *dist_out,
                         sssp_stats *stats, uint32_t *phase_of, sssp_phase_rec *trace,
                         uint32_t trace_cap, const sssp_selector *sel = nullptr, float *feat_host = nullptr,
-                        uint32_t *cf_host = nullptr) {
+                        uint32_t *cf_host = nullptr, const uint64_t *oracle_ref = nullptr) {
     const bool learn = sel != nullptr;
+    const bool oracle = oracle_ref != nullptr;
     const bool trace_mode = learn && !delta_mode && cf_host != nullptr;
     if (!g) return sssp_set_error(SSSP_ERR_INVALID, "graph is NULL");
     if (!dist_out) return sssp_set_error(SSSP_ERR_INVALID, "dist_out is NULL");
@@ -1596,6 +1620,8 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
         out = OUT_FULL_M;
     } else if (learn) {
         // bucket widths come from the selector
+    } else if (oracle) {
+        // ORACLE: no term pass, no thresholds
     } else if (!delta_mode) {
         if (crit == 0 || (crit & ~SSSP_CRIT_ALL))
             return sssp_set_error(SSSP_ERR_INVALID, "criterion 0x%x is empty or has unknown bits", crit);
@@ -1634,6 +1660,7 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
     a.crit = crit;
     a.mlp_w = learn ? selector_device_weights(sel) : nullptr;
     a.wm = g->m ? (double)g->sum_w / (double)g->m : 1.0;
+    a.ref = (const unsigned long long *)oracle_ref;
     a.b.trace_feat = nullptr;
     a.b.trace_cf = nullptr;
     if (trace_cap) {
@@ -1648,7 +1675,7 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
                        g->ip, delta_mode ? a.b.stamp : nullptr);
     hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(64), 0, s, a.b.ctl, g->vmin, source, n_deltas);
     if (learn) hipLaunchKernelGGL(k_init_choice, dim3(1), dim3(64), 0, s, a, source, (int)delta_mode);
-    const PhaseKernels K = pick_phase(g->cfg.chunk, in, out, delta_mode, learn, trace_mode);
+    const PhaseKernels K = oracle ? pick_oracle(g->cfg.chunk) : pick_phase(g->cfg.chunk, in, out, delta_mode, learn, trace_mode);
     // phases <= reachable vertices; Delta rounds <= 2 * n + light rounds bounded by n per bucket
     // Delta: light rounds per bucket <= window vertices + 1, one heavy round per bucket
     const uint64_t max_phases = delta_mode ? 4ull * g->n + 64 : (uint64_t)g->n + 2;
@@ -1706,6 +1733,13 @@ extern "C" int sssp_delta_step_ex(sssp_graph *g, uint32_t source, const uint64_t
                                   uint64_t *dist_out, sssp_stats *stats, sssp_phase_rec *trace,
                                   uint32_t trace_cap) {
     return solve_common(g, source, true, 0, deltas, n_deltas, dist_out, stats, nullptr, trace, trace_cap);
+}
+
+extern "C" int sssp_solve_oracle(sssp_graph *g, uint32_t source, const uint64_t *dist_ref, uint64_t *dist_out,
+                                 sssp_stats *stats, uint32_t *phase_of) {
+    if (!dist_ref) return sssp_set_error(SSSP_ERR_INVALID, "dist_ref is NULL");
+    return solve_common(g, source, false, 0, nullptr, 0, dist_out, stats, phase_of, nullptr, 0, nullptr, nullptr,
+                        nullptr, dist_ref);
 }
 
 extern "C" int sssp_profile_enable(sssp_graph *g, int enable) {
