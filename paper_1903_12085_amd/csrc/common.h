@@ -151,6 +151,15 @@ static inline void sssp_host_free(void *p) {
     if (p) (void)hipHostFree(p);
 }
 
+// Owner of a device allocation made inside one call: freed on every return path.
+struct CallBuffer {
+    void *p = nullptr;
+    CallBuffer() = default;
+    CallBuffer(const CallBuffer &) = delete;
+    CallBuffer &operator=(const CallBuffer &) = delete;
+    ~CallBuffer() { sssp_free(p); }
+};
+
 #define HIP_OK(call)                                                                      \
     do {                                                                                  \
         hipError_t _e = (call);                                                           \

@@ -1663,11 +1663,15 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
     a.ref = (const unsigned long long *)oracle_ref;
     a.b.trace_feat = nullptr;
     a.b.trace_cf = nullptr;
+    CallBuffer trace_buf, feat_buf, cf_buf;  // freed on every return below
     if (trace_cap) {
-        HIP_OK(hipMalloc(&a.b.trace, (uint64_t)trace_cap * sizeof(PhaseRec)));
+        HIP_OK(hipMalloc(&trace_buf.p, (uint64_t)trace_cap * sizeof(PhaseRec)));
+        a.b.trace = (PhaseRec *)trace_buf.p;
         a.b.trace_cap = trace_cap;
-        if (feat_host) HIP_OK(hipMalloc(&a.b.trace_feat, (uint64_t)trace_cap * kMlpIn * sizeof(float)));
-        if (cf_host) HIP_OK(hipMalloc(&a.b.trace_cf, (uint64_t)trace_cap * 3 * sizeof(uint32_t)));
+        if (feat_host) HIP_OK(hipMalloc(&feat_buf.p, (uint64_t)trace_cap * kMlpIn * sizeof(float)));
+        if (cf_host) HIP_OK(hipMalloc(&cf_buf.p, (uint64_t)trace_cap * 3 * sizeof(uint32_t)));
+        a.b.trace_feat = (float *)feat_buf.p;
+        a.b.trace_cf = (uint32_t *)cf_buf.p;
     }
     const int ib = (int)(((uint64_t)g->n + 255) / 256 > 8192 ? 8192 : ((uint64_t)g->n + 255) / 256);
     hipLaunchKernelGGL(k_init_state, dim3(ib), dim3(256), 0, s, g->n, source, a.b.dist, a.b.st, phase_of,
@@ -1700,9 +1704,6 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
             hipMemcpy(cf_host, a.b.trace_cf, (uint64_t)cnt * 3 * sizeof(uint32_t), hipMemcpyDeviceToHost) != hipSuccess)
             rc = sssp_set_error(SSSP_ERR_DEVICE, "count trace copy failed");
     }
-    sssp_free(a.b.trace_feat);
-    sssp_free(a.b.trace_cf);
-    if (a.b.trace) sssp_free(a.b.trace);
     return rc;
 }
 
