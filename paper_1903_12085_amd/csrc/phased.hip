@@ -1557,7 +1557,7 @@ static int run_loop(sssp_graph *g, const KArgs &a, const PhaseKernels &K, uint64
         }
         have_prev = true;
         slot ^= 1;
-        if (batch < 48) batch *= 2;
+        if (batch < 16) batch *= 2;
         if (k > max_phases + 2 * 64 + 8)
             return sssp_set_error(SSSP_ERR_INTERNAL, "phase loop did not terminate after %llu phases",
                                   (unsigned long long)k);
