@@ -1577,7 +1577,9 @@ static unsigned long long shard_sum(const Sharded &x) {
 static int finish_stats(const sssp_graph *g, const Ctl *dctl, sssp_stats *st, uint32_t *phases) {
     Ctl *c = new (std::nothrow) Ctl;
     if (!c) return sssp_set_error(SSSP_ERR_OOM, "host control block");
-    hipError_t e = hipMemcpy(c, dctl, sizeof(Ctl), hipMemcpyDeviceToHost);
+    // on the solve's stream: the copy waits for this solve only, not for other streams' work
+    hipError_t e = hipMemcpyAsync(c, dctl, sizeof(Ctl), hipMemcpyDeviceToHost, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
     if (e != hipSuccess) { delete c; return sssp_set_error(SSSP_ERR_DEVICE, "control block copy: %s", hipGetErrorString(e)); }
     const unsigned long long reached = shard_sum(c->reached);
     int rc = SSSP_OK;
@@ -1693,16 +1695,16 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
     if (rc == SSSP_OK) rc = finish_stats(g, a.b.ctl, stats, &phases);
     if (rc == SSSP_OK && trace_cap) {
         const uint32_t cnt = phases < trace_cap ? phases : trace_cap;
-        if (cnt && hipMemcpy(trace, a.b.trace, cnt * sizeof(PhaseRec), hipMemcpyDeviceToHost) != hipSuccess)
-            rc = sssp_set_error(SSSP_ERR_DEVICE, "trace copy failed");
         const uint32_t fcnt = delta_mode ? (stats ? stats->buckets : 0) : cnt;
         const uint32_t fc = fcnt < trace_cap ? fcnt : trace_cap;
-        if (rc == SSSP_OK && feat_host && fc &&
-            hipMemcpy(feat_host, a.b.trace_feat, (uint64_t)fc * kMlpIn * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
-            rc = sssp_set_error(SSSP_ERR_DEVICE, "feature trace copy failed");
-        if (rc == SSSP_OK && cf_host && cnt &&
-            hipMemcpy(cf_host, a.b.trace_cf, (uint64_t)cnt * 3 * sizeof(uint32_t), hipMemcpyDeviceToHost) != hipSuccess)
-            rc = sssp_set_error(SSSP_ERR_DEVICE, "count trace copy failed");
+        hipError_t e = hipSuccess;
+        if (cnt) e = hipMemcpyAsync(trace, a.b.trace, cnt * sizeof(PhaseRec), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess && feat_host && fc)
+            e = hipMemcpyAsync(feat_host, a.b.trace_feat, (uint64_t)fc * kMlpIn * sizeof(float), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess && cf_host && cnt)
+            e = hipMemcpyAsync(cf_host, a.b.trace_cf, (uint64_t)cnt * 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) rc = sssp_set_error(SSSP_ERR_DEVICE, "trace copy failed: %s", hipGetErrorString(e));
     }
     return rc;
 }
