@@ -69,7 +69,7 @@ def _L():
             lib.orc_bellman_ford.argtypes = [u32, P, P, P, u32, P]
             lib.orc_static_minima.argtypes = [u32, P, P, P, P, P]
             lib.orc_phased.argtypes = [u32, P, P, P, u32, u32, P, u32, i, P, P,
-                                       ctypes.POINTER(_Stats), u32, P, P, P, P, P, P, P, P, P]
+                                       ctypes.POINTER(_Stats), u32, P, P, P, P, P, P, P, P, P, u32]
             lib.orc_delta_step.argtypes = [u32, P, P, P, u32, P, u32, P, ctypes.POINTER(_DStats), u32, P, P]
             lib.orc_features.argtypes = [P, ctypes.c_double, i, P]
             lib.orc_features.restype = None
@@ -151,11 +151,11 @@ _ERRS = {-1: "invalid argument", -2: "out of memory", -10: "unsound: certified v
 
 
 def phased(g, src: int, crit: int, crit_seq=None, check: bool = False, dist_ref=None,
-           trace_cap: int | None = None, mlp_w=None) -> PhasedResult:
+           trace_cap: int | None = None, mlp_w=None, commit: int = 0) -> PhasedResult:
     """Generic phased algorithm of Section 3 with the given criterion bits.
 
     mlp_w: float32[5382] selector weights; the criterion of each phase is then the selector's
-    choice on that phase's features (crit is ignored)."""
+    choice (crit is ignored). commit = K > 0: the choice made for phase K is kept from then on."""
     n, rp, col, w = _csr(g)
     mw = None if mlp_w is None else np.ascontiguousarray(mlp_w, np.float32)
     cap = n if trace_cap is None else trace_cap
@@ -173,7 +173,7 @@ def phased(g, src: int, crit: int, crit_seq=None, check: bool = False, dist_ref=
     rc = _L().orc_phased(n, _p(rp), _p(col), _p(w), src, crit, _p(seq), 0 if seq is None else len(seq),
                          int(check), _p(None if dist_ref is None else np.ascontiguousarray(dist_ref, np.uint64)),
                          _p(dist), ctypes.byref(st), cap, _p(tf), _p(ts), _p(tm), _p(tc), _p(po), _p(mw), _p(tcr),
-                         _p(tun), _p(tft))
+                         _p(tun), _p(tft), int(commit))
     if rc != 0:
         raise OracleError("orc_phased: %s (%d)" % (_ERRS.get(rc, "?"), rc))
     k = min(st.phases, cap)

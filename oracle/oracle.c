@@ -504,13 +504,16 @@ static int chain_ok(uint32_t b) {
  *             ALL_BITS).
  *   phase_of  optional: 1-based phase in which each vertex was settled, 0 if
  *             never (unreachable).
+ *   mlp_w     optional selector weights: each phase's criterion is the
+ *             selector's choice (crit is ignored); with commit = K > 0 the
+ *             choice made for phase K is kept for all later phases.
  */
 int orc_phased(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32_t *w, uint32_t src,
                uint32_t crit, const uint32_t *crit_seq, uint32_t seq_len, int check,
                const uint64_t *dist_ref, uint64_t *dist_out, orc_stats *stats, uint32_t trace_cap,
                uint32_t *trace_f, uint32_t *trace_s, uint64_t *trace_mind, uint32_t *trace_counts,
                uint32_t *phase_of, const float *mlp_w, uint32_t *trace_crit, uint32_t *trace_union,
-               float *trace_feat) {
+               float *trace_feat, uint32_t commit) {
     if (src >= n || (crit == 0 && !crit_seq && !mlp_w) || (crit & ~C_ALL)) return ORC_EINVAL;
     int rc = ORC_OK;
     csc_t c = {0, 0, 0};
@@ -591,8 +594,9 @@ int orc_phased(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32
             if (trace_counts) memcpy(trace_counts + 8ull * k, cnt, sizeof cnt);
             if (trace_union) memcpy(trace_union + 3ull * k, uni, sizeof uni);
         }
-        if (mlp_w) {
-            /* the selector for phase k+1, on phase k's snapshot and outcome */
+        if (mlp_w && (!commit || k + 1 <= commit)) {
+            /* the selector for phase k+1, on phase k's snapshot and outcome (with a commit phase
+             * K > 0, phase K's choice is kept for every later phase) */
             uint64_t SD = 0, DG = 0;
             for (uint64_t i = 0; i < nF; ++i) { SD += d[Fl[i]]; DG += rp[Fl[i] + 1] - rp[Fl[i]]; }
             feat_in q = {n, rp[n], nF, settled, nF + settled, T.minD, T.t_out_static, SD, DG, prevF, nF, nS, nin,

@@ -156,3 +156,29 @@ def test_features_match_independent_simulation():
         lr = O.phased(g, 0, 0, mlp_w=constant_net(0))
         assert lr.trace_feat.shape == ref.shape
         assert np.array_equal(lr.trace_feat, ref)
+
+
+def mixed_net(seed):
+    """Float64-reference initialisation with large output biases jittered so that several
+    criteria win on different states."""
+    w = M.init_params(seed).astype(np.float32)
+    rng = np.random.default_rng(seed)
+    w[-6:-3] = rng.normal(0, 0.5, 3).astype(np.float32)
+    return w
+
+
+@pytest.mark.parametrize("commit", [1, 5, 12])
+def test_commit_keeps_the_choice_of_phase_k(commit):
+    for seed, g in enumerate((G.er(800, 6, 1, 500, 21), G.grid(20, 15, 1, 40, 22), G.rmat(10, 8, 1, 1000, 23))):
+        w = mixed_net(seed + 3)
+        free = O.phased(g, 0, 0, mlp_w=w, trace_cap=g.n)
+        com = O.phased(g, 0, 0, mlp_w=w, commit=commit, trace_cap=g.n)
+        k = min(commit, com.phases)
+        # phases before K choose exactly as without commit; from K on, phase K's choice stays
+        assert np.array_equal(com.trace_crit[:k], free.trace_crit[:k])
+        if com.phases > commit:
+            assert (com.trace_crit[commit:] == com.trace_crit[commit]).all()
+        # the run equals the fixed per-phase sequence it recorded (the crit_seq path)
+        seq = O.phased(g, 0, 0, crit_seq=com.trace_crit)
+        assert seq.phases == com.phases and np.array_equal(seq.dist, com.dist)
+        assert np.array_equal(seq.phase_of, com.phase_of)
