@@ -124,6 +124,8 @@ def bench_learned(B, torch, G, dg, src, m_reach, plain_ms):
     ref = B.to_u64(B.solve(dg, src, B.STATIC_OR, B.new_dist(dg.n)).dist)
     tl, r = timed(lambda: B.solve_learned(dg, src, sel, dist))
     exact = bool(np.array_equal(B.to_u64(r.dist), ref))
+    tc, rc = timed(lambda: B.solve_learned(dg, src, sel, dist, commit=S.COMMIT_PHASES))
+    exact = exact and bool(np.array_equal(B.to_u64(rc.dist), ref))
     td, rd = timed(lambda: B.delta_step_learned(dg, src, sel, dist))
     exact = exact and bool(np.array_equal(B.to_u64(rd.dist), ref))
     res = {"weights": "selector_weights.npy (trained on random 2^16..2^21, R-MAT 16..20, grids 256^2..1024^2; "
@@ -131,6 +133,9 @@ def bench_learned(B, torch, G, dg, src, m_reach, plain_ms):
            "headline": {"learned_ms": round(tl * 1e3, 3), "learned_phases": r.phases,
                         "learned_gteps": round(m_reach / tl / 1e9, 4), "plain_ms": round(plain_ms, 3),
                         "learned_over_plain": round(tl * 1e3 / plain_ms, 3),
+                        "learned_commit_ms": round(tc * 1e3, 3), "learned_commit_phases": rc.phases,
+                        "commit_after": S.COMMIT_PHASES,
+                        "learned_commit_over_plain": round(tc * 1e3 / plain_ms, 3),
                         "learned_delta_ms": round(td * 1e3, 3), "learned_delta_rounds": rd.phases,
                         "learned_delta_gteps": round(m_reach / td / 1e9, 4)}}
     for g in S.evaluation_graphs()[1:]:
@@ -139,11 +144,14 @@ def bench_learned(B, torch, G, dg, src, m_reach, plain_ms):
         e = S.evaluate(sel, h, s)
         ref = B.to_u64(B.solve(h, s, B.STATIC_OR).dist)
         e["distances_exact"] = bool(np.array_equal(B.to_u64(B.solve_learned(h, s, sel).dist), ref) and
+                                    np.array_equal(B.to_u64(B.solve_learned(h, s, sel, commit=S.COMMIT_PHASES).dist),
+                                                   ref) and
                                     np.array_equal(B.to_u64(B.delta_step_learned(h, s, sel).dist), ref))
         exact = exact and e["distances_exact"]
         fixed = [e["static_or_ms"], e["simple_or_ms"], e["full_or_ms"]]
         e["learned_over_best_fixed"] = round(e["learned_ms"] / min(fixed), 3)
         e["learned_over_mean_fixed"] = round(e["learned_ms"] / (sum(fixed) / 3), 3)
+        e["learned_commit_over_best_fixed"] = round(e["learned_commit_ms"] / min(fixed), 3)
         res[g.name] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in e.items()}
         del h
     res["distances_exact"] = exact

@@ -311,6 +311,22 @@ int sssp_selector_train(sssp_selector *s, const float *x, const int32_t *y, uint
 int sssp_solve_learned(sssp_graph *g, uint32_t source, const sssp_selector *sel, uint64_t *dist_out,
                        sssp_stats *stats, uint32_t *phase_of, sssp_phase_rec *trace, uint32_t trace_cap);
 
+/*
+ * Learned phased SSSP with the choice committed after a prefix: the selector
+ * chooses the criteria of phases 0 .. commit_phase - 1 one by one, exactly as
+ * sssp_solve_learned does, and every later phase uses the criterion it chose
+ * for phase commit_phase, run by that criterion's plain kernels (no per-phase
+ * features or network after the prefix). This trades the selector's per-phase
+ * cost against adapting late in the solve, the accuracy-versus-overhead
+ * question that the paper's concluding remarks (Section 7) leave open. commit_phase >= 1
+ * (SSSP_ERR_INVALID otherwise). The host reads the control block once, after
+ * the prefix. Distances are those of every other solver; other arguments as
+ * sssp_solve_ex.
+ */
+int sssp_solve_learned_commit(sssp_graph *g, uint32_t source, const sssp_selector *sel, uint32_t commit_phase,
+                              uint64_t *dist_out, sssp_stats *stats, uint32_t *phase_of, sssp_phase_rec *trace,
+                              uint32_t trace_cap);
+
 /* Delta-stepping whose bucket width is chosen per bucket by the selector. */
 int sssp_delta_step_learned(sssp_graph *g, uint32_t source, const sssp_selector *sel, uint64_t *dist_out,
                             sssp_stats *stats, sssp_phase_rec *trace, uint32_t trace_cap);

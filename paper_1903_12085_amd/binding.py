@@ -30,7 +30,8 @@ SYMBOLS = ["sssp_graph_create", "sssp_graph_destroy", "sssp_set_stream", "sssp_g
            "sssp_solve_batch_ex", "sssp_batch_set_config", "sssp_batch_get_config", "sssp_autotune",
            "sssp_autotune_batch", "sssp_selector_create", "sssp_selector_destroy", "sssp_selector_get_weights",
            "sssp_selector_set_weights", "sssp_selector_forward", "sssp_selector_grad", "sssp_selector_train",
-           "sssp_solve_learned", "sssp_delta_step_learned", "sssp_trace_learned"]
+           "sssp_solve_learned", "sssp_delta_step_learned", "sssp_trace_learned",
+           "sssp_solve_learned_commit"]
 
 ERRORS = {-1: "SSSP_ERR_INVALID", -2: "SSSP_ERR_OOM", -3: "SSSP_ERR_DEVICE", -4: "SSSP_ERR_UNSUPPORTED",
           -5: "SSSP_ERR_INTERNAL"}
@@ -121,6 +122,7 @@ def load(path: str = LIB_PATH):
     lib.sssp_selector_grad.argtypes = [P, P, P, u32, f32p, P]
     lib.sssp_selector_train.argtypes = [P, P, P, u32, u32, u32, ctypes.c_float, u64, f32p]
     lib.sssp_solve_learned.argtypes = [P, u32, P, P, ctypes.POINTER(Stats), P, P, u32]
+    lib.sssp_solve_learned_commit.argtypes = [P, u32, P, u32, P, ctypes.POINTER(Stats), P, P, u32]
     lib.sssp_delta_step_learned.argtypes = [P, u32, P, P, ctypes.POINTER(Stats), P, u32]
     lib.sssp_trace_learned.argtypes = [P, u32, P, i, P, ctypes.POINTER(Stats), u32, P, P, P]
     lib.sssp_last_error.restype = ctypes.c_char_p
@@ -423,15 +425,23 @@ class Selector:
 
 
 def solve_learned(g: DeviceGraph, source: int, sel: Selector, dist=None, phase_of: bool = False,
-                  trace_cap: int = 0) -> SolveResult:
+                  trace_cap: int = 0, commit: int = 0) -> SolveResult:
+    """commit = 0: the selector chooses every phase (sssp_solve_learned); commit = K >= 1: it
+    chooses phases 0 .. K - 1, then phase K's choice holds (sssp_solve_learned_commit)."""
     import torch
     dist = new_dist(g.n) if dist is None else dist
     po = torch.empty(g.n, dtype=torch.int32, device="cuda") if phase_of else None
     tr = np.zeros(trace_cap, PHASE_REC) if trace_cap else None
     st = Stats()
     g._bind_stream()
-    _check(load().sssp_solve_learned(g.handle, source, sel.handle, ctypes.c_void_p(dist.data_ptr()), ctypes.byref(st),
-                                     ctypes.c_void_p(po.data_ptr()) if po is not None else None, _np_ptr(tr), trace_cap))
+    po_p = ctypes.c_void_p(po.data_ptr()) if po is not None else None
+    if commit:
+        _check(load().sssp_solve_learned_commit(g.handle, source, sel.handle, int(commit),
+                                                ctypes.c_void_p(dist.data_ptr()), ctypes.byref(st), po_p,
+                                                _np_ptr(tr), trace_cap))
+    else:
+        _check(load().sssp_solve_learned(g.handle, source, sel.handle, ctypes.c_void_p(dist.data_ptr()),
+                                         ctypes.byref(st), po_p, _np_ptr(tr), trace_cap))
     if tr is not None:
         tr = tr[:min(st.phases, trace_cap)]
     return SolveResult(dist, int(st.phases), st.as_dict(), po, tr)

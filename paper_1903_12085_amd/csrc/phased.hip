@@ -47,6 +47,12 @@ struct KArgs {
 static __device__ const uint32_t kChoiceCrit[3] = {SSSP_IN_STATIC | SSSP_OUT_STATIC, SSSP_IN_SIMPLE | SSSP_OUT_SIMPLE,
                                                   SSSP_IN_FULL | SSSP_OUT_FULL};
 
+// Host side of kChoiceCrit (same order).
+static uint32_t choice_criterion(unsigned int c) {
+    return c == 0 ? (SSSP_IN_STATIC | SSSP_OUT_STATIC) : c == 1 ? (SSSP_IN_SIMPLE | SSSP_OUT_SIMPLE)
+                                                                : (SSSP_IN_FULL | SSSP_OUT_FULL);
+}
+
 __device__ __forceinline__ unsigned long long *slot_of(Sharded &s, int i) { return &s.v[i * kPad]; }
 __device__ __forceinline__ int my_shard() { return (int)(blockIdx.x % kShards); }
 
@@ -1424,8 +1430,11 @@ static PhaseKernels pick_oracle(int chunk) {
 static int valid_chunk(int c) { return c == 256 || c == 512 || c == 1024; }
 
 // Phase loop with an event before and after every kernel (profiling): one
-// batch at a time, durations summed over the non-empty phases.
-static int run_loop_profiled(sssp_graph *g, const KArgs &a, const PhaseKernels &K, uint64_t max_phases) {
+// batch at a time, durations summed over the non-empty phases. Phases k0 ..
+// k_stop - 1 at most; a run that starts at k0 > 0 adds to the previous run's
+// figures. On stopping at k_stop, *head gets the control header it left.
+static int run_loop_profiled(sssp_graph *g, const KArgs &a, const PhaseKernels &K, uint64_t max_phases,
+                             uint64_t k0, uint64_t k_stop, CtlHead *head) {
     constexpr uint32_t kBatch = 64;
     hipStream_t s = g->stream;
     if (g->pev_cap < 4 * kBatch) {
@@ -1435,12 +1444,13 @@ static int run_loop_profiled(sssp_graph *g, const KArgs &a, const PhaseKernels &
         g->pev_cap = 4 * kBatch;
     }
     sssp_kernel_profile pr{};
-    g->phase_ms.clear();
+    if (k0) pr = g->last_prof;
+    else g->phase_ms.clear();
     const dim3 blk(kBlock), gs(g->cfg.scan_blocks), gr(g->cfg.relax_blocks);
-    uint64_t k = 0;
+    uint64_t k = k0;
     for (;;) {
-        const uint64_t k0 = k;
-        for (uint32_t i = 0; i < kBatch; ++i, ++k) {
+        const uint64_t kb = k;
+        for (uint32_t i = 0; i < kBatch && k < k_stop; ++i, ++k) {
             const int par = (int)(k % 6);
             hipEvent_t *e = &g->pev[4 * i];
             HIP_OK(hipEventRecord(e[0], s));
@@ -1456,7 +1466,7 @@ static int run_loop_profiled(sssp_graph *g, const KArgs &a, const PhaseKernels &
         HIP_OK(hipMemcpyAsync(&g->h_ctl[0], a.b.ctl, sizeof(CtlHead), hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
         const uint64_t real = g->h_ctl[0].phases;
-        for (uint32_t i = 0; i < kBatch && k0 + i < real; ++i) {
+        for (uint32_t i = 0; kb + i < k && kb + i < real; ++i) {
             float t0 = 0, t1 = 0, t2 = 0;
             hipEvent_t *e = &g->pev[4 * i];
             HIP_OK(hipEventElapsedTime(&t0, e[0], e[1]));
@@ -1469,6 +1479,10 @@ static int run_loop_profiled(sssp_graph *g, const KArgs &a, const PhaseKernels &
             g->phase_ms.push_back((K.terms ? t0 : 0.f) + t1 + t2);
         }
         if (g->h_ctl[0].done) break;
+        if (k >= k_stop) {
+            if (head) *head = g->h_ctl[0];
+            break;
+        }
         if (k > max_phases + 2 * kBatch)
             return sssp_set_error(SSSP_ERR_INTERNAL, "phase loop did not terminate after %llu phases",
                                   (unsigned long long)k);
@@ -1521,36 +1535,49 @@ static int ensure_phase_graph(sssp_graph *g, const KArgs &a, const PhaseKernels 
 
 // Runs the phase loop: queues phases in growing batches, keeps one batch in
 // flight while the host inspects the previous batch's copy of the control
-// block, and stops once a batch ends with F empty.
-static int run_loop(sssp_graph *g, const KArgs &a, const PhaseKernels &K, uint64_t max_phases) {
-    if (g->prof) return run_loop_profiled(g, a, K, max_phases);
-    if (g->cfg.use_graph) {
+// block, and stops once a batch ends with F empty. Phases k0 .. k_stop - 1 at
+// most (a run may continue another one's phases); phases whose index is a
+// multiple of six start a captured six-phase graph when graphs are enabled.
+// On stopping at k_stop, *head gets the control header the last phase left.
+static int run_loop(sssp_graph *g, const KArgs &a, const PhaseKernels &K, uint64_t max_phases, uint64_t k0 = 0,
+                    uint64_t k_stop = UINT64_MAX, CtlHead *head = nullptr) {
+    if (g->prof) return run_loop_profiled(g, a, K, max_phases, k0, k_stop, head);
+    const bool graphs = g->cfg.use_graph;
+    if (graphs) {
         int rc = ensure_phase_graph(g, a, K);
         if (rc) return rc;
     }
     hipStream_t s = g->stream;
     const dim3 blk(kBlock);
     const dim3 gs(g->cfg.scan_blocks), gr(g->cfg.relax_blocks);
-    uint64_t k = 0;
-    uint32_t batch = g->cfg.use_graph ? kGraphPhases : 4;
+    uint64_t k = k0;
+    uint32_t batch = graphs ? kGraphPhases : 4;
     int slot = 0;
     bool have_prev = false;
     for (;;) {
-        if (g->cfg.use_graph) {
-            for (uint32_t i = 0; i < batch; i += kGraphPhases, k += kGraphPhases)
+        for (uint32_t i = 0; i < batch && k < k_stop;) {
+            if (graphs && k % kGraphPhases == 0 && k + kGraphPhases <= k_stop) {
                 HIP_OK(hipGraphLaunch(g->graph_exec, s));
-        } else {
-            for (uint32_t i = 0; i < batch; ++i, ++k) {
-                const int par = (int)(k % 6);
-                if (K.terms) hipLaunchKernelGGL(K.terms, gs, blk, 0, s, a, par);
-                hipLaunchKernelGGL(K.identify, gs, blk, 0, s, a, par);
-                hipLaunchKernelGGL(K.relax, gr, blk, 0, s, a, par);
-                if (K.select) hipLaunchKernelGGL(K.select, dim3(1), dim3(64), 0, s, a, par);
+                i += kGraphPhases;
+                k += kGraphPhases;
+                continue;
             }
+            const int par = (int)(k % 6);
+            if (K.terms) hipLaunchKernelGGL(K.terms, gs, blk, 0, s, a, par);
+            hipLaunchKernelGGL(K.identify, gs, blk, 0, s, a, par);
+            hipLaunchKernelGGL(K.relax, gr, blk, 0, s, a, par);
+            if (K.select) hipLaunchKernelGGL(K.select, dim3(1), dim3(64), 0, s, a, par);
+            ++i;
+            ++k;
         }
         HIP_OK(hipGetLastError());
         HIP_OK(hipMemcpyAsync(&g->h_ctl[slot], a.b.ctl, sizeof(CtlHead), hipMemcpyDeviceToHost, s));
         HIP_OK(hipEventRecord(g->ev[slot], s));
+        if (k >= k_stop) {
+            HIP_OK(hipEventSynchronize(g->ev[slot]));
+            if (head) *head = g->h_ctl[slot];
+            break;
+        }
         if (have_prev) {
             HIP_OK(hipEventSynchronize(g->ev[slot ^ 1]));
             if (g->h_ctl[slot ^ 1].done) break;
@@ -1608,7 +1635,7 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
                         const uint64_t *deltas, uint32_t n_deltas, uint64_t *dist_out,
                         sssp_stats *stats, uint32_t *phase_of, sssp_phase_rec *trace,
                         uint32_t trace_cap, const sssp_selector *sel = nullptr, float *feat_host = nullptr,
-                        uint32_t *cf_host = nullptr, const uint64_t *oracle_ref = nullptr) {
+                        uint32_t *cf_host = nullptr, const uint64_t *oracle_ref = nullptr, uint32_t commit = 0) {
     const bool learn = sel != nullptr;
     const bool oracle = oracle_ref != nullptr;
     const bool trace_mode = learn && !delta_mode && cf_host != nullptr;
@@ -1616,6 +1643,8 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
     if (!dist_out) return sssp_set_error(SSSP_ERR_INVALID, "dist_out is NULL");
     if (source >= g->n) return sssp_set_error(SSSP_ERR_INVALID, "source %u >= n = %u", source, g->n);
     if (trace_cap && !trace) return sssp_set_error(SSSP_ERR_INVALID, "trace is NULL but trace_cap > 0");
+    if (commit && (!learn || delta_mode || trace_mode))
+        return sssp_set_error(SSSP_ERR_INVALID, "commit applies to the learned phased solver only");
     int in = IN_NONE, out = OUT_NONE;
     if (learn && !delta_mode) {
         in = IN_FULL_M;  // any of the three criteria may be chosen: CSC and cursors are needed
@@ -1685,7 +1714,26 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
     // phases <= reachable vertices; Delta rounds <= 2 * n + light rounds bounded by n per bucket
     // Delta: light rounds per bucket <= window vertices + 1, one heavy round per bucket
     const uint64_t max_phases = delta_mode ? 4ull * g->n + 64 : (uint64_t)g->n + 2;
-    rc = run_loop(g, a, K, max_phases);
+    if (commit) {
+        // the selector chooses phases 0 .. commit - 1 one by one (queued without
+        // graphs: they are few), then the rest run the plain kernels of the
+        // criterion it chose for phase `commit`
+        CtlHead h{};
+        const bool graphs = g->cfg.use_graph;
+        g->cfg.use_graph = false;
+        rc = run_loop(g, a, K, max_phases, 0, commit, &h);
+        g->cfg.use_graph = graphs;
+        if (rc == SSSP_OK && !h.done) {
+            KArgs a2 = a;
+            a2.crit = choice_criterion(h.choice[commit & 1]);
+            a2.mlp_w = nullptr;
+            int in2 = IN_NONE, out2 = OUT_NONE;
+            crit_modes(a2.crit, &in2, &out2);
+            rc = run_loop(g, a2, pick_phase(g->cfg.chunk, in2, out2, false, false, false), max_phases, commit);
+        }
+    } else {
+        rc = run_loop(g, a, K, max_phases);
+    }
     if (rc == SSSP_OK) {
         hipLaunchKernelGGL(k_clear_settled, dim3(ib), dim3(256), 0, s, g->n, a.b.dist);
         HIP_OK(hipGetLastError());
@@ -1791,6 +1839,15 @@ extern "C" int sssp_solve_learned(sssp_graph *g, uint32_t source, const sssp_sel
                                   sssp_stats *stats, uint32_t *phase_of, sssp_phase_rec *trace, uint32_t trace_cap) {
     if (!sel) return sssp_set_error(SSSP_ERR_INVALID, "selector is NULL");
     return solve_common(g, source, false, 0, nullptr, 0, dist_out, stats, phase_of, trace, trace_cap, sel);
+}
+
+extern "C" int sssp_solve_learned_commit(sssp_graph *g, uint32_t source, const sssp_selector *sel,
+                                         uint32_t commit_phase, uint64_t *dist_out, sssp_stats *stats,
+                                         uint32_t *phase_of, sssp_phase_rec *trace, uint32_t trace_cap) {
+    if (!sel) return sssp_set_error(SSSP_ERR_INVALID, "selector is NULL");
+    if (commit_phase == 0) return sssp_set_error(SSSP_ERR_INVALID, "commit_phase must be >= 1");
+    return solve_common(g, source, false, 0, nullptr, 0, dist_out, stats, phase_of, trace, trace_cap, sel, nullptr,
+                        nullptr, nullptr, commit_phase);
 }
 
 extern "C" int sssp_delta_step_learned(sssp_graph *g, uint32_t source, const sssp_selector *sel, uint64_t *dist_out,

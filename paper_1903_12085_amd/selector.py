@@ -131,13 +131,22 @@ def train(X, y, seed: int = 0, epochs: int = 60, batch: int = 256, lr: float = 3
     return sel, loss
 
 
+# Phases the selector chooses one by one in committed mode before its choice is kept.
+COMMIT_PHASES = 32
+
+
 def evaluate(sel, dg, src: int, reps: int = 2) -> dict:
-    """Learned solves against the fixed criteria / widths on one graph (times in ms)."""
+    """Learned solves (per phase, and committed after COMMIT_PHASES phases) against the fixed
+    criteria / widths on one graph (times in ms)."""
     dist = B.new_dist(dg.n)
     res = {}
     ph = []
     res["learned_ms"] = 1e3 * _timed(lambda: ph.append(B.solve_learned(dg, src, sel, dist).phases), reps)
     res["learned_phases"] = ph[-1]
+    ph = []
+    res["learned_commit_ms"] = 1e3 * _timed(
+        lambda: ph.append(B.solve_learned(dg, src, sel, dist, commit=COMMIT_PHASES).phases), reps)
+    res["learned_commit_phases"] = ph[-1]
     for name, crit in zip(("static_or", "simple_or", "full_or"), B.CHOICE_CRIT):
         ph = []
         res[name + "_ms"] = 1e3 * _timed(lambda: ph.append(B.solve(dg, src, crit, dist).phases), reps)

@@ -136,3 +136,42 @@ def test_trace_mode_delta_features_match_oracle(B):
     r, feat, _ = B.trace_learned(B.DeviceGraph.from_graph(g), 0, B.Selector(w), delta_mode=True)
     assert r.phases == ref.rounds and feat.shape[0] == ref.buckets
     assert np.array_equal(r.dist_u64(), ref.dist)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_learned_commit_matches_oracle_replay(B, seed):
+    # prefix of K selector choices, then phase K's choice on the plain kernels; with captured
+    # six-phase graphs on and off (K not a multiple of six starts the graphs mid-way), and with
+    # per-phase profiling (which runs its own loop)
+    w = mixed_weights(seed)
+    sel = B.Selector(w)
+    for g in (G.er(3000, 8, 1, 1000, seed), G.rmat(11, 16, 1, 1 << 16, seed), G.grid(40, 37, 1, 1 << 16, seed)):
+        dg = B.DeviceGraph.from_graph(g)
+        free = O.phased(g, 0, 0, mlp_w=w)
+        for commit in (1, 3, 7, 12, free.phases + 5):
+            ref = O.phased(g, 0, 0, mlp_w=w, commit=commit)
+            for use_graph, prof in ((0, False), (1, False), (1, True)):
+                dg.set_launch(use_graph=use_graph)
+                dg.profile(prof)
+                r = B.solve_learned(dg, 0, sel, phase_of=True, trace_cap=ref.phases + 4, commit=commit)
+                case = (g.name, commit, use_graph, prof)
+                assert np.array_equal(r.dist_u64(), ref.dist), case
+                assert r.phases == ref.phases, (case, r.phases, ref.phases)
+                assert np.array_equal(r.trace["criterion"], ref.trace_crit), case
+                assert np.array_equal(r.phase_of.cpu().numpy().view(np.uint32), ref.phase_of), case
+                if prof:
+                    assert len(dg.phase_times()) == ref.phases, case
+            dg.profile(False)
+
+
+def test_learned_commit_rejects_phase_zero_and_keeps_plain_solves_intact(B):
+    g = G.er(2000, 6, 1, 500, 9)
+    dg = B.DeviceGraph.from_graph(g)
+    sel = B.Selector(mixed_weights(9))
+    with pytest.raises(B.SsspError):
+        B._check(B.load().sssp_solve_learned_commit(dg.handle, 0, sel.handle, 0, None, None, None, None, 0))
+    # a plain solve after a committed one (shared cached graph, shared control block)
+    ref = O.phased(g, 0, O.STATIC_OR)
+    B.solve_learned(dg, 0, sel, commit=4)
+    r = B.solve(dg, 0, O.STATIC_OR)
+    assert np.array_equal(r.dist_u64(), ref.dist) and r.phases == ref.phases
