@@ -236,6 +236,11 @@ typedef struct {
     uint32_t relax_blocks;  /* blocks of the relax kernel */
     uint32_t chunk;         /* edges per relax chunk: 256, 512 or 1024 */
     uint32_t use_graph;     /* 1: replay phases from a captured HIP graph; 0: plain launches */
+    uint32_t queue;         /* criteria made of DIJK, IN_STATIC and OUT_STATIC only: 1 keeps the
+                               queued vertices with their distance and static minima in per-block
+                               queue arrays, so identify reads F itself instead of scanning the
+                               distance and minima arrays of all vertices; 0: that dense scan.
+                               Ignored by every other criterion and solver. */
 } sssp_launch_cfg;
 
 /* Read the launch shape used by later solves on g. */

@@ -13,7 +13,10 @@
 // Vertex state byte: low two bits = set membership, bit 2 = "IN test passed"
 // flag written by the dynamic-term pass for the current phase (bit 3: the IN
 // (full) test, written only by the trace-mode term pass, which evaluates both).
-enum : uint8_t { ST_U = 0, ST_F = 1, ST_S = 2, ST_R = 3, ST_SET = 3, ST_INOK = 4, ST_INOK_FULL = 8 };
+// Queue arrays only: bit 4 (ST_QNEW) = discovered by a relax since the vertex's
+// scan block last looked, bit 5 (ST_QDIRTY) = distance lowered since then.
+enum : uint8_t { ST_U = 0, ST_F = 1, ST_S = 2, ST_R = 3, ST_SET = 3, ST_INOK = 4, ST_INOK_FULL = 8, ST_QNEW = 16,
+                 ST_QDIRTY = 32 };
 
 // A settled vertex carries this bit in its distance word while the solve runs
 // (real distances stay below 2^58 and INF is all ones, so a word with the bit
@@ -38,6 +41,9 @@ static inline void crit_modes(uint32_t c, int *in, int *out) {
          : (c & SSSP_OUT_SIMPLE) ? OUT_SIMPLE_M : (c & SSSP_OUT_STATIC) ? OUT_STATIC_M : OUT_NONE;
     if (*in == IN_NONE && *out == OUT_NONE && (c & SSSP_DIJK)) *in = IN_DIJK;
 }
+
+// Criteria made of DIJK, IN-STATIC and OUT-STATIC only (the queue-array kernels).
+static inline bool static_modes(int in, int out) { return in <= IN_STATIC_M && out <= OUT_STATIC_M; }
 
 // Same-address device-scope atomics serialise (about 12 ns each on MI355X),
 // so every value that many blocks combine is spread over kShards slots, each
@@ -74,6 +80,7 @@ struct alignas(128) CtlHead {
     unsigned long long next_delta;  // learned Delta-stepping: width of the next bucket
     unsigned long long last_settled;// |S'| of the last phase (selector feature input)
     unsigned int stalled;           // a phase with F non-empty certified nothing (bad ORACLE reference)
+    unsigned int qlive[2];          // queue arrays: the phase with this parity left them current
 };
 
 // Device control block of one solve. Slots indexed by phase parity (mod 2 or
@@ -139,6 +146,13 @@ struct SolveBufs {
     uint32_t *trace_cf;     // trace mode: vertices each criterion certifies per phase, [cap][3]
     uint32_t *phase_of;
     unsigned long long *dist;
+    // Queue arrays (static criteria, launch option `queue`): scan block b keeps
+    // an entry for each queued vertex it owns in slots [b * qspan, (b+1) * qspan).
+    unsigned long long *qd; // distance of the entry's vertex (kTomb once it settled)
+    uint32_t *qv;           // the entry's vertex
+    uint2 *qm;              // its (minIn, minOut)
+    uint32_t *qcnt;         // per scan block: slots in use, then tombstones among them
+    uint32_t qspan;         // slots per scan block (vertices it owns)
 };
 
 int sssp_set_error(int code, const char *fmt, ...);
@@ -270,11 +284,12 @@ __device__ __forceinline__ void block_reduce(unsigned long long *v, unsigned lon
 constexpr int kBlock = 256;          // threads per block for the phase kernels
 constexpr int kWaves = kBlock / 64;
 
-// Launch shape chosen per graph (autotuned; see tune.cpp).
+// Launch shape chosen per graph (autotuned in tune.hip).
 struct LaunchCfg {
     int scan_blocks;    // blocks of the dense vertex-scan kernels
     int relax_blocks;   // blocks of the relax kernel
     int chunk;          // edges per relax chunk (256, 512 or 1024)
     int use_graph;      // replay phases from a captured HIP graph
+    int queue;          // static criteria: per-block queue arrays instead of the dense scan
 };
 constexpr int kMaxChunk = 2048;

@@ -42,5 +42,5 @@ struct sssp_graph {
 DevGraph dev_view(const sssp_graph *g);
 int graph_ensure_csc(sssp_graph *g);
 void graph_default_cfg(sssp_graph *g);
-int solve_bufs_ensure(sssp_graph *g, bool cursors, bool stamps);
+int solve_bufs_ensure(sssp_graph *g, bool cursors, bool stamps, bool queue);
 void solve_bufs_free(sssp_graph *g);

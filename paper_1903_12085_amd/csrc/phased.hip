@@ -502,6 +502,65 @@ __global__ __launch_bounds__(kBlock) void k_terms_learned(KArgs a, int par) {
 // ---------------------------------------------------------------------------
 // identify (phased)
 
+// Start of an identify pass, every block: with F empty (reached == settled)
+// block 0 marks the solve done, and the caller returns.
+__device__ __forceinline__ bool phase_done(Ctl *ctl, int p2, unsigned int P, unsigned long long reached,
+                                           unsigned long long settled) {
+    if (reached != settled) return false;
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) {
+            ctl->h.done = 1;
+            ctl->h.pnum[p2 ^ 1] = P;
+        }
+        shard_fill(ctl->spack[p2 ^ 1], 0);
+        shard_fill(ctl->szero[p2 ^ 1], 0);
+    }
+    return true;
+}
+
+// Start of a non-empty phase, block 0 only: header counters, the trace record
+// and the control slots that the next phases fill.
+template <bool LEARN, bool TRACE>
+__device__ __forceinline__ void phase_open(const KArgs &a, Ctl *ctl, int p2, int p3, unsigned int P,
+                                           unsigned long long reached, unsigned long long settled,
+                                           unsigned long long minD, unsigned long long dgall) {
+    if (threadIdx.x == 0) {
+        ctl->h.pnum[p2 ^ 1] = P + 1;
+        ctl->h.phases = P + 1;
+        ctl->h.sum_f += reached - settled;
+        if (LEARN) {
+            ctl->h.fprev = ctl->h.fk;
+            ctl->h.dgk = dgall - ctl->h.m_reach;
+        }
+        ctl->h.fk = reached - settled;
+        ctl->h.s_k = settled;
+        ctl->h.m_k = ctl->h.m_reach;
+        if (P < a.b.trace_cap) {
+            PhaseRec r;
+            r.min_d = minD;
+            r.fringe = (unsigned int)(reached - settled);
+            r.settled = 0;
+            r.criterion = LEARN ? kChoiceCrit[ctl->h.choice[p2]] : a.crit;
+            r.edges = 0;
+            a.b.trace[P] = r;
+        }
+    }
+    shard_fill(ctl->spack[p2 ^ 1], 0);
+    shard_fill(ctl->szero[p2 ^ 1], 0);
+    shard_fill(ctl->minD[(p3 + 2) % 3], INF64);
+    shard_fill(ctl->tst[(p3 + 2) % 3], INF64);
+    shard_fill(ctl->tdyn[(p3 + 1) % 3], INF64);
+    if (LEARN) {
+        shard_fill(ctl->sumd[(p3 + 2) % 3], 0);
+        shard_fill(ctl->nin[p2 ^ 1], 0);
+        shard_fill(ctl->nout[p2 ^ 1], 0);
+    }
+    if (TRACE) {
+        shard_fill(ctl->tdyn2[(p3 + 1) % 3], INF64);
+        for (int c = 0; c < 3; ++c) shard_fill(ctl->cnt_cf[(p2 ^ 1) * 3 + c], 0);
+    }
+}
+
 // IN: IN_NONE, IN_DIJK, IN_STATIC_M, 3 = "flag from the term pass", or
 // kInOracle = the clairvoyant criterion d[v] = dist(s, v) against a reference.
 // OUT: 0 none, 1 static threshold, 2 threshold from the term pass.
@@ -529,55 +588,11 @@ __device__ __forceinline__ void identify_body(const KArgs &a, int par, unsigned 
     const unsigned long long reached = wave_sum64(r0);
     const unsigned long long minD = wave_min64(m0);
     const unsigned long long T = OUT ? wave_min64(t0) : 0ull;
-    if (reached == settled) {
-        if (blockIdx.x == 0) {
-            if (threadIdx.x == 0) {
-                ctl->h.done = 1;
-                ctl->h.pnum[p2 ^ 1] = P;
-            }
-            shard_fill(ctl->spack[p2 ^ 1], 0);
-            shard_fill(ctl->szero[p2 ^ 1], 0);
-        }
-        return;
-    }
+    if (phase_done(ctl, p2, P, reached, settled)) return;
     if (blockIdx.x == 0) {
         // learned mode: sum over F of out-degrees = degrees of all ever queued minus those settled
         const unsigned long long dgall = LEARN ? wave_sum64(dg0) : 0ull;
-        if (threadIdx.x == 0) {
-            ctl->h.pnum[p2 ^ 1] = P + 1;
-            ctl->h.phases = P + 1;
-            ctl->h.sum_f += reached - settled;
-            if (LEARN) {
-                ctl->h.fprev = ctl->h.fk;
-                ctl->h.dgk = dgall - ctl->h.m_reach;
-            }
-            ctl->h.fk = reached - settled;
-            ctl->h.s_k = settled;
-            ctl->h.m_k = ctl->h.m_reach;
-            if (P < a.b.trace_cap) {
-                PhaseRec r;
-                r.min_d = minD;
-                r.fringe = (unsigned int)(reached - settled);
-                r.settled = 0;
-                r.criterion = LEARN ? kChoiceCrit[ctl->h.choice[p2]] : a.crit;
-                r.edges = 0;
-                a.b.trace[P] = r;
-            }
-        }
-        shard_fill(ctl->spack[p2 ^ 1], 0);
-        shard_fill(ctl->szero[p2 ^ 1], 0);
-        shard_fill(ctl->minD[(p3 + 2) % 3], INF64);
-        shard_fill(ctl->tst[(p3 + 2) % 3], INF64);
-        shard_fill(ctl->tdyn[(p3 + 1) % 3], INF64);
-        if (LEARN) {
-            shard_fill(ctl->sumd[(p3 + 2) % 3], 0);
-            shard_fill(ctl->nin[p2 ^ 1], 0);
-            shard_fill(ctl->nout[p2 ^ 1], 0);
-        }
-        if (TRACE) {
-            shard_fill(ctl->tdyn2[(p3 + 1) % 3], INF64);
-            for (int c = 0; c < 3; ++c) shard_fill(ctl->cnt_cf[(p2 ^ 1) * 3 + c], 0);
-        }
+        phase_open<LEARN, TRACE>(a, ctl, p2, p3, P, reached, settled, minD, dgall);
     }
     __syncthreads();  // LDS counters initialised
     unsigned long long fmin = INF64, ftst = INF64, fsum = 0, cin = 0, cout = 0, cc[3] = {0, 0, 0};
@@ -725,6 +740,260 @@ __global__ __launch_bounds__(kBlock) void k_identify_learned(KArgs a, int par) {
     __shared__ AppendLds L;
     if (a.b.ctl->h.choice[par & 1] == 0) identify_body<IN_STATIC_M, 1, CH, true>(a, par, sh, L);
     else identify_body<3, 2, CH, true>(a, par, sh, L);
+}
+
+// ---------------------------------------------------------------------------
+// identify over queue arrays (static criteria)
+
+constexpr unsigned long long kTomb = INF64;  // queue entry whose vertex has settled
+constexpr uint32_t kOwnSpan = 16 * kBlock;   // consecutive vertices a scan block owns per grid step
+constexpr uint32_t kQWin = 4 * kOwnSpan;     // most vertices a scan block may own (state window in LDS)
+
+// Queue-array identify for criteria made of DIJK, IN-STATIC and OUT-STATIC
+// (IN: IN_NONE, IN_DIJK or IN_STATIC_M; OUT: 0, or 1 = OUT-STATIC threshold).
+// Scan block b owns the vertices kOwnSpan * (k * G + b) + [0, kOwnSpan),
+// k = 0, 1, ... (G blocks), and keeps an entry (d, v, minIn, minOut) for each
+// of them that is queued, in slots [b * qspan, (b + 1) * qspan): a phase reads
+// those entries, 20 bytes per queued vertex, and the state bytes of the block's
+// vertices, instead of the distance and minima of every vertex. Relax flags a
+// vertex it discovers ST_QNEW and one whose distance it lowers ST_QDIRTY; the
+// owner gathers a new vertex's distance and minima once and gives it an entry
+// if it stays queued, and reloads a dirty entry's distance, so an entry holds
+// its vertex's distance at phase start. A settled entry becomes a tombstone; a
+// block whose slots hold more than a quarter of tombstones moves its live
+// entries down over them. Each vertex gets at most one entry, so a block's
+// slots never overflow.
+// With 3/8 or more of the vertices queued the entries cost about as much as
+// the dense scan (measured on random graphs), so such phases run the dense scan
+// (identify_body) and leave the arrays stale; the next queue phase rebuilds
+// them from the state bytes, as the first phase of a solve does. The switch
+// back waits until F is below 3/10 of the vertices, so that F sizes near the
+// threshold do not rebuild every other phase. Every block takes the same
+// decision from the phase-start counters.
+template <int IN, int OUT, int CH>
+__global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
+    __shared__ unsigned long long sh[8 * kWaves];
+    __shared__ AppendLds L;
+    __shared__ uint32_t s_wk[kWaves];  // compaction: entries each wavefront keeps in one step
+    __shared__ uint32_t s_app;         // entries appended to this block's slots in this pass
+    __shared__ uint4 s_st[kQWin / 16]; // state bytes of the block's vertices
+    Ctl *ctl = a.b.ctl;
+    const int p2 = par & 1, p3 = par % 3;
+    const unsigned long long r0 = lane_slot(ctl->reached, 0ull), m0 = lane_slot(ctl->minD[p3], INF64);
+    const unsigned long long t0 = OUT == 1 ? lane_slot(ctl->tst[p3], INF64) : 0ull;
+    const unsigned long long settled = ctl->h.settled;
+    const unsigned int live = ctl->h.qlive[p2];
+    const unsigned int P = ctl->h.pnum[p2];
+    const uint32_t n = a.g.n, b = blockIdx.x, G = gridDim.x;
+    const uint32_t cnt0 = live ? a.b.qcnt[2 * b] : 0u, tomb0 = live ? a.b.qcnt[2 * b + 1] : 0u;
+    const unsigned long long reached = wave_sum64(r0);
+    const unsigned long long nf = reached - settled;
+    const bool dense = live ? nf * 8 >= 3ull * n : nf * 10 >= 3ull * n;  // grid-uniform
+    if (dense) {
+        if (b == 0 && threadIdx.x == 0 && nf) ctl->h.qlive[p2 ^ 1] = 0;
+        identify_body<IN, OUT, CH, false>(a, par, sh, L);
+        return;
+    }
+    if (threadIdx.x == 0) { L.cnt = 0; L.filled = 0; L.zero = 0; s_app = 0; }
+    const unsigned long long minD = wave_min64(m0);
+    const unsigned long long T = OUT == 1 ? wave_min64(t0) : 0ull;
+    if (phase_done(ctl, p2, P, reached, settled)) return;
+    if (b == 0) {
+        phase_open<false, false>(a, ctl, p2, p3, P, reached, settled, minD, 0ull);
+        if (threadIdx.x == 0) ctl->h.qlive[p2 ^ 1] = 1;
+    }
+    // state bytes of the block's vertices into LDS (window w = the block's w-th grid step)
+    const uint32_t span = a.b.qspan;
+#pragma unroll 1
+    for (uint32_t w = 0; w * kOwnSpan < span; ++w) {
+        const uint64_t v0 = (uint64_t)kOwnSpan * ((uint64_t)w * G + b) + 16u * threadIdx.x;
+        uint4 x = make_uint4(0u, 0u, 0u, 0u);
+        if (v0 + 16 <= n) {
+            x = *reinterpret_cast<const uint4 *>(a.b.st + v0);
+        } else if (v0 < n) {
+            uint32_t q[4] = {0u, 0u, 0u, 0u};
+            for (uint32_t j = 0; v0 + j < n; ++j) q[j >> 2] |= (uint32_t)a.b.st[v0 + j] << (8 * (j & 3));
+            x = make_uint4(q[0], q[1], q[2], q[3]);
+        }
+        s_st[w * kBlock + threadIdx.x] = x;
+    }
+    __syncthreads();  // LDS counters and state window ready
+    const uint8_t *sw = reinterpret_cast<const uint8_t *>(s_st);
+    auto win_of = [&](uint32_t v) {  // LDS index of an owned vertex's state byte
+        const uint32_t step = ((v / kOwnSpan) - b) / G;
+        return step * kOwnSpan + (v % kOwnSpan);
+    };
+    unsigned long long fmin = INF64, ftst = INF64, ntomb = 0;
+    const uint64_t rb = (uint64_t)b * span;
+    unsigned long long *qd = a.b.qd + rb;
+    uint32_t *qv = a.b.qv + rb;
+    uint2 *qm = a.b.qm + rb;
+    auto certified = [&](unsigned long long d, uint2 mm) {
+        bool ok = false;
+        if (IN == IN_DIJK) ok = d == minD;
+        else if (IN == IN_STATIC_M) ok = d <= sadd64(minD, w64(mm.x));  // eq. crit:instatic
+        if (OUT == 1) ok = ok || d <= T;                                // eq. crit:outstatic
+        return ok;
+    };
+    auto settle = [&](uint32_t v, unsigned long long d, uint32_t &row, uint32_t &deg) {
+        a.b.st[v] = ST_S;
+        a.b.dist[v] = d | kSettledBit;
+        if (a.b.phase_of) a.b.phase_of[v] = P + 1;
+        row = a.g.rp[v];
+        deg = a.g.rp[v + 1] - row;
+    };
+    // 1. the block's entries, four consecutive ones per lane
+    const bool compact = tomb0 * 4u > cnt0;  // block-uniform
+    uint32_t kept = 0;                       // compaction: entries kept so far
+    for (uint32_t i0 = 0; i0 < cnt0; i0 += 4 * kBlock) {
+        const uint32_t i = i0 + 4 * threadIdx.x;
+        unsigned long long d[4];
+        uint32_t v[4];
+        uint2 mm[4];
+        if (i + 4 <= cnt0) {
+            const ulonglong2 *dp = reinterpret_cast<const ulonglong2 *>(qd + i);
+            const uint4 *mp = reinterpret_cast<const uint4 *>(qm + i);
+            const ulonglong2 d01 = dp[0], d23 = dp[1];
+            const uint4 vv = *reinterpret_cast<const uint4 *>(qv + i);
+            const uint4 m01 = mp[0], m23 = mp[1];
+            d[0] = d01.x; d[1] = d01.y; d[2] = d23.x; d[3] = d23.y;
+            v[0] = vv.x; v[1] = vv.y; v[2] = vv.z; v[3] = vv.w;
+            mm[0] = make_uint2(m01.x, m01.y); mm[1] = make_uint2(m01.z, m01.w);
+            mm[2] = make_uint2(m23.x, m23.y); mm[3] = make_uint2(m23.z, m23.w);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                d[j] = kTomb;
+                v[j] = 0;
+                mm[j] = make_uint2(INF32, INF32);
+                if (i + j < cnt0) {
+                    d[j] = qd[i + j];
+                    v[j] = qv[i + j];
+                    mm[j] = qm[i + j];
+                }
+            }
+        }
+        // entries whose distance a relax lowered: reload it, clear the flag
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (d[j] != kTomb && (sw[win_of(v[j])] & ST_QDIRTY)) {
+                d[j] = a.b.dist[v[j]];
+                if (!compact) qd[i + j] = d[j];
+                a.b.st[v[j]] = ST_F;
+            }
+        uint32_t sm = 0, keep = 0;
+        uint32_t row[4], deg[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            row[j] = deg[j] = 0;
+            if (d[j] == kTomb) continue;
+            if (certified(d[j], mm[j])) {
+                sm |= 1u << j;
+            } else {
+                keep |= 1u << j;
+                fmin = umin64(fmin, d[j]);
+                if (OUT == 1) ftst = umin64(ftst, sadd64(d[j], w64(mm[j].y)));
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if ((sm >> j) & 1u) settle(v[j], d[j], row[j], deg[j]);
+        append_settled_n<CH, 4>(a, ctl, p2, L, sm, row, deg, d);
+        if (!compact) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if ((sm >> j) & 1u) qd[i + j] = kTomb;
+            ntomb += (unsigned long long)__popc(sm);
+        } else {
+            // kept entries move down to [kept, kept + this step's count): below every slot a
+            // later step reads; this step's loads have all returned before the first barrier
+            const uint32_t kc = (uint32_t)__popc(keep);
+            const uint32_t incl = wave_incl_scan(kc);
+            const int w = threadIdx.x >> 6;
+            if ((threadIdx.x & 63) == 63) s_wk[w] = incl;
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            uint32_t wb = 0, tot = 0;
+#pragma unroll
+            for (int x = 0; x < kWaves; ++x) {
+                wb += x < w ? s_wk[x] : 0u;
+                tot += s_wk[x];
+            }
+            __syncthreads();  // s_wk is rewritten by the next step
+            uint32_t o = kept + wb + incl - kc;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if ((keep >> j) & 1u) {
+                    qd[o] = d[j];
+                    qv[o] = v[j];
+                    qm[o] = mm[j];
+                    ++o;
+                }
+            kept += tot;
+        }
+    }
+    const uint32_t cnt = compact ? kept : cnt0;  // block-uniform
+    // 2. vertices that need an entry: new ones, or (rebuild) every queued one; sixteen
+    // state bytes per lane from the LDS window
+    const int lane = threadIdx.x & 63;
+#pragma unroll 1
+    for (uint32_t w = 0; w * kOwnSpan < span; ++w) {
+        const uint64_t v0 = (uint64_t)kOwnSpan * ((uint64_t)w * G + b) + 16u * threadIdx.x;
+        if (v0 >= n && __ballot(v0 < n) == 0) break;  // wavefront-uniform
+        const uint4 x = s_st[w * kBlock + threadIdx.x];
+        const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
+        uint32_t nm = 0;  // bit j: vertex v0 + j needs an entry
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t sb = (xs[q] >> (8 * j)) & 0xffu;
+                if (live ? (sb & ST_QNEW) != 0 : (sb & ST_SET) == ST_F) nm |= 1u << (4 * q + j);
+            }
+        while (__ballot(nm != 0)) {  // wavefront-uniform: one vertex per lane per round
+            const bool has = nm != 0;
+            uint32_t v = 0, row = 0, deg = 0;
+            unsigned long long d = INF64;
+            uint2 mm = make_uint2(INF32, INF32);
+            if (has) {
+                v = (uint32_t)v0 + (uint32_t)(__ffs(nm) - 1);
+                nm &= nm - 1;
+                d = a.b.dist[v];
+                mm = a.g.vmin[v];
+            }
+            const bool ok = has && certified(d, mm);
+            if (ok) settle(v, d, row, deg);
+            append_settled<CH>(a, ctl, p2, L, ok, row, deg, d);
+            const bool app = has && !ok;
+            if (app) {
+                fmin = umin64(fmin, d);
+                if (OUT == 1) ftst = umin64(ftst, sadd64(d, w64(mm.y)));
+            }
+            const unsigned long long am = __ballot(app);
+            if (am) {
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(&s_app, (uint32_t)__popcll(am));
+                base = (uint32_t)__builtin_amdgcn_readlane((int)base, 0);
+                if (app) {
+                    const uint32_t o = cnt + base + (uint32_t)__popcll(am & ((1ull << lane) - 1ull));
+                    qd[o] = d;
+                    qv[o] = v;
+                    qm[o] = mm;
+                    a.b.st[v] = ST_F;
+                }
+            }
+        }
+    }
+    append_flush<CH>(a, ctl, p2, L);  // starts with a barrier: s_app is final after it
+    // [0] fmin, [1] ftst, [2] entries settled (tombstones made)
+    unsigned long long r[8] = {fmin, ftst, ntomb, 0, 0, 0, 0, 0};
+    block_reduce<kWaves, OUT == 1 ? 0x7u : 0x5u, 0x3u, 0x4u>(r, sh);
+    if (threadIdx.x == 0) {
+        a.b.qcnt[2 * b] = cnt + s_app;
+        a.b.qcnt[2 * b + 1] = compact ? 0u : tomb0 + (uint32_t)r[2];
+        if (r[0] != INF64) atomicMin(slot_of(ctl->minD[(p3 + 1) % 3], my_shard()), r[0]);
+        if (OUT == 1 && r[1] != INF64) atomicMin(slot_of(ctl->tst[(p3 + 1) % 3], my_shard()), r[1]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -983,7 +1252,10 @@ __device__ __forceinline__ void select_next_phase(const KArgs &a, int p2, int p3
 // over the queued set) for the next phase; in the phased solver block 0 only
 // evaluates the selector for phase k+1 and the other blocks take its share of
 // the edges.
-template <int CH, bool DELTA, bool FOLDT, bool LEARN>
+// Q: queue arrays are in use (static criteria): a discovered vertex is marked
+// ST_F | ST_QNEW and a vertex whose distance drops ST_QDIRTY, for its owner's
+// identify.
+template <int CH, bool DELTA, bool FOLDT, bool LEARN, bool Q = false>
 __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
     Ctl *ctl = a.b.ctl;
     const int p2 = par & 1, p3 = par % 3;
@@ -1158,8 +1430,14 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
                 if (prev != P + 1) ++winimp;
             }
             if (LEARN && !DELTA) dsum += old[k] == INF64 ? cand[k] : cand[k] - old[k];  // mod 2^64: sum over F of d
+            if (Q) {
+                // flag for the owner's identify: word-wide OR, as other lanes flag the same word
+                uint32_t *w = reinterpret_cast<uint32_t *>(a.b.st + (v & ~3u));
+                const uint32_t f = old[k] == INF64 ? (uint32_t)(ST_F | ST_QNEW) : (uint32_t)ST_QDIRTY;
+                atomicOr(w, f << (8 * (v & 3u)));
+            }
             if (old[k] == INF64) {
-                a.b.st[v] = ST_F;
+                if (!Q) a.b.st[v] = ST_F;
                 ++disc;
                 if (LEARN && !DELTA) ddeg += a.g.rp[v + 1] - a.g.rp[v];
             }
@@ -1276,12 +1554,14 @@ void graph_default_cfg(sssp_graph *g) {
     if (rb > (uint64_t)cus * 4) rb = (uint64_t)cus * 4;
     g->cfg.relax_blocks = (int)rb;
     g->cfg.use_graph = 0;
+    g->cfg.queue = 1;
 }
 
 void solve_bufs_free(sssp_graph *g) {
     SolveBufs &b = g->b;
     sssp_free(b.ctl); sssp_free(b.st); sssp_free(b.srow); sssp_free(b.soff); sssp_free(b.sdu);
     sssp_free(b.chunk_start); sssp_free(b.in_cur); sssp_free(b.out_cur); sssp_free(b.stamp); sssp_free(b.deltas);
+    sssp_free(b.qd); sssp_free(b.qv); sssp_free(b.qm); sssp_free(b.qcnt);
     if (g->h_ctl) sssp_host_free(g->h_ctl);
     for (uint32_t i = 0; i < g->pev_cap; ++i) (void)hipEventDestroy(g->pev[i]);
     delete[] g->pev;
@@ -1303,12 +1583,12 @@ void solve_bufs_free(sssp_graph *g) {
     g->delta_cap = 0;  // b.deltas was released with the rest
 }
 
-// Vertices a shard can settle in one phase: block b scans the vertex quads
-// q = b*kBlock + i + k*G*kBlock (vertices 4q..4q+3), shard = b % kShards, so
-// a shard owns at most ceil(G / kShards) blocks of at most
-// 4 * kBlock * ceil(ceil(n / 4) / (G * kBlock)) vertices each.
-// Most S' entries one shard can receive in a phase: the vertices its blocks
-// scan (4 vertices per lane in both identify kernels).
+// Vertices a shard can settle in one phase: block b of the dense scan owns
+// the vertex quads q = b*kBlock + i + k*G*kBlock (vertices 4q..4q+3); with
+// queue arrays it owns kOwnSpan = 16 * kBlock consecutive vertices per grid
+// step. Shard = b % kShards, so a shard owns at most ceil(G / kShards) blocks
+// of at most scan_span(n, G, vpl) = vpl * kBlock * ceil(ceil(n / vpl) / (G * kBlock))
+// vertices each (vpl = 4 or 16 vertices per lane).
 static uint64_t scan_span(uint32_t n, int G, uint64_t vpl) {
     const uint64_t nv = ((uint64_t)n + vpl - 1) / vpl;
     const uint64_t iters = (nv + (uint64_t)G * kBlock - 1) / ((uint64_t)G * kBlock);
@@ -1316,10 +1596,11 @@ static uint64_t scan_span(uint32_t n, int G, uint64_t vpl) {
 }
 static uint32_t shard_capacity(uint32_t n, int G) {
     const uint64_t blocks = ((uint64_t)G + kShards - 1) / kShards;
-    return (uint32_t)(blocks * scan_span(n, G, 4));
+    const uint64_t a = scan_span(n, G, 4), b = scan_span(n, G, 16);
+    return (uint32_t)(blocks * (a > b ? a : b));
 }
 
-int solve_bufs_ensure(sssp_graph *g, bool cursors, bool stamps) {
+int solve_bufs_ensure(sssp_graph *g, bool cursors, bool stamps, bool queue) {
     SolveBufs &b = g->b;
     const uint64_t n = g->n;
     if (g->bufs_ready && g->bufs_scan_blocks != (uint32_t)g->cfg.scan_blocks) {
@@ -1331,7 +1612,7 @@ int solve_bufs_ensure(sssp_graph *g, bool cursors, bool stamps) {
         b.chunk_cap = (uint32_t)(g->m / 256 + 2);  // every chunk size is >= 256 edges
         const uint64_t sent = (uint64_t)kShards * b.shard_cap;
         HIP_OK(hipMalloc(&b.ctl, sizeof(Ctl)));
-        HIP_OK(hipMalloc(&b.st, n));
+        HIP_OK(hipMalloc(&b.st, (n + 15) & ~15ull));  // whole words: relax ORs flags into 32-bit words
         HIP_OK(hipMalloc(&b.srow, sent * 4));
         HIP_OK(hipMalloc(&b.soff, sent * 4));
         HIP_OK(hipMalloc(&b.sdu, sent * 8));
@@ -1347,6 +1628,16 @@ int solve_bufs_ensure(sssp_graph *g, bool cursors, bool stamps) {
         HIP_OK(hipMalloc(&b.out_cur, n * 4));
     }
     if (stamps && !b.stamp) HIP_OK(hipMalloc(&b.stamp, n * 4));
+    if (queue && !b.qd) {
+        const uint64_t G = (uint64_t)g->cfg.scan_blocks;
+        const uint64_t span = scan_span(g->n, g->cfg.scan_blocks, 16);
+        if (G * span >= INF32) return sssp_set_error(SSSP_ERR_UNSUPPORTED, "queue arrays: too many slots");
+        b.qspan = (uint32_t)span;
+        HIP_OK(hipMalloc(&b.qd, G * span * 8));
+        HIP_OK(hipMalloc(&b.qv, G * span * 4));
+        HIP_OK(hipMalloc(&b.qm, G * span * 8));
+        HIP_OK(hipMalloc(&b.qcnt, G * 8));
+    }
     return SSSP_OK;
 }
 
@@ -1382,6 +1673,19 @@ struct PhaseKernels {
     kfn terms = nullptr, identify = nullptr, relax = nullptr, select = nullptr;
 };
 
+
+template <int CH>
+static PhaseKernels pick_queue(int in, int out) {
+    static const kfn tab[3][2] = {
+        {nullptr, k_identify_queue<IN_NONE, 1, CH>},
+        {k_identify_queue<IN_DIJK, 0, CH>, k_identify_queue<IN_DIJK, 1, CH>},
+        {k_identify_queue<IN_STATIC_M, 0, CH>, k_identify_queue<IN_STATIC_M, 1, CH>}};
+    PhaseKernels k;
+    k.identify = tab[in][out];
+    k.relax = out == OUT_STATIC_M ? k_relax<CH, false, true, false, true> : k_relax<CH, false, false, false, true>;
+    return k;
+}
+
 template <int CH>
 static PhaseKernels pick_phase_ch(int in, int out, bool delta, bool learn, bool trace = false) {
     PhaseKernels k;
@@ -1409,7 +1713,14 @@ static PhaseKernels pick_phase_ch(int in, int out, bool delta, bool learn, bool 
     return k;
 }
 
-static PhaseKernels pick_phase(int chunk, int in, int out, bool delta, bool learn, bool trace) {
+static PhaseKernels pick_phase(int chunk, int in, int out, bool delta, bool learn, bool trace, bool queue = false) {
+    if (queue) {
+        switch (chunk) {
+        case 256: return pick_queue<256>(in, out);
+        case 1024: return pick_queue<1024>(in, out);
+        default: return pick_queue<512>(in, out);
+        }
+    }
     switch (chunk) {
     case 256: return pick_phase_ch<256>(in, out, delta, learn, trace);
     case 1024: return pick_phase_ch<1024>(in, out, delta, learn, trace);
@@ -1665,11 +1976,16 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
     if (!valid_chunk(g->cfg.chunk)) return sssp_set_error(SSSP_ERR_INTERNAL, "bad chunk size");
     HIP_OK(hipSetDevice(g->device));
     const bool dyn = in >= IN_SIMPLE_M || out >= OUT_SIMPLE_M;
+    // queue arrays: plain static criteria, or the plain static phases after a committed prefix
+    // (a scan block's state window must fit in LDS: at most kQWin vertices per block)
+    const bool queue_fits = g->cfg.queue && scan_span(g->n, g->cfg.scan_blocks, 16) <= kQWin;
+    const bool queue_now = queue_fits && !learn && !oracle && !delta_mode && static_modes(in, out);
+    const bool queue_later = queue_fits && commit != 0;
     if (in >= IN_SIMPLE_M) {
         int rc = graph_ensure_csc(g);
         if (rc) return rc;
     }
-    int rc = solve_bufs_ensure(g, dyn, delta_mode);
+    int rc = solve_bufs_ensure(g, dyn, delta_mode, queue_now || queue_later);
     if (rc) return rc;
     if (learn) n_deltas = 0;
     if (delta_mode && g->delta_cap < n_deltas) {
@@ -1710,7 +2026,8 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
                        g->ip, delta_mode ? a.b.stamp : nullptr);
     hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(64), 0, s, a.b.ctl, g->vmin, source, n_deltas);
     if (learn) hipLaunchKernelGGL(k_init_choice, dim3(1), dim3(64), 0, s, a, source, (int)delta_mode);
-    const PhaseKernels K = oracle ? pick_oracle(g->cfg.chunk) : pick_phase(g->cfg.chunk, in, out, delta_mode, learn, trace_mode);
+    const PhaseKernels K = oracle ? pick_oracle(g->cfg.chunk)
+                                  : pick_phase(g->cfg.chunk, in, out, delta_mode, learn, trace_mode, queue_now);
     // phases <= reachable vertices; Delta rounds <= 2 * n + light rounds bounded by n per bucket
     // Delta: light rounds per bucket <= window vertices + 1, one heavy round per bucket
     const uint64_t max_phases = delta_mode ? 4ull * g->n + 64 : (uint64_t)g->n + 2;
@@ -1729,7 +2046,9 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
             a2.mlp_w = nullptr;
             int in2 = IN_NONE, out2 = OUT_NONE;
             crit_modes(a2.crit, &in2, &out2);
-            rc = run_loop(g, a2, pick_phase(g->cfg.chunk, in2, out2, false, false, false), max_phases, commit);
+            // the first queue-array phase rebuilds the arrays from the state bytes (qlive = 0)
+            const bool q2 = queue_later && static_modes(in2, out2);
+            rc = run_loop(g, a2, pick_phase(g->cfg.chunk, in2, out2, false, false, false, q2), max_phases, commit);
         }
     } else {
         rc = run_loop(g, a, K, max_phases);
@@ -1819,6 +2138,7 @@ extern "C" int sssp_get_launch(const sssp_graph *g, sssp_launch_cfg *out) {
     out->relax_blocks = (uint32_t)g->cfg.relax_blocks;
     out->chunk = (uint32_t)g->cfg.chunk;
     out->use_graph = (uint32_t)g->cfg.use_graph;
+    out->queue = (uint32_t)g->cfg.queue;
     return SSSP_OK;
 }
 
@@ -1832,6 +2152,7 @@ extern "C" int sssp_set_launch(sssp_graph *g, const sssp_launch_cfg *cfg) {
     g->cfg.relax_blocks = (int)cfg->relax_blocks;
     g->cfg.chunk = (int)cfg->chunk;
     g->cfg.use_graph = cfg->use_graph != 0;
+    g->cfg.queue = cfg->queue != 0;
     return SSSP_OK;
 }
 

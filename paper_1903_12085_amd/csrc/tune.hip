@@ -50,23 +50,27 @@ extern "C" int sssp_autotune(sssp_graph *g, uint32_t source, uint32_t criterion,
     HIP_OK(hipMalloc(&dist, (uint64_t)g->n * sizeof(uint64_t)));
     const int cus = device_cus();
     const uint64_t quads = ((uint64_t)g->n + 3) / 4;
+    int in = IN_NONE, out = OUT_NONE;
+    crit_modes(criterion, &in, &out);
+    const uint32_t queue_max = static_modes(in, out) ? 1u : 0u;  // other criteria ignore the option
     std::vector<sssp_launch_cfg> cands;
     for (int sb_mul : {1, 2, 4, 8})
         for (int rb_mul : {2, 4, 8})
             for (uint32_t ch : {256u, 512u})
-                for (uint32_t ug : {0u, 1u}) {
-                    uint64_t sb = (uint64_t)cus * sb_mul;
-                    const uint64_t need = (quads + kBlock - 1) / kBlock;
-                    if (sb > need) sb = need ? need : 1;
-                    uint64_t rb = (uint64_t)cus * rb_mul;
-                    const uint64_t rneed = (g->m + ch - 1) / ch;
-                    if (rb > rneed) rb = rneed ? rneed : 1;
-                    sssp_launch_cfg c = {(uint32_t)sb, (uint32_t)rb, ch, ug};
-                    bool dup = false;
-                    for (auto &o : cands) dup |= o.scan_blocks == c.scan_blocks && o.relax_blocks == c.relax_blocks &&
-                                                o.chunk == c.chunk && o.use_graph == c.use_graph;
-                    if (!dup) cands.push_back(c);
-                }
+                for (uint32_t ug : {0u, 1u})
+                    for (uint32_t qu = 0; qu <= queue_max; ++qu) {
+                        uint64_t sb = (uint64_t)cus * sb_mul;
+                        const uint64_t need = (quads + kBlock - 1) / kBlock;
+                        if (sb > need) sb = need ? need : 1;
+                        uint64_t rb = (uint64_t)cus * rb_mul;
+                        const uint64_t rneed = (g->m + ch - 1) / ch;
+                        if (rb > rneed) rb = rneed ? rneed : 1;
+                        sssp_launch_cfg c = {(uint32_t)sb, (uint32_t)rb, ch, ug, qu};
+                        bool dup = false;
+                        for (auto &o : cands) dup |= o.scan_blocks == c.scan_blocks && o.relax_blocks == c.relax_blocks &&
+                                                    o.chunk == c.chunk && o.use_graph == c.use_graph && o.queue == c.queue;
+                        if (!dup) cands.push_back(c);
+                    }
     sssp_launch_cfg keep;
     sssp_get_launch(g, &keep);
     sssp_launch_cfg win = keep;

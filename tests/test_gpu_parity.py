@@ -270,3 +270,57 @@ def test_autotuners_keep_results(B):
     dists, phases = B.solve_batch([dgs[i] for i, _ in queries], [s for _, s in queries], O.STATIC_OR)
     for (i, s), d in zip(queries, dists):
         assert np.array_equal(B.to_u64(d), O.dijkstra(graphs[i], s)[0])
+
+
+STATIC_CRITS = [O.STATIC_OR, O.IN_STATIC, O.OUT_STATIC, O.DIJK, O.DIJK | O.OUT_STATIC, O.DIJK | O.IN_STATIC]
+
+
+@pytest.mark.parametrize("cfg", [dict(scan_blocks=1), dict(scan_blocks=2), dict(scan_blocks=5, relax_blocks=3, chunk=1024),
+                                 dict(scan_blocks=64, use_graph=1), dict(scan_blocks=4096, chunk=512)])
+def test_queue_arrays_match_oracle(B, cfg):
+    """Static criteria with per-block queue arrays (on by default) and with the dense scan: every
+    observable of the oracle, on graphs whose vertex counts are not multiples of a block's span.
+    With one or two scan blocks each block owns thousands of vertices, so its slots fill with
+    tombstones and are compacted over several steps, many times per solve (one block cannot hold
+    the 20011-vertex graph's state window and takes the dense scan there). On the random graph
+    two thirds of the vertices are queued at the peak, far above the 3/8 at which identify switches
+    to the dense scan, so solves switch over and back, rebuilding the arrays."""
+    graphs = [G.er(20011, 10, 1, 5000, 41), G.rmat(13, 16, 1, 1 << 16, 42), G.grid(97, 61, 1, 1 << 16, 43),
+              G.random_small(300, 1500, 0xFFFFFFFF, 44)]
+    peak = O.phased(graphs[0], 0, O.STATIC_OR, trace_cap=1 << 16).trace_f.max()
+    assert 8 * peak >= 3 * graphs[0].n and 5 * peak < 4 * graphs[0].n
+    for g in graphs:
+        refs = {c: O.phased(g, 0, c) for c in STATIC_CRITS}
+        for queue in (1, 0):
+            dg = B.DeviceGraph.from_graph(g)
+            dg.set_launch(queue=queue, **cfg)
+            for c in STATIC_CRITS:
+                ref = refs[c]
+                r = B.solve_ex(dg, 0, c, phase_of=True, trace_cap=ref.phases + 4)
+                label = (g.name, queue, cfg, c)
+                assert np.array_equal(r.dist_u64(), ref.dist), label
+                assert r.phases == ref.phases and r.stats["sum_f"] == ref.sum_f, label
+                assert r.stats["relax_edges"] == ref.relax_edges, label
+                assert np.array_equal(r.phase_of.cpu().numpy().view(np.uint32), ref.phase_of), label
+                assert np.array_equal(r.trace["settled"], ref.trace_s), label
+            dg.close()
+
+
+def test_queue_arrays_survive_solve_kind_changes(B):
+    """Queue-array solves interleaved with dense, dynamic, Delta-stepping and other-source solves
+    on one handle: each starts from a clean state."""
+    g = G.er(5000, 8, 1, 1000, 45)
+    dg = B.DeviceGraph.from_graph(g)
+    srcs = [0, 17, 4999]
+    refs = {s: O.phased(g, s, O.STATIC_OR) for s in srcs}
+    full = O.phased(g, 0, O.FULL_OR)
+    dl = O.delta_step(g, 0, [256])
+    for step in range(3):
+        for s in srcs:
+            r = B.solve(dg, s, O.STATIC_OR)
+            assert np.array_equal(r.dist_u64(), refs[s].dist) and r.phases == refs[s].phases, (step, s)
+        r = B.solve(dg, 0, O.FULL_OR)
+        assert np.array_equal(r.dist_u64(), full.dist) and r.phases == full.phases
+        r = B.delta_step_ex(dg, 0, [256])
+        assert np.array_equal(r.dist_u64(), dl.dist) and r.phases == dl.rounds
+        dg.set_launch(queue=step % 2)
