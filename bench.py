@@ -48,9 +48,11 @@ def measured_traffic(kern, log2n):
     kernel source changed since the counters were taken (or another kernel/size dominates)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic_identify_er22.json")
-    if kern != "identify" or log2n != 22 or not os.path.exists(path):
+    if log2n != 22 or not os.path.exists(path):
         return None
     rec = json.load(open(path))
+    if rec["kernel"] != kern:
+        return None
     h = hashlib.sha256()
     for f in ("paper_1903_12085_amd/csrc/phased.hip", "paper_1903_12085_amd/csrc/common.h"):
         h.update(open(os.path.join(ROOT, f), "rb").read())
@@ -172,7 +174,7 @@ def main():
     ap.add_argument("--profile-run", action="store_true",
                     help="one solve with the default launch shape, for rocprofv3 (no tuning, no extra passes)")
     ap.add_argument("--launch", default=None,
-                    help="with --profile-run: scan_blocks,relax_blocks,chunk,use_graph (e.g. the shape the "
+                    help="with --profile-run: scan_blocks,relax_blocks,chunk,use_graph[,queue] (e.g. the shape the "
                          "autotuner picks for the timed run)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device-to-device copy kernel (known bytes) for counter calibration")
@@ -201,8 +203,9 @@ def main():
         g = G.config_er_large(seed=1, log2n=args.log2n)
         dg = B.DeviceGraph.from_graph(g)
         if args.launch:
-            sb, rb, ch, ug = (int(x) for x in args.launch.split(","))
-            dg.set_launch(scan_blocks=sb, relax_blocks=rb, chunk=ch, use_graph=ug)
+            f = [int(x) for x in args.launch.split(",")]
+            keys = ("scan_blocks", "relax_blocks", "chunk", "use_graph", "queue")
+            dg.set_launch(**dict(zip(keys, f)))
         r = B.solve(dg, 0, B.STATIC_OR)
         torch.cuda.synchronize()
         print(json.dumps({"profile_run": True, "phases": r.phases, "launch": dg.launch()}))
@@ -248,13 +251,15 @@ def main():
     prof = dg.last_profile()
     dg.profile(False)
     kern = "identify" if prof["identify_ms"] >= prof["relax_ms"] else "relax"
+    # with queue arrays on (static criteria) identify runs as k_identify_queue
+    kname = "k_identify_queue" if kern == "identify" and dg.launch()["queue"] else "k_" + kern
     kms = prof[kern + "_ms"]
     per_launch = alg_bytes(kern, st, prof["phases"])
     avg_us = kms * 1e3 / prof["phases"]
     achieved = per_launch / (avg_us * 1e-6) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kern, args.log2n),
-                "kernel": "k_" + kern,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kname, args.log2n),
+                "kernel": kname,
                 "alg_bytes_per_launch": round(per_launch), "avg_launch_us": round(avg_us, 2),
                 "launches": prof["phases"], "identify_ms": round(prof["identify_ms"], 3),
                 "relax_ms": round(prof["relax_ms"], 3)}
