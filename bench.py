@@ -9,8 +9,11 @@ resident in HBM. GTEPS = out-edges of reachable vertices / solve time.
 
 Also reported (outside the timed region): the other criteria and Delta-stepping on the same
 graph, the batched form (512 queries over 64 uneven graphs in one launch), the learned per-phase
-selector (headline graph plus held-out R-MAT and grid graphs), the dominant kernel's roofline fraction (algorithmic bytes / HIP-event kernel time vs the
-8 TB/s HBM peak), and the CPU oracle (binary-heap Dijkstra, one core) timed on the host.
+selector (headline graph plus held-out R-MAT and grid graphs), the dominant kernel's roofline
+fraction (algorithmic bytes / HIP-event kernel time vs the 8 TB/s HBM peak), the whole-solve
+fraction of each form (all algorithmic bytes of a solve / its time), the same plain measurement on
+the largest random graph (2^23 vertices), and the CPU oracle (binary-heap Dijkstra, one core)
+timed on the host.
 
 usage: python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu] [--no-extra] [--no-batch]
                       [--no-learned]
@@ -41,6 +44,54 @@ def alg_bytes(kernel, st, phases):
     # relax: per S' vertex 16 B (row range 8, id + snapshot distance 8); per out-edge of S' 16 B
     # (target+weight 8, target distance 8); per improving relaxation 8 B (the atomic write)
     return (16.0 * st["n_reach"] + 16.0 * st["m_reach"] + 8.0 * st["improving"]) / phases
+
+
+def solve_bytes(st):
+    """Algorithmic bytes of one whole phased solve: both kernels' per-unit figures summed over the
+    phases (every queued vertex once per phase it waits, every reachable vertex and out-edge once,
+    every improving relaxation once)."""
+    return 24.0 * st["sum_f"] + 16.0 * st["n_reach"] + 16.0 * st["m_reach"] + 8.0 * st["improving"]
+
+
+def solve_frac(st, ms):
+    """Whole-solve algorithmic bytes per second as a fraction of the 8 TB/s HBM peak."""
+    return round(solve_bytes(st) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+
+
+def measure_plain(B, torch, dg, src, crit, steps, warmup, log2n):
+    """Timed plain solves (steps after warmup) and the dominant kernel's roofline from a separate
+    HIP-event pass over the same solve."""
+    dist = B.new_dist(dg.n)
+    for _ in range(warmup):
+        B.solve(dg, src, crit, dist)
+    torch.cuda.synchronize()
+    phases = None
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        phases = B.solve(dg, src, crit, dist).phases
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    st = B.solve_ex(dg, src, crit, dist).stats
+    # per-kernel HIP-event timing on the solve stream (same workload, separate pass)
+    dg.profile(True)
+    for _ in range(max(1, min(steps, 3))):
+        B.solve(dg, src, crit, dist)
+    torch.cuda.synchronize()
+    prof = dg.last_profile()
+    dg.profile(False)
+    kern = "identify" if prof["identify_ms"] >= prof["relax_ms"] else "relax"
+    # with queue arrays on (static criteria) identify runs as k_identify_queue
+    kname = "k_identify_queue" if kern == "identify" and dg.launch()["queue"] else "k_" + kern
+    per_launch = alg_bytes(kern, st, prof["phases"])
+    avg_us = prof[kern + "_ms"] * 1e3 / prof["phases"]
+    achieved = per_launch / (avg_us * 1e-6) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kname, log2n),
+                "kernel": kname,
+                "alg_bytes_per_launch": round(per_launch), "avg_launch_us": round(avg_us, 2),
+                "launches": prof["phases"], "identify_ms": round(prof["identify_ms"], 3),
+                "relax_ms": round(prof["relax_ms"], 3)}
+    return ms, phases, st, roofline, prof, dist
 
 
 def measured_traffic(kern, log2n):
@@ -92,12 +143,17 @@ def bench_batched(B, torch, G):
     pph = [B.solve(dg, s, B.STATIC_OR, d).phases for dg, s, d in zip(qg, qs, pd)]
     torch.cuda.synchronize()
     tp = time.perf_counter() - tt
+    # algorithmic bytes of the same queries, from the plain solver's counts (same phases and F sets)
+    qbytes = 0.0
+    for dg, s_, d in zip(qg, qs, pd):
+        qbytes += solve_bytes(B.solve_ex(dg, s_, B.STATIC_OR, d).stats)
     same = all(np.array_equal(B.to_u64(a), B.to_u64(b)) for a, b in zip(dists, pd)) and list(bph) == pph
     res = {"workload": "64 graphs (random 2^12..2^18 deg 4..32, grids 64^2..512^2, R-MAT 12..18 ef 16), "
                        "8 sources each, weights [1, 2^16], IN_STATIC|OUT_STATIC",
            "queries": len(queries), "m_reach_total": m_reach, "batched_ms": round(tb * 1e3, 3),
            "batched_gteps": round(m_reach / tb / 1e9, 4), "plain_ms": round(tp * 1e3, 3),
            "plain_gteps": round(m_reach / tp / 1e9, 4), "speedup_vs_plain": round(tp / tb, 2),
+           "batched_solve_hbm_frac": round(qbytes / tb / 1e9 / HBM_PEAK_GBS, 4),
            "phases_total": int(sum(pph)), "max_phases": int(max(pph)), "autotuned": tuned,
            "batched_equals_plain": bool(same)}
     log("batched", res)
@@ -128,6 +184,8 @@ def bench_learned(B, torch, G, dg, src, m_reach, plain_ms):
     exact = bool(np.array_equal(B.to_u64(r.dist), ref))
     tc, rc = timed(lambda: B.solve_learned(dg, src, sel, dist, commit=S.COMMIT_PHASES))
     exact = exact and bool(np.array_equal(B.to_u64(rc.dist), ref))
+    lst = B.solve_learned(dg, src, sel, dist).stats
+    cst = B.solve_learned(dg, src, sel, dist, commit=S.COMMIT_PHASES).stats
     td, rd = timed(lambda: B.delta_step_learned(dg, src, sel, dist))
     exact = exact and bool(np.array_equal(B.to_u64(rd.dist), ref))
     res = {"weights": "selector_weights.npy (trained on random 2^16..2^21, R-MAT 16..20, grids 256^2..1024^2; "
@@ -138,6 +196,8 @@ def bench_learned(B, torch, G, dg, src, m_reach, plain_ms):
                         "learned_commit_ms": round(tc * 1e3, 3), "learned_commit_phases": rc.phases,
                         "commit_after": S.COMMIT_PHASES,
                         "learned_commit_over_plain": round(tc * 1e3 / plain_ms, 3),
+                        "learned_solve_hbm_frac": solve_frac(lst, tl * 1e3),
+                        "learned_commit_solve_hbm_frac": solve_frac(cst, tc * 1e3),
                         "learned_delta_ms": round(td * 1e3, 3), "learned_delta_rounds": rd.phases,
                         "learned_delta_gteps": round(m_reach / td / 1e9, 4)}}
     for g in S.evaluation_graphs()[1:]:
@@ -219,50 +279,13 @@ def main():
     torch.cuda.synchronize()
     log("device graph ready in %.1fs" % (time.time() - t))
     crit = B.STATIC_OR
-    dist = B.new_dist(g.n)
     tuned, tuned_ms = B.autotune(dg, src, crit)  # one-time launch-shape search (untimed)
     log("autotuned launch shape", tuned, "%.3f ms" % tuned_ms)
 
-    for _ in range(args.warmup):
-        B.solve(dg, src, crit, dist)
-    torch.cuda.synchronize()
-    log("warmup done")
-    phases = None
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        phases = B.solve(dg, src, crit, dist).phases
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
+    ms, phases, st, roofline, prof, dist = measure_plain(B, torch, dg, src, crit, args.steps, args.warmup,
+                                                         args.log2n)
     log("timed %d steps: %.3f ms/step, %d phases" % (args.steps, ms, phases))
-
-    r = B.solve_ex(dg, src, crit, dist)
-    st = r.stats
     gteps = st["m_reach"] / (ms * 1e-3) / 1e9
-
-    # per-kernel HIP-event timing on the solve stream (same workload, separate pass)
-    dg.profile(True)
-    prof_ms = []
-    for _ in range(max(1, min(args.steps, 3))):
-        tp = time.perf_counter()
-        B.solve(dg, src, crit, dist)
-        torch.cuda.synchronize()
-        prof_ms.append((time.perf_counter() - tp) * 1e3)
-    prof = dg.last_profile()
-    dg.profile(False)
-    kern = "identify" if prof["identify_ms"] >= prof["relax_ms"] else "relax"
-    # with queue arrays on (static criteria) identify runs as k_identify_queue
-    kname = "k_identify_queue" if kern == "identify" and dg.launch()["queue"] else "k_" + kern
-    kms = prof[kern + "_ms"]
-    per_launch = alg_bytes(kern, st, prof["phases"])
-    avg_us = kms * 1e3 / prof["phases"]
-    achieved = per_launch / (avg_us * 1e-6) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kname, args.log2n),
-                "kernel": kname,
-                "alg_bytes_per_launch": round(per_launch), "avg_launch_us": round(avg_us, 2),
-                "launches": prof["phases"], "identify_ms": round(prof["identify_ms"], 3),
-                "relax_ms": round(prof["relax_ms"], 3)}
     log("profile", prof)
 
     out = {
@@ -276,6 +299,7 @@ def main():
         "us_per_phase": round(ms * 1e3 / phases, 2), "precompute_ms": round(st["precompute_ns"] / 1e6, 3),
         "gteps_incl_precompute": round(st["m_reach"] / ((ms + st["precompute_ns"] / 1e6) * 1e-3) / 1e9, 4),
         "roofline": roofline,
+        "solve_hbm_frac": solve_frac(st, ms),
     }
 
     if not args.no_extra:
@@ -301,6 +325,20 @@ def main():
                                        "gteps": round(st["m_reach"] / dt / 1e9, 4)}
             log("delta", k, forms["delta_2^%d" % k])
         out["forms"] = forms
+
+    if not args.no_extra and args.log2n == 22:
+        # the largest random graph of the workloads (2^23 vertices, same out-degree and weights),
+        # with the launch shape tuned above
+        gl = G.config_er_large(seed=seed, log2n=23)
+        dl = B.DeviceGraph.from_graph(gl)
+        dl.set_launch(**tuned)
+        lms, lph, lst, lroof, _, ldist = measure_plain(B, torch, dl, src, crit, 3, 1, 23)
+        out["largest"] = {"workload": "er_n%d_outdeg16_w1-2^20_src0" % gl.n, "n": gl.n, "m": gl.m,
+                          "launch": tuned, "ms": round(lms, 3), "phases": lph,
+                          "gteps": round(lst["m_reach"] / (lms * 1e-3) / 1e9, 4), "roofline": lroof,
+                          "solve_hbm_frac": solve_frac(lst, lms)}
+        log("largest", out["largest"])
+        del dl, ldist, gl
 
     if not args.no_batch:
         out["batched"] = bench_batched(B, torch, G)
