@@ -98,8 +98,8 @@ def measured_traffic(kern, log2n):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE record, or None when the
     kernel source changed since the counters were taken (or another kernel/size dominates)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic_identify_er22.json")
-    if log2n != 22 or not os.path.exists(path):
+    path = os.path.join(ROOT, "profiles", "traffic_identify_er%d.json" % log2n)
+    if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     if rec["kernel"] != kern:
