@@ -46,16 +46,40 @@ def alg_bytes(kernel, st, phases):
     return (16.0 * st["n_reach"] + 16.0 * st["m_reach"] + 8.0 * st["improving"]) / phases
 
 
-def solve_bytes(st):
+def solve_bytes(st, n):
     """Algorithmic bytes of one whole phased solve: both kernels' per-unit figures summed over the
     phases (every queued vertex once per phase it waits, every reachable vertex and out-edge once,
-    every improving relaxation once)."""
-    return 24.0 * st["sum_f"] + 16.0 * st["n_reach"] + 16.0 * st["m_reach"] + 8.0 * st["improving"]
+    every improving relaxation once), plus 16 B per vertex of initialisation (distance, state)."""
+    return (24.0 * st["sum_f"] + 16.0 * st["n_reach"] + 16.0 * st["m_reach"] + 8.0 * st["improving"] +
+            16.0 * n)
 
 
-def solve_frac(st, ms):
+def device_ceilings(B, torch):
+    """Measured ceilings of this device: a 1 GiB device-to-device copy (bytes read + written per
+    second, median of three) and returning 64-bit atomicMin throughput on random distinct
+    addresses (2^22 slots, the size of the headline distance array), on 32 slots and on one."""
+    src = torch.empty(1 << 27, dtype=torch.int64, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ts = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    copy_gbs = 2.0 * (1 << 30) / (sorted(ts)[1] * 1e-3) / 1e9
+    del src, dst
+    atom = {"random_2^22_slots_Gops": B.measure_atomic_min(1 << 22, 1024, 64) / 1e9,
+            "32_slots_Gops": B.measure_atomic_min(32, 64, 32) / 1e9,
+            "1_slot_Gops": B.measure_atomic_min(1, 16, 16) / 1e9}
+    return round(copy_gbs, 1), {k: round(v, 3) for k, v in atom.items()}
+
+
+def solve_frac(st, ms, n):
     """Whole-solve algorithmic bytes per second as a fraction of the 8 TB/s HBM peak."""
-    return round(solve_bytes(st) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    return round(solve_bytes(st, n) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
 
 
 def measure_plain(B, torch, dg, src, crit, steps, warmup, log2n):
@@ -146,7 +170,7 @@ def bench_batched(B, torch, G):
     # algorithmic bytes of the same queries, from the plain solver's counts (same phases and F sets)
     qbytes = 0.0
     for dg, s_, d in zip(qg, qs, pd):
-        qbytes += solve_bytes(B.solve_ex(dg, s_, B.STATIC_OR, d).stats)
+        qbytes += solve_bytes(B.solve_ex(dg, s_, B.STATIC_OR, d).stats, dg.n)
     same = all(np.array_equal(B.to_u64(a), B.to_u64(b)) for a, b in zip(dists, pd)) and list(bph) == pph
     res = {"workload": "64 graphs (random 2^12..2^18 deg 4..32, grids 64^2..512^2, R-MAT 12..18 ef 16), "
                        "8 sources each, weights [1, 2^16], IN_STATIC|OUT_STATIC",
@@ -196,8 +220,8 @@ def bench_learned(B, torch, G, dg, src, m_reach, plain_ms):
                         "learned_commit_ms": round(tc * 1e3, 3), "learned_commit_phases": rc.phases,
                         "commit_after": S.COMMIT_PHASES,
                         "learned_commit_over_plain": round(tc * 1e3 / plain_ms, 3),
-                        "learned_solve_hbm_frac": solve_frac(lst, tl * 1e3),
-                        "learned_commit_solve_hbm_frac": solve_frac(cst, tc * 1e3),
+                        "learned_solve_hbm_frac": solve_frac(lst, tl * 1e3, dg.n),
+                        "learned_commit_solve_hbm_frac": solve_frac(cst, tc * 1e3, dg.n),
                         "learned_delta_ms": round(td * 1e3, 3), "learned_delta_rounds": rd.phases,
                         "learned_delta_gteps": round(m_reach / td / 1e9, 4)}}
     for g in S.evaluation_graphs()[1:]:
@@ -287,6 +311,10 @@ def main():
     log("timed %d steps: %.3f ms/step, %d phases" % (args.steps, ms, phases))
     gteps = st["m_reach"] / (ms * 1e-3) / 1e9
     log("profile", prof)
+    copy_gbs, atomics = device_ceilings(B, torch)
+    roofline["stream_copy_GBs"] = copy_gbs
+    roofline["frac_vs_copy"] = round(roofline["achieved"] / copy_gbs, 4)
+    log("device ceilings: copy %.1f GB/s, atomicMin %s" % (copy_gbs, atomics))
 
     out = {
         "metric": METRIC, "value": round(gteps, 4), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
@@ -299,7 +327,8 @@ def main():
         "us_per_phase": round(ms * 1e3 / phases, 2), "precompute_ms": round(st["precompute_ns"] / 1e6, 3),
         "gteps_incl_precompute": round(st["m_reach"] / ((ms + st["precompute_ns"] / 1e6) * 1e-3) / 1e9, 4),
         "roofline": roofline,
-        "solve_hbm_frac": solve_frac(st, ms),
+        "solve_hbm_frac": solve_frac(st, ms, g.n),
+        "atomic_min": atomics,
     }
 
     if not args.no_extra:
@@ -336,7 +365,9 @@ def main():
         out["largest"] = {"workload": "er_n%d_outdeg16_w1-2^20_src0" % gl.n, "n": gl.n, "m": gl.m,
                           "launch": tuned, "ms": round(lms, 3), "phases": lph,
                           "gteps": round(lst["m_reach"] / (lms * 1e-3) / 1e9, 4), "roofline": lroof,
-                          "solve_hbm_frac": solve_frac(lst, lms)}
+                          "solve_hbm_frac": solve_frac(lst, lms, gl.n)}
+        lroof["stream_copy_GBs"] = copy_gbs
+        lroof["frac_vs_copy"] = round(lroof["achieved"] / copy_gbs, 4)
         log("largest", out["largest"])
         del dl, ldist, gl
 

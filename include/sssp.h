@@ -349,6 +349,19 @@ int sssp_trace_learned(sssp_graph *g, uint32_t source, const sssp_selector *sel,
                        uint64_t *dist_out, sssp_stats *stats, uint32_t trace_cap, sssp_phase_rec *trace,
                        float *features_out, uint32_t *counts_out);
 
+/*
+ * Measurement helper: throughput of the returning 64-bit atomicMin that relax
+ * uses to lower distances, the second ceiling of the phase loop beside HBM
+ * bandwidth. blocks x 256 threads each issue iters atomics on slots of buf
+ * drawn from a per-thread pseudo-random sequence (slots = 1: one contended
+ * address). buf: DEVICE, slots uint64 entries, caller-owned, overwritten with
+ * smaller values. slots a power of two, blocks in [1, 2^20], iters in
+ * [1, 2^16], else SSSP_ERR_INVALID. hip_stream: a hipStream_t or NULL.
+ * *ms_out (HOST): median of three timed launches after one untimed one.
+ */
+int sssp_measure_atomic_min(uint64_t *buf, uint64_t slots, uint32_t blocks, uint32_t iters, void *hip_stream,
+                            float *ms_out);
+
 /* Human-readable description of the last error on the calling thread. */
 const char *sssp_last_error(void);
 

@@ -31,7 +31,7 @@ SYMBOLS = ["sssp_graph_create", "sssp_graph_destroy", "sssp_set_stream", "sssp_g
            "sssp_autotune_batch", "sssp_selector_create", "sssp_selector_destroy", "sssp_selector_get_weights",
            "sssp_selector_set_weights", "sssp_selector_forward", "sssp_selector_grad", "sssp_selector_train",
            "sssp_solve_learned", "sssp_delta_step_learned", "sssp_trace_learned",
-           "sssp_solve_learned_commit"]
+           "sssp_solve_learned_commit", "sssp_measure_atomic_min"]
 
 ERRORS = {-1: "SSSP_ERR_INVALID", -2: "SSSP_ERR_OOM", -3: "SSSP_ERR_DEVICE", -4: "SSSP_ERR_UNSUPPORTED",
           -5: "SSSP_ERR_INTERNAL"}
@@ -125,6 +125,7 @@ def load(path: str = LIB_PATH):
     lib.sssp_solve_learned_commit.argtypes = [P, u32, P, u32, P, ctypes.POINTER(Stats), P, P, u32]
     lib.sssp_delta_step_learned.argtypes = [P, u32, P, P, ctypes.POINTER(Stats), P, u32]
     lib.sssp_trace_learned.argtypes = [P, u32, P, i, P, ctypes.POINTER(Stats), u32, P, P, P]
+    lib.sssp_measure_atomic_min.argtypes = [P, ctypes.c_uint64, u32, u32, P, ctypes.POINTER(ctypes.c_float)]
     lib.sssp_last_error.restype = ctypes.c_char_p
     lib.sssp_last_error.argtypes = []
     for name in SYMBOLS:
@@ -473,3 +474,15 @@ def trace_learned(g: DeviceGraph, source: int, sel: Selector, delta_mode: bool =
     kb = min(st.buckets, cap) if delta_mode else k
     res = SolveResult(dist, int(st.phases), st.as_dict(), None, tr[:k])
     return res, feat[:kb], (None if cnt is None else cnt[:k])
+
+
+def measure_atomic_min(slots: int, blocks: int, iters: int) -> float:
+    """Returning 64-bit atomicMin operations per second (sssp_measure_atomic_min) on `slots`
+    distinct addresses, on torch's current stream."""
+    import torch
+    buf = torch.full((slots,), -1, dtype=torch.int64, device="cuda")
+    ms = ctypes.c_float(0)
+    _check(load().sssp_measure_atomic_min(ctypes.c_void_p(buf.data_ptr()), slots, blocks, iters,
+                                          ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
+                                          ctypes.byref(ms)))
+    return blocks * 256.0 * iters / (ms.value * 1e-3)

@@ -116,3 +116,36 @@ extern "C" int sssp_autotune_batch(sssp_graph *const *graphs, const uint32_t *so
     if (best_ms) *best_ms = win_ms;
     return SSSP_OK;
 }
+
+// Throughput of returning 64-bit atomicMin (the relax kernel's update): every
+// thread issues `iters` atomics on slots drawn from its own xorshift sequence
+// (slots is a power of two; slots = 1 is one contended address). Eight per
+// thread are in flight at a time; the returned values are summed so the
+// atomics stay returning.
+__global__ __launch_bounds__(256) void k_atomic_min_bench(unsigned long long *buf, uint64_t mask, uint32_t iters) {
+    uint64_t x = 0x9E3779B97F4A7C15ull * ((uint64_t)blockIdx.x * 256u + threadIdx.x + 1u);
+    unsigned long long acc = 0;
+#pragma unroll 8
+    for (uint32_t i = 0; i < iters; ++i) {
+        x ^= x << 13;
+        x ^= x >> 7;
+        x ^= x << 17;
+        acc += atomicMin(&buf[(x >> 11) & mask], x >> 1);
+    }
+    if (acc == 0x5A5A5A5A5A5A5A5Aull) buf[0] = acc;  // practically never: keeps the sum live
+}
+
+extern "C" int sssp_measure_atomic_min(uint64_t *buf, uint64_t slots, uint32_t blocks, uint32_t iters,
+                                       void *hip_stream, float *ms_out) {
+    if (!buf || !ms_out) return sssp_set_error(SSSP_ERR_INVALID, "NULL argument");
+    if (slots == 0 || (slots & (slots - 1)) != 0) return sssp_set_error(SSSP_ERR_INVALID, "slots must be a power of two");
+    if (blocks == 0 || blocks > (1u << 20) || iters == 0 || iters > (1u << 16))
+        return sssp_set_error(SSSP_ERR_INVALID, "blocks in [1, 2^20] and iters in [1, 2^16]");
+    hipStream_t s = (hipStream_t)hip_stream;
+    return time_call(s, 3, [&] {
+        hipLaunchKernelGGL(k_atomic_min_bench, dim3(blocks), dim3(256), 0, s, (unsigned long long *)buf, slots - 1,
+                           iters);
+        HIP_OK(hipGetLastError());
+        return (int)SSSP_OK;
+    }, ms_out);
+}
