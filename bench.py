@@ -12,11 +12,11 @@ graph, the batched form (512 queries over 64 uneven graphs in one launch), the l
 selector (headline graph plus held-out R-MAT and grid graphs), the dominant kernel's roofline
 fraction (algorithmic bytes / HIP-event kernel time vs the 8 TB/s HBM peak), the whole-solve
 fraction of each form (all algorithmic bytes of a solve / its time), the same plain measurement on
-the largest random graph (2^23 vertices), and the CPU oracle (binary-heap Dijkstra, one core)
-timed on the host.
+the largest random graph (2^23 vertices), R-MAT scale 22 and the 2048^2 grid (plain against
+Delta-stepping), and the CPU oracle (binary-heap Dijkstra, one core) timed on the host.
 
 usage: python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu] [--no-extra] [--no-batch]
-                      [--no-learned]
+                      [--no-learned] [--no-c3]
 """
 import argparse
 import json
@@ -184,6 +184,52 @@ def bench_batched(B, torch, G):
     return res
 
 
+def bench_c3(B, torch, G, tuned):
+    """R-MAT scale 22 (8 sources) and the 2048^2 grid (2 sources): the plain solver with
+    IN_STATIC|OUT_STATIC against Delta-stepping, per solve (mean over the sources, one untimed call
+    before each timed one), with the launch shape tuned on the headline graph. The grid is
+    latency-bound (thousands of phases with a small F), so its plain figure is also given per phase."""
+    res = {}
+    for name, make, nsrc in (("rmat_s22_ef16", lambda: G.config_rmat(seed=1), 8),
+                             ("grid_2048x2048", lambda: G.config_grid(seed=1), 2)):
+        t = time.time()
+        g = make()
+        dg = B.DeviceGraph.from_graph(g)
+        dg.set_launch(**tuned)
+        srcs = [int(x) for x in G.sources(g, nsrc, 11)]
+        dist = B.new_dist(g.n)
+        m_reach = sum(B.solve_ex(dg, s_, B.STATIC_OR, dist).stats["m_reach"] for s_ in srcs)
+
+        def run(fn):
+            tot, ph = 0.0, 0
+            for s_ in srcs:
+                fn(s_)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = fn(s_)
+                torch.cuda.synchronize()
+                tot += time.perf_counter() - t0
+                ph += r.phases
+            return tot, ph
+
+        tp, php = run(lambda s_: B.solve(dg, s_, B.STATIC_OR, dist))
+        e = {"n": g.n, "m": g.m, "sources": nsrc, "plain_ms": round(tp * 1e3 / nsrc, 3),
+             "plain_phases": round(php / nsrc, 1), "plain_gteps": round(m_reach / tp / 1e9, 4),
+             "plain_us_per_phase": round(tp * 1e6 / php, 2)}
+        ref = B.to_u64(B.solve(dg, srcs[0], B.STATIC_OR, dist).dist)
+        same = True
+        for k in (12, 14, 16):
+            td, rd = run(lambda s_: B.delta_step(dg, s_, 1 << k, dist))
+            same = same and bool(np.array_equal(B.to_u64(B.delta_step(dg, srcs[0], 1 << k, dist).dist), ref))
+            e["delta_2^%d" % k] = {"ms": round(td * 1e3 / nsrc, 3), "rounds": round(rd / nsrc, 1),
+                                   "gteps": round(m_reach / td / 1e9, 4)}
+        e["delta_equals_plain"] = same
+        res[name] = e
+        log("c3", name, e, "%.1fs" % (time.time() - t))
+        del dg, dist, g
+    return res
+
+
 def bench_learned(B, torch, G, dg, src, m_reach, plain_ms):
     """The learned per-phase selector (weights trained on training seeds by the package's training
     script) on the headline graph and on held-out R-MAT and grid graphs, against every fixed
@@ -255,6 +301,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-c3", action="store_true", help="skip the R-MAT 22 / 2048^2 grid section")
     ap.add_argument("--profile-run", action="store_true",
                     help="one solve with the default launch shape, for rocprofv3 (no tuning, no extra passes)")
     ap.add_argument("--launch", default=None,
@@ -370,6 +417,9 @@ def main():
         lroof["frac_vs_copy"] = round(lroof["achieved"] / copy_gbs, 4)
         log("largest", out["largest"])
         del dl, ldist, gl
+
+    if not args.no_extra and not args.no_c3:
+        out["c3"] = bench_c3(B, torch, G, tuned)
 
     if not args.no_batch:
         out["batched"] = bench_batched(B, torch, G)
