@@ -239,7 +239,10 @@ typedef struct {
     uint32_t queue;         /* criteria made of DIJK, IN_STATIC and OUT_STATIC only: 1 keeps the
                                queued vertices with their distance and static minima in per-block
                                queue arrays, so identify reads F itself instead of scanning the
-                               distance and minima arrays of all vertices; 0: that dense scan.
+                               distance and minima arrays of all vertices (phases with 3/8 or more
+                               of the vertices queued still use that dense scan); 0: the dense
+                               scan always. Applies when each scan block owns at most 16384
+                               vertices (n <= 4096 * scan_blocks * 4), else the dense scan runs.
                                Ignored by every other criterion and solver. */
 } sssp_launch_cfg;
 
