@@ -216,6 +216,16 @@ def bench_c3(B, torch, G, tuned):
         e = {"n": g.n, "m": g.m, "sources": nsrc, "plain_ms": round(tp * 1e3 / nsrc, 3),
              "plain_phases": round(php / nsrc, 1), "plain_gteps": round(m_reach / tp / 1e9, 4),
              "plain_us_per_phase": round(tp * 1e6 / php, 2)}
+        n_reach = sum(B.solve_ex(dg, s_, B.STATIC_OR, dist).stats["n_reach"] for s_ in srcs)
+        if n_reach <= 4096 * php:
+            # few vertices settled per phase (the autotuner's rule): also the one-workgroup form
+            dg.set_launch(single=1)
+            ts, phs = run(lambda s_: B.solve(dg, s_, B.STATIC_OR, dist))
+            dg.set_launch(single=0)
+            e["single_ms"] = round(ts * 1e3 / nsrc, 3)
+            e["single_gteps"] = round(m_reach / ts / 1e9, 4)
+            e["single_us_per_phase"] = round(ts * 1e6 / phs, 2)
+            e["single_phases_equal"] = phs == php
         ref = B.to_u64(B.solve(dg, srcs[0], B.STATIC_OR, dist).dist)
         same = True
         for k in (12, 14, 16):

@@ -244,6 +244,12 @@ typedef struct {
                                scan always. Applies when each scan block owns at most 16384
                                vertices (n <= 4096 * scan_blocks * 4), else the dense scan runs.
                                Ignored by every other criterion and solver. */
+    uint32_t single;        /* 1: sssp_solve with a criterion made of DIJK, IN_STATIC and OUT_STATIC
+                               runs the whole solve in one workgroup of the batched kernel
+                               (sssp_solve_batch with one query): no kernel launch per phase, for
+                               graphs whose phases settle few vertices each (grids). Same
+                               distances and phase count. sssp_solve_ex and every other solver
+                               ignore it. */
 } sssp_launch_cfg;
 
 /* Read the launch shape used by later solves on g. */

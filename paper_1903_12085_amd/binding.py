@@ -62,7 +62,7 @@ class KernelProfile(ctypes.Structure):
 
 class LaunchCfg(ctypes.Structure):
     _fields_ = [("scan_blocks", ctypes.c_uint32), ("relax_blocks", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
-                ("use_graph", ctypes.c_uint32), ("queue", ctypes.c_uint32)]
+                ("use_graph", ctypes.c_uint32), ("queue", ctypes.c_uint32), ("single", ctypes.c_uint32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

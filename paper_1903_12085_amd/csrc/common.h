@@ -291,5 +291,6 @@ struct LaunchCfg {
     int chunk;          // edges per relax chunk (256, 512 or 1024)
     int use_graph;      // replay phases from a captured HIP graph
     int queue;          // static criteria: per-block queue arrays instead of the dense scan
+    int single;         // sssp_solve with static criteria: the whole solve in one workgroup
 };
 constexpr int kMaxChunk = 2048;

@@ -37,6 +37,10 @@ struct sssp_graph {
     hipGraphExec_t graph_exec = nullptr;
     unsigned char graph_key[512] = {0};
     uint32_t graph_key_len = 0;
+    // one-workgroup solves (launch option `single`): the batched kernel's per-query scratch
+    uint8_t *one_st = nullptr;     // state bytes, n rounded up to 256
+    uint32_t *one_fl = nullptr;    // two fringe lists and the settled list, 3 * n
+    void *one_aux = nullptr;       // query record, order, phase count, work-queue control
 };
 
 DevGraph dev_view(const sssp_graph *g);
@@ -44,3 +48,5 @@ int graph_ensure_csc(sssp_graph *g);
 void graph_default_cfg(sssp_graph *g);
 int solve_bufs_ensure(sssp_graph *g, bool cursors, bool stamps, bool queue);
 void solve_bufs_free(sssp_graph *g);
+int batch_solve_one(sssp_graph *g, uint32_t source, int in, bool out_static, uint64_t *dist_out,
+                    uint32_t *phases_out);

@@ -1562,6 +1562,10 @@ void solve_bufs_free(sssp_graph *g) {
     sssp_free(b.ctl); sssp_free(b.st); sssp_free(b.srow); sssp_free(b.soff); sssp_free(b.sdu);
     sssp_free(b.chunk_start); sssp_free(b.in_cur); sssp_free(b.out_cur); sssp_free(b.stamp); sssp_free(b.deltas);
     sssp_free(b.qd); sssp_free(b.qv); sssp_free(b.qm); sssp_free(b.qcnt);
+    sssp_free(g->one_st); sssp_free(g->one_fl); sssp_free(g->one_aux);
+    g->one_st = nullptr;
+    g->one_fl = nullptr;
+    g->one_aux = nullptr;
     if (g->h_ctl) sssp_host_free(g->h_ctl);
     for (uint32_t i = 0; i < g->pev_cap; ++i) (void)hipEventDestroy(g->pev[i]);
     delete[] g->pev;
@@ -2078,6 +2082,16 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
 
 extern "C" int sssp_solve(sssp_graph *g, uint32_t source, uint32_t criterion, uint64_t *dist_out,
                           uint32_t *phases_out) {
+    if (g && g->cfg.single && criterion != 0 && !(criterion & ~SSSP_CRIT_ALL)) {
+        int in = IN_NONE, out = OUT_NONE;
+        crit_modes(criterion, &in, &out);
+        if (static_modes(in, out)) {  // the whole solve in one workgroup (the batched kernel)
+            if (!dist_out) return sssp_set_error(SSSP_ERR_INVALID, "dist_out is NULL");
+            if (source >= g->n) return sssp_set_error(SSSP_ERR_INVALID, "source %u >= n = %u", source, g->n);
+            HIP_OK(hipSetDevice(g->device));
+            return batch_solve_one(g, source, in, out == OUT_STATIC_M, dist_out, phases_out);
+        }
+    }
     sssp_stats st;
     int rc = solve_common(g, source, false, criterion, nullptr, 0, dist_out, &st, nullptr, nullptr, 0);
     if (rc == SSSP_OK && phases_out) *phases_out = st.phases;
@@ -2139,6 +2153,7 @@ extern "C" int sssp_get_launch(const sssp_graph *g, sssp_launch_cfg *out) {
     out->chunk = (uint32_t)g->cfg.chunk;
     out->use_graph = (uint32_t)g->cfg.use_graph;
     out->queue = (uint32_t)g->cfg.queue;
+    out->single = (uint32_t)g->cfg.single;
     return SSSP_OK;
 }
 
@@ -2153,6 +2168,7 @@ extern "C" int sssp_set_launch(sssp_graph *g, const sssp_launch_cfg *cfg) {
     g->cfg.chunk = (int)cfg->chunk;
     g->cfg.use_graph = cfg->use_graph != 0;
     g->cfg.queue = cfg->queue != 0;
+    g->cfg.single = cfg->single != 0;
     return SSSP_OK;
 }
 

@@ -65,7 +65,7 @@ extern "C" int sssp_autotune(sssp_graph *g, uint32_t source, uint32_t criterion,
                         uint64_t rb = (uint64_t)cus * rb_mul;
                         const uint64_t rneed = (g->m + ch - 1) / ch;
                         if (rb > rneed) rb = rneed ? rneed : 1;
-                        sssp_launch_cfg c = {(uint32_t)sb, (uint32_t)rb, ch, ug, qu};
+                        sssp_launch_cfg c = {(uint32_t)sb, (uint32_t)rb, ch, ug, qu, 0};
                         bool dup = false;
                         for (auto &o : cands) dup |= o.scan_blocks == c.scan_blocks && o.relax_blocks == c.relax_blocks &&
                                                     o.chunk == c.chunk && o.use_graph == c.use_graph && o.queue == c.queue;
@@ -76,6 +76,20 @@ extern "C" int sssp_autotune(sssp_graph *g, uint32_t source, uint32_t criterion,
     sssp_launch_cfg win = keep;
     float win_ms = 1e30f;
     int rc = SSSP_OK;
+    if (queue_max) {
+        // one workgroup for the whole solve: a candidate only when phases settle few vertices
+        // on average (a workgroup would take too long over a large F)
+        sssp_launch_cfg c = keep;
+        c.single = 0;
+        sssp_stats st{};
+        rc = sssp_set_launch(g, &c);
+        if (rc == SSSP_OK) rc = sssp_solve_ex(g, source, criterion, dist, &st, nullptr, nullptr, 0);
+        if (rc) { sssp_free(dist); sssp_set_launch(g, &keep); return rc; }
+        if (st.phases && st.n_reach <= 4096ull * st.phases) {
+            c.single = 1;
+            cands.push_back(c);
+        }
+    }
     for (const auto &c : cands) {
         rc = sssp_set_launch(g, &c);
         if (rc) break;

@@ -324,3 +324,28 @@ def test_queue_arrays_survive_solve_kind_changes(B):
         r = B.delta_step_ex(dg, 0, [256])
         assert np.array_equal(r.dist_u64(), dl.dist) and r.phases == dl.rounds
         dg.set_launch(queue=step % 2)
+
+
+def test_single_workgroup_solves_match_oracle(B):
+    """Launch option `single`: sssp_solve with a static criterion runs in one workgroup of the batched
+    kernel; distances and phase counts equal the oracle's, also on repeated calls with other sources
+    (the scratch stays on the graph). Dynamic criteria and sssp_solve_ex ignore the option."""
+    graphs = [G.grid(61, 53, 1, 1 << 16, 51), G.er(3000, 6, 1, 500, 52), G.rmat(12, 16, 1, 1 << 16, 53),
+              G.random_small(200, 800, 0xFFFFFFFF, 54), G.from_edges(1, [])]
+    for g in graphs:
+        dg = B.DeviceGraph.from_graph(g)
+        dg.set_launch(single=1)
+        srcs = [0] if g.m == 0 else [int(x) for x in G.sources(g, 2, 55)]
+        for src in srcs:
+            for c in STATIC_CRITS:
+                ref = O.phased(g, src, c)
+                r = B.solve(dg, src, c)
+                assert np.array_equal(r.dist_u64(), ref.dist), (g.name, src, c)
+                assert r.phases == ref.phases, (g.name, src, c, r.phases, ref.phases)
+        ref = O.phased(g, 0, O.SIMPLE_OR)
+        r = B.solve(dg, 0, O.SIMPLE_OR)
+        assert np.array_equal(r.dist_u64(), ref.dist) and r.phases == ref.phases
+        ref = O.phased(g, 0, O.STATIC_OR)
+        r = B.solve_ex(dg, 0, O.STATIC_OR, phase_of=True)
+        assert np.array_equal(r.dist_u64(), ref.dist) and r.stats["sum_f"] == ref.sum_f
+        dg.close()
