@@ -234,6 +234,11 @@ def bench_c3(B, torch, G, tuned):
             e["delta_2^%d" % k] = {"ms": round(td * 1e3 / nsrc, 3), "rounds": round(rd / nsrc, 1),
                                    "gteps": round(m_reach / td / 1e9, 4)}
         e["delta_equals_plain"] = same
+        if name.startswith("rmat"):
+            # the dominant kernel's roofline on the first source, as for the headline graph
+            rms, _, rst, rroof, _, _ = measure_plain(B, torch, dg, srcs[0], B.STATIC_OR, 3, 1, 0)
+            e["roofline_src0"] = rroof
+            e["solve_hbm_frac_src0"] = solve_frac(rst, rms, g.n)
         res[name] = e
         log("c3", name, e, "%.1fs" % (time.time() - t))
         del dg, dist, g
