@@ -58,15 +58,25 @@ __device__ __forceinline__ uint32_t ld_u32(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Workgroup minima of a and b in one LDS round with one barrier. The caller
+// writes sh again only after at least one more barrier (the next phase's),
+// so no second barrier is needed to protect it.
 template <int BS>
-__device__ __forceinline__ unsigned long long bmin(unsigned long long x, unsigned long long *sh) {
-    x = wave_min64(x);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = x;
+__device__ __forceinline__ void bmin2(unsigned long long &a, unsigned long long &b, unsigned long long *sh) {
+    a = wave_min64(a);
+    b = wave_min64(b);
+    if ((threadIdx.x & 63) == 0) {
+        sh[threadIdx.x >> 6] = a;
+        sh[BS / 64 + (threadIdx.x >> 6)] = b;
+    }
     __syncthreads();
-    unsigned long long r = INF64;
-    for (int i = 0; i < BS / 64; ++i) r = umin64(r, sh[i]);
-    __syncthreads();
-    return r;
+    unsigned long long ra = INF64, rb = INF64;
+    for (int i = 0; i < BS / 64; ++i) {
+        ra = umin64(ra, sh[i]);
+        rb = umin64(rb, sh[BS / 64 + i]);
+    }
+    a = ra;
+    b = rb;
 }
 
 // Wavefront-aggregated append of v to a list whose length is the LDS counter
@@ -132,11 +142,13 @@ template <int BS, int IN, bool OUT>
 __global__ __launch_bounds__(BS) void k_batch(const BatchQuery *__restrict__ queries, const uint32_t *__restrict__ order,
                                               uint32_t nq, BatchCtl *ctl, uint32_t *__restrict__ phases_out,
                                               uint32_t split) {
-    __shared__ unsigned long long sh[BS / 64];
+    __shared__ unsigned long long sh[2 * (BS / 64)];
     __shared__ uint32_t s_q;
     __shared__ uint32_t hub_v[kHubCap];
     __shared__ unsigned long long hub_du[kHubCap];
-    __shared__ uint32_t hub_n, s_nset, s_nnext;
+    // list counters by phase parity: phase p appends with set p & 1 while the
+    // other set, last read at the end of phase p - 1, is cleared for phase p + 1
+    __shared__ uint32_t hub_n[2], s_nset[2], s_nnext[2];
     for (;;) {
         if (threadIdx.x == 0) s_q = atomicAdd(&ctl->next, 1u);
         __syncthreads();
@@ -149,7 +161,10 @@ __global__ __launch_bounds__(BS) void k_batch(const BatchQuery *__restrict__ que
             q.dist[v] = v == q.src ? 0ull : INF64;
             q.st[v] = v == q.src ? ST_F : ST_U;
         }
-        if (threadIdx.x == 0) q.fl[0] = q.src;
+        if (threadIdx.x == 0) {
+            q.fl[0] = q.src;
+            for (int k = 0; k < 2; ++k) hub_n[k] = s_nset[k] = s_nnext[k] = 0;
+        }
         uint32_t nF = 1, cur = 0, phases = 0;
         unsigned long long minD = 0, T = w64(q.vmin[q.src].y);
         __syncthreads();
@@ -157,8 +172,7 @@ __global__ __launch_bounds__(BS) void k_batch(const BatchQuery *__restrict__ que
             uint32_t *F = q.fl + (uint64_t)cur * n;
             uint32_t *Fn = q.fl + (uint64_t)(cur ^ 1) * n;
             uint32_t *Sp = q.fl + 2ull * n;
-            if (threadIdx.x == 0) { s_nset = 0; s_nnext = 0; hub_n = 0; }
-            __syncthreads();
+            const int pp = (int)(phases & 1u);
             // identify over the fringe list
             unsigned long long fmin = INF64, ftst = INF64;
             // kBatchU fringe entries per thread and step, their loads issued together
@@ -202,12 +216,14 @@ __global__ __launch_bounds__(BS) void k_batch(const BatchQuery *__restrict__ que
                             q.st[v[j]] = ST_NEW;
                         }
                     }
-                    wave_append(set, v[j], Sp, &s_nset);
-                    wave_append(keep, v[j], Fn, &s_nnext);
+                    wave_append(set, v[j], Sp, &s_nset[pp]);
+                    wave_append(keep, v[j], Fn, &s_nnext[pp]);
                 }
             }
             __syncthreads();
-            const uint32_t nS = s_nset;
+            // every wavefront is past the previous phase's last counter reads
+            if (threadIdx.x == 0) hub_n[pp ^ 1] = s_nset[pp ^ 1] = s_nnext[pp ^ 1] = 0;
+            const uint32_t nS = s_nset[pp];
             ++phases;
             if (nS == 0 || phases > n + 1) {  // a non-empty fringe always certifies its minimum
                 if (threadIdx.x == 0) atomicOr(&ctl->error, 1u);
@@ -226,7 +242,7 @@ __global__ __launch_bounds__(BS) void k_batch(const BatchQuery *__restrict__ que
                     e = q.rp[v + 1];
                     du = ld_dist(&q.dist[v]);
                     if (e - b > split) {
-                        const uint32_t slot = atomicAdd(&hub_n, 1u);
+                        const uint32_t slot = atomicAdd(&hub_n[pp], 1u);
                         if (slot < kHubCap) {
                             hub_v[slot] = v;
                             hub_du[slot] = du;
@@ -252,11 +268,11 @@ __global__ __launch_bounds__(BS) void k_batch(const BatchQuery *__restrict__ que
                     const uint32_t disc = relax_edges<kBatchU, OUT>(q, du, ed, have, cmin, ctst);
 #pragma unroll
                     for (int j = 0; j < kBatchU; ++j)  // every lane of the wavefront takes part
-                        wave_append((disc >> j) & 1u, ed[j].x, Fn, &s_nnext);
+                        wave_append((disc >> j) & 1u, ed[j].x, Fn, &s_nnext[pp]);
                 }
             }
             __syncthreads();
-            const uint32_t nh = min(hub_n, (uint32_t)kHubCap);
+            const uint32_t nh = min(hub_n[pp], (uint32_t)kHubCap);
             for (uint32_t h = 0; h < nh; ++h) {
                 const uint32_t v = hub_v[h];
                 const uint32_t b = q.rp[v], e = q.rp[v + 1];
@@ -274,14 +290,15 @@ __global__ __launch_bounds__(BS) void k_batch(const BatchQuery *__restrict__ que
                     }
                     const uint32_t disc = relax_edges<kBatchU, OUT>(q, hub_du[h], ed, have, cmin, ctst);
 #pragma unroll
-                    for (int j = 0; j < kBatchU; ++j) wave_append((disc >> j) & 1u, ed[j].x, Fn, &s_nnext);
+                    for (int j = 0; j < kBatchU; ++j) wave_append((disc >> j) & 1u, ed[j].x, Fn, &s_nnext[pp]);
                 }
             }
-            minD = bmin<BS>(umin64(fmin, cmin), sh);
-            if (OUT) T = bmin<BS>(umin64(ftst, ctst), sh);
-            nF = s_nnext;  // complete: bmin ends with a barrier
+            unsigned long long a = umin64(fmin, cmin), t = umin64(ftst, ctst);
+            bmin2<BS>(a, t, sh);  // its barrier also completes every append of this phase
+            minD = a;
+            if (OUT) T = t;
+            nF = s_nnext[pp];
             cur ^= 1;
-            __syncthreads();  // every wavefront has read s_nnext before thread 0 resets it
         }
         if (threadIdx.x == 0) phases_out[order[qi]] = phases;
         __syncthreads();
