@@ -12,8 +12,9 @@ graph, the batched form (512 queries over 64 uneven graphs in one launch), the l
 selector (headline graph plus held-out R-MAT and grid graphs), the dominant kernel's roofline
 fraction (algorithmic bytes / HIP-event kernel time vs the 8 TB/s HBM peak), the whole-solve
 fraction of each form (all algorithmic bytes of a solve / its time), the same plain measurement on
-the largest random graph (2^23 vertices), R-MAT scale 22 and the 2048^2 grid (plain against
-Delta-stepping), and the CPU oracle (binary-heap Dijkstra, one core) timed on the host.
+the largest random graph (2^23 vertices), switched solves (static criteria, then a stronger one
+once the queue has shrunk), R-MAT scale 22 and the 2048^2 grid (plain against Delta-stepping),
+and the CPU oracle (binary-heap Dijkstra, one core) timed on the host.
 
 usage: python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu] [--no-extra] [--no-batch]
                       [--no-learned] [--no-c3]
@@ -184,6 +185,32 @@ def bench_batched(B, torch, G):
     return res
 
 
+SWITCHES = (("IN_SIMPLE|OUT_STATIC", 1, 2), ("SIMPLE_OR", 1, 3))
+
+
+def bench_switched(B, torch, dg, src, m_reach, plain_ms, ref):
+    """Switched solves (IN_STATIC|OUT_STATIC until |F| falls to a fraction of its peak, then a
+    stronger criterion) against the plain solver on the same graph; distances checked against ref."""
+    crits = {"IN_SIMPLE|OUT_STATIC": B.IN_SIMPLE | B.OUT_STATIC, "SIMPLE_OR": B.SIMPLE_OR}
+    out = {}
+    dist = B.new_dist(dg.n)
+    for name, num, den in SWITCHES:
+        fn = lambda: B.solve_switch(dg, src, B.STATIC_OR, crits[name], (num, den), dist)
+        fn()
+        torch.cuda.synchronize()
+        ts, r = [], None
+        for _ in range(3):
+            t0 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        t = sorted(ts)[1]
+        out["then %s at %d/%d of peak F" % (name, num, den)] = {
+            "ms": round(t * 1e3, 3), "phases": r.phases, "gteps": round(m_reach / t / 1e9, 4),
+            "over_plain": round(t * 1e3 / plain_ms, 3), "distances_exact": bool(np.array_equal(B.to_u64(r.dist), ref))}
+    return out
+
+
 def bench_c3(B, torch, G, tuned):
     """R-MAT scale 22 (8 sources) and the 2048^2 grid (2 sources): the plain solver with
     IN_STATIC|OUT_STATIC against Delta-stepping, per solve (mean over the sources, one untimed call
@@ -235,6 +262,13 @@ def bench_c3(B, torch, G, tuned):
                                    "gteps": round(m_reach / td / 1e9, 4)}
         e["delta_equals_plain"] = same
         if name.startswith("rmat"):
+            rp = B.solve(dg, srcs[0], B.STATIC_OR, dist)
+            t0 = time.perf_counter()
+            B.solve(dg, srcs[0], B.STATIC_OR, dist)
+            torch.cuda.synchronize()
+            tp0 = (time.perf_counter() - t0) * 1e3
+            e["switched_src0"] = bench_switched(B, torch, dg, srcs[0], B.solve_ex(dg, srcs[0], B.STATIC_OR, dist)
+                                                .stats["m_reach"], tp0, B.to_u64(rp.dist))
             # the dominant kernel's roofline on the first source, as for the headline graph
             rms, _, rst, rroof, _, _ = measure_plain(B, torch, dg, srcs[0], B.STATIC_OR, 3, 1, 0)
             e["roofline_src0"] = rroof
@@ -432,6 +466,10 @@ def main():
         lroof["frac_vs_copy"] = round(lroof["achieved"] / copy_gbs, 4)
         log("largest", out["largest"])
         del dl, ldist, gl
+
+    if not args.no_extra:
+        out["switched"] = bench_switched(B, torch, dg, src, st["m_reach"], ms, B.to_u64(dist))
+        log("switched", out["switched"])
 
     if not args.no_extra and not args.no_c3:
         out["c3"] = bench_c3(B, torch, G, tuned)

@@ -341,6 +341,29 @@ int sssp_solve_learned_commit(sssp_graph *g, uint32_t source, const sssp_selecto
                               uint64_t *dist_out, sssp_stats *stats, uint32_t *phase_of, sssp_phase_rec *trace,
                               uint32_t trace_cap);
 
+/*
+ * Switched phased solve: phases evaluate crit_first, a criterion made of DIJK,
+ * IN_STATIC and OUT_STATIC (the cheap static tests of Section 3), until |F| has
+ * fallen to drop_num/drop_den of its peak, then crit_then (any criterion, e.g.
+ * IN_SIMPLE | OUT_STATIC) for every later phase. The stronger criteria of
+ * Section 3 certify most of the remaining queue in a few phases once most
+ * vertices are settled, where a static criterion needs many short phases. Every
+ * criterion is sound, so distances equal every other solver's. The switch is
+ * taken at a batch boundary: phases run in batches of 16, the host checks |F|
+ * at the start of the last phase of each batch one batch behind, and the first
+ * check at or below the fraction of the largest |F| seen at an earlier check
+ * (and below it) makes the phase two batch boundaries later the first with
+ * crit_then; the phase is therefore independent of timing. Trace records carry
+ * each phase's criterion. Errors: SSSP_ERR_INVALID for a crit_first that is not
+ * static, an empty or unknown crit_then, drop_num = 0 or drop_num > drop_den,
+ * or a crit_then with OUT_STATIC after a crit_first without it (no threshold
+ * is carried over). No per-kernel timing is recorded. Other arguments as
+ * sssp_solve_ex.
+ */
+int sssp_solve_switch(sssp_graph *g, uint32_t source, uint32_t crit_first, uint32_t crit_then, uint32_t drop_num,
+                      uint32_t drop_den, uint64_t *dist_out, sssp_stats *stats, uint32_t *phase_of,
+                      sssp_phase_rec *trace, uint32_t trace_cap);
+
 /* Delta-stepping whose bucket width is chosen per bucket by the selector. */
 int sssp_delta_step_learned(sssp_graph *g, uint32_t source, const sssp_selector *sel, uint64_t *dist_out,
                             sssp_stats *stats, sssp_phase_rec *trace, uint32_t trace_cap);

@@ -31,7 +31,7 @@ SYMBOLS = ["sssp_graph_create", "sssp_graph_destroy", "sssp_set_stream", "sssp_g
            "sssp_autotune_batch", "sssp_selector_create", "sssp_selector_destroy", "sssp_selector_get_weights",
            "sssp_selector_set_weights", "sssp_selector_forward", "sssp_selector_grad", "sssp_selector_train",
            "sssp_solve_learned", "sssp_delta_step_learned", "sssp_trace_learned",
-           "sssp_solve_learned_commit", "sssp_measure_atomic_min"]
+           "sssp_solve_learned_commit", "sssp_measure_atomic_min", "sssp_solve_switch"]
 
 ERRORS = {-1: "SSSP_ERR_INVALID", -2: "SSSP_ERR_OOM", -3: "SSSP_ERR_DEVICE", -4: "SSSP_ERR_UNSUPPORTED",
           -5: "SSSP_ERR_INTERNAL"}
@@ -125,6 +125,7 @@ def load(path: str = LIB_PATH):
     lib.sssp_solve_learned_commit.argtypes = [P, u32, P, u32, P, ctypes.POINTER(Stats), P, P, u32]
     lib.sssp_delta_step_learned.argtypes = [P, u32, P, P, ctypes.POINTER(Stats), P, u32]
     lib.sssp_trace_learned.argtypes = [P, u32, P, i, P, ctypes.POINTER(Stats), u32, P, P, P]
+    lib.sssp_solve_switch.argtypes = [P, u32, u32, u32, u32, u32, P, ctypes.POINTER(Stats), P, P, u32]
     lib.sssp_measure_atomic_min.argtypes = [P, ctypes.c_uint64, u32, u32, P, ctypes.POINTER(ctypes.c_float)]
     lib.sssp_last_error.restype = ctypes.c_char_p
     lib.sssp_last_error.argtypes = []
@@ -443,6 +444,24 @@ def solve_learned(g: DeviceGraph, source: int, sel: Selector, dist=None, phase_o
     else:
         _check(load().sssp_solve_learned(g.handle, source, sel.handle, ctypes.c_void_p(dist.data_ptr()),
                                          ctypes.byref(st), po_p, _np_ptr(tr), trace_cap))
+    if tr is not None:
+        tr = tr[:min(st.phases, trace_cap)]
+    return SolveResult(dist, int(st.phases), st.as_dict(), po, tr)
+
+
+def solve_switch(g: DeviceGraph, source: int, crit_first: int, crit_then: int, drop=(1, 2), dist=None,
+                 phase_of: bool = False, trace_cap: int = 0) -> SolveResult:
+    """crit_first until |F| falls to drop[0]/drop[1] of its peak, then crit_then (sssp_solve_switch)."""
+    import torch
+    dist = new_dist(g.n) if dist is None else dist
+    po = torch.empty(g.n, dtype=torch.int32, device="cuda") if phase_of else None
+    tr = np.zeros(trace_cap, PHASE_REC) if trace_cap else None
+    st = Stats()
+    g._bind_stream()
+    _check(load().sssp_solve_switch(g.handle, source, crit_first, crit_then, int(drop[0]), int(drop[1]),
+                                    ctypes.c_void_p(dist.data_ptr()), ctypes.byref(st),
+                                    ctypes.c_void_p(po.data_ptr()) if po is not None else None, _np_ptr(tr),
+                                    trace_cap))
     if tr is not None:
         tr = tr[:min(st.phases, trace_cap)]
     return SolveResult(dist, int(st.phases), st.as_dict(), po, tr)

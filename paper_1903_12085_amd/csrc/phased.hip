@@ -1908,6 +1908,54 @@ static int run_loop(sssp_graph *g, const KArgs &a, const PhaseKernels &K, uint64
     return SSSP_OK;
 }
 
+// First stage of a switched solve (sssp_solve_switch): plain launches in
+// fixed batches of kSwitchBatch phases. After queuing batch j the host reads
+// the header copy of batch j - 1; once |F| there (at the start of that batch's
+// last phase) is at most num/den of the largest |F| seen at an earlier check,
+// and below it, batch j is the last one of this stage. The switch phase is
+// therefore kSwitchBatch * (j + 1) whatever the timing. *k_next gets the index
+// of the first phase not queued, *head the header after it (done set when the
+// solve ended in this stage).
+constexpr uint32_t kSwitchBatch = 16;
+
+static int run_until_drop(sssp_graph *g, const KArgs &a, const PhaseKernels &K, uint64_t max_phases, uint32_t num,
+                          uint32_t den, uint64_t *k_next, CtlHead *head) {
+    hipStream_t s = g->stream;
+    const dim3 blk(kBlock), gs(g->cfg.scan_blocks), gr(g->cfg.relax_blocks);
+    uint64_t k = 0;
+    int slot = 0;
+    bool have_prev = false;
+    unsigned long long peak = 0;
+    for (;;) {
+        for (uint32_t i = 0; i < kSwitchBatch; ++i, ++k) {
+            const int par = (int)(k % 6);
+            if (K.terms) hipLaunchKernelGGL(K.terms, gs, blk, 0, s, a, par);
+            hipLaunchKernelGGL(K.identify, gs, blk, 0, s, a, par);
+            hipLaunchKernelGGL(K.relax, gr, blk, 0, s, a, par);
+        }
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipMemcpyAsync(&g->h_ctl[slot], a.b.ctl, sizeof(CtlHead), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipEventRecord(g->ev[slot], s));
+        if (have_prev) {
+            HIP_OK(hipEventSynchronize(g->ev[slot ^ 1]));
+            const CtlHead &h = g->h_ctl[slot ^ 1];
+            const unsigned long long f = h.fk;
+            if (h.done || (peak && f < peak && (unsigned __int128)f * den <= (unsigned __int128)peak * num)) {
+                HIP_OK(hipEventSynchronize(g->ev[slot]));
+                *head = g->h_ctl[slot];
+                *k_next = k;
+                return SSSP_OK;
+            }
+            if (f > peak) peak = f;
+        }
+        have_prev = true;
+        slot ^= 1;
+        if (k > max_phases + 2 * kSwitchBatch)
+            return sssp_set_error(SSSP_ERR_INTERNAL, "phase loop did not terminate after %llu phases",
+                                  (unsigned long long)k);
+    }
+}
+
 static unsigned long long shard_sum(const Sharded &x) {
     unsigned long long t = 0;
     for (int i = 0; i < kShards; ++i) t += x.v[i * kPad];
@@ -1946,11 +1994,18 @@ static int finish_stats(const sssp_graph *g, const Ctl *dctl, sssp_stats *st, ui
     return rc;
 }
 
+// A switched solve's second criterion and the fraction of the peak |F| at
+// which it takes over.
+struct SwitchReq {
+    uint32_t crit_then, num, den;
+};
+
 static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_t crit,
                         const uint64_t *deltas, uint32_t n_deltas, uint64_t *dist_out,
                         sssp_stats *stats, uint32_t *phase_of, sssp_phase_rec *trace,
                         uint32_t trace_cap, const sssp_selector *sel = nullptr, float *feat_host = nullptr,
-                        uint32_t *cf_host = nullptr, const uint64_t *oracle_ref = nullptr, uint32_t commit = 0) {
+                        uint32_t *cf_host = nullptr, const uint64_t *oracle_ref = nullptr, uint32_t commit = 0,
+                        const SwitchReq *sw = nullptr) {
     const bool learn = sel != nullptr;
     const bool oracle = oracle_ref != nullptr;
     const bool trace_mode = learn && !delta_mode && cf_host != nullptr;
@@ -1977,15 +2032,29 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
         for (uint32_t i = 0; i < n_deltas; ++i)
             if (deltas[i] == 0) return sssp_set_error(SSSP_ERR_INVALID, "bucket width must be >= 1");
     }
+    int in2 = IN_NONE, out2 = OUT_NONE;  // switched solves: the second stage's modes
+    if (sw) {
+        if (learn || oracle || delta_mode || !static_modes(in, out))
+            return sssp_set_error(SSSP_ERR_INVALID, "the first criterion of a switched solve must be made of "
+                                                    "DIJK, IN_STATIC and OUT_STATIC");
+        if (sw->crit_then == 0 || (sw->crit_then & ~SSSP_CRIT_ALL))
+            return sssp_set_error(SSSP_ERR_INVALID, "criterion 0x%x is empty or has unknown bits", sw->crit_then);
+        if (sw->num == 0 || sw->den < sw->num)
+            return sssp_set_error(SSSP_ERR_INVALID, "drop fraction %u/%u is not in (0, 1]", sw->num, sw->den);
+        crit_modes(sw->crit_then, &in2, &out2);
+        if (out2 == OUT_STATIC_M && out != OUT_STATIC_M)
+            return sssp_set_error(SSSP_ERR_INVALID, "OUT_STATIC after the switch needs OUT_STATIC before it");
+    }
     if (!valid_chunk(g->cfg.chunk)) return sssp_set_error(SSSP_ERR_INTERNAL, "bad chunk size");
     HIP_OK(hipSetDevice(g->device));
-    const bool dyn = in >= IN_SIMPLE_M || out >= OUT_SIMPLE_M;
+    const int in_all = in > in2 ? in : in2, out_all = out > out2 ? out : out2;  // both stages' needs
+    const bool dyn = in_all >= IN_SIMPLE_M || out_all >= OUT_SIMPLE_M;
     // queue arrays: plain static criteria, or the plain static phases after a committed prefix
     // (a scan block's state window must fit in LDS: at most kQWin vertices per block)
     const bool queue_fits = g->cfg.queue && scan_span(g->n, g->cfg.scan_blocks, 16) <= kQWin;
     const bool queue_now = queue_fits && !learn && !oracle && !delta_mode && static_modes(in, out);
-    const bool queue_later = queue_fits && commit != 0;
-    if (in >= IN_SIMPLE_M) {
+    const bool queue_later = queue_fits && (commit != 0 || (sw && static_modes(in2, out2)));
+    if (in_all >= IN_SIMPLE_M) {
         int rc = graph_ensure_csc(g);
         if (rc) return rc;
     }
@@ -2026,7 +2095,7 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
     }
     const int ib = (int)(((uint64_t)g->n + 255) / 256 > 8192 ? 8192 : ((uint64_t)g->n + 255) / 256);
     hipLaunchKernelGGL(k_init_state, dim3(ib), dim3(256), 0, s, g->n, source, a.b.dist, a.b.st, phase_of,
-                       dyn ? a.b.out_cur : nullptr, g->rp, (in >= IN_SIMPLE_M) ? a.b.in_cur : nullptr,
+                       dyn ? a.b.out_cur : nullptr, g->rp, (in_all >= IN_SIMPLE_M) ? a.b.in_cur : nullptr,
                        g->ip, delta_mode ? a.b.stamp : nullptr);
     hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(64), 0, s, a.b.ctl, g->vmin, source, n_deltas);
     if (learn) hipLaunchKernelGGL(k_init_choice, dim3(1), dim3(64), 0, s, a, source, (int)delta_mode);
@@ -2054,6 +2123,21 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
             const bool q2 = queue_later && static_modes(in2, out2);
             rc = run_loop(g, a2, pick_phase(g->cfg.chunk, in2, out2, false, false, false, q2), max_phases, commit);
         }
+    } else if (sw) {
+        // static phases until F has fallen to the given fraction of its peak, then the second
+        // criterion's plain kernels (no per-kernel timing: both stages use plain launches)
+        const bool prof = g->prof;
+        g->prof = false;
+        CtlHead h{};
+        uint64_t k_next = 0;
+        rc = run_until_drop(g, a, K, max_phases, sw->num, sw->den, &k_next, &h);
+        if (rc == SSSP_OK && !h.done) {
+            KArgs a2 = a;
+            a2.crit = sw->crit_then;
+            const bool q2 = queue_later && static_modes(in2, out2);
+            rc = run_loop(g, a2, pick_phase(g->cfg.chunk, in2, out2, false, false, false, q2), max_phases, k_next);
+        }
+        g->prof = prof;
     } else {
         rc = run_loop(g, a, K, max_phases);
     }
@@ -2185,6 +2269,14 @@ extern "C" int sssp_solve_learned_commit(sssp_graph *g, uint32_t source, const s
     if (commit_phase == 0) return sssp_set_error(SSSP_ERR_INVALID, "commit_phase must be >= 1");
     return solve_common(g, source, false, 0, nullptr, 0, dist_out, stats, phase_of, trace, trace_cap, sel, nullptr,
                         nullptr, nullptr, commit_phase);
+}
+
+extern "C" int sssp_solve_switch(sssp_graph *g, uint32_t source, uint32_t crit_first, uint32_t crit_then,
+                                 uint32_t drop_num, uint32_t drop_den, uint64_t *dist_out, sssp_stats *stats,
+                                 uint32_t *phase_of, sssp_phase_rec *trace, uint32_t trace_cap) {
+    const SwitchReq sw{crit_then, drop_num, drop_den};
+    return solve_common(g, source, false, crit_first, nullptr, 0, dist_out, stats, phase_of, trace, trace_cap,
+                        nullptr, nullptr, nullptr, nullptr, 0, &sw);
 }
 
 extern "C" int sssp_delta_step_learned(sssp_graph *g, uint32_t source, const sssp_selector *sel, uint64_t *dist_out,

@@ -349,3 +349,53 @@ def test_single_workgroup_solves_match_oracle(B):
         r = B.solve_ex(dg, 0, O.STATIC_OR, phase_of=True)
         assert np.array_equal(r.dist_u64(), ref.dist) and r.stats["sum_f"] == ref.sum_f
         dg.close()
+
+
+def expected_switch(trace_f, phases, num, den, batch=16):
+    """The switch phase of sssp_solve_switch as its header documents it, from the static-only
+    oracle trace (the first stage is that solve): the host checks |F| at the start of the last
+    phase of batch b - 1 after queuing batch b; the first check at or below num/den of the largest
+    earlier check (and below it) ends the first stage after batch b. None: no switch before F empties."""
+    peak, b = 0, 0
+    while True:
+        if b >= 1:
+            last = batch * b - 1
+            if last >= phases:  # the solve had ended: header shows done
+                return None
+            f = int(trace_f[last])
+            if peak and f < peak and f * den <= peak * num:
+                return batch * (b + 1)
+            peak = max(peak, f)
+        b += 1
+
+
+def test_switched_solve_matches_oracle_replay(B):
+    """sssp_solve_switch: static phases, then the second criterion from the documented batch
+    boundary on; every observable equals the oracle's replay of the recorded criterion sequence,
+    distances equal Dijkstra's, and the switch phase equals the one computed from the oracle's
+    static-only trace."""
+    graphs = [G.er(20011, 10, 1, 5000, 61), G.rmat(13, 16, 1, 1 << 16, 62), G.grid(97, 61, 1, 1 << 16, 63),
+              G.er(5000, 3, 1, 7, 64)]
+    for g in graphs:
+        dg = B.DeviceGraph.from_graph(g)
+        dj, _ = O.dijkstra(g, 0)
+        base = O.phased(g, 0, O.STATIC_OR, trace_cap=1 << 20)
+        for then in (O.CRIT["IN_SIMPLE"] | O.OUT_STATIC, O.SIMPLE_OR, O.FULL_OR):
+            for num, den in ((1, 2), (1, 3), (1, 1)):
+                r = B.solve_switch(dg, 0, O.STATIC_OR, then, (num, den), phase_of=True, trace_cap=g.n + 4)
+                label = (g.name, then, num, den)
+                assert np.array_equal(r.dist_u64(), dj), label
+                crit = np.asarray(r.trace["criterion"])
+                k = expected_switch(base.trace_f, base.phases, num, den)
+                if k is None or k >= r.phases:
+                    assert (crit == O.STATIC_OR).all(), label
+                else:
+                    assert (crit[:k] == O.STATIC_OR).all() and (crit[k:] == then).all(), (label, k)
+                rep = O.phased(g, 0, 0, crit_seq=crit.astype(np.uint32))
+                assert r.phases == rep.phases and r.stats["sum_f"] == rep.sum_f, label
+                assert np.array_equal(r.phase_of.cpu().numpy().view(np.uint32), rep.phase_of), label
+        for bad in ((O.SIMPLE_OR, O.STATIC_OR, 1, 2), (O.STATIC_OR, 0, 1, 2), (O.STATIC_OR, O.SIMPLE_OR, 0, 2),
+                    (O.STATIC_OR, O.SIMPLE_OR, 3, 2), (O.IN_STATIC, O.OUT_STATIC, 1, 2)):
+            with pytest.raises(B.SsspError):
+                B.solve_switch(dg, 0, bad[0], bad[1], (bad[2], bad[3]))
+        dg.close()
