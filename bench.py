@@ -303,6 +303,8 @@ def bench_learned(B, torch, G, dg, src, m_reach, plain_ms):
     exact = bool(np.array_equal(B.to_u64(r.dist), ref))
     tc, rc = timed(lambda: B.solve_learned(dg, src, sel, dist, commit=S.COMMIT_PHASES))
     exact = exact and bool(np.array_equal(B.to_u64(rc.dist), ref))
+    tw, rw = timed(lambda: B.solve_learned(dg, src, sel, dist, commit=S.COMMIT_PHASES, switch=S.SWITCH))
+    exact = exact and bool(np.array_equal(B.to_u64(rw.dist), ref))
     lst = B.solve_learned(dg, src, sel, dist).stats
     cst = B.solve_learned(dg, src, sel, dist, commit=S.COMMIT_PHASES).stats
     td, rd = timed(lambda: B.delta_step_learned(dg, src, sel, dist))
@@ -315,6 +317,9 @@ def bench_learned(B, torch, G, dg, src, m_reach, plain_ms):
                         "learned_commit_ms": round(tc * 1e3, 3), "learned_commit_phases": rc.phases,
                         "commit_after": S.COMMIT_PHASES,
                         "learned_commit_over_plain": round(tc * 1e3 / plain_ms, 3),
+                        "learned_switch_ms": round(tw * 1e3, 3), "learned_switch_phases": rw.phases,
+                        "learned_switch_gteps": round(m_reach / tw / 1e9, 4),
+                        "learned_switch_over_plain": round(tw * 1e3 / plain_ms, 3),
                         "learned_solve_hbm_frac": solve_frac(lst, tl * 1e3, dg.n),
                         "learned_commit_solve_hbm_frac": solve_frac(cst, tc * 1e3, dg.n),
                         "learned_delta_ms": round(td * 1e3, 3), "learned_delta_rounds": rd.phases,
@@ -333,6 +338,7 @@ def bench_learned(B, torch, G, dg, src, m_reach, plain_ms):
         e["learned_over_best_fixed"] = round(e["learned_ms"] / min(fixed), 3)
         e["learned_over_mean_fixed"] = round(e["learned_ms"] / (sum(fixed) / 3), 3)
         e["learned_commit_over_best_fixed"] = round(e["learned_commit_ms"] / min(fixed), 3)
+        e["learned_switch_over_best_fixed"] = round(e["learned_switch_ms"] / min(fixed), 3)
         res[g.name] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in e.items()}
         del h
     res["distances_exact"] = exact

@@ -364,6 +364,19 @@ int sssp_solve_switch(sssp_graph *g, uint32_t source, uint32_t crit_first, uint3
                       uint32_t drop_den, uint64_t *dist_out, sssp_stats *stats, uint32_t *phase_of,
                       sssp_phase_rec *trace, uint32_t trace_cap);
 
+/*
+ * sssp_solve_learned_commit followed, when the committed choice is the static
+ * criterion (IN_STATIC | OUT_STATIC), by the switch of sssp_solve_switch: from
+ * phase commit_phase on, the static criterion runs until |F| has fallen to
+ * drop_num/drop_den of its peak (batches of 16 counted from commit_phase), then
+ * crit_then. A committed choice of a stronger criterion runs to the end as in
+ * sssp_solve_learned_commit. Errors as for both; other arguments as
+ * sssp_solve_ex.
+ */
+int sssp_solve_learned_switch(sssp_graph *g, uint32_t source, const sssp_selector *sel, uint32_t commit_phase,
+                              uint32_t crit_then, uint32_t drop_num, uint32_t drop_den, uint64_t *dist_out,
+                              sssp_stats *stats, uint32_t *phase_of, sssp_phase_rec *trace, uint32_t trace_cap);
+
 /* Delta-stepping whose bucket width is chosen per bucket by the selector. */
 int sssp_delta_step_learned(sssp_graph *g, uint32_t source, const sssp_selector *sel, uint64_t *dist_out,
                             sssp_stats *stats, sssp_phase_rec *trace, uint32_t trace_cap);

@@ -31,7 +31,8 @@ SYMBOLS = ["sssp_graph_create", "sssp_graph_destroy", "sssp_set_stream", "sssp_g
            "sssp_autotune_batch", "sssp_selector_create", "sssp_selector_destroy", "sssp_selector_get_weights",
            "sssp_selector_set_weights", "sssp_selector_forward", "sssp_selector_grad", "sssp_selector_train",
            "sssp_solve_learned", "sssp_delta_step_learned", "sssp_trace_learned",
-           "sssp_solve_learned_commit", "sssp_measure_atomic_min", "sssp_solve_switch"]
+           "sssp_solve_learned_commit", "sssp_measure_atomic_min", "sssp_solve_switch",
+           "sssp_solve_learned_switch"]
 
 ERRORS = {-1: "SSSP_ERR_INVALID", -2: "SSSP_ERR_OOM", -3: "SSSP_ERR_DEVICE", -4: "SSSP_ERR_UNSUPPORTED",
           -5: "SSSP_ERR_INTERNAL"}
@@ -126,6 +127,7 @@ def load(path: str = LIB_PATH):
     lib.sssp_delta_step_learned.argtypes = [P, u32, P, P, ctypes.POINTER(Stats), P, u32]
     lib.sssp_trace_learned.argtypes = [P, u32, P, i, P, ctypes.POINTER(Stats), u32, P, P, P]
     lib.sssp_solve_switch.argtypes = [P, u32, u32, u32, u32, u32, P, ctypes.POINTER(Stats), P, P, u32]
+    lib.sssp_solve_learned_switch.argtypes = [P, u32, P, u32, u32, u32, u32, P, ctypes.POINTER(Stats), P, P, u32]
     lib.sssp_measure_atomic_min.argtypes = [P, ctypes.c_uint64, u32, u32, P, ctypes.POINTER(ctypes.c_float)]
     lib.sssp_last_error.restype = ctypes.c_char_p
     lib.sssp_last_error.argtypes = []
@@ -427,9 +429,11 @@ class Selector:
 
 
 def solve_learned(g: DeviceGraph, source: int, sel: Selector, dist=None, phase_of: bool = False,
-                  trace_cap: int = 0, commit: int = 0) -> SolveResult:
+                  trace_cap: int = 0, commit: int = 0, switch=None) -> SolveResult:
     """commit = 0: the selector chooses every phase (sssp_solve_learned); commit = K >= 1: it
-    chooses phases 0 .. K - 1, then phase K's choice holds (sssp_solve_learned_commit)."""
+    chooses phases 0 .. K - 1, then phase K's choice holds (sssp_solve_learned_commit); with
+    switch = (crit_then, num, den) as well, a committed static choice switches to crit_then once
+    |F| has fallen to num/den of its peak (sssp_solve_learned_switch)."""
     import torch
     dist = new_dist(g.n) if dist is None else dist
     po = torch.empty(g.n, dtype=torch.int32, device="cuda") if phase_of else None
@@ -437,7 +441,11 @@ def solve_learned(g: DeviceGraph, source: int, sel: Selector, dist=None, phase_o
     st = Stats()
     g._bind_stream()
     po_p = ctypes.c_void_p(po.data_ptr()) if po is not None else None
-    if commit:
+    if switch is not None:
+        _check(load().sssp_solve_learned_switch(g.handle, source, sel.handle, int(commit), int(switch[0]),
+                                                int(switch[1]), int(switch[2]), ctypes.c_void_p(dist.data_ptr()),
+                                                ctypes.byref(st), po_p, _np_ptr(tr), trace_cap))
+    elif commit:
         _check(load().sssp_solve_learned_commit(g.handle, source, sel.handle, int(commit),
                                                 ctypes.c_void_p(dist.data_ptr()), ctypes.byref(st), po_p,
                                                 _np_ptr(tr), trace_cap))

@@ -1909,7 +1909,8 @@ static int run_loop(sssp_graph *g, const KArgs &a, const PhaseKernels &K, uint64
 }
 
 // First stage of a switched solve (sssp_solve_switch): plain launches in
-// fixed batches of kSwitchBatch phases. After queuing batch j the host reads
+// fixed batches of kSwitchBatch phases from phase k0 (0, or the end of a
+// committed learned prefix). After queuing batch j the host reads
 // the header copy of batch j - 1; once |F| there (at the start of that batch's
 // last phase) is at most num/den of the largest |F| seen at an earlier check,
 // and below it, batch j is the last one of this stage. The switch phase is
@@ -1919,10 +1920,10 @@ static int run_loop(sssp_graph *g, const KArgs &a, const PhaseKernels &K, uint64
 constexpr uint32_t kSwitchBatch = 16;
 
 static int run_until_drop(sssp_graph *g, const KArgs &a, const PhaseKernels &K, uint64_t max_phases, uint32_t num,
-                          uint32_t den, uint64_t *k_next, CtlHead *head) {
+                          uint32_t den, uint64_t *k_next, CtlHead *head, uint64_t k0 = 0) {
     hipStream_t s = g->stream;
     const dim3 blk(kBlock), gs(g->cfg.scan_blocks), gr(g->cfg.relax_blocks);
-    uint64_t k = 0;
+    uint64_t k = k0;
     int slot = 0;
     bool have_prev = false;
     unsigned long long peak = 0;
@@ -2034,7 +2035,8 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
     }
     int in2 = IN_NONE, out2 = OUT_NONE;  // switched solves: the second stage's modes
     if (sw) {
-        if (learn || oracle || delta_mode || !static_modes(in, out))
+        // plain: crit is the first stage's criterion; learned: the committed choice, if static
+        if (learn ? (delta_mode || trace_mode || !commit) : (oracle || delta_mode || !static_modes(in, out)))
             return sssp_set_error(SSSP_ERR_INVALID, "the first criterion of a switched solve must be made of "
                                                     "DIJK, IN_STATIC and OUT_STATIC");
         if (sw->crit_then == 0 || (sw->crit_then & ~SSSP_CRIT_ALL))
@@ -2042,7 +2044,7 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
         if (sw->num == 0 || sw->den < sw->num)
             return sssp_set_error(SSSP_ERR_INVALID, "drop fraction %u/%u is not in (0, 1]", sw->num, sw->den);
         crit_modes(sw->crit_then, &in2, &out2);
-        if (out2 == OUT_STATIC_M && out != OUT_STATIC_M)
+        if (out2 == OUT_STATIC_M && out != OUT_STATIC_M && !learn)
             return sssp_set_error(SSSP_ERR_INVALID, "OUT_STATIC after the switch needs OUT_STATIC before it");
     }
     if (!valid_chunk(g->cfg.chunk)) return sssp_set_error(SSSP_ERR_INTERNAL, "bad chunk size");
@@ -2117,11 +2119,30 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
             KArgs a2 = a;
             a2.crit = choice_criterion(h.choice[commit & 1]);
             a2.mlp_w = nullptr;
-            int in2 = IN_NONE, out2 = OUT_NONE;
-            crit_modes(a2.crit, &in2, &out2);
+            int ic = IN_NONE, oc = OUT_NONE;
+            crit_modes(a2.crit, &ic, &oc);
             // the first queue-array phase rebuilds the arrays from the state bytes (qlive = 0)
-            const bool q2 = queue_later && static_modes(in2, out2);
-            rc = run_loop(g, a2, pick_phase(g->cfg.chunk, in2, out2, false, false, false, q2), max_phases, commit);
+            const bool q2 = queue_later && static_modes(ic, oc);
+            const PhaseKernels K2 = pick_phase(g->cfg.chunk, ic, oc, false, false, false, q2);
+            if (sw && static_modes(ic, oc)) {
+                // committed to the static criterion: switch to the second criterion once F has
+                // fallen to the given fraction of its peak (batch boundaries counted from commit)
+                CtlHead h2{};
+                uint64_t k_next = commit;
+                const bool prof = g->prof;
+                g->prof = false;
+                rc = run_until_drop(g, a2, K2, max_phases, sw->num, sw->den, &k_next, &h2, commit);
+                if (rc == SSSP_OK && !h2.done) {
+                    KArgs a3 = a2;
+                    a3.crit = sw->crit_then;
+                    rc = run_loop(g, a3, pick_phase(g->cfg.chunk, in2, out2, false, false, false,
+                                                    queue_fits && static_modes(in2, out2)),
+                                  max_phases, k_next);
+                }
+                g->prof = prof;
+            } else {
+                rc = run_loop(g, a2, K2, max_phases, commit);
+            }
         }
     } else if (sw) {
         // static phases until F has fallen to the given fraction of its peak, then the second
@@ -2277,6 +2298,17 @@ extern "C" int sssp_solve_switch(sssp_graph *g, uint32_t source, uint32_t crit_f
     const SwitchReq sw{crit_then, drop_num, drop_den};
     return solve_common(g, source, false, crit_first, nullptr, 0, dist_out, stats, phase_of, trace, trace_cap,
                         nullptr, nullptr, nullptr, nullptr, 0, &sw);
+}
+
+extern "C" int sssp_solve_learned_switch(sssp_graph *g, uint32_t source, const sssp_selector *sel,
+                                         uint32_t commit_phase, uint32_t crit_then, uint32_t drop_num,
+                                         uint32_t drop_den, uint64_t *dist_out, sssp_stats *stats, uint32_t *phase_of,
+                                         sssp_phase_rec *trace, uint32_t trace_cap) {
+    if (!sel) return sssp_set_error(SSSP_ERR_INVALID, "selector is NULL");
+    if (commit_phase == 0) return sssp_set_error(SSSP_ERR_INVALID, "commit_phase must be >= 1");
+    const SwitchReq sw{crit_then, drop_num, drop_den};
+    return solve_common(g, source, false, 0, nullptr, 0, dist_out, stats, phase_of, trace, trace_cap, sel, nullptr,
+                        nullptr, nullptr, commit_phase, &sw);
 }
 
 extern "C" int sssp_delta_step_learned(sssp_graph *g, uint32_t source, const sssp_selector *sel, uint64_t *dist_out,

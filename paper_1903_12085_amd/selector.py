@@ -133,6 +133,8 @@ def train(X, y, seed: int = 0, epochs: int = 60, batch: int = 256, lr: float = 3
 
 # Phases the selector chooses one by one in committed mode before its choice is kept.
 COMMIT_PHASES = 32
+# After a committed static choice: IN_SIMPLE | OUT_STATIC once |F| has fallen to half its peak.
+SWITCH = (B.IN_SIMPLE | B.OUT_STATIC, 1, 2)
 
 
 def evaluate(sel, dg, src: int, reps: int = 2) -> dict:
@@ -147,6 +149,10 @@ def evaluate(sel, dg, src: int, reps: int = 2) -> dict:
     res["learned_commit_ms"] = 1e3 * _timed(
         lambda: ph.append(B.solve_learned(dg, src, sel, dist, commit=COMMIT_PHASES).phases), reps)
     res["learned_commit_phases"] = ph[-1]
+    ph = []
+    res["learned_switch_ms"] = 1e3 * _timed(
+        lambda: ph.append(B.solve_learned(dg, src, sel, dist, commit=COMMIT_PHASES, switch=SWITCH).phases), reps)
+    res["learned_switch_phases"] = ph[-1]
     for name, crit in zip(("static_or", "simple_or", "full_or"), B.CHOICE_CRIT):
         ph = []
         res[name + "_ms"] = 1e3 * _timed(lambda: ph.append(B.solve(dg, src, crit, dist).phases), reps)

@@ -3,8 +3,9 @@
 The selector's weights are the package's trained ones. On each family it must keep distances exact
 (against the oracle's Dijkstra), stay within a bounded overhead of the best fixed criterion, and,
 summed over the families, take at most half the time of a fixed criterion picked without looking
-at the graph (the mean over the three fixed criteria). Committed after a prefix of phases, its
-overhead over the best fixed criterion must be small. Times are best-of-three on the GPU.
+at the graph (the mean over the three fixed criteria). Committed after a prefix of phases, and
+committed with the static-to-IN-SIMPLE switch, its overhead over the best fixed criterion must be
+small. Times are best-of-three on the GPU.
 """
 import numpy as np
 import pytest
@@ -37,12 +38,15 @@ def test_learned_selector_gain_on_held_out_graphs(B):
         r = B.solve_learned(dg, src, sel)
         assert np.array_equal(r.dist_u64(), ref), g.name
         assert np.array_equal(B.solve_learned(dg, src, sel, commit=S.COMMIT_PHASES).dist_u64(), ref), g.name
+        assert np.array_equal(B.solve_learned(dg, src, sel, commit=S.COMMIT_PHASES, switch=S.SWITCH).dist_u64(),
+                              ref), g.name
         assert np.array_equal(B.delta_step_learned(dg, src, sel).dist_u64(), ref), g.name
         e = S.evaluate(sel, dg, src, reps=3)
         fixed = [e["static_or_ms"], e["simple_or_ms"], e["full_or_ms"]]
         print(g.name, {k: round(v, 3) if isinstance(v, float) else v for k, v in e.items()}, flush=True)
         assert e["learned_ms"] <= 1.6 * min(fixed), (g.name, e)
         assert e["learned_commit_ms"] <= 1.25 * min(fixed), (g.name, e)
+        assert e["learned_switch_ms"] <= 1.25 * min(fixed), (g.name, e)
         total_learned += e["learned_ms"]
         total_uninformed += sum(fixed) / 3
     assert total_learned <= 0.5 * total_uninformed, (total_learned, total_uninformed)

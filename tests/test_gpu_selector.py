@@ -175,3 +175,30 @@ def test_learned_commit_rejects_phase_zero_and_keeps_plain_solves_intact(B):
     B.solve_learned(dg, 0, sel, commit=4)
     r = B.solve(dg, 0, O.STATIC_OR)
     assert np.array_equal(r.dist_u64(), ref.dist) and r.phases == ref.phases
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_learned_commit_switch_matches_oracle_replay(B, seed):
+    # committed learned prefix, then (committed static choice) static until |F| falls to half its
+    # peak, then IN_SIMPLE|OUT_STATIC; the recorded per-phase criteria replayed by the oracle give
+    # every observable, and the prefix equals the oracle's committed run
+    w = mixed_weights(seed)
+    sel = B.Selector(w)
+    then = O.CRIT["IN_SIMPLE"] | O.OUT_STATIC
+    zero = np.zeros(O.MLP_NPARAM, np.float32)  # every logit 0: the first choice, the static criterion
+    static = B.Selector(zero)
+    for g in (G.er(3000, 8, 1, 1000, seed), G.rmat(11, 16, 1, 1 << 16, seed), G.grid(40, 37, 1, 1 << 16, seed)):
+        dg = B.DeviceGraph.from_graph(g)
+        dj, _ = O.dijkstra(g, 0)
+        for s_ in (sel, static):
+            for commit in (1, 16):
+                r = B.solve_learned(dg, 0, s_, phase_of=True, trace_cap=g.n + 4, commit=commit, switch=(then, 1, 2))
+                assert np.array_equal(r.dist_u64(), dj), (g.name, commit)
+                crit = np.asarray(r.trace["criterion"])
+                com = O.phased(g, 0, 0, mlp_w=w if s_ is sel else zero, commit=commit, trace_cap=g.n)
+                k = min(commit, r.phases)
+                assert np.array_equal(crit[:k], com.trace_crit[:k]), (g.name, commit)
+                rep = O.phased(g, 0, 0, crit_seq=crit.astype(np.uint32))
+                assert r.phases == rep.phases and r.stats["sum_f"] == rep.sum_f, (g.name, commit)
+                assert np.array_equal(r.phase_of.cpu().numpy().view(np.uint32), rep.phase_of), (g.name, commit)
+        dg.close()
