@@ -248,8 +248,9 @@ typedef struct {
                                runs the whole solve in one workgroup of the batched kernel
                                (sssp_solve_batch with one query): no kernel launch per phase, for
                                graphs whose phases settle few vertices each (grids). Same
-                               distances and phase count. sssp_solve_ex and every other solver
-                               ignore it. */
+                               distances and phase count; no per-kernel timing is recorded
+                               (sssp_profile_get keeps the previous figures). sssp_solve_ex and
+                               every other solver ignore it. */
 } sssp_launch_cfg;
 
 /* Read the launch shape used by later solves on g. */
