@@ -399,3 +399,25 @@ def test_switched_solve_matches_oracle_replay(B):
             with pytest.raises(B.SsspError):
                 B.solve_switch(dg, 0, bad[0], bad[1], (bad[2], bad[3]))
         dg.close()
+
+
+@pytest.mark.parametrize("cfg", [dict(use_graph=1), dict(queue=0), dict(use_graph=1, queue=0, scan_blocks=7)])
+def test_switched_solve_launch_shapes(B, cfg):
+    """The switched solve with captured six-phase graphs in the second stage (which starts at a
+    16-phase boundary, mostly not a multiple of six) and with the dense scan in the first stage."""
+    g = G.er(20011, 10, 1, 5000, 65)
+    dg = B.DeviceGraph.from_graph(g)
+    dg.set_launch(**cfg)
+    dj, _ = O.dijkstra(g, 0)
+    base = O.phased(g, 0, O.STATIC_OR, trace_cap=1 << 20)
+    then = O.CRIT["IN_SIMPLE"] | O.OUT_STATIC
+    for num, den in ((1, 2), (1, 4)):
+        r = B.solve_switch(dg, 0, O.STATIC_OR, then, (num, den), phase_of=True, trace_cap=g.n + 4)
+        crit = np.asarray(r.trace["criterion"])
+        k = expected_switch(base.trace_f, base.phases, num, den)
+        assert k is not None and 0 < k < r.phases, (cfg, k)
+        assert (crit[:k] == O.STATIC_OR).all() and (crit[k:] == then).all(), (cfg, k)
+        rep = O.phased(g, 0, 0, crit_seq=crit.astype(np.uint32))
+        assert np.array_equal(r.dist_u64(), dj) and r.phases == rep.phases, cfg
+        assert np.array_equal(r.phase_of.cpu().numpy().view(np.uint32), rep.phase_of), cfg
+    dg.close()
