@@ -138,6 +138,8 @@ struct SolveBufs {
     uint32_t *chunk_start;  // first S' entry (shard-local) of each shard-local edge chunk
     uint32_t *in_cur;       // IN-SIMPLE cursors (absolute CSC index)
     uint32_t *out_cur;      // OUT-SIMPLE cursors (absolute CSR index)
+    uint2 *in_head;         // (source, weight) of the in-edge at each IN-SIMPLE cursor; x = INF32 at the row end
+    uint2 *out_head;        // (target, weight) of the out-edge at each OUT-SIMPLE cursor; likewise
     uint32_t *stamp;        // Delta-stepping improvement stamps
     unsigned long long *deltas; // Delta-stepping widths per bucket
     PhaseRec *trace;

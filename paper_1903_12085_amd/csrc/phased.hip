@@ -84,13 +84,24 @@ __global__ void k_init_state(uint32_t n, uint32_t src, unsigned long long *__res
                              uint8_t *__restrict__ st, uint32_t *__restrict__ phase_of,
                              uint32_t *__restrict__ out_cur, const uint32_t *__restrict__ rp,
                              uint32_t *__restrict__ in_cur, const uint32_t *__restrict__ ip,
-                             uint32_t *__restrict__ stamp) {
+                             uint32_t *__restrict__ stamp, uint2 *__restrict__ out_head,
+                             const uint2 *__restrict__ edges, uint2 *__restrict__ in_head,
+                             const uint2 *__restrict__ in_edges) {
+    const uint2 none = make_uint2(INF32, INF32);
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         d[v] = v == src ? 0ull : INF64;
         st[v] = v == src ? ST_F : ST_U;
         if (phase_of) phase_of[v] = 0;
-        if (out_cur) out_cur[v] = rp[v];
-        if (in_cur) in_cur[v] = ip[v];
+        if (out_cur) {  // cursors at each row's first (lightest) edge, nothing settled yet
+            const uint32_t b = rp[v];
+            out_cur[v] = b;
+            out_head[v] = b < rp[v + 1] ? edges[b] : none;
+        }
+        if (in_cur) {
+            const uint32_t b = ip[v];
+            in_cur[v] = b;
+            in_head[v] = b < ip[v + 1] ? in_edges[b] : none;
+        }
         if (stamp) stamp[v] = 0;
     }
 }
@@ -355,6 +366,33 @@ __device__ __forceinline__ unsigned long long walk_nonsettled(const KArgs &a, ui
     return INF64;
 }
 
+// SIMPLE terms (eq. crit:insimple, crit:outsimple): the weight of the lightest
+// edge of v's weight-sorted row whose other end is not settled. The cursor
+// only moves forward (settled stays settled); head caches the edge at the
+// cursor, so while its end is not settled the term costs one state load. A
+// settled end moves cursor and cache past every settled end.
+__device__ __forceinline__ unsigned long long cursor_term(uint32_t *__restrict__ curs, uint2 *__restrict__ head,
+                                                          const uint2 *__restrict__ row_edges,
+                                                          const uint32_t *__restrict__ row_ptr, uint32_t v,
+                                                          const uint8_t *__restrict__ st) {
+    uint2 h = head[v];
+    if (h.x != INF32 && (st[h.x] & ST_SET) == ST_S) {
+        uint32_t cur = curs[v] + 1;
+        const uint32_t end = row_ptr[v + 1];
+        h = make_uint2(INF32, INF32);
+        for (; cur < end; ++cur) {
+            const uint2 e = row_edges[cur];
+            if ((st[e.x] & ST_SET) != ST_S) {
+                h = e;
+                break;
+            }
+        }
+        curs[v] = cur;
+        head[v] = h;
+    }
+    return h.x != INF32 ? (unsigned long long)h.y : INF64;
+}
+
 template <int IN, int OUT>
 __device__ __forceinline__ void terms_body(const KArgs &a, int par, unsigned long long *sh) {
     Ctl *ctl = a.b.ctl;
@@ -379,11 +417,7 @@ __device__ __forceinline__ void terms_body(const KArgs &a, int par, unsigned lon
             unsigned long long term = INF64;
             if (IN == IN_SIMPLE_M) {
                 // eq. crit:insimple: lightest in-edge from a non-settled vertex; sorted row + cursor
-                uint32_t cur = a.b.in_cur[v];
-                const uint32_t end = a.g.ip[v + 1];
-                while (cur < end && (a.b.st[a.g.in_edges[cur].x] & ST_SET) == ST_S) ++cur;
-                a.b.in_cur[v] = cur;
-                if (cur < end) term = a.g.in_edges[cur].y;
+                term = cursor_term(a.b.in_cur, a.b.in_head, a.g.in_edges, a.g.ip, v, a.b.st);
             } else {
                 // eq. crit:in: in-edges from F, or from w in U plus w's own lightest in-edge
                 // (every in-neighbour of an unexplored w is queued or unexplored)
@@ -403,10 +437,7 @@ __device__ __forceinline__ void terms_body(const KArgs &a, int par, unsigned lon
             const uint32_t end = a.g.rp[v + 1];
             if (OUT == OUT_SIMPLE_M) {
                 // eq. crit:outsimple (u in F, w in F u U): lightest out-edge to a non-settled vertex
-                uint32_t cur = a.b.out_cur[v];
-                while (cur < end && (a.b.st[a.g.edges[cur].x] & ST_SET) == ST_S) ++cur;
-                a.b.out_cur[v] = cur;
-                if (cur < end) term = a.g.edges[cur].y;
+                term = cursor_term(a.b.out_cur, a.b.out_head, a.g.edges, a.g.rp, v, a.b.st);
             } else {
                 for (uint32_t e = a.g.rp[v]; e < end; ++e) {
                     const uint2 ed = a.g.edges[e];
@@ -448,12 +479,9 @@ __global__ __launch_bounds__(kBlock) void k_terms_trace(KArgs a, int par) {
         const uint8_t s = a.b.st[v];
         if ((s & ST_SET) != ST_F) continue;
         const unsigned long long dv = a.b.dist[v];
-        unsigned long long ins = INF64, inf = INF64, outs = INF64, outf = INF64;
-        uint32_t cur = a.b.in_cur[v];
+        unsigned long long inf = INF64, outf = INF64;
+        const unsigned long long ins = cursor_term(a.b.in_cur, a.b.in_head, a.g.in_edges, a.g.ip, v, a.b.st);
         uint32_t end = a.g.ip[v + 1];
-        while (cur < end && (a.b.st[a.g.in_edges[cur].x] & ST_SET) == ST_S) ++cur;
-        a.b.in_cur[v] = cur;
-        if (cur < end) ins = a.g.in_edges[cur].y;
         for (uint32_t e = a.g.ip[v]; e < end; ++e) {
             const uint2 ie = a.g.in_edges[e];
             const uint8_t sw = a.b.st[ie.x] & ST_SET;
@@ -461,10 +489,7 @@ __global__ __launch_bounds__(kBlock) void k_terms_trace(KArgs a, int par) {
             else if (sw == ST_U) inf = umin64(inf, sadd64(ie.y, w64(a.g.vmin[ie.x].x)));
         }
         end = a.g.rp[v + 1];
-        cur = a.b.out_cur[v];
-        while (cur < end && (a.b.st[a.g.edges[cur].x] & ST_SET) == ST_S) ++cur;
-        a.b.out_cur[v] = cur;
-        if (cur < end) outs = a.g.edges[cur].y;
+        const unsigned long long outs = cursor_term(a.b.out_cur, a.b.out_head, a.g.edges, a.g.rp, v, a.b.st);
         for (uint32_t e = a.g.rp[v]; e < end; ++e) {
             const uint2 ed = a.g.edges[e];
             const uint8_t sx = a.b.st[ed.x] & ST_SET;
@@ -1561,6 +1586,7 @@ void solve_bufs_free(sssp_graph *g) {
     SolveBufs &b = g->b;
     sssp_free(b.ctl); sssp_free(b.st); sssp_free(b.srow); sssp_free(b.soff); sssp_free(b.sdu);
     sssp_free(b.chunk_start); sssp_free(b.in_cur); sssp_free(b.out_cur); sssp_free(b.stamp); sssp_free(b.deltas);
+    sssp_free(b.in_head); sssp_free(b.out_head);
     sssp_free(b.qd); sssp_free(b.qv); sssp_free(b.qm); sssp_free(b.qcnt);
     sssp_free(g->one_st); sssp_free(g->one_fl); sssp_free(g->one_aux);
     g->one_st = nullptr;
@@ -1630,6 +1656,8 @@ int solve_bufs_ensure(sssp_graph *g, bool cursors, bool stamps, bool queue) {
     if (cursors && !b.out_cur) {
         HIP_OK(hipMalloc(&b.in_cur, n * 4));
         HIP_OK(hipMalloc(&b.out_cur, n * 4));
+        HIP_OK(hipMalloc(&b.in_head, n * 8));
+        HIP_OK(hipMalloc(&b.out_head, n * 8));
     }
     if (stamps && !b.stamp) HIP_OK(hipMalloc(&b.stamp, n * 4));
     if (queue && !b.qd) {
@@ -2098,7 +2126,7 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
     const int ib = (int)(((uint64_t)g->n + 255) / 256 > 8192 ? 8192 : ((uint64_t)g->n + 255) / 256);
     hipLaunchKernelGGL(k_init_state, dim3(ib), dim3(256), 0, s, g->n, source, a.b.dist, a.b.st, phase_of,
                        dyn ? a.b.out_cur : nullptr, g->rp, (in_all >= IN_SIMPLE_M) ? a.b.in_cur : nullptr,
-                       g->ip, delta_mode ? a.b.stamp : nullptr);
+                       g->ip, delta_mode ? a.b.stamp : nullptr, a.b.out_head, g->edges, a.b.in_head, g->in_edges);
     hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(64), 0, s, a.b.ctl, g->vmin, source, n_deltas);
     if (learn) hipLaunchKernelGGL(k_init_choice, dim3(1), dim3(64), 0, s, a, source, (int)delta_mode);
     const PhaseKernels K = oracle ? pick_oracle(g->cfg.chunk)
