@@ -247,7 +247,8 @@ static int build_csc(uint32_t n, const uint64_t *rp, const uint32_t *col, const 
 static void free_csc(csc_t *c) { free(c->ip); free(c->is); free(c->iw); }
 
 /* Static minima (equations crit:instatic and crit:outstatic): minimum
- * weight over all in-edges / all out-edges; U32INF when there are none. */
+ * weight over all in-edges / all out-edges; U32INF when there are none.
+ * Exported form only: a real minimum can also be 2^32 - 1. */
 static void static_minima(uint32_t n, const uint64_t *rp, const uint32_t *w, const csc_t *c,
                           uint32_t *min_in, uint32_t *min_out) {
     for (uint32_t v = 0; v < n; ++v) {
@@ -268,7 +269,18 @@ int orc_static_minima(uint32_t n, const uint64_t *rp, const uint32_t *col, const
     return ORC_OK;
 }
 
-static inline uint64_t w64(uint32_t x) { return x == U32INF ? INF : (uint64_t)x; }
+/* The same minima in 64 bits, INF for an empty edge set. A real minimum may be
+ * 2^32 - 1 (a legal weight), so the criteria never read the 32-bit form, whose
+ * U32INF would stand for both. */
+static void static_minima64(uint32_t n, const uint64_t *rp, const uint32_t *w, const csc_t *c,
+                            uint64_t *min_in, uint64_t *min_out) {
+    for (uint32_t v = 0; v < n; ++v) {
+        uint64_t mo = INF, mi = INF;
+        for (uint64_t e = rp[v]; e < rp[v + 1]; ++e) mo = min64(mo, w[e]);
+        for (uint64_t e = c->ip[v]; e < c->ip[v + 1]; ++e) mi = min64(mi, c->iw[e]);
+        min_out[v] = mo; min_in[v] = mi;
+    }
+}
 
 /* Which criterion (single bit) holds for v on the snapshot. Thresholds that
  * do not depend on v (minD and the OUT-family right-hand sides) are passed
@@ -287,7 +299,11 @@ static uint64_t in_simple_term(uint32_t v, const csc_t *c, const uint8_t *st) {
     return t;
 }
 
-static uint64_t in_full_term(uint32_t v, const csc_t *c, const uint8_t *st) {
+/* Per-phase memo of an inner minimum: val[x] is valid while stamp[x] equals the
+ * phase's stamp (the snapshot does not change while a phase is evaluated). */
+typedef struct { uint64_t *val; uint32_t *stamp; uint32_t now; } memo_t;
+
+static uint64_t in_full_term(uint32_t v, const csc_t *c, const uint8_t *st, memo_t *M) {
     /* crit:in: min( min_{w in F, (w,v)} c(w,v),
      *               min_{w in U, w' in F u U, (w,v), (w',w)} c(w,v) + c(w',w) ) */
     uint64_t t = INF;
@@ -296,23 +312,27 @@ static uint64_t in_full_term(uint32_t v, const csc_t *c, const uint8_t *st) {
         if (st[wv] == ST_F) {
             t = min64(t, c->iw[e]);
         } else if (st[wv] == ST_U) {
-            uint64_t inner = INF;
-            for (uint64_t f = c->ip[wv]; f < c->ip[wv + 1]; ++f)
-                if (st[c->is[f]] != ST_S) inner = min64(inner, c->iw[f]);
-            t = min64(t, sadd(c->iw[e], inner));
+            if (M->stamp[wv] != M->now) {
+                uint64_t inner = INF;
+                for (uint64_t f = c->ip[wv]; f < c->ip[wv + 1]; ++f)
+                    if (st[c->is[f]] != ST_S) inner = min64(inner, c->iw[f]);
+                M->val[wv] = inner;
+                M->stamp[wv] = M->now;
+            }
+            t = min64(t, sadd(c->iw[e], M->val[wv]));
         }
     }
     return t;
 }
 
 static uint32_t eval_bits(uint32_t v, uint32_t want, const thresholds_t *T, const uint64_t *d,
-                          const uint8_t *st, const uint32_t *min_in, const csc_t *c) {
+                          const uint8_t *st, const uint64_t *min_in, const csc_t *c, memo_t *M) {
     uint32_t b = 0;
     uint64_t dv = d[v];
     if ((want & C_DIJK) && dv == T->minD) b |= C_DIJK;
-    if ((want & C_IN_STATIC) && dv <= sadd(T->minD, w64(min_in[v]))) b |= C_IN_STATIC;
+    if ((want & C_IN_STATIC) && dv <= sadd(T->minD, min_in[v])) b |= C_IN_STATIC;
     if ((want & C_IN_SIMPLE) && dv <= sadd(T->minD, in_simple_term(v, c, st))) b |= C_IN_SIMPLE;
-    if ((want & C_IN_FULL) && dv <= sadd(T->minD, in_full_term(v, c, st))) b |= C_IN_FULL;
+    if ((want & C_IN_FULL) && dv <= sadd(T->minD, in_full_term(v, c, st, M))) b |= C_IN_FULL;
     if ((want & C_OUT_STATIC) && dv <= T->t_out_static) b |= C_OUT_STATIC;
     if ((want & C_OUT_SIMPLE) && dv <= T->t_out_simple) b |= C_OUT_SIMPLE;
     if ((want & C_OUT_WEAK) && dv <= T->t_out_weak) b |= C_OUT_WEAK;
@@ -326,7 +346,7 @@ static uint32_t eval_bits(uint32_t v, uint32_t want, const thresholds_t *T, cons
  * term of crit:out with w' in F u U); memo_stamp marks validity. */
 static void out_thresholds(uint32_t want, const uint32_t *Flist, uint64_t nF, const uint64_t *rp,
                            const uint32_t *col, const uint32_t *w, const uint64_t *d, const uint8_t *st,
-                           const uint32_t *min_out, uint64_t *inner_ns, uint32_t *memo_stamp,
+                           const uint64_t *min_out, uint64_t *inner_ns, uint32_t *memo_stamp,
                            uint32_t stamp, thresholds_t *T) {
     T->t_out_static = T->t_out_simple = T->t_out_weak = T->t_out_full = INF;
     const uint32_t dyn = want & (C_OUT_SIMPLE | C_OUT_WEAK | C_OUT_FULL);
@@ -335,7 +355,7 @@ static void out_thresholds(uint32_t want, const uint32_t *Flist, uint64_t nF, co
         uint64_t du = d[u];
         /* crit:outstatic: min over u in F and all out-edges (u, w) of d[u] + c(u, w)
          * = d[u] + minOut[u], the precomputed static minimum (Section 3) */
-        if (want & C_OUT_STATIC) T->t_out_static = min64(T->t_out_static, sadd(du, w64(min_out[u])));
+        if (want & C_OUT_STATIC) T->t_out_static = min64(T->t_out_static, sadd(du, min_out[u]));
         if (!dyn) continue;
         for (uint64_t e = rp[u]; e < rp[u + 1]; ++e) {
             uint32_t x = col[e];
@@ -349,7 +369,7 @@ static void out_thresholds(uint32_t want, const uint32_t *Flist, uint64_t nF, co
                 if (want & C_OUT_FULL) T->t_out_full = min64(T->t_out_full, sadd(du, c));
             } else { /* x in U: second line */
                 if (want & C_OUT_WEAK) /* w' in V */
-                    T->t_out_weak = min64(T->t_out_weak, sadd(sadd(du, c), w64(min_out[x])));
+                    T->t_out_weak = min64(T->t_out_weak, sadd(sadd(du, c), min_out[x]));
                 if (want & C_OUT_FULL) { /* w' in F u U */
                     if (memo_stamp[x] != stamp) {
                         uint64_t inner = INF;
@@ -517,19 +537,21 @@ int orc_phased(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32
     if (src >= n || (crit == 0 && !crit_seq && !mlp_w) || (crit & ~C_ALL)) return ORC_EINVAL;
     int rc = ORC_OK;
     csc_t c = {0, 0, 0};
-    uint32_t *min_in = (uint32_t *)malloc((uint64_t)n * 4), *min_out = (uint32_t *)malloc((uint64_t)n * 4);
+    uint64_t *min_in = (uint64_t *)malloc((uint64_t)n * 8), *min_out = (uint64_t *)malloc((uint64_t)n * 8);
     uint8_t *st = (uint8_t *)calloc(n, 1);
     uint32_t *Fl = (uint32_t *)malloc((uint64_t)n * 4), *Fn = (uint32_t *)malloc((uint64_t)n * 4);
     uint32_t *Sp = (uint32_t *)malloc((uint64_t)n * 4);
     uint64_t *inner = (uint64_t *)malloc((uint64_t)n * 8);
     uint32_t *stamp = (uint32_t *)calloc(n, 4);
+    memo_t M = {(uint64_t *)malloc((uint64_t)n * 8), (uint32_t *)calloc(n, 4), 0};
     uint64_t *d = dist_out;
     orc_stats S;
     memset(&S, 0, sizeof S);
-    if (!min_in || !min_out || !st || !Fl || !Fn || !Sp || !inner || !stamp || build_csc(n, rp, col, w, &c)) {
+    if (!min_in || !min_out || !st || !Fl || !Fn || !Sp || !inner || !stamp || !M.val || !M.stamp ||
+        build_csc(n, rp, col, w, &c)) {
         rc = ORC_ENOMEM; goto out;
     }
-    static_minima(n, rp, w, &c, min_in, min_out);
+    static_minima64(n, rp, w, &c, min_in, min_out);
     for (uint32_t v = 0; v < n; ++v) d[v] = INF;
     if (phase_of) memset(phase_of, 0, (uint64_t)n * 4);
     d[src] = 0; st[src] = ST_F;
@@ -546,7 +568,7 @@ int orc_phased(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32
         Wm = (double)sw / (double)rp[n];
     }
     if (mlp_w) {  /* phase 0: the state {s}, nothing evaluated yet */
-        feat_in q = {n, rp[n], 1, 0, 1, 0, w64(min_out[src]), 0, rp[src + 1] - rp[src],
+        feat_in q = {n, rp[n], 1, 0, 1, 0, min_out[src], 0, rp[src + 1] - rp[src],
                      0, 0, 0, 0, 0, 0, Wm, 0};
         float x[MLP_IN];
         features(&q, x);
@@ -566,11 +588,12 @@ int orc_phased(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32
         if (ck == 0 || (ck & ~C_ALL)) { rc = ORC_EINVAL; goto out; }
         if (k < trace_cap && trace_crit) trace_crit[k] = ck;
         out_thresholds(want, Fl, nF, rp, col, w, d, st, min_out, inner, stamp, k + 1, &T);
+        M.now = k + 1;
         uint32_t cnt[8] = {0}, uni[3] = {0, 0, 0};
         uint64_t nS = 0, nK = 0, nin = 0, nout = 0;
         for (uint64_t i = 0; i < nF; ++i) {
             uint32_t v = Fl[i];
-            uint32_t b = eval_bits(v, want, &T, d, st, min_in, &c);
+            uint32_t b = eval_bits(v, want, &T, d, st, min_in, &c, &M);
             nin += (b & C_IN_STATIC) ? 1 : 0;
             nout += (b & C_OUT_STATIC) ? 1 : 0;
             if (check) {
@@ -638,6 +661,7 @@ int orc_phased(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32
 out:
     if (stats) *stats = S;
     free(min_in); free(min_out); free(st); free(Fl); free(Fn); free(Sp); free(inner); free(stamp);
+    free(M.val); free(M.stamp);
     free_csc(&c);
     return rc;
 }

@@ -35,6 +35,7 @@ struct BatchQuery {
     uint32_t *fl;      // 3 * n entries: fringe list A, fringe list B, settled list
     uint32_t n;
     uint32_t src;
+    uint32_t wmax;     // the graph has an edge of weight 2^32 - 1 (see min_out64)
 };
 
 struct BatchCtl {
@@ -126,7 +127,7 @@ __device__ __forceinline__ uint32_t relax_edges(const BatchQuery &q, unsigned lo
     for (int j = 0; j < U; ++j) {
         if (!((issued >> j) & 1u) || !(cand[j] < old[j])) continue;
         cmin = umin64(cmin, cand[j]);
-        if (OUT) ctst = umin64(ctst, sadd64(cand[j], w64(q.vmin[ed[j].x].y)));
+        if (OUT) ctst = umin64(ctst, sadd64(cand[j], min_out64(q.vmin[ed[j].x].y, q.wmax, q.rp, ed[j].x)));
         if (old[j] == INF64) {
             q.st[ed[j].x] = ST_F;
             disc |= 1u << j;
@@ -166,7 +167,7 @@ __global__ __launch_bounds__(BS) void k_batch(const BatchQuery *__restrict__ que
             for (int k = 0; k < 2; ++k) hub_n[k] = s_nset[k] = s_nnext[k] = 0;
         }
         uint32_t nF = 1, cur = 0, phases = 0;
-        unsigned long long minD = 0, T = w64(q.vmin[q.src].y);
+        unsigned long long minD = 0, T = min_out64(q.vmin[q.src].y, q.wmax, q.rp, q.src);
         __syncthreads();
         while (nF > 0) {
             uint32_t *F = q.fl + (uint64_t)cur * n;
@@ -205,13 +206,13 @@ __global__ __launch_bounds__(BS) void k_batch(const BatchQuery *__restrict__ que
                     if ((have >> j) & 1u) {
                         bool ok = false;
                         if (IN == IN_DIJK) ok = dv[j] == minD;
-                        else if (IN == IN_STATIC_M) ok = dv[j] <= sadd64(minD, w64(mm[j].x));
+                        else if (IN == IN_STATIC_M) ok = dv[j] <= sadd64(minD, min_in_test(mm[j].x));
                         if (OUT) ok = ok || dv[j] <= T;
                         set = ok;
                         keep = !ok;
                         if (keep) {
                             fmin = umin64(fmin, dv[j]);
-                            if (OUT) ftst = umin64(ftst, sadd64(dv[j], w64(mm[j].y)));
+                            if (OUT) ftst = umin64(ftst, sadd64(dv[j], min_out64(mm[j].y, q.wmax, q.rp, v[j])));
                         } else {
                             q.st[v[j]] = ST_NEW;
                         }
@@ -344,7 +345,8 @@ int batch_solve_one(sssp_graph *g, uint32_t source, int in, bool out_static, uin
     }
     OneAux h;
     memset(&h, 0, sizeof h);
-    h.q = BatchQuery{g->rp, g->edges, g->vmin, (unsigned long long *)dist_out, g->one_st, g->one_fl, g->n, source};
+    h.q = BatchQuery{g->rp, g->edges, g->vmin, (unsigned long long *)dist_out, g->one_st, g->one_fl, g->n, source,
+                     g->wmax};
     OneAux *d = (OneAux *)g->one_aux;
     HIP_OK(hipMemcpyAsync(d, &h, sizeof h, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(pick_batch(512, in, out_static), dim3(1), dim3(512), 0, s, &d->q, &d->order, 1u, &d->ctl,
@@ -404,6 +406,7 @@ extern "C" int sssp_solve_batch_ex(sssp_graph *const *graphs, const uint32_t *so
         hq[i].dist = (unsigned long long *)dist_outs[i];
         hq[i].n = g->n;
         hq[i].src = sources[i];
+        hq[i].wmax = g->wmax;
         st_off[i] = st_total;
         st_total += (g->n + 255) & ~255ull;
         fl_off[i] = fl_total;

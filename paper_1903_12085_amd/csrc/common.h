@@ -124,6 +124,7 @@ struct DevGraph {
     const uint2 *vmin;      // (minIn, minOut) per vertex
     const uint32_t *ip;     // CSC in_ptr (n+1) or null
     const uint2 *in_edges;  // CSC (source, weight), rows sorted by weight, or null
+    uint32_t wmax;          // nonzero if some edge weighs 2^32 - 1 (see min_out64)
 };
 
 // Scratch used by a solve.
@@ -192,12 +193,34 @@ __device__ __forceinline__ unsigned long long sadd64(unsigned long long a, unsig
     unsigned long long s = a + b;
     return s < a ? INF64 : s;
 }
-__device__ __forceinline__ unsigned long long w64(uint32_t x) {
-    return x == INF32 ? INF64 : (unsigned long long)x;
-}
 __device__ __forceinline__ unsigned long long umin64(unsigned long long a, unsigned long long b) {
     return a < b ? a : b;
 }
+
+// The static minima are stored as u32 with INF32 for an empty edge set, but
+// 2^32 - 1 is also a legal weight. Only graphs holding such an edge (wmax) need
+// the row length to tell the two apart; elsewhere INF32 always means empty.
+//   minOut (eq. crit:outstatic, and the second edge of eq. crit:outweak): an
+//   empty row makes the term infinite.
+__device__ __forceinline__ unsigned long long min_out64(uint32_t x, uint32_t wmax, const uint32_t *rp, uint32_t v) {
+    if (x != INF32) return x;
+    if (!wmax) return INF64;
+    return rp[v + 1] > rp[v] ? (unsigned long long)INF32 : INF64;
+}
+//   minIn in the unexplored-vertex term of eq. crit:in: an unexplored vertex
+//   without in-edges contributes no two-edge path (needs the reverse adjacency).
+__device__ __forceinline__ unsigned long long min_in_u64(uint32_t x, uint32_t wmax, const uint32_t *ip, uint32_t w) {
+    if (x != INF32) return x;
+    if (!wmax) return INF64;
+    return ip[w + 1] > ip[w] ? (unsigned long long)INF32 : INF64;
+}
+//   minIn in the IN-STATIC test (eq. crit:instatic) is read as the number it
+//   holds: a queued vertex other than the source was reached over an in-edge,
+//   so its minimum is real; the source is queued alone in phase 1 and is the
+//   queue minimum, certified by any threshold. Reading INF32 as 2^32 - 1
+//   therefore never changes a test, while reading a real 2^32 - 1 as infinity
+//   would certify every such vertex.
+__device__ __forceinline__ unsigned long long min_in_test(uint32_t x) { return (unsigned long long)x; }
 
 // Wavefront reductions with DPP lane moves inside each row of 16 lanes
 // (quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror: after

@@ -17,6 +17,7 @@ struct sssp_graph {
     uint2 *in_edges = nullptr;     // CSC (source, weight), rows sorted by weight (lazy)
     uint64_t precompute_ns = 0;
     uint64_t sum_w = 0;            // exact sum of edge weights (selector feature scale)
+    uint32_t wmax = 0;             // some edge weighs 2^32 - 1 (a stored minimum INF32 is then ambiguous)
     LaunchCfg cfg{};
     // per-solve scratch, allocated on first use and kept
     SolveBufs b{};

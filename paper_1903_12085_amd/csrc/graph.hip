@@ -106,16 +106,30 @@ __global__ void k_min_in(uint64_t m, const uint2 *__restrict__ edges, uint2 *__r
     }
 }
 
-// Exact sum of all edge weights (one block-level sum and one atomic per block).
+// Exact sum of all edge weights (one block-level sum and one atomic per block);
+// out[1] counts the edges of weight 2^32 - 1.
 __global__ void k_sum_w(uint64_t m, const uint2 *__restrict__ edges, unsigned long long *__restrict__ out) {
-    __shared__ unsigned long long sh[4];
-    unsigned long long t = 0;
-    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x)
-        t += edges[e].y;
-    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = t;
+    __shared__ unsigned long long sh[4], shx[4];
+    unsigned long long t = 0, x = 0;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t w = edges[e].y;
+        t += w;
+        x += w == INF32 ? 1u : 0u;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        t += __shfl_xor(t, o, 64);
+        x += __shfl_xor(x, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sh[threadIdx.x >> 6] = t;
+        shx[threadIdx.x >> 6] = x;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) atomicAdd(out, sh[0] + sh[1] + sh[2] + sh[3]);
+    if (threadIdx.x == 0) {
+        atomicAdd(out, sh[0] + sh[1] + sh[2] + sh[3]);
+        const unsigned long long nx = shx[0] + shx[1] + shx[2] + shx[3];
+        if (nx) atomicAdd(out + 1, nx);
+    }
 }
 
 // in_ptr[v] = first index whose sorted key has target >= v.
@@ -236,16 +250,17 @@ static int create_impl(uint32_t n, uint64_t m, const uint64_t *row_ptr, const ui
         if (m) hipLaunchKernelGGL(k_min_in, dim3(grid_for(m)), dim3(256), 0, s, m, g->edges, g->vmin);
         TRY(hipEventRecord(e1, s));
         TRY(hipEventSynchronize(e1));
-        if (m) {  // weight sum for the selector's feature scale (not part of the timed precompute)
+        if (m) {  // weight sum for the selector's feature scale and the 2^32 - 1 flag (not timed)
             unsigned long long *dsum = nullptr;
-            TRY(hipMalloc(&dsum, sizeof(unsigned long long)));
-            TRY(hipMemsetAsync(dsum, 0, sizeof(unsigned long long), s));
+            TRY(hipMalloc(&dsum, 2 * sizeof(unsigned long long)));
+            TRY(hipMemsetAsync(dsum, 0, 2 * sizeof(unsigned long long), s));
             hipLaunchKernelGGL(k_sum_w, dim3(grid_for(m, 256, 1024)), dim3(256), 0, s, m, g->edges, dsum);
-            unsigned long long hs = 0;
-            TRY(hipMemcpyAsync(&hs, dsum, sizeof hs, hipMemcpyDeviceToHost, s));
+            unsigned long long hs[2] = {0, 0};
+            TRY(hipMemcpyAsync(hs, dsum, sizeof hs, hipMemcpyDeviceToHost, s));
             TRY(hipStreamSynchronize(s));
             sssp_free(dsum);
-            g->sum_w = hs;
+            g->sum_w = hs[0];
+            g->wmax = hs[1] != 0;
         }
         float ms = 0;
         TRY(hipEventElapsedTime(&ms, e0, e1));

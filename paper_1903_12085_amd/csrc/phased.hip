@@ -107,7 +107,8 @@ __global__ void k_init_state(uint32_t n, uint32_t src, unsigned long long *__res
 }
 
 // One block of 64 threads.
-__global__ void k_init_ctl(Ctl *ctl, const uint2 *__restrict__ vmin, uint32_t src, uint32_t n_deltas) {
+__global__ void k_init_ctl(Ctl *ctl, const uint2 *__restrict__ vmin, const uint32_t *__restrict__ rp, uint32_t wmax,
+                           uint32_t src, uint32_t n_deltas) {
     const int i = threadIdx.x;
     if (i == 0) {
         CtlHead h;
@@ -125,7 +126,7 @@ __global__ void k_init_ctl(Ctl *ctl, const uint2 *__restrict__ vmin, uint32_t sr
         }
         for (int k = 0; k < 3; ++k) ctl->minD[k].v[o] = ctl->tst[k].v[o] = ctl->tdyn[k].v[o] = INF64;
         ctl->minD[0].v[o] = i == 0 ? 0ull : INF64;
-        ctl->tst[0].v[o] = i == 0 ? w64(vmin[src].y) : INF64;  // 0 + minOut[s]
+        ctl->tst[0].v[o] = i == 0 ? min_out64(vmin[src].y, wmax, rp, src) : INF64;  // 0 + minOut[s]
         ctl->nextmin[0].v[o] = i == 0 ? 0ull : INF64;
         ctl->nextmin[1].v[o] = INF64;
         for (int k = 0; k < 3; ++k) ctl->sumd[k].v[o] = 0;  // sum over F = {s} of d is 0
@@ -151,7 +152,7 @@ __global__ __launch_bounds__(64) void k_init_choice(KArgs a, uint32_t src, int d
     q.S = 0;
     q.R = 1;
     q.a = 0;
-    q.t = w64(a.g.vmin[src].y);
+    q.t = min_out64(a.g.vmin[src].y, a.g.wmax, a.g.rp, src);
     q.SD = 0;
     q.DG = deg;
     q.Fp = q.D = q.Sp = q.Ip = q.Op = 0;
@@ -426,7 +427,7 @@ __device__ __forceinline__ void terms_body(const KArgs &a, int par, unsigned lon
                     const uint2 ie = a.g.in_edges[e];
                     const uint8_t sw = a.b.st[ie.x] & ST_SET;
                     if (sw == ST_F) term = umin64(term, ie.y);
-                    else if (sw == ST_U) term = umin64(term, sadd64(ie.y, w64(a.g.vmin[ie.x].x)));
+                    else if (sw == ST_U) term = umin64(term, sadd64(ie.y, min_in_u64(a.g.vmin[ie.x].x, a.g.wmax, a.g.ip, ie.x)));
                 }
             }
             const bool ok = dv <= sadd64(minD, term);
@@ -447,7 +448,7 @@ __device__ __forceinline__ void terms_body(const KArgs &a, int par, unsigned lon
                     } else if (sx == ST_U) {
                         // eq. crit:outweak: second edge over all of V; eq. crit:out: into F u U
                         const unsigned long long second =
-                            OUT == OUT_WEAK_M ? w64(a.g.vmin[ed.x].y) : walk_nonsettled(a, ed.x);
+                            OUT == OUT_WEAK_M ? min_out64(a.g.vmin[ed.x].y, a.g.wmax, a.g.rp, ed.x) : walk_nonsettled(a, ed.x);
                         term = umin64(term, sadd64(ed.y, second));
                     }
                 }
@@ -486,7 +487,7 @@ __global__ __launch_bounds__(kBlock) void k_terms_trace(KArgs a, int par) {
             const uint2 ie = a.g.in_edges[e];
             const uint8_t sw = a.b.st[ie.x] & ST_SET;
             if (sw == ST_F) inf = umin64(inf, ie.y);
-            else if (sw == ST_U) inf = umin64(inf, sadd64(ie.y, w64(a.g.vmin[ie.x].x)));
+            else if (sw == ST_U) inf = umin64(inf, sadd64(ie.y, min_in_u64(a.g.vmin[ie.x].x, a.g.wmax, a.g.ip, ie.x)));
         }
         end = a.g.rp[v + 1];
         const unsigned long long outs = cursor_term(a.b.out_cur, a.b.out_head, a.g.edges, a.g.rp, v, a.b.st);
@@ -666,12 +667,12 @@ __device__ __forceinline__ void identify_body(const KArgs &a, int par, unsigned 
             const uint8_t s = (uint8_t)(s4 >> (8 * i));
             if ((s & ST_SET) != ST_F) continue;
             if (LEARN) {
-                cin += dv[i] <= sadd64(minD, w64(mm[i].x)) ? 1 : 0;
+                cin += dv[i] <= sadd64(minD, min_in_test(mm[i].x)) ? 1 : 0;
                 cout += dv[i] <= Tst ? 1 : 0;
             }
             bool ok = false;
             if (TRACE) {
-                const bool c0 = dv[i] <= sadd64(minD, w64(mm[i].x)) || dv[i] <= Tst;
+                const bool c0 = dv[i] <= sadd64(minD, min_in_test(mm[i].x)) || dv[i] <= Tst;
                 const bool c1 = (s & ST_INOK) != 0 || dv[i] <= Tsi;
                 const bool c2 = (s & ST_INOK_FULL) != 0 || dv[i] <= Tfu;
                 cc[0] += c0;
@@ -680,7 +681,7 @@ __device__ __forceinline__ void identify_body(const KArgs &a, int par, unsigned 
                 ok = choice == 0 ? c0 : choice == 1 ? c1 : c2;
             } else {
                 if (IN == IN_DIJK) ok = dv[i] == minD;
-                else if (IN == IN_STATIC_M) ok = dv[i] <= sadd64(minD, w64(mm[i].x));
+                else if (IN == IN_STATIC_M) ok = dv[i] <= sadd64(minD, min_in_test(mm[i].x));
                 else if (IN == 3) ok = (s & ST_INOK) != 0;
                 else if (IN == kInOracle) ok = dv[i] == a.ref[v0 + i];  // Section 3: ORACLE(v)
                 if (OUT != 0) ok = ok || dv[i] <= T;
@@ -689,7 +690,7 @@ __device__ __forceinline__ void identify_body(const KArgs &a, int par, unsigned 
                 sm |= 1u << i;
             } else {
                 fmin = umin64(fmin, dv[i]);
-                if (LEARN || OUT == 1) ftst = umin64(ftst, sadd64(dv[i], w64(mm[i].y)));
+                if (LEARN || OUT == 1) ftst = umin64(ftst, sadd64(dv[i], min_out64(mm[i].y, a.g.wmax, a.g.rp, v0 + i)));
                 if (LEARN) fsum += dv[i];
             }
         }
@@ -856,7 +857,7 @@ __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
     auto certified = [&](unsigned long long d, uint2 mm) {
         bool ok = false;
         if (IN == IN_DIJK) ok = d == minD;
-        else if (IN == IN_STATIC_M) ok = d <= sadd64(minD, w64(mm.x));  // eq. crit:instatic
+        else if (IN == IN_STATIC_M) ok = d <= sadd64(minD, min_in_test(mm.x));  // eq. crit:instatic
         if (OUT == 1) ok = ok || d <= T;                                // eq. crit:outstatic
         return ok;
     };
@@ -917,7 +918,7 @@ __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
             } else {
                 keep |= 1u << j;
                 fmin = umin64(fmin, d[j]);
-                if (OUT == 1) ftst = umin64(ftst, sadd64(d[j], w64(mm[j].y)));
+                if (OUT == 1) ftst = umin64(ftst, sadd64(d[j], min_out64(mm[j].y, a.g.wmax, a.g.rp, v[j])));
             }
         }
 #pragma unroll
@@ -992,7 +993,7 @@ __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
             const bool app = has && !ok;
             if (app) {
                 fmin = umin64(fmin, d);
-                if (OUT == 1) ftst = umin64(ftst, sadd64(d, w64(mm.y)));
+                if (OUT == 1) ftst = umin64(ftst, sadd64(d, min_out64(mm.y, a.g.wmax, a.g.rp, v)));
             }
             const unsigned long long am = __ballot(app);
             if (am) {
@@ -1447,7 +1448,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
             ++improv;
             if (!DELTA) {
                 cmin = umin64(cmin, cand[k]);
-                if (FOLDT) ctst = umin64(ctst, sadd64(cand[k], w64(a.g.vmin[v].y)));
+                if (FOLDT) ctst = umin64(ctst, sadd64(cand[k], min_out64(a.g.vmin[v].y, a.g.wmax, a.g.rp, v)));
             } else if (kind == 2) {
                 cmin = umin64(cmin, cand[k]);
             } else if (cand[k] < hi) {
@@ -1551,6 +1552,7 @@ DevGraph dev_view(const sssp_graph *g) {
     d.vmin = g->vmin;
     d.ip = g->ip;
     d.in_edges = g->in_edges;
+    d.wmax = g->wmax;
     return d;
 }
 
@@ -1630,6 +1632,25 @@ static uint32_t shard_capacity(uint32_t n, int G) {
     return (uint32_t)(blocks * (a > b ? a : b));
 }
 
+// Allocates every buffer of a group or none: on a failure the buffers already
+// taken are released and every pointer of the group is null again, so a later
+// call starts the group afresh.
+static int alloc_group(void **const *ptr, const uint64_t *bytes, int k) {
+    for (int i = 0; i < k; ++i) {
+        const hipError_t e = hipMalloc(ptr[i], bytes[i] ? bytes[i] : 1);
+        if (e != hipSuccess) {
+            for (int j = 0; j < k; ++j) {
+                sssp_free(*ptr[j]);
+                *ptr[j] = nullptr;
+            }
+            return sssp_set_error(e == hipErrorOutOfMemory ? SSSP_ERR_OOM : SSSP_ERR_DEVICE,
+                                  "scratch allocation of %llu bytes failed: %s", (unsigned long long)bytes[i],
+                                  hipGetErrorString(e));
+        }
+    }
+    return SSSP_OK;
+}
+
 int solve_bufs_ensure(sssp_graph *g, bool cursors, bool stamps, bool queue) {
     SolveBufs &b = g->b;
     const uint64_t n = g->n;
@@ -1638,37 +1659,39 @@ int solve_bufs_ensure(sssp_graph *g, bool cursors, bool stamps, bool queue) {
         solve_bufs_free(g);
     }
     if (!g->bufs_ready) {
+        solve_bufs_free(g);  // whatever a failed earlier call left behind
         b.shard_cap = shard_capacity(g->n, g->cfg.scan_blocks);
         b.chunk_cap = (uint32_t)(g->m / 256 + 2);  // every chunk size is >= 256 edges
         const uint64_t sent = (uint64_t)kShards * b.shard_cap;
-        HIP_OK(hipMalloc(&b.ctl, sizeof(Ctl)));
-        HIP_OK(hipMalloc(&b.st, (n + 15) & ~15ull));  // whole words: relax ORs flags into 32-bit words
-        HIP_OK(hipMalloc(&b.srow, sent * 4));
-        HIP_OK(hipMalloc(&b.soff, sent * 4));
-        HIP_OK(hipMalloc(&b.sdu, sent * 8));
-        HIP_OK(hipMalloc(&b.chunk_start, (uint64_t)kShards * b.chunk_cap * 4));
+        void **const p[] = {(void **)&b.ctl, (void **)&b.st, (void **)&b.srow, (void **)&b.soff, (void **)&b.sdu,
+                            (void **)&b.chunk_start};
+        // st in whole words: relax ORs flags into 32-bit words
+        const uint64_t z[] = {sizeof(Ctl), (n + 15) & ~15ull, sent * 4, sent * 4, sent * 8,
+                              (uint64_t)kShards * b.chunk_cap * 4};
+        int rc = alloc_group(p, z, 6);
+        if (rc) return rc;
         HIP_OK(hipHostMalloc((void **)&g->h_ctl, 2 * sizeof(CtlHead), hipHostMallocDefault));
         HIP_OK(hipEventCreateWithFlags(&g->ev[0], hipEventDisableTiming));
         HIP_OK(hipEventCreateWithFlags(&g->ev[1], hipEventDisableTiming));
         g->bufs_ready = true;
         g->bufs_scan_blocks = (uint32_t)g->cfg.scan_blocks;
     }
-    if (cursors && !b.out_cur) {
-        HIP_OK(hipMalloc(&b.in_cur, n * 4));
-        HIP_OK(hipMalloc(&b.out_cur, n * 4));
-        HIP_OK(hipMalloc(&b.in_head, n * 8));
-        HIP_OK(hipMalloc(&b.out_head, n * 8));
+    if (cursors && !(b.in_cur && b.out_cur && b.in_head && b.out_head)) {
+        void **const p[] = {(void **)&b.in_cur, (void **)&b.out_cur, (void **)&b.in_head, (void **)&b.out_head};
+        const uint64_t z[] = {n * 4, n * 4, n * 8, n * 8};
+        int rc = alloc_group(p, z, 4);
+        if (rc) return rc;
     }
     if (stamps && !b.stamp) HIP_OK(hipMalloc(&b.stamp, n * 4));
-    if (queue && !b.qd) {
+    if (queue && !(b.qd && b.qv && b.qm && b.qcnt)) {
         const uint64_t G = (uint64_t)g->cfg.scan_blocks;
         const uint64_t span = scan_span(g->n, g->cfg.scan_blocks, 16);
         if (G * span >= INF32) return sssp_set_error(SSSP_ERR_UNSUPPORTED, "queue arrays: too many slots");
         b.qspan = (uint32_t)span;
-        HIP_OK(hipMalloc(&b.qd, G * span * 8));
-        HIP_OK(hipMalloc(&b.qv, G * span * 4));
-        HIP_OK(hipMalloc(&b.qm, G * span * 8));
-        HIP_OK(hipMalloc(&b.qcnt, G * 8));
+        void **const p[] = {(void **)&b.qd, (void **)&b.qv, (void **)&b.qm, (void **)&b.qcnt};
+        const uint64_t z[] = {G * span * 8, G * span * 4, G * span * 8, G * 8};
+        int rc = alloc_group(p, z, 4);
+        if (rc) return rc;
     }
     return SSSP_OK;
 }
@@ -2127,7 +2150,7 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
     hipLaunchKernelGGL(k_init_state, dim3(ib), dim3(256), 0, s, g->n, source, a.b.dist, a.b.st, phase_of,
                        dyn ? a.b.out_cur : nullptr, g->rp, (in_all >= IN_SIMPLE_M) ? a.b.in_cur : nullptr,
                        g->ip, delta_mode ? a.b.stamp : nullptr, a.b.out_head, g->edges, a.b.in_head, g->in_edges);
-    hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(64), 0, s, a.b.ctl, g->vmin, source, n_deltas);
+    hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(64), 0, s, a.b.ctl, g->vmin, g->rp, g->wmax, source, n_deltas);
     if (learn) hipLaunchKernelGGL(k_init_choice, dim3(1), dim3(64), 0, s, a, source, (int)delta_mode);
     const PhaseKernels K = oracle ? pick_oracle(g->cfg.chunk)
                                   : pick_phase(g->cfg.chunk, in, out, delta_mode, learn, trace_mode, queue_now);

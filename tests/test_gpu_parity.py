@@ -421,3 +421,33 @@ def test_switched_solve_launch_shapes(B, cfg):
         assert np.array_equal(r.dist_u64(), dj) and r.phases == rep.phases, cfg
         assert np.array_equal(r.phase_of.cpu().numpy().view(np.uint32), rep.phase_of), cfg
     dg.close()
+
+
+def test_max_weight_minima_every_static_path(B):
+    """A real static minimum of 2^32 - 1 is not an empty edge set (hand traces MAXW_IN, MAXW_OUT):
+    queue arrays, the dense scan, the one-workgroup kernel and the batched kernel all settle the
+    hand-derived sets and reach the oracle's distances; the single-query batch counts its phases."""
+    import json, os
+    fix = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "hand_traces.json")))
+    for key in ("MAXW_IN", "MAXW_OUT"):
+        ent = fix["graphs"][key]
+        g = G.from_edges(ent["n"], ent["edges"])
+        for name, sets in ent["phases"].items():
+            c = {"IN_STATIC": O.IN_STATIC, "OUT_STATIC": O.OUT_STATIC, "STATIC_OR": O.STATIC_OR}[name]
+            for queue in (1, 0):
+                dg = B.DeviceGraph.from_graph(g)
+                dg.set_launch(queue=queue)
+                r = B.solve_ex(dg, 0, c, phase_of=True)
+                po = r.phase_of.cpu().numpy().view(np.uint32)
+                got = [[v for v in range(g.n) if po[v] == p] for p in range(1, r.phases + 1)]
+                assert got == sets, (key, name, queue, got)
+                assert [int(x) for x in r.dist_u64()] == ent["dist"], (key, name, queue)
+                dg.set_launch(single=1)
+                r = B.solve(dg, 0, c)
+                assert [int(x) for x in r.dist_u64()] == ent["dist"] and r.phases == len(sets), (key, name)
+                dg.close()
+            dg = B.DeviceGraph.from_graph(g)
+            dists, phases = B.solve_batch([dg, dg], [0, 0], c)
+            for d, ph in zip(dists, phases):
+                assert [int(x) for x in B.to_u64(d)] == ent["dist"] and int(ph) == len(sets), (key, name)
+            dg.close()
