@@ -44,6 +44,21 @@ def build(force: bool = False) -> str:
     return _LIB_PATH
 
 
+_SAN_SRC = os.path.join(_HERE, "sanitize_main.c")
+_GEN_SRC = os.path.join(os.path.dirname(_HERE), "graphgen", "gen.c")
+SANITIZED_EXE = os.path.join(_HERE, "orc_sanitize")
+
+
+def build_sanitized(exe: str = SANITIZED_EXE) -> str:
+    """The stdin-driven sanitizer driver: oracle.c + graphgen/gen.c + sanitize_main.c, host code
+    built by gcc with AddressSanitizer and UndefinedBehaviorSanitizer."""
+    tmp = exe + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-std=c11", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                           "-fno-omit-frame-pointer", "-g", "-O1", _SRC, _GEN_SRC, _SAN_SRC, "-lm", "-o", tmp])
+    os.replace(tmp, exe)
+    return exe
+
+
 class _Stats(ctypes.Structure):
     _fields_ = [("phases", ctypes.c_uint32), ("pad", ctypes.c_uint32), ("sum_f", ctypes.c_uint64),
                 ("n_reach", ctypes.c_uint64), ("m_reach", ctypes.c_uint64),

@@ -451,3 +451,20 @@ def test_max_weight_minima_every_static_path(B):
             for d, ph in zip(dists, phases):
                 assert [int(x) for x in B.to_u64(d)] == ent["dist"] and int(ph) == len(sets), (key, name)
             dg.close()
+
+
+def test_delta_stepping_hand_traces(B):
+    """The hand-traced Delta-stepping runs (tests/golden/delta_hand_traces.json) on the GPU: distances,
+    rounds and buckets as traced by hand, and the per-round frontier sizes of the trace."""
+    import json, os
+    fix = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "delta_hand_traces.json")))
+    for key, ent in fix["graphs"].items():
+        g = G.from_edges(ent["n"], ent["edges"])
+        dg = B.DeviceGraph.from_graph(g)
+        r = B.delta_step_ex(dg, 0, [ent["delta"]], trace_cap=64)
+        assert [int(x) for x in r.dist_u64()] == ent["dist"], key
+        assert r.phases == ent["rounds"] and r.stats["buckets"] == ent["buckets"], (key, r.phases)
+        light = [len(f) for b in ent["frontiers"] for f in b]
+        got = [int(s) for s, k in zip(r.trace["settled"], r.trace["criterion"]) if int(k) != 2]
+        assert got == light, (key, got, light)
+        dg.close()

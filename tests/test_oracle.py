@@ -219,3 +219,19 @@ def test_config_small_static_or_runs_and_is_sound():
     r = O.phased(g, 0, O.STATIC_OR, check=True, dist_ref=d)
     assert r.n_reach == int((d != O.INF).sum()) > 0.99 * g.n  # a few vertices have no in-edge
     assert 1 + int(hops[d != O.INF].max()) <= r.phases < 1000
+
+
+def test_delta_stepping_hand_traces():
+    """Hand-traced Delta-stepping runs (tests/golden/delta_hand_traces.json): buckets needing several
+    light rounds, a vertex re-relaxed inside its bucket, and light rounds that discover or lower a
+    vertex at or past the window end, which must not join the bucket's next light round."""
+    fix = json.load(open(os.path.join(HERE, "golden", "delta_hand_traces.json")))
+    for key, ent in fix["graphs"].items():
+        g = G.from_edges(ent["n"], ent["edges"])
+        r = O.delta_step(g, 0, [ent["delta"]], trace_cap=16)
+        assert [int(x) for x in r.dist] == ent["dist"], key
+        assert [int(x) for x in O.dijkstra(g, 0)[0]] == ent["dist"], key
+        assert r.rounds == ent["rounds"] and r.buckets == ent["buckets"], (key, r.rounds, r.buckets)
+        assert r.light_relax == ent["light_relax"] and r.heavy_relax == ent["heavy_relax"], key
+        assert r.sum_frontier == ent["sum_frontier"] == sum(len(f) for b in ent["frontiers"] for f in b), key
+        assert r.rounds == sum(len(b) for b in ent["frontiers"]) + r.buckets, key
