@@ -38,6 +38,79 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+GOLDEN = os.path.join(ROOT, "tests", "golden", "full")
+
+
+def golden(graph, what, src):
+    """The oracle's stored expectations for a full-size run (written by tests/golden/make_full_size.py,
+    which calls only the oracle and the input generators), or None."""
+    path = os.path.join(GOLDEN, "%s_%s_s%d.json" % (graph, what.replace("|", "_"), src))
+    return json.load(open(path)) if os.path.exists(path) else None
+
+
+def dist_sha(d):
+    import hashlib
+    return hashlib.sha256(np.ascontiguousarray(d).astype("<u8").tobytes()).hexdigest()
+
+
+def exact_vs_golden(graph, src, d):
+    """Distances equal to the oracle's for this graph and source (SHA-256 of the uint64 array), or
+    None when no stored expectation exists."""
+    rec = golden(graph, "dist", src)
+    return None if rec is None else dist_sha(d) == rec["sha256"]
+
+
+def median_time(torch, fn, reps=3):
+    """Median wall time (s) of reps calls after one untimed call, and the last result."""
+    fn()
+    torch.cuda.synchronize()
+    ts, r = [], None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return sorted(ts)[len(ts) // 2], r
+
+
+class CpuBaseline:
+    """The oracle's binary-heap Dijkstra timed on the host, single-threaded per solve: `reps` solves
+    of the same graph and source one after the other on one background thread (the C oracle releases
+    the interpreter lock), started after the headline's timed region so that it overlaps the later
+    GPU legs rather than lengthening the run. Reports the median solve."""
+
+    def __init__(self, g, src, reps=10):
+        import threading
+        self.g, self.src, self.reps = g, src, reps
+        self.times, self.dist, self.err = [], None, None
+        self.th = threading.Thread(target=self._run, daemon=True)
+        self.th.start()
+
+    def _run(self):
+        try:
+            import oracle as O
+            for _ in range(self.reps):
+                t0 = time.perf_counter()
+                d, _ = O.dijkstra(self.g, self.src)
+                self.times.append(time.perf_counter() - t0)
+                self.dist = d
+        except Exception as e:  # reported in the JSON line
+            self.err = repr(e)
+
+    def result(self, m_reach):
+        self.th.join()
+        if self.err or not self.times:
+            return {"error": self.err or "no solve finished"}
+        med = sorted(self.times)[len(self.times) // 2]
+        return {"value": round(m_reach / med / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+                "seconds_median": round(med, 3), "seconds_min": round(min(self.times), 3),
+                "seconds_max": round(max(self.times), 3), "solves": len(self.times),
+                "host_nproc": os.cpu_count(),
+                "sample": "%d full solves of the same graph and source with the oracle's binary-heap Dijkstra, one "
+                          "thread, one solve at a time on a background thread while the later GPU legs ran; "
+                          "median" % len(self.times)}
+
+
 def alg_bytes(kernel, st, phases):
     """Algorithmic bytes per launch of a phase kernel (per-unit figures from the design notes)."""
     if kernel == "identify":
@@ -173,6 +246,12 @@ def bench_batched(B, torch, G):
     for dg, s_, d in zip(qg, qs, pd):
         qbytes += solve_bytes(B.solve_ex(dg, s_, B.STATIC_OR, d).stats, dg.n)
     same = all(np.array_equal(B.to_u64(a), B.to_u64(b)) for a, b in zip(dists, pd)) and list(bph) == pph
+    gpath = os.path.join(GOLDEN, "batch_c4.json")
+    exact = phases_ok = None
+    if os.path.exists(gpath):  # every query against the oracle's stored distances and phase count
+        grec = json.load(open(gpath))["queries"]
+        exact = all(dist_sha(B.to_u64(d)) == q["sha256"] for d, q in zip(dists, grec))
+        phases_ok = [int(x) for x in bph] == [q["phases"] for q in grec]
     res = {"workload": "64 graphs (random 2^12..2^18 deg 4..32, grids 64^2..512^2, R-MAT 12..18 ef 16), "
                        "8 sources each, weights [1, 2^16], IN_STATIC|OUT_STATIC",
            "queries": len(queries), "m_reach_total": m_reach, "batched_ms": round(tb * 1e3, 3),
@@ -180,7 +259,7 @@ def bench_batched(B, torch, G):
            "plain_gteps": round(m_reach / tp / 1e9, 4), "speedup_vs_plain": round(tp / tb, 2),
            "batched_solve_hbm_frac": round(qbytes / tb / 1e9 / HBM_PEAK_GBS, 4),
            "phases_total": int(sum(pph)), "max_phases": int(max(pph)), "autotuned": tuned,
-           "batched_equals_plain": bool(same)}
+           "batched_equals_plain": bool(same), "distances_exact": exact, "phases_equal_oracle": phases_ok}
     log("batched", res)
     return res
 
@@ -211,66 +290,88 @@ def bench_switched(B, torch, dg, src, m_reach, plain_ms, ref):
     return out
 
 
+def bench_c1(B, torch, G):
+    """The small random graph (n = 16384, out-degree 8, weights [1, 1000], source 0) with
+    IN_STATIC|OUT_STATIC: latency-bound (about a hundred short phases), so reported per phase, for
+    the grid-wide kernels and the one-workgroup launch option; median of 11 solves."""
+    g = G.config_small(seed=1)
+    dg = B.DeviceGraph.from_graph(g)
+    dist = B.new_dist(g.n)
+    st = B.solve_ex(dg, 0, B.STATIC_OR, dist).stats
+    rec = golden("er16k", "STATIC_OR", 0)
+    res = {"workload": "er_n16384_outdeg8_w1-1000_src0", "n": g.n, "m": g.m, "m_reach": st["m_reach"]}
+    for single in (0, 1):
+        dg.set_launch(single=single)
+        dt, r = median_time(torch, lambda: B.solve(dg, 0, B.STATIC_OR, dist), reps=11)
+        res["single" if single else "plain"] = {
+            "ms": round(dt * 1e3, 4), "phases": r.phases, "us_per_phase": round(dt * 1e6 / r.phases, 2),
+            "gteps": round(st["m_reach"] / dt / 1e9, 4),
+            "distances_exact": exact_vs_golden("er16k", 0, B.to_u64(dist)),
+            "phases_equal_oracle": None if rec is None else r.phases == rec["phases"]}
+    log("c1", res)
+    return res
+
+
 def bench_c3(B, torch, G, tuned):
-    """R-MAT scale 22 (8 sources) and the 2048^2 grid (2 sources): the plain solver with
-    IN_STATIC|OUT_STATIC against Delta-stepping, per solve (mean over the sources, one untimed call
-    before each timed one), with the launch shape tuned on the headline graph. The grid is
-    latency-bound (thousands of phases with a small F), so its plain figure is also given per phase."""
+    """R-MAT scale 22 and the 2048^2 grid, the 8 seeded sources each: the plain solver with
+    IN_STATIC|OUT_STATIC against Delta-stepping (2^12, 2^14, 2^16), median of three solves per
+    source, with the launch shape tuned on the headline graph; distances, phase and round counts
+    against the oracle's stored values. The grid is latency-bound (thousands of phases with a small
+    F), so its plain figure is also given per phase, with the one-workgroup launch option beside it."""
     res = {}
-    for name, make, nsrc in (("rmat_s22_ef16", lambda: G.config_rmat(seed=1), 8),
-                             ("grid_2048x2048", lambda: G.config_grid(seed=1), 2)):
+    for name, gname, make in (("rmat_s22_ef16", "rmat22", lambda: G.config_rmat(seed=1)),
+                              ("grid_2048x2048", "grid2048", lambda: G.config_grid(seed=1))):
         t = time.time()
         g = make()
         dg = B.DeviceGraph.from_graph(g)
         dg.set_launch(**tuned)
-        srcs = [int(x) for x in G.sources(g, nsrc, 11)]
+        srcs = [int(x) for x in G.sources(g, 8, 11)]
         dist = B.new_dist(g.n)
-        m_reach = sum(B.solve_ex(dg, s_, B.STATIC_OR, dist).stats["m_reach"] for s_ in srcs)
+        sts = [B.solve_ex(dg, s_, B.STATIC_OR, dist).stats for s_ in srcs]
+        m_reach = sum(x["m_reach"] for x in sts)
+        n_reach = sum(x["n_reach"] for x in sts)
+        checks = {"distances_exact": True, "phases_equal_oracle": True, "rounds_equal_oracle": True}
 
-        def run(fn):
+        def check(key, ok):
+            checks[key] = checks[key] and ok is not None and bool(ok)
+
+        def run(fn, kind=None):
             tot, ph = 0.0, 0
             for s_ in srcs:
-                fn(s_)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                r = fn(s_)
-                torch.cuda.synchronize()
-                tot += time.perf_counter() - t0
+                dt, r = median_time(torch, lambda: fn(s_))
+                tot += dt
                 ph += r.phases
+                check("distances_exact", exact_vs_golden(gname, s_, B.to_u64(dist)))
+                if kind is not None:
+                    rec = golden(gname, kind, s_)
+                    key = "rounds" if kind.startswith("delta") else "phases"
+                    check(key + "_equal_oracle", None if rec is None else r.phases == rec[key])
             return tot, ph
 
-        tp, php = run(lambda s_: B.solve(dg, s_, B.STATIC_OR, dist))
-        e = {"n": g.n, "m": g.m, "sources": nsrc, "plain_ms": round(tp * 1e3 / nsrc, 3),
+        nsrc = len(srcs)
+        tp, php = run(lambda s_: B.solve(dg, s_, B.STATIC_OR, dist), "STATIC_OR")
+        e = {"n": g.n, "m": g.m, "sources": nsrc, "m_reach_total": m_reach, "plain_ms": round(tp * 1e3 / nsrc, 3),
              "plain_phases": round(php / nsrc, 1), "plain_gteps": round(m_reach / tp / 1e9, 4),
              "plain_us_per_phase": round(tp * 1e6 / php, 2)}
-        n_reach = sum(B.solve_ex(dg, s_, B.STATIC_OR, dist).stats["n_reach"] for s_ in srcs)
         if n_reach <= 4096 * php:
             # few vertices settled per phase (the autotuner's rule): also the one-workgroup form
             dg.set_launch(single=1)
-            ts, phs = run(lambda s_: B.solve(dg, s_, B.STATIC_OR, dist))
+            ts, phs = run(lambda s_: B.solve(dg, s_, B.STATIC_OR, dist), "STATIC_OR")
             dg.set_launch(single=0)
             e["single_ms"] = round(ts * 1e3 / nsrc, 3)
             e["single_gteps"] = round(m_reach / ts / 1e9, 4)
             e["single_us_per_phase"] = round(ts * 1e6 / phs, 2)
-            e["single_phases_equal"] = phs == php
-        ref = B.to_u64(B.solve(dg, srcs[0], B.STATIC_OR, dist).dist)
-        same = True
         for k in (12, 14, 16):
-            td, rd = run(lambda s_: B.delta_step(dg, s_, 1 << k, dist))
-            same = same and bool(np.array_equal(B.to_u64(B.delta_step(dg, srcs[0], 1 << k, dist).dist), ref))
+            td, rd = run(lambda s_: B.delta_step(dg, s_, 1 << k, dist), "delta%d" % k)
             e["delta_2^%d" % k] = {"ms": round(td * 1e3 / nsrc, 3), "rounds": round(rd / nsrc, 1),
                                    "gteps": round(m_reach / td / 1e9, 4)}
-        e["delta_equals_plain"] = same
+        e.update(checks)
         if name.startswith("rmat"):
-            rp = B.solve(dg, srcs[0], B.STATIC_OR, dist)
-            t0 = time.perf_counter()
-            B.solve(dg, srcs[0], B.STATIC_OR, dist)
-            torch.cuda.synchronize()
-            tp0 = (time.perf_counter() - t0) * 1e3
-            e["switched_src0"] = bench_switched(B, torch, dg, srcs[0], B.solve_ex(dg, srcs[0], B.STATIC_OR, dist)
-                                                .stats["m_reach"], tp0, B.to_u64(rp.dist))
+            s0 = srcs[0]
+            tp0, rp = median_time(torch, lambda: B.solve(dg, s0, B.STATIC_OR, dist))
+            e["switched_src0"] = bench_switched(B, torch, dg, s0, sts[0]["m_reach"], tp0 * 1e3, B.to_u64(rp.dist))
             # the dominant kernel's roofline on the first source, as for the headline graph
-            rms, _, rst, rroof, _, _ = measure_plain(B, torch, dg, srcs[0], B.STATIC_OR, 3, 1, 0)
+            rms, _, rst, rroof, _, _ = measure_plain(B, torch, dg, s0, B.STATIC_OR, 3, 1, 0)
             e["roofline_src0"] = rroof
             e["solve_hbm_frac_src0"] = solve_frac(rst, rms, g.n)
         res[name] = e
@@ -433,29 +534,32 @@ def main():
         "atomic_min": atomics,
     }
 
+    gname = "er%d" % args.log2n
+    out["distances_exact"] = exact_vs_golden(gname, src, B.to_u64(dist))
+    cpu = None if args.no_cpu else CpuBaseline(g, src)
+
     if not args.no_extra:
+        # the other criteria and Delta-stepping on the same graph: median of three solves after one
+        # untimed one, distances and phase / round counts against the oracle's stored values
         forms = {}
         for name, c in [("IN_STATIC", B.IN_STATIC), ("OUT_STATIC", B.OUT_STATIC), ("SIMPLE_OR", B.SIMPLE_OR),
                         ("IN_FULL|OUT_WEAK", B.IN_FULL | B.OUT_WEAK), ("FULL_OR", B.FULL_OR)]:
-            B.solve(dg, src, c, dist)
-            torch.cuda.synchronize()
-            tt = time.perf_counter()
-            ph = B.solve(dg, src, c, dist).phases
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - tt
-            forms[name] = {"phases": ph, "ms": round(dt * 1e3, 3), "gteps": round(st["m_reach"] / dt / 1e9, 4)}
+            dt, r = median_time(torch, lambda: B.solve(dg, src, c, dist))
+            rec = golden(gname, name, src)
+            forms[name] = {"phases": r.phases, "ms": round(dt * 1e3, 3), "gteps": round(st["m_reach"] / dt / 1e9, 4),
+                           "distances_exact": exact_vs_golden(gname, src, B.to_u64(dist)),
+                           "phases_equal_oracle": None if rec is None else r.phases == rec["phases"]}
             log("criterion", name, forms[name])
         for k in (12, 14, 16):
-            B.delta_step(dg, src, 1 << k, dist)
-            torch.cuda.synchronize()
-            tt = time.perf_counter()
-            ph = B.delta_step(dg, src, 1 << k, dist).phases
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - tt
-            forms["delta_2^%d" % k] = {"rounds": ph, "ms": round(dt * 1e3, 3),
-                                       "gteps": round(st["m_reach"] / dt / 1e9, 4)}
+            dt, r = median_time(torch, lambda: B.delta_step(dg, src, 1 << k, dist))
+            rec = golden(gname, "delta%d" % k, src)
+            forms["delta_2^%d" % k] = {"rounds": r.phases, "ms": round(dt * 1e3, 3),
+                                       "gteps": round(st["m_reach"] / dt / 1e9, 4),
+                                       "distances_exact": exact_vs_golden(gname, src, B.to_u64(dist)),
+                                       "rounds_equal_oracle": None if rec is None else r.phases == rec["rounds"]}
             log("delta", k, forms["delta_2^%d" % k])
         out["forms"] = forms
+        out["c1"] = bench_c1(B, torch, G)
 
     if not args.no_extra and args.log2n == 22:
         # the largest random graph of the workloads (2^23 vertices, same out-degree and weights),
@@ -464,10 +568,14 @@ def main():
         dl = B.DeviceGraph.from_graph(gl)
         dl.set_launch(**tuned)
         lms, lph, lst, lroof, _, ldist = measure_plain(B, torch, dl, src, crit, 3, 1, 23)
+        rec = golden("er23", "STATIC_OR", src)
         out["largest"] = {"workload": "er_n%d_outdeg16_w1-2^20_src0" % gl.n, "n": gl.n, "m": gl.m,
+                          "solve_hbm_frac": solve_frac(lst, lms, gl.n),
                           "launch": tuned, "ms": round(lms, 3), "phases": lph,
-                          "gteps": round(lst["m_reach"] / (lms * 1e-3) / 1e9, 4), "roofline": lroof,
-                          "solve_hbm_frac": solve_frac(lst, lms, gl.n)}
+                          "gteps": round(lst["m_reach"] / (lms * 1e-3) / 1e9, 4),
+                          "distances_exact": exact_vs_golden("er23", src, B.to_u64(ldist)),
+                          "phases_equal_oracle": None if rec is None else lph == rec["phases"],
+                          "roofline": lroof}
         lroof["stream_copy_GBs"] = copy_gbs
         lroof["frac_vs_copy"] = round(lroof["achieved"] / copy_gbs, 4)
         log("largest", out["largest"])
@@ -486,18 +594,11 @@ def main():
     if not args.no_learned:
         out["learned"] = bench_learned(B, torch, G, dg, src, st["m_reach"], ms)
 
-    if not args.no_cpu:
-        import oracle as O
-        tc = time.perf_counter()
-        ref, _ = O.dijkstra(g, src)
-        tcpu = time.perf_counter() - tc
-        got = B.to_u64(dist) if args.no_extra else B.to_u64(B.solve(dg, src, crit, dist).dist)
-        out["distances_exact"] = bool(np.array_equal(got, ref))
-        out["cpu_baseline"] = {"value": round(st["m_reach"] / tcpu / 1e9, 5), "unit": "GTEPS", "cores": 1,
-                               "kind": "oracle", "seconds": round(tcpu, 2),
-                               "sample": "one full solve of the same graph and source with the oracle's "
-                                         "binary-heap Dijkstra (single thread)"}
-        log("cpu oracle %.1fs, exact=%s" % (tcpu, out["distances_exact"]))
+    if cpu is not None:
+        out["cpu_baseline"] = cpu.result(st["m_reach"])
+        if cpu.dist is not None:
+            out["distances_equal_cpu_oracle"] = bool(np.array_equal(B.to_u64(dist), cpu.dist))
+        log("cpu oracle", out["cpu_baseline"])
     print(json.dumps(out), flush=True)
 
 

@@ -1,7 +1,7 @@
 """Write the oracle's expected values for the full-size workloads (calls only oracle/ and graphgen).
 
 usage: python tests/golden/make_full_size.py JOB [JOB ...]
-  JOB = <graph>:<what>[:<sources>], graph in {er22, er23, rmat22, grid2048}, what in
+  JOB = <graph>:<what>[:<sources>], graph in {er16k, er22, er23, rmat22, grid2048}, what in
   {dist, STATIC_OR, IN_STATIC, OUT_STATIC, SIMPLE_OR, FULL_OR, IN_FULL|OUT_WEAK, delta12, delta14, delta16};
   sources = comma-separated indices into the graph's source list (default: all of them).
   JOB = batch writes the per-query expectations of the 512-query batch workload.
@@ -29,6 +29,7 @@ import oracle as O  # noqa: E402
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "full")
 
 GRAPHS = {
+    "er16k": lambda: G.config_small(seed=1),
     "er22": lambda: G.config_er_large(seed=1),
     "er23": lambda: G.config_er_large(seed=1, log2n=23),
     "rmat22": lambda: G.config_rmat(seed=1),
