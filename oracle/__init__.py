@@ -29,6 +29,7 @@ INF = np.uint64(0xFFFFFFFFFFFFFFFF)
 INF_INT = 0xFFFFFFFFFFFFFFFF
 
 DIJK, IN_STATIC, OUT_STATIC, IN_SIMPLE, OUT_SIMPLE, IN_FULL, OUT_WEAK, OUT_FULL = (1 << i for i in range(8))
+IN_APPROX, OUT_APPROX = 1 << 8, 1 << 9  # approximate criteria (Section 3, last paragraphs); see phased()
 BIT_NAMES = ["DIJK", "IN_STATIC", "OUT_STATIC", "IN_SIMPLE", "OUT_SIMPLE", "IN_FULL", "OUT_WEAK", "OUT_FULL"]
 CRIT = {name: 1 << i for i, name in enumerate(BIT_NAMES)}
 STATIC_OR = IN_STATIC | OUT_STATIC
@@ -84,7 +85,7 @@ def _L():
             lib.orc_bellman_ford.argtypes = [u32, P, P, P, u32, P]
             lib.orc_static_minima.argtypes = [u32, P, P, P, P, P]
             lib.orc_phased.argtypes = [u32, P, P, P, u32, u32, P, u32, i, P, P,
-                                       ctypes.POINTER(_Stats), u32, P, P, P, P, P, P, P, P, P, u32]
+                                       ctypes.POINTER(_Stats), u32, P, P, P, P, P, P, P, P, P, u32, u32]
             lib.orc_delta_step.argtypes = [u32, P, P, P, u32, P, u32, P, ctypes.POINTER(_DStats), u32, P, P]
             lib.orc_features.argtypes = [P, ctypes.c_double, i, P]
             lib.orc_features.restype = None
@@ -166,11 +167,13 @@ _ERRS = {-1: "invalid argument", -2: "out of memory", -10: "unsound: certified v
 
 
 def phased(g, src: int, crit: int, crit_seq=None, check: bool = False, dist_ref=None,
-           trace_cap: int | None = None, mlp_w=None, commit: int = 0) -> PhasedResult:
+           trace_cap: int | None = None, mlp_w=None, commit: int = 0, approx_k: int = 0) -> PhasedResult:
     """Generic phased algorithm of Section 3 with the given criterion bits.
 
     mlp_w: float32[5382] selector weights; the criterion of each phase is then the selector's
-    choice (crit is ignored). commit = K > 0: the choice made for phase K is kept from then on."""
+    choice (crit is ignored). commit = K > 0: the choice made for phase K is kept from then on.
+    IN_APPROX / OUT_APPROX: the approximate criteria, minima recomputed at the evaluation of a vertex
+    with at least approx_k counted changes (0: never)."""
     n, rp, col, w = _csr(g)
     mw = None if mlp_w is None else np.ascontiguousarray(mlp_w, np.float32)
     cap = n if trace_cap is None else trace_cap
@@ -188,7 +191,7 @@ def phased(g, src: int, crit: int, crit_seq=None, check: bool = False, dist_ref=
     rc = _L().orc_phased(n, _p(rp), _p(col), _p(w), src, crit, _p(seq), 0 if seq is None else len(seq),
                          int(check), _p(None if dist_ref is None else np.ascontiguousarray(dist_ref, np.uint64)),
                          _p(dist), ctypes.byref(st), cap, _p(tf), _p(ts), _p(tm), _p(tc), _p(po), _p(mw), _p(tcr),
-                         _p(tun), _p(tft), int(commit))
+                         _p(tun), _p(tft), int(commit), int(approx_k))
     if rc != 0:
         raise OracleError("orc_phased: %s (%d)" % (_ERRS.get(rc, "?"), rc))
     k = min(st.phases, cap)

@@ -74,7 +74,9 @@ enum { ST_U = 0, ST_F = 1, ST_S = 2 };
 enum {
     C_DIJK = 1u << 0, C_IN_STATIC = 1u << 1, C_OUT_STATIC = 1u << 2, C_IN_SIMPLE = 1u << 3,
     C_OUT_SIMPLE = 1u << 4, C_IN_FULL = 1u << 5, C_OUT_WEAK = 1u << 6, C_OUT_FULL = 1u << 7,
-    C_ALL = 0xFFu
+    C_ALL = 0xFFu,
+    /* approximate criteria (Section 3, last paragraphs): see approx_t below */
+    C_IN_APPROX = 1u << 8, C_OUT_APPROX = 1u << 9, C_APPROX = C_IN_APPROX | C_OUT_APPROX
 };
 
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_EUNSOUND = -10, ORC_EINCOMPLETE = -11,
@@ -496,15 +498,65 @@ static const uint32_t CHOICE_CRIT[3] = {C_IN_STATIC | C_OUT_STATIC, C_IN_SIMPLE 
 static const uint32_t ALL_BITS[8] = {C_DIJK, C_IN_STATIC, C_OUT_STATIC, C_IN_SIMPLE,
                                      C_OUT_SIMPLE, C_IN_FULL, C_OUT_WEAK, C_OUT_FULL};
 
-static int chain_ok(uint32_t b) {
-    /* DIJK => every criterion; X-STATIC => X-SIMPLE => (OUTWEAK =>) X */
+static int chain_ok(uint32_t b, uint32_t evaluated) {
+    /* DIJK => every criterion; X-STATIC => X-SIMPLE => (OUTWEAK =>) X; and, when the approximate
+     * criteria are evaluated, DIJK and X-STATIC => X-APPROX (an approximate minimum is never below the
+     * static one: it is a minimum over a subset of the same edges, each term at least its weight) */
 #define IMPL(a, c) (!(b & (a)) || (b & (c)))
     int ok = 1;
     for (int i = 1; i < 8; ++i) ok &= IMPL(C_DIJK, ALL_BITS[i]);
     ok &= IMPL(C_IN_STATIC, C_IN_SIMPLE) & IMPL(C_IN_SIMPLE, C_IN_FULL);
     ok &= IMPL(C_OUT_STATIC, C_OUT_SIMPLE) & IMPL(C_OUT_SIMPLE, C_OUT_WEAK) & IMPL(C_OUT_WEAK, C_OUT_FULL);
+    if (evaluated & C_IN_APPROX) ok &= IMPL(C_DIJK, C_IN_APPROX) & IMPL(C_IN_STATIC, C_IN_APPROX);
+    if (evaluated & C_OUT_APPROX) ok &= IMPL(C_DIJK, C_OUT_APPROX) & IMPL(C_OUT_STATIC, C_OUT_APPROX);
 #undef IMPL
     return ok;
+}
+
+/*
+ * Approximate criteria (Section 3, closing paragraphs). With each vertex v the
+ * paper keeps four minima: min_{w in F} c(w,v) and min_{w in U} (c(w,v) + min_{w'
+ * in V} c(w',w)) for IN, min_{w in F} c(v,w) and min_{w in U} (c(v,w) + min_{w' in
+ * V} c(w,w')) for OUTWEAK; each criterion uses the smaller of its pair, so one
+ * value per side is kept here: in[v] and out[v]. They are maintained
+ * conservatively -- never above the exact value, which would be unsound:
+ *   - a neighbour w moving U -> F turns its term c + minIn(w) (c + minOut(w)) into
+ *     c, a decrease, applied at once: in[v] = min(in[v], c(w,v)) for every out-edge
+ *     (w,v), out[u] = min(out[u], c(u,w)) for every in-edge (u,w);
+ *   - a neighbour moving F -> S removes a term, which may raise the exact value: it
+ *     is only counted (cin[v] per edge (w,v), cout[u] per edge (u,w)); the value is
+ *     recomputed from the current state when the vertex is evaluated (queued, at a
+ *     phase start) with at least k counted changes, and the count restarts;
+ *     k = 0: never recomputed (minima computed once, then only lowered).
+ * All values start exact for the state F = {s}. IN-APPROX(v): d[v] - in[v] <= minD;
+ * OUT-APPROX(v): d[v] <= min_{u in F} d[u] + out[u]. Changes of a phase are applied
+ * after its relaxation, so the next phase's evaluation sees them.
+ */
+typedef struct {
+    uint32_t k;
+    uint64_t *in, *out;
+    uint32_t *cin, *cout;
+} approx_t;
+
+static uint64_t approx_in_exact(uint32_t v, const csc_t *c, const uint8_t *st, const uint64_t *min_in) {
+    uint64_t t = INF;
+    for (uint64_t e = c->ip[v]; e < c->ip[v + 1]; ++e) {
+        uint32_t x = c->is[e];
+        if (st[x] == ST_F) t = min64(t, c->iw[e]);
+        else if (st[x] == ST_U) t = min64(t, sadd(c->iw[e], min_in[x]));
+    }
+    return t;
+}
+
+static uint64_t approx_out_exact(uint32_t u, const uint64_t *rp, const uint32_t *col, const uint32_t *w,
+                                 const uint8_t *st, const uint64_t *min_out) {
+    uint64_t t = INF;
+    for (uint64_t e = rp[u]; e < rp[u + 1]; ++e) {
+        uint32_t x = col[e];
+        if (st[x] == ST_F) t = min64(t, w[e]);
+        else if (st[x] == ST_U) t = min64(t, sadd(w[e], min_out[x]));
+    }
+    return t;
 }
 
 /*
@@ -533,8 +585,9 @@ int orc_phased(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32
                const uint64_t *dist_ref, uint64_t *dist_out, orc_stats *stats, uint32_t trace_cap,
                uint32_t *trace_f, uint32_t *trace_s, uint64_t *trace_mind, uint32_t *trace_counts,
                uint32_t *phase_of, const float *mlp_w, uint32_t *trace_crit, uint32_t *trace_union,
-               float *trace_feat, uint32_t commit) {
-    if (src >= n || (crit == 0 && !crit_seq && !mlp_w) || (crit & ~C_ALL)) return ORC_EINVAL;
+               float *trace_feat, uint32_t commit, uint32_t approx_k) {
+    if (src >= n || (crit == 0 && !crit_seq && !mlp_w) || (crit & ~(C_ALL | C_APPROX))) return ORC_EINVAL;
+    if ((crit & C_APPROX) && (crit_seq || mlp_w)) return ORC_EINVAL;
     int rc = ORC_OK;
     csc_t c = {0, 0, 0};
     uint64_t *min_in = (uint64_t *)malloc((uint64_t)n * 8), *min_out = (uint64_t *)malloc((uint64_t)n * 8);
@@ -544,6 +597,7 @@ int orc_phased(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32
     uint64_t *inner = (uint64_t *)malloc((uint64_t)n * 8);
     uint32_t *stamp = (uint32_t *)calloc(n, 4);
     memo_t M = {(uint64_t *)malloc((uint64_t)n * 8), (uint32_t *)calloc(n, 4), 0};
+    approx_t A = {approx_k, NULL, NULL, NULL, NULL};
     uint64_t *d = dist_out;
     orc_stats S;
     memset(&S, 0, sizeof S);
@@ -555,6 +609,17 @@ int orc_phased(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32
     for (uint32_t v = 0; v < n; ++v) d[v] = INF;
     if (phase_of) memset(phase_of, 0, (uint64_t)n * 4);
     d[src] = 0; st[src] = ST_F;
+    if (crit & C_APPROX) {  /* exact approximate minima for the state F = {s} */
+        A.in = (uint64_t *)malloc((uint64_t)n * 8);
+        A.out = (uint64_t *)malloc((uint64_t)n * 8);
+        A.cin = (uint32_t *)calloc(n, 4);
+        A.cout = (uint32_t *)calloc(n, 4);
+        if (!A.in || !A.out || !A.cin || !A.cout) { rc = ORC_ENOMEM; goto out; }
+        for (uint32_t v = 0; v < n; ++v) {
+            A.in[v] = approx_in_exact(v, &c, st, min_in);
+            A.out[v] = approx_out_exact(v, rp, col, w, st, min_out);
+        }
+    }
     uint64_t nF = 1;
     Fl[0] = src;
     uint32_t k = 0;
@@ -577,7 +642,7 @@ int orc_phased(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32
     }
     while (nF > 0) {
         uint32_t ck = crit_seq ? crit_seq[k < seq_len ? k : seq_len - 1] : crit;
-        uint32_t want = check ? C_ALL : ck;
+        uint32_t want = check ? C_ALL | (ck & C_APPROX) : ck;
         thresholds_t T;
         T.minD = INF;
         for (uint64_t i = 0; i < nF; ++i) T.minD = min64(T.minD, d[Fl[i]]);
@@ -585,21 +650,33 @@ int orc_phased(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32
             ck = CHOICE_CRIT[choice];
             want = (check ? C_ALL : ck) | C_IN_STATIC | C_OUT_STATIC;
         }
-        if (ck == 0 || (ck & ~C_ALL)) { rc = ORC_EINVAL; goto out; }
+        if (ck == 0 || (ck & ~(C_ALL | C_APPROX))) { rc = ORC_EINVAL; goto out; }
         if (k < trace_cap && trace_crit) trace_crit[k] = ck;
         out_thresholds(want, Fl, nF, rp, col, w, d, st, min_out, inner, stamp, k + 1, &T);
         M.now = k + 1;
+        uint64_t t_apx = INF;
+        if (want & C_APPROX) {
+            /* queued vertices with k or more counted changes recompute from this snapshot */
+            for (uint64_t i = 0; i < nF; ++i) {
+                uint32_t v = Fl[i];
+                if (A.k && A.cin[v] >= A.k) { A.in[v] = approx_in_exact(v, &c, st, min_in); A.cin[v] = 0; }
+                if (A.k && A.cout[v] >= A.k) { A.out[v] = approx_out_exact(v, rp, col, w, st, min_out); A.cout[v] = 0; }
+            }
+            for (uint64_t i = 0; i < nF; ++i) t_apx = min64(t_apx, sadd(d[Fl[i]], A.out[Fl[i]]));
+        }
         uint32_t cnt[8] = {0}, uni[3] = {0, 0, 0};
         uint64_t nS = 0, nK = 0, nin = 0, nout = 0;
         for (uint64_t i = 0; i < nF; ++i) {
             uint32_t v = Fl[i];
             uint32_t b = eval_bits(v, want, &T, d, st, min_in, &c, &M);
+            if ((want & C_IN_APPROX) && d[v] <= sadd(T.minD, A.in[v])) b |= C_IN_APPROX;
+            if ((want & C_OUT_APPROX) && d[v] <= t_apx) b |= C_OUT_APPROX;
             nin += (b & C_IN_STATIC) ? 1 : 0;
             nout += (b & C_OUT_STATIC) ? 1 : 0;
             if (check) {
                 for (int j = 0; j < 8; ++j) cnt[j] += (b & ALL_BITS[j]) ? 1 : 0;
                 for (int j = 0; j < 3; ++j) uni[j] += (b & CHOICE_CRIT[j]) ? 1 : 0;
-                if (!chain_ok(b)) { rc = ORC_ECHAIN; goto out; }
+                if (!chain_ok(b, want)) { rc = ORC_ECHAIN; goto out; }
                 if (d[v] == T.minD && !(b & C_DIJK)) { rc = ORC_EINCOMPLETE; goto out; }
             }
             if (b & ck) {
@@ -634,6 +711,7 @@ int orc_phased(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32
         /* settle all of S' (moved to S), then relax their out-edges */
         for (uint64_t i = 0; i < nS; ++i) st[Sp[i]] = ST_S;
         if (phase_of) for (uint64_t i = 0; i < nS; ++i) phase_of[Sp[i]] = k + 1;
+        const uint64_t nK0 = nK;  /* Fn[nK0 ..] will hold the vertices this relaxation discovers */
         for (uint64_t i = 0; i < nS; ++i) {
             uint32_t u = Sp[i];
             S.m_reach += rp[u + 1] - rp[u];
@@ -650,6 +728,20 @@ int orc_phased(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32
             }
         }
         S.n_reach += nS;
+        if (crit & C_APPROX) {
+            /* F -> S moves are counted on both sides of each edge of a settled vertex */
+            for (uint64_t i = 0; i < nS; ++i) {
+                uint32_t x = Sp[i];
+                for (uint64_t e = rp[x]; e < rp[x + 1]; ++e) A.cin[col[e]]++;
+                for (uint64_t e = c.ip[x]; e < c.ip[x + 1]; ++e) A.cout[c.is[e]]++;
+            }
+            /* U -> F moves lower the neighbours' minima at once */
+            for (uint64_t i = nK0; i < nK; ++i) {
+                uint32_t x = Fn[i];
+                for (uint64_t e = rp[x]; e < rp[x + 1]; ++e) A.in[col[e]] = min64(A.in[col[e]], w[e]);
+                for (uint64_t e = c.ip[x]; e < c.ip[x + 1]; ++e) A.out[c.is[e]] = min64(A.out[c.is[e]], c.iw[e]);
+            }
+        }
         uint32_t *t = Fl; Fl = Fn; Fn = t;
         nF = nK;
         ++k;
@@ -662,6 +754,7 @@ out:
     if (stats) *stats = S;
     free(min_in); free(min_out); free(st); free(Fl); free(Fn); free(Sp); free(inner); free(stamp);
     free(M.val); free(M.stamp);
+    free(A.in); free(A.out); free(A.cin); free(A.cout);
     free_csc(&c);
     return rc;
 }

@@ -43,7 +43,7 @@ int orc_phased(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32
                const uint32_t *crit_seq, uint32_t seq_len, int check, const uint64_t *dist_ref, uint64_t *dist_out,
                orc_stats *stats, uint32_t trace_cap, uint32_t *trace_f, uint32_t *trace_s, uint64_t *trace_mind,
                uint32_t *trace_counts, uint32_t *phase_of, const float *mlp_w, uint32_t *trace_crit,
-               uint32_t *trace_union, float *trace_feat, uint32_t commit);
+               uint32_t *trace_union, float *trace_feat, uint32_t commit, uint32_t approx_k);
 int orc_delta_step(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32_t *w, uint32_t src,
                    const uint64_t *deltas, uint32_t n_deltas, uint64_t *dist_out, orc_dstats *stats,
                    uint32_t trace_cap, uint64_t *trace_delta, const float *mlp_w);
@@ -55,8 +55,9 @@ int gg_grid(uint32_t W, uint32_t H, uint32_t wlo, uint32_t whi, uint64_t seed, u
             uint32_t *w);
 int gg_sources(uint32_t n, const uint64_t *row_ptr, uint32_t count, uint64_t seed, uint32_t *out);
 
-/* the criteria, as bit sets: each single bit, the three disjunctions, IN_FULL|OUT_WEAK */
-static const uint32_t CRITS[] = {1, 2, 4, 8, 16, 32, 64, 128, 6, 24, 160, 96};
+/* the criteria, as bit sets: each single bit, the three disjunctions, IN_FULL|OUT_WEAK, and the
+ * approximate pair with DIJK (recomputed every second change) */
+static const uint32_t CRITS[] = {1, 2, 4, 8, 16, 32, 64, 128, 6, 24, 160, 96, 769};
 #define NCRIT (sizeof CRITS / sizeof CRITS[0])
 
 static uint64_t fnv(uint64_t h, const void *p, size_t len) {
@@ -82,7 +83,7 @@ static int solve_all(uint32_t n, const uint64_t *rp, const uint32_t *col, const 
     for (size_t c = 0; c < NCRIT; ++c) {
         orc_stats st;
         int r = orc_phased(n, rp, col, w, src, CRITS[c], NULL, 0, 1, d, x, &st, 0, NULL, NULL, NULL, NULL, NULL,
-                           NULL, NULL, NULL, NULL, 0);
+                           NULL, NULL, NULL, NULL, 0, 2);
         if (r != 0 || memcmp(x, d, (size_t)n * 8)) { rc = 4; goto out; }
         printf(" %u %llu", st.phases, (unsigned long long)st.sum_f);
     }

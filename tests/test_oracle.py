@@ -235,3 +235,42 @@ def test_delta_stepping_hand_traces():
         assert r.light_relax == ent["light_relax"] and r.heavy_relax == ent["heavy_relax"], key
         assert r.sum_frontier == ent["sum_frontier"] == sum(len(f) for b in ent["frontiers"] for f in b), key
         assert r.rounds == sum(len(b) for b in ent["frontiers"]) + r.buckets, key
+
+
+def test_approximate_criteria_hand_traces():
+    """Approximate criteria (Section 3, closing paragraphs) against hand-traced runs
+    (tests/golden/approx_hand_traces.json) for several recomputation intervals k; k = 1 recomputes at
+    every change, so it must also equal the exact IN (full) / OUT-WEAK run."""
+    fix = json.load(open(os.path.join(HERE, "golden", "approx_hand_traces.json")))
+    names = {"DIJK|IN_APPROX": (O.DIJK | O.IN_APPROX, O.IN_FULL),
+             "DIJK|OUT_APPROX": (O.DIJK | O.OUT_APPROX, O.OUT_WEAK)}
+    for key, ent in fix["graphs"].items():
+        g = G.from_edges(ent["n"], ent["edges"])
+        d, _ = O.dijkstra(g, 0)
+        assert [int(x) for x in d] == ent["dist"], key
+        c, exact = names[ent["criterion"]]
+        for k, sets in ent["phases"].items():
+            r = O.phased(g, 0, c, check=True, dist_ref=d, approx_k=int(k))
+            got = [[v for v in range(ent["n"]) if r.phase_of[v] == p] for p in range(1, r.phases + 1)]
+            assert got == sets, (key, k, got)
+        ex = O.phased(g, 0, exact)
+        assert list(ex.phase_of) == list(O.phased(g, 0, c, approx_k=1).phase_of), key
+
+
+def test_approximate_criteria_invariants():
+    """On random multigraphs and every k: sound (check mode compares each settled distance with
+    Dijkstra), complete, at least as strong as the static criterion (DIJK and X-STATIC imply
+    X-APPROX on every snapshot, asserted in check mode), k = 1 equal to the exact IN (full) /
+    OUT-WEAK criteria, and phases between the ORACLE bound and the reachable vertex count."""
+    for g in small_graphs(150, 12000):
+        d, hops = O.dijkstra(g, 0)
+        lower = 1 + int(hops[d != O.INF].max())
+        n_reach = int((d != O.INF).sum())
+        for c, exact in ((O.DIJK | O.IN_APPROX, O.IN_FULL), (O.DIJK | O.OUT_APPROX, O.OUT_WEAK),
+                         (O.DIJK | O.IN_APPROX | O.OUT_APPROX, O.IN_FULL | O.OUT_WEAK)):
+            for k in (0, 1, 2, 5):
+                r = O.phased(g, 0, c | O.IN_STATIC | O.OUT_STATIC, check=True, dist_ref=d, approx_k=k)
+                assert lower <= r.phases <= n_reach
+                r = O.phased(g, 0, c, check=True, dist_ref=d, approx_k=k)
+                assert lower <= r.phases <= n_reach
+            assert list(O.phased(g, 0, c, approx_k=1).phase_of) == list(O.phased(g, 0, exact).phase_of)

@@ -19,7 +19,7 @@ import oracle as O
 
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-CRITS = [1, 2, 4, 8, 16, 32, 64, 128, 6, 24, 160, 96]  # same list and order as the driver
+CRITS = [1, 2, 4, 8, 16, 32, 64, 128, 6, 24, 160, 96, 769]  # same list and order as the driver (769: approx, k 2)
 
 
 def fnv(data: bytes) -> int:
@@ -50,7 +50,7 @@ def expected_line(g, src, deltas):
     n_reach = int((d != O.INF).sum())
     parts = ["OK", str(g.n), str(g.m), str(src), str(fnv(d.astype("<u8").tobytes())), str(n_reach)]
     for c in CRITS:
-        r = O.phased(g, src, c)
+        r = O.phased(g, src, c, approx_k=2)
         parts += [str(r.phases), str(r.sum_f)]
     for dl in deltas:
         r = O.delta_step(g, src, [int(dl)])
