@@ -70,7 +70,10 @@ enum {
     SSSP_IN_FULL = 1u << 5,
     SSSP_OUT_WEAK = 1u << 6,
     SSSP_OUT_FULL = 1u << 7,
-    SSSP_CRIT_ALL = 0xFFu
+    SSSP_CRIT_ALL = 0xFFu,
+    /* approximate criteria (Section 3, closing paragraphs), sssp_solve_approx only */
+    SSSP_IN_APPROX = 1u << 8,
+    SSSP_OUT_APPROX = 1u << 9
 };
 
 /* Per-solve statistics (Section 4 measures phases and the summed fringe sizes). */
@@ -196,7 +199,8 @@ int sssp_batch_get_config(sssp_batch_cfg *cfg);
  * the graph's stream around every kernel launch (observability; enabling it
  * adds one host synchronisation per batch of queued phases). */
 typedef struct {
-    uint32_t phases;       /* non-empty phases (or rounds) that were timed */
+    uint32_t phases;       /* non-empty phases (or rounds) that were timed; with keyed queue
+                              arrays also the rebuild launches */
     float term_ms;         /* total time of the dynamic-term pass kernels */
     float identify_ms;     /* total time of the identify kernels */
     float relax_ms;        /* total time of the relax kernels (learned mode: plus the selector) */
@@ -216,15 +220,37 @@ typedef struct {
 int sssp_solve_oracle(sssp_graph *g, uint32_t source, const uint64_t *dist_ref, uint64_t *dist_out,
                       sssp_stats *stats, uint32_t *phase_of);
 
+/*
+ * Phased SSSP with the approximate criteria of Section 3 (closing paragraphs).
+ * With each vertex v one IN value is kept, the minimum over in-edges (w,v) of
+ * c(w,v) for w in F and c(w,v) + min over all in-edges of w for w in U (the
+ * two IN minima of the paper), and one OUTWEAK value, the same over out-edges
+ * (v,w) with the minimum out-edge of w. They are kept conservatively, never
+ * above their exact value: a neighbour moving U -> F lowers them at once; a
+ * neighbour moving F -> S, which may raise the exact value, is only counted
+ * (per edge), and a queued vertex evaluated with at least k counted changes
+ * recomputes its values from the phase-start state (k = 0: never, the minima
+ * computed once and only lowered afterwards). Criteria: SSSP_IN_APPROX holds if
+ * d[v] - in[v] <= minD, SSSP_OUT_APPROX if d[v] <= min_{u in F} d[u] + out[u];
+ * criterion is a non-empty disjunction of SSSP_DIJK, SSSP_IN_APPROX and
+ * SSSP_OUT_APPROX (the paper combines the approximate criteria with DIJK;
+ * with non-negative weights DIJK implies both). k = 1 gives the exact IN
+ * (eq. crit:in) and OUTWEAK (eq. crit:outweak) criteria. Arguments otherwise as
+ * sssp_solve_ex; SSSP_ERR_INVALID for other criterion bits.
+ */
+int sssp_solve_approx(sssp_graph *g, uint32_t source, uint32_t criterion, uint32_t k, uint64_t *dist_out,
+                      sssp_stats *stats, uint32_t *phase_of, sssp_phase_rec *trace, uint32_t trace_cap);
+
 /* Turn per-kernel event timing on (enable != 0) or off for later solves on g. */
 int sssp_profile_enable(sssp_graph *g, int enable);
 
 /* Read the per-kernel times of the last solve run with timing on. */
 int sssp_profile_get(const sssp_graph *g, sssp_kernel_profile *out);
 
-/* Per-phase kernel time (term pass + identify + relax, milliseconds, phase
- * order) of the last phased solve run with timing on: *count receives the
- * number of phases, and the first min(*count, cap) times are written to ms
+/* Per-phase kernel time (term pass + identify + relax, milliseconds, launch
+ * order; a keyed rebuild launch, see sssp_launch_cfg.queue, has an entry of
+ * its own) of the last phased solve run with timing on: *count receives the
+ * number of entries, and the first min(*count, cap) times are written to ms
  * (host memory, caller-owned). Returns SSSP_ERR_INVALID for a NULL g or count,
  * or a NULL ms with cap > 0. */
 int sssp_profile_phases(const sssp_graph *g, float *ms, uint32_t cap, uint32_t *count);
@@ -241,9 +267,18 @@ typedef struct {
                                queue arrays, so identify reads F itself instead of scanning the
                                distance and minima arrays of all vertices (phases with 3/8 or more
                                of the vertices queued still use that dense scan); 0: the dense
-                               scan always. Applies when each scan block owns at most 16384
-                               vertices (n <= 4096 * scan_blocks * 4), else the dense scan runs.
-                               Ignored by every other criterion and solver. */
+                               scan always; 2: keyed queue arrays (the keyed priority queues of
+                               Section 5, partitioned by the IN-STATIC key d - minIn): a block's
+                               entries hold only the queued vertices whose key is at most a split
+                               kept above the phase's threshold (OUT-STATIC's T, else minD), which
+                               contain every vertex the phase certifies and the vertices attaining
+                               the next thresholds; the others are not read until the threshold
+                               passes the split, when one extra launch rebuilds the entries (it
+                               settles nothing and is not counted as a phase). sssp_solve and
+                               sssp_solve_ex only; switched and committed solves use 1. Applies
+                               when each scan block owns at most 16384 vertices (n <= 4096 *
+                               scan_blocks * 4), else the dense scan runs. Ignored by every other
+                               criterion and solver. Values above 2: SSSP_ERR_INVALID. */
     uint32_t single;        /* 1: sssp_solve with a criterion made of DIJK, IN_STATIC and OUT_STATIC
                                runs the whole solve in one workgroup of the batched kernel
                                (sssp_solve_batch with one query): no kernel launch per phase, for
@@ -263,7 +298,9 @@ int sssp_set_launch(sssp_graph *g, const sssp_launch_cfg *cfg);
 /*
  * Autotuner for the plain solver: times sssp_solve(g, source, criterion) with
  * HIP events for a set of launch shapes (scan grid, relax grid, chunk size,
- * graph replay), keeps the fastest on g and returns it in best (may be NULL)
+ * graph replay; for static criteria also the dense scan, queue arrays, keyed
+ * queue arrays and the one-workgroup option), keeps the fastest on g and
+ * returns it in best (may be NULL)
  * with its time in best_ms (may be NULL). Distances are never affected.
  */
 int sssp_autotune(sssp_graph *g, uint32_t source, uint32_t criterion, sssp_launch_cfg *best,

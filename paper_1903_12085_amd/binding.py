@@ -22,6 +22,7 @@ CRIT = {name: 1 << i for i, name in enumerate(CRIT_NAMES)}
 STATIC_OR = IN_STATIC | OUT_STATIC
 SIMPLE_OR = IN_SIMPLE | OUT_SIMPLE
 FULL_OR = IN_FULL | OUT_FULL
+IN_APPROX, OUT_APPROX = 1 << 8, 1 << 9  # approximate criteria (sssp_solve_approx)
 
 SYMBOLS = ["sssp_graph_create", "sssp_graph_destroy", "sssp_set_stream", "sssp_graph_minima", "sssp_solve",
            "sssp_solve_ex", "sssp_delta_step", "sssp_delta_step_ex", "sssp_solve_batch", "sssp_last_error",
@@ -32,7 +33,7 @@ SYMBOLS = ["sssp_graph_create", "sssp_graph_destroy", "sssp_set_stream", "sssp_g
            "sssp_selector_set_weights", "sssp_selector_forward", "sssp_selector_grad", "sssp_selector_train",
            "sssp_solve_learned", "sssp_delta_step_learned", "sssp_trace_learned",
            "sssp_solve_learned_commit", "sssp_measure_atomic_min", "sssp_solve_switch",
-           "sssp_solve_learned_switch"]
+           "sssp_solve_learned_switch", "sssp_solve_approx"]
 
 ERRORS = {-1: "SSSP_ERR_INVALID", -2: "SSSP_ERR_OOM", -3: "SSSP_ERR_DEVICE", -4: "SSSP_ERR_UNSUPPORTED",
           -5: "SSSP_ERR_INTERNAL"}
@@ -99,6 +100,7 @@ def load(path: str = LIB_PATH):
     lib.sssp_set_stream.argtypes = [P, P]
     lib.sssp_graph_minima.argtypes = [P, P, P]
     lib.sssp_solve.argtypes = [P, u32, u32, P, P]
+    lib.sssp_solve_approx.argtypes = [P, u32, u32, u32, P, ctypes.POINTER(Stats), P, P, u32]
     lib.sssp_solve_ex.argtypes = [P, u32, u32, P, ctypes.POINTER(Stats), P, P, u32]
     lib.sssp_delta_step.argtypes = [P, u32, u64, P, P]
     lib.sssp_solve_oracle.argtypes = [P, u32, P, P, ctypes.POINTER(Stats), P]
@@ -274,6 +276,24 @@ def solve_ex(g: DeviceGraph, source: int, criterion: int, dist=None, phase_of: b
     _check(load().sssp_solve_ex(g.handle, source, criterion, ctypes.c_void_p(dist.data_ptr()), ctypes.byref(st),
                                 ctypes.c_void_p(po.data_ptr()) if po is not None else None,
                                 _np_ptr(tr), trace_cap))
+    if tr is not None:
+        tr = tr[:min(st.phases, trace_cap)]
+    return SolveResult(dist, int(st.phases), st.as_dict(), po, tr)
+
+
+def solve_approx(g: DeviceGraph, source: int, criterion: int, k: int, dist=None, phase_of: bool = False,
+                 trace_cap: int = 0) -> SolveResult:
+    """sssp_solve_approx: the approximate criteria (criterion made of DIJK, IN_APPROX, OUT_APPROX),
+    minima recomputed after k counted changes (0: never)."""
+    import torch
+    dist = new_dist(g.n) if dist is None else dist
+    po = torch.empty(g.n, dtype=torch.int32, device="cuda") if phase_of else None
+    tr = np.zeros(trace_cap, PHASE_REC) if trace_cap else None
+    st = Stats()
+    g._bind_stream()
+    _check(load().sssp_solve_approx(g.handle, source, criterion, k, ctypes.c_void_p(dist.data_ptr()),
+                                    ctypes.byref(st), ctypes.c_void_p(po.data_ptr()) if po is not None else None,
+                                    _np_ptr(tr), trace_cap))
     if tr is not None:
         tr = tr[:min(st.phases, trace_cap)]
     return SolveResult(dist, int(st.phases), st.as_dict(), po, tr)

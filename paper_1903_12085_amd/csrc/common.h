@@ -14,9 +14,11 @@
 // flag written by the dynamic-term pass for the current phase (bit 3: the IN
 // (full) test, written only by the trace-mode term pass, which evaluates both).
 // Queue arrays only: bit 4 (ST_QNEW) = discovered by a relax since the vertex's
-// scan block last looked, bit 5 (ST_QDIRTY) = distance lowered since then.
+// scan block last looked, bit 5 (ST_QDIRTY) = distance lowered since then;
+// keyed queue arrays: bit 6 (ST_QFAR) = queued vertex kept out of its block's
+// entries because its IN-STATIC key d - minIn exceeded the split.
 enum : uint8_t { ST_U = 0, ST_F = 1, ST_S = 2, ST_R = 3, ST_SET = 3, ST_INOK = 4, ST_INOK_FULL = 8, ST_QNEW = 16,
-                 ST_QDIRTY = 32 };
+                 ST_QDIRTY = 32, ST_QFAR = 64 };
 
 // A settled vertex carries this bit in its distance word while the solve runs
 // (real distances stay below 2^58 and INF is all ones, so a word with the bit
@@ -81,6 +83,13 @@ struct alignas(128) CtlHead {
     unsigned long long last_settled;// |S'| of the last phase (selector feature input)
     unsigned int stalled;           // a phase with F non-empty certified nothing (bad ORACLE reference)
     unsigned int qlive[2];          // queue arrays: the phase with this parity left them current
+    // keyed queue arrays, by launch parity: the launch with parity p reads [p] and writes [p ^ 1]
+    unsigned int repart[2];         // the launch with this parity rebuilt the entries (not a phase)
+    unsigned int qprep[2];          // phase index of the last rebuild
+    unsigned long long qsplit[2];   // split: entries hold the queued vertices with d - minIn <= split
+    unsigned long long qdelta[2];   // split margin above the threshold at the last rebuild
+    unsigned long long qxrep[2];    // threshold at the last rebuild
+    unsigned int qrebuilds;         // rebuild launches so far (launches = phases + rebuilds)
 };
 
 // Device control block of one solve. Slots indexed by phase parity (mod 2 or
@@ -156,6 +165,9 @@ struct SolveBufs {
     uint2 *qm;              // its (minIn, minOut)
     uint32_t *qcnt;         // per scan block: slots in use, then tombstones among them
     uint32_t qspan;         // slots per scan block (vertices it owns)
+    // approximate criteria: phase index of each vertex's last IN / OUT recomputation, and the
+    // 1-based settle phase of each vertex (the caller's phase_of when given)
+    uint32_t *apx_lin, *apx_lout, *apx_sp;
 };
 
 int sssp_set_error(int code, const char *fmt, ...);
@@ -315,7 +327,7 @@ struct LaunchCfg {
     int relax_blocks;   // blocks of the relax kernel
     int chunk;          // edges per relax chunk (256, 512 or 1024)
     int use_graph;      // replay phases from a captured HIP graph
-    int queue;          // static criteria: per-block queue arrays instead of the dense scan
+    int queue;          // static criteria: per-block queue arrays instead of the dense scan (2: keyed)
     int single;         // sssp_solve with static criteria: the whole solve in one workgroup
 };
 constexpr int kMaxChunk = 2048;

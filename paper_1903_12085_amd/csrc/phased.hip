@@ -39,6 +39,7 @@ struct KArgs {
     DevGraph g;
     SolveBufs b;
     uint32_t crit;
+    uint32_t approx_k;   // approximate criteria: recompute after this many counted changes (0: never)
     const float *mlp_w;  // learned mode: selector weights (device)
     double wm;           // learned mode: mean edge weight (feature scale)
     const unsigned long long *ref;  // ORACLE mode: dist(s, .) of this source (device)
@@ -71,6 +72,14 @@ __device__ __forceinline__ void shard_fill(Sharded &s, unsigned long long x) {
 
 // ---------------------------------------------------------------------------
 // initialisation
+
+// Fill two u32 arrays of n entries with x (either may be null).
+__global__ void k_fill_u32(uint32_t n, uint32_t *__restrict__ p, uint32_t *__restrict__ q, uint32_t x) {
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        if (p) p[v] = x;
+        if (q) q[v] = x;
+    }
+}
 
 // End of a solve: drop the settled bit from every distance word.
 __global__ void k_clear_settled(uint32_t n, unsigned long long *__restrict__ d) {
@@ -108,12 +117,13 @@ __global__ void k_init_state(uint32_t n, uint32_t src, unsigned long long *__res
 
 // One block of 64 threads.
 __global__ void k_init_ctl(Ctl *ctl, const uint2 *__restrict__ vmin, const uint32_t *__restrict__ rp, uint32_t wmax,
-                           uint32_t src, uint32_t n_deltas) {
+                           uint32_t src, uint32_t n_deltas, unsigned long long qdelta0) {
     const int i = threadIdx.x;
     if (i == 0) {
         CtlHead h;
         memset(&h, 0, sizeof h);
         h.n_deltas = n_deltas;
+        h.qdelta[0] = qdelta0;  // keyed queue arrays: split margin of the first rebuild
         ctl->h = h;
     }
     if (i < kShards) {
@@ -517,6 +527,81 @@ __global__ __launch_bounds__(kBlock) void k_terms(KArgs a, int par) {
     terms_body<IN, OUT>(a, par, sh);
 }
 
+// Approximate criteria (Section 3, closing paragraphs): per queued vertex the
+// IN value (minimum over in-edges (w,v): c for w queued, c + minIn(w) for w
+// unexplored) and the OUTWEAK value (out-edges (v,w): c for w queued, c +
+// minOut(w) for w unexplored), maintained conservatively: a neighbour's move
+// U -> F lowers the value at once, a move F -> S only counts as a change, and a
+// vertex evaluated with k or more counted changes recomputes from this phase's
+// state (k = 0: never). Evaluated here in closed form from the settle phase of
+// each neighbour: the kept value equals the exact one except that neighbours
+// settled after the vertex's last recomputation (phase index L) still count as
+// queued, and the counted changes are exactly those edges. One pass over the row
+// gives both the exact minimum and the stale terms; a recomputation sets L to
+// this phase's index (every settled vertex settled in a phase <= it).
+template <bool IN_ON, bool OUT_ON>
+__global__ __launch_bounds__(kBlock) void k_terms_approx(KArgs a, int par) {
+    __shared__ unsigned long long sh[8 * kWaves];
+    Ctl *ctl = a.b.ctl;
+    const int p2 = par & 1, p3 = par % 3;
+    __shared__ unsigned long long s_reached, s_minD;
+    const unsigned int P = ctl->h.pnum[p2];
+    if (threadIdx.x < 64) {
+        const unsigned long long r0 = lane_slot(ctl->reached, 0ull), m0 = lane_slot(ctl->minD[p3], INF64);
+        const unsigned long long r = wave_sum64(r0);
+        const unsigned long long md = wave_min64(m0);
+        if (threadIdx.x == 0) { s_reached = r; s_minD = md; }
+    }
+    __syncthreads();
+    if (s_reached == ctl->h.settled) return;
+    const unsigned long long minD = s_minD;
+    const uint32_t k = a.approx_k;
+    unsigned long long tmin = INF64;
+    const uint32_t n = a.g.n;
+    for (uint32_t v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) {
+        const uint8_t s = a.b.st[v];
+        if ((s & ST_SET) != ST_F) continue;
+        const unsigned long long dv = a.b.dist[v];
+        if (IN_ON) {
+            const uint32_t L = a.b.apx_lin[v];
+            unsigned long long exact = INF64, stale = INF64;
+            uint32_t changes = 0;
+            const uint32_t end = a.g.ip[v + 1];
+            for (uint32_t e = a.g.ip[v]; e < end; ++e) {
+                const uint2 ie = a.g.in_edges[e];
+                const uint8_t sw = a.b.st[ie.x] & ST_SET;
+                if (sw == ST_F) exact = umin64(exact, ie.y);
+                else if (sw == ST_U) exact = umin64(exact, sadd64(ie.y, min_in_u64(a.g.vmin[ie.x].x, a.g.wmax, a.g.ip, ie.x)));
+                else if (a.b.apx_sp[ie.x] > L) { stale = umin64(stale, ie.y); ++changes; }
+            }
+            const bool recompute = k && changes >= k;
+            if (recompute) a.b.apx_lin[v] = P;
+            const unsigned long long term = recompute ? exact : umin64(exact, stale);
+            a.b.st[v] = dv <= sadd64(minD, term) ? (uint8_t)(ST_F | ST_INOK) : (uint8_t)ST_F;
+        }
+        if (OUT_ON) {
+            const uint32_t L = a.b.apx_lout[v];
+            unsigned long long exact = INF64, stale = INF64;
+            uint32_t changes = 0;
+            const uint32_t end = a.g.rp[v + 1];
+            for (uint32_t e = a.g.rp[v]; e < end; ++e) {
+                const uint2 ed = a.g.edges[e];
+                const uint8_t sx = a.b.st[ed.x] & ST_SET;
+                if (sx == ST_F) exact = umin64(exact, ed.y);
+                else if (sx == ST_U) exact = umin64(exact, sadd64(ed.y, min_out64(a.g.vmin[ed.x].y, a.g.wmax, a.g.rp, ed.x)));
+                else if (a.b.apx_sp[ed.x] > L) { stale = umin64(stale, ed.y); ++changes; }
+            }
+            const bool recompute = k && changes >= k;
+            if (recompute) a.b.apx_lout[v] = P;
+            tmin = umin64(tmin, sadd64(dv, recompute ? exact : umin64(exact, stale)));
+        }
+    }
+    if (OUT_ON) {
+        block_reduce<kWaves, 1u, 1u>(&tmin, sh);
+        if (threadIdx.x == 0 && tmin != INF64) atomicMin(slot_of(ctl->tdyn[p3], my_shard()), tmin);
+    }
+}
+
 // Learned mode: the term pass of the criterion the selector chose for this phase.
 __global__ __launch_bounds__(kBlock) void k_terms_learned(KArgs a, int par) {
     __shared__ unsigned long long sh[8 * kWaves];
@@ -796,7 +881,25 @@ constexpr uint32_t kQWin = 4 * kOwnSpan;     // most vertices a scan block may o
 // back waits until F is below 3/10 of the vertices, so that F sizes near the
 // threshold do not rebuild every other phase. Every block takes the same
 // decision from the phase-start counters.
-template <int IN, int OUT, int CH>
+//
+// KEYED (launch option queue = 2; the paper's keyed queues of Section 5 in one
+// partition): a block's entries hold only the queued vertices whose IN-STATIC
+// key d - minIn is at most a grid-wide split; the others carry ST_QFAR in their
+// state byte and are not read. Every vertex the criteria certify has key <= X,
+// X = the OUT-STATIC threshold T when OUT-STATIC is on (d <= T gives key <= T,
+// and minD <= T), else minD; the vertices attaining minD and T have key <= X as
+// well. So while the split is >= X, the entries alone certify the phase and fold
+// the next thresholds exactly: a far vertex has d >= key > split >= X. Relax
+// flags the far vertices it lowers; their owner moves those whose key fell to
+// the split into its entries. When the folded threshold of a launch exceeds the
+// split, that launch is a rebuild and not a phase: every block gathers all its
+// queued vertices, enters those with key <= X + margin (the new split), marks
+// the rest far, and folds the exact minD and T over all of them; relax skips
+// it and the next launch runs the phase. The margin is kSplitPhases times the
+// threshold's advance per phase since the previous rebuild.
+constexpr unsigned long long kSplitPhases = 16;
+
+template <int IN, int OUT, int CH, bool KEYED = false>
 __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
     __shared__ unsigned long long sh[8 * kWaves];
     __shared__ AppendLds L;
@@ -811,10 +914,13 @@ __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
     const unsigned int live = ctl->h.qlive[p2];
     const unsigned int P = ctl->h.pnum[p2];
     const uint32_t n = a.g.n, b = blockIdx.x, G = gridDim.x;
-    const uint32_t cnt0 = live ? a.b.qcnt[2 * b] : 0u, tomb0 = live ? a.b.qcnt[2 * b + 1] : 0u;
+    const uint32_t cnt_l = a.b.qcnt[2 * b], tomb_l = a.b.qcnt[2 * b + 1];
+    const unsigned long long ksplit = KEYED ? ctl->h.qsplit[p2] : 0ull, kdelta = KEYED ? ctl->h.qdelta[p2] : 0ull;
+    const unsigned long long kxrep = KEYED ? ctl->h.qxrep[p2] : 0ull;
+    const unsigned int kprep = KEYED ? ctl->h.qprep[p2] : 0u;
     const unsigned long long reached = wave_sum64(r0);
     const unsigned long long nf = reached - settled;
-    const bool dense = live ? nf * 8 >= 3ull * n : nf * 10 >= 3ull * n;  // grid-uniform
+    const bool dense = !KEYED && (live ? nf * 8 >= 3ull * n : nf * 10 >= 3ull * n);  // grid-uniform
     if (dense) {
         if (b == 0 && threadIdx.x == 0 && nf) ctl->h.qlive[p2 ^ 1] = 0;
         identify_body<IN, OUT, CH, false>(a, par, sh, L);
@@ -824,10 +930,50 @@ __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
     const unsigned long long minD = wave_min64(m0);
     const unsigned long long T = OUT == 1 ? wave_min64(t0) : 0ull;
     if (phase_done(ctl, p2, P, reached, settled)) return;
-    if (b == 0) {
+    // keyed: a rebuild when the entries are not current or the threshold passed the split
+    const unsigned long long X = OUT == 1 ? T : minD;
+    const bool rebuild = KEYED && (!live || X > ksplit);  // grid-uniform
+    unsigned long long split = ksplit;
+    if (rebuild) {
+        unsigned long long margin = kdelta;
+        if (live && P > kprep && X > kxrep) {
+            const unsigned long long rate = (X - kxrep) / (P - kprep);
+            margin = rate > INF64 / kSplitPhases ? INF64 : rate * kSplitPhases;
+            if (margin < 1) margin = 1;
+        }
+        split = sadd64(X, margin);
+        if (b == 0) {
+            if (threadIdx.x == 0) {
+                ctl->h.repart[p2] = 1;
+                ctl->h.qrebuilds += 1;
+                ctl->h.pnum[p2 ^ 1] = P;  // the next launch runs phase P
+                ctl->h.qsplit[p2 ^ 1] = split;
+                ctl->h.qdelta[p2 ^ 1] = margin;
+                ctl->h.qxrep[p2 ^ 1] = X;
+                ctl->h.qprep[p2 ^ 1] = P;
+                ctl->h.qlive[p2 ^ 1] = 1;
+            }
+            // the slots the next launch (phase P) clears in a phase: its S' counters and the
+            // fold slots of the phase after it (this launch folds phase P's exact thresholds)
+            shard_fill(ctl->spack[p2 ^ 1], 0);
+            shard_fill(ctl->szero[p2 ^ 1], 0);
+            shard_fill(ctl->minD[(p3 + 2) % 3], INF64);
+            shard_fill(ctl->tst[(p3 + 2) % 3], INF64);
+        }
+    } else if (b == 0) {
         phase_open<false, false>(a, ctl, p2, p3, P, reached, settled, minD, 0ull);
-        if (threadIdx.x == 0) ctl->h.qlive[p2 ^ 1] = 1;
+        if (threadIdx.x == 0) {
+            ctl->h.qlive[p2 ^ 1] = 1;
+            if (KEYED) {
+                ctl->h.repart[p2] = 0;
+                ctl->h.qsplit[p2 ^ 1] = ksplit;
+                ctl->h.qdelta[p2 ^ 1] = kdelta;
+                ctl->h.qxrep[p2 ^ 1] = kxrep;
+                ctl->h.qprep[p2 ^ 1] = kprep;
+            }
+        }
     }
+    const uint32_t cnt0 = live && !rebuild ? cnt_l : 0u, tomb0 = live && !rebuild ? tomb_l : 0u;
     // state bytes of the block's vertices into LDS (window w = the block's w-th grid step)
     const uint32_t span = a.b.qspan;
 #pragma unroll 1
@@ -960,8 +1106,15 @@ __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
     }
     const uint32_t cnt = compact ? kept : cnt0;  // block-uniform
     // 2. vertices that need an entry: new ones, or (rebuild) every queued one; sixteen
-    // state bytes per lane from the LDS window
+    // state bytes per lane from the LDS window. Keyed: also far vertices whose distance
+    // dropped; a vertex stays far (no entry, no fold) while its key exceeds the split,
+    // except in a rebuild, which folds every queued vertex and certifies none.
     const int lane = threadIdx.x & 63;
+    const bool gather_all = KEYED ? rebuild : !live;
+    auto in_key = [&](unsigned long long d, uint2 mm) {  // d - minIn, floored at 0 (eq. crit:instatic)
+        const unsigned long long mi = min_in_test(mm.x);
+        return d > mi ? d - mi : 0ull;
+    };
 #pragma unroll 1
     for (uint32_t w = 0; w * kOwnSpan < span; ++w) {
         const uint64_t v0 = (uint64_t)kOwnSpan * ((uint64_t)w * G + b) + 16u * threadIdx.x;
@@ -974,7 +1127,10 @@ __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const uint32_t sb = (xs[q] >> (8 * j)) & 0xffu;
-                if (live ? (sb & ST_QNEW) != 0 : (sb & ST_SET) == ST_F) nm |= 1u << (4 * q + j);
+                const bool need = gather_all ? (sb & ST_SET) == ST_F
+                                  : KEYED ? (sb & ST_QNEW) != 0 || (sb & (ST_QDIRTY | ST_QFAR)) == (ST_QDIRTY | ST_QFAR)
+                                          : (sb & ST_QNEW) != 0;
+                if (need) nm |= 1u << (4 * q + j);
             }
         while (__ballot(nm != 0)) {  // wavefront-uniform: one vertex per lane per round
             const bool has = nm != 0;
@@ -987,14 +1143,16 @@ __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
                 d = a.b.dist[v];
                 mm = a.g.vmin[v];
             }
-            const bool ok = has && certified(d, mm);
+            const bool ok = has && !rebuild && certified(d, mm);
             if (ok) settle(v, d, row, deg);
             append_settled<CH>(a, ctl, p2, L, ok, row, deg, d);
-            const bool app = has && !ok;
-            if (app) {
+            const bool far = KEYED && has && !ok && in_key(d, mm) > split;
+            const bool app = has && !ok && !far;
+            if (app || (rebuild && far)) {
                 fmin = umin64(fmin, d);
                 if (OUT == 1) ftst = umin64(ftst, sadd64(d, min_out64(mm.y, a.g.wmax, a.g.rp, v)));
             }
+            if (far) a.b.st[v] = ST_F | ST_QFAR;
             const unsigned long long am = __ballot(app);
             if (am) {
                 uint32_t base = 0;
@@ -1293,6 +1451,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
     __shared__ unsigned long long s_tot_settled, s_tot_edges;
     // header fields, loaded with the shard slots (before the barrier)
     const unsigned int done = ctl->h.done, P = ctl->h.pnum[p2];
+    const unsigned int rebuilt = Q ? ctl->h.repart[p2] : 0u;  // keyed: a rebuild launch, not a phase
     const unsigned int rmode = DELTA ? ctl->h.rmode[p2] : 0u;
     const unsigned long long win_hi = DELTA ? ctl->h.win_hi : INF64, win_delta = DELTA ? ctl->h.win_delta : 0ull;
     if (threadIdx.x < 64) {
@@ -1314,6 +1473,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
         if (i == 0) { s_tot_settled = tset; s_tot_edges = tedge; }
     }
     __syncthreads();
+    if (rebuilt) return;  // it settled nothing (its S' counters are zero) and relaxes nothing
     if (!DELTA && s_tot_settled == 0 && !done && blockIdx.x == 0 && threadIdx.x == 0) {
         // F is non-empty but nothing was certified: only an ORACLE reference that is not
         // dist(s, .) gets here (every other criterion certifies the queue minimum)
@@ -1590,6 +1750,7 @@ void solve_bufs_free(sssp_graph *g) {
     sssp_free(b.chunk_start); sssp_free(b.in_cur); sssp_free(b.out_cur); sssp_free(b.stamp); sssp_free(b.deltas);
     sssp_free(b.in_head); sssp_free(b.out_head);
     sssp_free(b.qd); sssp_free(b.qv); sssp_free(b.qm); sssp_free(b.qcnt);
+    sssp_free(b.apx_lin); sssp_free(b.apx_lout); sssp_free(b.apx_sp);
     sssp_free(g->one_st); sssp_free(g->one_fl); sssp_free(g->one_aux);
     g->one_st = nullptr;
     g->one_fl = nullptr;
@@ -1651,7 +1812,7 @@ static int alloc_group(void **const *ptr, const uint64_t *bytes, int k) {
     return SSSP_OK;
 }
 
-int solve_bufs_ensure(sssp_graph *g, bool cursors, bool stamps, bool queue) {
+int solve_bufs_ensure(sssp_graph *g, bool cursors, bool stamps, bool queue, bool approx) {
     SolveBufs &b = g->b;
     const uint64_t n = g->n;
     if (g->bufs_ready && g->bufs_scan_blocks != (uint32_t)g->cfg.scan_blocks) {
@@ -1693,6 +1854,12 @@ int solve_bufs_ensure(sssp_graph *g, bool cursors, bool stamps, bool queue) {
         int rc = alloc_group(p, z, 4);
         if (rc) return rc;
     }
+    if (approx && !(b.apx_lin && b.apx_lout && b.apx_sp)) {
+        void **const p[] = {(void **)&b.apx_lin, (void **)&b.apx_lout, (void **)&b.apx_sp};
+        const uint64_t z[] = {n * 4, n * 4, n * 4};
+        int rc = alloc_group(p, z, 3);
+        if (rc) return rc;
+    }
     return SSSP_OK;
 }
 
@@ -1726,17 +1893,23 @@ static kfn pick_terms(int in, int out) {
 
 struct PhaseKernels {
     kfn terms = nullptr, identify = nullptr, relax = nullptr, select = nullptr;
+    int keyed = 0;  // keyed queue arrays: a launch may rebuild instead of running a phase
 };
 
 
 template <int CH>
-static PhaseKernels pick_queue(int in, int out) {
+static PhaseKernels pick_queue(int in, int out, bool keyed) {
     static const kfn tab[3][2] = {
         {nullptr, k_identify_queue<IN_NONE, 1, CH>},
         {k_identify_queue<IN_DIJK, 0, CH>, k_identify_queue<IN_DIJK, 1, CH>},
         {k_identify_queue<IN_STATIC_M, 0, CH>, k_identify_queue<IN_STATIC_M, 1, CH>}};
+    static const kfn tabk[3][2] = {
+        {nullptr, k_identify_queue<IN_NONE, 1, CH, true>},
+        {k_identify_queue<IN_DIJK, 0, CH, true>, k_identify_queue<IN_DIJK, 1, CH, true>},
+        {k_identify_queue<IN_STATIC_M, 0, CH, true>, k_identify_queue<IN_STATIC_M, 1, CH, true>}};
     PhaseKernels k;
-    k.identify = tab[in][out];
+    k.identify = keyed ? tabk[in][out] : tab[in][out];
+    k.keyed = keyed;
     k.relax = out == OUT_STATIC_M ? k_relax<CH, false, true, false, true> : k_relax<CH, false, false, false, true>;
     return k;
 }
@@ -1768,18 +1941,43 @@ static PhaseKernels pick_phase_ch(int in, int out, bool delta, bool learn, bool 
     return k;
 }
 
-static PhaseKernels pick_phase(int chunk, int in, int out, bool delta, bool learn, bool trace, bool queue = false) {
+static PhaseKernels pick_phase(int chunk, int in, int out, bool delta, bool learn, bool trace, bool queue = false,
+                               bool keyed = false) {
     if (queue) {
         switch (chunk) {
-        case 256: return pick_queue<256>(in, out);
-        case 1024: return pick_queue<1024>(in, out);
-        default: return pick_queue<512>(in, out);
+        case 256: return pick_queue<256>(in, out, keyed);
+        case 1024: return pick_queue<1024>(in, out, keyed);
+        default: return pick_queue<512>(in, out, keyed);
         }
     }
     switch (chunk) {
     case 256: return pick_phase_ch<256>(in, out, delta, learn, trace);
     case 1024: return pick_phase_ch<1024>(in, out, delta, learn, trace);
     default: return pick_phase_ch<512>(in, out, delta, learn, trace);
+    }
+}
+
+// Approximate criteria: their term pass, then identify with the IN flag (3) and/or the
+// dynamic OUT threshold (2), DIJK otherwise implied (it implies both criteria).
+template <int CH>
+static PhaseKernels pick_approx_ch(uint32_t crit) {
+    const bool in = crit & SSSP_IN_APPROX, out = crit & SSSP_OUT_APPROX;
+    PhaseKernels k;
+    k.terms = in ? (out ? k_terms_approx<true, true> : k_terms_approx<true, false>)
+                 : (out ? k_terms_approx<false, true> : nullptr);
+    k.identify = in ? (out ? k_identify<3, 2, CH> : k_identify<3, 0, CH>)
+                    : (out ? k_identify<1, 2, CH> : k_identify<1, 0, CH>);
+    if (in && !out && !(crit & SSSP_DIJK)) k.identify = k_identify<3, 0, CH>;
+    if (!in && out && !(crit & SSSP_DIJK)) k.identify = k_identify<0, 2, CH>;
+    k.relax = k_relax<CH, false, false, false>;
+    return k;
+}
+
+static PhaseKernels pick_approx(int chunk, uint32_t crit) {
+    switch (chunk) {
+    case 256: return pick_approx_ch<256>(crit);
+    case 1024: return pick_approx_ch<1024>(crit);
+    default: return pick_approx_ch<512>(crit);
     }
 }
 
@@ -1831,7 +2029,7 @@ static int run_loop_profiled(sssp_graph *g, const KArgs &a, const PhaseKernels &
         HIP_OK(hipGetLastError());
         HIP_OK(hipMemcpyAsync(&g->h_ctl[0], a.b.ctl, sizeof(CtlHead), hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
-        const uint64_t real = g->h_ctl[0].phases;
+        const uint64_t real = g->h_ctl[0].phases + g->h_ctl[0].qrebuilds;  // launches that did work
         for (uint32_t i = 0; kb + i < k && kb + i < real; ++i) {
             float t0 = 0, t1 = 0, t2 = 0;
             hipEvent_t *e = &g->pev[4 * i];
@@ -1849,7 +2047,7 @@ static int run_loop_profiled(sssp_graph *g, const KArgs &a, const PhaseKernels &
             if (head) *head = g->h_ctl[0];
             break;
         }
-        if (k > max_phases + 2 * kBatch)
+        if (k > (K.keyed ? 2 : 1) * max_phases + 2 * kBatch)
             return sssp_set_error(SSSP_ERR_INTERNAL, "phase loop did not terminate after %llu phases",
                                   (unsigned long long)k);
     }
@@ -1951,7 +2149,7 @@ static int run_loop(sssp_graph *g, const KArgs &a, const PhaseKernels &K, uint64
         have_prev = true;
         slot ^= 1;
         if (batch < 16) batch *= 2;
-        if (k > max_phases + 2 * 64 + 8)
+        if (k > (K.keyed ? 2 : 1) * max_phases + 2 * 64 + 8)  // keyed: at most one rebuild per phase
             return sssp_set_error(SSSP_ERR_INTERNAL, "phase loop did not terminate after %llu phases",
                                   (unsigned long long)k);
     }
@@ -2057,7 +2255,7 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
                         sssp_stats *stats, uint32_t *phase_of, sssp_phase_rec *trace,
                         uint32_t trace_cap, const sssp_selector *sel = nullptr, float *feat_host = nullptr,
                         uint32_t *cf_host = nullptr, const uint64_t *oracle_ref = nullptr, uint32_t commit = 0,
-                        const SwitchReq *sw = nullptr) {
+                        const SwitchReq *sw = nullptr, const uint32_t *apx = nullptr) {
     const bool learn = sel != nullptr;
     const bool oracle = oracle_ref != nullptr;
     const bool trace_mode = learn && !delta_mode && cf_host != nullptr;
@@ -2075,6 +2273,11 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
         // bucket widths come from the selector
     } else if (oracle) {
         // ORACLE: no term pass, no thresholds
+    } else if (apx) {
+        // approximate criteria: their own term pass (pick_approx)
+        if (crit == 0 || (crit & ~(SSSP_DIJK | SSSP_IN_APPROX | SSSP_OUT_APPROX)))
+            return sssp_set_error(SSSP_ERR_INVALID, "criterion 0x%x: the approximate solve takes DIJK, IN_APPROX "
+                                                    "and OUT_APPROX", crit);
     } else if (!delta_mode) {
         if (crit == 0 || (crit & ~SSSP_CRIT_ALL))
             return sssp_set_error(SSSP_ERR_INVALID, "criterion 0x%x is empty or has unknown bits", crit);
@@ -2105,13 +2308,13 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
     // queue arrays: plain static criteria, or the plain static phases after a committed prefix
     // (a scan block's state window must fit in LDS: at most kQWin vertices per block)
     const bool queue_fits = g->cfg.queue && scan_span(g->n, g->cfg.scan_blocks, 16) <= kQWin;
-    const bool queue_now = queue_fits && !learn && !oracle && !delta_mode && static_modes(in, out);
+    const bool queue_now = queue_fits && !learn && !oracle && !apx && !delta_mode && static_modes(in, out);
     const bool queue_later = queue_fits && (commit != 0 || (sw && static_modes(in2, out2)));
-    if (in_all >= IN_SIMPLE_M) {
+    if (in_all >= IN_SIMPLE_M || (apx && (crit & SSSP_IN_APPROX))) {
         int rc = graph_ensure_csc(g);
         if (rc) return rc;
     }
-    int rc = solve_bufs_ensure(g, dyn, delta_mode, queue_now || queue_later);
+    int rc = solve_bufs_ensure(g, dyn, delta_mode, queue_now || queue_later, apx != nullptr);
     if (rc) return rc;
     if (learn) n_deltas = 0;
     if (delta_mode && g->delta_cap < n_deltas) {
@@ -2128,9 +2331,14 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
     a.b = g->b;
     a.b.dist = (unsigned long long *)dist_out;
     a.b.phase_of = phase_of;
+    if (apx) {  // the approximate term pass reads every vertex's settle phase
+        if (!phase_of) a.b.phase_of = a.b.apx_sp;
+        a.b.apx_sp = a.b.phase_of;
+    }
     a.b.trace = nullptr;
     a.b.trace_cap = 0;
     a.crit = crit;
+    a.approx_k = apx ? *apx : 0u;
     a.mlp_w = learn ? selector_device_weights(sel) : nullptr;
     a.wm = g->m ? (double)g->sum_w / (double)g->m : 1.0;
     a.ref = (const unsigned long long *)oracle_ref;
@@ -2147,13 +2355,21 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
         a.b.trace_cf = (uint32_t *)cf_buf.p;
     }
     const int ib = (int)(((uint64_t)g->n + 255) / 256 > 8192 ? 8192 : ((uint64_t)g->n + 255) / 256);
-    hipLaunchKernelGGL(k_init_state, dim3(ib), dim3(256), 0, s, g->n, source, a.b.dist, a.b.st, phase_of,
+    hipLaunchKernelGGL(k_init_state, dim3(ib), dim3(256), 0, s, g->n, source, a.b.dist, a.b.st, a.b.phase_of,
                        dyn ? a.b.out_cur : nullptr, g->rp, (in_all >= IN_SIMPLE_M) ? a.b.in_cur : nullptr,
                        g->ip, delta_mode ? a.b.stamp : nullptr, a.b.out_head, g->edges, a.b.in_head, g->in_edges);
-    hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(64), 0, s, a.b.ctl, g->vmin, g->rp, g->wmax, source, n_deltas);
+    // keyed queue arrays: the first split lies a sixteenth of the mean weight above T (or minD)
+    const unsigned long long qdelta0 = g->m ? (g->sum_w / g->m) / 16 + 1 : 1;
+    hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(64), 0, s, a.b.ctl, g->vmin, g->rp, g->wmax, source, n_deltas,
+                       qdelta0);
     if (learn) hipLaunchKernelGGL(k_init_choice, dim3(1), dim3(64), 0, s, a, source, (int)delta_mode);
+    if (apx) hipLaunchKernelGGL(k_fill_u32, dim3(ib), dim3(256), 0, s, g->n, a.b.apx_lin, a.b.apx_lout, 0u);
     const PhaseKernels K = oracle ? pick_oracle(g->cfg.chunk)
-                                  : pick_phase(g->cfg.chunk, in, out, delta_mode, learn, trace_mode, queue_now);
+                         : apx ? pick_approx(g->cfg.chunk, crit)
+                                  : pick_phase(g->cfg.chunk, in, out, delta_mode, learn, trace_mode, queue_now,
+                                               // keyed: launches and phases differ, so not where the host
+                                               // counts phases by launches (switched and committed solves)
+                                               queue_now && g->cfg.queue == 2 && !sw && !commit);
     // phases <= reachable vertices; Delta rounds <= 2 * n + light rounds bounded by n per bucket
     // Delta: light rounds per bucket <= window vertices + 1, one heavy round per bucket
     const uint64_t max_phases = delta_mode ? 4ull * g->n + 64 : (uint64_t)g->n + 2;
@@ -2282,6 +2498,13 @@ extern "C" int sssp_solve_oracle(sssp_graph *g, uint32_t source, const uint64_t 
                         nullptr, dist_ref);
 }
 
+extern "C" int sssp_solve_approx(sssp_graph *g, uint32_t source, uint32_t criterion, uint32_t k,
+                                 uint64_t *dist_out, sssp_stats *stats, uint32_t *phase_of, sssp_phase_rec *trace,
+                                 uint32_t trace_cap) {
+    return solve_common(g, source, false, criterion, nullptr, 0, dist_out, stats, phase_of, trace, trace_cap,
+                        nullptr, nullptr, nullptr, nullptr, 0, nullptr, &k);
+}
+
 extern "C" int sssp_profile_enable(sssp_graph *g, int enable) {
     if (!g) return sssp_set_error(SSSP_ERR_INVALID, "graph is NULL");
     g->prof = enable != 0;
@@ -2316,14 +2539,14 @@ extern "C" int sssp_get_launch(const sssp_graph *g, sssp_launch_cfg *out) {
 extern "C" int sssp_set_launch(sssp_graph *g, const sssp_launch_cfg *cfg) {
     if (!g || !cfg) return sssp_set_error(SSSP_ERR_INVALID, "NULL argument");
     if (cfg->scan_blocks == 0 || cfg->relax_blocks == 0 || cfg->scan_blocks > (1u << 20) ||
-        cfg->relax_blocks > (1u << 20) || !valid_chunk((int)cfg->chunk))
+        cfg->relax_blocks > (1u << 20) || !valid_chunk((int)cfg->chunk) || cfg->queue > 2)
         return sssp_set_error(SSSP_ERR_INVALID, "bad launch shape (%u, %u, %u)", cfg->scan_blocks,
                               cfg->relax_blocks, cfg->chunk);
     g->cfg.scan_blocks = (int)cfg->scan_blocks;
     g->cfg.relax_blocks = (int)cfg->relax_blocks;
     g->cfg.chunk = (int)cfg->chunk;
     g->cfg.use_graph = cfg->use_graph != 0;
-    g->cfg.queue = cfg->queue != 0;
+    g->cfg.queue = (int)cfg->queue;
     g->cfg.single = cfg->single != 0;
     return SSSP_OK;
 }

@@ -278,8 +278,10 @@ STATIC_CRITS = [O.STATIC_OR, O.IN_STATIC, O.OUT_STATIC, O.DIJK, O.DIJK | O.OUT_S
 @pytest.mark.parametrize("cfg", [dict(scan_blocks=1), dict(scan_blocks=2), dict(scan_blocks=5, relax_blocks=3, chunk=1024),
                                  dict(scan_blocks=64, use_graph=1), dict(scan_blocks=4096, chunk=512)])
 def test_queue_arrays_match_oracle(B, cfg):
-    """Static criteria with per-block queue arrays (on by default) and with the dense scan: every
-    observable of the oracle, on graphs whose vertex counts are not multiples of a block's span.
+    """Static criteria with keyed queue arrays, with per-block queue arrays (on by default) and with
+    the dense scan: every observable of the oracle, on graphs whose vertex counts are not multiples
+    of a block's span (keyed: rebuild launches are not phases, so the phase-indexed trace and
+    settle phases must still equal the oracle's).
     With one or two scan blocks each block owns thousands of vertices, so its slots fill with
     tombstones and are compacted over several steps, many times per solve (one block cannot hold
     the 20011-vertex graph's state window and takes the dense scan there). On the random graph
@@ -291,7 +293,7 @@ def test_queue_arrays_match_oracle(B, cfg):
     assert 8 * peak >= 3 * graphs[0].n and 5 * peak < 4 * graphs[0].n
     for g in graphs:
         refs = {c: O.phased(g, 0, c) for c in STATIC_CRITS}
-        for queue in (1, 0):
+        for queue in (2, 1, 0):
             dg = B.DeviceGraph.from_graph(g)
             dg.set_launch(queue=queue, **cfg)
             for c in STATIC_CRITS:
@@ -323,7 +325,7 @@ def test_queue_arrays_survive_solve_kind_changes(B):
         assert np.array_equal(r.dist_u64(), full.dist) and r.phases == full.phases
         r = B.delta_step_ex(dg, 0, [256])
         assert np.array_equal(r.dist_u64(), dl.dist) and r.phases == dl.rounds
-        dg.set_launch(queue=step % 2)
+        dg.set_launch(queue=(step + 2) % 3)
 
 
 def test_single_workgroup_solves_match_oracle(B):
@@ -434,7 +436,7 @@ def test_max_weight_minima_every_static_path(B):
         g = G.from_edges(ent["n"], ent["edges"])
         for name, sets in ent["phases"].items():
             c = {"IN_STATIC": O.IN_STATIC, "OUT_STATIC": O.OUT_STATIC, "STATIC_OR": O.STATIC_OR}[name]
-            for queue in (1, 0):
+            for queue in (2, 1, 0):
                 dg = B.DeviceGraph.from_graph(g)
                 dg.set_launch(queue=queue)
                 r = B.solve_ex(dg, 0, c, phase_of=True)
@@ -468,3 +470,53 @@ def test_delta_stepping_hand_traces(B):
         got = [int(s) for s, k in zip(r.trace["settled"], r.trace["criterion"]) if int(k) != 2]
         assert got == light, (key, got, light)
         dg.close()
+
+
+APPROX = [("DIJK|IN_APPROX", O.DIJK | O.IN_APPROX), ("DIJK|OUT_APPROX", O.DIJK | O.OUT_APPROX),
+          ("DIJK|IN_APPROX|OUT_APPROX", O.DIJK | O.IN_APPROX | O.OUT_APPROX), ("OUT_APPROX", O.OUT_APPROX)]
+
+
+def check_approx(B, g, src, crit, k, label):
+    dg = B.DeviceGraph.from_graph(g)
+    ref = O.phased(g, src, crit, approx_k=k)
+    r = B.solve_approx(dg, src, crit, k, phase_of=True, trace_cap=ref.phases + 4)
+    assert np.array_equal(r.dist_u64(), ref.dist), label
+    assert r.phases == ref.phases, (label, r.phases, ref.phases)
+    assert np.array_equal(r.phase_of.cpu().numpy().view(np.uint32), ref.phase_of), label
+    assert r.stats["sum_f"] == ref.sum_f and r.stats["relax_edges"] == ref.relax_edges, label
+    assert np.array_equal(r.trace["settled"], ref.trace_s), label
+    dg.close()
+
+
+def test_approximate_criteria_match_oracle(B):
+    """sssp_solve_approx (the GPU evaluates the kept minima in closed form from each neighbour's settle
+    phase) against the oracle (which maintains them as the paper describes: lowered on U -> F, changes
+    counted on F -> S, recomputed every k-th change): hand traces, random multigraphs, medium graphs,
+    k in {0, 1, 2, 5}."""
+    import json, os
+    fix = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "approx_hand_traces.json")))
+    for key, ent in fix["graphs"].items():
+        g = G.from_edges(ent["n"], ent["edges"])
+        c = {"DIJK|IN_APPROX": O.DIJK | O.IN_APPROX, "DIJK|OUT_APPROX": O.DIJK | O.OUT_APPROX}[ent["criterion"]]
+        for k, sets in ent["phases"].items():
+            dg = B.DeviceGraph.from_graph(g)
+            r = B.solve_approx(dg, 0, c, int(k), phase_of=True)
+            po = r.phase_of.cpu().numpy().view(np.uint32)
+            assert [[v for v in range(g.n) if po[v] == p] for p in range(1, r.phases + 1)] == sets, (key, k)
+            dg.close()
+    for g in small_cases()[:30]:
+        for name, c in APPROX:
+            for k in (0, 1, 3):
+                check_approx(B, g, 0, c, k, "%s/%s/k%d" % (g.name, name, k))
+    for g in [G.er(1 << 14, 8, 1, 1000, 61), G.rmat(13, 16, 1, 1 << 16, 62), G.grid(61, 47, 1, 1 << 16, 63)]:
+        src = int(G.sources(g, 1, 64)[0])
+        for name, c in APPROX[:3]:
+            for k in (0, 1, 2, 5):
+                check_approx(B, g, src, c, k, "%s/%s/k%d" % (g.name, name, k))
+
+
+def test_approximate_rejects_other_bits(B):
+    dg = B.DeviceGraph.from_graph(G.er(100, 3, 1, 10, 65))
+    for c in (0, O.STATIC_OR, O.IN_APPROX | O.IN_FULL):
+        with pytest.raises(B.SsspError):
+            B.solve_approx(dg, 0, c, 2)
