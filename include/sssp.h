@@ -445,6 +445,31 @@ int sssp_trace_learned(sssp_graph *g, uint32_t source, const sssp_selector *sel,
 int sssp_measure_atomic_min(uint64_t *buf, uint64_t slots, uint32_t blocks, uint32_t iters, void *hip_stream,
                             float *ms_out);
 
+/*
+ * sssp_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same phased solve with a static criterion (a disjunction of SSSP_DIJK,
+ * SSSP_IN_STATIC and SSSP_OUT_STATIC), the same kernels (dense-scan identify
+ * and relax) and the same distances and phase count, with every per-solve
+ * scratch buffer (control block, state bytes, settled-vertex lists) carved
+ * from one device array of 64 MiB that the library holds on each device it
+ * runs on until the process ends. The call makes no device or pinned host
+ * allocation; the graph handle must already exist (sssp_graph_create
+ * allocates) and the caller owns dist_out.
+ *   dist_out   DEVICE, n uint64: dist(s, v), UINT64_MAX if unreachable.
+ *   phases_out HOST, may be NULL: number of phases.
+ * Scratch needed: about 17 bytes per vertex plus 2 bytes per edge (the exact
+ * figure depends on the graph's scan grid); a graph needing more than the
+ * array holds is rejected with SSSP_ERR_UNSUPPORTED before any device work.
+ * All calls on one device share its array and each call overwrites it, so
+ * calls on one device are serialised by a per-device lock inside the library;
+ * without it, overlapping calls would race. Errors: SSSP_ERR_INVALID for a
+ * NULL graph or dist_out, source >= n, an empty or unknown criterion;
+ * SSSP_ERR_UNSUPPORTED for a dynamic criterion or an oversized graph.
+ */
+int sssp_solve_noalloc(sssp_graph *g, uint32_t source, uint32_t criterion, uint64_t *dist_out,
+                       uint32_t *phases_out);
+
 /* Human-readable description of the last error on the calling thread. */
 const char *sssp_last_error(void);
 

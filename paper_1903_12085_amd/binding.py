@@ -33,7 +33,7 @@ SYMBOLS = ["sssp_graph_create", "sssp_graph_destroy", "sssp_set_stream", "sssp_g
            "sssp_selector_set_weights", "sssp_selector_forward", "sssp_selector_grad", "sssp_selector_train",
            "sssp_solve_learned", "sssp_delta_step_learned", "sssp_trace_learned",
            "sssp_solve_learned_commit", "sssp_measure_atomic_min", "sssp_solve_switch",
-           "sssp_solve_learned_switch", "sssp_solve_approx"]
+           "sssp_solve_learned_switch", "sssp_solve_approx", "sssp_solve_noalloc"]
 
 ERRORS = {-1: "SSSP_ERR_INVALID", -2: "SSSP_ERR_OOM", -3: "SSSP_ERR_DEVICE", -4: "SSSP_ERR_UNSUPPORTED",
           -5: "SSSP_ERR_INTERNAL"}
@@ -100,6 +100,7 @@ def load(path: str = LIB_PATH):
     lib.sssp_set_stream.argtypes = [P, P]
     lib.sssp_graph_minima.argtypes = [P, P, P]
     lib.sssp_solve.argtypes = [P, u32, u32, P, P]
+    lib.sssp_solve_noalloc.argtypes = [P, u32, u32, P, P]
     lib.sssp_solve_approx.argtypes = [P, u32, u32, u32, P, ctypes.POINTER(Stats), P, P, u32]
     lib.sssp_solve_ex.argtypes = [P, u32, u32, P, ctypes.POINTER(Stats), P, P, u32]
     lib.sssp_delta_step.argtypes = [P, u32, u64, P, P]
@@ -262,6 +263,17 @@ def solve(g: DeviceGraph, source: int, criterion: int, dist=None) -> SolveResult
     ph = ctypes.c_uint32(0)
     g._bind_stream()
     _check(load().sssp_solve(g.handle, source, criterion, ctypes.c_void_p(dist.data_ptr()), ctypes.byref(ph)))
+    return SolveResult(dist, int(ph.value))
+
+
+def solve_noalloc(g: DeviceGraph, source: int, criterion: int, dist=None) -> SolveResult:
+    """sssp_solve_noalloc: the static-criterion solve with the library's fixed scratch array
+    (dist, if given, is the caller's device output; otherwise one is made here)."""
+    dist = new_dist(g.n) if dist is None else dist
+    ph = ctypes.c_uint32(0)
+    g._bind_stream()
+    _check(load().sssp_solve_noalloc(g.handle, source, criterion, ctypes.c_void_p(dist.data_ptr()),
+                                     ctypes.byref(ph)))
     return SolveResult(dist, int(ph.value))
 
 

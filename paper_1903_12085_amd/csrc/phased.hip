@@ -29,6 +29,8 @@
 // combined by many blocks are sharded (see Sharded in common.h).
 #include <string.h>
 
+#include <mutex>
+
 #include "common.h"
 #include "graph.h"
 #include "selector.h"
@@ -2602,4 +2604,132 @@ extern "C" int sssp_trace_learned(sssp_graph *g, uint32_t source, const sssp_sel
                           features_out, delta_mode ? nullptr : counts_out);
     if (stats) *stats = st;
     return rc;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free solve (sssp_solve_noalloc): the plain static-criterion phase
+// loop (dense scan identify + relax, the kernels of sssp_solve) with its
+// per-solve scratch -- control block, state bytes, S' shards, chunk starts --
+// carved from one file-scope device array instead of graph-owned buffers.
+
+constexpr uint64_t kNoAllocBytes = 64ull << 20;  // per device, held until the process ends
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kNoAllocMaxDev = 64;
+static void *g_noalloc_ptr[kNoAllocMaxDev];     // device address of `scratch`, per device
+static std::mutex g_noalloc_mu[kNoAllocMaxDev]; // calls on one device share its array
+
+struct NoAllocLayout {
+    uint64_t ctl, st, srow, soff, sdu, chunk, total;
+    uint32_t shard_cap, chunk_cap;
+};
+
+static uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+static NoAllocLayout noalloc_layout(uint32_t n, uint64_t m, int scan_blocks) {
+    NoAllocLayout L;
+    // dense scan only: a shard holds the S' entries of ceil(G / kShards) blocks of at most
+    // scan_span(n, G, 4) vertices each
+    L.shard_cap = (uint32_t)(((uint64_t)scan_blocks + kShards - 1) / kShards * scan_span(n, scan_blocks, 4));
+    L.chunk_cap = (uint32_t)(m / 256 + 2);
+    const uint64_t sent = (uint64_t)kShards * L.shard_cap;
+    uint64_t o = 0;
+    L.ctl = o;   o = align256(o + sizeof(Ctl));
+    L.st = o;    o = align256(o + (((uint64_t)n + 15) & ~15ull));
+    L.srow = o;  o = align256(o + sent * 4);
+    L.soff = o;  o = align256(o + sent * 4);
+    L.sdu = o;   o = align256(o + sent * 8);
+    L.chunk = o; o = align256(o + (uint64_t)kShards * L.chunk_cap * 4);
+    L.total = o;
+    return L;
+}
+
+// Device address of `scratch` on device dev, looked up once per device with
+// that device current (each device holds its own copy at its own address).
+static int noalloc_scratch(int dev, unsigned char **out) {
+    if (dev < 0 || dev >= kNoAllocMaxDev) return sssp_set_error(SSSP_ERR_UNSUPPORTED, "device %d out of range", dev);
+    if (!g_noalloc_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return sssp_set_error(SSSP_ERR_DEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_noalloc_ptr[dev] = p;
+    }
+    *out = (unsigned char *)g_noalloc_ptr[dev];
+    return SSSP_OK;
+}
+
+extern "C" int sssp_solve_noalloc(sssp_graph *g, uint32_t source, uint32_t criterion, uint64_t *dist_out,
+                                  uint32_t *phases_out) {
+    if (!g) return sssp_set_error(SSSP_ERR_INVALID, "graph is NULL");
+    if (!dist_out) return sssp_set_error(SSSP_ERR_INVALID, "dist_out is NULL");
+    if (source >= g->n) return sssp_set_error(SSSP_ERR_INVALID, "source %u >= n = %u", source, g->n);
+    if (criterion == 0 || (criterion & ~SSSP_CRIT_ALL))
+        return sssp_set_error(SSSP_ERR_INVALID, "criterion 0x%x is empty or has unknown bits", criterion);
+    int in = IN_NONE, out = OUT_NONE;
+    crit_modes(criterion, &in, &out);
+    if (!static_modes(in, out))
+        return sssp_set_error(SSSP_ERR_UNSUPPORTED, "sssp_solve_noalloc evaluates DIJK, IN_STATIC and OUT_STATIC");
+    if (!valid_chunk(g->cfg.chunk)) return sssp_set_error(SSSP_ERR_INTERNAL, "bad chunk size");
+    const NoAllocLayout L = noalloc_layout(g->n, g->m, g->cfg.scan_blocks);
+    if (L.total > kNoAllocBytes)
+        return sssp_set_error(SSSP_ERR_UNSUPPORTED,
+                              "sssp_solve_noalloc: the graph needs %llu bytes of scratch, more than its %llu "
+                              "(n = %u, m = %llu, %d scan blocks)", (unsigned long long)L.total,
+                              (unsigned long long)kNoAllocBytes, g->n, (unsigned long long)g->m, g->cfg.scan_blocks);
+    HIP_OK(hipSetDevice(g->device));
+    if (g->device < 0 || g->device >= kNoAllocMaxDev)
+        return sssp_set_error(SSSP_ERR_UNSUPPORTED, "device %d out of range", g->device);
+    std::lock_guard<std::mutex> lock(g_noalloc_mu[g->device]);
+    unsigned char *base = nullptr;
+    int rc = noalloc_scratch(g->device, &base);
+    if (rc) return rc;
+    KArgs a;
+    memset(&a, 0, sizeof a);
+    a.g = dev_view(g);
+    a.b.ctl = (Ctl *)(base + L.ctl);
+    a.b.st = base + L.st;
+    a.b.srow = (uint32_t *)(base + L.srow);
+    a.b.soff = (uint32_t *)(base + L.soff);
+    a.b.sdu = (unsigned long long *)(base + L.sdu);
+    a.b.chunk_start = (uint32_t *)(base + L.chunk);
+    a.b.shard_cap = L.shard_cap;
+    a.b.chunk_cap = L.chunk_cap;
+    a.b.dist = (unsigned long long *)dist_out;
+    a.crit = criterion;
+    hipStream_t s = g->stream;
+    const int ib = (int)(((uint64_t)g->n + 255) / 256 > 8192 ? 8192 : ((uint64_t)g->n + 255) / 256);
+    // every byte a solve reads before writing it is set here: state bytes, distances, control block
+    hipLaunchKernelGGL(k_init_state, dim3(ib), dim3(256), 0, s, g->n, source, a.b.dist, a.b.st, nullptr, nullptr,
+                       g->rp, nullptr, g->ip, nullptr, nullptr, g->edges, nullptr, g->in_edges);
+    hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(64), 0, s, a.b.ctl, g->vmin, g->rp, g->wmax, source, 0u, 1ull);
+    const PhaseKernels K = pick_phase(g->cfg.chunk, in, out, false, false, false, false);
+    const dim3 blk(kBlock), gs(g->cfg.scan_blocks), gr(g->cfg.relax_blocks);
+    const uint64_t max_phases = (uint64_t)g->n + 2;
+    CtlHead h;
+    uint64_t k = 0;
+    for (;;) {  // batches of 16 phases; the header is read into host stack memory after each
+        for (uint32_t i = 0; i < 16; ++i, ++k) {
+            const int par = (int)(k % 6);
+            hipLaunchKernelGGL(K.identify, gs, blk, 0, s, a, par);
+            hipLaunchKernelGGL(K.relax, gr, blk, 0, s, a, par);
+        }
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipMemcpyAsync(&h, a.b.ctl, sizeof h, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        if (h.done) break;
+        if (k > max_phases + 32)
+            return sssp_set_error(SSSP_ERR_INTERNAL, "phase loop did not terminate after %llu phases",
+                                  (unsigned long long)k);
+    }
+    hipLaunchKernelGGL(k_clear_settled, dim3(ib), dim3(256), 0, s, g->n, a.b.dist);
+    Sharded reached;
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(&reached, &a.b.ctl->reached, sizeof reached, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (shard_sum(reached) != h.settled)
+        return sssp_set_error(SSSP_ERR_INTERNAL, "solve ended in an inconsistent state (reached=%llu settled=%llu)",
+                              shard_sum(reached), h.settled);
+    if (phases_out) *phases_out = h.phases;
+    return SSSP_OK;
 }
