@@ -85,7 +85,7 @@ def _L():
             lib.orc_bellman_ford.argtypes = [u32, P, P, P, u32, P]
             lib.orc_static_minima.argtypes = [u32, P, P, P, P, P]
             lib.orc_phased.argtypes = [u32, P, P, P, u32, u32, P, u32, i, P, P,
-                                       ctypes.POINTER(_Stats), u32, P, P, P, P, P, P, P, P, P, u32, u32]
+                                       ctypes.POINTER(_Stats), u32, P, P, P, P, P, P, P, P, P, u32, u32, u32]
             lib.orc_delta_step.argtypes = [u32, P, P, P, u32, P, u32, P, ctypes.POINTER(_DStats), u32, P, P]
             lib.orc_features.argtypes = [P, ctypes.c_double, i, P]
             lib.orc_features.restype = None
@@ -167,13 +167,17 @@ _ERRS = {-1: "invalid argument", -2: "out of memory", -10: "unsound: certified v
 
 
 def phased(g, src: int, crit: int, crit_seq=None, check: bool = False, dist_ref=None,
-           trace_cap: int | None = None, mlp_w=None, commit: int = 0, approx_k: int = 0) -> PhasedResult:
+           trace_cap: int | None = None, mlp_w=None, commit: int = 0, approx_k: int = 0,
+           checkpoint: bool = False) -> PhasedResult:
     """Generic phased algorithm of Section 3 with the given criterion bits.
 
     mlp_w: float32[5382] selector weights; the criterion of each phase is then the selector's
     choice (crit is ignored). commit = K > 0: the choice made for phase K is kept from then on.
     IN_APPROX / OUT_APPROX: the approximate criteria, minima recomputed at the evaluation of a vertex
-    with at least approx_k counted changes (0: never)."""
+    with at least approx_k counted changes (0: never).
+    checkpoint=True (with mlp_w, crit = STATIC_OR): the learned checkpoint mode -- static phases, the
+    selector evaluated after every 16th phase k on checkpoint features (trace_feat row k // 16), and
+    the first choice c != 0 at phase k switches every phase from k + 17 on to CHOICE_CRIT[c]."""
     n, rp, col, w = _csr(g)
     mw = None if mlp_w is None else np.ascontiguousarray(mlp_w, np.float32)
     cap = n if trace_cap is None else trace_cap
@@ -191,7 +195,7 @@ def phased(g, src: int, crit: int, crit_seq=None, check: bool = False, dist_ref=
     rc = _L().orc_phased(n, _p(rp), _p(col), _p(w), src, crit, _p(seq), 0 if seq is None else len(seq),
                          int(check), _p(None if dist_ref is None else np.ascontiguousarray(dist_ref, np.uint64)),
                          _p(dist), ctypes.byref(st), cap, _p(tf), _p(ts), _p(tm), _p(tc), _p(po), _p(mw), _p(tcr),
-                         _p(tun), _p(tft), int(commit), int(approx_k))
+                         _p(tun), _p(tft), int(commit), int(approx_k), int(checkpoint))
     if rc != 0:
         raise OracleError("orc_phased: %s (%d)" % (_ERRS.get(rc, "?"), rc))
     k = min(st.phases, cap)
@@ -236,11 +240,13 @@ def reach_stats(g, dist):
 
 
 MLP_NPARAM = 64 * 12 + 64 + 64 * 64 + 64 + 6 * 64 + 6
-CHOICE_CRIT = [STATIC_OR, SIMPLE_OR, FULL_OR]
+CHOICE_CRIT = [STATIC_OR, SIMPLE_OR, IN_SIMPLE | OUT_STATIC]
 
 
-def features(ints, Wm: float, delta_mode: bool = False) -> np.ndarray:
-    """The 12 selector features of one state; ints = (n m F S R a t SD DG Fp D Sp Ip Op k)."""
+def features(ints, Wm: float, delta_mode: int = 0) -> np.ndarray:
+    """The 12 selector features of one state; ints = (n m F S R a t SD DG Fp D Sp Ip Op k);
+    delta_mode 0: phased solver, 1: Delta-stepping bucket start, 2: checkpoint (x5 = floor(log2 n)/32,
+    x6 = min(m/n, 64)/64, x7 = x8 = 0)."""
     a = np.ascontiguousarray(ints, np.uint64)
     x = np.zeros(12, np.float32)
     _L().orc_features(_p(a), float(Wm), int(delta_mode), _p(x))

@@ -411,15 +411,18 @@ static void out_thresholds(uint32_t want, const uint32_t *Flist, uint64_t nF, co
  * from phase k's snapshot together with phase k's own outcome (D = |F_k|,
  * Sp = |S'_k|, Fp = |F_{k-1}|), so it is known as soon as phase k has
  * identified S'_k and can be evaluated while S'_k relaxes.
- * Delta-stepping: the state is taken at a bucket start (a = minD, D = |F| at
- * the previous bucket start, Sp = the vertices that bucket settled, Ip = Op =
- * 0); x4..x9 are 0.
+ * Delta-stepping (delta_mode 1): the state is taken at a bucket start (a =
+ * minD, D = |F| at the previous bucket start, Sp = the vertices that bucket
+ * settled, Ip = Op = 0); x4..x9 are 0. Checkpoint mode (delta_mode 2): after
+ * every 16th phase k of a static solve, phase k's snapshot and outcome as for
+ * the phased solver, Fp = |F| at the previous checkpoint; x5 = floor(log2 n)/32,
+ * x6 = min(m/n, 64)/64, x7 = x8 = 0.
  * MLP: 12 -> 64 (ReLU) -> 64 (ReLU) -> 6, FP32; each neuron is its bias
  * followed by fmaf over its inputs in index order. Weights, flat: W1[64][12],
  * b1[64], W2[64][64], b2[64], W3[6][64], b3[6] (5382 floats). The phased
  * solver takes the argmax of outputs 0..2 (ties: lowest index) as the phase's
  * criterion: 0 = IN-STATIC|OUT-STATIC, 1 = IN-SIMPLE|OUT-SIMPLE, 2 =
- * IN|OUT; Delta-stepping takes the argmax of outputs 3..5 as the bucket width
+ * IN-SIMPLE|OUT-STATIC; Delta-stepping takes the argmax of outputs 3..5 as the bucket width
  * 2^12, 2^14, 2^16.
  */
 #define MLP_IN 12
@@ -444,7 +447,7 @@ static void features(const feat_in *q, float *x) {
     x[3] = (float)(dmin(F / 4194304.0, 4.0) / 4.0);
     x[10] = (float)((n - (double)q->R) / n);
     x[11] = (float)(dmin((double)q->a / q->Wm, 4096.0) / 4096.0);
-    if (q->delta_mode) {
+    if (q->delta_mode == 1) {
         for (int i = 4; i < 10; ++i) x[i] = 0.0f;
         return;
     }
@@ -454,6 +457,11 @@ static void features(const feat_in *q, float *x) {
     x[7] = (float)(q->D ? (double)q->Ip / D : 0.0);
     x[8] = (float)(q->D ? (double)q->Op / D : 0.0);
     x[9] = (float)(q->Fp ? dmin(F / Fp, 4.0) / 4.0 : 0.0);
+    if (q->delta_mode == 2) {  /* checkpoint mode: the graph's size and mean degree */
+        x[5] = (float)((double)(63 - __builtin_clzll(q->n)) / 32.0);
+        x[6] = (float)(dmin(m / n, 64.0) / 64.0);
+        x[7] = x[8] = 0.0f;
+    }
 }
 
 /* FP32 forward pass; returns the argmax of outputs [lo, lo+3). */
@@ -493,7 +501,7 @@ void orc_features(const uint64_t *ints /* n m F S R a t SD DG Fp D Sp Ip Op k */
 
 int orc_mlp_choice(const float *w, const float *x, int lo, float *logits) { return mlp_choice(w, x, lo, logits); }
 
-static const uint32_t CHOICE_CRIT[3] = {C_IN_STATIC | C_OUT_STATIC, C_IN_SIMPLE | C_OUT_SIMPLE, C_IN_FULL | C_OUT_FULL};
+static const uint32_t CHOICE_CRIT[3] = {C_IN_STATIC | C_OUT_STATIC, C_IN_SIMPLE | C_OUT_SIMPLE, C_IN_SIMPLE | C_OUT_STATIC};
 
 static const uint32_t ALL_BITS[8] = {C_DIJK, C_IN_STATIC, C_OUT_STATIC, C_IN_SIMPLE,
                                      C_OUT_SIMPLE, C_IN_FULL, C_OUT_WEAK, C_OUT_FULL};
@@ -585,9 +593,10 @@ int orc_phased(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32
                const uint64_t *dist_ref, uint64_t *dist_out, orc_stats *stats, uint32_t trace_cap,
                uint32_t *trace_f, uint32_t *trace_s, uint64_t *trace_mind, uint32_t *trace_counts,
                uint32_t *phase_of, const float *mlp_w, uint32_t *trace_crit, uint32_t *trace_union,
-               float *trace_feat, uint32_t commit, uint32_t approx_k) {
+               float *trace_feat, uint32_t commit, uint32_t approx_k, uint32_t ckpt) {
     if (src >= n || (crit == 0 && !crit_seq && !mlp_w) || (crit & ~(C_ALL | C_APPROX))) return ORC_EINVAL;
     if ((crit & C_APPROX) && (crit_seq || mlp_w)) return ORC_EINVAL;
+    if (ckpt && (!mlp_w || crit != (C_IN_STATIC | C_OUT_STATIC) || crit_seq || commit)) return ORC_EINVAL;
     int rc = ORC_OK;
     csc_t c = {0, 0, 0};
     uint64_t *min_in = (uint64_t *)malloc((uint64_t)n * 8), *min_out = (uint64_t *)malloc((uint64_t)n * 8);
@@ -626,13 +635,17 @@ int orc_phased(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32
     /* learned mode: |F| of the previous phase and the choice for the next phase */
     uint64_t prevF = 0, settled = 0;
     int choice = 0;
+    /* checkpoint mode: the first checkpoint choosing c != 0 switches from phase cp_at on */
+    int cp_decided = 0;
+    uint32_t cp_at = 0, cp_crit = 0;
+    uint64_t cp_fprev = 0;
     double Wm = 1.0;
     if (mlp_w && rp[n] > 0) {  /* exact integer weight sum, then one division */
         uint64_t sw = 0;
         for (uint64_t e = 0; e < rp[n]; ++e) sw += w[e];
         Wm = (double)sw / (double)rp[n];
     }
-    if (mlp_w) {  /* phase 0: the state {s}, nothing evaluated yet */
+    if (mlp_w && !ckpt) {  /* phase 0: the state {s}, nothing evaluated yet */
         feat_in q = {n, rp[n], 1, 0, 1, 0, min_out[src], 0, rp[src + 1] - rp[src],
                      0, 0, 0, 0, 0, 0, Wm, 0};
         float x[MLP_IN];
@@ -646,9 +659,13 @@ int orc_phased(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32
         thresholds_t T;
         T.minD = INF;
         for (uint64_t i = 0; i < nF; ++i) T.minD = min64(T.minD, d[Fl[i]]);
-        if (mlp_w) {
+        if (mlp_w && !ckpt) {
             ck = CHOICE_CRIT[choice];
             want = (check ? C_ALL : ck) | C_IN_STATIC | C_OUT_STATIC;
+        }
+        if (ckpt && cp_decided && k >= cp_at) {
+            ck = cp_crit;
+            want = check ? C_ALL : ck;
         }
         if (ck == 0 || (ck & ~(C_ALL | C_APPROX))) { rc = ORC_EINVAL; goto out; }
         if (k < trace_cap && trace_crit) trace_crit[k] = ck;
@@ -694,7 +711,20 @@ int orc_phased(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32
             if (trace_counts) memcpy(trace_counts + 8ull * k, cnt, sizeof cnt);
             if (trace_union) memcpy(trace_union + 3ull * k, uni, sizeof uni);
         }
-        if (mlp_w && (!commit || k + 1 <= commit)) {
+        if (ckpt && !cp_decided && (k + 1) % 16 == 0) {
+            /* checkpoint after the last phase of a batch of 16: phase k's snapshot and outcome,
+             * |F| at the previous checkpoint; no SD, DG, Ip, Op (delta_mode 2) */
+            feat_in q = {n, rp[n], nF, settled, nF + settled, T.minD, T.t_out_static, 0, 0, cp_fprev, nF, nS, 0, 0,
+                         k + 1, Wm, 2};
+            float x[MLP_IN];
+            features(&q, x);
+            uint32_t j = k / 16;
+            if (j < trace_cap && trace_feat) memcpy(trace_feat + (uint64_t)MLP_IN * j, x, sizeof x);
+            int c = mlp_choice(mlp_w, x, 0, NULL);
+            cp_fprev = nF;
+            if (c != 0) { cp_decided = 1; cp_at = k + 17; cp_crit = CHOICE_CRIT[c]; }
+        }
+        if (mlp_w && !ckpt && (!commit || k + 1 <= commit)) {
             /* the selector for phase k+1, on phase k's snapshot and outcome (with a commit phase
              * K > 0, phase K's choice is kept for every later phase) */
             uint64_t SD = 0, DG = 0;

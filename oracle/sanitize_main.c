@@ -43,7 +43,7 @@ int orc_phased(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32
                const uint32_t *crit_seq, uint32_t seq_len, int check, const uint64_t *dist_ref, uint64_t *dist_out,
                orc_stats *stats, uint32_t trace_cap, uint32_t *trace_f, uint32_t *trace_s, uint64_t *trace_mind,
                uint32_t *trace_counts, uint32_t *phase_of, const float *mlp_w, uint32_t *trace_crit,
-               uint32_t *trace_union, float *trace_feat, uint32_t commit, uint32_t approx_k);
+               uint32_t *trace_union, float *trace_feat, uint32_t commit, uint32_t approx_k, uint32_t ckpt);
 int orc_delta_step(uint32_t n, const uint64_t *rp, const uint32_t *col, const uint32_t *w, uint32_t src,
                    const uint64_t *deltas, uint32_t n_deltas, uint64_t *dist_out, orc_dstats *stats,
                    uint32_t trace_cap, uint64_t *trace_delta, const float *mlp_w);
@@ -83,7 +83,7 @@ static int solve_all(uint32_t n, const uint64_t *rp, const uint32_t *col, const 
     for (size_t c = 0; c < NCRIT; ++c) {
         orc_stats st;
         int r = orc_phased(n, rp, col, w, src, CRITS[c], NULL, 0, 1, d, x, &st, 0, NULL, NULL, NULL, NULL, NULL,
-                           NULL, NULL, NULL, NULL, 0, 2);
+                           NULL, NULL, NULL, NULL, 0, 2, 0);
         if (r != 0 || memcmp(x, d, (size_t)n * 8)) { rc = 4; goto out; }
         printf(" %u %llu", st.phases, (unsigned long long)st.sum_f);
     }

@@ -182,3 +182,90 @@ def test_commit_keeps_the_choice_of_phase_k(commit):
         seq = O.phased(g, 0, 0, crit_seq=com.trace_crit)
         assert seq.phases == com.phases and np.array_equal(seq.dist, com.dist)
         assert np.array_equal(seq.phase_of, com.phase_of)
+
+
+def python_checkpoint_features(g, src):
+    """Checkpoint features (delta_mode 2) from an independent re-simulation of IN-STATIC|OUT-STATIC:
+    after every 16th phase k (k + 1 divisible by 16), phase k's F, S, minD, OUT-STATIC threshold and
+    |S'|, and |F| at the previous checkpoint; x5 = floor(log2 n)/32 and x6 = min(m/n, 64)/64 (size and
+    mean degree), x7 = x8 = 0."""
+    n, m = g.n, g.m
+    rp, col, w = [int(x) for x in g.row_ptr], [int(x) for x in g.col], [int(x) for x in g.w]
+    INF = O.INF_INT
+    min_in, min_out = [INF] * n, [INF] * n
+    for u in range(n):
+        for e in range(rp[u], rp[u + 1]):
+            min_out[u] = min(min_out[u], w[e])
+            min_in[col[e]] = min(min_in[col[e]], w[e])
+    Wm = (float(sum(w)) / float(m)) if m else 1.0
+    d, st = [INF] * n, [0] * n
+    d[src], st[src] = 0, 1
+    settled, fprev, k, rows = 0, 0, 0, []
+    while True:
+        Fs = [v for v in range(n) if st[v] == 1]
+        if not Fs:
+            break
+        F = len(Fs)
+        a = min(d[v] for v in Fs)
+        t = min((d[v] + min_out[v]) if min_out[v] != INF else INF for v in Fs)
+        S = [v for v in Fs if min_in[v] == INF or d[v] <= a + min_in[v] or d[v] <= t]
+        if (k + 1) % 16 == 0:
+            x = [0.0] * 12
+            x[0] = F / n
+            x[1] = settled / n
+            x[2] = len(S) / F
+            x[3] = min(F / 4194304.0, 4.0) / 4.0
+            x[4] = 1.0 if t == INF else min((t - a) / Wm, 64.0) / 64.0
+            x[5] = (n.bit_length() - 1) / 32.0
+            x[6] = min(m / n, 64.0) / 64.0
+            x[9] = min(F / fprev, 4.0) / 4.0 if fprev else 0.0
+            x[10] = (n - (F + settled)) / n
+            x[11] = min(a / Wm, 4096.0) / 4096.0
+            rows.append(np.array(x, np.float64).astype(np.float32))
+            fprev = F
+        for v in S:
+            st[v] = 2
+        for u in S:
+            for e in range(rp[u], rp[u + 1]):
+                x_ = col[e]
+                if st[x_] != 2 and d[u] + w[e] < d[x_]:
+                    d[x_] = d[u] + w[e]
+                    st[x_] = 1
+        settled += len(S)
+        k += 1
+    return np.array(rows)
+
+
+CKPT_GRAPHS = (G.grid(20, 15, 1, 40, 31), G.grid(33, 9, 1, 1000, 32), G.er(4000, 2, 1, 1000, 33))
+
+
+def test_checkpoint_features_match_independent_simulation():
+    for g in CKPT_GRAPHS:
+        ref = python_checkpoint_features(g, 0)
+        assert len(ref) >= 2, g.name
+        lr = O.phased(g, 0, O.STATIC_OR, mlp_w=constant_net(0), checkpoint=True, trace_cap=g.n)
+        assert np.array_equal(lr.trace_feat[:len(ref)], ref), g.name
+
+
+@pytest.mark.parametrize("choice", [0, 1, 2])
+def test_checkpoint_constant_choice_switches_at_phase_32(choice):
+    """A network that always chooses c: c = 0 keeps the static criterion throughout; otherwise the
+    first checkpoint (after phase 15) switches every phase from 32 on (two batch boundaries later)."""
+    for g in CKPT_GRAPHS:
+        r = O.phased(g, 0, O.STATIC_OR, mlp_w=constant_net(choice), checkpoint=True, trace_cap=g.n, check=True)
+        seq = [O.STATIC_OR] * 32 + [O.CHOICE_CRIT[choice]] * g.n
+        ref = O.phased(g, 0, 0, crit_seq=seq, trace_cap=g.n)
+        assert r.phases == ref.phases and np.array_equal(r.phase_of, ref.phase_of), (g.name, choice)
+        assert list(r.trace_crit) == list(ref.trace_crit), (g.name, choice)
+
+
+def test_checkpoint_mixed_network_replays_as_its_schedule():
+    for seed, g in enumerate(CKPT_GRAPHS):
+        w = mixed_net(seed + 11)
+        r = O.phased(g, 0, O.STATIC_OR, mlp_w=w, checkpoint=True, trace_cap=g.n)
+        crit = [int(c) for c in r.trace_crit]
+        # static up to a multiple of 16 (>= 32), one criterion after it
+        sw = next((i for i, c in enumerate(crit) if c != O.STATIC_OR), len(crit))
+        assert sw == len(crit) or (sw >= 32 and sw % 16 == 0 and len(set(crit[sw:])) == 1)
+        seq = O.phased(g, 0, 0, crit_seq=r.trace_crit, trace_cap=g.n)
+        assert seq.phases == r.phases and np.array_equal(seq.dist, r.dist) and np.array_equal(seq.phase_of, r.phase_of)
