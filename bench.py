@@ -381,69 +381,42 @@ def bench_c3(B, torch, G, tuned):
 
 
 def bench_learned(B, torch, G, dg, src, m_reach, plain_ms):
-    """The learned per-phase selector (weights trained on training seeds by the package's training
-    script) on the headline graph and on held-out R-MAT and grid graphs, against every fixed
-    criterion and bucket width; distances are checked against the plain solver's."""
+    """The learned selector (weights trained on training seeds by the package's training script) on
+    the headline graph and on the held-out evaluation graphs (random 2^23, R-MAT 23, grid 4096^2):
+    the network-only checkpoint solve against the plain static solve, the hand-set switch and the
+    stronger criteria from the start; the per-phase learned solve; learned Delta-stepping against
+    every fixed width. Distances of every learned form are checked against the plain solver's."""
     from paper_1903_12085_amd import selector as S
     sel = S.load_trained()
-
-    def timed(fn, reps=3):
-        fn()
-        torch.cuda.synchronize()
-        ts, r = [], None
-        for _ in range(reps):
-            tt = time.perf_counter()
-            r = fn()
-            torch.cuda.synchronize()
-            ts.append(time.perf_counter() - tt)
-        return sorted(ts)[len(ts) // 2], r
-
-    dist = B.new_dist(dg.n)
-    ref = B.to_u64(B.solve(dg, src, B.STATIC_OR, B.new_dist(dg.n)).dist)
-    tl, r = timed(lambda: B.solve_learned(dg, src, sel, dist))
-    exact = bool(np.array_equal(B.to_u64(r.dist), ref))
-    tc, rc = timed(lambda: B.solve_learned(dg, src, sel, dist, commit=S.COMMIT_PHASES))
-    exact = exact and bool(np.array_equal(B.to_u64(rc.dist), ref))
-    tw, rw = timed(lambda: B.solve_learned(dg, src, sel, dist, commit=S.COMMIT_PHASES, switch=S.SWITCH))
-    exact = exact and bool(np.array_equal(B.to_u64(rw.dist), ref))
-    lst = B.solve_learned(dg, src, sel, dist).stats
-    cst = B.solve_learned(dg, src, sel, dist, commit=S.COMMIT_PHASES).stats
-    td, rd = timed(lambda: B.delta_step_learned(dg, src, sel, dist))
-    exact = exact and bool(np.array_equal(B.to_u64(rd.dist), ref))
     res = {"weights": "selector_weights.npy (trained on random 2^16..2^21, R-MAT 16..20, grids 256^2..1024^2; "
-                      "other seeds)",
-           "headline": {"learned_ms": round(tl * 1e3, 3), "learned_phases": r.phases,
-                        "learned_gteps": round(m_reach / tl / 1e9, 4), "plain_ms": round(plain_ms, 3),
-                        "learned_over_plain": round(tl * 1e3 / plain_ms, 3),
-                        "learned_commit_ms": round(tc * 1e3, 3), "learned_commit_phases": rc.phases,
-                        "commit_after": S.COMMIT_PHASES,
-                        "learned_commit_over_plain": round(tc * 1e3 / plain_ms, 3),
-                        "learned_switch_ms": round(tw * 1e3, 3), "learned_switch_phases": rw.phases,
-                        "learned_switch_gteps": round(m_reach / tw / 1e9, 4),
-                        "learned_switch_over_plain": round(tw * 1e3 / plain_ms, 3),
-                        "learned_solve_hbm_frac": solve_frac(lst, tl * 1e3, dg.n),
-                        "learned_commit_solve_hbm_frac": solve_frac(cst, tc * 1e3, dg.n),
-                        "learned_delta_ms": round(td * 1e3, 3), "learned_delta_rounds": rd.phases,
-                        "learned_delta_gteps": round(m_reach / td / 1e9, 4)}}
-    for g in S.evaluation_graphs()[1:]:
+                      "other seeds)"}
+    exact = True
+
+    def one(name, h, s, mr, per_phase):
+        nonlocal exact
+        e = S.evaluate(sel, h, s, reps=3, per_phase=per_phase)
+        ref = B.to_u64(B.solve(h, s, B.STATIC_OR).dist)
+        ok = (np.array_equal(B.to_u64(B.solve_checkpoint(h, s, sel).dist), ref) and
+              np.array_equal(B.to_u64(B.delta_step_learned(h, s, sel).dist), ref) and
+              (not per_phase or np.array_equal(B.to_u64(B.solve_learned(h, s, sel).dist), ref)))
+        e["distances_exact"] = bool(ok)
+        exact = exact and e["distances_exact"]
+        e["checkpoint_gteps"] = mr / (e["checkpoint_ms"] * 1e6)
+        e["static_or_gteps"] = mr / (e["static_or_ms"] * 1e6)
+        e["best_fixed_delta_ms"] = min(e["delta_%d_ms" % d] for d in B.CHOICE_DELTA)
+        e["learned_delta_over_best_fixed"] = e["learned_delta_ms"] / e["best_fixed_delta_ms"]
+        res[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in e.items()}
+        log("learned", name, res[name])
+
+    one("headline", dg, src, m_reach, True)
+    res["headline"]["plain_ms_timed_run"] = round(plain_ms, 3)
+    for g in S.evaluation_graphs():
         h = B.DeviceGraph.from_graph(g)
         s = int(G.sources(g, 1, 5)[0])
-        e = S.evaluate(sel, h, s)
-        ref = B.to_u64(B.solve(h, s, B.STATIC_OR).dist)
-        e["distances_exact"] = bool(np.array_equal(B.to_u64(B.solve_learned(h, s, sel).dist), ref) and
-                                    np.array_equal(B.to_u64(B.solve_learned(h, s, sel, commit=S.COMMIT_PHASES).dist),
-                                                   ref) and
-                                    np.array_equal(B.to_u64(B.delta_step_learned(h, s, sel).dist), ref))
-        exact = exact and e["distances_exact"]
-        fixed = [e["static_or_ms"], e["simple_or_ms"], e["full_or_ms"]]
-        e["learned_over_best_fixed"] = round(e["learned_ms"] / min(fixed), 3)
-        e["learned_over_mean_fixed"] = round(e["learned_ms"] / (sum(fixed) / 3), 3)
-        e["learned_commit_over_best_fixed"] = round(e["learned_commit_ms"] / min(fixed), 3)
-        e["learned_switch_over_best_fixed"] = round(e["learned_switch_ms"] / min(fixed), 3)
-        res[g.name] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in e.items()}
+        mr = B.solve_ex(h, s, B.STATIC_OR).stats["m_reach"]
+        one(g.name, h, s, mr, False)
         del h
     res["distances_exact"] = exact
-    log("learned", res)
     return res
 
 

@@ -320,7 +320,7 @@ int sssp_autotune_batch(sssp_graph *const *graphs, const uint32_t *sources, uint
  * Learned per-phase selector: an MLP 12 -> 64 (ReLU) -> 64 (ReLU) -> 6 in FP32
  * that looks at the phase-start state and picks, per phase, which criterion
  * the phased solver evaluates (outputs 0..2: IN-STATIC|OUT-STATIC,
- * IN-SIMPLE|OUT-SIMPLE, IN|OUT) or, per bucket, Delta-stepping's width
+ * IN-SIMPLE|OUT-SIMPLE, IN-SIMPLE|OUT-STATIC) or, per bucket, Delta-stepping's width
  * (outputs 3..5: 2^12, 2^14, 2^16). Every criterion is sound (Section 3), so a
  * choice changes work and phase count, never a distance.
  * Features (12 floats, each a ratio of exact integers computed in double and
@@ -414,6 +414,39 @@ int sssp_solve_switch(sssp_graph *g, uint32_t source, uint32_t crit_first, uint3
 int sssp_solve_learned_switch(sssp_graph *g, uint32_t source, const sssp_selector *sel, uint32_t commit_phase,
                               uint32_t crit_then, uint32_t drop_num, uint32_t drop_den, uint64_t *dist_out,
                               sssp_stats *stats, uint32_t *phase_of, sssp_phase_rec *trace, uint32_t trace_cap);
+
+/*
+ * Fixed two-stage schedule: phases 0 .. switch_phase - 1 evaluate crit_first, a
+ * criterion made of DIJK, IN_STATIC and OUT_STATIC, every later phase crit_then
+ * (any criterion; OUT_STATIC in crit_then needs OUT_STATIC in crit_first).
+ * switch_phase = 0 runs crit_then throughout. Every criterion is sound
+ * (Section 3), so distances equal every other solver's. Errors and other
+ * arguments as sssp_solve_switch.
+ */
+int sssp_solve_schedule(sssp_graph *g, uint32_t source, uint32_t crit_first, uint32_t crit_then, uint32_t switch_phase,
+                        uint64_t *dist_out, sssp_stats *stats, uint32_t *phase_of, sssp_phase_rec *trace,
+                        uint32_t trace_cap);
+
+/*
+ * Learned checkpoint solve: IN_STATIC | OUT_STATIC on the plain kernels, and
+ * after every 16th phase (the last phase k of each batch of 16) one wavefront
+ * runs the selector on phase k's snapshot and outcome with the checkpoint
+ * features (delta_mode 2: F, S, minD and the OUT-STATIC threshold of phase k,
+ * |S'| of phase k, |F| at the previous checkpoint, the graph's size and mean
+ * degree as x5 = floor(log2 n)/32 and x6 = min(m/n, 64)/64; x7 = x8 = 0). Its output 0
+ * keeps the static criterion; the first checkpoint j that chooses 1
+ * (IN_SIMPLE | OUT_SIMPLE) or 2 (IN_SIMPLE | OUT_STATIC) switches every phase
+ * from 16 (j + 2) on to that criterion (the host reads each checkpoint one
+ * batch behind, so the switch phase does not depend on timing). The network
+ * alone decides; its cost is one small launch per 16 phases. Distances equal
+ * every other solver's.
+ *   features_out HOST, may be NULL: row j (12 floats) = checkpoint j's features,
+ *                for j < min(checkpoints, trace_cap); needs trace_cap > 0.
+ * Other arguments as sssp_solve_ex; trace records carry each phase's criterion.
+ */
+int sssp_solve_learned_checkpoint(sssp_graph *g, uint32_t source, const sssp_selector *sel, uint64_t *dist_out,
+                                  sssp_stats *stats, uint32_t *phase_of, sssp_phase_rec *trace, uint32_t trace_cap,
+                                  float *features_out);
 
 /* Delta-stepping whose bucket width is chosen per bucket by the selector. */
 int sssp_delta_step_learned(sssp_graph *g, uint32_t source, const sssp_selector *sel, uint64_t *dist_out,

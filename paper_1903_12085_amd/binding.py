@@ -33,7 +33,8 @@ SYMBOLS = ["sssp_graph_create", "sssp_graph_destroy", "sssp_set_stream", "sssp_g
            "sssp_selector_set_weights", "sssp_selector_forward", "sssp_selector_grad", "sssp_selector_train",
            "sssp_solve_learned", "sssp_delta_step_learned", "sssp_trace_learned",
            "sssp_solve_learned_commit", "sssp_measure_atomic_min", "sssp_solve_switch",
-           "sssp_solve_learned_switch", "sssp_solve_approx", "sssp_solve_noalloc"]
+           "sssp_solve_learned_switch", "sssp_solve_approx", "sssp_solve_noalloc",
+           "sssp_solve_schedule", "sssp_solve_learned_checkpoint"]
 
 ERRORS = {-1: "SSSP_ERR_INVALID", -2: "SSSP_ERR_OOM", -3: "SSSP_ERR_DEVICE", -4: "SSSP_ERR_UNSUPPORTED",
           -5: "SSSP_ERR_INTERNAL"}
@@ -101,6 +102,8 @@ def load(path: str = LIB_PATH):
     lib.sssp_graph_minima.argtypes = [P, P, P]
     lib.sssp_solve.argtypes = [P, u32, u32, P, P]
     lib.sssp_solve_noalloc.argtypes = [P, u32, u32, P, P]
+    lib.sssp_solve_schedule.argtypes = [P, u32, u32, u32, u32, P, ctypes.POINTER(Stats), P, P, u32]
+    lib.sssp_solve_learned_checkpoint.argtypes = [P, u32, P, P, ctypes.POINTER(Stats), P, P, u32, P]
     lib.sssp_solve_approx.argtypes = [P, u32, u32, u32, P, ctypes.POINTER(Stats), P, P, u32]
     lib.sssp_solve_ex.argtypes = [P, u32, u32, P, ctypes.POINTER(Stats), P, P, u32]
     lib.sssp_delta_step.argtypes = [P, u32, u64, P, P]
@@ -399,7 +402,7 @@ def autotune_batch(graphs, sources, criterion: int, dists=None):
 
 
 SELECTOR_PARAMS = 5382
-CHOICE_CRIT = [STATIC_OR, SIMPLE_OR, FULL_OR]
+CHOICE_CRIT = [STATIC_OR, SIMPLE_OR, IN_SIMPLE | OUT_STATIC]
 CHOICE_DELTA = [1 << 12, 1 << 14, 1 << 16]
 
 
@@ -505,6 +508,47 @@ def solve_switch(g: DeviceGraph, source: int, crit_first: int, crit_then: int, d
     if tr is not None:
         tr = tr[:min(st.phases, trace_cap)]
     return SolveResult(dist, int(st.phases), st.as_dict(), po, tr)
+
+
+def solve_schedule(g: DeviceGraph, source: int, crit_first: int, crit_then: int, switch_phase: int, dist=None,
+                   phase_of: bool = False, trace_cap: int = 0) -> SolveResult:
+    """crit_first for phases 0 .. switch_phase - 1, crit_then afterwards (sssp_solve_schedule)."""
+    import torch
+    dist = new_dist(g.n) if dist is None else dist
+    po = torch.empty(g.n, dtype=torch.int32, device="cuda") if phase_of else None
+    tr = np.zeros(trace_cap, PHASE_REC) if trace_cap else None
+    st = Stats()
+    g._bind_stream()
+    _check(load().sssp_solve_schedule(g.handle, source, crit_first, crit_then, int(switch_phase),
+                                      ctypes.c_void_p(dist.data_ptr()), ctypes.byref(st),
+                                      ctypes.c_void_p(po.data_ptr()) if po is not None else None, _np_ptr(tr),
+                                      trace_cap))
+    if tr is not None:
+        tr = tr[:min(st.phases, trace_cap)]
+    return SolveResult(dist, int(st.phases), st.as_dict(), po, tr)
+
+
+def solve_checkpoint(g: DeviceGraph, source: int, sel: Selector, dist=None, phase_of: bool = False,
+                     trace_cap: int = 0, features: bool = False):
+    """The learned checkpoint solve (sssp_solve_learned_checkpoint). With features=True, returns
+    (result, feature rows of the checkpoints) and needs trace_cap >= the number of checkpoints."""
+    import torch
+    dist = new_dist(g.n) if dist is None else dist
+    po = torch.empty(g.n, dtype=torch.int32, device="cuda") if phase_of else None
+    tr = np.zeros(trace_cap, PHASE_REC) if trace_cap else None
+    feat = np.zeros((trace_cap, 12), np.float32) if features else None
+    st = Stats()
+    g._bind_stream()
+    _check(load().sssp_solve_learned_checkpoint(g.handle, source, sel.handle, ctypes.c_void_p(dist.data_ptr()),
+                                                ctypes.byref(st),
+                                                ctypes.c_void_p(po.data_ptr()) if po is not None else None,
+                                                _np_ptr(tr), trace_cap, _np_ptr(feat)))
+    if tr is not None:
+        tr = tr[:min(st.phases, trace_cap)]
+    r = SolveResult(dist, int(st.phases), st.as_dict(), po, tr)
+    if features:
+        return r, feat[:min(st.phases // 16, trace_cap)]
+    return r
 
 
 def delta_step_learned(g: DeviceGraph, source: int, sel: Selector, dist=None, trace_cap: int = 0) -> SolveResult:

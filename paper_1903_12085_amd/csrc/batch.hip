@@ -30,6 +30,7 @@ struct BatchQuery {
     const uint32_t *rp;
     const uint2 *edges;
     const uint2 *vmin;
+    const uint32_t *emin;  // per edge: minOut of its target
     unsigned long long *dist;
     uint8_t *st;
     uint32_t *fl;      // 3 * n entries: fringe list A, fringe list B, settled list
@@ -99,7 +100,8 @@ __device__ __forceinline__ void wave_append(bool take, uint32_t v, uint32_t *lis
 // target was discovered; exactly one atomic can do that).
 template <int U, bool OUT>
 __device__ __forceinline__ uint32_t relax_edges(const BatchQuery &q, unsigned long long du, const uint2 *ed,
-                                                uint32_t have, unsigned long long &cmin, unsigned long long &ctst) {
+                                                const uint32_t *em, uint32_t have, unsigned long long &cmin,
+                                                unsigned long long &ctst) {
     uint8_t sv[U];
     unsigned long long cur[U], cand[U], old[U];
 #pragma unroll
@@ -127,7 +129,7 @@ __device__ __forceinline__ uint32_t relax_edges(const BatchQuery &q, unsigned lo
     for (int j = 0; j < U; ++j) {
         if (!((issued >> j) & 1u) || !(cand[j] < old[j])) continue;
         cmin = umin64(cmin, cand[j]);
-        if (OUT) ctst = umin64(ctst, sadd64(cand[j], min_out64(q.vmin[ed[j].x].y, q.wmax, q.rp, ed[j].x)));
+        if (OUT) ctst = umin64(ctst, sadd64(cand[j], min_out64(em[j], q.wmax, q.rp, ed[j].x)));
         if (old[j] == INF64) {
             q.st[ed[j].x] = ST_F;
             disc |= 1u << j;
@@ -257,16 +259,19 @@ __global__ __launch_bounds__(BS) void k_batch(const BatchQuery *__restrict__ que
                 for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor(mx, o, 64));
                 for (uint32_t k = 0; k < mx; k += kBatchU) {
                     uint2 ed[kBatchU];
+                    uint32_t em[kBatchU];
                     uint32_t have = 0;
 #pragma unroll
                     for (int j = 0; j < kBatchU; ++j) {
                         ed[j] = make_uint2(0u, 0u);
+                        em[j] = INF32;
                         if (k + j < len) {
                             ed[j] = q.edges[b + k + j];
+                            if (OUT) em[j] = q.emin[b + k + j];
                             have |= 1u << j;
                         }
                     }
-                    const uint32_t disc = relax_edges<kBatchU, OUT>(q, du, ed, have, cmin, ctst);
+                    const uint32_t disc = relax_edges<kBatchU, OUT>(q, du, ed, em, have, cmin, ctst);
 #pragma unroll
                     for (int j = 0; j < kBatchU; ++j)  // every lane of the wavefront takes part
                         wave_append((disc >> j) & 1u, ed[j].x, Fn, &s_nnext[pp]);
@@ -279,17 +284,20 @@ __global__ __launch_bounds__(BS) void k_batch(const BatchQuery *__restrict__ que
                 const uint32_t b = q.rp[v], e = q.rp[v + 1];
                 for (uint64_t kb = b; kb < e; kb += BS * kBatchU) {
                     uint2 ed[kBatchU];
+                    uint32_t em[kBatchU];
                     uint32_t have = 0;
 #pragma unroll
                     for (int j = 0; j < kBatchU; ++j) {
                         const uint64_t k = kb + (uint64_t)j * BS + threadIdx.x;
                         ed[j] = make_uint2(0u, 0u);
+                        em[j] = INF32;
                         if (k < e) {
                             ed[j] = q.edges[k];
+                            if (OUT) em[j] = q.emin[k];
                             have |= 1u << j;
                         }
                     }
-                    const uint32_t disc = relax_edges<kBatchU, OUT>(q, hub_du[h], ed, have, cmin, ctst);
+                    const uint32_t disc = relax_edges<kBatchU, OUT>(q, hub_du[h], ed, em, have, cmin, ctst);
 #pragma unroll
                     for (int j = 0; j < kBatchU; ++j) wave_append((disc >> j) & 1u, ed[j].x, Fn, &s_nnext[pp]);
                 }
@@ -345,8 +353,8 @@ int batch_solve_one(sssp_graph *g, uint32_t source, int in, bool out_static, uin
     }
     OneAux h;
     memset(&h, 0, sizeof h);
-    h.q = BatchQuery{g->rp, g->edges, g->vmin, (unsigned long long *)dist_out, g->one_st, g->one_fl, g->n, source,
-                     g->wmax};
+    h.q = BatchQuery{g->rp, g->edges, g->vmin, g->emin, (unsigned long long *)dist_out, g->one_st, g->one_fl, g->n,
+                     source, g->wmax};
     OneAux *d = (OneAux *)g->one_aux;
     HIP_OK(hipMemcpyAsync(d, &h, sizeof h, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(pick_batch(512, in, out_static), dim3(1), dim3(512), 0, s, &d->q, &d->order, 1u, &d->ctl,
@@ -403,6 +411,7 @@ extern "C" int sssp_solve_batch_ex(sssp_graph *const *graphs, const uint32_t *so
         hq[i].rp = g->rp;
         hq[i].edges = g->edges;
         hq[i].vmin = g->vmin;
+        hq[i].emin = g->emin;
         hq[i].dist = (unsigned long long *)dist_outs[i];
         hq[i].n = g->n;
         hq[i].src = sources[i];

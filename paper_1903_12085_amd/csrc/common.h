@@ -11,13 +11,12 @@
 #define INF32 0xFFFFFFFFu
 
 // Vertex state byte: low two bits = set membership, bit 2 = "IN test passed"
-// flag written by the dynamic-term pass for the current phase (bit 3: the IN
-// (full) test, written only by the trace-mode term pass, which evaluates both).
+// flag written by the dynamic-term pass for the current phase.
 // Queue arrays only: bit 4 (ST_QNEW) = discovered by a relax since the vertex's
 // scan block last looked, bit 5 (ST_QDIRTY) = distance lowered since then;
 // keyed queue arrays: bit 6 (ST_QFAR) = queued vertex kept out of its block's
 // entries because its IN-STATIC key d - minIn exceeded the split.
-enum : uint8_t { ST_U = 0, ST_F = 1, ST_S = 2, ST_R = 3, ST_SET = 3, ST_INOK = 4, ST_INOK_FULL = 8, ST_QNEW = 16,
+enum : uint8_t { ST_U = 0, ST_F = 1, ST_S = 2, ST_R = 3, ST_SET = 3, ST_INOK = 4, ST_QNEW = 16,
                  ST_QDIRTY = 32, ST_QFAR = 64 };
 
 // A settled vertex carries this bit in its distance word while the solve runs
@@ -90,6 +89,10 @@ struct alignas(128) CtlHead {
     unsigned long long qdelta[2];   // split margin above the threshold at the last rebuild
     unsigned long long qxrep[2];    // threshold at the last rebuild
     unsigned int qrebuilds;         // rebuild launches so far (launches = phases + rebuilds)
+    // learned checkpoint mode: the selector's choice at the last checkpoint (0 = stay static)
+    // and |F| at that checkpoint's phase
+    unsigned int cp_choice;
+    unsigned long long cp_fprev;
 };
 
 // Device control block of one solve. Slots indexed by phase parity (mod 2 or
@@ -112,7 +115,6 @@ struct Ctl {
     Sharded degsum;                 // sum of out-degrees of every vertex ever queued
     Sharded nin[2], nout[2];        // queued vertices passing IN-STATIC / OUT-STATIC, by phase parity
     // trace mode (training data): every criterion evaluated on every snapshot
-    Sharded tdyn2[3];               // min: OUT (full) threshold, while tdyn holds OUT-SIMPLE's
     Sharded cnt_cf[6];              // sum: vertices each of the three criteria certifies, [parity*3 + c]
 };
 
@@ -133,6 +135,7 @@ struct DevGraph {
     const uint2 *vmin;      // (minIn, minOut) per vertex
     const uint32_t *ip;     // CSC in_ptr (n+1) or null
     const uint2 *in_edges;  // CSC (source, weight), rows sorted by weight, or null
+    const uint32_t *emin;   // per edge (CSR order): minOut of its target (vmin[target].y)
     uint32_t wmax;          // nonzero if some edge weighs 2^32 - 1 (see min_out64)
 };
 

@@ -13,6 +13,7 @@ struct sssp_graph {
     uint32_t *rp = nullptr;        // row_ptr as u32 (n+1)
     uint2 *edges = nullptr;        // (target, weight), rows sorted by weight
     uint2 *vmin = nullptr;         // (minIn, minOut)
+    uint32_t *emin = nullptr;      // per edge: minOut of its target (relax folds the next OUT-STATIC threshold)
     uint32_t *ip = nullptr;        // CSC in_ptr (lazy)
     uint2 *in_edges = nullptr;     // CSC (source, weight), rows sorted by weight (lazy)
     uint64_t precompute_ns = 0;

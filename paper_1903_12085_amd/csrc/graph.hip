@@ -106,6 +106,14 @@ __global__ void k_min_in(uint64_t m, const uint2 *__restrict__ edges, uint2 *__r
     }
 }
 
+// emin[e] = minOut of edge e's target: relax folds the next OUT-STATIC threshold
+// from the edge's own row position, with no load that waits for the atomic.
+__global__ void k_emin(uint64_t m, const uint2 *__restrict__ edges, const uint2 *__restrict__ vmin,
+                       uint32_t *__restrict__ emin) {
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x)
+        emin[e] = vmin[edges[e].x].y;
+}
+
 // Exact sum of all edge weights (one block-level sum and one atomic per block);
 // out[1] counts the edges of weight 2^32 - 1.
 __global__ void k_sum_w(uint64_t m, const uint2 *__restrict__ edges, unsigned long long *__restrict__ out) {
@@ -196,6 +204,7 @@ static int create_impl(uint32_t n, uint64_t m, const uint64_t *row_ptr, const ui
     TRY(hipMalloc(&g->rp, (n + 1) * sizeof(uint32_t)));
     TRY(hipMalloc(&g->vmin, (uint64_t)n * sizeof(uint2)));
     TRY(hipMalloc(&g->edges, (m ? m : 1) * sizeof(uint2)));
+    TRY(hipMalloc(&g->emin, (m ? m : 1) * sizeof(uint32_t)));
     TRY(hipMalloc(&bad, sizeof(unsigned int)));
     TRY(hipMemsetAsync(bad, 0, sizeof(unsigned int), s));
     if (device_ptrs) {
@@ -248,6 +257,7 @@ static int create_impl(uint32_t n, uint64_t m, const uint64_t *row_ptr, const ui
         // 3. static minima
         hipLaunchKernelGGL(k_min_out, dim3(grid_for(n)), dim3(256), 0, s, n, g->rp, g->edges, g->vmin);
         if (m) hipLaunchKernelGGL(k_min_in, dim3(grid_for(m)), dim3(256), 0, s, m, g->edges, g->vmin);
+        if (m) hipLaunchKernelGGL(k_emin, dim3(grid_for(m)), dim3(256), 0, s, m, g->edges, g->vmin, g->emin);
         TRY(hipEventRecord(e1, s));
         TRY(hipEventSynchronize(e1));
         if (m) {  // weight sum for the selector's feature scale and the 2^32 - 1 flag (not timed)
@@ -309,7 +319,7 @@ extern "C" int sssp_graph_create(uint32_t n, uint64_t m, const uint64_t *row_ptr
 
 extern "C" int sssp_graph_destroy(sssp_graph *g) {
     if (!g) return SSSP_OK;
-    sssp_free(g->rp); sssp_free(g->edges); sssp_free(g->vmin);
+    sssp_free(g->rp); sssp_free(g->edges); sssp_free(g->vmin); sssp_free(g->emin);
     sssp_free(g->ip); sssp_free(g->in_edges);
     solve_bufs_free(g);
     delete g;

@@ -30,6 +30,7 @@
 #include <string.h>
 
 #include <mutex>
+#include <vector>
 
 #include "common.h"
 #include "graph.h"
@@ -47,13 +48,14 @@ struct KArgs {
     const unsigned long long *ref;  // ORACLE mode: dist(s, .) of this source (device)
 };
 
+// The selector's three criteria: IN-STATIC|OUT-STATIC, IN-SIMPLE|OUT-SIMPLE, IN-SIMPLE|OUT-STATIC.
 static __device__ const uint32_t kChoiceCrit[3] = {SSSP_IN_STATIC | SSSP_OUT_STATIC, SSSP_IN_SIMPLE | SSSP_OUT_SIMPLE,
-                                                  SSSP_IN_FULL | SSSP_OUT_FULL};
+                                                  SSSP_IN_SIMPLE | SSSP_OUT_STATIC};
 
 // Host side of kChoiceCrit (same order).
 static uint32_t choice_criterion(unsigned int c) {
     return c == 0 ? (SSSP_IN_STATIC | SSSP_OUT_STATIC) : c == 1 ? (SSSP_IN_SIMPLE | SSSP_OUT_SIMPLE)
-                                                                : (SSSP_IN_FULL | SSSP_OUT_FULL);
+                                                                : (SSSP_IN_SIMPLE | SSSP_OUT_STATIC);
 }
 
 __device__ __forceinline__ unsigned long long *slot_of(Sharded &s, int i) { return &s.v[i * kPad]; }
@@ -146,7 +148,6 @@ __global__ void k_init_ctl(Ctl *ctl, const uint2 *__restrict__ vmin, const uint3
         for (int k = 0; k < 2; ++k) {
             ctl->nin[k].v[o] = ctl->nout[k].v[o] = 0;
         }
-        for (int k = 0; k < 3; ++k) ctl->tdyn2[k].v[o] = INF64;
         for (int k = 0; k < 6; ++k) ctl->cnt_cf[k].v[o] = 0;
     }
 }
@@ -406,6 +407,57 @@ __device__ __forceinline__ unsigned long long cursor_term(uint32_t *__restrict__
     return h.x != INF32 ? (unsigned long long)h.y : INF64;
 }
 
+// Dynamic terms of one queued vertex v (distance dv at phase start): the IN
+// result (IN-SIMPLE or IN (full)) as a flag, and d + the OUT term (OUT-SIMPLE,
+// OUTWEAK or OUT) for the phase threshold, INF64 without a dynamic OUT.
+template <int IN, int OUT>
+__device__ __forceinline__ bool vertex_terms(const KArgs &a, uint32_t v, unsigned long long dv,
+                                             unsigned long long minD, unsigned long long &tval) {
+    bool ok = false;
+    if (IN != IN_NONE) {
+        unsigned long long term = INF64;
+        if (IN == IN_SIMPLE_M) {
+            // eq. crit:insimple: lightest in-edge from a non-settled vertex; sorted row + cursor
+            term = cursor_term(a.b.in_cur, a.b.in_head, a.g.in_edges, a.g.ip, v, a.b.st);
+        } else {
+            // eq. crit:in: in-edges from F, or from w in U plus w's own lightest in-edge
+            // (every in-neighbour of an unexplored w is queued or unexplored)
+            const uint32_t end = a.g.ip[v + 1];
+            for (uint32_t e = a.g.ip[v]; e < end; ++e) {
+                const uint2 ie = a.g.in_edges[e];
+                const uint8_t sw = a.b.st[ie.x] & ST_SET;
+                if (sw == ST_F) term = umin64(term, ie.y);
+                else if (sw == ST_U) term = umin64(term, sadd64(ie.y, min_in_u64(a.g.vmin[ie.x].x, a.g.wmax, a.g.ip, ie.x)));
+            }
+        }
+        ok = dv <= sadd64(minD, term);
+    }
+    tval = INF64;
+    if (OUT != OUT_NONE) {
+        unsigned long long term = INF64;
+        if (OUT == OUT_SIMPLE_M) {
+            // eq. crit:outsimple (u in F, w in F u U): lightest out-edge to a non-settled vertex
+            term = cursor_term(a.b.out_cur, a.b.out_head, a.g.edges, a.g.rp, v, a.b.st);
+        } else {
+            const uint32_t end = a.g.rp[v + 1];
+            for (uint32_t e = a.g.rp[v]; e < end; ++e) {
+                const uint2 ed = a.g.edges[e];
+                const uint8_t sx = a.b.st[ed.x] & ST_SET;
+                if (sx == ST_F) {
+                    term = umin64(term, ed.y);
+                } else if (sx == ST_U) {
+                    // eq. crit:outweak: second edge over all of V; eq. crit:out: into F u U
+                    const unsigned long long second =
+                        OUT == OUT_WEAK_M ? min_out64(a.g.vmin[ed.x].y, a.g.wmax, a.g.rp, ed.x) : walk_nonsettled(a, ed.x);
+                    term = umin64(term, sadd64(ed.y, second));
+                }
+            }
+        }
+        tval = sadd64(dv, term);
+    }
+    return ok;
+}
+
 template <int IN, int OUT>
 __device__ __forceinline__ void terms_body(const KArgs &a, int par, unsigned long long *sh) {
     Ctl *ctl = a.b.ctl;
@@ -425,48 +477,10 @@ __device__ __forceinline__ void terms_body(const KArgs &a, int par, unsigned lon
     for (uint32_t v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) {
         const uint8_t s = a.b.st[v];
         if ((s & ST_SET) != ST_F) continue;
-        const unsigned long long dv = a.b.dist[v];
-        if (IN != IN_NONE) {
-            unsigned long long term = INF64;
-            if (IN == IN_SIMPLE_M) {
-                // eq. crit:insimple: lightest in-edge from a non-settled vertex; sorted row + cursor
-                term = cursor_term(a.b.in_cur, a.b.in_head, a.g.in_edges, a.g.ip, v, a.b.st);
-            } else {
-                // eq. crit:in: in-edges from F, or from w in U plus w's own lightest in-edge
-                // (every in-neighbour of an unexplored w is queued or unexplored)
-                const uint32_t end = a.g.ip[v + 1];
-                for (uint32_t e = a.g.ip[v]; e < end; ++e) {
-                    const uint2 ie = a.g.in_edges[e];
-                    const uint8_t sw = a.b.st[ie.x] & ST_SET;
-                    if (sw == ST_F) term = umin64(term, ie.y);
-                    else if (sw == ST_U) term = umin64(term, sadd64(ie.y, min_in_u64(a.g.vmin[ie.x].x, a.g.wmax, a.g.ip, ie.x)));
-                }
-            }
-            const bool ok = dv <= sadd64(minD, term);
-            a.b.st[v] = ok ? (uint8_t)(ST_F | ST_INOK) : (uint8_t)ST_F;
-        }
-        if (OUT != OUT_NONE) {
-            unsigned long long term = INF64;
-            const uint32_t end = a.g.rp[v + 1];
-            if (OUT == OUT_SIMPLE_M) {
-                // eq. crit:outsimple (u in F, w in F u U): lightest out-edge to a non-settled vertex
-                term = cursor_term(a.b.out_cur, a.b.out_head, a.g.edges, a.g.rp, v, a.b.st);
-            } else {
-                for (uint32_t e = a.g.rp[v]; e < end; ++e) {
-                    const uint2 ed = a.g.edges[e];
-                    const uint8_t sx = a.b.st[ed.x] & ST_SET;
-                    if (sx == ST_F) {
-                        term = umin64(term, ed.y);
-                    } else if (sx == ST_U) {
-                        // eq. crit:outweak: second edge over all of V; eq. crit:out: into F u U
-                        const unsigned long long second =
-                            OUT == OUT_WEAK_M ? min_out64(a.g.vmin[ed.x].y, a.g.wmax, a.g.rp, ed.x) : walk_nonsettled(a, ed.x);
-                        term = umin64(term, sadd64(ed.y, second));
-                    }
-                }
-            }
-            tmin = umin64(tmin, sadd64(dv, term));
-        }
+        unsigned long long tv;
+        const bool ok = vertex_terms<IN, OUT>(a, v, a.b.dist[v], minD, tv);
+        if (IN != IN_NONE) a.b.st[v] = ok ? (uint8_t)(ST_F | ST_INOK) : (uint8_t)ST_F;
+        tmin = umin64(tmin, tv);
     }
     if (OUT != OUT_NONE) {
         block_reduce<kWaves, 1u, 1u>(&tmin, sh);
@@ -474,9 +488,9 @@ __device__ __forceinline__ void terms_body(const KArgs &a, int par, unsigned lon
     }
 }
 
-// Trace mode: every dynamic term of every criterion on the same snapshot.
-// IN-SIMPLE and IN (full) results go to state bits 2 and 3; OUT-SIMPLE's
-// threshold to tdyn, OUT (full)'s to tdyn2.
+// Trace mode: the dynamic terms of the selector's criteria on the same
+// snapshot: the IN-SIMPLE result goes to state bit 2, OUT-SIMPLE's threshold
+// to tdyn (IN-SIMPLE|OUT-STATIC reuses both halves).
 __global__ __launch_bounds__(kBlock) void k_terms_trace(KArgs a, int par) {
     __shared__ unsigned long long sh[8 * kWaves];
     Ctl *ctl = a.b.ctl;
@@ -486,41 +500,19 @@ __global__ __launch_bounds__(kBlock) void k_terms_trace(KArgs a, int par) {
     const unsigned long long reached = wave_sum64(r0);
     if (reached == settled) return;
     const unsigned long long minD = wave_min64(m0);
-    unsigned long long ts = INF64, tf = INF64;
+    unsigned long long ts = INF64;
     const uint32_t n = a.g.n;
     for (uint32_t v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) {
         const uint8_t s = a.b.st[v];
         if ((s & ST_SET) != ST_F) continue;
         const unsigned long long dv = a.b.dist[v];
-        unsigned long long inf = INF64, outf = INF64;
         const unsigned long long ins = cursor_term(a.b.in_cur, a.b.in_head, a.g.in_edges, a.g.ip, v, a.b.st);
-        uint32_t end = a.g.ip[v + 1];
-        for (uint32_t e = a.g.ip[v]; e < end; ++e) {
-            const uint2 ie = a.g.in_edges[e];
-            const uint8_t sw = a.b.st[ie.x] & ST_SET;
-            if (sw == ST_F) inf = umin64(inf, ie.y);
-            else if (sw == ST_U) inf = umin64(inf, sadd64(ie.y, min_in_u64(a.g.vmin[ie.x].x, a.g.wmax, a.g.ip, ie.x)));
-        }
-        end = a.g.rp[v + 1];
         const unsigned long long outs = cursor_term(a.b.out_cur, a.b.out_head, a.g.edges, a.g.rp, v, a.b.st);
-        for (uint32_t e = a.g.rp[v]; e < end; ++e) {
-            const uint2 ed = a.g.edges[e];
-            const uint8_t sx = a.b.st[ed.x] & ST_SET;
-            if (sx == ST_F) outf = umin64(outf, ed.y);
-            else if (sx == ST_U) outf = umin64(outf, sadd64(ed.y, walk_nonsettled(a, ed.x)));
-        }
-        a.b.st[v] = (uint8_t)(ST_F | (dv <= sadd64(minD, ins) ? ST_INOK : 0) | (dv <= sadd64(minD, inf) ? ST_INOK_FULL : 0));
+        a.b.st[v] = (uint8_t)(ST_F | (dv <= sadd64(minD, ins) ? ST_INOK : 0));
         ts = umin64(ts, sadd64(dv, outs));
-        tf = umin64(tf, sadd64(dv, outf));
     }
-    unsigned long long v[2] = {ts, tf};
-    block_reduce<kWaves, 3u, 3u>(v, sh);
-    ts = v[0];
-    tf = v[1];
-    if (threadIdx.x == 0) {
-        if (ts != INF64) atomicMin(slot_of(ctl->tdyn[p3], my_shard()), ts);
-        if (tf != INF64) atomicMin(slot_of(ctl->tdyn2[p3], my_shard()), tf);
-    }
+    block_reduce<kWaves, 1u, 1u>(&ts, sh);
+    if (threadIdx.x == 0 && ts != INF64) atomicMin(slot_of(ctl->tdyn[p3], my_shard()), ts);
 }
 
 template <int IN, int OUT>
@@ -609,7 +601,7 @@ __global__ __launch_bounds__(kBlock) void k_terms_learned(KArgs a, int par) {
     __shared__ unsigned long long sh[8 * kWaves];
     const unsigned int c = a.b.ctl->h.choice[par & 1];
     if (c == 1) terms_body<IN_SIMPLE_M, OUT_SIMPLE_M>(a, par, sh);
-    else if (c == 2) terms_body<IN_FULL_M, OUT_FULL_M>(a, par, sh);
+    else if (c == 2) terms_body<IN_SIMPLE_M, OUT_NONE>(a, par, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -669,7 +661,6 @@ __device__ __forceinline__ void phase_open(const KArgs &a, Ctl *ctl, int p2, int
         shard_fill(ctl->nout[p2 ^ 1], 0);
     }
     if (TRACE) {
-        shard_fill(ctl->tdyn2[(p3 + 1) % 3], INF64);
         for (int c = 0; c < 3; ++c) shard_fill(ctl->cnt_cf[(p2 ^ 1) * 3 + c], 0);
     }
 }
@@ -694,7 +685,6 @@ __device__ __forceinline__ void identify_body(const KArgs &a, int par, unsigned 
     const unsigned long long st0 = LEARN ? lane_slot(ctl->tst[p3], INF64) : 0ull;
     const unsigned long long dg0 = LEARN && blockIdx.x == 0 ? lane_slot(ctl->degsum, 0ull) : 0ull;
     const unsigned long long si0 = TRACE ? lane_slot(ctl->tdyn[p3], INF64) : 0ull;
-    const unsigned long long sf0 = TRACE ? lane_slot(ctl->tdyn2[p3], INF64) : 0ull;
     const unsigned long long settled = ctl->h.settled;
     const unsigned int P = ctl->h.pnum[p2];
     const unsigned int choice = TRACE ? ctl->h.choice[p2] : 0u;
@@ -711,7 +701,6 @@ __device__ __forceinline__ void identify_body(const KArgs &a, int par, unsigned 
     unsigned long long fmin = INF64, ftst = INF64, fsum = 0, cin = 0, cout = 0, cc[3] = {0, 0, 0};
     const unsigned long long Tst = LEARN ? wave_min64(st0) : 0ull;
     const unsigned long long Tsi = TRACE ? wave_min64(si0) : 0ull;
-    const unsigned long long Tfu = TRACE ? wave_min64(sf0) : 0ull;
     const uint32_t n = a.g.n;
     const uint32_t nq = (n + 3) / 4;  // lane q takes vertices 4q .. 4q+3
     constexpr bool kMinima = LEARN || IN == IN_STATIC_M || OUT == 1;
@@ -761,7 +750,7 @@ __device__ __forceinline__ void identify_body(const KArgs &a, int par, unsigned 
             if (TRACE) {
                 const bool c0 = dv[i] <= sadd64(minD, min_in_test(mm[i].x)) || dv[i] <= Tst;
                 const bool c1 = (s & ST_INOK) != 0 || dv[i] <= Tsi;
-                const bool c2 = (s & ST_INOK_FULL) != 0 || dv[i] <= Tfu;
+                const bool c2 = (s & ST_INOK) != 0 || dv[i] <= Tst;
                 cc[0] += c0;
                 cc[1] += c1;
                 cc[2] += c2;
@@ -852,7 +841,8 @@ __global__ __launch_bounds__(kBlock) void k_identify_learned(KArgs a, int par) {
     __shared__ unsigned long long sh[8 * kWaves];
     __shared__ AppendLds L;
     if (a.b.ctl->h.choice[par & 1] == 0) identify_body<IN_STATIC_M, 1, CH, true>(a, par, sh, L);
-    else identify_body<3, 2, CH, true>(a, par, sh, L);
+    else if (a.b.ctl->h.choice[par & 1] == 1) identify_body<3, 2, CH, true>(a, par, sh, L);
+    else identify_body<3, 1, CH, true>(a, par, sh, L);  // IN-SIMPLE flag or the OUT-STATIC threshold
 }
 
 // ---------------------------------------------------------------------------
@@ -862,8 +852,10 @@ constexpr unsigned long long kTomb = INF64;  // queue entry whose vertex has set
 constexpr uint32_t kOwnSpan = 16 * kBlock;   // consecutive vertices a scan block owns per grid step
 constexpr uint32_t kQWin = 4 * kOwnSpan;     // most vertices a scan block may own (state window in LDS)
 
-// Queue-array identify for criteria made of DIJK, IN-STATIC and OUT-STATIC
-// (IN: IN_NONE, IN_DIJK or IN_STATIC_M; OUT: 0, or 1 = OUT-STATIC threshold).
+// Queue-array identify (IN: IN_NONE, IN_DIJK, IN_STATIC_M, or 3 = the dynamic
+// IN flag in the state byte; OUT: 0, 1 = OUT-STATIC threshold, 2 = the dynamic
+// OUT threshold). With a dynamic criterion, k_terms_queue has evaluated the
+// phase's terms over the same entries before this launch.
 // Scan block b owns the vertices kOwnSpan * (k * G + b) + [0, kOwnSpan),
 // k = 0, 1, ... (G blocks), and keeps an entry (d, v, minIn, minOut) for each
 // of them that is queued, in slots [b * qspan, (b + 1) * qspan): a phase reads
@@ -903,6 +895,7 @@ constexpr unsigned long long kSplitPhases = 16;
 
 template <int IN, int OUT, int CH, bool KEYED = false>
 __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
+    static_assert(!KEYED || (IN <= IN_STATIC_M && OUT <= 1), "keyed queue arrays take static criteria only");
     __shared__ unsigned long long sh[8 * kWaves];
     __shared__ AppendLds L;
     __shared__ uint32_t s_wk[kWaves];  // compaction: entries each wavefront keeps in one step
@@ -911,7 +904,7 @@ __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
     Ctl *ctl = a.b.ctl;
     const int p2 = par & 1, p3 = par % 3;
     const unsigned long long r0 = lane_slot(ctl->reached, 0ull), m0 = lane_slot(ctl->minD[p3], INF64);
-    const unsigned long long t0 = OUT == 1 ? lane_slot(ctl->tst[p3], INF64) : 0ull;
+    const unsigned long long t0 = OUT == 1 ? lane_slot(ctl->tst[p3], INF64) : OUT == 2 ? lane_slot(ctl->tdyn[p3], INF64) : 0ull;
     const unsigned long long settled = ctl->h.settled;
     const unsigned int live = ctl->h.qlive[p2];
     const unsigned int P = ctl->h.pnum[p2];
@@ -920,6 +913,23 @@ __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
     const unsigned long long ksplit = KEYED ? ctl->h.qsplit[p2] : 0ull, kdelta = KEYED ? ctl->h.qdelta[p2] : 0ull;
     const unsigned long long kxrep = KEYED ? ctl->h.qxrep[p2] : 0ull;
     const unsigned int kprep = KEYED ? ctl->h.qprep[p2] : 0u;
+    // the block's state bytes (window w = its w-th grid step, at most four) are loaded
+    // now, with the control slots, and written to LDS once the phase is known to run
+    const uint32_t span = a.b.qspan;
+    uint4 win[kQWin / kOwnSpan];
+#pragma unroll
+    for (uint32_t w = 0; w < kQWin / kOwnSpan; ++w) {
+        win[w] = make_uint4(0u, 0u, 0u, 0u);
+        if (w * kOwnSpan >= span) continue;
+        const uint64_t v0 = (uint64_t)kOwnSpan * ((uint64_t)w * G + b) + 16u * threadIdx.x;
+        if (v0 + 16 <= n) {
+            win[w] = *reinterpret_cast<const uint4 *>(a.b.st + v0);
+        } else if (v0 < n) {
+            uint32_t q[4] = {0u, 0u, 0u, 0u};
+            for (uint32_t j = 0; v0 + j < n; ++j) q[j >> 2] |= (uint32_t)a.b.st[v0 + j] << (8 * (j & 3));
+            win[w] = make_uint4(q[0], q[1], q[2], q[3]);
+        }
+    }
     const unsigned long long reached = wave_sum64(r0);
     const unsigned long long nf = reached - settled;
     const bool dense = !KEYED && (live ? nf * 8 >= 3ull * n : nf * 10 >= 3ull * n);  // grid-uniform
@@ -930,7 +940,7 @@ __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
     }
     if (threadIdx.x == 0) { L.cnt = 0; L.filled = 0; L.zero = 0; s_app = 0; }
     const unsigned long long minD = wave_min64(m0);
-    const unsigned long long T = OUT == 1 ? wave_min64(t0) : 0ull;
+    const unsigned long long T = OUT ? wave_min64(t0) : 0ull;
     if (phase_done(ctl, p2, P, reached, settled)) return;
     // keyed: a rebuild when the entries are not current or the threshold passed the split
     const unsigned long long X = OUT == 1 ? T : minD;
@@ -976,21 +986,10 @@ __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
         }
     }
     const uint32_t cnt0 = live && !rebuild ? cnt_l : 0u, tomb0 = live && !rebuild ? tomb_l : 0u;
-    // state bytes of the block's vertices into LDS (window w = the block's w-th grid step)
-    const uint32_t span = a.b.qspan;
-#pragma unroll 1
-    for (uint32_t w = 0; w * kOwnSpan < span; ++w) {
-        const uint64_t v0 = (uint64_t)kOwnSpan * ((uint64_t)w * G + b) + 16u * threadIdx.x;
-        uint4 x = make_uint4(0u, 0u, 0u, 0u);
-        if (v0 + 16 <= n) {
-            x = *reinterpret_cast<const uint4 *>(a.b.st + v0);
-        } else if (v0 < n) {
-            uint32_t q[4] = {0u, 0u, 0u, 0u};
-            for (uint32_t j = 0; v0 + j < n; ++j) q[j >> 2] |= (uint32_t)a.b.st[v0 + j] << (8 * (j & 3));
-            x = make_uint4(q[0], q[1], q[2], q[3]);
-        }
-        s_st[w * kBlock + threadIdx.x] = x;
-    }
+    // state bytes of the block's vertices into LDS
+#pragma unroll
+    for (uint32_t w = 0; w < kQWin / kOwnSpan; ++w)
+        if (w * kOwnSpan < span) s_st[w * kBlock + threadIdx.x] = win[w];
     __syncthreads();  // LDS counters and state window ready
     const uint8_t *sw = reinterpret_cast<const uint8_t *>(s_st);
     auto win_of = [&](uint32_t v) {  // LDS index of an owned vertex's state byte
@@ -1002,11 +1001,12 @@ __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
     unsigned long long *qd = a.b.qd + rb;
     uint32_t *qv = a.b.qv + rb;
     uint2 *qm = a.b.qm + rb;
-    auto certified = [&](unsigned long long d, uint2 mm) {
+    auto certified = [&](unsigned long long d, uint2 mm, uint32_t sb) {
         bool ok = false;
         if (IN == IN_DIJK) ok = d == minD;
         else if (IN == IN_STATIC_M) ok = d <= sadd64(minD, min_in_test(mm.x));  // eq. crit:instatic
-        if (OUT == 1) ok = ok || d <= T;                                // eq. crit:outstatic
+        else if (IN == 3) ok = (sb & ST_INOK) != 0;                     // the term pass's IN result
+        if (OUT != 0) ok = ok || d <= T;                                // eq. crit:outstatic, or dynamic
         return ok;
     };
     auto settle = [&](uint32_t v, unsigned long long d, uint32_t &row, uint32_t &deg) {
@@ -1048,20 +1048,23 @@ __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
             }
         }
         // entries whose distance a relax lowered: reload it, clear the flag
+        uint32_t sbj[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-            if (d[j] != kTomb && (sw[win_of(v[j])] & ST_QDIRTY)) {
+        for (int j = 0; j < 4; ++j) {
+            sbj[j] = d[j] != kTomb ? sw[win_of(v[j])] : 0u;
+            if (sbj[j] & ST_QDIRTY) {
                 d[j] = a.b.dist[v[j]];
                 if (!compact) qd[i + j] = d[j];
                 a.b.st[v[j]] = ST_F;
             }
+        }
         uint32_t sm = 0, keep = 0;
         uint32_t row[4], deg[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             row[j] = deg[j] = 0;
             if (d[j] == kTomb) continue;
-            if (certified(d[j], mm[j])) {
+            if (certified(d[j], mm[j], sbj[j])) {
                 sm |= 1u << j;
             } else {
                 keep |= 1u << j;
@@ -1136,16 +1139,18 @@ __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
             }
         while (__ballot(nm != 0)) {  // wavefront-uniform: one vertex per lane per round
             const bool has = nm != 0;
-            uint32_t v = 0, row = 0, deg = 0;
+            uint32_t v = 0, row = 0, deg = 0, sb = 0;
             unsigned long long d = INF64;
             uint2 mm = make_uint2(INF32, INF32);
             if (has) {
-                v = (uint32_t)v0 + (uint32_t)(__ffs(nm) - 1);
+                const int j = __ffs(nm) - 1;
+                v = (uint32_t)v0 + (uint32_t)j;
+                sb = sw[w * kOwnSpan + 16u * threadIdx.x + (uint32_t)j];
                 nm &= nm - 1;
                 d = a.b.dist[v];
                 mm = a.g.vmin[v];
             }
-            const bool ok = has && !rebuild && certified(d, mm);
+            const bool ok = has && !rebuild && certified(d, mm, sb);
             if (ok) settle(v, d, row, deg);
             append_settled<CH>(a, ctl, p2, L, ok, row, deg, d);
             const bool far = KEYED && has && !ok && in_key(d, mm) > split;
@@ -1179,6 +1184,77 @@ __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
         a.b.qcnt[2 * b + 1] = compact ? 0u : tomb0 + (uint32_t)r[2];
         if (r[0] != INF64) atomicMin(slot_of(ctl->minD[(p3 + 1) % 3], my_shard()), r[0]);
         if (OUT == 1 && r[1] != INF64) atomicMin(slot_of(ctl->tst[(p3 + 1) % 3], my_shard()), r[1]);
+    }
+}
+
+// Term pass of the queue-array kernels (dynamic criteria): each scan block
+// evaluates the terms of the queued vertices it owns (the same ownership as
+// k_identify_queue), finding them in an LDS copy of its state bytes. The state
+// loads of all its windows are issued at once; windows without a queued vertex
+// are skipped, and the vertices of a window are taken one per thread in vertex
+// order, so that a wavefront's distance, cursor and cache loads are coalesced.
+// The IN result goes to the vertex's ST_INOK bit (its other flag bits kept for
+// identify), the OUT threshold is folded into this phase's tdyn slots.
+template <int IN, int OUT>
+__global__ __launch_bounds__(kBlock) void k_terms_queue(KArgs a, int par) {
+    __shared__ unsigned long long sh[8 * kWaves];
+    __shared__ uint4 s_st[kQWin / 16];
+    Ctl *ctl = a.b.ctl;
+    const int p3 = par % 3;
+    const unsigned long long r0 = lane_slot(ctl->reached, 0ull), m0 = lane_slot(ctl->minD[p3], INF64);
+    const unsigned long long settled = ctl->h.settled;
+    const uint32_t n = a.g.n, b = blockIdx.x, G = gridDim.x;
+    const uint32_t span = a.b.qspan;
+    uint4 win[kQWin / kOwnSpan];
+#pragma unroll
+    for (uint32_t w = 0; w < kQWin / kOwnSpan; ++w) {
+        win[w] = make_uint4(0u, 0u, 0u, 0u);
+        if (w * kOwnSpan >= span) continue;
+        const uint64_t v0 = (uint64_t)kOwnSpan * ((uint64_t)w * G + b) + 16u * threadIdx.x;
+        if (v0 + 16 <= n) {
+            win[w] = *reinterpret_cast<const uint4 *>(a.b.st + v0);
+        } else if (v0 < n) {
+            uint32_t q[4] = {0u, 0u, 0u, 0u};
+            for (uint32_t j = 0; v0 + j < n; ++j) q[j >> 2] |= (uint32_t)a.b.st[v0 + j] << (8 * (j & 3));
+            win[w] = make_uint4(q[0], q[1], q[2], q[3]);
+        }
+    }
+    const unsigned long long reached = wave_sum64(r0);
+    if (reached == settled) return;
+    const unsigned long long minD = wave_min64(m0);
+    // bit w: window w holds a queued vertex of this thread's sixteen
+    uint32_t fw = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < kQWin / kOwnSpan; ++w) {
+        if (w * kOwnSpan < span) s_st[w * kBlock + threadIdx.x] = win[w];
+        const uint32_t xs[4] = {win[w].x, win[w].y, win[w].z, win[w].w};
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) any |= ((xs[j >> 2] >> (8 * (j & 3))) & ST_SET) == ST_F;
+        fw |= any ? 1u << w : 0u;
+    }
+    const uint8_t *sw = reinterpret_cast<const uint8_t *>(s_st);
+    unsigned long long tmin = INF64;
+#pragma unroll 1
+    for (uint32_t w = 0; w * kOwnSpan < span; ++w) {
+        if (!__syncthreads_or((fw >> w) & 1u)) continue;  // block-uniform; the first one also orders the LDS writes
+        const uint64_t vb = (uint64_t)kOwnSpan * ((uint64_t)w * G + b);
+        if (vb >= n) break;
+#pragma unroll 2
+        for (uint32_t r = 0; r < kOwnSpan / kBlock; ++r) {
+            const uint32_t i = r * kBlock + threadIdx.x;
+            const uint32_t sb = sw[w * kOwnSpan + i];
+            if ((sb & ST_SET) != ST_F) continue;
+            const uint32_t v = (uint32_t)vb + i;
+            unsigned long long tv;
+            const bool ok = vertex_terms<IN, OUT>(a, v, a.b.dist[v], minD, tv);
+            if (IN != IN_NONE) a.b.st[v] = (uint8_t)((sb & ~(uint32_t)ST_INOK) | (ok ? ST_INOK : 0u));
+            tmin = umin64(tmin, tv);
+        }
+    }
+    if (OUT != OUT_NONE) {
+        block_reduce<kWaves, 1u, 1u>(&tmin, sh);
+        if (threadIdx.x == 0 && tmin != INF64) atomicMin(slot_of(ctl->tdyn[p3], my_shard()), tmin);
     }
 }
 
@@ -1449,8 +1525,25 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
     __shared__ uint32_t s_start[CH + 1];
     __shared__ unsigned long long s_du[CH + 1];
     __shared__ unsigned long long sh[8 * kWaves];
-    __shared__ uint32_t s_ns[kShards], s_E[kShards], s_cb[kShards + 1];
+    __shared__ uint32_t s_ns[kShards], s_E[kShards], s_nch[kShards];
+    __shared__ uint32_t s_cmax;
     __shared__ unsigned long long s_tot_settled, s_tot_edges;
+    // Chunks are interleaved over the shards: chunk c is chunk c / kShards of shard
+    // c % kShards, so a block knows its first chunk before it has read the shard
+    // counters and loads that chunk's entry bounds with them (guarded to stay inside
+    // the chunk_start rows; the values count only if the chunk exists).
+    constexpr bool kSel = LEARN && !DELTA;
+    const bool split = kSel && gridDim.x > 1;  // block 0 selects, blocks 1.. relax
+    const uint32_t cfirst = split ? blockIdx.x - 1 : blockIdx.x, cstep = split ? gridDim.x - 1 : gridDim.x;
+    const uint32_t lc0 = cfirst / kShards;
+    const int sd0 = (int)(cfirst % kShards);
+    uint32_t spec0 = 0, spec1 = 0;
+    const bool spec = lc0 + 1 < a.b.chunk_cap;
+    if (spec) {
+        const uint32_t *cs = a.b.chunk_start + (uint64_t)sd0 * a.b.chunk_cap;
+        spec0 = cs[lc0];
+        spec1 = cs[lc0 + 1];
+    }
     // header fields, loaded with the shard slots (before the barrier)
     const unsigned int done = ctl->h.done, P = ctl->h.pnum[p2];
     const unsigned int rebuilt = Q ? ctl->h.repart[p2] : 0u;  // keyed: a rebuild launch, not a phase
@@ -1463,16 +1556,16 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
         const unsigned long long nz = i < kShards ? ctl->szero[p2].v[i * kPad] : 0ull;
         const uint32_t ns = (uint32_t)(pk >> 32), E = (uint32_t)pk;
         const uint32_t nch = (uint32_t)(((uint64_t)E + CH - 1) / CH);
-        const uint32_t incl = wave_incl_scan(nch);
+        uint32_t mx = nch;  // most chunks in one shard: chunks c < kShards * mx may exist
+        for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor(mx, o, 64));
         if (i < kShards) {
             s_ns[i] = ns;
             s_E[i] = E;
-            s_cb[i] = incl - nch;
+            s_nch[i] = nch;
         }
-        if (i == kShards - 1) s_cb[kShards] = incl;
         const unsigned long long tset = wave_sum64((unsigned long long)ns + nz);
         const unsigned long long tedge = wave_sum64(E);
-        if (i == 0) { s_tot_settled = tset; s_tot_edges = tedge; }
+        if (i == 0) { s_tot_settled = tset; s_tot_edges = tedge; s_cmax = kShards * mx; }
     }
     __syncthreads();
     if (rebuilt) return;  // it settled nothing (its S' counters are zero) and relaxes nothing
@@ -1503,36 +1596,45 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
                 for (int c = 0; c < 3; ++c) a.b.trace_cf[3 * P + c] = (uint32_t)shard_sum_all(ctl->cnt_cf[p2 * 3 + c]);
         }
     }
-    constexpr bool kSel = LEARN && !DELTA;
-    const bool split = kSel && gridDim.x > 1;  // block 0 selects, blocks 1.. relax
     if (kSel && blockIdx.x == 0) {
         select_next_phase(a, p2, p3, P, s_tot_settled);
         if (split) return;
     }
     unsigned long long cmin = INF64, ctst = INF64, tried = 0, improv = 0, disc = 0, winimp = 0, dsum = 0, ddeg = 0;
-    const uint32_t nch = s_cb[kShards];
-    const uint32_t cfirst = split ? blockIdx.x - 1 : blockIdx.x, cstep = split ? gridDim.x - 1 : gridDim.x;
-    // Chunk c's shard, shard-local index and first / last S' entry; the entry
-    // bounds of the block's next chunk are loaded while this one is processed.
+    const uint32_t cmax = s_cmax;
+    // Chunk c's shard, shard-local index and first / last S' entry (ok = the chunk
+    // exists); the entry bounds of the block's next chunk are loaded while this one
+    // is processed.
     struct ChunkRef {
         int sd;
         uint32_t lc, j0, jend;
+        bool ok;
     };
-    auto chunk_ref = [&](uint32_t c) {
+    auto chunk_ref = [&](uint32_t c, bool use_spec) {
         ChunkRef r;
-        r.sd = 0;  // last shard with s_cb[sd] <= c
-        while (r.sd + 1 < kShards && s_cb[r.sd + 1] <= c) ++r.sd;
-        r.lc = c - s_cb[r.sd];
-        const uint32_t *cs = a.b.chunk_start + (uint64_t)r.sd * a.b.chunk_cap;
-        r.j0 = cs[r.lc];
-        r.jend = ((uint64_t)r.lc * CH + CH < s_E[r.sd]) ? cs[r.lc + 1] : s_ns[r.sd] - 1;
+        r.sd = (int)(c % kShards);
+        r.lc = c / kShards;
+        r.ok = r.lc < s_nch[r.sd];
+        r.j0 = r.jend = 0;
+        if (r.ok) {
+            const bool last = (uint64_t)r.lc * CH + CH >= s_E[r.sd];
+            if (use_spec) {
+                r.j0 = spec0;
+                r.jend = last ? s_ns[r.sd] - 1 : spec1;
+            } else {
+                const uint32_t *cs = a.b.chunk_start + (uint64_t)r.sd * a.b.chunk_cap;
+                r.j0 = cs[r.lc];
+                r.jend = last ? s_ns[r.sd] - 1 : cs[r.lc + 1];
+            }
+        }
         return r;
     };
     ChunkRef nxt{};
-    if (cfirst < nch) nxt = chunk_ref(cfirst);
-    for (uint32_t c = cfirst; c < nch; c += cstep) {
+    if (cfirst < cmax) nxt = chunk_ref(cfirst, spec);
+    for (uint32_t c = cfirst; c < cmax; c += cstep) {
         const ChunkRef ck = nxt;
-        if (c + cstep < nch) nxt = chunk_ref(c + cstep);
+        if (c + cstep < cmax) nxt = chunk_ref(c + cstep, false);
+        if (!ck.ok) continue;  // block-uniform
         const int sd = ck.sd;
         const uint32_t lc = ck.lc;
         const uint32_t Es = s_E[sd];
@@ -1572,14 +1674,18 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
                 }
             }
         uint2 ed[E];
+        uint32_t em[E];  // FOLDT: minOut of each edge's target, loaded beside the edge
         unsigned long long cur[E], cand[E], old[E];
         uint32_t live = 0, issued = 0;
 #pragma unroll
         for (int k = 0; k < E; ++k) {
             const uint32_t i = threadIdx.x + k * kBlock;
             ed[k] = make_uint2(0u, 0u);
+            em[k] = INF32;
             if (i < len) {
-                ed[k] = a.g.edges[s_start[lo[k]] + (i - s_pos[lo[k]])];
+                const uint32_t e = s_start[lo[k]] + (i - s_pos[lo[k]]);
+                ed[k] = a.g.edges[e];
+                if (FOLDT) em[k] = a.g.emin[e];
                 live |= 1u << k;
             }
         }
@@ -1610,7 +1716,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
             ++improv;
             if (!DELTA) {
                 cmin = umin64(cmin, cand[k]);
-                if (FOLDT) ctst = umin64(ctst, sadd64(cand[k], min_out64(a.g.vmin[v].y, a.g.wmax, a.g.rp, v)));
+                if (FOLDT) ctst = umin64(ctst, sadd64(cand[k], min_out64(em[k], a.g.wmax, a.g.rp, v)));
             } else if (kind == 2) {
                 cmin = umin64(cmin, cand[k]);
             } else if (cand[k] < hi) {
@@ -1702,6 +1808,49 @@ __global__ __launch_bounds__(64) void k_select_delta(KArgs a, int par) {
     }
 }
 
+// Learned checkpoint mode, one wavefront after the last phase k of every batch
+// of kSwitchBatch phases of a plain static solve: the selector looks at phase
+// k's snapshot and outcome (F, S, minD and the OUT-STATIC threshold of phase k,
+// what it settled, |F| at the previous checkpoint; checkpoint features) and
+// writes its choice: 0 = keep the static criterion, 1 = IN-SIMPLE|OUT-SIMPLE,
+// 2 = IN-SIMPLE|OUT-STATIC from now on. Everything read was final when relax(k)
+// ended; identify(k+1) clears phase k's slots only after this kernel.
+__global__ __launch_bounds__(64) void k_select_checkpoint(KArgs a, int par) {
+    Ctl *ctl = a.b.ctl;
+    const int p2 = par & 1, p3 = par % 3;
+    MlpRegs W;
+    mlp_load(a.mlp_w, W);
+    const unsigned int done = ctl->h.done, P = ctl->h.pnum[p2];
+    const unsigned long long F = ctl->h.fk, S = ctl->h.s_k, Sp = ctl->h.last_settled, Fp = ctl->h.cp_fprev;
+    const unsigned long long a0 = lane_slot(ctl->minD[p3], INF64), t0 = lane_slot(ctl->tst[p3], INF64);
+    if (done) return;
+    FeatIn q;
+    q.n = a.g.n;
+    q.m = a.g.m;
+    q.F = F;
+    q.S = S;
+    q.R = F + S;
+    q.a = wave_min64(a0);
+    q.t = wave_min64(t0);
+    q.SD = q.DG = q.Ip = q.Op = 0;
+    q.Fp = Fp;
+    q.D = F;
+    q.Sp = Sp;
+    q.k = P + 1ull;
+    q.Wm = a.wm;
+    q.delta_mode = 2;
+    float x[kMlpIn];
+    features_dev(q, x);
+    const int c = mlp_eval(W, x, 0);
+    if (threadIdx.x == 0) {
+        ctl->h.cp_choice = (unsigned int)c;
+        ctl->h.cp_fprev = F;
+        const unsigned int j = P / 16;  // checkpoint index (phases 16 j .. 16 j + 15 before it)
+        if (a.b.trace_feat && j < a.b.trace_cap)
+            for (int i = 0; i < kMlpIn; ++i) a.b.trace_feat[j * kMlpIn + i] = x[i];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // host side
 
@@ -1714,6 +1863,7 @@ DevGraph dev_view(const sssp_graph *g) {
     d.vmin = g->vmin;
     d.ip = g->ip;
     d.in_edges = g->in_edges;
+    d.emin = g->emin;
     d.wmax = g->wmax;
     return d;
 }
@@ -1899,18 +2049,39 @@ struct PhaseKernels {
 };
 
 
+static kfn pick_terms_queue(int in, int out) {
+    const int i = in == IN_SIMPLE_M ? 1 : in == IN_FULL_M ? 2 : 0;
+    const int o = out == OUT_SIMPLE_M ? 1 : out == OUT_WEAK_M ? 2 : out == OUT_FULL_M ? 3 : 0;
+    static const kfn tab[3][4] = {
+        {nullptr, k_terms_queue<0, OUT_SIMPLE_M>, k_terms_queue<0, OUT_WEAK_M>, k_terms_queue<0, OUT_FULL_M>},
+        {k_terms_queue<IN_SIMPLE_M, 0>, k_terms_queue<IN_SIMPLE_M, OUT_SIMPLE_M>,
+         k_terms_queue<IN_SIMPLE_M, OUT_WEAK_M>, k_terms_queue<IN_SIMPLE_M, OUT_FULL_M>},
+        {k_terms_queue<IN_FULL_M, 0>, k_terms_queue<IN_FULL_M, OUT_SIMPLE_M>, k_terms_queue<IN_FULL_M, OUT_WEAK_M>,
+         k_terms_queue<IN_FULL_M, OUT_FULL_M>}};
+    return tab[i][o];
+}
+
+// Queue-array kernels for any criterion: the term pass over the entries when a
+// criterion is dynamic, then identify with the static tests, the IN flag (3)
+// and / or the dynamic OUT threshold (2). Keyed arrays: static criteria only.
 template <int CH>
 static PhaseKernels pick_queue(int in, int out, bool keyed) {
-    static const kfn tab[3][2] = {
-        {nullptr, k_identify_queue<IN_NONE, 1, CH>},
-        {k_identify_queue<IN_DIJK, 0, CH>, k_identify_queue<IN_DIJK, 1, CH>},
-        {k_identify_queue<IN_STATIC_M, 0, CH>, k_identify_queue<IN_STATIC_M, 1, CH>}};
+    const int i = in >= IN_SIMPLE_M ? 3 : in;
+    const int o = out >= OUT_SIMPLE_M ? 2 : out;
+    static const kfn tab[4][3] = {
+        {nullptr, k_identify_queue<IN_NONE, 1, CH>, k_identify_queue<IN_NONE, 2, CH>},
+        {k_identify_queue<IN_DIJK, 0, CH>, k_identify_queue<IN_DIJK, 1, CH>, k_identify_queue<IN_DIJK, 2, CH>},
+        {k_identify_queue<IN_STATIC_M, 0, CH>, k_identify_queue<IN_STATIC_M, 1, CH>,
+         k_identify_queue<IN_STATIC_M, 2, CH>},
+        {k_identify_queue<3, 0, CH>, k_identify_queue<3, 1, CH>, k_identify_queue<3, 2, CH>}};
     static const kfn tabk[3][2] = {
         {nullptr, k_identify_queue<IN_NONE, 1, CH, true>},
         {k_identify_queue<IN_DIJK, 0, CH, true>, k_identify_queue<IN_DIJK, 1, CH, true>},
         {k_identify_queue<IN_STATIC_M, 0, CH, true>, k_identify_queue<IN_STATIC_M, 1, CH, true>}};
     PhaseKernels k;
-    k.identify = keyed ? tabk[in][out] : tab[in][out];
+    keyed = keyed && i < 3 && o < 2;
+    k.identify = keyed ? tabk[i][o] : tab[i][o];
+    k.terms = pick_terms_queue(in, out);
     k.keyed = keyed;
     k.relax = out == OUT_STATIC_M ? k_relax<CH, false, true, false, true> : k_relax<CH, false, false, false, true>;
     return k;
@@ -2044,7 +2215,10 @@ static int run_loop_profiled(sssp_graph *g, const KArgs &a, const PhaseKernels &
             pr.phases++;
             g->phase_ms.push_back((K.terms ? t0 : 0.f) + t1 + t2);
         }
-        if (g->h_ctl[0].done) break;
+        if (g->h_ctl[0].done) {
+            if (head) *head = g->h_ctl[0];  // F emptied before k_stop
+            break;
+        }
         if (k >= k_stop) {
             if (head) *head = g->h_ctl[0];
             break;
@@ -2146,7 +2320,10 @@ static int run_loop(sssp_graph *g, const KArgs &a, const PhaseKernels &K, uint64
         }
         if (have_prev) {
             HIP_OK(hipEventSynchronize(g->ev[slot ^ 1]));
-            if (g->h_ctl[slot ^ 1].done) break;
+            if (g->h_ctl[slot ^ 1].done) {
+                if (head) *head = g->h_ctl[slot ^ 1];  // F emptied before k_stop
+                break;
+            }
         }
         have_prev = true;
         slot ^= 1;
@@ -2170,8 +2347,12 @@ static int run_loop(sssp_graph *g, const KArgs &a, const PhaseKernels &K, uint64
 // solve ended in this stage).
 constexpr uint32_t kSwitchBatch = 16;
 
+// Learned checkpoint mode (checkpoint = true): instead of the |F| rule, the
+// k_select_checkpoint kernel runs after each batch's last phase and the first
+// batch whose choice is not 0 (keep static) ends the stage in the same way.
 static int run_until_drop(sssp_graph *g, const KArgs &a, const PhaseKernels &K, uint64_t max_phases, uint32_t num,
-                          uint32_t den, uint64_t *k_next, CtlHead *head, uint64_t k0 = 0) {
+                          uint32_t den, uint64_t *k_next, CtlHead *head, uint64_t k0 = 0, bool checkpoint = false,
+                          unsigned int *choice = nullptr) {
     hipStream_t s = g->stream;
     const dim3 blk(kBlock), gs(g->cfg.scan_blocks), gr(g->cfg.relax_blocks);
     uint64_t k = k0;
@@ -2185,6 +2366,7 @@ static int run_until_drop(sssp_graph *g, const KArgs &a, const PhaseKernels &K, 
             hipLaunchKernelGGL(K.identify, gs, blk, 0, s, a, par);
             hipLaunchKernelGGL(K.relax, gr, blk, 0, s, a, par);
         }
+        if (checkpoint) hipLaunchKernelGGL(k_select_checkpoint, dim3(1), dim3(64), 0, s, a, (int)((k - 1) % 6));
         HIP_OK(hipGetLastError());
         HIP_OK(hipMemcpyAsync(&g->h_ctl[slot], a.b.ctl, sizeof(CtlHead), hipMemcpyDeviceToHost, s));
         HIP_OK(hipEventRecord(g->ev[slot], s));
@@ -2192,7 +2374,10 @@ static int run_until_drop(sssp_graph *g, const KArgs &a, const PhaseKernels &K, 
             HIP_OK(hipEventSynchronize(g->ev[slot ^ 1]));
             const CtlHead &h = g->h_ctl[slot ^ 1];
             const unsigned long long f = h.fk;
-            if (h.done || (peak && f < peak && (unsigned __int128)f * den <= (unsigned __int128)peak * num)) {
+            const bool decide = checkpoint ? h.cp_choice != 0
+                                           : peak && f < peak && (unsigned __int128)f * den <= (unsigned __int128)peak * num;
+            if (h.done || decide) {
+                if (choice) *choice = h.cp_choice;  // the deciding checkpoint's choice
                 HIP_OK(hipEventSynchronize(g->ev[slot]));
                 *head = g->h_ctl[slot];
                 *k_next = k;
@@ -2248,8 +2433,14 @@ static int finish_stats(const sssp_graph *g, const Ctl *dctl, sssp_stats *st, ui
 
 // A switched solve's second criterion and the fraction of the peak |F| at
 // which it takes over.
+// mode 0: the |F| rule (num/den of the peak); mode 1: at phase `at` (a fixed
+// schedule); mode 2: when the selector's checkpoint choice is not static, to
+// the criterion it chose (learned checkpoint mode; crit_then names the
+// strongest criterion that may follow, for buffer set-up).
 struct SwitchReq {
     uint32_t crit_then, num, den;
+    uint32_t at = 0;
+    int mode = 0;
 };
 
 static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_t crit,
@@ -2258,7 +2449,8 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
                         uint32_t trace_cap, const sssp_selector *sel = nullptr, float *feat_host = nullptr,
                         uint32_t *cf_host = nullptr, const uint64_t *oracle_ref = nullptr, uint32_t commit = 0,
                         const SwitchReq *sw = nullptr, const uint32_t *apx = nullptr) {
-    const bool learn = sel != nullptr;
+    const bool ckpt = sw && sw->mode == 2;  // the selector only chooses at checkpoints
+    const bool learn = sel != nullptr && !ckpt;
     const bool oracle = oracle_ref != nullptr;
     const bool trace_mode = learn && !delta_mode && cf_host != nullptr;
     if (!g) return sssp_set_error(SSSP_ERR_INVALID, "graph is NULL");
@@ -2269,8 +2461,8 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
         return sssp_set_error(SSSP_ERR_INVALID, "commit applies to the learned phased solver only");
     int in = IN_NONE, out = OUT_NONE;
     if (learn && !delta_mode) {
-        in = IN_FULL_M;  // any of the three criteria may be chosen: CSC and cursors are needed
-        out = OUT_FULL_M;
+        in = IN_SIMPLE_M;  // any of the three criteria may be chosen: CSC and cursors are needed
+        out = OUT_SIMPLE_M;
     } else if (learn) {
         // bucket widths come from the selector
     } else if (oracle) {
@@ -2297,8 +2489,9 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
                                                     "DIJK, IN_STATIC and OUT_STATIC");
         if (sw->crit_then == 0 || (sw->crit_then & ~SSSP_CRIT_ALL))
             return sssp_set_error(SSSP_ERR_INVALID, "criterion 0x%x is empty or has unknown bits", sw->crit_then);
-        if (sw->num == 0 || sw->den < sw->num)
+        if (sw->mode == 0 && (sw->num == 0 || sw->den < sw->num))
             return sssp_set_error(SSSP_ERR_INVALID, "drop fraction %u/%u is not in (0, 1]", sw->num, sw->den);
+        if (ckpt && !sel) return sssp_set_error(SSSP_ERR_INVALID, "selector is NULL");
         crit_modes(sw->crit_then, &in2, &out2);
         if (out2 == OUT_STATIC_M && out != OUT_STATIC_M && !learn)
             return sssp_set_error(SSSP_ERR_INVALID, "OUT_STATIC after the switch needs OUT_STATIC before it");
@@ -2310,8 +2503,8 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
     // queue arrays: plain static criteria, or the plain static phases after a committed prefix
     // (a scan block's state window must fit in LDS: at most kQWin vertices per block)
     const bool queue_fits = g->cfg.queue && scan_span(g->n, g->cfg.scan_blocks, 16) <= kQWin;
-    const bool queue_now = queue_fits && !learn && !oracle && !apx && !delta_mode && static_modes(in, out);
-    const bool queue_later = queue_fits && (commit != 0 || (sw && static_modes(in2, out2)));
+    const bool queue_now = queue_fits && !learn && !oracle && !apx && !delta_mode;
+    const bool queue_later = queue_fits && (commit != 0 || sw);
     if (in_all >= IN_SIMPLE_M || (apx && (crit & SSSP_IN_APPROX))) {
         int rc = graph_ensure_csc(g);
         if (rc) return rc;
@@ -2341,7 +2534,7 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
     a.b.trace_cap = 0;
     a.crit = crit;
     a.approx_k = apx ? *apx : 0u;
-    a.mlp_w = learn ? selector_device_weights(sel) : nullptr;
+    a.mlp_w = sel ? selector_device_weights(sel) : nullptr;
     a.wm = g->m ? (double)g->sum_w / (double)g->m : 1.0;
     a.ref = (const unsigned long long *)oracle_ref;
     a.b.trace_feat = nullptr;
@@ -2371,10 +2564,12 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
                                   : pick_phase(g->cfg.chunk, in, out, delta_mode, learn, trace_mode, queue_now,
                                                // keyed: launches and phases differ, so not where the host
                                                // counts phases by launches (switched and committed solves)
-                                               queue_now && g->cfg.queue == 2 && !sw && !commit);
+                                               queue_now && g->cfg.queue == 2 && !sw && !commit &&
+                                                   static_modes(in, out));
     // phases <= reachable vertices; Delta rounds <= 2 * n + light rounds bounded by n per bucket
     // Delta: light rounds per bucket <= window vertices + 1, one heavy round per bucket
     const uint64_t max_phases = delta_mode ? 4ull * g->n + 64 : (uint64_t)g->n + 2;
+    uint32_t cp_rows = 0;  // checkpoint mode: feature rows written (one per checkpoint)
     if (commit) {
         // the selector chooses phases 0 .. commit - 1 one by one (queued without
         // graphs: they are few), then the rest run the plain kernels of the
@@ -2391,7 +2586,7 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
             int ic = IN_NONE, oc = OUT_NONE;
             crit_modes(a2.crit, &ic, &oc);
             // the first queue-array phase rebuilds the arrays from the state bytes (qlive = 0)
-            const bool q2 = queue_later && static_modes(ic, oc);
+            const bool q2 = queue_later;
             const PhaseKernels K2 = pick_phase(g->cfg.chunk, ic, oc, false, false, false, q2);
             if (sw && static_modes(ic, oc)) {
                 // committed to the static criterion: switch to the second criterion once F has
@@ -2405,7 +2600,7 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
                     KArgs a3 = a2;
                     a3.crit = sw->crit_then;
                     rc = run_loop(g, a3, pick_phase(g->cfg.chunk, in2, out2, false, false, false,
-                                                    queue_fits && static_modes(in2, out2)),
+                                                    queue_fits),
                                   max_phases, k_next);
                 }
                 g->prof = prof;
@@ -2414,18 +2609,31 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
             }
         }
     } else if (sw) {
-        // static phases until F has fallen to the given fraction of its peak, then the second
-        // criterion's plain kernels (no per-kernel timing: both stages use plain launches)
+        // static phases until F has fallen to the given fraction of its peak (or until phase
+        // sw->at, or until the selector chooses at a checkpoint), then the second criterion's
+        // plain kernels (no per-kernel timing: both stages use plain launches)
         const bool prof = g->prof;
         g->prof = false;
         CtlHead h{};
         uint64_t k_next = 0;
-        rc = run_until_drop(g, a, K, max_phases, sw->num, sw->den, &k_next, &h);
+        unsigned int choice = 0;
+        if (sw->mode == 1) {
+            const bool graphs = g->cfg.use_graph;
+            g->cfg.use_graph = false;
+            rc = sw->at ? run_loop(g, a, K, max_phases, 0, sw->at, &h) : SSSP_OK;
+            g->cfg.use_graph = graphs;
+            k_next = sw->at;
+        } else {
+            rc = run_until_drop(g, a, K, max_phases, sw->num, sw->den, &k_next, &h, 0, ckpt, &choice);
+        }
+        if (ckpt) cp_rows = (uint32_t)(k_next / kSwitchBatch);
         if (rc == SSSP_OK && !h.done) {
             KArgs a2 = a;
-            a2.crit = sw->crit_then;
-            const bool q2 = queue_later && static_modes(in2, out2);
-            rc = run_loop(g, a2, pick_phase(g->cfg.chunk, in2, out2, false, false, false, q2), max_phases, k_next);
+            a2.crit = ckpt ? choice_criterion(choice) : sw->crit_then;
+            int i2 = in2, o2 = out2;
+            if (ckpt) crit_modes(a2.crit, &i2, &o2);
+            const bool q2 = queue_later;
+            rc = run_loop(g, a2, pick_phase(g->cfg.chunk, i2, o2, false, false, false, q2), max_phases, k_next);
         }
         g->prof = prof;
     } else {
@@ -2440,7 +2648,7 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
     if (rc == SSSP_OK) rc = finish_stats(g, a.b.ctl, stats, &phases);
     if (rc == SSSP_OK && trace_cap) {
         const uint32_t cnt = phases < trace_cap ? phases : trace_cap;
-        const uint32_t fcnt = delta_mode ? (stats ? stats->buckets : 0) : cnt;
+        const uint32_t fcnt = delta_mode ? (stats ? stats->buckets : 0) : ckpt ? (cp_rows < phases / kSwitchBatch ? cp_rows : phases / kSwitchBatch) : cnt;
         const uint32_t fc = fcnt < trace_cap ? fcnt : trace_cap;
         hipError_t e = hipSuccess;
         if (cnt) e = hipMemcpyAsync(trace, a.b.trace, cnt * sizeof(PhaseRec), hipMemcpyDeviceToHost, s);
@@ -2585,6 +2793,33 @@ extern "C" int sssp_solve_learned_switch(sssp_graph *g, uint32_t source, const s
     const SwitchReq sw{crit_then, drop_num, drop_den};
     return solve_common(g, source, false, 0, nullptr, 0, dist_out, stats, phase_of, trace, trace_cap, sel, nullptr,
                         nullptr, nullptr, commit_phase, &sw);
+}
+
+extern "C" int sssp_solve_schedule(sssp_graph *g, uint32_t source, uint32_t crit_first, uint32_t crit_then,
+                                   uint32_t switch_phase, uint64_t *dist_out, sssp_stats *stats, uint32_t *phase_of,
+                                   sssp_phase_rec *trace, uint32_t trace_cap) {
+    SwitchReq sw{crit_then, 1, 1};
+    sw.at = switch_phase;
+    sw.mode = 1;
+    return solve_common(g, source, false, crit_first, nullptr, 0, dist_out, stats, phase_of, trace, trace_cap,
+                        nullptr, nullptr, nullptr, nullptr, 0, &sw);
+}
+
+extern "C" int sssp_solve_learned_checkpoint(sssp_graph *g, uint32_t source, const sssp_selector *sel,
+                                             uint64_t *dist_out, sssp_stats *stats, uint32_t *phase_of,
+                                             sssp_phase_rec *trace, uint32_t trace_cap, float *features_out) {
+    if (!sel) return sssp_set_error(SSSP_ERR_INVALID, "selector is NULL");
+    if (features_out && !trace_cap) return sssp_set_error(SSSP_ERR_INVALID, "features_out needs trace_cap > 0");
+    SwitchReq sw{SSSP_IN_SIMPLE | SSSP_OUT_SIMPLE | SSSP_OUT_STATIC, 1, 1};
+    sw.mode = 2;
+    if (!trace && features_out) {
+        // feature rows ride on the trace buffers: keep a host trace of trace_cap records here
+        std::vector<sssp_phase_rec> tmp(trace_cap);
+        return solve_common(g, source, false, SSSP_IN_STATIC | SSSP_OUT_STATIC, nullptr, 0, dist_out, stats,
+                            phase_of, tmp.data(), trace_cap, sel, features_out, nullptr, nullptr, 0, &sw);
+    }
+    return solve_common(g, source, false, SSSP_IN_STATIC | SSSP_OUT_STATIC, nullptr, 0, dist_out, stats, phase_of,
+                        trace, trace ? trace_cap : 0, sel, features_out, nullptr, nullptr, 0, &sw);
 }
 
 extern "C" int sssp_delta_step_learned(sssp_graph *g, uint32_t source, const sssp_selector *sel, uint64_t *dist_out,

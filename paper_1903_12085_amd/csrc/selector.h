@@ -16,12 +16,16 @@
 // Wm = (sum of weights)/m. Phase 0's choice uses the state {s} with nothing
 // evaluated (D = Sp = Ip = Op = Fp = 0); phase k+1's uses phase k's snapshot
 // and phase k's own outcome (D = |F_k|, Sp = |S'_k|, Fp = |F_{k-1}|), so it
-// is made while S'_k relaxes. For Delta-stepping (bucket starts) D = |F| at
-// the previous bucket start, Sp = what that bucket settled, and x4..x9 are 0.
+// is made while S'_k relaxes. For Delta-stepping (bucket starts, delta_mode 1)
+// D = |F| at the previous bucket start, Sp = what that bucket settled, and
+// x4..x9 are 0. Checkpoint mode (delta_mode 2; a choice after every 16th phase
+// of a plain static solve): the snapshot of the checkpoint phase k and its
+// outcome as above, Fp = |F| at the previous checkpoint, x5 = floor(log2 n)/32,
+// x6 = min(m/n, 64)/64 (the graph's size and mean degree) and x7 = x8 = 0.
 // Network: W1[64][12] b1[64] W2[64][64] b2[64] W3[6][64] b3[6]; each neuron is
 // its bias followed by fmaf over its inputs in index order; ReLU on the two
 // hidden layers. Outputs 0..2 choose the phase criterion (IN-STATIC|OUT-STATIC,
-// IN-SIMPLE|OUT-SIMPLE, IN|OUT), outputs 3..5 the bucket width 2^12, 2^14, 2^16;
+// IN-SIMPLE|OUT-SIMPLE, IN-SIMPLE|OUT-STATIC), outputs 3..5 the bucket width 2^12, 2^14, 2^16;
 // the argmax takes the lowest index on ties.
 #pragma once
 
@@ -48,7 +52,7 @@ __device__ __forceinline__ void features_dev(const FeatIn &q, float *x) {
     x[3] = (float)(fdmin(F / 4194304.0, 4.0) / 4.0);
     x[10] = (float)((n - (double)q.R) / n);
     x[11] = (float)(fdmin((double)q.a / q.Wm, 4096.0) / 4096.0);
-    if (q.delta_mode) {
+    if (q.delta_mode == 1) {
         for (int i = 4; i < 10; ++i) x[i] = 0.0f;
         return;
     }
@@ -58,6 +62,11 @@ __device__ __forceinline__ void features_dev(const FeatIn &q, float *x) {
     x[7] = (float)(q.D ? (double)q.Ip / D : 0.0);
     x[8] = (float)(q.D ? (double)q.Op / D : 0.0);
     x[9] = (float)(q.Fp ? fdmin(F / Fp, 4.0) / 4.0 : 0.0);
+    if (q.delta_mode == 2) {  // checkpoint mode: the plain kernels fold no SD, DG, Ip, Op
+        x[5] = (float)((double)(63 - __clzll(q.n)) / 32.0);
+        x[6] = (float)(fdmin(m / n, 64.0) / 64.0);
+        x[7] = x[8] = 0.0f;
+    }
 }
 
 // One wavefront evaluates the network. Lane j loads row j of W1 and W2 and

@@ -52,7 +52,7 @@ extern "C" int sssp_autotune(sssp_graph *g, uint32_t source, uint32_t criterion,
     const uint64_t quads = ((uint64_t)g->n + 3) / 4;
     int in = IN_NONE, out = OUT_NONE;
     crit_modes(criterion, &in, &out);
-    const uint32_t queue_max = static_modes(in, out) ? 2u : 0u;  // 2 = keyed; other criteria ignore the option
+    const uint32_t queue_max = static_modes(in, out) ? 2u : 1u;  // 2 = keyed, static criteria only
     std::vector<sssp_launch_cfg> cands;
     for (int sb_mul : {1, 2, 4, 8})
         for (int rb_mul : {2, 4, 8})
@@ -76,7 +76,7 @@ extern "C" int sssp_autotune(sssp_graph *g, uint32_t source, uint32_t criterion,
     sssp_launch_cfg win = keep;
     float win_ms = 1e30f;
     int rc = SSSP_OK;
-    if (queue_max) {
+    if (static_modes(in, out)) {
         // one workgroup for the whole solve: a candidate only when phases settle few vertices
         // on average (a workgroup would take too long over a large F)
         sssp_launch_cfg c = keep;

@@ -308,6 +308,39 @@ def test_queue_arrays_match_oracle(B, cfg):
             dg.close()
 
 
+DYN_CRITS = [O.SIMPLE_OR, O.IN_SIMPLE, O.OUT_SIMPLE, O.CRIT["IN_SIMPLE"] | O.OUT_STATIC,
+             O.IN_STATIC | O.OUT_SIMPLE, O.DIJK | O.OUT_SIMPLE, O.FULL_OR, O.IN_FULL | O.OUT_WEAK]
+
+
+@pytest.mark.parametrize("cfg", [dict(scan_blocks=1), dict(scan_blocks=5, relax_blocks=3, chunk=1024),
+                                 dict(scan_blocks=64, use_graph=1), dict(scan_blocks=4096, chunk=512)])
+def test_queue_arrays_dynamic_criteria_match_oracle(B, cfg):
+    """Dynamic criteria on the queue arrays (term pass over the entries and the vertices flagged
+    new, identify with the IN flag and the dynamic OUT threshold) against the dense scan and the
+    oracle: every observable, on graphs whose vertex counts are not multiples of a block's span.
+    The random graph's peak queue passes the dense-scan threshold, so the term pass also runs
+    after dense phases, when the entries are stale and it takes every queued vertex."""
+    graphs = [G.er(20011, 10, 1, 5000, 46), G.rmat(13, 16, 1, 1 << 16, 47), G.grid(97, 61, 1, 1 << 16, 48),
+              G.random_small(300, 1500, 0xFFFFFFFF, 49)]
+    for g in graphs:
+        crits = DYN_CRITS
+        refs = {c: O.phased(g, 0, c) for c in crits}
+        for queue in (1, 0, 2):
+            dg = B.DeviceGraph.from_graph(g)
+            dg.set_launch(queue=queue, **cfg)
+            for c in crits:
+                ref = refs[c]
+                r = B.solve_ex(dg, 0, c, phase_of=True, trace_cap=ref.phases + 4)
+                label = (g.name, queue, cfg, c)
+                assert np.array_equal(r.dist_u64(), ref.dist), label
+                assert r.phases == ref.phases and r.stats["sum_f"] == ref.sum_f, label
+                assert r.stats["relax_edges"] == ref.relax_edges, label
+                assert np.array_equal(r.phase_of.cpu().numpy().view(np.uint32), ref.phase_of), label
+                assert np.array_equal(r.trace["settled"], ref.trace_s), label
+                assert np.array_equal(r.trace["min_d"], ref.trace_mind), label
+            dg.close()
+
+
 def test_queue_arrays_survive_solve_kind_changes(B):
     """Queue-array solves interleaved with dense, dynamic, Delta-stepping and other-source solves
     on one handle: each starts from a clean state."""

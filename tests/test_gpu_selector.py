@@ -202,3 +202,49 @@ def test_learned_commit_switch_matches_oracle_replay(B, seed):
                 assert r.phases == rep.phases and r.stats["sum_f"] == rep.sum_f, (g.name, commit)
                 assert np.array_equal(r.phase_of.cpu().numpy().view(np.uint32), rep.phase_of), (g.name, commit)
         dg.close()
+
+
+CKPT_GRAPHS = lambda seed: (G.grid(40, 37, 1, 1 << 16, seed), G.er(20000, 3, 1, 1000, seed),  # noqa: E731
+                            G.rmat(12, 16, 1, 1 << 16, seed), G.grid(90, 11, 1, 1000, seed))
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_checkpoint_solve_matches_oracle(B, seed):
+    """The learned checkpoint solve against the oracle's checkpoint mode with the same network
+    (weights from the oracle side): checkpoint features bitwise, per-phase criteria (so the switch
+    phase and target), phases, settle phases and distances exactly."""
+    ws = [mixed_weights(seed)] + [M.pack(dict(M.unpack(np.zeros(M.NPARAM)), b3=np.eye(6)[c] * 10.0)).astype(np.float32)
+                                  for c in (0, 1, 2)]
+    for w in ws:
+        sel = B.Selector(w)
+        for g in CKPT_GRAPHS(seed):
+            ref = O.phased(g, 0, O.STATIC_OR, mlp_w=w, checkpoint=True, trace_cap=g.n)
+            dg = B.DeviceGraph.from_graph(g)
+            r, feat = B.solve_checkpoint(dg, 0, sel, phase_of=True, trace_cap=g.n, features=True)
+            assert np.array_equal(r.dist_u64(), ref.dist), g.name
+            assert r.phases == ref.phases, (g.name, r.phases, ref.phases)
+            assert np.array_equal(r.trace["criterion"], ref.trace_crit), g.name
+            assert np.array_equal(r.phase_of.cpu().numpy().view(np.uint32), ref.phase_of), g.name
+            # checkpoints up to the deciding one (a switch at 16 (j + 2) was decided at checkpoint j;
+            # the GPU's static stage runs one more batch, whose checkpoint the oracle does not need)
+            sw = next((k for k, c in enumerate(ref.trace_crit) if int(c) != O.STATIC_OR), None)
+            rows = ref.phases // 16 if sw is None else sw // 16 - 1
+            assert len(feat) >= rows, g.name
+            assert np.array_equal(feat[:rows], ref.trace_feat[:rows]), g.name
+            dg.close()
+
+
+def test_schedule_matches_oracle_replay(B):
+    """sssp_solve_schedule (static until a given phase, then another criterion) against the oracle's
+    per-phase criterion sequence, for switch phases 0, 1, 17 and past the end."""
+    for g in (G.er(5000, 6, 1, 1000, 41), G.grid(50, 41, 1, 1 << 16, 42)):
+        dg = B.DeviceGraph.from_graph(g)
+        for then in (O.SIMPLE_OR, O.IN_SIMPLE | O.OUT_STATIC, O.DIJK):
+            for at in (0, 1, 17, 100000):
+                seq = [O.STATIC_OR] * min(at, g.n + 2) + [then]
+                ref = O.phased(g, 0, 0, crit_seq=seq, trace_cap=g.n)
+                r = B.solve_schedule(dg, 0, O.STATIC_OR, then, at, phase_of=True, trace_cap=g.n)
+                assert np.array_equal(r.dist_u64(), ref.dist) and r.phases == ref.phases, (g.name, then, at)
+                assert np.array_equal(r.trace["criterion"], ref.trace_crit), (g.name, then, at)
+                assert np.array_equal(r.phase_of.cpu().numpy().view(np.uint32), ref.phase_of), (g.name, then, at)
+        dg.close()
