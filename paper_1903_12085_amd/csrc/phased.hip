@@ -458,6 +458,8 @@ __device__ __forceinline__ bool vertex_terms(const KArgs &a, uint32_t v, unsigne
     return ok;
 }
 
+// Dynamic terms over every vertex, one per thread in a grid-stride loop (the
+// per-phase learned mode, whose criterion changes from phase to phase).
 template <int IN, int OUT>
 __device__ __forceinline__ void terms_body(const KArgs &a, int par, unsigned long long *sh) {
     Ctl *ctl = a.b.ctl;
@@ -513,12 +515,6 @@ __global__ __launch_bounds__(kBlock) void k_terms_trace(KArgs a, int par) {
     }
     block_reduce<kWaves, 1u, 1u>(&ts, sh);
     if (threadIdx.x == 0 && ts != INF64) atomicMin(slot_of(ctl->tdyn[p3], my_shard()), ts);
-}
-
-template <int IN, int OUT>
-__global__ __launch_bounds__(kBlock) void k_terms(KArgs a, int par) {
-    __shared__ unsigned long long sh[8 * kWaves];
-    terms_body<IN, OUT>(a, par, sh);
 }
 
 // Approximate criteria (Section 3, closing paragraphs): per queued vertex the
@@ -854,7 +850,7 @@ constexpr uint32_t kQWin = 4 * kOwnSpan;     // most vertices a scan block may o
 
 // Queue-array identify (IN: IN_NONE, IN_DIJK, IN_STATIC_M, or 3 = the dynamic
 // IN flag in the state byte; OUT: 0, 1 = OUT-STATIC threshold, 2 = the dynamic
-// OUT threshold). With a dynamic criterion, k_terms_queue has evaluated the
+// OUT threshold). With a dynamic criterion, k_terms_win has evaluated the
 // phase's terms over the same entries before this launch.
 // Scan block b owns the vertices kOwnSpan * (k * G + b) + [0, kOwnSpan),
 // k = 0, 1, ... (G blocks), and keeps an entry (d, v, minIn, minOut) for each
@@ -1187,70 +1183,62 @@ __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
     }
 }
 
-// Term pass of the queue-array kernels (dynamic criteria): each scan block
-// evaluates the terms of the queued vertices it owns (the same ownership as
-// k_identify_queue), finding them in an LDS copy of its state bytes. The state
-// loads of all its windows are issued at once; windows without a queued vertex
-// are skipped, and the vertices of a window are taken one per thread in vertex
-// order, so that a wavefront's distance, cursor and cache loads are coalesced.
-// The IN result goes to the vertex's ST_INOK bit (its other flag bits kept for
-// identify), the OUT threshold is folded into this phase's tdyn slots.
+// Term pass of the plain solvers (dynamic criteria): block b evaluates the
+// terms of the queued vertices among kOwnSpan consecutive vertices (b + k G) *
+// kOwnSpan + [0, kOwnSpan), k = 0, 1, ...; the host launches enough blocks for
+// one window each, independent of the scan grid, so that the dependent loads of
+// the cursor walks are spread over as many threads as the device holds. A
+// window's state bytes are loaded with one 16-byte load per thread, issued with
+// the control-slot loads for the first window, and staged in LDS; a window
+// without a queued vertex is skipped, and the queued vertices are taken one per
+// thread in vertex order, so that a wavefront's distance, cursor and cache loads
+// are coalesced. The IN result goes to the vertex's ST_INOK bit (its other flag
+// bits are kept for the queue-array identify), the OUT threshold is folded into
+// this phase's tdyn slots.
 template <int IN, int OUT>
-__global__ __launch_bounds__(kBlock) void k_terms_queue(KArgs a, int par) {
+__global__ __launch_bounds__(kBlock) void k_terms_win(KArgs a, int par) {
     __shared__ unsigned long long sh[8 * kWaves];
-    __shared__ uint4 s_st[kQWin / 16];
+    __shared__ uint4 s_st[kOwnSpan / 16];
     Ctl *ctl = a.b.ctl;
     const int p3 = par % 3;
     const unsigned long long r0 = lane_slot(ctl->reached, 0ull), m0 = lane_slot(ctl->minD[p3], INF64);
     const unsigned long long settled = ctl->h.settled;
-    const uint32_t n = a.g.n, b = blockIdx.x, G = gridDim.x;
-    const uint32_t span = a.b.qspan;
-    uint4 win[kQWin / kOwnSpan];
-#pragma unroll
-    for (uint32_t w = 0; w < kQWin / kOwnSpan; ++w) {
-        win[w] = make_uint4(0u, 0u, 0u, 0u);
-        if (w * kOwnSpan >= span) continue;
-        const uint64_t v0 = (uint64_t)kOwnSpan * ((uint64_t)w * G + b) + 16u * threadIdx.x;
-        if (v0 + 16 <= n) {
-            win[w] = *reinterpret_cast<const uint4 *>(a.b.st + v0);
-        } else if (v0 < n) {
-            uint32_t q[4] = {0u, 0u, 0u, 0u};
-            for (uint32_t j = 0; v0 + j < n; ++j) q[j >> 2] |= (uint32_t)a.b.st[v0 + j] << (8 * (j & 3));
-            win[w] = make_uint4(q[0], q[1], q[2], q[3]);
-        }
-    }
+    const uint32_t n = a.g.n;
+    auto load16 = [&](uint64_t v0) {
+        if (v0 + 16 <= n) return *reinterpret_cast<const uint4 *>(a.b.st + v0);
+        uint32_t q[4] = {0u, 0u, 0u, 0u};
+        for (uint32_t j = 0; v0 + j < n; ++j) q[j >> 2] |= (uint32_t)a.b.st[v0 + j] << (8 * (j & 3));
+        return make_uint4(q[0], q[1], q[2], q[3]);
+    };
+    const uint64_t step = (uint64_t)gridDim.x * kOwnSpan;
+    uint64_t vb = (uint64_t)blockIdx.x * kOwnSpan;
+    uint4 x = vb < n ? load16(vb + 16u * threadIdx.x) : make_uint4(0u, 0u, 0u, 0u);
     const unsigned long long reached = wave_sum64(r0);
     if (reached == settled) return;
     const unsigned long long minD = wave_min64(m0);
-    // bit w: window w holds a queued vertex of this thread's sixteen
-    uint32_t fw = 0;
-#pragma unroll
-    for (uint32_t w = 0; w < kQWin / kOwnSpan; ++w) {
-        if (w * kOwnSpan < span) s_st[w * kBlock + threadIdx.x] = win[w];
-        const uint32_t xs[4] = {win[w].x, win[w].y, win[w].z, win[w].w};
-        bool any = false;
-#pragma unroll
-        for (int j = 0; j < 16; ++j) any |= ((xs[j >> 2] >> (8 * (j & 3))) & ST_SET) == ST_F;
-        fw |= any ? 1u << w : 0u;
-    }
     const uint8_t *sw = reinterpret_cast<const uint8_t *>(s_st);
     unsigned long long tmin = INF64;
-#pragma unroll 1
-    for (uint32_t w = 0; w * kOwnSpan < span; ++w) {
-        if (!__syncthreads_or((fw >> w) & 1u)) continue;  // block-uniform; the first one also orders the LDS writes
-        const uint64_t vb = (uint64_t)kOwnSpan * ((uint64_t)w * G + b);
-        if (vb >= n) break;
+    for (; vb < n; vb += step) {  // block-uniform
+        bool any = false;
+        const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+        for (int j = 0; j < 16; ++j) any |= ((xs[j >> 2] >> (8 * (j & 3))) & ST_SET) == ST_F;
+        __syncthreads();  // the previous window's LDS reads are done
+        s_st[threadIdx.x] = x;
+        if (__syncthreads_or(any)) {
 #pragma unroll 2
-        for (uint32_t r = 0; r < kOwnSpan / kBlock; ++r) {
-            const uint32_t i = r * kBlock + threadIdx.x;
-            const uint32_t sb = sw[w * kOwnSpan + i];
-            if ((sb & ST_SET) != ST_F) continue;
-            const uint32_t v = (uint32_t)vb + i;
-            unsigned long long tv;
-            const bool ok = vertex_terms<IN, OUT>(a, v, a.b.dist[v], minD, tv);
-            if (IN != IN_NONE) a.b.st[v] = (uint8_t)((sb & ~(uint32_t)ST_INOK) | (ok ? ST_INOK : 0u));
-            tmin = umin64(tmin, tv);
+            for (uint32_t r = 0; r < kOwnSpan / kBlock; ++r) {
+                const uint32_t i = r * kBlock + threadIdx.x;
+                const uint32_t sb = sw[i];
+                if ((sb & ST_SET) != ST_F) continue;
+                const uint32_t v = (uint32_t)vb + i;
+                unsigned long long tv;
+                const bool ok = vertex_terms<IN, OUT>(a, v, a.b.dist[v], minD, tv);
+                if (IN != IN_NONE) a.b.st[v] = (uint8_t)((sb & ~(uint32_t)ST_INOK) | (ok ? ST_INOK : 0u));
+                tmin = umin64(tmin, tv);
+            }
         }
+        if (vb + step < n) x = load16(vb + step + 16u * threadIdx.x);
     }
     if (OUT != OUT_NONE) {
         block_reduce<kWaves, 1u, 1u>(&tmin, sh);
@@ -2035,12 +2023,19 @@ static kfn pick_terms(int in, int out) {
     const int i = in == IN_SIMPLE_M ? 1 : in == IN_FULL_M ? 2 : 0;
     const int o = out == OUT_SIMPLE_M ? 1 : out == OUT_WEAK_M ? 2 : out == OUT_FULL_M ? 3 : 0;
     static const kfn tab[3][4] = {
-        {nullptr, k_terms<0, OUT_SIMPLE_M>, k_terms<0, OUT_WEAK_M>, k_terms<0, OUT_FULL_M>},
-        {k_terms<IN_SIMPLE_M, 0>, k_terms<IN_SIMPLE_M, OUT_SIMPLE_M>, k_terms<IN_SIMPLE_M, OUT_WEAK_M>,
-         k_terms<IN_SIMPLE_M, OUT_FULL_M>},
-        {k_terms<IN_FULL_M, 0>, k_terms<IN_FULL_M, OUT_SIMPLE_M>, k_terms<IN_FULL_M, OUT_WEAK_M>,
-         k_terms<IN_FULL_M, OUT_FULL_M>}};
+        {nullptr, k_terms_win<0, OUT_SIMPLE_M>, k_terms_win<0, OUT_WEAK_M>, k_terms_win<0, OUT_FULL_M>},
+        {k_terms_win<IN_SIMPLE_M, 0>, k_terms_win<IN_SIMPLE_M, OUT_SIMPLE_M>, k_terms_win<IN_SIMPLE_M, OUT_WEAK_M>,
+         k_terms_win<IN_SIMPLE_M, OUT_FULL_M>},
+        {k_terms_win<IN_FULL_M, 0>, k_terms_win<IN_FULL_M, OUT_SIMPLE_M>, k_terms_win<IN_FULL_M, OUT_WEAK_M>,
+         k_terms_win<IN_FULL_M, OUT_FULL_M>}};
     return tab[i][o];
+}
+
+// Grid of the term pass: one block per kOwnSpan vertices, independent of the
+// scan grid (the term kernels loop over further windows if the grid is capped).
+static uint32_t terms_grid(uint32_t n) {
+    const uint64_t b = ((uint64_t)n + kOwnSpan - 1) / kOwnSpan;
+    return (uint32_t)(b < 1 ? 1 : b > 65535 ? 65535 : b);
 }
 
 struct PhaseKernels {
@@ -2048,18 +2043,6 @@ struct PhaseKernels {
     int keyed = 0;  // keyed queue arrays: a launch may rebuild instead of running a phase
 };
 
-
-static kfn pick_terms_queue(int in, int out) {
-    const int i = in == IN_SIMPLE_M ? 1 : in == IN_FULL_M ? 2 : 0;
-    const int o = out == OUT_SIMPLE_M ? 1 : out == OUT_WEAK_M ? 2 : out == OUT_FULL_M ? 3 : 0;
-    static const kfn tab[3][4] = {
-        {nullptr, k_terms_queue<0, OUT_SIMPLE_M>, k_terms_queue<0, OUT_WEAK_M>, k_terms_queue<0, OUT_FULL_M>},
-        {k_terms_queue<IN_SIMPLE_M, 0>, k_terms_queue<IN_SIMPLE_M, OUT_SIMPLE_M>,
-         k_terms_queue<IN_SIMPLE_M, OUT_WEAK_M>, k_terms_queue<IN_SIMPLE_M, OUT_FULL_M>},
-        {k_terms_queue<IN_FULL_M, 0>, k_terms_queue<IN_FULL_M, OUT_SIMPLE_M>, k_terms_queue<IN_FULL_M, OUT_WEAK_M>,
-         k_terms_queue<IN_FULL_M, OUT_FULL_M>}};
-    return tab[i][o];
-}
 
 // Queue-array kernels for any criterion: the term pass over the entries when a
 // criterion is dynamic, then identify with the static tests, the IN flag (3)
@@ -2081,7 +2064,7 @@ static PhaseKernels pick_queue(int in, int out, bool keyed) {
     PhaseKernels k;
     keyed = keyed && i < 3 && o < 2;
     k.identify = keyed ? tabk[i][o] : tab[i][o];
-    k.terms = pick_terms_queue(in, out);
+    k.terms = pick_terms(in, out);
     k.keyed = keyed;
     k.relax = out == OUT_STATIC_M ? k_relax<CH, false, true, false, true> : k_relax<CH, false, false, false, true>;
     return k;
@@ -2183,7 +2166,7 @@ static int run_loop_profiled(sssp_graph *g, const KArgs &a, const PhaseKernels &
     sssp_kernel_profile pr{};
     if (k0) pr = g->last_prof;
     else g->phase_ms.clear();
-    const dim3 blk(kBlock), gs(g->cfg.scan_blocks), gr(g->cfg.relax_blocks);
+    const dim3 blk(kBlock), gs(g->cfg.scan_blocks), gr(g->cfg.relax_blocks), gt(terms_grid(g->n));
     uint64_t k = k0;
     for (;;) {
         const uint64_t kb = k;
@@ -2191,7 +2174,7 @@ static int run_loop_profiled(sssp_graph *g, const KArgs &a, const PhaseKernels &
             const int par = (int)(k % 6);
             hipEvent_t *e = &g->pev[4 * i];
             HIP_OK(hipEventRecord(e[0], s));
-            if (K.terms) hipLaunchKernelGGL(K.terms, gs, blk, 0, s, a, par);
+            if (K.terms) hipLaunchKernelGGL(K.terms, gt, blk, 0, s, a, par);
             HIP_OK(hipEventRecord(e[1], s));
             hipLaunchKernelGGL(K.identify, gs, blk, 0, s, a, par);
             HIP_OK(hipEventRecord(e[2], s));
@@ -2257,10 +2240,10 @@ static int ensure_phase_graph(sssp_graph *g, const KArgs &a, const PhaseKernels 
     g->graph_key_len = 0;
     if (!g->cap_stream) HIP_OK(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
     hipStream_t cs = g->cap_stream;
-    const dim3 blk(kBlock), gs(g->cfg.scan_blocks), gr(g->cfg.relax_blocks);
+    const dim3 blk(kBlock), gs(g->cfg.scan_blocks), gr(g->cfg.relax_blocks), gt(terms_grid(g->n));
     HIP_OK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     for (int par = 0; par < kGraphPhases; ++par) {
-        if (K.terms) hipLaunchKernelGGL(K.terms, gs, blk, 0, cs, a, par);
+        if (K.terms) hipLaunchKernelGGL(K.terms, gt, blk, 0, cs, a, par);
         hipLaunchKernelGGL(K.identify, gs, blk, 0, cs, a, par);
         hipLaunchKernelGGL(K.relax, gr, blk, 0, cs, a, par);
         if (K.select) hipLaunchKernelGGL(K.select, dim3(1), dim3(64), 0, cs, a, par);
@@ -2289,7 +2272,7 @@ static int run_loop(sssp_graph *g, const KArgs &a, const PhaseKernels &K, uint64
     }
     hipStream_t s = g->stream;
     const dim3 blk(kBlock);
-    const dim3 gs(g->cfg.scan_blocks), gr(g->cfg.relax_blocks);
+    const dim3 gs(g->cfg.scan_blocks), gr(g->cfg.relax_blocks), gt(terms_grid(g->n));
     uint64_t k = k0;
     uint32_t batch = graphs ? kGraphPhases : 4;
     int slot = 0;
@@ -2303,7 +2286,7 @@ static int run_loop(sssp_graph *g, const KArgs &a, const PhaseKernels &K, uint64
                 continue;
             }
             const int par = (int)(k % 6);
-            if (K.terms) hipLaunchKernelGGL(K.terms, gs, blk, 0, s, a, par);
+            if (K.terms) hipLaunchKernelGGL(K.terms, gt, blk, 0, s, a, par);
             hipLaunchKernelGGL(K.identify, gs, blk, 0, s, a, par);
             hipLaunchKernelGGL(K.relax, gr, blk, 0, s, a, par);
             if (K.select) hipLaunchKernelGGL(K.select, dim3(1), dim3(64), 0, s, a, par);
@@ -2354,7 +2337,7 @@ static int run_until_drop(sssp_graph *g, const KArgs &a, const PhaseKernels &K, 
                           uint32_t den, uint64_t *k_next, CtlHead *head, uint64_t k0 = 0, bool checkpoint = false,
                           unsigned int *choice = nullptr) {
     hipStream_t s = g->stream;
-    const dim3 blk(kBlock), gs(g->cfg.scan_blocks), gr(g->cfg.relax_blocks);
+    const dim3 blk(kBlock), gs(g->cfg.scan_blocks), gr(g->cfg.relax_blocks), gt(terms_grid(g->n));
     uint64_t k = k0;
     int slot = 0;
     bool have_prev = false;
@@ -2362,7 +2345,7 @@ static int run_until_drop(sssp_graph *g, const KArgs &a, const PhaseKernels &K, 
     for (;;) {
         for (uint32_t i = 0; i < kSwitchBatch; ++i, ++k) {
             const int par = (int)(k % 6);
-            if (K.terms) hipLaunchKernelGGL(K.terms, gs, blk, 0, s, a, par);
+            if (K.terms) hipLaunchKernelGGL(K.terms, gt, blk, 0, s, a, par);
             hipLaunchKernelGGL(K.identify, gs, blk, 0, s, a, par);
             hipLaunchKernelGGL(K.relax, gr, blk, 0, s, a, par);
         }
