@@ -16,8 +16,11 @@
 // scan block last looked, bit 5 (ST_QDIRTY) = distance lowered since then;
 // keyed queue arrays: bit 6 (ST_QFAR) = queued vertex kept out of its block's
 // entries because its IN-STATIC key d - minIn exceeded the split.
-enum : uint8_t { ST_U = 0, ST_F = 1, ST_S = 2, ST_R = 3, ST_SET = 3, ST_INOK = 4, ST_QNEW = 16,
-                 ST_QDIRTY = 32, ST_QFAR = 64 };
+// Stored IN (full) / OUTWEAK / OUT (full) terms: bit 7 (ST_CHG) = the vertex
+// changed state in the last phase (settled by identify, discovered by relax),
+// bit 3 (ST_TDIRTY) = its stored terms must be computed in full.
+enum : uint8_t { ST_U = 0, ST_F = 1, ST_S = 2, ST_R = 3, ST_SET = 3, ST_INOK = 4, ST_TDIRTY = 8, ST_QNEW = 16,
+                 ST_QDIRTY = 32, ST_QFAR = 64, ST_CHG = 128 };
 
 // A settled vertex carries this bit in its distance word while the solve runs
 // (real distances stay below 2^58 and INF is all ones, so a word with the bit
@@ -171,6 +174,9 @@ struct SolveBufs {
     // approximate criteria: phase index of each vertex's last IN / OUT recomputation, and the
     // 1-based settle phase of each vertex (the caller's phase_of when given)
     uint32_t *apx_lin, *apx_lout, *apx_sp;
+    // stored terms of the queued vertices: IN (full) and OUTWEAK / OUT (full), kept
+    // by the dirty-set pass (k_mark) and recomputed in full only where flagged
+    unsigned long long *tin, *tout;
 };
 
 int sssp_set_error(int code, const char *fmt, ...);

@@ -48,7 +48,7 @@ struct sssp_graph {
 DevGraph dev_view(const sssp_graph *g);
 int graph_ensure_csc(sssp_graph *g);
 void graph_default_cfg(sssp_graph *g);
-int solve_bufs_ensure(sssp_graph *g, bool cursors, bool stamps, bool queue, bool approx = false);
+int solve_bufs_ensure(sssp_graph *g, bool cursors, bool stamps, bool queue, bool approx = false, bool store = false);
 void solve_bufs_free(sssp_graph *g);
 int batch_solve_one(sssp_graph *g, uint32_t source, int in, bool out_static, uint64_t *dist_out,
                     uint32_t *phases_out);

@@ -46,6 +46,8 @@ struct KArgs {
     const float *mlp_w;  // learned mode: selector weights (device)
     double wm;           // learned mode: mean edge weight (feature scale)
     const unsigned long long *ref;  // ORACLE mode: dist(s, .) of this source (device)
+    uint32_t mark;       // stored full terms: identify and relax flag state changes (ST_CHG)
+    uint32_t fresh_at;   // stored full terms: the phase at which every queued vertex computes them
 };
 
 // The selector's three criteria: IN-STATIC|OUT-STATIC, IN-SIMPLE|OUT-SIMPLE, IN-SIMPLE|OUT-STATIC.
@@ -369,6 +371,10 @@ __device__ __forceinline__ uint32_t load_st4(const uint8_t *st, uint32_t q, uint
 // ---------------------------------------------------------------------------
 // term pass (dynamic criteria)
 
+// Consecutive vertices in one window: a queue-array scan block owns such windows
+// (one per grid step), the term and dirty-set passes take one per block.
+constexpr uint32_t kOwnSpan = 16 * kBlock;
+
 // Minimum weight of an out-edge of x towards a non-settled vertex, read-only
 // walk of x's weight-sorted row (x is unexplored, so no cursor owner exists).
 __device__ __forceinline__ unsigned long long walk_nonsettled(const KArgs &a, uint32_t x) {
@@ -407,55 +413,169 @@ __device__ __forceinline__ unsigned long long cursor_term(uint32_t *__restrict__
     return h.x != INF32 ? (unsigned long long)h.y : INF64;
 }
 
+// The dynamic IN term of a queued vertex v (INF64 when none): eq. crit:insimple
+// from the cursor, or eq. crit:in by a scan of v's in-edges.
+template <int IN>
+__device__ __forceinline__ unsigned long long in_term(const KArgs &a, uint32_t v) {
+    if (IN == IN_SIMPLE_M) {
+        // eq. crit:insimple: lightest in-edge from a non-settled vertex; sorted row + cursor
+        return cursor_term(a.b.in_cur, a.b.in_head, a.g.in_edges, a.g.ip, v, a.b.st);
+    }
+    // eq. crit:in: in-edges from F, or from w in U plus w's own lightest in-edge
+    // (every in-neighbour of an unexplored w is queued or unexplored)
+    unsigned long long term = INF64;
+    const uint32_t end = a.g.ip[v + 1];
+    for (uint32_t e = a.g.ip[v]; e < end; ++e) {
+        const uint2 ie = a.g.in_edges[e];
+        const uint8_t sw = a.b.st[ie.x] & ST_SET;
+        if (sw == ST_F) term = umin64(term, ie.y);
+        else if (sw == ST_U) term = umin64(term, sadd64(ie.y, min_in_u64(a.g.vmin[ie.x].x, a.g.wmax, a.g.ip, ie.x)));
+    }
+    return term;
+}
+
+// The dynamic OUT term of a queued vertex u (INF64 when none): eq. crit:outsimple
+// from the cursor, eq. crit:outweak or eq. crit:out by a scan of u's out-edges.
+template <int OUT>
+__device__ __forceinline__ unsigned long long out_term(const KArgs &a, uint32_t u) {
+    if (OUT == OUT_SIMPLE_M) {
+        // eq. crit:outsimple (u in F, w in F u U): lightest out-edge to a non-settled vertex
+        return cursor_term(a.b.out_cur, a.b.out_head, a.g.edges, a.g.rp, u, a.b.st);
+    }
+    unsigned long long term = INF64;
+    const uint32_t end = a.g.rp[u + 1];
+    for (uint32_t e = a.g.rp[u]; e < end; ++e) {
+        const uint2 ed = a.g.edges[e];
+        const uint8_t sx = a.b.st[ed.x] & ST_SET;
+        if (sx == ST_F) {
+            term = umin64(term, ed.y);
+        } else if (sx == ST_U) {
+            // eq. crit:outweak: second edge over all of V; eq. crit:out: into F u U
+            const unsigned long long second =
+                OUT == OUT_WEAK_M ? min_out64(a.g.vmin[ed.x].y, a.g.wmax, a.g.rp, ed.x) : walk_nonsettled(a, ed.x);
+            term = umin64(term, sadd64(ed.y, second));
+        }
+    }
+    return term;
+}
+
 // Dynamic terms of one queued vertex v (distance dv at phase start): the IN
-// result (IN-SIMPLE or IN (full)) as a flag, and d + the OUT term (OUT-SIMPLE,
-// OUTWEAK or OUT) for the phase threshold, INF64 without a dynamic OUT.
+// result as a flag, and d + the OUT term for the phase threshold (INF64
+// without a dynamic OUT).
 template <int IN, int OUT>
 __device__ __forceinline__ bool vertex_terms(const KArgs &a, uint32_t v, unsigned long long dv,
                                              unsigned long long minD, unsigned long long &tval) {
-    bool ok = false;
-    if (IN != IN_NONE) {
-        unsigned long long term = INF64;
-        if (IN == IN_SIMPLE_M) {
-            // eq. crit:insimple: lightest in-edge from a non-settled vertex; sorted row + cursor
-            term = cursor_term(a.b.in_cur, a.b.in_head, a.g.in_edges, a.g.ip, v, a.b.st);
-        } else {
-            // eq. crit:in: in-edges from F, or from w in U plus w's own lightest in-edge
-            // (every in-neighbour of an unexplored w is queued or unexplored)
-            const uint32_t end = a.g.ip[v + 1];
-            for (uint32_t e = a.g.ip[v]; e < end; ++e) {
-                const uint2 ie = a.g.in_edges[e];
-                const uint8_t sw = a.b.st[ie.x] & ST_SET;
-                if (sw == ST_F) term = umin64(term, ie.y);
-                else if (sw == ST_U) term = umin64(term, sadd64(ie.y, min_in_u64(a.g.vmin[ie.x].x, a.g.wmax, a.g.ip, ie.x)));
-            }
+    const bool ok = IN != IN_NONE && dv <= sadd64(minD, in_term<IN>(a, v));
+    tval = OUT != OUT_NONE ? sadd64(dv, out_term<OUT>(a, v)) : INF64;
+    return ok;
+}
+
+// Dirty-set maintenance of the stored IN (full), OUTWEAK and OUT (full) terms
+// (Section 3 keeps these minima per vertex and updates them as neighbours
+// change state). A vertex whose state changed in the last phase carries ST_CHG:
+//  - discovered w (U -> F; relax also flagged w ST_TDIRTY, so its own terms are
+//    computed in full): the candidate of w in an out-neighbour v's IN term was
+//    c(w,v) + minIn(w) and is now c(w,v), so tin[v] = min(tin[v], c(w,v)); the
+//    candidate of w in an in-neighbour u's OUT term (c(u,w) plus w's static
+//    lightest out-edge, or plus its lightest out-edge to a non-settled vertex)
+//    is now c(u,w), so tout[u] = min(tout[u], c(u,w));
+//  - settled w (F -> S): its candidate c leaves the IN term of each out-neighbour
+//    and the OUT term of each in-neighbour; where the stored term equals c it may
+//    rise, and that vertex is flagged ST_TDIRTY (computed in full by the term
+//    pass); elsewhere the minimum is unchanged;
+//  - OUT (full) only: a settled w may also raise, for an unexplored in-neighbour
+//    x, the lightest out-edge of x to a non-settled vertex, which enters the OUT
+//    term of every in-neighbour of x: those are flagged.
+// Stored values of vertices that are not queued are never read (a vertex is
+// computed in full in the phase it is first queued, after this pass), so updates
+// that land on them are harmless. Rows are walked by the thread that found the
+// changed vertex; rows longer than kLongRow edges go to an LDS list that the
+// whole block walks (skewed degrees). All state writes here are atomic.
+constexpr uint32_t kLongRow = 128, kLongCap = 64;
+
+__device__ __forceinline__ void flag_state(uint8_t *st, uint32_t v, uint32_t f) {
+    atomicOr(reinterpret_cast<uint32_t *>(st + (v & ~3u)), f << (8 * (v & 3u)));
+}
+
+template <bool IN_ON, int OUT_M>
+__device__ __forceinline__ void mark_row(const KArgs &a, uint32_t w, bool settled, bool out_dir, uint32_t lo,
+                                         uint32_t hi, uint32_t stride) {
+    if (!out_dir) {  // out-edges (w, v): the IN terms of the out-neighbours
+        for (uint32_t e = lo; e < hi; e += stride) {
+            const uint2 ed = a.g.edges[e];
+            if (!settled) atomicMin(&a.b.tin[ed.x], (unsigned long long)ed.y);
+            else if (a.b.tin[ed.x] == ed.y) flag_state(a.b.st, ed.x, ST_TDIRTY);
         }
-        ok = dv <= sadd64(minD, term);
-    }
-    tval = INF64;
-    if (OUT != OUT_NONE) {
-        unsigned long long term = INF64;
-        if (OUT == OUT_SIMPLE_M) {
-            // eq. crit:outsimple (u in F, w in F u U): lightest out-edge to a non-settled vertex
-            term = cursor_term(a.b.out_cur, a.b.out_head, a.g.edges, a.g.rp, v, a.b.st);
-        } else {
-            const uint32_t end = a.g.rp[v + 1];
-            for (uint32_t e = a.g.rp[v]; e < end; ++e) {
-                const uint2 ed = a.g.edges[e];
-                const uint8_t sx = a.b.st[ed.x] & ST_SET;
-                if (sx == ST_F) {
-                    term = umin64(term, ed.y);
-                } else if (sx == ST_U) {
-                    // eq. crit:outweak: second edge over all of V; eq. crit:out: into F u U
-                    const unsigned long long second =
-                        OUT == OUT_WEAK_M ? min_out64(a.g.vmin[ed.x].y, a.g.wmax, a.g.rp, ed.x) : walk_nonsettled(a, ed.x);
-                    term = umin64(term, sadd64(ed.y, second));
+    } else {  // in-edges (u, w): the OUT terms of the in-neighbours
+        for (uint32_t e = lo; e < hi; e += stride) {
+            const uint2 ie = a.g.in_edges[e];
+            if (!settled) {
+                atomicMin(&a.b.tout[ie.x], (unsigned long long)ie.y);
+            } else {
+                if (a.b.tout[ie.x] == ie.y) flag_state(a.b.st, ie.x, ST_TDIRTY);
+                if (OUT_M == OUT_FULL_M && (a.b.st[ie.x] & ST_SET) == ST_U) {
+                    const uint32_t end = a.g.ip[ie.x + 1];
+                    for (uint32_t f = a.g.ip[ie.x]; f < end; ++f) flag_state(a.b.st, a.g.in_edges[f].x, ST_TDIRTY);
                 }
             }
         }
-        tval = sadd64(dv, term);
     }
-    return ok;
+}
+
+template <bool IN_ON, int OUT_M>
+__global__ __launch_bounds__(kBlock) void k_mark(KArgs a, int par) {
+    __shared__ uint4 s_st[kOwnSpan / 16];
+    __shared__ uint32_t s_long[kLongCap], s_nlong;
+    Ctl *ctl = a.b.ctl;
+    const unsigned long long r0 = lane_slot(ctl->reached, 0ull);
+    const unsigned long long settled_cnt = ctl->h.settled;
+    const uint32_t n = a.g.n;
+    const unsigned long long reached = wave_sum64(r0);
+    if (reached == settled_cnt) return;
+    const uint8_t *sw = reinterpret_cast<const uint8_t *>(s_st);
+    for (uint64_t vb = (uint64_t)blockIdx.x * kOwnSpan; vb < n; vb += (uint64_t)gridDim.x * kOwnSpan) {
+        const uint64_t v0 = vb + 16u * threadIdx.x;
+        uint4 x = make_uint4(0u, 0u, 0u, 0u);
+        if (v0 + 16 <= n) {
+            x = *reinterpret_cast<const uint4 *>(a.b.st + v0);
+        } else if (v0 < n) {
+            uint32_t q[4] = {0u, 0u, 0u, 0u};
+            for (uint32_t j = 0; v0 + j < n; ++j) q[j >> 2] |= (uint32_t)a.b.st[v0 + j] << (8 * (j & 3));
+            x = make_uint4(q[0], q[1], q[2], q[3]);
+        }
+        const bool any = ((x.x | x.y | x.z | x.w) & 0x80808080u) != 0;
+        __syncthreads();  // the previous window's LDS reads are done
+        s_st[threadIdx.x] = x;
+        if (threadIdx.x == 0) s_nlong = 0;
+        if (!__syncthreads_or(any)) continue;  // block-uniform
+        for (uint32_t r = 0; r < kOwnSpan / kBlock; ++r) {
+            const uint32_t i = r * kBlock + threadIdx.x;
+            const uint32_t sb = sw[i];
+            if (!(sb & ST_CHG)) continue;
+            const uint32_t w = (uint32_t)vb + i;
+            atomicAnd(reinterpret_cast<uint32_t *>(a.b.st + (w & ~3u)), ~((uint32_t)ST_CHG << (8 * (w & 3u))));
+            const bool sett = (sb & ST_SET) == ST_S;
+            const uint32_t ob = a.g.rp[w], oe = a.g.rp[w + 1];
+            const uint32_t ib = OUT_M ? a.g.ip[w] : 0u, ie = OUT_M ? a.g.ip[w + 1] : 0u;
+            if ((IN_ON ? oe - ob : 0u) + (ie - ib) > kLongRow) {
+                const uint32_t k = atomicAdd(&s_nlong, 1u);
+                if (k < kLongCap) {
+                    s_long[k] = w;
+                    continue;
+                }
+            }
+            if (IN_ON) mark_row<IN_ON, OUT_M>(a, w, sett, false, ob, oe, 1);
+            if (OUT_M) mark_row<IN_ON, OUT_M>(a, w, sett, true, ib, ie, 1);
+        }
+        __syncthreads();
+        const uint32_t nl = s_nlong < kLongCap ? s_nlong : kLongCap;
+        for (uint32_t k = 0; k < nl; ++k) {  // block-uniform: the long rows, all threads per row
+            const uint32_t w = s_long[k];
+            const bool sett = (sw[w - (uint32_t)vb] & ST_SET) == ST_S;
+            if (IN_ON) mark_row<IN_ON, OUT_M>(a, w, sett, false, a.g.rp[w] + threadIdx.x, a.g.rp[w + 1], kBlock);
+            if (OUT_M) mark_row<IN_ON, OUT_M>(a, w, sett, true, a.g.ip[w] + threadIdx.x, a.g.ip[w + 1], kBlock);
+        }
+    }
 }
 
 // Dynamic terms over every vertex, one per thread in a grid-stride loop (the
@@ -786,7 +906,7 @@ __device__ __forceinline__ void identify_body(const KArgs &a, int par, unsigned 
 #pragma unroll
             for (int i = 0; i < 4; ++i)
                 if ((sm >> i) & 1u) {
-                    a.b.st[v0 + i] = ST_S;
+                    a.b.st[v0 + i] = (uint8_t)(ST_S | (a.mark ? ST_CHG : 0));
                     a.b.dist[v0 + i] = dv[i] | kSettledBit;
                     if (a.b.phase_of) a.b.phase_of[v0 + i] = P + 1;
                 }
@@ -845,7 +965,6 @@ __global__ __launch_bounds__(kBlock) void k_identify_learned(KArgs a, int par) {
 // identify over queue arrays (static criteria)
 
 constexpr unsigned long long kTomb = INF64;  // queue entry whose vertex has settled
-constexpr uint32_t kOwnSpan = 16 * kBlock;   // consecutive vertices a scan block owns per grid step
 constexpr uint32_t kQWin = 4 * kOwnSpan;     // most vertices a scan block may own (state window in LDS)
 
 // Queue-array identify (IN: IN_NONE, IN_DIJK, IN_STATIC_M, or 3 = the dynamic
@@ -1006,7 +1125,7 @@ __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
         return ok;
     };
     auto settle = [&](uint32_t v, unsigned long long d, uint32_t &row, uint32_t &deg) {
-        a.b.st[v] = ST_S;
+        a.b.st[v] = (uint8_t)(ST_S | (a.mark ? ST_CHG : 0));
         a.b.dist[v] = d | kSettledBit;
         if (a.b.phase_of) a.b.phase_of[v] = P + 1;
         row = a.g.rp[v];
@@ -1194,15 +1313,22 @@ __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
 // thread in vertex order, so that a wavefront's distance, cursor and cache loads
 // are coalesced. The IN result goes to the vertex's ST_INOK bit (its other flag
 // bits are kept for the queue-array identify), the OUT threshold is folded into
-// this phase's tdyn slots.
+// this phase's tdyn slots. IN (full), OUTWEAK and OUT (full) terms are stored
+// per vertex (tin, tout) and kept by k_mark: a vertex recomputes them from its
+// rows only when flagged ST_TDIRTY, or in the phase a.fresh_at (every queued
+// vertex: the first phase of the criterion).
 template <int IN, int OUT>
 __global__ __launch_bounds__(kBlock) void k_terms_win(KArgs a, int par) {
+    constexpr bool kStoreIn = IN == IN_FULL_M, kStoreOut = OUT == OUT_WEAK_M || OUT == OUT_FULL_M;
     __shared__ unsigned long long sh[8 * kWaves];
     __shared__ uint4 s_st[kOwnSpan / 16];
+    __shared__ uint32_t s_long[kLongCap], s_nlong;
+    __shared__ unsigned long long s_red[2][kWaves];
     Ctl *ctl = a.b.ctl;
     const int p3 = par % 3;
     const unsigned long long r0 = lane_slot(ctl->reached, 0ull), m0 = lane_slot(ctl->minD[p3], INF64);
     const unsigned long long settled = ctl->h.settled;
+    const bool fresh_all = (kStoreIn || kStoreOut) && ctl->h.pnum[par & 1] == a.fresh_at;
     const uint32_t n = a.g.n;
     auto load16 = [&](uint64_t v0) {
         if (v0 + 16 <= n) return *reinterpret_cast<const uint4 *>(a.b.st + v0);
@@ -1218,6 +1344,14 @@ __global__ __launch_bounds__(kBlock) void k_terms_win(KArgs a, int par) {
     const unsigned long long minD = wave_min64(m0);
     const uint8_t *sw = reinterpret_cast<const uint8_t *>(s_st);
     unsigned long long tmin = INF64;
+    // the terms of v from the full (or stored) values ti / to: the IN flag, the OUT fold, the state byte
+    auto finish = [&](uint32_t v, uint32_t sb, unsigned long long dv, unsigned long long ti, unsigned long long to) {
+        bool ok = false;
+        if (IN != IN_NONE) ok = dv <= sadd64(minD, ti);
+        if (OUT != OUT_NONE) tmin = umin64(tmin, sadd64(dv, to));
+        if (IN != IN_NONE || (sb & ST_TDIRTY))
+            a.b.st[v] = (uint8_t)((sb & ~(uint32_t)(ST_INOK | ST_TDIRTY)) | (ok ? ST_INOK : 0u));
+    };
     for (; vb < n; vb += step) {  // block-uniform
         bool any = false;
         const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
@@ -1225,6 +1359,7 @@ __global__ __launch_bounds__(kBlock) void k_terms_win(KArgs a, int par) {
         for (int j = 0; j < 16; ++j) any |= ((xs[j >> 2] >> (8 * (j & 3))) & ST_SET) == ST_F;
         __syncthreads();  // the previous window's LDS reads are done
         s_st[threadIdx.x] = x;
+        if (threadIdx.x == 0) s_nlong = 0;
         if (__syncthreads_or(any)) {
 #pragma unroll 2
             for (uint32_t r = 0; r < kOwnSpan / kBlock; ++r) {
@@ -1232,10 +1367,89 @@ __global__ __launch_bounds__(kBlock) void k_terms_win(KArgs a, int par) {
                 const uint32_t sb = sw[i];
                 if ((sb & ST_SET) != ST_F) continue;
                 const uint32_t v = (uint32_t)vb + i;
-                unsigned long long tv;
-                const bool ok = vertex_terms<IN, OUT>(a, v, a.b.dist[v], minD, tv);
-                if (IN != IN_NONE) a.b.st[v] = (uint8_t)((sb & ~(uint32_t)ST_INOK) | (ok ? ST_INOK : 0u));
-                tmin = umin64(tmin, tv);
+                const bool full = fresh_all || (sb & ST_TDIRTY) != 0;
+                if ((kStoreIn || kStoreOut) && full) {
+                    // a long row is scanned by the whole block after this window's rounds
+                    const uint32_t deg = (kStoreIn ? a.g.ip[v + 1] - a.g.ip[v] : 0u) +
+                                         (kStoreOut ? a.g.rp[v + 1] - a.g.rp[v] : 0u);
+                    if (deg > kLongRow) {
+                        const uint32_t k = atomicAdd(&s_nlong, 1u);
+                        if (k < kLongCap) {
+                            s_long[k] = v;
+                            continue;
+                        }
+                    }
+                }
+                const unsigned long long dv = a.b.dist[v];
+                unsigned long long ti = 0, to = 0;
+                if (IN != IN_NONE) {
+                    if (kStoreIn && !full) {
+                        ti = a.b.tin[v];
+                    } else {
+                        ti = in_term<IN>(a, v);
+                        if (kStoreIn) a.b.tin[v] = ti;
+                    }
+                }
+                if (OUT != OUT_NONE) {
+                    if (kStoreOut && !full) {
+                        to = a.b.tout[v];
+                    } else {
+                        to = out_term<OUT>(a, v);
+                        if (kStoreOut) a.b.tout[v] = to;
+                    }
+                }
+                finish(v, sb, dv, ti, to);
+            }
+        }
+        if (kStoreIn || kStoreOut) {
+            __syncthreads();  // the long-row list is complete
+            const uint32_t nl = s_nlong < kLongCap ? s_nlong : kLongCap;
+            for (uint32_t k = 0; k < nl; ++k) {  // block-uniform
+                const uint32_t v = s_long[k];
+                unsigned long long ti = INF64, to = INF64;
+                if (kStoreIn) {
+                    const uint32_t end = a.g.ip[v + 1];
+                    for (uint32_t e = a.g.ip[v] + threadIdx.x; e < end; e += kBlock) {
+                        const uint2 ie = a.g.in_edges[e];
+                        const uint8_t s2 = a.b.st[ie.x] & ST_SET;
+                        if (s2 == ST_F) ti = umin64(ti, ie.y);
+                        else if (s2 == ST_U) ti = umin64(ti, sadd64(ie.y, min_in_u64(a.g.vmin[ie.x].x, a.g.wmax, a.g.ip, ie.x)));
+                    }
+                }
+                if (kStoreOut) {
+                    const uint32_t end = a.g.rp[v + 1];
+                    for (uint32_t e = a.g.rp[v] + threadIdx.x; e < end; e += kBlock) {
+                        const uint2 ed = a.g.edges[e];
+                        const uint8_t s2 = a.b.st[ed.x] & ST_SET;
+                        if (s2 == ST_F) {
+                            to = umin64(to, ed.y);
+                        } else if (s2 == ST_U) {
+                            const unsigned long long second = OUT == OUT_WEAK_M
+                                ? min_out64(a.g.vmin[ed.x].y, a.g.wmax, a.g.rp, ed.x) : walk_nonsettled(a, ed.x);
+                            to = umin64(to, sadd64(ed.y, second));
+                        }
+                    }
+                }
+                ti = wave_min64(ti);
+                to = wave_min64(to);
+                if ((threadIdx.x & 63) == 0) {
+                    s_red[0][threadIdx.x >> 6] = ti;
+                    s_red[1][threadIdx.x >> 6] = to;
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    for (int w = 1; w < kWaves; ++w) {
+                        ti = umin64(ti, s_red[0][w]);
+                        to = umin64(to, s_red[1][w]);
+                    }
+                    // the other side of a mixed criterion (a SIMPLE cursor) by this thread
+                    if (IN != IN_NONE && !kStoreIn) ti = in_term<IN>(a, v);
+                    if (OUT != OUT_NONE && !kStoreOut) to = out_term<OUT>(a, v);
+                    if (kStoreIn) a.b.tin[v] = ti;
+                    if (kStoreOut) a.b.tout[v] = to;
+                    finish(v, sw[v - (uint32_t)vb], a.b.dist[v], ti, to);
+                }
+                __syncthreads();  // s_red is rewritten by the next long row
             }
         }
         if (vb + step < n) x = load16(vb + step + 16u * threadIdx.x);
@@ -1715,11 +1929,12 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
             if (Q) {
                 // flag for the owner's identify: word-wide OR, as other lanes flag the same word
                 uint32_t *w = reinterpret_cast<uint32_t *>(a.b.st + (v & ~3u));
-                const uint32_t f = old[k] == INF64 ? (uint32_t)(ST_F | ST_QNEW) : (uint32_t)ST_QDIRTY;
+                const uint32_t f = old[k] == INF64 ? (uint32_t)(ST_F | ST_QNEW | (a.mark ? ST_CHG | ST_TDIRTY : 0))
+                                                   : (uint32_t)ST_QDIRTY;
                 atomicOr(w, f << (8 * (v & 3u)));
             }
             if (old[k] == INF64) {
-                if (!Q) a.b.st[v] = ST_F;
+                if (!Q) a.b.st[v] = (uint8_t)(ST_F | (a.mark ? ST_CHG | ST_TDIRTY : 0));
                 ++disc;
                 if (LEARN && !DELTA) ddeg += a.g.rp[v + 1] - a.g.rp[v];
             }
@@ -1891,6 +2106,7 @@ void solve_bufs_free(sssp_graph *g) {
     sssp_free(b.in_head); sssp_free(b.out_head);
     sssp_free(b.qd); sssp_free(b.qv); sssp_free(b.qm); sssp_free(b.qcnt);
     sssp_free(b.apx_lin); sssp_free(b.apx_lout); sssp_free(b.apx_sp);
+    sssp_free(b.tin); sssp_free(b.tout);
     sssp_free(g->one_st); sssp_free(g->one_fl); sssp_free(g->one_aux);
     g->one_st = nullptr;
     g->one_fl = nullptr;
@@ -1952,7 +2168,7 @@ static int alloc_group(void **const *ptr, const uint64_t *bytes, int k) {
     return SSSP_OK;
 }
 
-int solve_bufs_ensure(sssp_graph *g, bool cursors, bool stamps, bool queue, bool approx) {
+int solve_bufs_ensure(sssp_graph *g, bool cursors, bool stamps, bool queue, bool approx, bool store) {
     SolveBufs &b = g->b;
     const uint64_t n = g->n;
     if (g->bufs_ready && g->bufs_scan_blocks != (uint32_t)g->cfg.scan_blocks) {
@@ -2000,6 +2216,12 @@ int solve_bufs_ensure(sssp_graph *g, bool cursors, bool stamps, bool queue, bool
         int rc = alloc_group(p, z, 3);
         if (rc) return rc;
     }
+    if (store && !(b.tin && b.tout)) {
+        void **const p[] = {(void **)&b.tin, (void **)&b.tout};
+        const uint64_t z[] = {n * 8, n * 8};
+        int rc = alloc_group(p, z, 2);
+        if (rc) return rc;
+    }
     return SSSP_OK;
 }
 
@@ -2031,6 +2253,15 @@ static kfn pick_terms(int in, int out) {
     return tab[i][o];
 }
 
+// The dirty-set pass of the stored full terms (nullptr when the criterion has none).
+static kfn pick_mark(int in, int out) {
+    const bool i = in == IN_FULL_M;
+    const int o = out == OUT_WEAK_M ? 1 : out == OUT_FULL_M ? 2 : 0;
+    static const kfn tab[2][3] = {{nullptr, k_mark<false, OUT_WEAK_M>, k_mark<false, OUT_FULL_M>},
+                                  {k_mark<true, 0>, k_mark<true, OUT_WEAK_M>, k_mark<true, OUT_FULL_M>}};
+    return tab[i][o];
+}
+
 // Grid of the term pass: one block per kOwnSpan vertices, independent of the
 // scan grid (the term kernels loop over further windows if the grid is capped).
 static uint32_t terms_grid(uint32_t n) {
@@ -2039,7 +2270,7 @@ static uint32_t terms_grid(uint32_t n) {
 }
 
 struct PhaseKernels {
-    kfn terms = nullptr, identify = nullptr, relax = nullptr, select = nullptr;
+    kfn mark = nullptr, terms = nullptr, identify = nullptr, relax = nullptr, select = nullptr;
     int keyed = 0;  // keyed queue arrays: a launch may rebuild instead of running a phase
 };
 
@@ -2065,6 +2296,7 @@ static PhaseKernels pick_queue(int in, int out, bool keyed) {
     keyed = keyed && i < 3 && o < 2;
     k.identify = keyed ? tabk[i][o] : tab[i][o];
     k.terms = pick_terms(in, out);
+    k.mark = pick_mark(in, out);
     k.keyed = keyed;
     k.relax = out == OUT_STATIC_M ? k_relax<CH, false, true, false, true> : k_relax<CH, false, false, false, true>;
     return k;
@@ -2092,6 +2324,7 @@ static PhaseKernels pick_phase_ch(int in, int out, bool delta, bool learn, bool 
         return k;
     }
     k.terms = pick_terms(in, out);
+    k.mark = pick_mark(in, out);
     k.identify = pick_identify<CH>(in, out);
     k.relax = out == OUT_STATIC_M ? k_relax<CH, false, true, false> : k_relax<CH, false, false, false>;
     return k;
@@ -2174,6 +2407,7 @@ static int run_loop_profiled(sssp_graph *g, const KArgs &a, const PhaseKernels &
             const int par = (int)(k % 6);
             hipEvent_t *e = &g->pev[4 * i];
             HIP_OK(hipEventRecord(e[0], s));
+            if (K.mark) hipLaunchKernelGGL(K.mark, gt, blk, 0, s, a, par);
             if (K.terms) hipLaunchKernelGGL(K.terms, gt, blk, 0, s, a, par);
             HIP_OK(hipEventRecord(e[1], s));
             hipLaunchKernelGGL(K.identify, gs, blk, 0, s, a, par);
@@ -2243,6 +2477,7 @@ static int ensure_phase_graph(sssp_graph *g, const KArgs &a, const PhaseKernels 
     const dim3 blk(kBlock), gs(g->cfg.scan_blocks), gr(g->cfg.relax_blocks), gt(terms_grid(g->n));
     HIP_OK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     for (int par = 0; par < kGraphPhases; ++par) {
+        if (K.mark) hipLaunchKernelGGL(K.mark, gt, blk, 0, cs, a, par);
         if (K.terms) hipLaunchKernelGGL(K.terms, gt, blk, 0, cs, a, par);
         hipLaunchKernelGGL(K.identify, gs, blk, 0, cs, a, par);
         hipLaunchKernelGGL(K.relax, gr, blk, 0, cs, a, par);
@@ -2286,6 +2521,7 @@ static int run_loop(sssp_graph *g, const KArgs &a, const PhaseKernels &K, uint64
                 continue;
             }
             const int par = (int)(k % 6);
+            if (K.mark) hipLaunchKernelGGL(K.mark, gt, blk, 0, s, a, par);
             if (K.terms) hipLaunchKernelGGL(K.terms, gt, blk, 0, s, a, par);
             hipLaunchKernelGGL(K.identify, gs, blk, 0, s, a, par);
             hipLaunchKernelGGL(K.relax, gr, blk, 0, s, a, par);
@@ -2345,6 +2581,7 @@ static int run_until_drop(sssp_graph *g, const KArgs &a, const PhaseKernels &K, 
     for (;;) {
         for (uint32_t i = 0; i < kSwitchBatch; ++i, ++k) {
             const int par = (int)(k % 6);
+            if (K.mark) hipLaunchKernelGGL(K.mark, gt, blk, 0, s, a, par);
             if (K.terms) hipLaunchKernelGGL(K.terms, gt, blk, 0, s, a, par);
             hipLaunchKernelGGL(K.identify, gs, blk, 0, s, a, par);
             hipLaunchKernelGGL(K.relax, gr, blk, 0, s, a, par);
@@ -2488,11 +2725,15 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
     const bool queue_fits = g->cfg.queue && scan_span(g->n, g->cfg.scan_blocks, 16) <= kQWin;
     const bool queue_now = queue_fits && !learn && !oracle && !apx && !delta_mode;
     const bool queue_later = queue_fits && (commit != 0 || sw);
-    if (in_all >= IN_SIMPLE_M || (apx && (crit & SSSP_IN_APPROX))) {
+    // stored full terms (dirty-set pass) for IN (full), OUTWEAK and OUT (full) in the plain kernels;
+    // the pass walks in-edges for the OUT terms
+    auto stores = [](int i, int o) { return i == IN_FULL_M || o == OUT_WEAK_M || o == OUT_FULL_M; };
+    const bool store = !learn && !trace_mode && !oracle && !apx && !delta_mode && (stores(in, out) || stores(in2, out2));
+    if (in_all >= IN_SIMPLE_M || (apx && (crit & SSSP_IN_APPROX)) || store) {
         int rc = graph_ensure_csc(g);
         if (rc) return rc;
     }
-    int rc = solve_bufs_ensure(g, dyn, delta_mode, queue_now || queue_later, apx != nullptr);
+    int rc = solve_bufs_ensure(g, dyn, delta_mode, queue_now || queue_later, apx != nullptr, store);
     if (rc) return rc;
     if (learn) n_deltas = 0;
     if (delta_mode && g->delta_cap < n_deltas) {
@@ -2517,6 +2758,8 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
     a.b.trace_cap = 0;
     a.crit = crit;
     a.approx_k = apx ? *apx : 0u;
+    a.mark = !learn && !trace_mode && !oracle && !apx && !delta_mode && stores(in, out);
+    a.fresh_at = 0;
     a.mlp_w = sel ? selector_device_weights(sel) : nullptr;
     a.wm = g->m ? (double)g->sum_w / (double)g->m : 1.0;
     a.ref = (const unsigned long long *)oracle_ref;
@@ -2582,6 +2825,8 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
                 if (rc == SSSP_OK && !h2.done) {
                     KArgs a3 = a2;
                     a3.crit = sw->crit_then;
+                    a3.mark = stores(in2, out2);
+                    a3.fresh_at = (uint32_t)k_next;
                     rc = run_loop(g, a3, pick_phase(g->cfg.chunk, in2, out2, false, false, false,
                                                     queue_fits),
                                   max_phases, k_next);
@@ -2615,6 +2860,8 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
             a2.crit = ckpt ? choice_criterion(choice) : sw->crit_then;
             int i2 = in2, o2 = out2;
             if (ckpt) crit_modes(a2.crit, &i2, &o2);
+            a2.mark = stores(i2, o2);
+            a2.fresh_at = (uint32_t)k_next;
             const bool q2 = queue_later;
             rc = run_loop(g, a2, pick_phase(g->cfg.chunk, i2, o2, false, false, false, q2), max_phases, k_next);
         }
