@@ -375,15 +375,27 @@ __device__ __forceinline__ uint32_t load_st4(const uint8_t *st, uint32_t q, uint
 // (one per grid step), the term and dirty-set passes take one per block.
 constexpr uint32_t kOwnSpan = 16 * kBlock;
 
-// Minimum weight of an out-edge of x towards a non-settled vertex, read-only
-// walk of x's weight-sorted row (x is unexplored, so no cursor owner exists).
-__device__ __forceinline__ unsigned long long walk_nonsettled(const KArgs &a, uint32_t x) {
+// Minimum weight of an out-edge of an unexplored x towards a non-settled vertex
+// (the inner minimum of eq. crit:out), from x's weight-sorted row and x's
+// monotone cursor out_cur (settled stays settled, so the cursor only moves past
+// settled ends; the OUT criteria that use it have no OUT-SIMPLE cursor of their
+// own). Threads evaluating neighbours of the same x in one pass may advance its
+// cursor together: each starts at or before the first edge to a non-settled
+// vertex, finds that same edge, and publishes it with atomicMax.
+__device__ __forceinline__ unsigned long long ns_cursor(const KArgs &a, uint32_t x) {
     const uint32_t end = a.g.rp[x + 1];
-    for (uint32_t c = a.g.rp[x]; c < end; ++c) {
+    const uint32_t c0 = a.b.out_cur[x];
+    uint32_t c = c0;
+    unsigned long long w = INF64;
+    for (; c < end; ++c) {
         const uint2 ed = a.g.edges[c];
-        if ((a.b.st[ed.x] & ST_SET) != ST_S) return ed.y;
+        if ((a.b.st[ed.x] & ST_SET) != ST_S) {
+            w = ed.y;
+            break;
+        }
     }
-    return INF64;
+    if (c != c0) atomicMax(&a.b.out_cur[x], c);
+    return w;
 }
 
 // SIMPLE terms (eq. crit:insimple, crit:outsimple): the weight of the lightest
@@ -452,7 +464,7 @@ __device__ __forceinline__ unsigned long long out_term(const KArgs &a, uint32_t 
         } else if (sx == ST_U) {
             // eq. crit:outweak: second edge over all of V; eq. crit:out: into F u U
             const unsigned long long second =
-                OUT == OUT_WEAK_M ? min_out64(a.g.vmin[ed.x].y, a.g.wmax, a.g.rp, ed.x) : walk_nonsettled(a, ed.x);
+                OUT == OUT_WEAK_M ? min_out64(a.g.vmin[ed.x].y, a.g.wmax, a.g.rp, ed.x) : ns_cursor(a, ed.x);
             term = umin64(term, sadd64(ed.y, second));
         }
     }
@@ -484,40 +496,97 @@ __device__ __forceinline__ bool vertex_terms(const KArgs &a, uint32_t v, unsigne
 //    rise, and that vertex is flagged ST_TDIRTY (computed in full by the term
 //    pass); elsewhere the minimum is unchanged;
 //  - OUT (full) only: a settled w may also raise, for an unexplored in-neighbour
-//    x, the lightest out-edge of x to a non-settled vertex, which enters the OUT
-//    term of every in-neighbour of x: those are flagged.
+//    x, the lightest out-edge of x to a non-settled vertex (ns_cursor), which
+//    enters the OUT term of every in-neighbour of x: when x's cursor points at an
+//    edge to w, those are flagged. Every stored OUT term that used x's value was
+//    computed with the cursor at that edge, and the cursor cannot move on before
+//    w settles, so the check sees it there.
 // Stored values of vertices that are not queued are never read (a vertex is
 // computed in full in the phase it is first queued, after this pass), so updates
-// that land on them are harmless. Rows are walked by the thread that found the
-// changed vertex; rows longer than kLongRow edges go to an LDS list that the
-// whole block walks (skewed degrees). All state writes here are atomic.
-constexpr uint32_t kLongRow = 128, kLongCap = 64;
+// that land on them are harmless. The changed vertices of a window go to an LDS
+// list whose rows the block walks together (below); all state writes here are
+// atomic.
+
+// Flattened row walk of a block's list of selected vertices (dirty-set and term
+// passes): entry j holds a vertex, a flag byte, its first in-edge (CSC) and
+// first out-edge (CSR) and how many of its in-edges are walked (n1) before its
+// out-edges; off[j] holds its edge count until row_list_scan turns the counts
+// into exclusive offsets (off[cnt] = total). Each thread then takes an equal
+// contiguous range of the total, so one long row is shared by the whole block
+// and many short ones do not leave threads idle.
+constexpr uint32_t kListCap = 512;
+
+struct RowList {
+    uint32_t v[kListCap], a0[kListCap], b0[kListCap], n1[kListCap], off[kListCap + 1];
+    uint8_t f[kListCap];
+    uint32_t cnt;
+    uint32_t wsum[kWaves];
+};
+
+// All threads; cnt <= kListCap entries with their counts in off[0 .. cnt).
+__device__ __forceinline__ void row_list_scan(RowList &L, uint32_t cnt) {
+    const uint32_t j0 = 2 * threadIdx.x;
+    const uint32_t l0 = j0 < cnt ? L.off[j0] : 0u, l1 = j0 + 1 < cnt ? L.off[j0 + 1] : 0u;
+    const uint32_t sum = l0 + l1;
+    const uint32_t incl = wave_incl_scan(sum);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 63) L.wsum[w] = incl;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) {
+        base += i < w ? L.wsum[i] : 0u;
+        tot += L.wsum[i];
+    }
+    const uint32_t ex = base + incl - sum;
+    if (j0 < cnt) L.off[j0] = ex;
+    if (j0 + 1 < cnt) L.off[j0 + 1] = ex + l0;
+    if (threadIdx.x == 0) L.off[cnt] = tot;
+    __syncthreads();
+}
+
+// This thread's contiguous range [e, end) of the list's edges and the entry j
+// holding edge e (the last entry whose offset is <= e).
+__device__ __forceinline__ void row_list_range(const RowList &L, uint32_t cnt, uint32_t &e, uint32_t &end,
+                                               uint32_t &j) {
+    const uint32_t T = L.off[cnt];
+    const uint32_t chunk = (T + kBlock - 1) / kBlock;
+    e = threadIdx.x * chunk;
+    end = e + chunk < T ? e + chunk : T;
+    uint32_t lo = 0, hi = cnt;  // off[lo] <= e < off[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (L.off[mid] <= e) lo = mid;
+        else hi = mid;
+    }
+    j = lo;
+}
 
 __device__ __forceinline__ void flag_state(uint8_t *st, uint32_t v, uint32_t f) {
     atomicOr(reinterpret_cast<uint32_t *>(st + (v & ~3u)), f << (8 * (v & 3u)));
 }
 
-template <bool IN_ON, int OUT_M>
-__device__ __forceinline__ void mark_row(const KArgs &a, uint32_t w, bool settled, bool out_dir, uint32_t lo,
-                                         uint32_t hi, uint32_t stride) {
-    if (!out_dir) {  // out-edges (w, v): the IN terms of the out-neighbours
-        for (uint32_t e = lo; e < hi; e += stride) {
-            const uint2 ed = a.g.edges[e];
-            if (!settled) atomicMin(&a.b.tin[ed.x], (unsigned long long)ed.y);
-            else if (a.b.tin[ed.x] == ed.y) flag_state(a.b.st, ed.x, ST_TDIRTY);
-        }
-    } else {  // in-edges (u, w): the OUT terms of the in-neighbours
-        for (uint32_t e = lo; e < hi; e += stride) {
-            const uint2 ie = a.g.in_edges[e];
-            if (!settled) {
-                atomicMin(&a.b.tout[ie.x], (unsigned long long)ie.y);
-            } else {
-                if (a.b.tout[ie.x] == ie.y) flag_state(a.b.st, ie.x, ST_TDIRTY);
-                if (OUT_M == OUT_FULL_M && (a.b.st[ie.x] & ST_SET) == ST_U) {
-                    const uint32_t end = a.g.ip[ie.x + 1];
-                    for (uint32_t f = a.g.ip[ie.x]; f < end; ++f) flag_state(a.b.st, a.g.in_edges[f].x, ST_TDIRTY);
-                }
-            }
+// Dirty-set updates along one out-edge (w, v) of a changed vertex w: the IN term of v.
+__device__ __forceinline__ void mark_out_edge(const KArgs &a, uint2 ed, bool settled) {
+    if (!settled) atomicMin(&a.b.tin[ed.x], (unsigned long long)ed.y);
+    else if (a.b.tin[ed.x] == ed.y) flag_state(a.b.st, ed.x, ST_TDIRTY);
+}
+
+// Dirty-set updates along one in-edge (u, w) of a changed vertex w: the OUT term of u.
+template <int OUT_M>
+__device__ __forceinline__ void mark_in_edge(const KArgs &a, uint2 ie, bool settled, uint32_t w) {
+    if (!settled) {
+        atomicMin(&a.b.tout[ie.x], (unsigned long long)ie.y);
+        return;
+    }
+    if (a.b.tout[ie.x] == ie.y) flag_state(a.b.st, ie.x, ST_TDIRTY);
+    if (OUT_M == OUT_FULL_M && (a.b.st[ie.x] & ST_SET) == ST_U) {
+        // the lightest non-settled out-edge of the unexplored in-neighbour x rises only if
+        // x's cursor points at an edge to w; then every in-neighbour of x is flagged
+        const uint32_t c = a.b.out_cur[ie.x];
+        if (c < a.g.rp[ie.x + 1] && a.g.edges[c].x == w) {
+            const uint32_t end = a.g.ip[ie.x + 1];
+            for (uint32_t f = a.g.ip[ie.x]; f < end; ++f) flag_state(a.b.st, a.g.in_edges[f].x, ST_TDIRTY);
         }
     }
 }
@@ -525,7 +594,7 @@ __device__ __forceinline__ void mark_row(const KArgs &a, uint32_t w, bool settle
 template <bool IN_ON, int OUT_M>
 __global__ __launch_bounds__(kBlock) void k_mark(KArgs a, int par) {
     __shared__ uint4 s_st[kOwnSpan / 16];
-    __shared__ uint32_t s_long[kLongCap], s_nlong;
+    __shared__ RowList L;
     Ctl *ctl = a.b.ctl;
     const unsigned long long r0 = lane_slot(ctl->reached, 0ull);
     const unsigned long long settled_cnt = ctl->h.settled;
@@ -546,7 +615,7 @@ __global__ __launch_bounds__(kBlock) void k_mark(KArgs a, int par) {
         const bool any = ((x.x | x.y | x.z | x.w) & 0x80808080u) != 0;
         __syncthreads();  // the previous window's LDS reads are done
         s_st[threadIdx.x] = x;
-        if (threadIdx.x == 0) s_nlong = 0;
+        if (threadIdx.x == 0) L.cnt = 0;
         if (!__syncthreads_or(any)) continue;  // block-uniform
         for (uint32_t r = 0; r < kOwnSpan / kBlock; ++r) {
             const uint32_t i = r * kBlock + threadIdx.x;
@@ -555,25 +624,35 @@ __global__ __launch_bounds__(kBlock) void k_mark(KArgs a, int par) {
             const uint32_t w = (uint32_t)vb + i;
             atomicAnd(reinterpret_cast<uint32_t *>(a.b.st + (w & ~3u)), ~((uint32_t)ST_CHG << (8 * (w & 3u))));
             const bool sett = (sb & ST_SET) == ST_S;
-            const uint32_t ob = a.g.rp[w], oe = a.g.rp[w + 1];
+            const uint32_t ob = IN_ON ? a.g.rp[w] : 0u, oe = IN_ON ? a.g.rp[w + 1] : 0u;
             const uint32_t ib = OUT_M ? a.g.ip[w] : 0u, ie = OUT_M ? a.g.ip[w + 1] : 0u;
-            if ((IN_ON ? oe - ob : 0u) + (ie - ib) > kLongRow) {
-                const uint32_t k = atomicAdd(&s_nlong, 1u);
-                if (k < kLongCap) {
-                    s_long[k] = w;
-                    continue;
-                }
+            const uint32_t len = (oe - ob) + (ie - ib);
+            if (len == 0) continue;
+            const uint32_t j = atomicAdd(&L.cnt, 1u);
+            if (j < kListCap) {
+                L.v[j] = w;
+                L.f[j] = sett ? 1 : 0;
+                L.a0[j] = ib;
+                L.b0[j] = ob;
+                L.n1[j] = oe - ob;  // the out-edges first
+                L.off[j] = len;
+                continue;
             }
-            if (IN_ON) mark_row<IN_ON, OUT_M>(a, w, sett, false, ob, oe, 1);
-            if (OUT_M) mark_row<IN_ON, OUT_M>(a, w, sett, true, ib, ie, 1);
+            for (uint32_t e = ob; e < oe; ++e) mark_out_edge(a, a.g.edges[e], sett);  // list full
+            for (uint32_t e = ib; e < ie; ++e) mark_in_edge<OUT_M>(a, a.g.in_edges[e], sett, w);
         }
         __syncthreads();
-        const uint32_t nl = s_nlong < kLongCap ? s_nlong : kLongCap;
-        for (uint32_t k = 0; k < nl; ++k) {  // block-uniform: the long rows, all threads per row
-            const uint32_t w = s_long[k];
-            const bool sett = (sw[w - (uint32_t)vb] & ST_SET) == ST_S;
-            if (IN_ON) mark_row<IN_ON, OUT_M>(a, w, sett, false, a.g.rp[w] + threadIdx.x, a.g.rp[w + 1], kBlock);
-            if (OUT_M) mark_row<IN_ON, OUT_M>(a, w, sett, true, a.g.ip[w] + threadIdx.x, a.g.ip[w + 1], kBlock);
+        const uint32_t cnt = L.cnt < kListCap ? L.cnt : kListCap;
+        if (cnt == 0) continue;  // block-uniform
+        row_list_scan(L, cnt);
+        uint32_t e, end, j;
+        row_list_range(L, cnt, e, end, j);
+        for (; e < end; ++e) {
+            while (e >= L.off[j + 1]) ++j;
+            const uint32_t k = e - L.off[j];
+            const bool sett = L.f[j] != 0;
+            if (k < L.n1[j]) mark_out_edge(a, a.g.edges[L.b0[j] + k], sett);
+            else mark_in_edge<OUT_M>(a, a.g.in_edges[L.a0[j] + (k - L.n1[j])], sett, L.v[j]);
         }
     }
 }
@@ -1320,15 +1399,17 @@ __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
 template <int IN, int OUT>
 __global__ __launch_bounds__(kBlock) void k_terms_win(KArgs a, int par) {
     constexpr bool kStoreIn = IN == IN_FULL_M, kStoreOut = OUT == OUT_WEAK_M || OUT == OUT_FULL_M;
+    constexpr bool kStore = kStoreIn || kStoreOut;
     __shared__ unsigned long long sh[8 * kWaves];
     __shared__ uint4 s_st[kOwnSpan / 16];
-    __shared__ uint32_t s_long[kLongCap], s_nlong;
-    __shared__ unsigned long long s_red[2][kWaves];
+    // stored terms: the vertices computed in full in this window, and their minima
+    __shared__ RowList L;
+    __shared__ unsigned long long s_ti[kStore ? kListCap : 1], s_to[kStore ? kListCap : 1];
     Ctl *ctl = a.b.ctl;
     const int p3 = par % 3;
     const unsigned long long r0 = lane_slot(ctl->reached, 0ull), m0 = lane_slot(ctl->minD[p3], INF64);
     const unsigned long long settled = ctl->h.settled;
-    const bool fresh_all = (kStoreIn || kStoreOut) && ctl->h.pnum[par & 1] == a.fresh_at;
+    const bool fresh_all = kStore && ctl->h.pnum[par & 1] == a.fresh_at;
     const uint32_t n = a.g.n;
     auto load16 = [&](uint64_t v0) {
         if (v0 + 16 <= n) return *reinterpret_cast<const uint4 *>(a.b.st + v0);
@@ -1344,7 +1425,7 @@ __global__ __launch_bounds__(kBlock) void k_terms_win(KArgs a, int par) {
     const unsigned long long minD = wave_min64(m0);
     const uint8_t *sw = reinterpret_cast<const uint8_t *>(s_st);
     unsigned long long tmin = INF64;
-    // the terms of v from the full (or stored) values ti / to: the IN flag, the OUT fold, the state byte
+    // the phase's result for v from its terms ti / to: the IN flag, the OUT fold, the state byte
     auto finish = [&](uint32_t v, uint32_t sb, unsigned long long dv, unsigned long long ti, unsigned long long to) {
         bool ok = false;
         if (IN != IN_NONE) ok = dv <= sadd64(minD, ti);
@@ -1359,8 +1440,8 @@ __global__ __launch_bounds__(kBlock) void k_terms_win(KArgs a, int par) {
         for (int j = 0; j < 16; ++j) any |= ((xs[j >> 2] >> (8 * (j & 3))) & ST_SET) == ST_F;
         __syncthreads();  // the previous window's LDS reads are done
         s_st[threadIdx.x] = x;
-        if (threadIdx.x == 0) s_nlong = 0;
-        if (__syncthreads_or(any)) {
+        if (kStore && threadIdx.x == 0) L.cnt = 0;
+        if (__syncthreads_or(any)) {  // block-uniform
 #pragma unroll 2
             for (uint32_t r = 0; r < kOwnSpan / kBlock; ++r) {
                 const uint32_t i = r * kBlock + threadIdx.x;
@@ -1368,16 +1449,21 @@ __global__ __launch_bounds__(kBlock) void k_terms_win(KArgs a, int par) {
                 if ((sb & ST_SET) != ST_F) continue;
                 const uint32_t v = (uint32_t)vb + i;
                 const bool full = fresh_all || (sb & ST_TDIRTY) != 0;
-                if ((kStoreIn || kStoreOut) && full) {
-                    // a long row is scanned by the whole block after this window's rounds
-                    const uint32_t deg = (kStoreIn ? a.g.ip[v + 1] - a.g.ip[v] : 0u) +
-                                         (kStoreOut ? a.g.rp[v + 1] - a.g.rp[v] : 0u);
-                    if (deg > kLongRow) {
-                        const uint32_t k = atomicAdd(&s_nlong, 1u);
-                        if (k < kLongCap) {
-                            s_long[k] = v;
-                            continue;
-                        }
+                if (kStore && full) {
+                    // computed in full by the block's flattened walk below, unless the list is full
+                    const uint32_t ib = kStoreIn ? a.g.ip[v] : 0u, ie = kStoreIn ? a.g.ip[v + 1] : 0u;
+                    const uint32_t ob = kStoreOut ? a.g.rp[v] : 0u, oe = kStoreOut ? a.g.rp[v + 1] : 0u;
+                    const uint32_t j = atomicAdd(&L.cnt, 1u);
+                    if (j < kListCap) {
+                        L.v[j] = v;
+                        L.f[j] = (uint8_t)sb;
+                        L.a0[j] = ib;
+                        L.b0[j] = ob;
+                        L.n1[j] = ie - ib;  // the in-edges first
+                        L.off[j] = (ie - ib) + (oe - ob);
+                        s_ti[j] = INF64;
+                        s_to[j] = INF64;
+                        continue;
                     }
                 }
                 const unsigned long long dv = a.b.dist[v];
@@ -1401,55 +1487,49 @@ __global__ __launch_bounds__(kBlock) void k_terms_win(KArgs a, int par) {
                 finish(v, sb, dv, ti, to);
             }
         }
-        if (kStoreIn || kStoreOut) {
-            __syncthreads();  // the long-row list is complete
-            const uint32_t nl = s_nlong < kLongCap ? s_nlong : kLongCap;
-            for (uint32_t k = 0; k < nl; ++k) {  // block-uniform
-                const uint32_t v = s_long[k];
-                unsigned long long ti = INF64, to = INF64;
-                if (kStoreIn) {
-                    const uint32_t end = a.g.ip[v + 1];
-                    for (uint32_t e = a.g.ip[v] + threadIdx.x; e < end; e += kBlock) {
-                        const uint2 ie = a.g.in_edges[e];
+        if (kStore) {
+            __syncthreads();  // the list is complete
+            const uint32_t cnt = L.cnt < kListCap ? L.cnt : kListCap;
+            if (cnt) {  // block-uniform
+                row_list_scan(L, cnt);
+                uint32_t e, end, j;
+                row_list_range(L, cnt, e, end, j);
+                for (; e < end; ++e) {
+                    while (e >= L.off[j + 1]) ++j;
+                    const uint32_t k = e - L.off[j];
+                    if (kStoreIn && k < L.n1[j]) {
+                        // eq. crit:in: in-edges from F, or from w in U plus w's lightest in-edge
+                        const uint2 ie = a.g.in_edges[L.a0[j] + k];
                         const uint8_t s2 = a.b.st[ie.x] & ST_SET;
-                        if (s2 == ST_F) ti = umin64(ti, ie.y);
-                        else if (s2 == ST_U) ti = umin64(ti, sadd64(ie.y, min_in_u64(a.g.vmin[ie.x].x, a.g.wmax, a.g.ip, ie.x)));
-                    }
-                }
-                if (kStoreOut) {
-                    const uint32_t end = a.g.rp[v + 1];
-                    for (uint32_t e = a.g.rp[v] + threadIdx.x; e < end; e += kBlock) {
-                        const uint2 ed = a.g.edges[e];
+                        unsigned long long c = INF64;
+                        if (s2 == ST_F) c = ie.y;
+                        else if (s2 == ST_U) c = sadd64(ie.y, min_in_u64(a.g.vmin[ie.x].x, a.g.wmax, a.g.ip, ie.x));
+                        if (c != INF64) atomicMin(&s_ti[j], c);
+                    } else if (kStoreOut) {
+                        // eq. crit:outweak / crit:out: out-edges into F, or into w in U plus w's second edge
+                        const uint2 ed = a.g.edges[L.b0[j] + (k - L.n1[j])];
                         const uint8_t s2 = a.b.st[ed.x] & ST_SET;
+                        unsigned long long c = INF64;
                         if (s2 == ST_F) {
-                            to = umin64(to, ed.y);
+                            c = ed.y;
                         } else if (s2 == ST_U) {
-                            const unsigned long long second = OUT == OUT_WEAK_M
-                                ? min_out64(a.g.vmin[ed.x].y, a.g.wmax, a.g.rp, ed.x) : walk_nonsettled(a, ed.x);
-                            to = umin64(to, sadd64(ed.y, second));
+                            c = sadd64(ed.y, OUT == OUT_WEAK_M ? min_out64(a.g.vmin[ed.x].y, a.g.wmax, a.g.rp, ed.x)
+                                                               : ns_cursor(a, ed.x));
                         }
+                        if (c != INF64) atomicMin(&s_to[j], c);
                     }
                 }
-                ti = wave_min64(ti);
-                to = wave_min64(to);
-                if ((threadIdx.x & 63) == 0) {
-                    s_red[0][threadIdx.x >> 6] = ti;
-                    s_red[1][threadIdx.x >> 6] = to;
-                }
-                __syncthreads();
-                if (threadIdx.x == 0) {
-                    for (int w = 1; w < kWaves; ++w) {
-                        ti = umin64(ti, s_red[0][w]);
-                        to = umin64(to, s_red[1][w]);
-                    }
+                __syncthreads();  // the minima are complete
+                for (uint32_t q = threadIdx.x; q < cnt; q += kBlock) {
+                    const uint32_t v = L.v[q];
+                    unsigned long long ti = s_ti[q], to = s_to[q];
                     // the other side of a mixed criterion (a SIMPLE cursor) by this thread
                     if (IN != IN_NONE && !kStoreIn) ti = in_term<IN>(a, v);
                     if (OUT != OUT_NONE && !kStoreOut) to = out_term<OUT>(a, v);
                     if (kStoreIn) a.b.tin[v] = ti;
                     if (kStoreOut) a.b.tout[v] = to;
-                    finish(v, sw[v - (uint32_t)vb], a.b.dist[v], ti, to);
+                    finish(v, L.f[q], a.b.dist[v], ti, to);
                 }
-                __syncthreads();  // s_red is rewritten by the next long row
             }
         }
         if (vb + step < n) x = load16(vb + step + 16u * threadIdx.x);
