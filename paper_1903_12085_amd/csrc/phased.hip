@@ -497,10 +497,11 @@ __device__ __forceinline__ bool vertex_terms(const KArgs &a, uint32_t v, unsigne
 //    pass); elsewhere the minimum is unchanged;
 //  - OUT (full) only: a settled w may also raise, for an unexplored in-neighbour
 //    x, the lightest out-edge of x to a non-settled vertex (ns_cursor), which
-//    enters the OUT term of every in-neighbour of x: when x's cursor points at an
-//    edge to w, those are flagged. Every stored OUT term that used x's value was
-//    computed with the cursor at that edge, and the cursor cannot move on before
-//    w settles, so the check sees it there.
+//    enters the OUT term of every in-neighbour z of x as c(z, x) + that weight:
+//    when x's cursor points at an edge to w, each z whose stored term equals its
+//    candidate through x is flagged. Every stored OUT term that used x's value
+//    was computed with the cursor at that edge, and the cursor cannot move on
+//    before w settles, so the check sees it there.
 // Stored values of vertices that are not queued are never read (a vertex is
 // computed in full in the phase it is first queued, after this pass), so updates
 // that land on them are harmless. The changed vertices of a window go to an LDS
@@ -573,8 +574,13 @@ __device__ __forceinline__ void mark_out_edge(const KArgs &a, uint2 ed, bool set
 }
 
 // Dirty-set updates along one in-edge (u, w) of a changed vertex w: the OUT term of u.
+// OUT (full): for an unexplored u whose cursor points at an edge (u, w) to the settled
+// w, the candidate c(z, u) + c(u, w) of each in-neighbour z may rise: z is flagged
+// where its stored OUT term equals that candidate. The in-row of u goes to the
+// block's second list L2 (walked together after the first), or is walked here when
+// L2 is full.
 template <int OUT_M>
-__device__ __forceinline__ void mark_in_edge(const KArgs &a, uint2 ie, bool settled, uint32_t w) {
+__device__ __forceinline__ void mark_in_edge(const KArgs &a, uint2 ie, bool settled, uint32_t w, RowList *L2) {
     if (!settled) {
         atomicMin(&a.b.tout[ie.x], (unsigned long long)ie.y);
         return;
@@ -584,9 +590,22 @@ __device__ __forceinline__ void mark_in_edge(const KArgs &a, uint2 ie, bool sett
         // the lightest non-settled out-edge of the unexplored in-neighbour x rises only if
         // x's cursor points at an edge to w; then every in-neighbour of x is flagged
         const uint32_t c = a.b.out_cur[ie.x];
-        if (c < a.g.rp[ie.x + 1] && a.g.edges[c].x == w) {
-            const uint32_t end = a.g.ip[ie.x + 1];
-            for (uint32_t f = a.g.ip[ie.x]; f < end; ++f) flag_state(a.b.st, a.g.in_edges[f].x, ST_TDIRTY);
+        if (c < a.g.rp[ie.x + 1]) {
+            const uint2 ce = a.g.edges[c];
+            if (ce.x != w) return;
+            const uint32_t b = a.g.ip[ie.x], end = a.g.ip[ie.x + 1];
+            if (b == end) return;
+            const uint32_t j = atomicAdd(&L2->cnt, 1u);
+            if (j < kListCap) {
+                L2->a0[j] = b;
+                L2->b0[j] = ce.y;
+                L2->off[j] = end - b;
+                return;
+            }
+            for (uint32_t f = b; f < end; ++f) {
+                const uint2 ze = a.g.in_edges[f];
+                if (a.b.tout[ze.x] == (unsigned long long)ze.y + ce.y) flag_state(a.b.st, ze.x, ST_TDIRTY);
+            }
         }
     }
 }
@@ -595,6 +614,7 @@ template <bool IN_ON, int OUT_M>
 __global__ __launch_bounds__(kBlock) void k_mark(KArgs a, int par) {
     __shared__ uint4 s_st[kOwnSpan / 16];
     __shared__ RowList L;
+    __shared__ RowList L2[1];  // OUT (full): in-rows to flag
     Ctl *ctl = a.b.ctl;
     const unsigned long long r0 = lane_slot(ctl->reached, 0ull);
     const unsigned long long settled_cnt = ctl->h.settled;
@@ -615,7 +635,10 @@ __global__ __launch_bounds__(kBlock) void k_mark(KArgs a, int par) {
         const bool any = ((x.x | x.y | x.z | x.w) & 0x80808080u) != 0;
         __syncthreads();  // the previous window's LDS reads are done
         s_st[threadIdx.x] = x;
-        if (threadIdx.x == 0) L.cnt = 0;
+        if (threadIdx.x == 0) {
+            L.cnt = 0;
+            if (OUT_M == OUT_FULL_M) L2[0].cnt = 0;
+        }
         if (!__syncthreads_or(any)) continue;  // block-uniform
         for (uint32_t r = 0; r < kOwnSpan / kBlock; ++r) {
             const uint32_t i = r * kBlock + threadIdx.x;
@@ -639,20 +662,53 @@ __global__ __launch_bounds__(kBlock) void k_mark(KArgs a, int par) {
                 continue;
             }
             for (uint32_t e = ob; e < oe; ++e) mark_out_edge(a, a.g.edges[e], sett);  // list full
-            for (uint32_t e = ib; e < ie; ++e) mark_in_edge<OUT_M>(a, a.g.in_edges[e], sett, w);
+            for (uint32_t e = ib; e < ie; ++e) mark_in_edge<OUT_M>(a, a.g.in_edges[e], sett, w, &L2[0]);
         }
         __syncthreads();
         const uint32_t cnt = L.cnt < kListCap ? L.cnt : kListCap;
-        if (cnt == 0) continue;  // block-uniform
-        row_list_scan(L, cnt);
-        uint32_t e, end, j;
-        row_list_range(L, cnt, e, end, j);
-        for (; e < end; ++e) {
-            while (e >= L.off[j + 1]) ++j;
-            const uint32_t k = e - L.off[j];
-            const bool sett = L.f[j] != 0;
-            if (k < L.n1[j]) mark_out_edge(a, a.g.edges[L.b0[j] + k], sett);
-            else mark_in_edge<OUT_M>(a, a.g.in_edges[L.a0[j] + (k - L.n1[j])], sett, L.v[j]);
+        if (cnt) {  // block-uniform
+            row_list_scan(L, cnt);
+            uint32_t e, end, j;
+            row_list_range(L, cnt, e, end, j);
+            for (; e < end; e += 4) {  // four edges at a time, their loads issued together
+                uint32_t jq[4];
+                bool outq[4];
+                uint2 eq[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    jq[q] = kListCap;
+                    outq[q] = false;
+                    eq[q] = make_uint2(0u, 0u);
+                    if (e + q < end) {
+                        while (e + q >= L.off[j + 1]) ++j;
+                        const uint32_t k = e + q - L.off[j];
+                        jq[q] = j;
+                        outq[q] = k < L.n1[j];
+                        eq[q] = outq[q] ? a.g.edges[L.b0[j] + k] : a.g.in_edges[L.a0[j] + (k - L.n1[j])];
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (jq[q] == kListCap) continue;
+                    const bool sett = L.f[jq[q]] != 0;
+                    if (outq[q]) mark_out_edge(a, eq[q], sett);
+                    else mark_in_edge<OUT_M>(a, eq[q], sett, L.v[jq[q]], &L2[0]);
+                }
+            }
+        }
+        if (OUT_M == OUT_FULL_M) {  // the in-rows collected in L2, walked together
+            __syncthreads();
+            const uint32_t cnt2 = L2[0].cnt < kListCap ? L2[0].cnt : kListCap;
+            if (cnt2) {  // block-uniform
+                row_list_scan(L2[0], cnt2);
+                uint32_t e, end, j;
+                row_list_range(L2[0], cnt2, e, end, j);
+                for (; e < end; ++e) {
+                    while (e >= L2[0].off[j + 1]) ++j;
+                    const uint2 ze = a.g.in_edges[L2[0].a0[j] + (e - L2[0].off[j])];
+                    if (a.b.tout[ze.x] == (unsigned long long)ze.y + L2[0].b0[j]) flag_state(a.b.st, ze.x, ST_TDIRTY);
+                }
+            }
         }
     }
 }
@@ -1494,29 +1550,43 @@ __global__ __launch_bounds__(kBlock) void k_terms_win(KArgs a, int par) {
                 row_list_scan(L, cnt);
                 uint32_t e, end, j;
                 row_list_range(L, cnt, e, end, j);
-                for (; e < end; ++e) {
-                    while (e >= L.off[j + 1]) ++j;
-                    const uint32_t k = e - L.off[j];
-                    if (kStoreIn && k < L.n1[j]) {
-                        // eq. crit:in: in-edges from F, or from w in U plus w's lightest in-edge
-                        const uint2 ie = a.g.in_edges[L.a0[j] + k];
-                        const uint8_t s2 = a.b.st[ie.x] & ST_SET;
-                        unsigned long long c = INF64;
-                        if (s2 == ST_F) c = ie.y;
-                        else if (s2 == ST_U) c = sadd64(ie.y, min_in_u64(a.g.vmin[ie.x].x, a.g.wmax, a.g.ip, ie.x));
-                        if (c != INF64) atomicMin(&s_ti[j], c);
-                    } else if (kStoreOut) {
-                        // eq. crit:outweak / crit:out: out-edges into F, or into w in U plus w's second edge
-                        const uint2 ed = a.g.edges[L.b0[j] + (k - L.n1[j])];
-                        const uint8_t s2 = a.b.st[ed.x] & ST_SET;
-                        unsigned long long c = INF64;
-                        if (s2 == ST_F) {
-                            c = ed.y;
-                        } else if (s2 == ST_U) {
-                            c = sadd64(ed.y, OUT == OUT_WEAK_M ? min_out64(a.g.vmin[ed.x].y, a.g.wmax, a.g.rp, ed.x)
-                                                               : ns_cursor(a, ed.x));
+                // four edges at a time: their loads are issued together (the walk is a chain of
+                // dependent loads per edge: edge, end's state, end's minimum or cursor)
+                for (; e < end; e += 4) {
+                    uint32_t jq[4];
+                    bool inq[4];
+                    uint2 eq[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        jq[q] = kListCap;
+                        inq[q] = false;
+                        eq[q] = make_uint2(0u, 0u);
+                        if (e + q < end) {
+                            while (e + q >= L.off[j + 1]) ++j;
+                            const uint32_t k = e + q - L.off[j];
+                            jq[q] = j;
+                            inq[q] = kStoreIn && k < L.n1[j];
+                            eq[q] = inq[q] ? a.g.in_edges[L.a0[j] + k] : a.g.edges[L.b0[j] + (k - L.n1[j])];
                         }
-                        if (c != INF64) atomicMin(&s_to[j], c);
+                    }
+                    uint32_t sq[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) sq[q] = jq[q] < kListCap ? (a.b.st[eq[q].x] & ST_SET) : (uint32_t)ST_S;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        if (sq[q] == ST_S) continue;  // settled end (or no edge): no candidate
+                        unsigned long long c = eq[q].y;
+                        if (inq[q]) {
+                            // eq. crit:in: in-edges from F, or from w in U plus w's lightest in-edge
+                            if (sq[q] == ST_U) c = sadd64(c, min_in_u64(a.g.vmin[eq[q].x].x, a.g.wmax, a.g.ip, eq[q].x));
+                            atomicMin(&s_ti[jq[q]], c);
+                        } else if (kStoreOut) {
+                            // eq. crit:outweak / crit:out: out-edges into F, or into w in U plus w's second edge
+                            if (sq[q] == ST_U)
+                                c = sadd64(c, OUT == OUT_WEAK_M ? min_out64(a.g.vmin[eq[q].x].y, a.g.wmax, a.g.rp, eq[q].x)
+                                                                : ns_cursor(a, eq[q].x));
+                            atomicMin(&s_to[jq[q]], c);
+                        }
                     }
                 }
                 __syncthreads();  // the minima are complete
