@@ -176,12 +176,23 @@ int sssp_delta_step_ex(sssp_graph *g, uint32_t source, const uint64_t *deltas, u
 int sssp_solve_batch(sssp_graph *const *graphs, const uint32_t *sources, uint32_t nq,
                      uint32_t criterion, uint64_t *const *dist_outs, uint32_t *phases_out);
 
-/* Launch shape of the batched solver. A zero field means the default. */
+/* Launch shape of the batched solver. A zero field means the default.
+ * Queries on graphs with at least team_edges edges each run on a team of
+ * team_size workgroups that share its fringe and settled lists and meet at a
+ * barrier twice per phase, while the other resident workgroups take the other
+ * queries one per workgroup, all in one cooperative launch (so every member is
+ * resident; a member that waits longer than a bounded spin sets the error and
+ * the call returns SSSP_ERR_INTERNAL). */
 typedef struct {
-    uint32_t block;   /* threads per workgroup: 256, 512 or 1024 (default 512) */
-    uint32_t split;   /* rows with more out-edges than this are expanded by the whole
-                         workgroup instead of one lane (default 64) */
-    uint32_t blocks;  /* workgroups of the persistent launch (default 4 per compute unit) */
+    uint32_t block;      /* threads per workgroup: 256, 512 or 1024 (default 512) */
+    uint32_t split;      /* rows with more out-edges than this are expanded by the whole
+                            workgroup instead of one lane (default 64) */
+    uint32_t blocks;     /* workgroups of the persistent launch (default 4 per compute unit) */
+    uint32_t team_edges; /* edge count from which a query gets a team (default 2^20;
+                            UINT32_MAX: no teams) */
+    uint32_t team_size;  /* workgroups per team: 2 .. 64 (default: the largest power of two
+                            <= 16 that keeps the teams within half of the resident
+                            workgroups; more large queries than teams are taken in turn) */
 } sssp_batch_cfg;
 
 /* sssp_solve_batch with an explicit launch shape (cfg may be NULL: defaults). */
@@ -298,7 +309,7 @@ int sssp_set_launch(sssp_graph *g, const sssp_launch_cfg *cfg);
 /*
  * Autotuner for the plain solver: times sssp_solve(g, source, criterion) with
  * HIP events for a set of launch shapes (scan grid, relax grid, chunk size,
- * graph replay; for static criteria also the dense scan, queue arrays, keyed
+ * graph replay, the dense scan or queue arrays; for static criteria also keyed
  * queue arrays and the one-workgroup option), keeps the fastest on g and
  * returns it in best (may be NULL)
  * with its time in best_ms (may be NULL). Distances are never affected.
@@ -308,7 +319,8 @@ int sssp_autotune(sssp_graph *g, uint32_t source, uint32_t criterion, sssp_launc
 
 /*
  * Autotuner for the batched solver: times the batch for workgroup sizes,
- * degree-split thresholds and workgroup counts, makes the fastest the
+ * degree-split thresholds, workgroup counts and team thresholds (no teams,
+ * 2^20 or 2^22 edges, automatic team size), makes the fastest the
  * process-wide default and returns it. dist_outs are overwritten with the
  * batch's distances.
  */

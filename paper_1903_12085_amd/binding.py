@@ -72,7 +72,8 @@ class LaunchCfg(ctypes.Structure):
 
 
 class BatchCfg(ctypes.Structure):
-    _fields_ = [("block", ctypes.c_uint32), ("split", ctypes.c_uint32), ("blocks", ctypes.c_uint32)]
+    _fields_ = [("block", ctypes.c_uint32), ("split", ctypes.c_uint32), ("blocks", ctypes.c_uint32),
+                ("team_edges", ctypes.c_uint32), ("team_size", ctypes.c_uint32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

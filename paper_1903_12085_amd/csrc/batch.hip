@@ -59,6 +59,13 @@ __device__ __forceinline__ uint8_t ld_st(const uint8_t *p) {
 __device__ __forceinline__ uint32_t ld_u32(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Stores of values another workgroup of a team reads (team launch only): device-scope
+// atomic stores, which do not stay in one die's L2, so that a team barrier only has to
+// wait for its own stores to complete (no cache write-back).
+template <typename T>
+__device__ __forceinline__ void st_dev(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // Workgroup minima of a and b in one LDS round with one barrier. The caller
 // writes sh again only after at least one more barrier (the next phase's),
@@ -83,6 +90,7 @@ __device__ __forceinline__ void bmin2(unsigned long long &a, unsigned long long 
 
 // Wavefront-aggregated append of v to a list whose length is the LDS counter
 // *cnt: one LDS atomic by the lowest taking lane, which is always active.
+template <bool TEAM = false>
 __device__ __forceinline__ void wave_append(bool take, uint32_t v, uint32_t *list, uint32_t *cnt) {
     const int lane = threadIdx.x & 63;
     const unsigned long long mask = __ballot(take);
@@ -91,14 +99,17 @@ __device__ __forceinline__ void wave_append(bool take, uint32_t v, uint32_t *lis
     uint32_t base = 0;
     if (lane == leader) base = atomicAdd(cnt, (uint32_t)__popcll(mask));
     base = __shfl(base, leader, 64);
-    if (take) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = v;
+    if (!take) return;
+    uint32_t *slot = &list[base + __popcll(mask & ((1ull << lane) - 1ull))];
+    if (TEAM) st_dev(slot, v);
+    else *slot = v;
 }
 
 // Relaxes the edges ed[j] (bit j of have) from a vertex at distance du: the
 // state and distance loads of all of them are issued together, then the
 // atomics. Returns the mask of edges whose atomic replaced infinity (the
 // target was discovered; exactly one atomic can do that).
-template <int U, bool OUT>
+template <int U, bool OUT, bool TEAM = false>
 __device__ __forceinline__ uint32_t relax_edges(const BatchQuery &q, unsigned long long du, const uint2 *ed,
                                                 const uint32_t *em, uint32_t have, unsigned long long &cmin,
                                                 unsigned long long &ctst) {
@@ -131,7 +142,8 @@ __device__ __forceinline__ uint32_t relax_edges(const BatchQuery &q, unsigned lo
         cmin = umin64(cmin, cand[j]);
         if (OUT) ctst = umin64(ctst, sadd64(cand[j], min_out64(em[j], q.wmax, q.rp, ed[j].x)));
         if (old[j] == INF64) {
-            q.st[ed[j].x] = ST_F;
+            if (TEAM) st_dev(&q.st[ed[j].x], (uint8_t)ST_F);
+            else q.st[ed[j].x] = ST_F;
             disc |= 1u << j;
         }
     }
@@ -140,11 +152,12 @@ __device__ __forceinline__ uint32_t relax_edges(const BatchQuery &q, unsigned lo
 
 constexpr int kBatchU = 4;  // fringe entries / edges a lane handles per step
 
+// One workgroup per query, queries taken from order[0 .. nq) through ctl->next.
 // IN: IN_NONE, IN_DIJK or IN_STATIC_M; OUT: OUT-STATIC on/off.
 template <int BS, int IN, bool OUT>
-__global__ __launch_bounds__(BS) void k_batch(const BatchQuery *__restrict__ queries, const uint32_t *__restrict__ order,
-                                              uint32_t nq, BatchCtl *ctl, uint32_t *__restrict__ phases_out,
-                                              uint32_t split) {
+__device__ __forceinline__ void batch_single(const BatchQuery *__restrict__ queries, const uint32_t *__restrict__ order,
+                                             uint32_t nq, BatchCtl *ctl, uint32_t *__restrict__ phases_out,
+                                             uint32_t split) {
     __shared__ unsigned long long sh[2 * (BS / 64)];
     __shared__ uint32_t s_q;
     __shared__ uint32_t hub_v[kHubCap];
@@ -314,6 +327,275 @@ __global__ __launch_bounds__(BS) void k_batch(const BatchQuery *__restrict__ que
     }
 }
 
+// ---------------------------------------------------------------------------
+// Large queries: a team of W workgroups per query (one cooperative launch, so
+// that every member is resident while the others wait for it).
+//
+// The team runs the same phase loop with the query's lists shared: member m
+// takes the fringe entries and settled vertices m, m + W, ... (in steps of a
+// workgroup's width), appends to the shared lists through the team's global
+// counters (one atomic per wavefront) and folds its minima into the team's
+// slots, and the team meets at a barrier after identify and after relax. Lists
+// and counters are double-buffered by phase parity as in the one-workgroup
+// kernel: the slots of phase p + 1 are cleared by member 0 after phase p's first
+// barrier, when every member has read them for the last time.
+// Every value one member writes and another reads (distances, states, list
+// entries, counters, minima) is written with device-scope atomics (st_dev,
+// atomicAdd, atomicMin) and read with device-scope loads (ld_*), so the
+// barrier needs no cache write-back or invalidation: each thread waits for its
+// own memory operations to complete, then the member's thread 0 adds one to
+// the team's arrival counter and waits until it reaches W times the barrier's
+// index. The wait is bounded: past kTeamSpin polls, or once another member has
+// failed, the member sets the error and leaves, so a kernel whose members could
+// not all run ends instead of hanging.
+
+struct TeamCtl {
+    unsigned int bar;                   // arrivals (monotone over the launch)
+    unsigned int pad;
+    unsigned int nset[2], nnext[2];     // S' and next-fringe lengths by phase parity
+    unsigned long long fmin[2], ftst[2];// next minD / OUT-STATIC threshold by phase parity
+};
+
+constexpr unsigned long long kTeamSpin = 1ull << 22;
+
+// All threads of the member; false if the team failed (the caller leaves).
+__device__ __forceinline__ bool team_barrier(TeamCtl *tc, uint32_t W, uint32_t &arrivals, BatchCtl *ctl,
+                                             int *s_ok) {
+    __builtin_amdgcn_s_waitcnt(0);  // this thread's stores and atomics have completed
+    __syncthreads();
+    arrivals += W;
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        atomicAdd(&tc->bar, 1u);
+        unsigned long long spins = 0;
+        while (__hip_atomic_load(&tc->bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < arrivals) {
+            if (++spins > kTeamSpin || __hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (!ok) atomicOr(&ctl->error, 2u);
+        *s_ok = ok;
+    }
+    __syncthreads();
+    return *s_ok != 0;
+}
+
+// Workgroups [0, nteams * W) form the teams of the large queries; the others
+// take the remaining queries one per workgroup (batch_single) at the same time.
+template <int BS, int IN, bool OUT>
+__global__ __launch_bounds__(BS) void k_batch_team(const BatchQuery *__restrict__ queries,
+                                                   const uint32_t *__restrict__ large, uint32_t nlarge, uint32_t W,
+                                                   uint32_t nteams, TeamCtl *teams,
+                                                   const uint32_t *__restrict__ small, uint32_t nsmall, BatchCtl *ctl,
+                                                   uint32_t *__restrict__ phases_out, uint32_t split) {
+    __shared__ unsigned long long sh[2 * (BS / 64)];
+    __shared__ uint32_t hub_v[kHubCap];
+    __shared__ unsigned long long hub_du[kHubCap];
+    __shared__ uint32_t hub_n;
+    __shared__ int s_ok;
+    if (blockIdx.x >= nteams * W) {
+        batch_single<BS, IN, OUT>(queries, small, nsmall, ctl, phases_out, split);
+        return;
+    }
+    const uint32_t t = blockIdx.x / W, m = blockIdx.x % W;
+    TeamCtl *tc = teams + t;
+    uint32_t arrivals = 0;
+    for (uint32_t qi = t; qi < nlarge; qi += nteams) {
+        const BatchQuery q = queries[large[qi]];
+        const uint32_t n = q.n;
+        for (uint32_t v = m * BS + threadIdx.x; v < n; v += W * BS) {
+            st_dev(&q.dist[v], v == q.src ? 0ull : INF64);
+            st_dev(&q.st[v], (uint8_t)(v == q.src ? ST_F : ST_U));
+        }
+        if (m == 0 && threadIdx.x == 0) {
+            st_dev(&q.fl[0], q.src);
+            for (int k = 0; k < 2; ++k) {
+                st_dev(&tc->nset[k], 0u);
+                st_dev(&tc->nnext[k], 0u);
+                st_dev(&tc->fmin[k], INF64);
+                st_dev(&tc->ftst[k], INF64);
+            }
+        }
+        if (!team_barrier(tc, W, arrivals, ctl, &s_ok)) return;
+        uint32_t nF = 1, cur = 0, phases = 0;
+        unsigned long long minD = 0, T = min_out64(q.vmin[q.src].y, q.wmax, q.rp, q.src);
+        while (nF > 0) {  // team-uniform: every member reads the same counters after a barrier
+            uint32_t *F = q.fl + (uint64_t)cur * n;
+            uint32_t *Fn = q.fl + (uint64_t)(cur ^ 1) * n;
+            uint32_t *Sp = q.fl + 2ull * n;
+            const int pp = (int)(phases & 1u);
+            unsigned long long fmin = INF64, ftst = INF64;
+            for (uint32_t base = m * BS * kBatchU; base < nF; base += W * BS * kBatchU) {
+                uint32_t v[kBatchU];
+                unsigned long long dv[kBatchU];
+                uint2 mm[kBatchU];
+                uint32_t have = 0;
+#pragma unroll
+                for (int j = 0; j < kBatchU; ++j) {
+                    const uint32_t i = base + j * BS + threadIdx.x;
+                    v[j] = 0;
+                    if (i < nF) {
+                        v[j] = ld_u32(&F[i]);
+                        have |= 1u << j;
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < kBatchU; ++j) {
+                    dv[j] = INF64;
+                    mm[j] = make_uint2(INF32, INF32);
+                    if ((have >> j) & 1u) {
+                        dv[j] = ld_dist(&q.dist[v[j]]);
+                        mm[j] = q.vmin[v[j]];
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < kBatchU; ++j) {
+                    bool set = false, keep = false;
+                    if ((have >> j) & 1u) {
+                        bool ok = false;
+                        if (IN == IN_DIJK) ok = dv[j] == minD;
+                        else if (IN == IN_STATIC_M) ok = dv[j] <= sadd64(minD, min_in_test(mm[j].x));
+                        if (OUT) ok = ok || dv[j] <= T;
+                        set = ok;
+                        keep = !ok;
+                        if (keep) {
+                            fmin = umin64(fmin, dv[j]);
+                            if (OUT) ftst = umin64(ftst, sadd64(dv[j], min_out64(mm[j].y, q.wmax, q.rp, v[j])));
+                        } else {
+                            st_dev(&q.st[v[j]], (uint8_t)ST_NEW);
+                        }
+                    }
+                    wave_append<true>(set, v[j], Sp, &tc->nset[pp]);
+                    wave_append<true>(keep, v[j], Fn, &tc->nnext[pp]);
+                }
+            }
+            if (!team_barrier(tc, W, arrivals, ctl, &s_ok)) return;
+            const uint32_t nS = ld_u32(&tc->nset[pp]);
+            if (m == 0 && threadIdx.x == 0) {  // every member read phase p - 1's slots before this barrier
+                st_dev(&tc->nset[pp ^ 1], 0u);
+                st_dev(&tc->nnext[pp ^ 1], 0u);
+                st_dev(&tc->fmin[pp ^ 1], INF64);
+                st_dev(&tc->ftst[pp ^ 1], INF64);
+            }
+            if (threadIdx.x == 0) hub_n = 0;
+            ++phases;
+            if (nS == 0 || phases > n + 1) {  // a non-empty fringe always certifies its minimum
+                if (threadIdx.x == 0) atomicOr(&ctl->error, 1u);
+                return;
+            }
+            __syncthreads();  // hub_n cleared
+            unsigned long long cmin = INF64, ctst = INF64;
+            for (uint32_t base = m * BS; base < nS; base += W * BS) {
+                const uint32_t i = base + threadIdx.x;
+                uint32_t b = 0, e = 0;
+                unsigned long long du = 0;
+                if (i < nS) {
+                    const uint32_t v = ld_u32(&Sp[i]);
+                    st_dev(&q.st[v], (uint8_t)ST_S);
+                    b = q.rp[v];
+                    e = q.rp[v + 1];
+                    du = ld_dist(&q.dist[v]);
+                    if (e - b > split) {
+                        const uint32_t slot = atomicAdd(&hub_n, 1u);
+                        if (slot < kHubCap) {
+                            hub_v[slot] = v;
+                            hub_du[slot] = du;
+                            e = b;  // expanded below by the whole workgroup
+                        }
+                    }
+                }
+                uint32_t len = e - b;
+                uint32_t mx = len;
+                for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor(mx, o, 64));
+                for (uint32_t k = 0; k < mx; k += kBatchU) {
+                    uint2 ed[kBatchU];
+                    uint32_t em[kBatchU];
+                    uint32_t have = 0;
+#pragma unroll
+                    for (int j = 0; j < kBatchU; ++j) {
+                        ed[j] = make_uint2(0u, 0u);
+                        em[j] = INF32;
+                        if (k + j < len) {
+                            ed[j] = q.edges[b + k + j];
+                            if (OUT) em[j] = q.emin[b + k + j];
+                            have |= 1u << j;
+                        }
+                    }
+                    const uint32_t disc = relax_edges<kBatchU, OUT, true>(q, du, ed, em, have, cmin, ctst);
+#pragma unroll
+                    for (int j = 0; j < kBatchU; ++j) wave_append<true>((disc >> j) & 1u, ed[j].x, Fn, &tc->nnext[pp]);
+                }
+            }
+            __syncthreads();
+            const uint32_t nh = min(hub_n, (uint32_t)kHubCap);
+            for (uint32_t h = 0; h < nh; ++h) {
+                const uint32_t v = hub_v[h];
+                const uint32_t b = q.rp[v], e = q.rp[v + 1];
+                for (uint64_t kb = b; kb < e; kb += BS * kBatchU) {
+                    uint2 ed[kBatchU];
+                    uint32_t em[kBatchU];
+                    uint32_t have = 0;
+#pragma unroll
+                    for (int j = 0; j < kBatchU; ++j) {
+                        const uint64_t k = kb + (uint64_t)j * BS + threadIdx.x;
+                        ed[j] = make_uint2(0u, 0u);
+                        em[j] = INF32;
+                        if (k < e) {
+                            ed[j] = q.edges[k];
+                            if (OUT) em[j] = q.emin[k];
+                            have |= 1u << j;
+                        }
+                    }
+                    const uint32_t disc = relax_edges<kBatchU, OUT, true>(q, hub_du[h], ed, em, have, cmin, ctst);
+#pragma unroll
+                    for (int j = 0; j < kBatchU; ++j) wave_append<true>((disc >> j) & 1u, ed[j].x, Fn, &tc->nnext[pp]);
+                }
+            }
+            unsigned long long a = umin64(fmin, cmin), tt = umin64(ftst, ctst);
+            bmin2<BS>(a, tt, sh);
+            if (threadIdx.x == 0) {
+                if (a != INF64) atomicMin(&tc->fmin[pp], a);
+                if (OUT && tt != INF64) atomicMin(&tc->ftst[pp], tt);
+            }
+            if (!team_barrier(tc, W, arrivals, ctl, &s_ok)) return;
+            nF = ld_u32(&tc->nnext[pp]);
+            minD = __hip_atomic_load(&tc->fmin[pp], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (OUT) T = __hip_atomic_load(&tc->ftst[pp], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            cur ^= 1;
+        }
+        if (m == 0 && threadIdx.x == 0) phases_out[large[qi]] = phases;
+        // every member has read the last phase's counters before member 0 clears them for the next query
+        if (!team_barrier(tc, W, arrivals, ctl, &s_ok)) return;
+    }
+}
+
+typedef void (*tfn)(const BatchQuery *, const uint32_t *, uint32_t, uint32_t, uint32_t, TeamCtl *, const uint32_t *,
+                    uint32_t, BatchCtl *, uint32_t *, uint32_t);
+
+template <int BS>
+static tfn pick_team_bs(int in, bool out) {
+    if (in == IN_DIJK) return out ? k_batch_team<BS, IN_DIJK, true> : k_batch_team<BS, IN_DIJK, false>;
+    if (in == IN_STATIC_M) return out ? k_batch_team<BS, IN_STATIC_M, true> : k_batch_team<BS, IN_STATIC_M, false>;
+    return out ? k_batch_team<BS, IN_NONE, true> : k_batch_team<BS, IN_NONE, false>;
+}
+
+static tfn pick_team(int bs, int in, bool out) {
+    switch (bs) {
+    case 256: return pick_team_bs<256>(in, out);
+    case 1024: return pick_team_bs<1024>(in, out);
+    default: return pick_team_bs<512>(in, out);
+    }
+}
+
+template <int BS, int IN, bool OUT>
+__global__ __launch_bounds__(BS) void k_batch(const BatchQuery *__restrict__ queries, const uint32_t *__restrict__ order,
+                                              uint32_t nq, BatchCtl *ctl, uint32_t *__restrict__ phases_out,
+                                              uint32_t split) {
+    batch_single<BS, IN, OUT>(queries, order, nq, ctl, phases_out, split);
+}
+
 typedef void (*bfn)(const BatchQuery *, const uint32_t *, uint32_t, BatchCtl *, uint32_t *, uint32_t);
 
 template <int BS>
@@ -331,7 +613,7 @@ static bfn pick_batch(int bs, int in, bool out) {
     }
 }
 
-static sssp_batch_cfg g_batch_cfg = {0, 0, 0};  // process-wide default shape
+static sssp_batch_cfg g_batch_cfg = {0, 0, 0, 0, 0};  // process-wide default shape
 
 // One query on one workgroup of 512 threads (measured on 128^2 to 2048^2 grids:
 // 512 beats 1024 by 3-15 % and 256 on all but the smallest): sssp_solve's path
@@ -421,19 +703,26 @@ extern "C" int sssp_solve_batch_ex(sssp_graph *const *graphs, const uint32_t *so
         fl_off[i] = fl_total;
         fl_total += 3ull * g->n;
     }
-    // longest-processing-time order: most edges first
+    // longest-processing-time order: most edges first; queries on graphs with at least
+    // team_edges edges go to the team launch
     std::vector<uint32_t> order(nq);
     for (uint32_t i = 0; i < nq; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
         return graphs[x]->m + graphs[x]->n > graphs[y]->m + graphs[y]->n;
     });
+    const uint64_t team_edges = cfg.team_edges ? cfg.team_edges : (1u << 20);
+    if (cfg.team_size == 1 || cfg.team_size > 64)
+        return sssp_set_error(SSSP_ERR_INVALID, "team size must be 2 .. 64 (0: automatic)");
+    std::vector<uint32_t> large, small;
+    for (uint32_t i : order) (cfg.team_edges != UINT32_MAX && graphs[i]->m >= team_edges ? large : small).push_back(i);
     hipStream_t s = graphs[0]->stream;
     HIP_OK(hipSetDevice(graphs[0]->device));
     uint8_t *st = nullptr;
     uint32_t *fl = nullptr;
     BatchQuery *dq = nullptr;
-    uint32_t *dorder = nullptr, *dph = nullptr;
+    uint32_t *dorder = nullptr, *dph = nullptr, *dlarge = nullptr;
     BatchCtl *dctl = nullptr;
+    TeamCtl *dteams = nullptr;
     int rc = SSSP_OK;
 #define TRY(call) do { hipError_t _e = (call); if (_e != hipSuccess) { \
         rc = sssp_set_error(_e == hipErrorOutOfMemory ? SSSP_ERR_OOM : SSSP_ERR_DEVICE, "%s: %s", #call, hipGetErrorString(_e)); goto done; } } while (0)
@@ -448,27 +737,67 @@ extern "C" int sssp_solve_batch_ex(sssp_graph *const *graphs, const uint32_t *so
     TRY(hipMalloc(&dph, nq * sizeof(uint32_t)));
     TRY(hipMalloc(&dctl, sizeof(BatchCtl)));
     TRY(hipMemcpyAsync(dq, hq.data(), nq * sizeof(BatchQuery), hipMemcpyHostToDevice, s));
-    TRY(hipMemcpyAsync(dorder, order.data(), nq * sizeof(uint32_t), hipMemcpyHostToDevice, s));
     TRY(hipMemsetAsync(dctl, 0, sizeof(BatchCtl), s));
     {
         int dev = 0, cus = 256;
         hipDeviceProp_t p;
         if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
         const int bs = cfg.block ? (int)cfg.block : 512;
-        const uint32_t split = cfg.split ? cfg.split : 64;
-        uint32_t grid = cfg.blocks ? cfg.blocks : (uint32_t)cus * (bs >= 1024 ? 2 : 4);
-        if (grid > nq) grid = nq;
-        bfn k = pick_batch(bs, in, out == OUT_STATIC_M);
-        hipLaunchKernelGGL(k, dim3(grid), dim3(bs), 0, s, dq, dorder, nq, dctl, dph, split);
-        TRY(hipGetLastError());
+        uint32_t split = cfg.split ? cfg.split : 64;
+        bool teamed = false;
+        if (!large.empty()) {
+            // one cooperative launch: teams of W workgroups for the large queries, the other
+            // resident workgroups for the rest, all at once
+            tfn tk = pick_team(bs, in, out == OUT_STATIC_M);
+            int per_cu = 0;
+            TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)tk, bs, 0));
+            const uint64_t resident = (uint64_t)(per_cu > 0 ? per_cu : 0) * cus;
+            uint32_t nlarge = (uint32_t)large.size();
+            uint32_t W = cfg.team_size;
+            if (!W) {  // at most half of the resident workgroups in teams
+                W = 16;
+                while (W > 2 && (uint64_t)W * nlarge * 2 > resident) W /= 2;
+            }
+            const uint32_t nteams = (uint32_t)std::min<uint64_t>(nlarge, resident / W / 2 ? resident / W / 2 : 1);
+            const uint64_t team_blocks = (uint64_t)nteams * W;
+            if (team_blocks < resident) {
+                uint32_t nsmall = (uint32_t)small.size();
+                uint64_t single_blocks = cfg.blocks ? cfg.blocks : (uint64_t)cus * (bs >= 1024 ? 2 : 4);
+                if (single_blocks > nsmall) single_blocks = nsmall;
+                if (team_blocks + single_blocks > resident) single_blocks = resident - team_blocks;
+                uint32_t grid = (uint32_t)(team_blocks + single_blocks);
+                TRY(hipMalloc(&dlarge, nlarge * sizeof(uint32_t)));
+                TRY(hipMalloc(&dteams, nteams * sizeof(TeamCtl)));
+                TRY(hipMemcpyAsync(dlarge, large.data(), nlarge * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+                TRY(hipMemsetAsync(dteams, 0, nteams * sizeof(TeamCtl), s));
+                if (nsmall) TRY(hipMemcpyAsync(dorder, small.data(), nsmall * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+                uint32_t nt = nteams;
+                void *args[] = {&dq, &dlarge, &nlarge, &W, &nt, &dteams, &dorder, &nsmall, &dctl, &dph, &split};
+                TRY(hipLaunchCooperativeKernel((const void *)tk, dim3(grid), dim3(bs), args, 0, s));
+                teamed = true;
+            } else {
+                small.insert(small.begin(), large.begin(), large.end());  // no room for a team
+            }
+        }
+        const uint32_t nsmall = (uint32_t)small.size();
+        if (!teamed && nsmall) {
+            TRY(hipMemcpyAsync(dorder, small.data(), nsmall * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+            uint32_t grid = cfg.blocks ? cfg.blocks : (uint32_t)cus * (bs >= 1024 ? 2 : 4);
+            if (grid > nsmall) grid = nsmall;
+            bfn k = pick_batch(bs, in, out == OUT_STATIC_M);
+            hipLaunchKernelGGL(k, dim3(grid), dim3(bs), 0, s, dq, dorder, nsmall, dctl, dph, split);
+            TRY(hipGetLastError());
+        }
         BatchCtl hctl;
         TRY(hipMemcpyAsync(&hctl, dctl, sizeof hctl, hipMemcpyDeviceToHost, s));
         if (phases_out) TRY(hipMemcpyAsync(phases_out, dph, nq * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         TRY(hipStreamSynchronize(s));
-        if (hctl.error) rc = sssp_set_error(SSSP_ERR_INTERNAL, "a batched query exceeded its phase bound");
+        if (hctl.error & 2u) rc = sssp_set_error(SSSP_ERR_INTERNAL, "a team of the batched launch timed out at a barrier");
+        else if (hctl.error) rc = sssp_set_error(SSSP_ERR_INTERNAL, "a batched query exceeded its phase bound");
     }
 done:
 #undef TRY
     sssp_free(st); sssp_free(fl); sssp_free(dq); sssp_free(dorder); sssp_free(dph); sssp_free(dctl);
+    sssp_free(dlarge); sssp_free(dteams);
     return rc;
 }

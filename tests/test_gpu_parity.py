@@ -239,8 +239,13 @@ def small_batch():
 
 
 @pytest.mark.parametrize("crit", [O.STATIC_OR, O.IN_STATIC, O.OUT_STATIC, O.DIJK])
-@pytest.mark.parametrize("cfg", [None, dict(block=256, split=4, blocks=3), dict(block=1024, split=1000, blocks=64)])
+@pytest.mark.parametrize("cfg", [None, dict(block=256, split=4, blocks=3), dict(block=1024, split=1000, blocks=64),
+                                 dict(team_edges=1, team_size=4), dict(team_edges=3000, team_size=3, block=256, split=4),
+                                 dict(team_edges=1, team_size=64, block=1024)])
 def test_batched_matches_oracle(B, crit, cfg):
+    """The batched launch against the oracle, one workgroup per query and (team_edges) with teams
+    of workgroups sharing a query: odd team sizes, more members than a small query has fringe
+    entries, the degree split inside a team member."""
     graphs, queries = small_batch()
     dgs = [B.DeviceGraph.from_graph(g) for g in graphs]
     dists, phases = B.solve_batch([dgs[i] for i, _ in queries], [s for _, s in queries], crit, cfg=cfg)
