@@ -433,6 +433,9 @@ def main():
     ap.add_argument("--no-c3", action="store_true", help="skip the R-MAT 22 / 2048^2 grid section")
     ap.add_argument("--profile-run", action="store_true",
                     help="one solve with the default launch shape, for rocprofv3 (no tuning, no extra passes)")
+    ap.add_argument("--profile-graph", default="er", choices=("er", "rmat"),
+                    help="with --profile-run: the random graph of --log2n (source 0), or R-MAT scale 22 (the first "
+                         "of its 8 benchmark sources)")
     ap.add_argument("--launch", default=None,
                     help="with --profile-run: scan_blocks,relax_blocks,chunk,use_graph[,queue] (e.g. the shape the "
                          "autotuner picks for the timed run)")
@@ -460,13 +463,18 @@ def main():
         print(json.dumps({"copy_calibration_bytes": 1 << 30}))
         return
     if args.profile_run:
-        g = G.config_er_large(seed=1, log2n=args.log2n)
+        if args.profile_graph == "rmat":
+            g = G.config_rmat(seed=1)
+            psrc = int(G.sources(g, 8, 11)[0])
+        else:
+            g = G.config_er_large(seed=1, log2n=args.log2n)
+            psrc = 0
         dg = B.DeviceGraph.from_graph(g)
         if args.launch:
             f = [int(x) for x in args.launch.split(",")]
             keys = ("scan_blocks", "relax_blocks", "chunk", "use_graph", "queue")
             dg.set_launch(**dict(zip(keys, f)))
-        r = B.solve(dg, 0, B.STATIC_OR)
+        r = B.solve(dg, psrc, B.STATIC_OR)
         torch.cuda.synchronize()
         print(json.dumps({"profile_run": True, "phases": r.phases, "launch": dg.launch()}))
         return
