@@ -11,7 +11,8 @@ struct sssp_graph {
     int device = 0;
     hipStream_t stream = nullptr;
     uint32_t *rp = nullptr;        // row_ptr as u32 (n+1)
-    uint2 *edges = nullptr;        // (target, weight), rows sorted by weight
+    uint2 *edges = nullptr;        // (target, weight); rows sorted by weight once rows_sorted
+    bool rows_sorted = false;      // set by graph_ensure_sorted (the dynamic criteria's cursors)
     uint2 *vmin = nullptr;         // (minIn, minOut)
     uint32_t *emin = nullptr;      // per edge: minOut of its target (relax folds the next OUT-STATIC threshold)
     uint32_t *ip = nullptr;        // CSC in_ptr (lazy)
@@ -47,6 +48,7 @@ struct sssp_graph {
 
 DevGraph dev_view(const sssp_graph *g);
 int graph_ensure_csc(sssp_graph *g);
+int graph_ensure_sorted(sssp_graph *g);
 void graph_default_cfg(sssp_graph *g);
 int solve_bufs_ensure(sssp_graph *g, bool cursors, bool stamps, bool queue, bool approx = false, bool store = false);
 void solve_bufs_free(sssp_graph *g);

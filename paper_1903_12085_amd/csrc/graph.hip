@@ -1,8 +1,9 @@
-// Device graph: CSR upload and validation, per-row weight sort, static minima
+// Device graph: CSR upload and validation, static minima
 // (equations crit:instatic / crit:outstatic need min in- and out-edge weight
 // per vertex, computed once in O(m), Section 3; the implementation section
 // computes the minimum in-edge weight with an atomic minimum per edge), and
-// the lazily built reverse adjacency (CSC) that the dynamic IN criteria scan.
+// the per-row weight sort and the reverse adjacency (CSC), both built lazily
+// for the dynamic criteria.
 #include <chrono>
 #include <stdarg.h>
 #include <stdio.h>
@@ -49,20 +50,6 @@ __global__ void k_rp32(uint32_t n, const uint64_t *__restrict__ rp64, uint32_t *
         rp[v] = (uint32_t)rp64[v];
 }
 
-// Row of every edge by binary search in row_ptr; key = (row << 32) | weight.
-__global__ void k_row_keys(uint32_t n, uint64_t m, const uint32_t *__restrict__ rp,
-                           const uint32_t *__restrict__ w, unsigned long long *__restrict__ key) {
-    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
-         e += (uint64_t)gridDim.x * blockDim.x) {
-        uint32_t lo = 0, hi = n - 1;  // last row r with rp[r] <= e
-        while (lo < hi) {
-            uint32_t mid = lo + (hi - lo + 1) / 2;
-            if (rp[mid] <= e) lo = mid; else hi = mid - 1;
-        }
-        key[e] = ((unsigned long long)lo << 32) | w[e];
-    }
-}
-
 // key = (target << 32) | weight for the reverse adjacency; payload = source.
 __global__ void k_col_keys(uint64_t m, const uint2 *__restrict__ edges, const uint32_t *__restrict__ rp,
                            uint32_t n, unsigned long long *__restrict__ key, uint32_t *__restrict__ src) {
@@ -86,13 +73,56 @@ __global__ void k_pack_edges(uint64_t m, const unsigned long long *__restrict__ 
         out[e] = make_uint2(val[e], (uint32_t)(key[e] & 0xFFFFFFFFull));
 }
 
-// minOut = first (lightest) edge of each weight-sorted row; minIn reset to INF.
+// minOut = the lightest edge of each row (rows in input order); minIn reset to INF.
+// A lane scans a short row itself; the wavefront scans the long rows of its
+// lanes together, one row at a time.
 __global__ void k_min_out(uint32_t n, const uint32_t *__restrict__ rp, const uint2 *__restrict__ edges,
                           uint2 *__restrict__ vmin) {
-    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
-         v += (uint64_t)gridDim.x * blockDim.x) {
-        uint32_t b = rp[v], e = rp[v + 1];
-        vmin[v] = make_uint2(INF32, b < e ? edges[b].y : INF32);
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < n; base += stride) {
+        const uint64_t v = base + lane;  // base is wavefront-uniform
+        uint32_t b = 0, e = 0;
+        if (v < n) { b = rp[v]; e = rp[v + 1]; }
+        const bool longrow = e - b > 64;
+        uint32_t mo = INF32;
+        if (!longrow)
+            for (uint32_t k = b; k < e; ++k) mo = min(mo, edges[k].y);
+        unsigned long long lm = __ballot(longrow);
+        while (lm) {
+            const int l = __ffsll(lm) - 1;
+            lm &= lm - 1;
+            const uint32_t lb = __shfl(b, l, 64), le = __shfl(e, l, 64);
+            uint32_t x = INF32;
+            for (uint32_t k = lb + lane; k < le; k += 64) x = min(x, edges[k].y);
+            for (int o = 32; o > 0; o >>= 1) x = min(x, (uint32_t)__shfl_xor((int)x, o, 64));
+            if ((int)lane == l) mo = x;
+        }
+        if (v < n) vmin[v] = make_uint2(INF32, mo);
+    }
+}
+
+// The input's edges as (target, weight), rows in input order.
+__global__ void k_pack_cw(uint64_t m, const uint32_t *__restrict__ col, const uint32_t *__restrict__ w,
+                          uint2 *__restrict__ out) {
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x)
+        out[e] = make_uint2(col[e], w[e]);
+}
+
+// key = (row << 32) | weight and payload = target of every edge, for the row
+// sort; the row by binary search in row_ptr.
+__global__ void k_row_keys_e(uint32_t n, uint64_t m, const uint32_t *__restrict__ rp, const uint2 *__restrict__ edges,
+                             unsigned long long *__restrict__ key, uint32_t *__restrict__ val) {
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+         e += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t lo = 0, hi = n - 1;
+        while (lo < hi) {
+            uint32_t mid = lo + (hi - lo + 1) / 2;
+            if (rp[mid] <= e) lo = mid; else hi = mid - 1;
+        }
+        const uint2 ed = edges[e];
+        key[e] = ((unsigned long long)lo << 32) | ed.y;
+        val[e] = ed.x;
     }
 }
 
@@ -196,8 +226,6 @@ static int create_impl(uint32_t n, uint64_t m, const uint64_t *row_ptr, const ui
     uint64_t *rp64 = nullptr;
     uint32_t *dcol = nullptr, *dw = nullptr;
     unsigned int *bad = nullptr;
-    unsigned long long *k0 = nullptr, *k1 = nullptr;
-    uint32_t *v1 = nullptr;
     int rc = SSSP_OK;
 #define TRY(call) do { hipError_t _e = (call); if (_e != hipSuccess) { \
         rc = sssp_set_error(_e == hipErrorOutOfMemory ? SSSP_ERR_OOM : SSSP_ERR_DEVICE, "%s: %s", #call, hipGetErrorString(_e)); goto done; } } while (0)
@@ -234,26 +262,9 @@ static int create_impl(uint32_t n, uint64_t m, const uint64_t *row_ptr, const ui
         TRY(hipEventCreate(&e1));
         TRY(hipEventRecord(e0, s));
         hipLaunchKernelGGL(k_rp32, dim3(grid_for(n + 1)), dim3(256), 0, s, n, rp64, g->rp);
-        if (m) {
-            // 2. sort each row by weight: global radix sort of (row, weight) keys
-            uint32_t *v0 = nullptr;
-            TRY(hipMalloc(&k0, m * sizeof(unsigned long long)));
-            TRY(hipMalloc(&k1, m * sizeof(unsigned long long)));
-            TRY(hipMalloc(&v1, m * sizeof(uint32_t)));
-            hipLaunchKernelGGL(k_row_keys, dim3(grid_for(m)), dim3(256), 0, s, n, m, g->rp, dw, k0);
-            if (device_ptrs) {  // do not modify the caller's arrays
-                TRY(hipMalloc(&v0, m * sizeof(uint32_t)));
-                TRY(hipMemcpyAsync(v0, dcol, m * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
-            } else {
-                v0 = dcol;
-                dcol = nullptr;  // ownership moves to v0
-            }
-            rc = radix_sort(k0, k1, v0, v1, m, 32 + bits_for(n), s);
-            if (rc == SSSP_OK)
-                hipLaunchKernelGGL(k_pack_edges, dim3(grid_for(m)), dim3(256), 0, s, m, k0, v0, g->edges);
-            sssp_free(v0);
-            if (rc != SSSP_OK) goto done;
-        }
+        // 2. the edges in input order; rows are sorted by weight only when a solve first needs the
+        // cursors of the dynamic criteria (graph_ensure_sorted)
+        if (m) hipLaunchKernelGGL(k_pack_cw, dim3(grid_for(m)), dim3(256), 0, s, m, dcol, dw, g->edges);
         // 3. static minima
         hipLaunchKernelGGL(k_min_out, dim3(grid_for(n)), dim3(256), 0, s, n, g->rp, g->edges, g->vmin);
         if (m) hipLaunchKernelGGL(k_min_in, dim3(grid_for(m)), dim3(256), 0, s, m, g->edges, g->vmin);
@@ -282,7 +293,7 @@ static int create_impl(uint32_t n, uint64_t m, const uint64_t *row_ptr, const ui
 done:
 #undef TRY
     if (!device_ptrs) { sssp_free(rp64); sssp_free(dcol); sssp_free(dw); }
-    sssp_free(bad); sssp_free(k0); sssp_free(k1); sssp_free(v1);
+    sssp_free(bad);
     return rc;
 }
 
@@ -347,6 +358,38 @@ extern "C" int sssp_graph_minima(sssp_graph *g, uint32_t *min_in, uint32_t *min_
     HIP_OK(hipGetLastError());
     HIP_OK(hipStreamSynchronize(g->stream));
     return SSSP_OK;
+}
+
+// Sorts each row of the CSR by weight, in place (the cursors of the dynamic
+// criteria walk rows lightest first); emin follows the edges. Once per graph.
+int graph_ensure_sorted(sssp_graph *g) {
+    if (g->rows_sorted || g->m == 0) {
+        g->rows_sorted = true;
+        return SSSP_OK;
+    }
+    const uint64_t m = g->m;
+    hipStream_t s = g->stream;
+    unsigned long long *k0 = nullptr, *k1 = nullptr;
+    uint32_t *v0 = nullptr, *v1 = nullptr;
+    int rc = SSSP_OK;
+#define TRY(call) do { hipError_t _e = (call); if (_e != hipSuccess) { \
+        rc = sssp_set_error(_e == hipErrorOutOfMemory ? SSSP_ERR_OOM : SSSP_ERR_DEVICE, "%s: %s", #call, hipGetErrorString(_e)); goto done; } } while (0)
+    TRY(hipMalloc(&k0, m * sizeof(unsigned long long)));
+    TRY(hipMalloc(&k1, m * sizeof(unsigned long long)));
+    TRY(hipMalloc(&v0, m * sizeof(uint32_t)));
+    TRY(hipMalloc(&v1, m * sizeof(uint32_t)));
+    hipLaunchKernelGGL(k_row_keys_e, dim3(grid_for(m)), dim3(256), 0, s, g->n, m, g->rp, g->edges, k0, v0);
+    rc = radix_sort(k0, k1, v0, v1, m, 32 + bits_for(g->n), s);
+    if (rc != SSSP_OK) goto done;
+    hipLaunchKernelGGL(k_pack_edges, dim3(grid_for(m)), dim3(256), 0, s, m, k0, v0, g->edges);
+    hipLaunchKernelGGL(k_emin, dim3(grid_for(m)), dim3(256), 0, s, m, g->edges, g->vmin, g->emin);
+    TRY(hipGetLastError());
+    TRY(hipStreamSynchronize(s));
+    g->rows_sorted = true;
+done:
+#undef TRY
+    sssp_free(k0); sssp_free(k1); sssp_free(v0); sssp_free(v1);
+    return rc;
 }
 
 // Reverse adjacency with rows sorted by weight (for the dynamic IN terms).

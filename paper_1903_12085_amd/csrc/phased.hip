@@ -2771,13 +2771,24 @@ static unsigned long long shard_sum(const Sharded &x) {
 
 // Copies the whole control block once at the end of a solve and checks the
 // end state: F empty, and every vertex ever queued settled.
+// The control block's header and its first three sharded sums, the part a finished
+// solve reports (laid out first in Ctl, so one short copy fetches them).
+struct CtlPrefix {
+    CtlHead h;
+    Sharded reached, relax_edges, improving;
+};
+static_assert(offsetof(Ctl, reached) == offsetof(CtlPrefix, reached) &&
+                  offsetof(Ctl, improving) == offsetof(CtlPrefix, improving) &&
+                  sizeof(CtlPrefix) <= offsetof(Ctl, spack) + 0,
+              "finish_stats copies a prefix of Ctl");
+
 static int finish_stats(const sssp_graph *g, const Ctl *dctl, sssp_stats *st, uint32_t *phases) {
-    Ctl *c = new (std::nothrow) Ctl;
-    if (!c) return sssp_set_error(SSSP_ERR_OOM, "host control block");
+    CtlPrefix pre;
+    const CtlPrefix *c = &pre;
     // on the solve's stream: the copy waits for this solve only, not for other streams' work
-    hipError_t e = hipMemcpyAsync(c, dctl, sizeof(Ctl), hipMemcpyDeviceToHost, g->stream);
+    hipError_t e = hipMemcpyAsync(&pre, dctl, sizeof(CtlPrefix), hipMemcpyDeviceToHost, g->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
-    if (e != hipSuccess) { delete c; return sssp_set_error(SSSP_ERR_DEVICE, "control block copy: %s", hipGetErrorString(e)); }
+    if (e != hipSuccess) return sssp_set_error(SSSP_ERR_DEVICE, "control block copy: %s", hipGetErrorString(e));
     const unsigned long long reached = shard_sum(c->reached);
     int rc = SSSP_OK;
     if (c->h.stalled)
@@ -2797,7 +2808,6 @@ static int finish_stats(const sssp_graph *g, const Ctl *dctl, sssp_stats *st, ui
         st->improving = shard_sum(c->improving);
         st->precompute_ns = g->precompute_ns;
     }
-    delete c;
     return rc;
 }
 
@@ -2881,6 +2891,10 @@ static int solve_common(sssp_graph *g, uint32_t source, bool delta_mode, uint32_
     const bool store = !learn && !trace_mode && !oracle && !apx && !delta_mode && (stores(in, out) || stores(in2, out2));
     if (in_all >= IN_SIMPLE_M || (apx && (crit & SSSP_IN_APPROX)) || store) {
         int rc = graph_ensure_csc(g);
+        if (rc) return rc;
+    }
+    if (dyn) {  // the cursors walk each row lightest edge first
+        int rc = graph_ensure_sorted(g);
         if (rc) return rc;
     }
     int rc = solve_bufs_ensure(g, dyn, delta_mode, queue_now || queue_later, apx != nullptr, store);
