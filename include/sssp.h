@@ -103,8 +103,9 @@ typedef struct {
  * device_ptrs = 1: they are device pointers. The library copies the data into
  * buffers it owns, so the caller may free its arrays after the call. It
  * precomputes the static minima minIn/minOut (equations crit:instatic and
- * crit:outstatic, computed once in O(m), Section 3) and sorts every row by
- * weight. hip_stream: a hipStream_t or NULL for the null stream.
+ * crit:outstatic, computed once in O(m), Section 3). Rows keep the input's
+ * edge order; the first solve with a SIMPLE or full criterion sorts every row
+ * by weight in place, once. hip_stream: a hipStream_t or NULL for the null stream.
  * Errors: SSSP_ERR_INVALID for n = 0, a malformed CSR (checked on the device
  * when device_ptrs = 1) or out == NULL; SSSP_ERR_OOM; SSSP_ERR_UNSUPPORTED.
  */
