@@ -169,6 +169,7 @@ struct SolveBufs {
     unsigned long long *qd; // distance of the entry's vertex (kTomb once it settled)
     uint32_t *qv;           // the entry's vertex
     uint2 *qm;              // its (minIn, minOut)
+    uint2 *qr;              // its row start and out-degree (settling reads no row pointers)
     uint32_t *qcnt;         // per scan block: slots in use, then tombstones among them
     uint32_t qspan;         // slots per scan block (vertices it owns)
     // approximate criteria: phase index of each vertex's last IN / OUT recomputation, and the

@@ -1107,14 +1107,17 @@ constexpr uint32_t kQWin = 4 * kOwnSpan;     // most vertices a scan block may o
 // OUT threshold). With a dynamic criterion, k_terms_win has evaluated the
 // phase's terms over the same entries before this launch.
 // Scan block b owns the vertices kOwnSpan * (k * G + b) + [0, kOwnSpan),
-// k = 0, 1, ... (G blocks), and keeps an entry (d, v, minIn, minOut) for each
-// of them that is queued, in slots [b * qspan, (b + 1) * qspan): a phase reads
-// those entries, 20 bytes per queued vertex, and the state bytes of the block's
-// vertices, instead of the distance and minima of every vertex. Relax flags a
+// k = 0, 1, ... (G blocks), and keeps an entry (d, v, minIn, minOut, row start,
+// out-degree) for each of them that is queued, in slots [b * qspan, (b + 1) *
+// qspan): a phase reads those entries, 28 bytes per queued vertex, and the state
+// bytes of the block's vertices, instead of the distance and minima of every
+// vertex; settling an entry's vertex reads no row pointers. Relax flags a
 // vertex it discovers ST_QNEW and one whose distance it lowers ST_QDIRTY; the
 // owner gathers a new vertex's distance and minima once and gives it an entry
 // if it stays queued, and reloads a dirty entry's distance, so an entry holds
-// its vertex's distance at phase start. A settled entry becomes a tombstone; a
+// its vertex's distance at phase start. The new vertices' loads are issued before
+// the entries' (the two are independent), so that a phase waits for one round of
+// loads for both. A settled entry becomes a tombstone; a
 // block whose slots hold more than a quarter of tombstones moves its live
 // entries down over them. Each vertex gets at most one entry, so a block's
 // slots never overflow.
@@ -1151,6 +1154,7 @@ __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
     __shared__ uint32_t s_wk[kWaves];  // compaction: entries each wavefront keeps in one step
     __shared__ uint32_t s_app;         // entries appended to this block's slots in this pass
     __shared__ uint4 s_st[kQWin / 16]; // state bytes of the block's vertices
+    __shared__ uint16_t s_need[kBlock * 16];  // per wavefront: its window vertices that need an entry
     Ctl *ctl = a.b.ctl;
     const int p2 = par & 1, p3 = par % 3;
     const unsigned long long r0 = lane_slot(ctl->reached, 0ull), m0 = lane_slot(ctl->minD[p3], INF64);
@@ -1166,6 +1170,11 @@ __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
     // the block's state bytes (window w = its w-th grid step, at most four) are loaded
     // now, with the control slots, and written to LDS once the phase is known to run
     const uint32_t span = a.b.qspan;
+    const uint64_t rb = (uint64_t)b * span;
+    unsigned long long *qd = a.b.qd + rb;
+    uint32_t *qv = a.b.qv + rb;
+    uint2 *qm = a.b.qm + rb;
+    uint2 *qr = a.b.qr + rb;
     uint4 win[kQWin / kOwnSpan];
 #pragma unroll
     for (uint32_t w = 0; w < kQWin / kOwnSpan; ++w) {
@@ -1247,10 +1256,6 @@ __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
         return step * kOwnSpan + (v % kOwnSpan);
     };
     unsigned long long fmin = INF64, ftst = INF64, ntomb = 0;
-    const uint64_t rb = (uint64_t)b * span;
-    unsigned long long *qd = a.b.qd + rb;
-    uint32_t *qv = a.b.qv + rb;
-    uint2 *qm = a.b.qm + rb;
     auto certified = [&](unsigned long long d, uint2 mm, uint32_t sb) {
         bool ok = false;
         if (IN == IN_DIJK) ok = d == minD;
@@ -1259,13 +1264,86 @@ __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
         if (OUT != 0) ok = ok || d <= T;                                // eq. crit:outstatic, or dynamic
         return ok;
     };
-    auto settle = [&](uint32_t v, unsigned long long d, uint32_t &row, uint32_t &deg) {
+    auto settle = [&](uint32_t v, unsigned long long d) {
         a.b.st[v] = (uint8_t)(ST_S | (a.mark ? ST_CHG : 0));
         a.b.dist[v] = d | kSettledBit;
         if (a.b.phase_of) a.b.phase_of[v] = P + 1;
-        row = a.g.rp[v];
-        deg = a.g.rp[v + 1] - row;
     };
+    // 2a. vertices that need an entry: new ones, or (rebuild) every queued one, read from
+    // the LDS state window (sixteen per lane). Keyed: also far vertices whose distance
+    // dropped; a vertex stays far (no entry, no fold) while its key exceeds the split,
+    // except in a rebuild, which folds every queued vertex and certifies none. A
+    // wavefront lists its window's such vertices in LDS, so that each round gives every
+    // lane one of them, and issues the loads of its first round now, before the entries:
+    // they are independent of them (no entry holds a vertex that needs one).
+    const int lane = threadIdx.x & 63;
+    const bool gather_all = KEYED ? rebuild : !live;
+    auto in_key = [&](unsigned long long d, uint2 mm) {  // d - minIn, floored at 0 (eq. crit:instatic)
+        const unsigned long long mi = min_in_test(mm.x);
+        return d > mi ? d - mi : 0ull;
+    };
+    constexpr uint32_t kWin = kQWin / kOwnSpan;
+    const uint32_t wo = 1024u * (threadIdx.x >> 6);  // the wavefront's first vertex in a window
+    uint16_t *need = s_need + wo;
+    auto need_mask = [&](uint32_t w) {  // bit j: vertex 16 * threadIdx.x + j of window w
+        const uint4 x = s_st[w * kBlock + threadIdx.x];
+        const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
+        uint32_t nm = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t sb = (xs[q] >> (8 * j)) & 0xffu;
+                const bool nd = gather_all ? (sb & ST_SET) == ST_F
+                                : KEYED ? (sb & ST_QNEW) != 0 || (sb & (ST_QDIRTY | ST_QFAR)) == (ST_QDIRTY | ST_QFAR)
+                                        : (sb & ST_QNEW) != 0;
+                if (nd) nm |= 1u << (4 * q + j);
+            }
+        return nm;
+    };
+    auto list_need = [&](uint32_t nm) {  // wavefront-uniform; returns the list's length
+        const uint32_t c = (uint32_t)__popc(nm);
+        const uint32_t incl = wave_incl_scan(c);
+        const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+        if (tot != 0) {
+            __builtin_amdgcn_wave_barrier();  // earlier reads of the list come first
+            for (uint32_t o = incl - c, bits = nm; bits; bits &= bits - 1)
+                need[o++] = (uint16_t)(16 * lane + __ffs(bits) - 1);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        return tot;
+    };
+    struct Gathered {
+        uint32_t v, row, deg;
+        unsigned long long d;
+        uint2 mm;
+    };
+    auto gather = [&](uint64_t wv0, uint32_t off) {
+        Gathered g;
+        g.v = (uint32_t)(wv0 + off);
+        g.d = a.b.dist[g.v];
+        g.mm = a.g.vmin[g.v];
+        g.row = a.g.rp[g.v];
+        g.deg = a.g.rp[g.v + 1] - g.row;
+        return g;
+    };
+    uint32_t nmw[kWin], totw[kWin], offw[kWin];
+    Gathered gw[kWin];
+#pragma unroll
+    for (uint32_t w = 0; w < kWin; ++w) {
+        nmw[w] = totw[w] = offw[w] = 0;
+        gw[w] = Gathered{0u, 0u, 0u, INF64, make_uint2(INF32, INF32)};
+        const uint64_t wv0 = (uint64_t)kOwnSpan * ((uint64_t)w * G + b) + wo;
+        if (w * kOwnSpan >= span || wv0 >= n) continue;  // wavefront-uniform
+        nmw[w] = need_mask(w);
+        totw[w] = list_need(nmw[w]);
+        if ((uint32_t)lane < totw[w]) {
+            offw[w] = need[lane];
+            gw[w] = gather(wv0, offw[w]);
+        }
+    }
     // 1. the block's entries, four consecutive ones per lane
     const bool compact = tomb0 * 4u > cnt0;  // block-uniform
     uint32_t kept = 0;                       // compaction: entries kept so far
@@ -1273,27 +1351,31 @@ __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
         const uint32_t i = i0 + 4 * threadIdx.x;
         unsigned long long d[4];
         uint32_t v[4];
-        uint2 mm[4];
+        uint2 mm[4], rr[4];  // rr: (row start, out-degree)
         if (i + 4 <= cnt0) {
             const ulonglong2 *dp = reinterpret_cast<const ulonglong2 *>(qd + i);
             const uint4 *mp = reinterpret_cast<const uint4 *>(qm + i);
+            const uint4 *rp4 = reinterpret_cast<const uint4 *>(qr + i);
             const ulonglong2 d01 = dp[0], d23 = dp[1];
             const uint4 vv = *reinterpret_cast<const uint4 *>(qv + i);
-            const uint4 m01 = mp[0], m23 = mp[1];
+            const uint4 m01 = mp[0], m23 = mp[1], r01 = rp4[0], r23 = rp4[1];
             d[0] = d01.x; d[1] = d01.y; d[2] = d23.x; d[3] = d23.y;
             v[0] = vv.x; v[1] = vv.y; v[2] = vv.z; v[3] = vv.w;
             mm[0] = make_uint2(m01.x, m01.y); mm[1] = make_uint2(m01.z, m01.w);
             mm[2] = make_uint2(m23.x, m23.y); mm[3] = make_uint2(m23.z, m23.w);
+            rr[0] = make_uint2(r01.x, r01.y); rr[1] = make_uint2(r01.z, r01.w);
+            rr[2] = make_uint2(r23.x, r23.y); rr[3] = make_uint2(r23.z, r23.w);
         } else {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 d[j] = kTomb;
                 v[j] = 0;
-                mm[j] = make_uint2(INF32, INF32);
+                mm[j] = rr[j] = make_uint2(INF32, 0u);
                 if (i + j < cnt0) {
                     d[j] = qd[i + j];
                     v[j] = qv[i + j];
                     mm[j] = qm[i + j];
+                    rr[j] = qr[i + j];
                 }
             }
         }
@@ -1314,6 +1396,8 @@ __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
         for (int j = 0; j < 4; ++j) {
             row[j] = deg[j] = 0;
             if (d[j] == kTomb) continue;
+            row[j] = rr[j].x;
+            deg[j] = rr[j].y;
             if (certified(d[j], mm[j], sbj[j])) {
                 sm |= 1u << j;
             } else {
@@ -1324,7 +1408,7 @@ __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            if ((sm >> j) & 1u) settle(v[j], d[j], row[j], deg[j]);
+            if ((sm >> j) & 1u) settle(v[j], d[j]);
         append_settled_n<CH, 4>(a, ctl, p2, L, sm, row, deg, d);
         if (!compact) {
 #pragma unroll
@@ -1354,54 +1438,33 @@ __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
                     qd[o] = d[j];
                     qv[o] = v[j];
                     qm[o] = mm[j];
+                    qr[o] = rr[j];
                     ++o;
                 }
             kept += tot;
         }
     }
     const uint32_t cnt = compact ? kept : cnt0;  // block-uniform
-    // 2. vertices that need an entry: new ones, or (rebuild) every queued one; sixteen
-    // state bytes per lane from the LDS window. Keyed: also far vertices whose distance
-    // dropped; a vertex stays far (no entry, no fold) while its key exceeds the split,
-    // except in a rebuild, which folds every queued vertex and certifies none.
-    const int lane = threadIdx.x & 63;
-    const bool gather_all = KEYED ? rebuild : !live;
-    auto in_key = [&](unsigned long long d, uint2 mm) {  // d - minIn, floored at 0 (eq. crit:instatic)
-        const unsigned long long mi = min_in_test(mm.x);
-        return d > mi ? d - mi : 0ull;
-    };
-#pragma unroll 1
-    for (uint32_t w = 0; w * kOwnSpan < span; ++w) {
-        const uint64_t v0 = (uint64_t)kOwnSpan * ((uint64_t)w * G + b) + 16u * threadIdx.x;
-        if (v0 >= n && __ballot(v0 < n) == 0) break;  // wavefront-uniform
-        const uint4 x = s_st[w * kBlock + threadIdx.x];
-        const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
-        uint32_t nm = 0;  // bit j: vertex v0 + j needs an entry
+    // 2b. the vertices listed in 2a: certify, settle, or give an entry
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const uint32_t sb = (xs[q] >> (8 * j)) & 0xffu;
-                const bool need = gather_all ? (sb & ST_SET) == ST_F
-                                  : KEYED ? (sb & ST_QNEW) != 0 || (sb & (ST_QDIRTY | ST_QFAR)) == (ST_QDIRTY | ST_QFAR)
-                                          : (sb & ST_QNEW) != 0;
-                if (need) nm |= 1u << (4 * q + j);
+    for (uint32_t w = 0; w < kWin; ++w) {
+        if (totw[w] == 0) continue;  // wavefront-uniform
+        const uint64_t wv0 = (uint64_t)kOwnSpan * ((uint64_t)w * G + b) + wo;
+        if (totw[w] > 64) list_need(nmw[w]);  // the LDS list was overwritten by later windows
+        for (uint32_t k0 = 0; k0 < totw[w]; k0 += 64) {  // wavefront-uniform rounds
+            const bool has = k0 + (uint32_t)lane < totw[w];
+            uint32_t off = offw[w];
+            Gathered g = gw[w];
+            if (k0 != 0 && has) {
+                off = need[k0 + lane];
+                g = gather(wv0, off);
             }
-        while (__ballot(nm != 0)) {  // wavefront-uniform: one vertex per lane per round
-            const bool has = nm != 0;
-            uint32_t v = 0, row = 0, deg = 0, sb = 0;
-            unsigned long long d = INF64;
-            uint2 mm = make_uint2(INF32, INF32);
-            if (has) {
-                const int j = __ffs(nm) - 1;
-                v = (uint32_t)v0 + (uint32_t)j;
-                sb = sw[w * kOwnSpan + 16u * threadIdx.x + (uint32_t)j];
-                nm &= nm - 1;
-                d = a.b.dist[v];
-                mm = a.g.vmin[v];
-            }
+            const uint32_t v = g.v, row = g.row, deg = g.deg;
+            const unsigned long long d = g.d;
+            const uint2 mm = g.mm;
+            const uint32_t sb = has ? sw[w * kOwnSpan + wo + off] : 0u;
             const bool ok = has && !rebuild && certified(d, mm, sb);
-            if (ok) settle(v, d, row, deg);
+            if (ok) settle(v, d);
             append_settled<CH>(a, ctl, p2, L, ok, row, deg, d);
             const bool far = KEYED && has && !ok && in_key(d, mm) > split;
             const bool app = has && !ok && !far;
@@ -1420,6 +1483,7 @@ __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
                     qd[o] = d;
                     qv[o] = v;
                     qm[o] = mm;
+                    qr[o] = make_uint2(row, deg);
                     a.b.st[v] = ST_F;
                 }
             }
@@ -2254,7 +2318,7 @@ void solve_bufs_free(sssp_graph *g) {
     sssp_free(b.ctl); sssp_free(b.st); sssp_free(b.srow); sssp_free(b.soff); sssp_free(b.sdu);
     sssp_free(b.chunk_start); sssp_free(b.in_cur); sssp_free(b.out_cur); sssp_free(b.stamp); sssp_free(b.deltas);
     sssp_free(b.in_head); sssp_free(b.out_head);
-    sssp_free(b.qd); sssp_free(b.qv); sssp_free(b.qm); sssp_free(b.qcnt);
+    sssp_free(b.qd); sssp_free(b.qv); sssp_free(b.qm); sssp_free(b.qr); sssp_free(b.qcnt);
     sssp_free(b.apx_lin); sssp_free(b.apx_lout); sssp_free(b.apx_sp);
     sssp_free(b.tin); sssp_free(b.tout);
     sssp_free(g->one_st); sssp_free(g->one_fl); sssp_free(g->one_aux);
@@ -2350,14 +2414,14 @@ int solve_bufs_ensure(sssp_graph *g, bool cursors, bool stamps, bool queue, bool
         if (rc) return rc;
     }
     if (stamps && !b.stamp) HIP_OK(hipMalloc(&b.stamp, n * 4));
-    if (queue && !(b.qd && b.qv && b.qm && b.qcnt)) {
+    if (queue && !(b.qd && b.qv && b.qm && b.qr && b.qcnt)) {
         const uint64_t G = (uint64_t)g->cfg.scan_blocks;
         const uint64_t span = scan_span(g->n, g->cfg.scan_blocks, 16);
         if (G * span >= INF32) return sssp_set_error(SSSP_ERR_UNSUPPORTED, "queue arrays: too many slots");
         b.qspan = (uint32_t)span;
-        void **const p[] = {(void **)&b.qd, (void **)&b.qv, (void **)&b.qm, (void **)&b.qcnt};
-        const uint64_t z[] = {G * span * 8, G * span * 4, G * span * 8, G * 8};
-        int rc = alloc_group(p, z, 4);
+        void **const p[] = {(void **)&b.qd, (void **)&b.qv, (void **)&b.qm, (void **)&b.qr, (void **)&b.qcnt};
+        const uint64_t z[] = {G * span * 8, G * span * 4, G * span * 8, G * span * 8, G * 8};
+        int rc = alloc_group(p, z, 5);
         if (rc) return rc;
     }
     if (approx && !(b.apx_lin && b.apx_lout && b.apx_sp)) {
