@@ -1144,7 +1144,7 @@ constexpr uint32_t kQWin = 4 * kOwnSpan;     // most vertices a scan block may o
 // the rest far, and folds the exact minD and T over all of them; relax skips
 // it and the next launch runs the phase. The margin is kSplitPhases times the
 // threshold's advance per phase since the previous rebuild.
-constexpr unsigned long long kSplitPhases = 16;
+constexpr unsigned long long kSplitPhases = 32;
 
 template <int IN, int OUT, int CH, bool KEYED = false>
 __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
@@ -1942,7 +1942,8 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
     __shared__ unsigned long long s_du[CH + 1];
     __shared__ unsigned long long sh[8 * kWaves];
     __shared__ uint32_t s_ns[kShards], s_E[kShards], s_nch[kShards];
-    __shared__ uint32_t s_cmax;
+    __shared__ uint32_t s_cmax, s_ctot;
+    __shared__ uint32_t s_cpre[kShards];  // exclusive prefix of the shards' chunk counts
     __shared__ unsigned long long s_tot_settled, s_tot_edges;
     // Chunks are interleaved over the shards: chunk c is chunk c / kShards of shard
     // c % kShards, so a block knows its first chunk before it has read the shard
@@ -1974,11 +1975,14 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
         const uint32_t nch = (uint32_t)(((uint64_t)E + CH - 1) / CH);
         uint32_t mx = nch;  // most chunks in one shard: chunks c < kShards * mx may exist
         for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor(mx, o, 64));
+        const uint32_t cin = wave_incl_scan(i < kShards ? nch : 0u);
         if (i < kShards) {
             s_ns[i] = ns;
             s_E[i] = E;
             s_nch[i] = nch;
+            s_cpre[i] = cin - nch;
         }
+        if (i == kShards - 1) s_ctot = cin;
         const unsigned long long tset = wave_sum64((unsigned long long)ns + nz);
         const unsigned long long tedge = wave_sum64(E);
         if (i == 0) { s_tot_settled = tset; s_tot_edges = tedge; s_cmax = kShards * mx; }
@@ -2017,7 +2021,13 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
         if (split) return;
     }
     unsigned long long cmin = INF64, ctst = INF64, tried = 0, improv = 0, disc = 0, winimp = 0, dsum = 0, ddeg = 0;
-    const uint32_t cmax = s_cmax;
+    // Chunk c is chunk c / kShards of shard c % kShards while that leaves every block
+    // at most one chunk index (then the first chunk's bounds were loaded above);
+    // otherwise some shard holds many more edges than the others (a high-degree row
+    // settled), and the chunks are numbered shard by shard, so that the blocks take
+    // equal numbers of them.
+    const bool ilv = s_cmax <= cstep;  // block-uniform
+    const uint32_t cmax = ilv ? s_cmax : s_ctot;
     // Chunk c's shard, shard-local index and first / last S' entry (ok = the chunk
     // exists); the entry bounds of the block's next chunk are loaded while this one
     // is processed.
@@ -2028,8 +2038,18 @@ __global__ __launch_bounds__(kBlock) void k_relax(KArgs a, int par) {
     };
     auto chunk_ref = [&](uint32_t c, bool use_spec) {
         ChunkRef r;
-        r.sd = (int)(c % kShards);
-        r.lc = c / kShards;
+        if (ilv) {
+            r.sd = (int)(c % kShards);
+            r.lc = c / kShards;
+        } else {
+            int lo = 0;  // last shard whose first chunk number is <= c
+#pragma unroll
+            for (int st = kShards / 2; st > 0; st >>= 1)
+                if (s_cpre[lo + st] <= c) lo += st;
+            r.sd = lo;
+            r.lc = c - s_cpre[lo];
+            use_spec = false;
+        }
         r.ok = r.lc < s_nch[r.sd];
         r.j0 = r.jend = 0;
         if (r.ok) {
