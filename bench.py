@@ -156,7 +156,7 @@ def solve_frac(st, ms, n):
     return round(solve_bytes(st, n) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
 
 
-def measure_plain(B, torch, dg, src, crit, steps, warmup, log2n):
+def measure_plain(B, torch, dg, src, crit, steps, warmup, record):
     """Timed plain solves (steps after warmup) and the dominant kernel's roofline from a separate
     HIP-event pass over the same solve."""
     dist = B.new_dist(dg.n)
@@ -184,7 +184,7 @@ def measure_plain(B, torch, dg, src, crit, steps, warmup, log2n):
     avg_us = prof[kern + "_ms"] * 1e3 / prof["phases"]
     achieved = per_launch / (avg_us * 1e-6) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kname, log2n),
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kname, record, dg.launch()),
                 "kernel": kname,
                 "alg_bytes_per_launch": round(per_launch), "avg_launch_us": round(avg_us, 2),
                 "launches": prof["phases"], "identify_ms": round(prof["identify_ms"], 3),
@@ -192,20 +192,25 @@ def measure_plain(B, torch, dg, src, crit, steps, warmup, log2n):
     return ms, phases, st, roofline, prof, dist
 
 
-def measured_traffic(kern, log2n):
-    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE record, or None when the
-    kernel source changed since the counters were taken (or another kernel/size dominates)."""
+def measured_traffic(kern, record, launch):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE records, or None when the
+    kernel source changed since the counters were taken, or no record is for this kernel, size and
+    launch shape."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic_identify_er%d.json" % log2n)
+    path = os.path.join(ROOT, "profiles", "traffic_identify_%s.json" % record)
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec["kernel"] != kern:
-        return None
     h = hashlib.sha256()
     for f in ("paper_1903_12085_amd/csrc/phased.hip", "paper_1903_12085_amd/csrc/common.h"):
         h.update(open(os.path.join(ROOT, f), "rb").read())
-    return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
+    if h.hexdigest() != rec["source_sha256"] or rec["kernel"] != kern:
+        return None
+    shape = "%d,%d,%d,%d,%d" % tuple(launch[k] for k in ("scan_blocks", "relax_blocks", "chunk", "use_graph", "queue"))
+    for r in rec["by_launch"]:
+        if r["launch"] == shape:
+            return r["traffic_bytes_per_launch"]
+    return None
 
 
 def bench_batched(B, torch, G):
@@ -371,7 +376,7 @@ def bench_c3(B, torch, G, tuned):
             tp0, rp = median_time(torch, lambda: B.solve(dg, s0, B.STATIC_OR, dist))
             e["switched_src0"] = bench_switched(B, torch, dg, s0, sts[0]["m_reach"], tp0 * 1e3, B.to_u64(rp.dist))
             # the dominant kernel's roofline on the first source, as for the headline graph
-            rms, _, rst, rroof, _, _ = measure_plain(B, torch, dg, s0, B.STATIC_OR, 3, 1, 0)
+            rms, _, rst, rroof, _, _ = measure_plain(B, torch, dg, s0, B.STATIC_OR, 3, 1, gname)
             e["roofline_src0"] = rroof
             e["solve_hbm_frac_src0"] = solve_frac(rst, rms, g.n)
         res[name] = e
@@ -491,7 +496,7 @@ def main():
     log("autotuned launch shape", tuned, "%.3f ms" % tuned_ms)
 
     ms, phases, st, roofline, prof, dist = measure_plain(B, torch, dg, src, crit, args.steps, args.warmup,
-                                                         args.log2n)
+                                                         "er%d" % args.log2n)
     log("timed %d steps: %.3f ms/step, %d phases" % (args.steps, ms, phases))
     gteps = st["m_reach"] / (ms * 1e-3) / 1e9
     log("profile", prof)
@@ -548,7 +553,7 @@ def main():
         gl = G.config_er_large(seed=seed, log2n=23)
         dl = B.DeviceGraph.from_graph(gl)
         dl.set_launch(**tuned)
-        lms, lph, lst, lroof, _, ldist = measure_plain(B, torch, dl, src, crit, 3, 1, 23)
+        lms, lph, lst, lroof, _, ldist = measure_plain(B, torch, dl, src, crit, 3, 1, "er23")
         rec = golden("er23", "STATIC_OR", src)
         out["largest"] = {"workload": "er_n%d_outdeg16_w1-2^20_src0" % gl.n, "n": gl.n, "m": gl.m,
                           "solve_hbm_frac": solve_frac(lst, lms, gl.n),

@@ -1144,7 +1144,7 @@ constexpr uint32_t kQWin = 4 * kOwnSpan;     // most vertices a scan block may o
 // the rest far, and folds the exact minD and T over all of them; relax skips
 // it and the next launch runs the phase. The margin is kSplitPhases times the
 // threshold's advance per phase since the previous rebuild.
-constexpr unsigned long long kSplitPhases = 32;
+constexpr unsigned long long kSplitPhases = 20;
 
 template <int IN, int OUT, int CH, bool KEYED = false>
 __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
