@@ -34,6 +34,7 @@ struct BatchQuery {
     unsigned long long *dist;
     uint8_t *st;
     uint32_t *fl;      // 3 * n entries: fringe list A, fringe list B, settled list
+    uint2 *fm;         // 2 * n entries: (minIn, minOut) of each fringe list entry (one workgroup per query)
     uint32_t n;
     uint32_t src;
     uint32_t wmax;     // the graph has an edge of weight 2^32 - 1 (see min_out64)
@@ -58,6 +59,11 @@ __device__ __forceinline__ uint8_t ld_st(const uint8_t *p) {
 }
 __device__ __forceinline__ uint32_t ld_u32(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint2 ld_u2(const uint2 *p) {
+    const unsigned long long x =
+        __hip_atomic_load(reinterpret_cast<const unsigned long long *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return make_uint2((uint32_t)x, (uint32_t)(x >> 32));
 }
 // Stores of values another workgroup of a team reads (team launch only): device-scope
 // atomic stores, which do not stay in one die's L2, so that a team barrier only has to
@@ -108,20 +114,24 @@ __device__ __forceinline__ void wave_append(bool take, uint32_t v, uint32_t *lis
 // Relaxes the edges ed[j] (bit j of have) from a vertex at distance du: the
 // state and distance loads of all of them are issued together, then the
 // atomics. Returns the mask of edges whose atomic replaced infinity (the
-// target was discovered; exactly one atomic can do that).
-template <int U, bool OUT, bool TEAM = false>
+// target was discovered; exactly one atomic can do that). MM: also loads each
+// target's static minima into tm (with the state and distance), for the
+// fringe entry of a discovered target.
+template <int U, bool OUT, bool TEAM = false, bool MM = false>
 __device__ __forceinline__ uint32_t relax_edges(const BatchQuery &q, unsigned long long du, const uint2 *ed,
                                                 const uint32_t *em, uint32_t have, unsigned long long &cmin,
-                                                unsigned long long &ctst) {
+                                                unsigned long long &ctst, uint2 *tm = nullptr) {
     uint8_t sv[U];
     unsigned long long cur[U], cand[U], old[U];
 #pragma unroll
     for (int j = 0; j < U; ++j) {
         sv[j] = ST_S;
         cur[j] = 0;
+        if (MM) tm[j] = make_uint2(INF32, INF32);
         if ((have >> j) & 1u) {
             sv[j] = ld_st(&q.st[ed[j].x]);
             cur[j] = ld_dist(&q.dist[ed[j].x]);
+            if (MM) tm[j] = q.vmin[ed[j].x];
         }
     }
     uint32_t issued = 0;
@@ -152,6 +162,24 @@ __device__ __forceinline__ uint32_t relax_edges(const BatchQuery &q, unsigned lo
 
 constexpr int kBatchU = 4;  // fringe entries / edges a lane handles per step
 
+// Wavefront-aggregated append of a fringe entry: vertex v to list, its static
+// minima mm to mlist at the same index (a phase then reads a fringe vertex's
+// minima from its entry, coalesced, instead of gathering them).
+__device__ __forceinline__ void wave_append_fm(bool take, uint32_t v, uint2 mm, uint32_t *list, uint2 *mlist,
+                                               uint32_t *cnt) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long mask = __ballot(take);
+    if (!mask) return;
+    const int leader = __ffsll((long long)mask) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(cnt, (uint32_t)__popcll(mask));
+    base = __shfl(base, leader, 64);
+    if (!take) return;
+    const uint32_t i = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+    list[i] = v;
+    mlist[i] = mm;
+}
+
 // One workgroup per query, queries taken from order[0 .. nq) through ctl->next.
 // IN: IN_NONE, IN_DIJK or IN_STATIC_M; OUT: OUT-STATIC on/off.
 template <int BS, int IN, bool OUT>
@@ -179,6 +207,7 @@ __device__ __forceinline__ void batch_single(const BatchQuery *__restrict__ quer
         }
         if (threadIdx.x == 0) {
             q.fl[0] = q.src;
+            q.fm[0] = q.vmin[q.src];
             for (int k = 0; k < 2; ++k) hub_n[k] = s_nset[k] = s_nnext[k] = 0;
         }
         uint32_t nF = 1, cur = 0, phases = 0;
@@ -188,6 +217,8 @@ __device__ __forceinline__ void batch_single(const BatchQuery *__restrict__ quer
             uint32_t *F = q.fl + (uint64_t)cur * n;
             uint32_t *Fn = q.fl + (uint64_t)(cur ^ 1) * n;
             uint32_t *Sp = q.fl + 2ull * n;
+            const uint2 *Fm = q.fm + (uint64_t)cur * n;
+            uint2 *Fnm = q.fm + (uint64_t)(cur ^ 1) * n;
             const int pp = (int)(phases & 1u);
             // identify over the fringe list
             unsigned long long fmin = INF64, ftst = INF64;
@@ -212,7 +243,7 @@ __device__ __forceinline__ void batch_single(const BatchQuery *__restrict__ quer
                     mm[j] = make_uint2(INF32, INF32);
                     if ((have >> j) & 1u) {
                         dv[j] = ld_dist(&q.dist[v[j]]);
-                        mm[j] = q.vmin[v[j]];
+                        mm[j] = ld_u2(&Fm[base + j * BS + threadIdx.x]);  // the entry's minima (coalesced)
                     }
                 }
 #pragma unroll
@@ -233,7 +264,7 @@ __device__ __forceinline__ void batch_single(const BatchQuery *__restrict__ quer
                         }
                     }
                     wave_append(set, v[j], Sp, &s_nset[pp]);
-                    wave_append(keep, v[j], Fn, &s_nnext[pp]);
+                    wave_append_fm(keep, v[j], mm[j], Fn, Fnm, &s_nnext[pp]);
                 }
             }
             __syncthreads();
@@ -284,10 +315,11 @@ __device__ __forceinline__ void batch_single(const BatchQuery *__restrict__ quer
                             have |= 1u << j;
                         }
                     }
-                    const uint32_t disc = relax_edges<kBatchU, OUT>(q, du, ed, em, have, cmin, ctst);
+                    uint2 tm[kBatchU];
+                    const uint32_t disc = relax_edges<kBatchU, OUT, false, true>(q, du, ed, em, have, cmin, ctst, tm);
 #pragma unroll
                     for (int j = 0; j < kBatchU; ++j)  // every lane of the wavefront takes part
-                        wave_append((disc >> j) & 1u, ed[j].x, Fn, &s_nnext[pp]);
+                        wave_append_fm((disc >> j) & 1u, ed[j].x, tm[j], Fn, Fnm, &s_nnext[pp]);
                 }
             }
             __syncthreads();
@@ -310,9 +342,12 @@ __device__ __forceinline__ void batch_single(const BatchQuery *__restrict__ quer
                             have |= 1u << j;
                         }
                     }
-                    const uint32_t disc = relax_edges<kBatchU, OUT>(q, hub_du[h], ed, em, have, cmin, ctst);
+                    uint2 tm[kBatchU];
+                    const uint32_t disc =
+                        relax_edges<kBatchU, OUT, false, true>(q, hub_du[h], ed, em, have, cmin, ctst, tm);
 #pragma unroll
-                    for (int j = 0; j < kBatchU; ++j) wave_append((disc >> j) & 1u, ed[j].x, Fn, &s_nnext[pp]);
+                    for (int j = 0; j < kBatchU; ++j)
+                        wave_append_fm((disc >> j) & 1u, ed[j].x, tm[j], Fn, Fnm, &s_nnext[pp]);
                 }
             }
             unsigned long long a = umin64(fmin, cmin), t = umin64(ftst, ctst);
@@ -628,15 +663,21 @@ int batch_solve_one(sssp_graph *g, uint32_t source, int in, bool out_static, uin
         BatchCtl ctl;
     };
     hipStream_t s = g->stream;
-    if (!g->one_aux) {
+    if (!(g->one_aux && g->one_st && g->one_fl && g->one_fm)) {  // all or none (a failed call may leave some)
+        sssp_free(g->one_st); sssp_free(g->one_fl); sssp_free(g->one_fm); sssp_free(g->one_aux);
+        g->one_st = nullptr;
+        g->one_fl = nullptr;
+        g->one_fm = nullptr;
+        g->one_aux = nullptr;
         HIP_OK(hipMalloc(&g->one_st, ((uint64_t)g->n + 255) & ~255ull));
         HIP_OK(hipMalloc(&g->one_fl, 3ull * g->n * sizeof(uint32_t)));
+        HIP_OK(hipMalloc(&g->one_fm, 2ull * g->n * sizeof(uint2)));
         HIP_OK(hipMalloc(&g->one_aux, sizeof(OneAux)));
     }
     OneAux h;
     memset(&h, 0, sizeof h);
-    h.q = BatchQuery{g->rp, g->edges, g->vmin, g->emin, (unsigned long long *)dist_out, g->one_st, g->one_fl, g->n,
-                     source, g->wmax};
+    h.q = BatchQuery{g->rp,   g->edges,  g->vmin, g->emin, (unsigned long long *)dist_out, g->one_st, g->one_fl,
+                     g->one_fm, g->n, source, g->wmax};
     OneAux *d = (OneAux *)g->one_aux;
     HIP_OK(hipMemcpyAsync(d, &h, sizeof h, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(pick_batch(512, in, out_static), dim3(1), dim3(512), 0, s, &d->q, &d->order, 1u, &d->ctl,
@@ -684,8 +725,8 @@ extern "C" int sssp_solve_batch_ex(sssp_graph *const *graphs, const uint32_t *so
     if (in > IN_STATIC_M || out > OUT_STATIC_M)
         return sssp_set_error(SSSP_ERR_UNSUPPORTED, "the batched solver evaluates DIJK, IN-STATIC and OUT-STATIC");
     std::vector<BatchQuery> hq(nq);
-    std::vector<uint64_t> st_off(nq), fl_off(nq);
-    uint64_t st_total = 0, fl_total = 0;
+    std::vector<uint64_t> st_off(nq), fl_off(nq), fm_off(nq);
+    uint64_t st_total = 0, fl_total = 0, fm_total = 0;
     for (uint32_t i = 0; i < nq; ++i) {
         const sssp_graph *g = graphs[i];
         if (!g || !dist_outs[i]) return sssp_set_error(SSSP_ERR_INVALID, "query %u: NULL graph or output", i);
@@ -702,6 +743,8 @@ extern "C" int sssp_solve_batch_ex(sssp_graph *const *graphs, const uint32_t *so
         st_total += (g->n + 255) & ~255ull;
         fl_off[i] = fl_total;
         fl_total += 3ull * g->n;
+        fm_off[i] = fm_total;
+        fm_total += 2ull * g->n;
     }
     // longest-processing-time order: most edges first; queries on graphs with at least
     // team_edges edges go to the team launch
@@ -719,6 +762,7 @@ extern "C" int sssp_solve_batch_ex(sssp_graph *const *graphs, const uint32_t *so
     HIP_OK(hipSetDevice(graphs[0]->device));
     uint8_t *st = nullptr;
     uint32_t *fl = nullptr;
+    uint2 *fm = nullptr;
     BatchQuery *dq = nullptr;
     uint32_t *dorder = nullptr, *dph = nullptr, *dlarge = nullptr;
     BatchCtl *dctl = nullptr;
@@ -728,9 +772,11 @@ extern "C" int sssp_solve_batch_ex(sssp_graph *const *graphs, const uint32_t *so
         rc = sssp_set_error(_e == hipErrorOutOfMemory ? SSSP_ERR_OOM : SSSP_ERR_DEVICE, "%s: %s", #call, hipGetErrorString(_e)); goto done; } } while (0)
     TRY(hipMalloc(&st, st_total));
     TRY(hipMalloc(&fl, fl_total * sizeof(uint32_t)));
+    TRY(hipMalloc(&fm, fm_total * sizeof(uint2)));
     for (uint32_t i = 0; i < nq; ++i) {
         hq[i].st = st + st_off[i];
         hq[i].fl = fl + fl_off[i];
+        hq[i].fm = fm + fm_off[i];
     }
     TRY(hipMalloc(&dq, nq * sizeof(BatchQuery)));
     TRY(hipMalloc(&dorder, nq * sizeof(uint32_t)));
@@ -797,7 +843,7 @@ extern "C" int sssp_solve_batch_ex(sssp_graph *const *graphs, const uint32_t *so
     }
 done:
 #undef TRY
-    sssp_free(st); sssp_free(fl); sssp_free(dq); sssp_free(dorder); sssp_free(dph); sssp_free(dctl);
+    sssp_free(st); sssp_free(fl); sssp_free(fm); sssp_free(dq); sssp_free(dorder); sssp_free(dph); sssp_free(dctl);
     sssp_free(dlarge); sssp_free(dteams);
     return rc;
 }

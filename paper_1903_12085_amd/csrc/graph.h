@@ -43,6 +43,7 @@ struct sssp_graph {
     // one-workgroup solves (launch option `single`): the batched kernel's per-query scratch
     uint8_t *one_st = nullptr;     // state bytes, n rounded up to 256
     uint32_t *one_fl = nullptr;    // two fringe lists and the settled list, 3 * n
+    uint2 *one_fm = nullptr;       // (minIn, minOut) of the two fringe lists' entries, 2 * n
     void *one_aux = nullptr;       // query record, order, phase count, work-queue control
 };
 

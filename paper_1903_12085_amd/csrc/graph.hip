@@ -332,6 +332,7 @@ extern "C" int sssp_graph_destroy(sssp_graph *g) {
     if (!g) return SSSP_OK;
     sssp_free(g->rp); sssp_free(g->edges); sssp_free(g->vmin); sssp_free(g->emin);
     sssp_free(g->ip); sssp_free(g->in_edges);
+    sssp_free(g->one_fm);  // the one-workgroup scratch's other buffers go with solve_bufs_free
     solve_bufs_free(g);
     delete g;
     return SSSP_OK;
