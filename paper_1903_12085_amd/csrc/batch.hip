@@ -164,7 +164,9 @@ constexpr int kBatchU = 4;  // fringe entries / edges a lane handles per step
 
 // Wavefront-aggregated append of a fringe entry: vertex v to list, its static
 // minima mm to mlist at the same index (a phase then reads a fringe vertex's
-// minima from its entry, coalesced, instead of gathering them).
+// minima from its entry, coalesced, instead of gathering them). TEAM: other
+// members read the entry, so it is written with device-scope atomic stores.
+template <bool TEAM = false>
 __device__ __forceinline__ void wave_append_fm(bool take, uint32_t v, uint2 mm, uint32_t *list, uint2 *mlist,
                                                uint32_t *cnt) {
     const int lane = threadIdx.x & 63;
@@ -176,8 +178,13 @@ __device__ __forceinline__ void wave_append_fm(bool take, uint32_t v, uint2 mm, 
     base = __shfl(base, leader, 64);
     if (!take) return;
     const uint32_t i = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-    list[i] = v;
-    mlist[i] = mm;
+    if (TEAM) {
+        st_dev(&list[i], v);
+        st_dev(reinterpret_cast<unsigned long long *>(&mlist[i]), ((unsigned long long)mm.y << 32) | mm.x);
+    } else {
+        list[i] = v;
+        mlist[i] = mm;
+    }
 }
 
 // One workgroup per query, queries taken from order[0 .. nq) through ctl->next.
@@ -446,6 +453,8 @@ __global__ __launch_bounds__(BS) void k_batch_team(const BatchQuery *__restrict_
         }
         if (m == 0 && threadIdx.x == 0) {
             st_dev(&q.fl[0], q.src);
+            const uint2 m0 = q.vmin[q.src];
+            st_dev(reinterpret_cast<unsigned long long *>(&q.fm[0]), ((unsigned long long)m0.y << 32) | m0.x);
             for (int k = 0; k < 2; ++k) {
                 st_dev(&tc->nset[k], 0u);
                 st_dev(&tc->nnext[k], 0u);
@@ -460,6 +469,8 @@ __global__ __launch_bounds__(BS) void k_batch_team(const BatchQuery *__restrict_
             uint32_t *F = q.fl + (uint64_t)cur * n;
             uint32_t *Fn = q.fl + (uint64_t)(cur ^ 1) * n;
             uint32_t *Sp = q.fl + 2ull * n;
+            const uint2 *Fm = q.fm + (uint64_t)cur * n;
+            uint2 *Fnm = q.fm + (uint64_t)(cur ^ 1) * n;
             const int pp = (int)(phases & 1u);
             unsigned long long fmin = INF64, ftst = INF64;
             for (uint32_t base = m * BS * kBatchU; base < nF; base += W * BS * kBatchU) {
@@ -482,7 +493,7 @@ __global__ __launch_bounds__(BS) void k_batch_team(const BatchQuery *__restrict_
                     mm[j] = make_uint2(INF32, INF32);
                     if ((have >> j) & 1u) {
                         dv[j] = ld_dist(&q.dist[v[j]]);
-                        mm[j] = q.vmin[v[j]];
+                        mm[j] = ld_u2(&Fm[base + j * BS + threadIdx.x]);  // the entry's minima (coalesced)
                     }
                 }
 #pragma unroll
@@ -503,7 +514,7 @@ __global__ __launch_bounds__(BS) void k_batch_team(const BatchQuery *__restrict_
                         }
                     }
                     wave_append<true>(set, v[j], Sp, &tc->nset[pp]);
-                    wave_append<true>(keep, v[j], Fn, &tc->nnext[pp]);
+                    wave_append_fm<true>(keep, v[j], mm[j], Fn, Fnm, &tc->nnext[pp]);
                 }
             }
             if (!team_barrier(tc, W, arrivals, ctl, &s_ok)) return;
@@ -558,9 +569,11 @@ __global__ __launch_bounds__(BS) void k_batch_team(const BatchQuery *__restrict_
                             have |= 1u << j;
                         }
                     }
-                    const uint32_t disc = relax_edges<kBatchU, OUT, true>(q, du, ed, em, have, cmin, ctst);
+                    uint2 tm[kBatchU];
+                    const uint32_t disc = relax_edges<kBatchU, OUT, true, true>(q, du, ed, em, have, cmin, ctst, tm);
 #pragma unroll
-                    for (int j = 0; j < kBatchU; ++j) wave_append<true>((disc >> j) & 1u, ed[j].x, Fn, &tc->nnext[pp]);
+                    for (int j = 0; j < kBatchU; ++j)
+                        wave_append_fm<true>((disc >> j) & 1u, ed[j].x, tm[j], Fn, Fnm, &tc->nnext[pp]);
                 }
             }
             __syncthreads();
@@ -583,9 +596,12 @@ __global__ __launch_bounds__(BS) void k_batch_team(const BatchQuery *__restrict_
                             have |= 1u << j;
                         }
                     }
-                    const uint32_t disc = relax_edges<kBatchU, OUT, true>(q, hub_du[h], ed, em, have, cmin, ctst);
+                    uint2 tm[kBatchU];
+                    const uint32_t disc =
+                        relax_edges<kBatchU, OUT, true, true>(q, hub_du[h], ed, em, have, cmin, ctst, tm);
 #pragma unroll
-                    for (int j = 0; j < kBatchU; ++j) wave_append<true>((disc >> j) & 1u, ed[j].x, Fn, &tc->nnext[pp]);
+                    for (int j = 0; j < kBatchU; ++j)
+                        wave_append_fm<true>((disc >> j) & 1u, ed[j].x, tm[j], Fn, Fnm, &tc->nnext[pp]);
                 }
             }
             unsigned long long a = umin64(fmin, cmin), tt = umin64(ftst, ctst);
