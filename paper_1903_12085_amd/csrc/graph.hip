@@ -74,31 +74,39 @@ __global__ void k_pack_edges(uint64_t m, const unsigned long long *__restrict__ 
 }
 
 // minOut = the lightest edge of each row (rows in input order); minIn reset to INF.
-// A lane scans a short row itself; the wavefront scans the long rows of its
-// lanes together, one row at a time.
-__global__ void k_min_out(uint32_t n, const uint32_t *__restrict__ rp, const uint2 *__restrict__ edges,
-                          uint2 *__restrict__ vmin) {
+// A wavefront takes 64 consecutive rows, whose edges are contiguous: it reads
+// them 64 at a time (coalesced), finds each edge's row among the 64 by a
+// binary search over the row starts held one per lane, and folds the weight
+// into that row's minimum in LDS.
+__global__ __launch_bounds__(256) void k_min_out(uint32_t n, const uint32_t *__restrict__ rp,
+                                                 const uint2 *__restrict__ edges, uint2 *__restrict__ vmin) {
+    __shared__ uint32_t smin[256];
     const uint32_t lane = threadIdx.x & 63;
+    uint32_t *wmin = smin + (threadIdx.x & ~63u);
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < n; base += stride) {
         const uint64_t v = base + lane;  // base is wavefront-uniform
-        uint32_t b = 0, e = 0;
-        if (v < n) { b = rp[v]; e = rp[v + 1]; }
-        const bool longrow = e - b > 64;
-        uint32_t mo = INF32;
-        if (!longrow)
-            for (uint32_t k = b; k < e; ++k) mo = min(mo, edges[k].y);
-        unsigned long long lm = __ballot(longrow);
-        while (lm) {
-            const int l = __ffsll(lm) - 1;
-            lm &= lm - 1;
-            const uint32_t lb = __shfl(b, l, 64), le = __shfl(e, l, 64);
-            uint32_t x = INF32;
-            for (uint32_t k = lb + lane; k < le; k += 64) x = min(x, edges[k].y);
-            for (int o = 32; o > 0; o >>= 1) x = min(x, (uint32_t)__shfl_xor((int)x, o, 64));
-            if ((int)lane == l) mo = x;
+        const uint32_t rs = v < n ? rp[v] : rp[n];  // this lane's row start (rows past n are empty)
+        const uint32_t e0 = (uint32_t)__shfl((int)rs, 0, 64);
+        const uint32_t e1 = rp[base + 64 < n ? base + 64 : n];
+        wmin[lane] = INF32;
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t k = e0 + lane; __ballot(k < e1); k += 64) {  // wavefront-uniform
+            const bool in = k < e1;
+            const uint32_t w = in ? edges[k].y : INF32;
+            int lo = 0;  // last row of the window whose start is <= k (every lane shuffles)
+#pragma unroll
+            for (int st = 32; st > 0; st >>= 1) {
+                const uint32_t r = (uint32_t)__shfl((int)rs, lo + st, 64);
+                if (r <= k) lo += st;
+            }
+            if (in) atomicMin(&wmin[lo], w);
         }
-        if (v < n) vmin[v] = make_uint2(INF32, mo);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (v < n) vmin[v] = make_uint2(INF32, wmin[lane]);
+        __builtin_amdgcn_wave_barrier();
     }
 }
 

@@ -128,6 +128,32 @@ def test_static_minima_on_device(B):
     assert np.array_equal(mo.cpu().numpy().view(np.uint32), rmo)
 
 
+def skewed_rows_graph():
+    """CSR with the row shapes the minOut pass must get right: a 5000-edge row, a run of 200
+    empty rows, rows ending on a 64-row boundary, and n not a multiple of 64."""
+    n = 1000
+    deg = np.zeros(n, np.int64)
+    deg[:64] = 3                # one full window of short rows
+    deg[64:264] = 0             # a run of empty rows across windows
+    deg[300] = 5000             # one long row inside a window
+    deg[301:999] = (np.arange(301, 999) % 7)
+    deg[999] = 65               # the last row, in a partial window
+    rp = np.concatenate([[0], np.cumsum(deg)]).astype(np.uint64)
+    m = int(rp[-1])
+    x = G.u64_stream(9, 11, 2 * m)
+    col = (x[:m] % n).astype(np.uint32)
+    w = (1 + x[m:] % 1000000).astype(np.uint32)
+    return G.Graph(n, rp, col, w, "skewed_rows")
+
+
+def test_static_minima_skewed_rows(B):
+    for g in (skewed_rows_graph(), G.rmat(12, 16, 1, (1 << 20) - 1, 4)):
+        mi, mo = B.DeviceGraph.from_graph(g).minima()
+        rmi, rmo = O.static_minima(g)
+        assert np.array_equal(mi.cpu().numpy().view(np.uint32), rmi), g.name
+        assert np.array_equal(mo.cpu().numpy().view(np.uint32), rmo), g.name
+
+
 def check_delta(B, g, src, deltas):
     dg = B.DeviceGraph.from_graph(g)
     ref = O.delta_step(g, src, deltas, trace_cap=0)
