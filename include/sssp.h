@@ -170,9 +170,12 @@ int sssp_delta_step_ex(sssp_graph *g, uint32_t source, const uint64_t *deltas, u
  *   dist_outs  HOST array of nq DEVICE pointers, each with room for
  *              graphs[i]->n uint64; the buffers must not overlap.
  *   phases_out HOST, nq entries, may be NULL.
- * Runs on graphs[0]'s stream. Errors: SSSP_ERR_INVALID for nq = 0, a NULL
- * pointer, a bad source or criterion; SSSP_ERR_UNSUPPORTED for the dynamic
- * criteria.
+ * Runs on graphs[0]'s stream. The call allocates about 29 bytes of device
+ * scratch per vertex of each query (a state byte, two fringe lists holding each
+ * entry's vertex and static minima, a settled list) and frees it before
+ * returning. Errors: SSSP_ERR_INVALID for nq = 0, a NULL pointer, a bad source
+ * or criterion; SSSP_ERR_UNSUPPORTED for the dynamic criteria; SSSP_ERR_OOM
+ * when the scratch does not fit.
  */
 int sssp_solve_batch(sssp_graph *const *graphs, const uint32_t *sources, uint32_t nq,
                      uint32_t criterion, uint64_t *const *dist_outs, uint32_t *phases_out);
