@@ -34,7 +34,7 @@ struct BatchQuery {
     unsigned long long *dist;
     uint8_t *st;
     uint32_t *fl;      // 3 * n entries: fringe list A, fringe list B, settled list
-    uint2 *fm;         // 2 * n entries: (minIn, minOut) of each fringe list entry (one workgroup per query)
+    uint2 *fm;         // 2 * n entries: (minIn, minOut) of each fringe list entry
     uint32_t n;
     uint32_t src;
     uint32_t wmax;     // the graph has an edge of weight 2^32 - 1 (see min_out64)
