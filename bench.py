@@ -444,6 +444,9 @@ def main():
     ap.add_argument("--launch", default=None,
                     help="with --profile-run: scan_blocks,relax_blocks,chunk,use_graph[,queue] (e.g. the shape the "
                          "autotuner picks for the timed run)")
+    ap.add_argument("--profile-batch", default=None,
+                    help="one batched solve of the 512-query workload with the given launch shape "
+                         "block,split,blocks,team_edges (for rocprofv3; no tuning, no other legs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device-to-device copy kernel (known bytes) for counter calibration")
     args = ap.parse_args()
@@ -466,6 +469,19 @@ def main():
         dst_t.copy_(src_t)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": 1 << 30}))
+        return
+    if args.profile_batch:
+        graphs, queries = G.batch_workload(seed=7)
+        dgs = [B.DeviceGraph.from_graph(g) for g in graphs]
+        qg = [dgs[i] for i, _ in queries]
+        qs = [s for _, s in queries]
+        dists = [B.new_dist(graphs[i].n) for i, _ in queries]
+        f = [int(x) for x in args.profile_batch.split(",")]
+        cfg = dict(zip(("block", "split", "blocks", "team_edges"), f), team_size=0)
+        torch.cuda.synchronize()
+        _, ph = B.solve_batch(qg, qs, B.STATIC_OR, dists, cfg=cfg)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_batch": True, "queries": len(queries), "phases_total": int(ph.sum()), "cfg": cfg}))
         return
     if args.profile_run:
         if args.profile_graph == "rmat":
