@@ -324,8 +324,8 @@ int sssp_autotune(sssp_graph *g, uint32_t source, uint32_t criterion, sssp_launc
 /*
  * Autotuner for the batched solver: times the batch for workgroup sizes,
  * degree-split thresholds, workgroup counts and team thresholds (no teams,
- * 2^20 or 2^22 edges, automatic team size), makes the fastest the
- * process-wide default and returns it. dist_outs are overwritten with the
+ * 2^20 or 2^22 edges; automatic team size or teams of two), makes the fastest
+ * the process-wide default and returns it. dist_outs are overwritten with the
  * batch's distances.
  */
 int sssp_autotune_batch(sssp_graph *const *graphs, const uint32_t *sources, uint32_t nq,

@@ -116,16 +116,18 @@ extern "C" int sssp_autotune_batch(sssp_graph *const *graphs, const uint32_t *so
     for (uint32_t bs : {256u, 512u, 1024u})
         for (uint32_t split : {16u, 64u, 256u})
             for (uint32_t per_cu : {1u, 2u, 4u})
-                for (uint32_t team_edges : {UINT32_MAX, 1u << 20, 1u << 22}) {
-                    if (bs == 1024 && per_cu > 2) continue;
-                    sssp_batch_cfg c = {bs, split, (uint32_t)cus * per_cu, team_edges, 0};
-                    float ms = 0;
-                    int rc = time_call(graphs[0]->stream, 2, [&] {
-                        return sssp_solve_batch_ex(graphs, sources, nq, criterion, dist_outs, nullptr, &c);
-                    }, &ms);
-                    if (rc) return rc;
-                    if (ms < win_ms) { win_ms = ms; win = c; }
-                }
+                for (uint32_t team_edges : {UINT32_MAX, 1u << 20, 1u << 22})
+                    for (uint32_t team_size : {0u, 2u}) {  // automatic, or pairs (large teams lose under load)
+                        if (bs == 1024 && per_cu > 2) continue;
+                        if (team_edges == UINT32_MAX && team_size) continue;
+                        sssp_batch_cfg c = {bs, split, (uint32_t)cus * per_cu, team_edges, team_size};
+                        float ms = 0;
+                        int rc = time_call(graphs[0]->stream, 2, [&] {
+                            return sssp_solve_batch_ex(graphs, sources, nq, criterion, dist_outs, nullptr, &c);
+                        }, &ms);
+                        if (rc) return rc;
+                        if (ms < win_ms) { win_ms = ms; win = c; }
+                    }
     sssp_batch_set_config(&win);
     if (best) *best = win;
     if (best_ms) *best_ms = win_ms;
