@@ -1445,48 +1445,68 @@ __global__ __launch_bounds__(kBlock) void k_identify_queue(KArgs a, int par) {
         }
     }
     const uint32_t cnt = compact ? kept : cnt0;  // block-uniform
-    // 2b. the vertices listed in 2a: certify, settle, or give an entry
+    // 2b. the vertices listed in 2a: certify, settle, or give an entry. Lists longer than one
+    // round (a rebuild gathers every queued vertex) are taken kR rounds at a time, the loads of
+    // all of them issued together.
+    auto process = [&](bool has, uint32_t w, uint32_t off, const Gathered &g) {  // wavefront-uniform
+        const uint32_t v = g.v, row = g.row, deg = g.deg;
+        const unsigned long long d = g.d;
+        const uint2 mm = g.mm;
+        const uint32_t sb = has ? sw[w * kOwnSpan + wo + off] : 0u;
+        const bool ok = has && !rebuild && certified(d, mm, sb);
+        if (ok) settle(v, d);
+        append_settled<CH>(a, ctl, p2, L, ok, row, deg, d);
+        const bool far = KEYED && has && !ok && in_key(d, mm) > split;
+        const bool app = has && !ok && !far;
+        if (app || (rebuild && far)) {
+            fmin = umin64(fmin, d);
+            if (OUT == 1) ftst = umin64(ftst, sadd64(d, min_out64(mm.y, a.g.wmax, a.g.rp, v)));
+        }
+        if (far) a.b.st[v] = ST_F | ST_QFAR;
+        const unsigned long long am = __ballot(app);
+        if (am) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(&s_app, (uint32_t)__popcll(am));
+            base = (uint32_t)__builtin_amdgcn_readlane((int)base, 0);
+            if (app) {
+                const uint32_t o = cnt + base + (uint32_t)__popcll(am & ((1ull << lane) - 1ull));
+                qd[o] = d;
+                qv[o] = v;
+                qm[o] = mm;
+                qr[o] = make_uint2(row, deg);
+                a.b.st[v] = ST_F;
+            }
+        }
+    };
+    constexpr uint32_t kR = 4;
 #pragma unroll
     for (uint32_t w = 0; w < kWin; ++w) {
         if (totw[w] == 0) continue;  // wavefront-uniform
         const uint64_t wv0 = (uint64_t)kOwnSpan * ((uint64_t)w * G + b) + wo;
-        if (totw[w] > 64) list_need(nmw[w]);  // the LDS list was overwritten by later windows
-        for (uint32_t k0 = 0; k0 < totw[w]; k0 += 64) {  // wavefront-uniform rounds
-            const bool has = k0 + (uint32_t)lane < totw[w];
-            uint32_t off = offw[w];
-            Gathered g = gw[w];
-            if (k0 != 0 && has) {
-                off = need[k0 + lane];
-                g = gather(wv0, off);
-            }
-            const uint32_t v = g.v, row = g.row, deg = g.deg;
-            const unsigned long long d = g.d;
-            const uint2 mm = g.mm;
-            const uint32_t sb = has ? sw[w * kOwnSpan + wo + off] : 0u;
-            const bool ok = has && !rebuild && certified(d, mm, sb);
-            if (ok) settle(v, d);
-            append_settled<CH>(a, ctl, p2, L, ok, row, deg, d);
-            const bool far = KEYED && has && !ok && in_key(d, mm) > split;
-            const bool app = has && !ok && !far;
-            if (app || (rebuild && far)) {
-                fmin = umin64(fmin, d);
-                if (OUT == 1) ftst = umin64(ftst, sadd64(d, min_out64(mm.y, a.g.wmax, a.g.rp, v)));
-            }
-            if (far) a.b.st[v] = ST_F | ST_QFAR;
-            const unsigned long long am = __ballot(app);
-            if (am) {
-                uint32_t base = 0;
-                if (lane == 0) base = atomicAdd(&s_app, (uint32_t)__popcll(am));
-                base = (uint32_t)__builtin_amdgcn_readlane((int)base, 0);
-                if (app) {
-                    const uint32_t o = cnt + base + (uint32_t)__popcll(am & ((1ull << lane) - 1ull));
-                    qd[o] = d;
-                    qv[o] = v;
-                    qm[o] = mm;
-                    qr[o] = make_uint2(row, deg);
-                    a.b.st[v] = ST_F;
+        if (totw[w] <= 64) {  // one round, its loads issued in 2a
+            process((uint32_t)lane < totw[w], w, offw[w], gw[w]);
+            continue;
+        }
+        list_need(nmw[w]);  // the LDS list was overwritten by later windows
+        for (uint32_t k0 = 0; k0 < totw[w]; k0 += 64 * kR) {  // wavefront-uniform
+            uint32_t oq[kR];
+            Gathered gq[kR];
+#pragma unroll
+            for (uint32_t r = 0; r < kR; ++r) {
+                const uint32_t k = k0 + 64 * r + (uint32_t)lane;
+                oq[r] = 0;
+                gq[r] = Gathered{0u, 0u, 0u, INF64, make_uint2(INF32, INF32)};
+                if (k0 == 0 && r == 0) {
+                    oq[r] = offw[w];
+                    gq[r] = gw[w];
+                } else if (k < totw[w]) {
+                    oq[r] = need[k];
+                    gq[r] = gather(wv0, oq[r]);
                 }
             }
+#pragma unroll
+            for (uint32_t r = 0; r < kR; ++r)
+                if (k0 + 64 * r < totw[w]) process(k0 + 64 * r + (uint32_t)lane < totw[w], w, oq[r], gq[r]);
         }
     }
     append_flush<CH>(a, ctl, p2, L);  // starts with a barrier: s_app is final after it
