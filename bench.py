@@ -438,12 +438,12 @@ def main():
     ap.add_argument("--no-c3", action="store_true", help="skip the R-MAT 22 / 2048^2 grid section")
     ap.add_argument("--profile-run", action="store_true",
                     help="one solve with the default launch shape, for rocprofv3 (no tuning, no extra passes)")
-    ap.add_argument("--profile-graph", default="er", choices=("er", "rmat"),
-                    help="with --profile-run: the random graph of --log2n (source 0), or R-MAT scale 22 (the first "
-                         "of its 8 benchmark sources)")
+    ap.add_argument("--profile-graph", default="er", choices=("er", "rmat", "grid"),
+                    help="with --profile-run: the random graph of --log2n (source 0), or R-MAT scale 22 or the "
+                         "2048^2 grid (the first of their 8 benchmark sources)")
     ap.add_argument("--launch", default=None,
-                    help="with --profile-run: scan_blocks,relax_blocks,chunk,use_graph[,queue] (e.g. the shape the "
-                         "autotuner picks for the timed run)")
+                    help="with --profile-run: scan_blocks,relax_blocks,chunk,use_graph[,queue[,single]] (e.g. the "
+                         "shape the autotuner picks for the timed run)")
     ap.add_argument("--profile-batch", default=None,
                     help="one batched solve of the 512-query workload with the given launch shape "
                          "block,split,blocks,team_edges (for rocprofv3; no tuning, no other legs)")
@@ -484,8 +484,8 @@ def main():
         print(json.dumps({"profile_batch": True, "queries": len(queries), "phases_total": int(ph.sum()), "cfg": cfg}))
         return
     if args.profile_run:
-        if args.profile_graph == "rmat":
-            g = G.config_rmat(seed=1)
+        if args.profile_graph in ("rmat", "grid"):
+            g = G.config_rmat(seed=1) if args.profile_graph == "rmat" else G.config_grid(seed=1)
             psrc = int(G.sources(g, 8, 11)[0])
         else:
             g = G.config_er_large(seed=1, log2n=args.log2n)
@@ -493,7 +493,7 @@ def main():
         dg = B.DeviceGraph.from_graph(g)
         if args.launch:
             f = [int(x) for x in args.launch.split(",")]
-            keys = ("scan_blocks", "relax_blocks", "chunk", "use_graph", "queue")
+            keys = ("scan_blocks", "relax_blocks", "chunk", "use_graph", "queue", "single")
             dg.set_launch(**dict(zip(keys, f)))
         r = B.solve(dg, psrc, B.STATIC_OR)
         torch.cuda.synchronize()
