@@ -154,6 +154,31 @@ def test_static_minima_skewed_rows(B):
         assert np.array_equal(mo.cpu().numpy().view(np.uint32), rmo), g.name
 
 
+def test_rows_sorted_on_first_dynamic_solve(B):
+    """Rows stay in input order until a solve first needs the dynamic criteria's cursors, which sorts
+    them by weight in place: rows given heaviest edge first, static solves before and after the sort,
+    the static minima and every criterion stay exact against the oracle."""
+    g0 = G.er(4000, 12, 1, 1 << 20, 71)
+    col, w = g0.col.copy(), g0.w.copy()
+    for v in range(g0.n):  # each row heaviest edge first
+        b, e = int(g0.row_ptr[v]), int(g0.row_ptr[v + 1])
+        o = np.argsort(-w[b:e].astype(np.int64), kind="stable")
+        col[b:e], w[b:e] = col[b:e][o], w[b:e][o]
+    g = G.Graph(g0.n, g0.row_ptr.copy(), col, w, "er4000_rows_heaviest_first")
+    dg = B.DeviceGraph.from_graph(g)
+    rmi, rmo = O.static_minima(g)
+    src = int(G.sources(g, 1, 72)[0])
+    for c in (O.STATIC_OR, O.SIMPLE_OR, O.STATIC_OR, O.FULL_OR, O.IN_STATIC):
+        mi, mo = dg.minima()
+        assert np.array_equal(mi.cpu().numpy().view(np.uint32), rmi)
+        assert np.array_equal(mo.cpu().numpy().view(np.uint32), rmo)
+        ref = O.phased(g, src, c)
+        r = B.solve(dg, src, c)
+        assert np.array_equal(r.dist_u64(), ref.dist), c
+        assert r.phases == ref.phases, (c, r.phases, ref.phases)
+    dg.close()
+
+
 def check_delta(B, g, src, deltas):
     dg = B.DeviceGraph.from_graph(g)
     ref = O.delta_step(g, src, deltas, trace_cap=0)
