@@ -53,3 +53,14 @@ def test_algorithmic_bytes(bench):
     st = {"sum_f": 1000, "n_reach": 100, "m_reach": 1600, "improving": 50}
     assert bench.alg_bytes("identify", st, 10) == 24 * 1000 / 10
     assert bench.alg_bytes("relax", st, 10) == (16 * (100 + 1600) + 8 * 50) / 10
+
+
+def test_more_than_one_gpu_is_refused():
+    """bench.py measures one device; asked for several it says so and exits non-zero before it
+    touches a GPU (so this runs on a machine without one)."""
+    import subprocess
+    import sys
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], cwd=ROOT,
+                       stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU only" in p.stderr and p.stdout == ""
