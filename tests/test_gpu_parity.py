@@ -179,6 +179,53 @@ def test_rows_sorted_on_first_dynamic_solve(B):
     dg.close()
 
 
+def star_with_heavy_chain(n, seed):
+    """Vertex 0 reaches every other vertex v by one edge of seeded weight w(v) in [1, 2^20], and
+    every v in 1 .. n-2 has one more out-edge, to v + 1, of weight 2^31 (the last row is empty).
+    No path through a heavy edge is shorter, so dist(v) = w(v) in closed form."""
+    leaves = n - 1
+    w0 = (G.u64_stream(seed, 5, leaves) % np.uint64(1 << 20) + np.uint64(1)).astype(np.uint32)
+    rp = np.empty(n + 1, np.uint64)
+    rp[0] = 0
+    rp[1:n] = np.uint64(leaves) + np.arange(n - 1, dtype=np.uint64)  # rows 1 .. n-2 hold one edge each
+    rp[n] = rp[n - 1]
+    col = np.concatenate([np.arange(1, n, dtype=np.uint32), np.arange(2, n, dtype=np.uint32)])
+    w = np.concatenate([w0, np.full(max(n - 2, 0), 1 << 31, np.uint32)])
+    dist = np.concatenate([np.zeros(1, np.uint64), w0.astype(np.uint64)])
+    return G.Graph(n, rp, col, w, "star%d_heavy_chain" % n), dist
+
+
+def test_star_with_heavy_chain_small_matches_oracle(B):
+    """The construction of the largest-size test below, small enough for the oracle: its closed-form
+    distances and its two phases (the source, then every leaf) are the oracle's."""
+    g, dist = star_with_heavy_chain(3001, 81)
+    assert int(g.row_ptr[-1]) == len(g.col) == 2 * 3001 - 3
+    for c in (O.STATIC_OR, O.IN_STATIC):
+        ref = O.phased(g, 0, c)
+        assert np.array_equal(ref.dist, dist) and ref.phases == 2, c
+        r = B.solve(B.DeviceGraph.from_graph(g), 0, c)
+        assert np.array_equal(r.dist_u64(), dist) and r.phases == 2, c
+
+
+def test_largest_vertex_count(B):
+    """n = 2^26 - 1, the largest vertex count the library accepts, on the star with a heavy chain
+    (134 M edges): distances exact against the closed form, two phases, with the default launch
+    shape and with keyed queue arrays."""
+    n = (1 << 26) - 1
+    g, dist = star_with_heavy_chain(n, 82)
+    dg = B.DeviceGraph.from_graph(g)
+    del g
+    try:
+        for shape in (None, dict(scan_blocks=1024, relax_blocks=2048, chunk=256, use_graph=0, queue=2, single=0)):
+            if shape:
+                dg.set_launch(**shape)
+            r = B.solve(dg, 0, O.STATIC_OR)
+            assert r.phases == 2, shape
+            assert np.array_equal(r.dist_u64(), dist), shape
+    finally:
+        dg.close()
+
+
 def check_delta(B, g, src, deltas):
     dg = B.DeviceGraph.from_graph(g)
     ref = O.delta_step(g, src, deltas, trace_cap=0)
