@@ -226,6 +226,62 @@ def test_largest_vertex_count(B):
         dg.close()
 
 
+def star_with_heavy_rows(n, heavy, seed):
+    """Vertex 0 reaches every other vertex v by one edge of seeded weight w(v) in [1, 2^20], and
+    every v >= 1 has `heavy` more out-edges, to (v + k) mod n for k = 1 .. heavy, of weight 2^31:
+    m = (n - 1)(heavy + 1), and dist(v) = w(v) in closed form."""
+    w0 = (G.u64_stream(seed, 6, n - 1) % np.uint64(1 << 20) + np.uint64(1)).astype(np.uint32)
+    rp = np.empty(n + 1, np.uint64)
+    rp[0] = 0
+    rp[1:] = np.uint64(n - 1) + np.uint64(heavy) * np.arange(n, dtype=np.uint64)
+    m = int(rp[-1])
+    col = np.empty(m, np.uint32)
+    col[: n - 1] = np.arange(1, n, dtype=np.uint32)
+    hv = col[n - 1:].reshape(n - 1, heavy)
+    ks = np.arange(1, heavy + 1, dtype=np.uint64)
+    for r0 in range(0, n - 1, 1 << 18):  # rows in blocks, to keep the temporaries small
+        r1 = min(r0 + (1 << 18), n - 1)
+        t = np.arange(r0 + 1, r1 + 1, dtype=np.uint64)[:, None] + ks[None, :]
+        t[t >= n] -= np.uint64(n)
+        hv[r0:r1] = t
+    w = np.full(m, 1 << 31, np.uint32)
+    w[: n - 1] = w0
+    dist = np.concatenate([np.zeros(1, np.uint64), w0.astype(np.uint64)])
+    return G.Graph(n, rp, col, w, "star%d_heavy%d" % (n, heavy)), dist
+
+
+def test_star_with_heavy_rows_small_matches_oracle(B):
+    """The construction of the many-edges test below, small enough for the oracle: closed-form
+    distances and two phases are the oracle's, and the library's."""
+    g, dist = star_with_heavy_rows(1001, 7, 83)
+    assert int(g.row_ptr[-1]) == len(g.col) == 1000 * 8
+    for c in (O.STATIC_OR, O.IN_STATIC):
+        ref = O.phased(g, 0, c)
+        assert np.array_equal(ref.dist, dist) and ref.phases == 2, c
+        r = B.solve(B.DeviceGraph.from_graph(g), 0, c)
+        assert np.array_equal(r.dist_u64(), dist) and r.phases == 2, c
+
+
+def test_more_than_2_31_edges(B):
+    """m = 129 * 2^24 = 2,164,260,864 edges (above 2^31, below the 2^32 limit) on n = 2^24 + 1
+    vertices: edge indices past the signed 32-bit range in graph creation (minima, packing) and in
+    relax; distances exact against the closed form, two phases, default and keyed launch shapes."""
+    n = (1 << 24) + 1
+    g, dist = star_with_heavy_rows(n, 128, 84)
+    assert int(g.row_ptr[-1]) > (1 << 31)
+    dg = B.DeviceGraph.from_graph(g)
+    del g
+    try:
+        for shape in (None, dict(scan_blocks=1024, relax_blocks=2048, chunk=256, use_graph=0, queue=2, single=0)):
+            if shape:
+                dg.set_launch(**shape)
+            r = B.solve(dg, 0, O.STATIC_OR)
+            assert r.phases == 2, shape
+            assert np.array_equal(r.dist_u64(), dist), shape
+    finally:
+        dg.close()
+
+
 def check_delta(B, g, src, deltas):
     dg = B.DeviceGraph.from_graph(g)
     ref = O.delta_step(g, src, deltas, trace_cap=0)
