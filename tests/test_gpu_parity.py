@@ -200,7 +200,7 @@ def test_star_with_heavy_chain_small_matches_oracle(B):
     distances and its two phases (the source, then every leaf) are the oracle's."""
     g, dist = star_with_heavy_chain(3001, 81)
     assert int(g.row_ptr[-1]) == len(g.col) == 2 * 3001 - 3
-    for c in (O.STATIC_OR, O.IN_STATIC):
+    for c in (O.STATIC_OR, O.IN_STATIC, O.SIMPLE_OR):
         ref = O.phased(g, 0, c)
         assert np.array_equal(ref.dist, dist) and ref.phases == 2, c
         r = B.solve(B.DeviceGraph.from_graph(g), 0, c)
@@ -210,18 +210,21 @@ def test_star_with_heavy_chain_small_matches_oracle(B):
 def test_largest_vertex_count(B):
     """n = 2^26 - 1, the largest vertex count the library accepts, on the star with a heavy chain
     (134 M edges): distances exact against the closed form, two phases, with the default launch
-    shape and with keyed queue arrays."""
+    shape, keyed queue arrays and the one-workgroup form, and with the SIMPLE criteria (their
+    first solve sorts the rows)."""
     n = (1 << 26) - 1
     g, dist = star_with_heavy_chain(n, 82)
     dg = B.DeviceGraph.from_graph(g)
     del g
+    keyed = dict(scan_blocks=1024, relax_blocks=2048, chunk=256, use_graph=0, queue=2, single=0)
     try:
-        for shape in (None, dict(scan_blocks=1024, relax_blocks=2048, chunk=256, use_graph=0, queue=2, single=0)):
+        for shape, c in ((None, O.STATIC_OR), (keyed, O.STATIC_OR), (dict(keyed, single=1), O.STATIC_OR),
+                         (dict(keyed, single=0), O.SIMPLE_OR)):
             if shape:
                 dg.set_launch(**shape)
-            r = B.solve(dg, 0, O.STATIC_OR)
-            assert r.phases == 2, shape
-            assert np.array_equal(r.dist_u64(), dist), shape
+            r = B.solve(dg, 0, c)
+            assert r.phases == 2, (shape, c)
+            assert np.array_equal(r.dist_u64(), dist), (shape, c)
     finally:
         dg.close()
 
