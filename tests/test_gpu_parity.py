@@ -210,8 +210,8 @@ def test_star_with_heavy_chain_small_matches_oracle(B):
 def test_largest_vertex_count(B):
     """n = 2^26 - 1, the largest vertex count the library accepts, on the star with a heavy chain
     (134 M edges): distances exact against the closed form, two phases, with the default launch
-    shape, keyed queue arrays and the one-workgroup form, and with the SIMPLE criteria (their
-    first solve sorts the rows)."""
+    shape, keyed queue arrays and the one-workgroup form, with the SIMPLE criteria (their first
+    solve sorts the rows), and in a batch."""
     n = (1 << 26) - 1
     g, dist = star_with_heavy_chain(n, 82)
     dg = B.DeviceGraph.from_graph(g)
@@ -225,6 +225,16 @@ def test_largest_vertex_count(B):
             r = B.solve(dg, 0, c)
             assert r.phases == 2, (shape, c)
             assert np.array_equal(r.dist_u64(), dist), (shape, c)
+        # the batched form: two queries on this graph (teams of workgroups, as it has more than
+        # 2^20 edges) beside a small one (one workgroup)
+        small = G.er(1000, 8, 1, 1000, 85)
+        sdg = B.DeviceGraph.from_graph(small)
+        dists, phases = B.solve_batch([dg, sdg, dg], [0, 3, 0], O.STATIC_OR)
+        ref = O.phased(small, 3, O.STATIC_OR)
+        assert [int(x) for x in phases] == [2, ref.phases, 2]
+        assert np.array_equal(B.to_u64(dists[1]), ref.dist)
+        assert np.array_equal(B.to_u64(dists[0]), dist) and np.array_equal(B.to_u64(dists[2]), dist)
+        sdg.close()
     finally:
         dg.close()
 
