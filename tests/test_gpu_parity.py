@@ -195,23 +195,42 @@ def star_with_heavy_chain(n, seed):
     return G.Graph(n, rp, col, w, "star%d_heavy_chain" % n), dist
 
 
+def star_delta_rounds(dist, delta):
+    """Delta-stepping's rounds on that star (delta <= 2^31): bucket 0 takes a light round from the
+    source, a second one if some leaf is light, and its heavy round; every other bucket holding a
+    leaf takes one light round (its leaves have no light edge) and one heavy round."""
+    w0 = dist[1:]
+    later = np.unique(w0[w0 >= np.uint64(delta)] // np.uint64(delta))
+    return 2 + int(bool((w0 < np.uint64(delta)).any())) + 2 * len(later)
+
+
 def test_star_with_heavy_chain_small_matches_oracle(B):
     """The construction of the largest-size test below, small enough for the oracle: its closed-form
     distances and its two phases (the source, then every leaf) are the oracle's."""
     g, dist = star_with_heavy_chain(3001, 81)
     assert int(g.row_ptr[-1]) == len(g.col) == 2 * 3001 - 3
+    dg = B.DeviceGraph.from_graph(g)
     for c in (O.STATIC_OR, O.IN_STATIC, O.SIMPLE_OR):
         ref = O.phased(g, 0, c)
         assert np.array_equal(ref.dist, dist) and ref.phases == 2, c
-        r = B.solve(B.DeviceGraph.from_graph(g), 0, c)
+        r = B.solve(dg, 0, c)
         assert np.array_equal(r.dist_u64(), dist) and r.phases == 2, c
+    # Delta-stepping: with Delta = 2^21 every star edge is light (3 rounds, one bucket); with 2^19
+    # and 2^18 the leaves spread over several buckets
+    for delta, rounds in ((1 << 21, 3), (1 << 19, 5), (1 << 18, 9)):
+        assert star_delta_rounds(dist, delta) == rounds
+        ref = O.delta_step(g, 0, [delta])
+        assert np.array_equal(ref.dist, dist) and ref.rounds == rounds, delta
+        r = B.delta_step(dg, 0, delta)
+        assert np.array_equal(r.dist_u64(), dist) and r.phases == rounds, delta
+    dg.close()
 
 
 def test_largest_vertex_count(B):
     """n = 2^26 - 1, the largest vertex count the library accepts, on the star with a heavy chain
     (134 M edges): distances exact against the closed form, two phases, with the default launch
     shape, keyed queue arrays and the one-workgroup form, with the SIMPLE criteria (their first
-    solve sorts the rows), and in a batch."""
+    solve sorts the rows), in a batch, and Delta-stepping's rounds."""
     n = (1 << 26) - 1
     g, dist = star_with_heavy_chain(n, 82)
     dg = B.DeviceGraph.from_graph(g)
@@ -225,6 +244,10 @@ def test_largest_vertex_count(B):
             r = B.solve(dg, 0, c)
             assert r.phases == 2, (shape, c)
             assert np.array_equal(r.dist_u64(), dist), (shape, c)
+        for delta in (1 << 21, 1 << 19):  # with 2^19 some leaf weighs 2^20: a third bucket
+            r = B.delta_step(dg, 0, delta)
+            assert r.phases == star_delta_rounds(dist, delta), delta
+            assert np.array_equal(r.dist_u64(), dist), delta
         # the batched form: two queries on this graph (teams of workgroups, as it has more than
         # 2^20 edges) beside a small one (one workgroup)
         small = G.er(1000, 8, 1, 1000, 85)
